@@ -1,0 +1,274 @@
+#!/usr/bin/env python3
+"""Benchmark of the GB-OBC + Monte Carlo hot path on one MI355X.
+
+A step is one pass of the whole hot path over the E-REMD batch (16 replicas x
+2,500 atoms): Born radii, energy + forces + dE/dq + dE/drho (with the Born
+radius chain), Delta E / Delta G of every candidate state change, one
+protonation + redox Metropolis attempt per replica, and one replica-exchange
+attempt along the redox-potential ladder.  The step is captured in a HIP graph
+(two graphs: even and odd exchange parity) and replayed.
+
+Prints ONE JSON line.  Pair interactions/s = sum_b N_b (N_b - 1)/2 per step
+divided by the step time.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GB pair interactions/s (E+forces) & MC dE evals/s, FP32-fixed vs FP64, 1 GPU"
+KB, FARADAY = 1.98720426e-3, 23.0605478
+E0_REF, PKA_REF = -0.203, 4.4          # reference compound values of section III.C
+
+# Algorithmic work per unordered pair of one full evaluation, counted from the
+# closed-form expressions (FMA = 2; add, mul, min, max, abs, select = 1; each
+# reciprocal, sqrt, rsqrt, exp, log = 1 and counted as one operation):
+#   descreening pass 54 + 8, energy/force pass 53 + 4, chain pass 94 + 7.
+FLOPS_PER_PAIR = {"radii_pairs": 62, "energy_pairs": 57, "chain_pairs": 101}
+# Peak for FP32 vector arithmetic without packed-FP32 instructions (disabled in
+# this build): 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA) = 78.6 TFLOP/s;
+# FP64 vector: 78.6 TFLOP/s.
+PEAK_TFLOPS = {"fp32": 78.6, "fp64": 78.6}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--fp64-steps", type=int, default=20)
+    ap.add_argument("--kernel-steps", type=int, default=20)
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    return ap.parse_args()
+
+
+class Workload:
+    """Config-2 E-REMD batch resident on the GPU, with static step buffers."""
+
+    def __init__(self, precision, n_steps):
+        import numpy as np
+        import torch
+        import paper_1803_09652_amd as g
+        import synth
+        self.g, self.torch = g, torch
+        self.systems = synth.config2()
+        self.batch = b = synth.make_batch(self.systems)
+        self.B = b.n_systems
+        self.plan = g.Plan(b.atom_offset, precision)
+        self.atoms = g.Atoms.from_batch(self.plan, b)
+        dev = self.plan.device
+        self.params = g.IGB5
+        self.T = 300.0
+        self.E_rung = torch.as_tensor(synth.E_LADDER, dtype=torch.float64, device=dev)
+        self.rep_of_rung = torch.arange(self.B, dtype=torch.int32, device=dev)
+        self.E_rep = self.E_rung.clone()                   # replica r starts on rung r
+        self.pH = torch.full((self.B,), synth.PH_DEFAULT, dtype=torch.float64, device=dev)
+        self.cur = torch.as_tensor(b.current_state, device=dev)
+        # Gref: dG_elec,ref = Delta E of the starting geometry and states, plus
+        # the reference E0 / pKa terms (Eqs. 8 and 9)
+        sites0 = g.Sites.from_batch(self.plan, b)
+        g.radii(self.plan, self.atoms, self.params)
+        dE0, _ = g.mc_state_dE(self.plan, sites0, self.atoms, self.cur, self.pH, self.E_rep,
+                               self.T, self.params)
+        dE0 = dE0.cpu().numpy()
+        gref = np.zeros(b.state_count.size)
+        c = 0
+        for m in range(b.n_sites):
+            g0, g1 = int(b.site_state_offset[m]), int(b.site_state_offset[m + 1])
+            cur = int(b.current_state[m])
+            ref = FARADAY * E0_REF if b.site_kind[m] == 1 else KB * self.T * math.log(10) * PKA_REF
+            for t in range(g1 - g0):
+                if t == cur:
+                    continue
+                gref[g0 + t] = dE0[c] + ref * (b.state_count[g0 + t] - b.state_count[g0 + cur])
+                c += 1
+        self.sites = g.Sites.from_batch(self.plan, b, gref)
+        rng = torch.Generator(device=dev)
+        rng.manual_seed(2024)
+        self.u_all = torch.rand((n_steps, self.B, 6), dtype=torch.float64, device=dev, generator=rng)
+        self.ux_all = torch.rand((n_steps, self.B), dtype=torch.float64, device=dev, generator=rng)
+        self.u = torch.zeros((self.B, 6), dtype=torch.float64, device=dev)
+        self.ux = torch.zeros(self.B, dtype=torch.float64, device=dev)
+        self.pairs = int(sum(s.n * (s.n - 1) // 2 for s in self.systems))
+        self.n_cand = self.sites.n_candidates
+        # per-site attempt / acceptance counters, accumulated by the MC kernel
+        self.counters = torch.zeros((b.n_sites, 2), dtype=torch.int64, device=dev)
+
+    def step(self, parity):
+        g, p = self.g, self.params
+        g.radii(self.plan, self.atoms, p)
+        ef = g.energy_forces(self.plan, self.atoms, p)
+        dE, dG = g.mc_state_dE(self.plan, self.sites, self.atoms, self.cur, self.pH, self.E_rep,
+                               self.T, p)
+        mc = g.mc_step(self.plan, self.sites, self.atoms, self.cur, self.pH, self.E_rep, dE, dG,
+                       self.u, self.T, p, counters=self.counters)
+        acc, E_new = g.remd_exchange(self.E_rung, mc["n_electrons"], self.rep_of_rung, parity,
+                                     self.ux, self.T, True)
+        self.E_rep.copy_(E_new)
+        self.last_exchange = acc
+        return ef
+
+    def load_uniforms(self, k):
+        self.u.copy_(self.u_all[k])
+        self.ux.copy_(self.ux_all[k])
+
+
+def run_gpu(precision, steps, warmup, use_graph, kernel_steps):
+    import torch
+    n_total = steps + warmup + kernel_steps + 2
+    w = Workload(precision, n_total)
+    torch.cuda.synchronize()
+    k = 0
+    graphs = None
+    if use_graph:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for parity in (0, 1):
+                w.load_uniforms(k)
+                w.step(parity)
+                k += 1
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graphs = []
+        for parity in (0, 1):
+            gr = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(gr):
+                w.step(parity)
+            graphs.append(gr)
+
+    def one(i):
+        nonlocal k
+        w.load_uniforms(k)
+        k += 1
+        if graphs is not None:
+            graphs[i % 2].replay()
+        else:
+            w.step(i % 2)
+
+    for i in range(warmup):
+        one(i)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for i in range(steps):
+        one(i)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = ev0.elapsed_time(ev1) / steps
+    # per-kernel durations, eager calls bracketed by HIP events on this stream
+    w.plan.set_timing(True)
+    w.exchanges_accepted = w.exchanges_attempted = 0
+    sums = {}
+    for i in range(kernel_steps):
+        w.load_uniforms(k)
+        k += 1
+        w.step(i % 2)
+        for name, ms in w.plan.kernel_ms().items():
+            sums[name] = sums.get(name, 0.0) + ms
+        w.exchanges_accepted += int(w.last_exchange.sum())
+        w.exchanges_attempted += int(w.last_exchange.numel())
+    w.plan.set_timing(False)
+    kernel_ms = {n: v / max(1, kernel_steps) for n, v in sums.items()}
+    return w, ms_step, wall / steps * 1e3, kernel_ms
+
+
+def cpu_baseline(systems):
+    """The FP64 oracle as it stands, on the host cores, over every replica of
+    the batch (full evaluation + every candidate Delta E)."""
+    import oracle
+    oracle.lib()
+    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    t0 = time.perf_counter()
+    pairs = 0
+    for s in systems:
+        r = oracle.energy_forces(s)
+        oracle.site_dE(s, r["R"])
+        pairs += s.n * (s.n - 1) // 2
+    dt = time.perf_counter() - t0
+    return {"value": pairs / dt, "unit": "pair interactions/s", "cores": cores, "kind": "oracle",
+            "sample": f"all {len(systems)} replicas of the E-REMD batch ({pairs} pairs): radii, "
+                      f"energy, forces, dE/dq, dE/drho and every candidate Delta E, FP64, "
+                      f"OpenMP, {dt:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}): "
+              "the batch shards by replica across GPUs in principle, but this build measures "
+              "the single-GPU path", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    torch.cuda.set_device(0)
+    use_graph = not args.no_graph
+    w, ms_step, wall_ms, kms = run_gpu("fp32", args.steps, args.warmup, use_graph, args.kernel_steps)
+    pairs, n_cand = w.pairs, w.n_cand
+    value = pairs / (ms_step * 1e-3)
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pair interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "E-REMD batch: 16 replicas x 2500 atoms (18 A globules), 4 redox + 4 "
+                        "protonation sites each, E ladder -0.40..-0.10 V, pH 7, T 300 K, igb=5, "
+                        "no cutoff",
+            "systems": w.B, "atoms": w.batch.n_atoms, "pairs_per_step": pairs,
+            "candidates_per_step": n_cand, "hip_graph": use_graph,
+            "precision": "FP32 pair arithmetic, int64 fixed-point sums, FP64 MC",
+        },
+        "mc_dE_evals_per_s": n_cand / (ms_step * 1e-3),
+        "wall_ms_per_step": wall_ms,
+        "kernel_ms": kms,
+    }
+    if "site_rows" in kms or "site_dE" in kms:
+        t_mc = kms.get("site_rows", 0.0) + kms.get("site_dE", 0.0)
+        out["mc_dE_evals_per_s_standalone"] = n_cand / (t_mc * 1e-3)
+    pair_k = {n: kms[n] for n in FLOPS_PER_PAIR if n in kms}
+    if pair_k:
+        dom = max(pair_k, key=pair_k.get)
+        ach = FLOPS_PER_PAIR[dom] * pairs / (pair_k[dom] * 1e-3) / 1e12
+        out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": ach,
+                           "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
+                           "frac": ach / PEAK_TFLOPS["fp32"], "traffic": None,
+                           "per_kernel_tflops": {n: FLOPS_PER_PAIR[n] * pairs / (v * 1e-3) / 1e12
+                                                 for n, v in pair_k.items()}}
+    cnt = w.counters.sum(0).cpu().tolist()
+    out["mc_acceptance"] = {"state_attempts": cnt[0], "state_accepted": cnt[1],
+                            "exchange_attempts_eager": w.exchanges_attempted,
+                            "exchange_accepted_eager": w.exchanges_accepted}
+    del w
+    if not args.no_fp64:
+        w64, ms64, _, k64 = run_gpu("fp64", args.fp64_steps, 2, use_graph, 3)
+        v64 = pairs / (ms64 * 1e-3)
+        out["fp64"] = {"value": v64, "ms_per_step": ms64, "steps": args.fp64_steps,
+                       "kernel_ms": k64}
+        out["fp32_over_fp64"] = value / v64
+        del w64
+    if not args.no_cpu_baseline:
+        import synth
+        out["cpu_baseline"] = cpu_baseline(synth.config2())
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,266 @@
+/*
+ * gbmc.h -- C ABI of libgbmc: all-pairs Generalized Born (OBC) electrostatics
+ * and the discrete-state Monte Carlo / replica-exchange decisions of constant
+ * redox potential MD (CEMD), coupled constant pH and redox potential MD
+ * (C(pH,E)MD) and redox potential replica exchange MD (E-REMD) in implicit
+ * solvent, after Cruzeiro, Amaral & Roitberg, arXiv:1803.09652, on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * Conventions
+ *  - Units: Angstrom, elementary charge, kcal/mol, volt, kelvin.
+ *  - Every array argument is a DEVICE pointer owned by the caller unless its
+ *    comment says "host".  The library never frees caller memory.
+ *  - Every compute call is asynchronous on the caller's stream, performs no
+ *    host<->device synchronisation and no allocation, and may be captured in a
+ *    HIP graph (accumulators are cleared by kernels, never by memset).
+ *  - Every call returns a gbmc_status; on failure gbmc_last_error() returns a
+ *    thread-local message.  No C++ exception crosses this interface.
+ *  - A plan fixes the batch layout (systems of uneven size, concatenated) and
+ *    the precision.  In GBMC_FP32_FIXED plans per-atom arrays are float, pair
+ *    arithmetic is FP32 and every sum is accumulated in 64-bit fixed point, so
+ *    results are bitwise reproducible run to run; in GBMC_FP64 plans per-atom
+ *    arrays are double and the arithmetic is FP64.  Arrays documented as
+ *    double are FP64 in both precisions.
+ *  - Coordinates must lie within +-1e5 A and no two atoms of a system may
+ *    coincide (r_ij > 0).
+ */
+#ifndef GBMC_H
+#define GBMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GBMC_OK = 0,
+    GBMC_ERR_INVALID = -1,      /* bad argument, layout or table */
+    GBMC_ERR_HIP = -2,          /* a HIP runtime call failed */
+    GBMC_ERR_OVERFLOW = -3,     /* a fixed-point accumulator would overflow */
+    GBMC_ERR_UNSUPPORTED = -4   /* valid input this library does not handle */
+} gbmc_status;
+
+typedef enum { GBMC_FP32_FIXED = 0, GBMC_FP64 = 1 } gbmc_precision;
+
+/* GB model parameters.  The paper runs the Onufriev-Bashford-Case model with
+ * AMBER's igb=2 set (section III.D/E: alpha 0.8, beta 0, gamma 2.909125); the
+ * igb=5 set is alpha 1.0, beta 0.8, gamma 4.85.  offset is the dielectric
+ * offset subtracted from every intrinsic radius (0.09 A); coulomb_k is the
+ * Coulomb constant (332.0522 kcal A / (mol e^2)); kappa (inverse Debye length)
+ * must be 0: salt screening is GBMC_ERR_UNSUPPORTED. */
+typedef struct {
+    double alpha, beta, gamma;
+    double offset;
+    double eps_in, eps_out;
+    double coulomb_k;
+    double kappa;
+} gbmc_gb_params;
+
+/* Per-atom SoA inputs over the whole batch (N_tot = atom_offset[B] atoms),
+ * element type float (FP32_FIXED plans) or double (FP64 plans):
+ * x, y, z coordinates; q partial charges; rho intrinsic GB radii (> offset);
+ * screen HCT screening factors (>= 0). */
+typedef struct {
+    const void* x;
+    const void* y;
+    const void* z;
+    const void* q;
+    const void* rho;
+    const void* screen;
+} gbmc_atoms;
+
+/* Work-shape knob of the pair kernels: how many 64-atom j blocks one
+ * wavefront walks for its i block (>= 1; default 8).  Every 64 x 64 tile is
+ * rounded into fixed point on its own, so results are bitwise independent of
+ * this knob. */
+typedef struct {
+    int32_t j_blocks_per_item;
+} gbmc_tuning;
+
+typedef struct gbmc_plan gbmc_plan;
+typedef struct gbmc_sites gbmc_sites;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t gbmc_version(void);
+
+/* Thread-local message describing the last failure of this thread. */
+const char* gbmc_last_error(void);
+
+/* Host-only check of GB parameters: GBMC_ERR_UNSUPPORTED for kappa != 0,
+ * GBMC_ERR_INVALID for eps_in <= 0, eps_out <= 0, offset < 0 or non-finite
+ * values. */
+gbmc_status gbmc_params_validate(const gbmc_gb_params* params);
+
+/* Host-only: the pair-tile work list a plan with this layout would use.
+ * host_atom_offset[n_systems+1] (host) must start at 0 and be non-decreasing.
+ * Each item covers, for one system, the 64-atom i block I against the j
+ * blocks [J0, J1) with J0 >= I (every unordered pair of atoms lies in exactly
+ * one tile, the diagonal tile I == J holding the pairs inside one block).
+ * Items are ordered by decreasing cost.  *n_items receives the count; if items
+ * (host) is not NULL it receives 4 int32 per item: system, I, J0, J1 (the
+ * caller sizes it from a first call with items == NULL). */
+gbmc_status gbmc_schedule_build(int32_t n_systems, const int32_t* host_atom_offset,
+                                const gbmc_tuning* tuning, int32_t* n_items, int32_t* items);
+
+/* Create a plan for a batch of n_systems systems laid out back to back:
+ * system b owns atoms [host_atom_offset[b], host_atom_offset[b+1]) (host array,
+ * copied).  Empty systems are allowed.  tuning may be NULL (defaults).  The
+ * plan allocates its own device copy of the work list (the only device
+ * allocation the library makes, here and in gbmc_sites_create).  Requires the
+ * HIP device the plan will run on to be current. */
+gbmc_status gbmc_plan_create(gbmc_plan** plan, int32_t n_systems, const int32_t* host_atom_offset,
+                             gbmc_precision precision, const gbmc_tuning* tuning);
+void gbmc_plan_destroy(gbmc_plan* plan);
+
+/* Bytes of caller-owned device workspace a plan needs (256-byte aligned).
+ * The workspace carries per-atom state from gb_radii to gb_energy_forces and
+ * mc_state_dE; one workspace may serve one stream at a time. */
+size_t gbmc_plan_workspace_bytes(const gbmc_plan* plan);
+
+/* Effective Born radii (the GB model of section III.D; OBC formula):
+ *   I_i = sum_{j != i} H(r_ij; rho_i - offset, screen_j (rho_j - offset))
+ *   Psi_i = (rho_i - offset) I_i,  theta = alpha Psi - beta Psi^2 + gamma Psi^3
+ *   R_i = 1 / (1/(rho_i - offset) - tanh(theta)/rho_i)
+ * where H is the HCT pair integral (no cutoff).  Writes born_R[N_tot] (float or
+ * double per plan) and the per-atom state that gb_energy_forces and
+ * mc_state_dE use into workspace. */
+gbmc_status gb_radii(gbmc_plan* plan, const gbmc_atoms* atoms, const gbmc_gb_params* params,
+                     void* workspace, void* born_R, hipStream_t stream);
+
+/* Coulomb + GB energy and its derivatives, the electrostatics of the MD steps
+ * between Monte Carlo attempts (section III.A, Fig. 1):
+ *   E_C  = k sum_{i<j} q_i q_j / (eps_in r_ij)
+ *   E_GB = -(k/2)(1/eps_in - 1/eps_out) sum_i sum_j q_i q_j / f_ij,
+ *   f_ij = sqrt(r^2 + R_i R_j exp(-r^2 / (4 R_i R_j))),  f_ii = R_i,
+ * using the radii of the preceding gb_radii call on the same workspace and
+ * atoms.  Outputs (each may be NULL):
+ *   e_coul[B], e_gb[B]  double, per system;
+ *   force[N_tot][3]     -dE/dx including the Born-radius chain term;
+ *   dEdq[N_tot]         dE/dq (electrostatic potential, self term included);
+ *   dEdrho[N_tot]       dE/drho at fixed screening factors.
+ * With force, dEdq and dEdrho all NULL only the energies are computed. */
+gbmc_status gb_energy_forces(gbmc_plan* plan, const gbmc_atoms* atoms,
+                             const gbmc_gb_params* params, void* workspace,
+                             double* e_coul, double* e_gb, void* force, void* dEdq,
+                             void* dEdrho, hipStream_t stream);
+
+/* Titratable sites (host arrays, copied to the device; sites of one system
+ * must be disjoint):
+ *   site_system[S]          system of each site (non-decreasing)
+ *   site_kind[S]            0 = protonation, 1 = redox
+ *   site_atom_offset[S+1]   CSR into site_atoms (1..256 atoms per site)
+ *   site_atoms[...]         global atom indices inside the site's system
+ *   site_state_offset[S+1]  CSR into the state tables (2..8 states per site)
+ *   state_charge_offset[n_states_total+1] CSR into state_charges; row g holds
+ *                           the site's atom charges in state g
+ *   state_charges[...]      double
+ *   state_gref[n_states_total] double, kcal/mol: reference free energy of each
+ *                           state; for two states Gref(red) - Gref(oxi) =
+ *                           dG_elec,ref + F E0_ref (Eq. 8) and Gref(prot) -
+ *                           Gref(deprot) = dG_elec,ref + kB T ln10 pKa,ref (Eq. 9)
+ *   state_count[n_states_total]  protons n_H (protonation) or electrons n_e
+ *                           (redox) of each state.
+ * Candidates: every site in index order, and within a site every state other
+ * than the current one in ascending order; sites_n_candidates is their count. */
+gbmc_status gbmc_sites_validate(int32_t n_systems, const int32_t* host_atom_offset,
+                                int32_t n_sites, const int32_t* site_system,
+                                const int32_t* site_kind, const int32_t* site_atom_offset,
+                                const int32_t* site_atoms, const int32_t* site_state_offset,
+                                const int32_t* state_charge_offset, const int32_t* state_count);
+gbmc_status gbmc_sites_create(gbmc_plan* plan, gbmc_sites** sites, int32_t n_sites,
+                              const int32_t* site_system, const int32_t* site_kind,
+                              const int32_t* site_atom_offset, const int32_t* site_atoms,
+                              const int32_t* site_state_offset,
+                              const int32_t* state_charge_offset, const double* state_charges,
+                              const double* state_gref, const int32_t* state_count);
+void gbmc_sites_destroy(gbmc_sites* sites);
+int32_t gbmc_sites_n_candidates(const gbmc_sites* sites);
+/* Bytes of caller-owned device workspace mc_state_dE and mc_step need. */
+size_t gbmc_sites_workspace_bytes(const gbmc_sites* sites);
+
+/* Delta E_elec and Delta G of every candidate state change (sections II.A-B):
+ * the electrostatic energy difference between the proposed and the current
+ * state at fixed coordinates and Born radii, in FP64,
+ *   dE = dq . phi + 1/2 dq . K . dq,   dq = Q_m[s'] - Q_m[s] on the site atoms,
+ * and
+ *   protonation: dG = dE + kB T ln10 pH[b] (n_H(s') - n_H(s)) - (Gref(s') - Gref(s))
+ *   redox:       dG = dE + F E_volt[b] (n_e(s') - n_e(s)) - (Gref(s') - Gref(s)),
+ * the multi-state form of Eqs. 9 and 8.  current_state[S] (int32), pH[B] and
+ * E_volt[B] (double) are device arrays; dE_elec and dG receive n_candidates
+ * doubles (dG may be NULL).  Uses the Born radii of the last gb_radii call on
+ * workspace; atoms->q must be the charges of current_state. */
+gbmc_status mc_state_dE(gbmc_plan* plan, const gbmc_sites* sites, const gbmc_atoms* atoms,
+                        const gbmc_gb_params* params, void* workspace, void* site_workspace,
+                        const int32_t* current_state, const double* pH, const double* E_volt,
+                        double T, double* dE_elec, double* dG, hipStream_t stream);
+
+/* One implicit-solvent C(pH,E)MD attempt pair per system (section III.A.1,
+ * Fig. 1): a protonation attempt on one protonation site picked uniformly,
+ * then a redox attempt on one redox site picked uniformly; each proposes one
+ * of the site's other states uniformly and accepts iff u < exp(-dG/(kB T))
+ * (Metropolis, FP64).  The redox attempt sees the charges left by an accepted
+ * protonation attempt: its dG gains dq_redox . K . dq_prot.  Inputs dE_elec
+ * and dG come from mc_state_dE on the same state.  u[B][6] (double, device):
+ * site pick, state pick, acceptance for protonation, then for redox; a pick
+ * takes floor(u * count) clamped to count - 1.  Updates q[N_tot] (float or
+ * double per plan) and current_state[S] in place.  Optional outputs:
+ * n_electrons[B] (int32) sum of n_e over each system's redox sites after the
+ * step; counters[S][2] (int64) attempts and acceptances added per site;
+ * accepted[B][2] (int32) per system flags for the two attempts. */
+gbmc_status mc_step(gbmc_plan* plan, const gbmc_sites* sites, const gbmc_atoms* atoms, void* q,
+                    const gbmc_gb_params* params, void* workspace, void* site_workspace,
+                    int32_t* current_state, const double* pH, const double* E_volt, double T,
+                    const double* dE_elec, const double* dG, const double* u,
+                    int32_t* n_electrons, int64_t* counters, int32_t* accepted,
+                    hipStream_t stream);
+
+/* E-REMD exchange attempt (section II.C, Eqs. 14-15; pairing of section
+ * III.B).  Rungs 0..M-1 are ordered by increasing redox potential E_rung[M]
+ * (double, volt); rep_of_rung[M] (int32, in/out) holds the replica at each
+ * rung.  parity 0 pairs rungs (0,1),(2,3),...; parity 1 pairs (1,2),(3,4),...
+ * and, when wrap is nonzero and M is even and > 2, also (M-1, 0).  For the
+ * pair (rung l holding replica i, rung n holding replica j):
+ *   Delta = F (E_n - E_l)(N_i - N_j) / (kB T)
+ * and the pair swaps rungs iff Delta < 0 or u[p] < exp(-Delta).  Ne_of_rep[M]
+ * (int32) are electron counts, u[p] (double) and accepted[p] (int32) are
+ * indexed by the pair's position in the list above.  E_of_rep[M] (double,
+ * output) receives every replica's redox potential after the attempt.
+ * Replicas at different pH form separate ladders and separate calls. */
+gbmc_status remd_exchange(int32_t n_rep, const double* E_rung, const int32_t* Ne_of_rep,
+                          int32_t* rep_of_rung, double T, int32_t parity, int32_t wrap,
+                          const double* u, int32_t* accepted, double* E_of_rep,
+                          hipStream_t stream);
+
+/* Kernel timing hook (tracing).  While enabled, every compute call on this
+ * plan records HIP events on its stream immediately before and after each
+ * kernel of the hot path; gbmc_plan_kernel_ms waits for the last recorded
+ * events and writes the duration (ms) of the most recent launch of each kernel
+ * into ms[GBMC_N_KERNELS] (-1 for kernels not launched since enabling).
+ * Intended for eager calls, not for calls captured into a graph. */
+enum {
+    GBMC_K_RADII_PAIRS = 0,    /* descreening pair pass of gb_radii */
+    GBMC_K_ENERGY_PAIRS = 1,   /* energy / explicit force pair pass */
+    GBMC_K_CHAIN_PAIRS = 2,    /* Born-radius chain pair pass */
+    GBMC_K_SITE_ROWS = 3,      /* FP64 potential rows of mc_state_dE */
+    GBMC_K_SITE_DE = 4,        /* per-site Delta E / Delta G of mc_state_dE */
+    GBMC_K_MC_STEP = 5,        /* Metropolis step */
+    GBMC_N_KERNELS = 6
+};
+gbmc_status gbmc_plan_set_timing(gbmc_plan* plan, int32_t enable);
+gbmc_status gbmc_plan_kernel_ms(gbmc_plan* plan, float* ms);
+
+/* Reads and clears the workspace's fixed-point overflow flag.  Synchronises
+ * stream.  Returns GBMC_ERR_OVERFLOW (and *flag = 1) if any accumulator since
+ * the last gb_radii call (which clears the flag) or the last check would have
+ * exceeded 2^62 in magnitude. */
+gbmc_status gbmc_check_overflow(const gbmc_plan* plan, void* workspace, hipStream_t stream,
+                                int32_t* flag);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GBMC_H */

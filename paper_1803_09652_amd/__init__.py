@@ -1,0 +1,15 @@
+"""MI355X-native GB-OBC electrostatics with constant-pH / constant-redox Monte
+Carlo and E-REMD exchange (after arXiv:1803.09652).
+
+The compute path is libgbmc.so (HIP kernels for gfx950 behind the C ABI in
+include/gbmc.h); this package is its Python binding.
+"""
+from ._lib import GbmcError, load  # noqa: F401
+from .api import (  # noqa: F401
+    IGB2, IGB5, KIND_PROT, KIND_REDOX, Atoms, GBEnergy, GBParams, Plan, Sites, check_overflow,
+    energy_forces, mc_state_dE, mc_step, radii, remd_exchange,
+)
+
+__all__ = ["GbmcError", "load", "IGB2", "IGB5", "KIND_PROT", "KIND_REDOX", "Atoms", "GBEnergy",
+           "GBParams", "Plan", "Sites", "check_overflow", "energy_forces", "mc_state_dE", "mc_step",
+           "radii", "remd_exchange"]

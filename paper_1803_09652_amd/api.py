@@ -1,0 +1,339 @@
+"""Python binding of libgbmc: torch tensors in, libgbmc calls, torch tensors out.
+
+Every computation runs in the HIP kernels behind include/gbmc.h; this module
+only checks shapes and dtypes, allocates output tensors and passes device
+pointers plus the current HIP stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+KIND_PROT = 0
+KIND_REDOX = 1
+
+
+@dataclass(frozen=True)
+class GBParams:
+    """GB-OBC parameters (default: the igb=5 set; see IGB2 for the paper's)."""
+    alpha: float = 1.0
+    beta: float = 0.8
+    gamma: float = 4.85
+    offset: float = 0.09
+    eps_in: float = 1.0
+    eps_out: float = 78.5
+    coulomb_k: float = 332.0522
+    kappa: float = 0.0
+
+    def c(self) -> L.gbmc_gb_params:
+        return L.gbmc_gb_params(self.alpha, self.beta, self.gamma, self.offset, self.eps_in,
+                                self.eps_out, self.coulomb_k, self.kappa)
+
+
+IGB5 = GBParams()
+IGB2 = GBParams(alpha=0.8, beta=0.0, gamma=2.909125)
+
+
+def _stream(device) -> C.c_void_p:
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _i32p(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _f64p(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Plan:
+    """A batch layout (systems back to back) and a precision.
+
+    precision: "fp32" (FP32 pair arithmetic, 64-bit fixed-point sums) or
+    "fp64".  Owns the plan's device workspace."""
+
+    def __init__(self, atom_offset: Sequence[int], precision: str = "fp32",
+                 j_blocks_per_item: Optional[int] = None, device=None):
+        lib = L.load()
+        self.offset = np.ascontiguousarray(atom_offset, dtype=np.int32)
+        if self.offset.ndim != 1 or self.offset.size < 1:
+            raise ValueError("atom_offset must be a 1-D array of B+1 offsets")
+        if precision not in ("fp32", "fp64"):
+            raise ValueError("precision must be 'fp32' or 'fp64'")
+        self.precision = precision
+        self.dtype = torch.float32 if precision == "fp32" else torch.float64
+        self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
+            else torch.device(device)
+        tun = None
+        if j_blocks_per_item is not None:
+            tun = C.byref(L.gbmc_tuning(int(j_blocks_per_item)))
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(lib.gbmc_plan_create(C.byref(h), int(self.offset.size - 1), _i32p(self.offset),
+                                         L.GBMC_FP32_FIXED if precision == "fp32" else L.GBMC_FP64,
+                                         tun))
+        self._h = h
+        nbytes = int(lib.gbmc_plan_workspace_bytes(h))
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+        if self.workspace.data_ptr() % 256:
+            raise RuntimeError("workspace is not 256-byte aligned")
+        self.atom_sys = torch.repeat_interleave(
+            torch.arange(self.n_systems, device=self.device),
+            torch.as_tensor(np.diff(self.offset).astype(np.int64), device=self.device))
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n_systems(self) -> int:
+        return int(self.offset.size - 1)
+
+    @property
+    def n_atoms(self) -> int:
+        return int(self.offset[-1])
+
+    def set_timing(self, enable: bool = True) -> None:
+        """Record HIP events around each hot-path kernel of later eager calls."""
+        L.check(L.load().gbmc_plan_set_timing(self._h, int(bool(enable))))
+
+    def kernel_ms(self) -> dict:
+        """Duration (ms) of the most recent launch of each timed kernel."""
+        ms = (C.c_float * len(L.KERNEL_NAMES))()
+        L.check(L.load().gbmc_plan_kernel_ms(self._h, ms))
+        return {n: float(v) for n, v in zip(L.KERNEL_NAMES, ms) if v >= 0.0}
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                L.load().gbmc_plan_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+
+class Atoms:
+    """Per-atom SoA device tensors of one plan's dtype."""
+
+    def __init__(self, plan: Plan, x, y, z, q, rho, screen):
+        def dev(a):
+            t = torch.as_tensor(a, dtype=plan.dtype, device=plan.device)
+            t = t.contiguous()
+            if t.ndim != 1 or t.shape[0] != plan.n_atoms:
+                raise ValueError("atom arrays must be 1-D with one entry per atom")
+            return t
+        self.x, self.y, self.z = dev(x), dev(y), dev(z)
+        self.q, self.rho, self.screen = dev(q), dev(rho), dev(screen)
+
+    @classmethod
+    def from_batch(cls, plan: Plan, batch) -> "Atoms":
+        return cls(plan, batch.x, batch.y, batch.z, batch.q, batch.rho, batch.screen)
+
+    def c(self, q: Optional[torch.Tensor] = None) -> L.gbmc_atoms:
+        return L.gbmc_atoms(self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr(),
+                            (self.q if q is None else q).data_ptr(), self.rho.data_ptr(),
+                            self.screen.data_ptr())
+
+
+def radii(plan: Plan, atoms: Atoms, params: GBParams = IGB5) -> torch.Tensor:
+    """Effective Born radii R[N] (plan dtype); leaves the per-atom state in the
+    plan's workspace for energy_forces and mc_state_dE."""
+    R = torch.empty(plan.n_atoms, dtype=plan.dtype, device=plan.device)
+    a, p = atoms.c(), params.c()
+    L.check(L.load().gb_radii(plan.handle, C.byref(a), C.byref(p), _ptr(plan.workspace), _ptr(R),
+                              _stream(plan.device)))
+    return R
+
+
+def energy_forces(plan: Plan, atoms: Atoms, params: GBParams = IGB5, force: bool = True,
+                  dEdq: bool = True, dEdrho: bool = True) -> dict:
+    """E_C and E_GB per system (float64 [B]) and the requested gradients.
+    Needs a preceding radii() on the same plan and atoms."""
+    dev, dt, n = plan.device, plan.dtype, plan.n_atoms
+    out = {
+        "e_coul": torch.empty(plan.n_systems, dtype=torch.float64, device=dev),
+        "e_gb": torch.empty(plan.n_systems, dtype=torch.float64, device=dev),
+        "force": torch.empty((n, 3), dtype=dt, device=dev) if force else None,
+        "dEdq": torch.empty(n, dtype=dt, device=dev) if dEdq else None,
+        "dEdrho": torch.empty(n, dtype=dt, device=dev) if dEdrho else None,
+    }
+    a, p = atoms.c(), params.c()
+    L.check(L.load().gb_energy_forces(plan.handle, C.byref(a), C.byref(p), _ptr(plan.workspace),
+                                      _ptr(out["e_coul"]), _ptr(out["e_gb"]), _ptr(out["force"]),
+                                      _ptr(out["dEdq"]), _ptr(out["dEdrho"]),
+                                      _stream(plan.device)))
+    return out
+
+
+class Sites:
+    """Titratable-site tables of a plan (static), with the site workspace.
+
+    Arrays follow include/gbmc.h (global atom indices); a ``synth.Batch``
+    carries them under the same names."""
+
+    def __init__(self, plan: Plan, site_system, site_kind, site_atom_offset, site_atoms,
+                 site_state_offset, state_charge_offset, state_charges, state_gref, state_count):
+        lib = L.load()
+        i32 = lambda v: np.ascontiguousarray(v, dtype=np.int32)
+        f64 = lambda v: np.ascontiguousarray(v, dtype=np.float64)
+        self.site_system = i32(site_system)
+        self.site_kind = i32(site_kind)
+        self.site_atom_offset = i32(site_atom_offset)
+        self.site_atoms = i32(site_atoms)
+        self.site_state_offset = i32(site_state_offset)
+        self.state_charge_offset = i32(state_charge_offset)
+        self.state_charges = f64(state_charges)
+        self.state_gref = f64(state_gref)
+        self.state_count = i32(state_count)
+        self.plan = plan
+        h = C.c_void_p()
+        with torch.cuda.device(plan.device):
+            L.check(lib.gbmc_sites_create(plan.handle, C.byref(h), int(self.site_kind.size),
+                                          _i32p(self.site_system), _i32p(self.site_kind),
+                                          _i32p(self.site_atom_offset), _i32p(self.site_atoms),
+                                          _i32p(self.site_state_offset),
+                                          _i32p(self.state_charge_offset),
+                                          _f64p(self.state_charges), _f64p(self.state_gref),
+                                          _i32p(self.state_count)))
+        self._h = h
+        self.n_sites = int(self.site_kind.size)
+        self.n_candidates = int(lib.gbmc_sites_n_candidates(h))
+        nbytes = int(lib.gbmc_sites_workspace_bytes(h))
+        self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=plan.device)
+
+    @classmethod
+    def from_batch(cls, plan: Plan, batch, state_gref=None) -> "Sites":
+        gref = np.zeros(batch.state_count.size) if state_gref is None else state_gref
+        return cls(plan, batch.site_system, batch.site_kind, batch.site_atom_offset,
+                   batch.site_atoms, batch.site_state_offset, batch.state_charge_offset,
+                   batch.state_charges, gref, batch.state_count)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                L.load().gbmc_sites_destroy(h)
+            except Exception:
+                pass
+            self._h = None
+
+
+def _dev_f64(v, n, device):
+    t = torch.as_tensor(v, dtype=torch.float64, device=device)
+    if t.ndim == 0:
+        t = t.expand(n)
+    return t.contiguous()
+
+
+def mc_state_dE(plan: Plan, sites: Sites, atoms: Atoms, current_state: torch.Tensor, pH, E_volt,
+                T: float = 300.0, params: GBParams = IGB5, with_dG: bool = True):
+    """Delta E_elec and Delta G (float64 [n_candidates]) of every candidate
+    state change.  Needs a preceding radii() on the same plan and atoms."""
+    dev = plan.device
+    dE = torch.empty(sites.n_candidates, dtype=torch.float64, device=dev)
+    dG = torch.empty(sites.n_candidates, dtype=torch.float64, device=dev) if with_dG else None
+    pH_t = _dev_f64(pH, plan.n_systems, dev)
+    E_t = _dev_f64(E_volt, plan.n_systems, dev)
+    if current_state.dtype != torch.int32 or current_state.device != dev:
+        raise ValueError("current_state must be an int32 tensor on the plan's device")
+    a, p = atoms.c(), params.c()
+    L.check(L.load().mc_state_dE(plan.handle, sites.handle, C.byref(a), C.byref(p),
+                                 _ptr(plan.workspace), _ptr(sites.workspace), _ptr(current_state),
+                                 _ptr(pH_t), _ptr(E_t), float(T), _ptr(dE), _ptr(dG),
+                                 _stream(dev)))
+    return dE, dG
+
+
+def mc_step(plan: Plan, sites: Sites, atoms: Atoms, current_state: torch.Tensor, pH, E_volt,
+            dE: torch.Tensor, dG: torch.Tensor, u: torch.Tensor, T: float = 300.0,
+            params: GBParams = IGB5, counters: Optional[torch.Tensor] = None) -> dict:
+    """One protonation + redox attempt pair per system; updates atoms.q and
+    current_state in place."""
+    dev = plan.device
+    if u.dtype != torch.float64 or u.shape != (plan.n_systems, 6):
+        raise ValueError("u must be float64 [B, 6]")
+    pH_t = _dev_f64(pH, plan.n_systems, dev)
+    E_t = _dev_f64(E_volt, plan.n_systems, dev)
+    ne = torch.empty(plan.n_systems, dtype=torch.int32, device=dev)
+    acc = torch.empty((plan.n_systems, 2), dtype=torch.int32, device=dev)
+    a, p = atoms.c(), params.c()
+    L.check(L.load().mc_step(plan.handle, sites.handle, C.byref(a), _ptr(atoms.q), C.byref(p),
+                             _ptr(plan.workspace), _ptr(sites.workspace), _ptr(current_state),
+                             _ptr(pH_t), _ptr(E_t), float(T), _ptr(dE), _ptr(dG),
+                             _ptr(u.contiguous()), _ptr(ne), _ptr(counters), _ptr(acc),
+                             _stream(dev)))
+    return {"n_electrons": ne, "accepted": acc}
+
+
+def remd_exchange(E_rung: torch.Tensor, Ne_of_rep: torch.Tensor, rep_of_rung: torch.Tensor,
+                  parity: int, u: torch.Tensor, T: float = 300.0, wrap: bool = True):
+    """E-REMD exchange attempt; rep_of_rung (int32) is updated in place.
+    Returns (accepted[n_pairs] int32, E_of_rep[M] float64)."""
+    M = int(E_rung.shape[0])
+    dev = E_rung.device
+    acc = torch.empty(max(M, 1), dtype=torch.int32, device=dev)
+    Eo = torch.empty(M, dtype=torch.float64, device=dev)
+    L.check(L.load().remd_exchange(M, _ptr(E_rung), _ptr(Ne_of_rep), _ptr(rep_of_rung), float(T),
+                                   int(parity), int(bool(wrap)), _ptr(u), _ptr(acc), _ptr(Eo),
+                                   _stream(dev)))
+    inner = (M - parity) // 2
+    n_pairs = inner + (1 if (parity == 1 and wrap and M % 2 == 0 and M > 2) else 0)
+    return acc[:n_pairs], Eo
+
+
+def check_overflow(plan: Plan) -> bool:
+    """True if a fixed-point accumulator overflowed since the last radii()."""
+    flag = C.c_int32(0)
+    st = L.load().gbmc_check_overflow(plan.handle, _ptr(plan.workspace), _stream(plan.device),
+                                      C.byref(flag))
+    if st not in (L.GBMC_OK, L.GBMC_ERR_OVERFLOW):
+        L.check(st)
+    return bool(flag.value)
+
+
+class GBEnergy(torch.autograd.Function):
+    """E = E_C + E_GB per system (float64 [B]) as a differentiable function of
+    positions [N, 3], charges [N] and intrinsic radii [N] (screens fixed).
+
+    forward runs the radii and the energy-only pair pass; backward runs the
+    hand-written gradient kernels (pair forces, G = dE/dR, phi = dE/dq, then
+    the Born-radius chain and dE/drho)."""
+
+    @staticmethod
+    def forward(ctx, pos, q, rho, screen, plan: Plan, params: GBParams = IGB5):
+        pos_d, q_d, rho_d, scr_d = (t.detach() for t in (pos, q, rho, screen))
+        atoms = Atoms(plan, pos_d[:, 0], pos_d[:, 1], pos_d[:, 2], q_d, rho_d, scr_d)
+        radii(plan, atoms, params)
+        out = energy_forces(plan, atoms, params, force=False, dEdq=False, dEdrho=False)
+        ctx.plan, ctx.params = plan, params
+        ctx.save_for_backward(pos_d, q_d, rho_d, scr_d)
+        return out["e_coul"] + out["e_gb"]
+
+    @staticmethod
+    def backward(ctx, gE):
+        pos, q, rho, screen = ctx.saved_tensors
+        plan, params = ctx.plan, ctx.params
+        atoms = Atoms(plan, pos[:, 0], pos[:, 1], pos[:, 2], q, rho, screen)
+        radii(plan, atoms, params)
+        g = energy_forces(plan, atoms, params, force=ctx.needs_input_grad[0],
+                          dEdq=ctx.needs_input_grad[1], dEdrho=ctx.needs_input_grad[2])
+        w = gE.to(plan.dtype)[plan.atom_sys]
+        gpos = -g["force"] * w[:, None] if g["force"] is not None else None
+        gq = g["dEdq"] * w if g["dEdq"] is not None else None
+        grho = g["dEdrho"] * w if g["dEdrho"] is not None else None
+        return gpos, gq, grho, None, None, None

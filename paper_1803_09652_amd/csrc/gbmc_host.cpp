@@ -1,0 +1,677 @@
+// gbmc_host.cpp -- host runtime behind the C ABI in include/gbmc.h: plans,
+// work schedules, validation, workspace layout and kernel launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <initializer_list>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gbmc.h"
+#include "gbmc_internal.h"
+
+using namespace gbmc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+gbmc_status fail(gbmc_status st, const std::string& msg)
+{
+    g_last_error = msg;
+    return st;
+}
+
+gbmc_status hip_fail(hipError_t e, const char* where)
+{
+    return fail(GBMC_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+constexpr int32_t kDefaultJBlocks = 8;
+
+}  // namespace
+
+struct gbmc_plan {
+    int32_t n_sys = 0;
+    int32_t n_atoms = 0;
+    gbmc_precision prec = GBMC_FP32_FIXED;
+    gbmc_tuning tuning{kDefaultJBlocks};
+    std::vector<int32_t> offset;     // [B+1]
+    int32_t n_items = 0;
+    WorkItem* d_items = nullptr;
+    int device = 0;
+    // timing hook: events bracketing each timed kernel, recorded while enabled
+    bool timing = false;
+    hipEvent_t ev[2 * kNumKernels] = {};
+    bool recorded[kNumKernels] = {};
+    // workspace layout (byte offsets)
+    size_t off_I, off_F, off_G, off_phi, off_drho, off_E, off_I64, off_R64, off_T64, off_dR64,
+        off_G64, off_B64, off_Rt, off_at, off_Brt, off_ovf, ws_bytes;
+};
+
+struct gbmc_sites {
+    const gbmc_plan* plan = nullptr;
+    int32_t n_sites = 0, n_cand = 0, n_rowitems = 0;
+    size_t phi_part_len = 0;
+    void* d_mem = nullptr;
+    SiteDev dev{};
+};
+
+// ------------------------------------------------------------------ schedule
+
+static gbmc_status check_offsets(int32_t n_systems, const int32_t* off)
+{
+    if (n_systems < 0) return fail(GBMC_ERR_INVALID, "n_systems < 0");
+    if (n_systems > 0 && !off) return fail(GBMC_ERR_INVALID, "atom_offset is NULL");
+    if (n_systems == 0) return GBMC_OK;
+    if (off[0] != 0) return fail(GBMC_ERR_INVALID, "atom_offset[0] must be 0");
+    for (int32_t b = 0; b < n_systems; ++b) {
+        if (off[b + 1] < off[b]) return fail(GBMC_ERR_INVALID, "atom_offset must be non-decreasing");
+        if ((int64_t)off[b + 1] - off[b] > (int64_t)kTile * 65535)
+            return fail(GBMC_ERR_UNSUPPORTED, "a system has more than 4,194,240 atoms");
+    }
+    return GBMC_OK;
+}
+
+static gbmc_status build_items(int32_t n_systems, const int32_t* off, const gbmc_tuning& t,
+                               std::vector<WorkItem>& items)
+{
+    items.clear();
+    const int32_t jb = t.j_blocks_per_item;
+    for (int32_t b = 0; b < n_systems; ++b) {
+        const int32_t n = off[b + 1] - off[b];
+        const int32_t nb = (n + kTile - 1) / kTile;
+        for (int32_t I = 0; I < nb; ++I)
+            for (int32_t J0 = I; J0 < nb; J0 += jb) {
+                WorkItem w{};
+                w.base = off[b];
+                w.n = n;
+                w.sys = b;
+                w.I = I;
+                w.J0 = J0;
+                w.J1 = std::min(nb, J0 + jb);
+                items.push_back(w);
+            }
+    }
+    // longest first (a diagonal tile costs half an off-diagonal one); ties keep
+    // the construction order so the schedule is deterministic
+    auto cost = [](const WorkItem& w) { return 2 * (w.J1 - w.J0) - (w.J0 == w.I ? 1 : 0); };
+    std::stable_sort(items.begin(), items.end(),
+                     [&](const WorkItem& a, const WorkItem& b) { return cost(a) > cost(b); });
+    return GBMC_OK;
+}
+
+static gbmc_status check_tuning(const gbmc_tuning* in, gbmc_tuning& out)
+{
+    out = gbmc_tuning{kDefaultJBlocks};
+    if (!in) return GBMC_OK;
+    if (in->j_blocks_per_item < 1 || in->j_blocks_per_item > 65535)
+        return fail(GBMC_ERR_INVALID, "tuning.j_blocks_per_item must be in [1, 65535]");
+    out = *in;
+    return GBMC_OK;
+}
+
+template <typename T>
+static Work<T> carve(const gbmc_plan* p, void* ws)
+{
+    char* b = static_cast<char*>(ws);
+    Work<T> w;
+    w.I_fx = reinterpret_cast<unsigned long long*>(b + p->off_I);
+    w.F_fx = reinterpret_cast<unsigned long long*>(b + p->off_F);
+    w.G_fx = reinterpret_cast<unsigned long long*>(b + p->off_G);
+    w.phi_fx = reinterpret_cast<unsigned long long*>(b + p->off_phi);
+    w.drho_fx = reinterpret_cast<unsigned long long*>(b + p->off_drho);
+    w.E_fx = reinterpret_cast<unsigned long long*>(b + p->off_E);
+    w.I64 = reinterpret_cast<double*>(b + p->off_I64);
+    w.R64 = reinterpret_cast<double*>(b + p->off_R64);
+    w.T64 = reinterpret_cast<double*>(b + p->off_T64);
+    w.dRdPsi64 = reinterpret_cast<double*>(b + p->off_dR64);
+    w.G64 = reinterpret_cast<double*>(b + p->off_G64);
+    w.B64 = reinterpret_cast<double*>(b + p->off_B64);
+    w.R_t = reinterpret_cast<T*>(b + p->off_Rt);
+    w.a_t = reinterpret_cast<T*>(b + p->off_at);
+    w.Brt_t = reinterpret_cast<T*>(b + p->off_Brt);
+    w.ovf = reinterpret_cast<int*>(b + p->off_ovf);
+    return w;
+}
+
+static void layout(gbmc_plan* p)
+{
+    const size_t N = (size_t)p->n_atoms, B = (size_t)p->n_sys;
+    const size_t ts = p->prec == GBMC_FP64 ? 8 : 4;
+    size_t o = 0;
+    auto seg = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+    p->off_I = seg(8 * (N + 1));           // the overflow word follows I_fx
+    p->off_ovf = p->off_I + 8 * N;
+    // F (3N), G, phi, drho are one contiguous run of 6N int64: cleared by one kernel
+    p->off_F = seg(8 * 6 * N);
+    p->off_G = p->off_F + 8 * 3 * N;
+    p->off_phi = p->off_G + 8 * N;
+    p->off_drho = p->off_phi + 8 * N;
+    p->off_E = seg(8 * 2 * B);
+    p->off_I64 = seg(8 * N);
+    p->off_R64 = seg(8 * N);
+    p->off_T64 = seg(8 * N);
+    p->off_dR64 = seg(8 * N);
+    p->off_G64 = seg(8 * N);
+    p->off_B64 = seg(8 * N);
+    p->off_Rt = seg(ts * N);
+    p->off_at = seg(ts * N);
+    p->off_Brt = seg(ts * N);
+    p->ws_bytes = o;
+}
+
+static GBConst make_const(const gbmc_gb_params* gp)
+{
+    GBConst c;
+    c.alpha = gp->alpha;
+    c.beta = gp->beta;
+    c.gamma = gp->gamma;
+    c.offset = gp->offset;
+    c.kC = gp->coulomb_k / gp->eps_in;
+    c.kT = gp->coulomb_k * (1.0 / gp->eps_in - 1.0 / gp->eps_out);
+    return c;
+}
+
+static gbmc_status check_call(const gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp,
+                              const void* ws, bool need_q)
+{
+    if (!p) return fail(GBMC_ERR_INVALID, "plan is NULL");
+    if (!gp) return fail(GBMC_ERR_INVALID, "params is NULL");
+    gbmc_status st = gbmc_params_validate(gp);
+    if (st != GBMC_OK) return st;
+    if (p->n_atoms == 0) return GBMC_OK;
+    if (!a || !a->x || !a->y || !a->z || !a->rho || !a->screen || (need_q && !a->q))
+        return fail(GBMC_ERR_INVALID, "an atom array is NULL");
+    if (!ws) return fail(GBMC_ERR_INVALID, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+        return fail(GBMC_ERR_INVALID, "workspace must be 256-byte aligned");
+    return GBMC_OK;
+}
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int32_t gbmc_version(void) { return 10000; }
+
+const char* gbmc_last_error(void) { return g_last_error.c_str(); }
+
+gbmc_status gbmc_params_validate(const gbmc_gb_params* p)
+{
+    if (!p) return fail(GBMC_ERR_INVALID, "params is NULL");
+    const double v[] = {p->alpha, p->beta, p->gamma, p->offset, p->eps_in, p->eps_out,
+                        p->coulomb_k, p->kappa};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(GBMC_ERR_INVALID, "non-finite GB parameter");
+    if (p->kappa != 0.0) return fail(GBMC_ERR_UNSUPPORTED, "salt screening (kappa != 0) is not supported");
+    if (p->eps_in <= 0.0 || p->eps_out <= 0.0) return fail(GBMC_ERR_INVALID, "dielectric constants must be > 0");
+    if (p->offset < 0.0) return fail(GBMC_ERR_INVALID, "offset must be >= 0");
+    return GBMC_OK;
+}
+
+gbmc_status gbmc_schedule_build(int32_t n_systems, const int32_t* host_atom_offset,
+                                const gbmc_tuning* tuning, int32_t* n_items, int32_t* items)
+{
+    try {
+        if (!n_items) return fail(GBMC_ERR_INVALID, "n_items is NULL");
+        gbmc_status st = check_offsets(n_systems, host_atom_offset);
+        if (st != GBMC_OK) return st;
+        gbmc_tuning t;
+        st = check_tuning(tuning, t);
+        if (st != GBMC_OK) return st;
+        std::vector<WorkItem> v;
+        build_items(n_systems, host_atom_offset, t, v);
+        if (v.size() > 0x7fffffff) return fail(GBMC_ERR_UNSUPPORTED, "too many work items");
+        *n_items = (int32_t)v.size();
+        if (items)
+            for (size_t k = 0; k < v.size(); ++k) {
+                items[4 * k + 0] = v[k].sys;
+                items[4 * k + 1] = v[k].I;
+                items[4 * k + 2] = v[k].J0;
+                items[4 * k + 3] = v[k].J1;
+            }
+        return GBMC_OK;
+    } catch (const std::exception& e) {
+        return fail(GBMC_ERR_INVALID, e.what());
+    }
+}
+
+gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* host_atom_offset,
+                             gbmc_precision precision, const gbmc_tuning* tuning)
+{
+    try {
+        if (!out) return fail(GBMC_ERR_INVALID, "plan out-pointer is NULL");
+        *out = nullptr;
+        gbmc_status st = check_offsets(n_systems, host_atom_offset);
+        if (st != GBMC_OK) return st;
+        if (precision != GBMC_FP32_FIXED && precision != GBMC_FP64)
+            return fail(GBMC_ERR_INVALID, "unknown precision");
+        gbmc_tuning t;
+        st = check_tuning(tuning, t);
+        if (st != GBMC_OK) return st;
+        std::vector<WorkItem> items;
+        build_items(n_systems, host_atom_offset, t, items);
+        auto* p = new gbmc_plan();
+        p->n_sys = n_systems;
+        p->n_atoms = n_systems > 0 ? host_atom_offset[n_systems] : 0;
+        p->prec = precision;
+        p->tuning = t;
+        p->offset.assign(host_atom_offset, host_atom_offset + n_systems + 1);
+        if (n_systems == 0) p->offset.assign(1, 0);
+        p->n_items = (int32_t)items.size();
+        layout(p);
+        hipError_t e = hipGetDevice(&p->device);
+        if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
+        if (!items.empty()) {
+            e = hipMalloc(&p->d_items, items.size() * sizeof(WorkItem));
+            if (e != hipSuccess) { delete p; return hip_fail(e, "hipMalloc(work list)"); }
+            e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
+            if (e != hipSuccess) { (void)hipFree(p->d_items); delete p; return hip_fail(e, "hipMemcpy(work list)"); }
+        }
+        *out = p;
+        return GBMC_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(GBMC_ERR_INVALID, "host allocation failed");
+    }
+}
+
+void gbmc_plan_destroy(gbmc_plan* p)
+{
+    if (!p) return;
+    if (p->d_items) (void)hipFree(p->d_items);
+    for (hipEvent_t e : p->ev)
+        if (e) (void)hipEventDestroy(e);
+    delete p;
+}
+
+gbmc_status gbmc_plan_set_timing(gbmc_plan* p, int32_t enable)
+{
+    if (!p) return fail(GBMC_ERR_INVALID, "plan is NULL");
+    if (enable && !p->ev[0])
+        for (hipEvent_t& e : p->ev) {
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return hip_fail(r, "hipEventCreate");
+        }
+    p->timing = enable != 0;
+    for (bool& r : p->recorded) r = false;
+    return GBMC_OK;
+}
+
+gbmc_status gbmc_plan_kernel_ms(gbmc_plan* p, float* ms)
+{
+    if (!p || !ms) return fail(GBMC_ERR_INVALID, "NULL argument");
+    for (int k = 0; k < kNumKernels; ++k) {
+        ms[k] = -1.0f;
+        if (!p->recorded[k]) continue;
+        hipError_t r = hipEventSynchronize(p->ev[2 * k + 1]);
+        if (r == hipSuccess) r = hipEventElapsedTime(&ms[k], p->ev[2 * k], p->ev[2 * k + 1]);
+        if (r != hipSuccess) return hip_fail(r, "hipEventElapsedTime");
+    }
+    return GBMC_OK;
+}
+
+size_t gbmc_plan_workspace_bytes(const gbmc_plan* p) { return p ? p->ws_bytes : 0; }
+
+static hipEvent_t* events(gbmc_plan* p, std::initializer_list<int> ids)
+{
+    if (!p->timing) return nullptr;
+    for (int k : ids) p->recorded[k] = true;
+    return p->ev;
+}
+
+gbmc_status gb_radii(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp, void* ws,
+                     void* born_R, hipStream_t s)
+{
+    gbmc_status st = check_call(p, a, gp, ws, false);
+    if (st != GBMC_OK || p->n_atoms == 0) return st;
+    GBConst c = make_const(gp);
+    hipError_t e;
+    if (p->prec == GBMC_FP32_FIXED)
+        e = launch_radii<float>(p->d_items, p->n_items, p->n_atoms, nullptr, (const float*)a->x,
+                                (const float*)a->y, (const float*)a->z, (const float*)a->rho,
+                                (const float*)a->screen, c, carve<float>(p, ws), (float*)born_R, s,
+                                p->n_items > 0 ? events(p, {kKRadii}) : nullptr);
+    else
+        e = launch_radii<double>(p->d_items, p->n_items, p->n_atoms, nullptr, (const double*)a->x,
+                                 (const double*)a->y, (const double*)a->z, (const double*)a->rho,
+                                 (const double*)a->screen, c, carve<double>(p, ws), (double*)born_R, s,
+                                 p->n_items > 0 ? events(p, {kKRadii}) : nullptr);
+    return e == hipSuccess ? GBMC_OK : hip_fail(e, "gb_radii launch");
+}
+
+gbmc_status gb_energy_forces(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp, void* ws,
+                             double* e_coul, double* e_gb, void* force, void* dEdq, void* dEdrho,
+                             hipStream_t s)
+{
+    gbmc_status st = check_call(p, a, gp, ws, true);
+    if (st != GBMC_OK) return st;
+    GBConst c = make_const(gp);
+    hipEvent_t* ev = nullptr;
+    if (p->n_items > 0)
+        ev = (force || dEdrho) ? events(p, {kKEnergy, kKChain}) : events(p, {kKEnergy});
+    hipError_t e;
+    if (p->prec == GBMC_FP32_FIXED)
+        e = launch_energy_forces<float>(p->d_items, p->n_items, p->n_atoms, p->n_sys,
+                                        (const float*)a->x, (const float*)a->y, (const float*)a->z,
+                                        (const float*)a->q, (const float*)a->rho,
+                                        (const float*)a->screen, c, carve<float>(p, ws), e_coul,
+                                        e_gb, (float*)force, (float*)dEdq, (float*)dEdrho, s, ev);
+    else
+        e = launch_energy_forces<double>(p->d_items, p->n_items, p->n_atoms, p->n_sys,
+                                         (const double*)a->x, (const double*)a->y,
+                                         (const double*)a->z, (const double*)a->q,
+                                         (const double*)a->rho, (const double*)a->screen, c,
+                                         carve<double>(p, ws), e_coul, e_gb, (double*)force,
+                                         (double*)dEdq, (double*)dEdrho, s, ev);
+    return e == hipSuccess ? GBMC_OK : hip_fail(e, "gb_energy_forces launch");
+}
+
+// ------------------------------------------------------------------ sites
+
+gbmc_status gbmc_sites_validate(int32_t n_systems, const int32_t* off, int32_t n_sites,
+                                const int32_t* site_system, const int32_t* site_kind,
+                                const int32_t* site_atom_offset, const int32_t* site_atoms,
+                                const int32_t* site_state_offset,
+                                const int32_t* state_charge_offset, const int32_t* state_count)
+{
+    try {
+        gbmc_status st = check_offsets(n_systems, off);
+        if (st != GBMC_OK) return st;
+        if (n_sites < 0) return fail(GBMC_ERR_INVALID, "n_sites < 0");
+        if (n_sites == 0) return GBMC_OK;
+        if (!site_system || !site_kind || !site_atom_offset || !site_atoms || !site_state_offset ||
+            !state_charge_offset || !state_count)
+            return fail(GBMC_ERR_INVALID, "a site table is NULL");
+        const int32_t N = n_systems > 0 ? off[n_systems] : 0;
+        std::vector<char> used(N, 0);
+        if (site_atom_offset[0] != 0 || site_state_offset[0] != 0 || state_charge_offset[0] != 0)
+            return fail(GBMC_ERR_INVALID, "site CSR offsets must start at 0");
+        for (int32_t m = 0; m < n_sites; ++m) {
+            const int32_t b = site_system[m];
+            if (b < 0 || b >= n_systems) return fail(GBMC_ERR_INVALID, "site_system out of range");
+            if (m > 0 && b < site_system[m - 1]) return fail(GBMC_ERR_INVALID, "site_system must be non-decreasing");
+            if (site_kind[m] != 0 && site_kind[m] != 1) return fail(GBMC_ERR_INVALID, "site_kind must be 0 or 1");
+            const int32_t na = site_atom_offset[m + 1] - site_atom_offset[m];
+            if (na < 1) return fail(GBMC_ERR_INVALID, "a site needs at least one atom");
+            if (na > kMaxSiteAtoms) return fail(GBMC_ERR_UNSUPPORTED, "a site has more than 256 atoms");
+            for (int32_t k = site_atom_offset[m]; k < site_atom_offset[m + 1]; ++k) {
+                const int32_t g = site_atoms[k];
+                if (g < off[b] || g >= off[b + 1]) return fail(GBMC_ERR_INVALID, "site atom outside its system");
+                if (used[g]) return fail(GBMC_ERR_INVALID, "sites overlap (an atom belongs to two sites)");
+                used[g] = 1;
+            }
+            const int32_t ns = site_state_offset[m + 1] - site_state_offset[m];
+            if (ns < 2 || ns > kMaxStates) return fail(GBMC_ERR_UNSUPPORTED, "a site needs 2..8 states");
+            for (int32_t g = site_state_offset[m]; g < site_state_offset[m + 1]; ++g) {
+                if (state_charge_offset[g + 1] - state_charge_offset[g] != na)
+                    return fail(GBMC_ERR_INVALID, "a state charge row does not match its site's atom count");
+                if (state_count[g] < 0) return fail(GBMC_ERR_INVALID, "state_count must be >= 0");
+            }
+        }
+        return GBMC_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(GBMC_ERR_INVALID, "host allocation failed");
+    }
+}
+
+gbmc_status gbmc_sites_create(gbmc_plan* p, gbmc_sites** out, int32_t n_sites,
+                              const int32_t* site_system, const int32_t* site_kind,
+                              const int32_t* site_atom_offset, const int32_t* site_atoms,
+                              const int32_t* site_state_offset, const int32_t* state_charge_offset,
+                              const double* state_charges, const double* state_gref,
+                              const int32_t* state_count)
+{
+    try {
+        if (!out) return fail(GBMC_ERR_INVALID, "sites out-pointer is NULL");
+        *out = nullptr;
+        if (!p) return fail(GBMC_ERR_INVALID, "plan is NULL");
+        gbmc_status st = gbmc_sites_validate(p->n_sys, p->offset.data(), n_sites, site_system, site_kind,
+                                             site_atom_offset, site_atoms, site_state_offset,
+                                             state_charge_offset, state_count);
+        if (st != GBMC_OK) return st;
+        if (n_sites > 0 && (!state_charges || !state_gref))
+            return fail(GBMC_ERR_INVALID, "state_charges or state_gref is NULL");
+        const int32_t B = p->n_sys;
+        const int32_t S = n_sites;
+        const int32_t n_sa = S > 0 ? site_atom_offset[S] : 0;
+        const int32_t n_st = S > 0 ? site_state_offset[S] : 0;
+        const int32_t n_q = n_st > 0 ? state_charge_offset[n_st] : 0;
+        std::vector<int32_t> cand(S + 1, 0), prot_off(B + 1, 0), redox_off(B + 1, 0), prot, redox;
+        std::vector<int32_t> sys_sa(B + 1, 0), site_chunks(S, 0), site_phi(S, 0);
+        for (int32_t m = 0; m < S; ++m)
+            cand[m + 1] = cand[m] + (site_state_offset[m + 1] - site_state_offset[m] - 1);
+        // per-system site lists and site-atom ranges
+        std::vector<int32_t> first(B, -1), last(B, -1);
+        for (int32_t m = 0; m < S; ++m) {
+            int32_t b = site_system[m];
+            if (first[b] < 0) first[b] = m;
+            last[b] = m;
+        }
+        for (int32_t b = 0; b < B; ++b) {
+            for (int32_t m = 0; m < S; ++m)
+                if (site_system[m] == b) (site_kind[m] == 0 ? prot : redox).push_back(m);
+            prot_off[b + 1] = (int32_t)prot.size();
+            redox_off[b + 1] = (int32_t)redox.size();
+            sys_sa[b] = first[b] >= 0 ? site_atom_offset[first[b]] : (b > 0 ? sys_sa[b - 1] : 0);
+        }
+        // sys_sa must be monotone: recompute as a running boundary
+        for (int32_t b = 0; b < B; ++b) sys_sa[b + 1] = last[b] >= 0 ? site_atom_offset[last[b] + 1] : sys_sa[b];
+        for (int32_t b = 0; b < B; ++b)
+            if (first[b] < 0) sys_sa[b] = sys_sa[b + 1];
+        // FP64 potential-row items: (64 site atoms) x (kPhiChunk atoms) per system
+        std::vector<RowItem> rows;
+        size_t phi_len = 0;
+        for (int32_t b = 0; b < B; ++b) {
+            const int32_t na = sys_sa[b + 1] - sys_sa[b];
+            if (na == 0) continue;
+            const int32_t n = p->offset[b + 1] - p->offset[b];
+            const int32_t chunks = (n + kPhiChunk - 1) / kPhiChunk;
+            for (int32_t m = first[b]; m <= last[b]; ++m) {
+                site_chunks[m] = chunks;
+                site_phi[m] = (int32_t)phi_len;
+            }
+            for (int32_t c = 0; c < chunks; ++c)
+                for (int32_t s0 = 0; s0 < na; s0 += kTile) {
+                    RowItem r{};
+                    r.base = p->offset[b];
+                    r.n = n;
+                    r.sa0 = sys_sa[b] + s0;
+                    r.sa1 = sys_sa[b] + std::min(na, s0 + kTile);
+                    r.j0 = c * kPhiChunk;
+                    r.j1 = std::min(n, (c + 1) * kPhiChunk);
+                    r.out = (int32_t)phi_len + c * na + s0;
+                    rows.push_back(r);
+                }
+            phi_len += (size_t)chunks * na;
+        }
+        // one device allocation for every table
+        size_t o = 0;
+        auto seg = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
+        size_t o_sys = seg(4 * S), o_kind = seg(4 * S), o_sao = seg(4 * (S + 1)), o_sa = seg(4 * n_sa),
+               o_sso = seg(4 * (S + 1)), o_sco = seg(4 * (n_st + 1)), o_q = seg(8 * n_q),
+               o_gref = seg(8 * n_st), o_cnt = seg(4 * n_st), o_cand = seg(4 * (S + 1)),
+               o_po = seg(4 * (B + 1)), o_ps = seg(4 * prot.size()), o_ro = seg(4 * (B + 1)),
+               o_rs = seg(4 * redox.size()), o_chunks = seg(4 * S), o_phi = seg(4 * S),
+               o_syssa = seg(4 * (B + 1)), o_rows = seg(sizeof(RowItem) * rows.size());
+        std::vector<char> h(o, 0);
+        auto put = [&](size_t at, const void* src, size_t bytes) { if (bytes) std::memcpy(h.data() + at, src, bytes); };
+        if (S > 0) {
+            put(o_sys, site_system, 4 * S);
+            put(o_kind, site_kind, 4 * S);
+            put(o_sao, site_atom_offset, 4 * (S + 1));
+            put(o_sa, site_atoms, 4 * n_sa);
+            put(o_sso, site_state_offset, 4 * (S + 1));
+            put(o_sco, state_charge_offset, 4 * (n_st + 1));
+            put(o_q, state_charges, 8 * n_q);
+            put(o_gref, state_gref, 8 * n_st);
+            put(o_cnt, state_count, 4 * n_st);
+        }
+        put(o_cand, cand.data(), 4 * (S + 1));
+        put(o_po, prot_off.data(), 4 * (B + 1));
+        put(o_ps, prot.data(), 4 * prot.size());
+        put(o_ro, redox_off.data(), 4 * (B + 1));
+        put(o_rs, redox.data(), 4 * redox.size());
+        put(o_chunks, site_chunks.data(), 4 * S);
+        put(o_phi, site_phi.data(), 4 * S);
+        put(o_syssa, sys_sa.data(), 4 * (B + 1));
+        put(o_rows, rows.data(), sizeof(RowItem) * rows.size());
+        auto* sp = new gbmc_sites();
+        sp->plan = p;
+        sp->n_sites = S;
+        sp->n_cand = cand[S];
+        sp->n_rowitems = (int32_t)rows.size();
+        sp->phi_part_len = phi_len;
+        hipError_t e = hipMalloc(&sp->d_mem, std::max<size_t>(o, 256));
+        if (e != hipSuccess) { delete sp; return hip_fail(e, "hipMalloc(site tables)"); }
+        e = hipMemcpy(sp->d_mem, h.data(), o, hipMemcpyHostToDevice);
+        if (e != hipSuccess) { (void)hipFree(sp->d_mem); delete sp; return hip_fail(e, "hipMemcpy(site tables)"); }
+        char* d = static_cast<char*>(sp->d_mem);
+        SiteDev& sd = sp->dev;
+        sd.n_sites = S;
+        sd.n_cand = cand[S];
+        sd.n_rowitems = (int32_t)rows.size();
+        sd.site_system = (const int32_t*)(d + o_sys);
+        sd.site_kind = (const int32_t*)(d + o_kind);
+        sd.site_atom_offset = (const int32_t*)(d + o_sao);
+        sd.site_atoms = (const int32_t*)(d + o_sa);
+        sd.site_state_offset = (const int32_t*)(d + o_sso);
+        sd.state_charge_offset = (const int32_t*)(d + o_sco);
+        sd.state_charges = (const double*)(d + o_q);
+        sd.state_gref = (const double*)(d + o_gref);
+        sd.state_count = (const int32_t*)(d + o_cnt);
+        sd.cand_offset = (const int32_t*)(d + o_cand);
+        sd.sys_prot_offset = (const int32_t*)(d + o_po);
+        sd.sys_prot_sites = (const int32_t*)(d + o_ps);
+        sd.sys_redox_offset = (const int32_t*)(d + o_ro);
+        sd.sys_redox_sites = (const int32_t*)(d + o_rs);
+        sd.site_sa_offset = sd.site_atom_offset;
+        sd.site_chunks = (const int32_t*)(d + o_chunks);
+        sd.site_phi_offset = (const int32_t*)(d + o_phi);
+        sd.sys_sa_offset = (const int32_t*)(d + o_syssa);
+        sd.rowitems = (const RowItem*)(d + o_rows);
+        *out = sp;
+        return GBMC_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(GBMC_ERR_INVALID, "host allocation failed");
+    }
+}
+
+void gbmc_sites_destroy(gbmc_sites* s)
+{
+    if (!s) return;
+    if (s->d_mem) (void)hipFree(s->d_mem);
+    delete s;
+}
+
+int32_t gbmc_sites_n_candidates(const gbmc_sites* s) { return s ? s->n_cand : 0; }
+
+size_t gbmc_sites_workspace_bytes(const gbmc_sites* s)
+{
+    return s ? align256(std::max<size_t>(8 * s->phi_part_len, 8)) : 0;
+}
+
+static gbmc_status check_sites(const gbmc_plan* p, const gbmc_sites* s, const void* sws)
+{
+    if (!s) return fail(GBMC_ERR_INVALID, "sites is NULL");
+    if (s->plan != p) return fail(GBMC_ERR_INVALID, "sites were created for another plan");
+    if (s->phi_part_len > 0 && !sws) return fail(GBMC_ERR_INVALID, "site workspace is NULL");
+    return GBMC_OK;
+}
+
+gbmc_status mc_state_dE(gbmc_plan* p, const gbmc_sites* s, const gbmc_atoms* a,
+                        const gbmc_gb_params* gp, void* ws, void* sws, const int32_t* current_state,
+                        const double* pH, const double* E_volt, double T, double* dE, double* dG,
+                        hipStream_t stream)
+{
+    gbmc_status st = check_call(p, a, gp, ws, true);
+    if (st != GBMC_OK) return st;
+    st = check_sites(p, s, sws);
+    if (st != GBMC_OK) return st;
+    if (s->n_sites == 0) return GBMC_OK;
+    if (!current_state || !dE || !pH || !E_volt) return fail(GBMC_ERR_INVALID, "a Monte Carlo array is NULL");
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(GBMC_ERR_INVALID, "temperature must be > 0");
+    GBConst c = make_const(gp);
+    hipEvent_t* ev = s->dev.n_rowitems > 0 ? events(p, {kKSiteRows, kKSiteDE}) : events(p, {kKSiteDE});
+    hipError_t e;
+    if (p->prec == GBMC_FP32_FIXED)
+        e = launch_state_dE<float>(s->dev, (const float*)a->x, (const float*)a->y, (const float*)a->z,
+                                   (const float*)a->q, c, carve<float>(p, ws), (double*)sws,
+                                   current_state, pH, E_volt, T, dE, dG, stream, ev);
+    else
+        e = launch_state_dE<double>(s->dev, (const double*)a->x, (const double*)a->y,
+                                    (const double*)a->z, (const double*)a->q, c, carve<double>(p, ws),
+                                    (double*)sws, current_state, pH, E_volt, T, dE, dG, stream, ev);
+    return e == hipSuccess ? GBMC_OK : hip_fail(e, "mc_state_dE launch");
+}
+
+gbmc_status mc_step(gbmc_plan* p, const gbmc_sites* s, const gbmc_atoms* a, void* q,
+                    const gbmc_gb_params* gp, void* ws, void* sws, int32_t* current_state,
+                    const double* pH, const double* E_volt, double T, const double* dE,
+                    const double* dG, const double* u, int32_t* n_electrons, int64_t* counters,
+                    int32_t* accepted, hipStream_t stream)
+{
+    gbmc_status st = check_call(p, a, gp, ws, false);
+    if (st != GBMC_OK) return st;
+    st = check_sites(p, s, sws);
+    if (st != GBMC_OK) return st;
+    if (p->n_sys == 0) return GBMC_OK;
+    if (s->n_sites > 0 && (!q || !current_state || !dE || !dG || !u || !pH || !E_volt))
+        return fail(GBMC_ERR_INVALID, "a Monte Carlo array is NULL");
+    if (!u) return fail(GBMC_ERR_INVALID, "uniforms are NULL");
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(GBMC_ERR_INVALID, "temperature must be > 0");
+    GBConst c = make_const(gp);
+    hipEvent_t* ev = events(p, {kKMCStep});
+    hipError_t e;
+    if (p->prec == GBMC_FP32_FIXED)
+        e = launch_mc_step<float>(s->dev, p->n_sys, (const float*)a->x, (const float*)a->y,
+                                  (const float*)a->z, (float*)q, c, carve<float>(p, ws), current_state,
+                                  pH, E_volt, T, dE, dG, u, n_electrons, counters, accepted, stream, ev);
+    else
+        e = launch_mc_step<double>(s->dev, p->n_sys, (const double*)a->x, (const double*)a->y,
+                                   (const double*)a->z, (double*)q, c, carve<double>(p, ws),
+                                   current_state, pH, E_volt, T, dE, dG, u, n_electrons, counters,
+                                   accepted, stream, ev);
+    return e == hipSuccess ? GBMC_OK : hip_fail(e, "mc_step launch");
+}
+
+gbmc_status remd_exchange(int32_t M, const double* E_rung, const int32_t* Ne, int32_t* rep, double T,
+                          int32_t parity, int32_t wrap, const double* u, int32_t* accepted,
+                          double* E_of_rep, hipStream_t stream)
+{
+    if (M < 0) return fail(GBMC_ERR_INVALID, "n_rep < 0");
+    if (parity != 0 && parity != 1) return fail(GBMC_ERR_INVALID, "parity must be 0 or 1");
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(GBMC_ERR_INVALID, "temperature must be > 0");
+    if (M < 2) return GBMC_OK;
+    if (!E_rung || !Ne || !rep || !u) return fail(GBMC_ERR_INVALID, "an exchange array is NULL");
+    hipError_t e = launch_remd_exchange(M, E_rung, Ne, rep, T, parity, wrap, u, accepted, E_of_rep, stream);
+    return e == hipSuccess ? GBMC_OK : hip_fail(e, "remd_exchange launch");
+}
+
+gbmc_status gbmc_check_overflow(const gbmc_plan* p, void* ws, hipStream_t s, int32_t* flag)
+{
+    if (!p || !ws || !flag) return fail(GBMC_ERR_INVALID, "NULL argument");
+    int* d = reinterpret_cast<int*>(static_cast<char*>(ws) + p->off_ovf);
+    int h = 0;
+    hipError_t e = hipMemcpyAsync(&h, d, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "gbmc_check_overflow");
+    *flag = h ? 1 : 0;
+    if (h) {
+        const int zero = 0;
+        e = hipMemcpyAsync(d, &zero, sizeof(int), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "gbmc_check_overflow");
+        return fail(GBMC_ERR_OVERFLOW, "a fixed-point accumulator overflowed");
+    }
+    return GBMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+// Internal declarations shared by the host runtime and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gbmc {
+
+constexpr int kTile = 64;                 // atoms per block; one wavefront per tile
+constexpr int kMaxSiteAtoms = 256;
+constexpr int kMaxStates = 8;
+constexpr int kPhiChunk = 512;            // j atoms per FP64 potential-row work item
+
+// Fixed-point scales (powers of two, so scaling is exact).
+constexpr double kScaleI = 4503599627370496.0;   // 2^52: descreening sums, 1/A
+constexpr double kScaleF = 1099511627776.0;      // 2^40: forces, dE/dR, dE/dq, dE/drho
+constexpr double kScaleE = 4294967296.0;         // 2^32: energies
+constexpr double kFixLimit = 4611686018427387904.0;  // 2^62
+
+// One pair work item: system `sys` (atoms [base, base+n)), i block I, j blocks
+// [J0, J1) with J0 >= I.
+struct WorkItem {
+    int32_t base, n, sys, I, J0, J1, pad0, pad1;
+};
+
+// One FP64 potential-row work item: up to 64 site atoms [sa0, sa1) of one system
+// against the system's atoms [j0, j1); the partial sums go to phi_part[out + k].
+struct RowItem {
+    int32_t base, n, sa0, sa1, j0, j1, out, pad;
+};
+
+// Device pointers carved from the caller's workspace.
+template <typename T>
+struct Work {
+    unsigned long long* I_fx;     // [N]
+    unsigned long long* F_fx;     // [3][N]
+    unsigned long long* G_fx;     // [N]
+    unsigned long long* phi_fx;   // [N]
+    unsigned long long* drho_fx;  // [N]
+    unsigned long long* E_fx;     // [B][2]
+    double* I64;                  // [N] descreening sum
+    double* R64;                  // [N] Born radius
+    double* T64;                  // [N] tanh(theta)
+    double* dRdPsi64;             // [N]
+    double* G64;                  // [N] dE/dR
+    double* B64;                  // [N] dE/dR * dR/dPsi
+    T* R_t;                       // [N] Born radius in the pair precision
+    T* a_t;                       // [N] sqrt(log2(e)/4) / R
+    T* Brt_t;                     // [N] B * (rho - offset)
+    int* ovf;                     // overflow flag
+};
+
+struct SiteDev {
+    int32_t n_sites, n_cand, n_rowitems;
+    const int32_t* site_system;
+    const int32_t* site_kind;
+    const int32_t* site_atom_offset;
+    const int32_t* site_atoms;
+    const int32_t* site_state_offset;
+    const int32_t* state_charge_offset;
+    const double* state_charges;
+    const double* state_gref;
+    const int32_t* state_count;
+    const int32_t* cand_offset;       // [S+1]
+    const int32_t* sys_prot_offset;   // [B+1] CSR into sys_prot_sites
+    const int32_t* sys_prot_sites;
+    const int32_t* sys_redox_offset;  // [B+1]
+    const int32_t* sys_redox_sites;
+    const int32_t* site_sa_offset;    // [S+1]: first flattened site-atom slot of each site
+    const int32_t* site_chunks;       // [S]: potential-row chunks of the site's system
+    const int32_t* site_phi_offset;   // [S]: first phi_part slot of the site's system
+    const int32_t* sys_sa_offset;     // [B+1]
+    const RowItem* rowitems;
+};
+
+struct GBConst {
+    double alpha, beta, gamma, offset;
+    double kC;      // k / eps_in
+    double kT;      // k (1/eps_in - 1/eps_out)
+};
+
+// Kernel ids of the timing hook (events ev[2 id] / ev[2 id + 1] bracket a kernel).
+enum KernelId { kKRadii = 0, kKEnergy = 1, kKChain = 2, kKSiteRows = 3, kKSiteDE = 4, kKMCStep = 5,
+                kNumKernels = 6 };
+
+// Launchers (gbmc_kernels.hip).  All return hipSuccess or the launch error.
+// ev (nullable) holds 2 * kNumKernels events recorded around the timed kernels.
+template <typename T>
+hipError_t launch_radii(const WorkItem* items, int n_items, int n_atoms, const int32_t* atom_sys,
+                        const T* x, const T* y, const T* z, const T* rho, const T* screen,
+                        const GBConst& c, const Work<T>& w, T* born_R, hipStream_t s,
+                        hipEvent_t* ev);
+template <typename T>
+hipError_t launch_energy_forces(const WorkItem* items, int n_items, int n_atoms, int n_sys,
+                                const T* x, const T* y, const T* z, const T* q, const T* rho,
+                                const T* screen, const GBConst& c, const Work<T>& w,
+                                double* e_coul, double* e_gb, T* force, T* dEdq, T* dEdrho,
+                                hipStream_t s, hipEvent_t* ev);
+template <typename T>
+hipError_t launch_state_dE(const SiteDev& sd, const T* x, const T* y, const T* z, const T* q,
+                           const GBConst& c, const Work<T>& w, double* phi_part,
+                           const int32_t* current_state, const double* pH, const double* E_volt,
+                           double T_kelvin, double* dE, double* dG, hipStream_t s,
+                           hipEvent_t* ev);
+template <typename T>
+hipError_t launch_mc_step(const SiteDev& sd, int n_sys, const T* x, const T* y, const T* z,
+                          T* q, const GBConst& c, const Work<T>& w, int32_t* current_state,
+                          const double* pH, const double* E_volt, double T_kelvin,
+                          const double* dE, const double* dG, const double* u,
+                          int32_t* n_electrons, int64_t* counters, int32_t* accepted,
+                          hipStream_t s, hipEvent_t* ev);
+hipError_t launch_remd_exchange(int M, const double* E_rung, const int32_t* Ne, int32_t* rep,
+                                double T_kelvin, int parity, int wrap, const double* u,
+                                int32_t* accepted, double* E_of_rep, hipStream_t s);
+
+}  // namespace gbmc

@@ -1,0 +1,1003 @@
+// gbmc_kernels.hip -- HIP kernels for gfx950 (CDNA4): all-pairs GB-OBC radii,
+// energy and forces, FP64 Monte Carlo Delta E / Delta G, the Metropolis step and
+// the E-REMD exchange.
+//
+// Pair work is split into 64 x 64 tiles of one system (i block I, j block J,
+// J >= I); one wavefront owns a tile.  Lane l holds atom i = 64 I + l in
+// registers.  The j block is staged twice into the wavefront's LDS slice, so
+// that at step k lane l reads j = (l + k) mod 64 at slot l + k with no wrap:
+// the 64 lanes touch 64 distinct j every step, which makes the j-side
+// accumulation a conflict-free, order-fixed LDS float atomic add (ds_add) and
+// lets every unordered pair be evaluated once.  At the end of a tile both the
+// i-side (registers) and the j-side (LDS) partial sums are rounded once into
+// 64-bit fixed point; tiles combine with integer atomics, so sums are exact
+// and the result does not depend on the order in which tiles run.
+//
+// Atoms past the end of a system (ragged last block) are replaced by dummies
+// with q = 0, screen = 0, B = 0 placed far away: every pair term involving a
+// dummy vanishes on the real atom's side, and dummies are never flushed.
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gbmc_internal.h"
+
+namespace gbmc {
+
+#include "hct_poly.inc"
+
+constexpr float kLn2f = 0.693147180559945309f;
+constexpr double kLn2 = 0.693147180559945309;
+constexpr double kKB = 1.98720426e-3;      // kcal/(mol K)
+constexpr double kFaraday = 23.0605478;    // kcal/(mol V)
+constexpr double kLn10 = 2.302585092994045684;
+// sqrt(log2(e) / 4): a_i a_j r^2 = r^2 log2(e) / (4 R_i R_j)
+constexpr double kAScale = 0.60056120439322491;
+
+template <typename T>
+struct alignas(4 * sizeof(T)) Q4 {
+    T x, y, z, w;
+};
+
+// ------------------------------------------------------------------ math
+
+__device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
+__device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
+__device__ __forceinline__ float ln(float v) { return __builtin_amdgcn_logf(v) * kLn2f; }
+__device__ __forceinline__ float exp2neg(float t) { return __builtin_amdgcn_exp2f(-t); }
+__device__ __forceinline__ double rsq(double v) { return 1.0 / sqrt(v); }
+__device__ __forceinline__ double rcp(double v) { return 1.0 / v; }
+__device__ __forceinline__ double ln(double v) { return log(v); }
+__device__ __forceinline__ double exp2neg(double t) { return exp2(-t); }
+
+__device__ __forceinline__ long long to_fixed(double v, double scale, int* ovf)
+{
+    double s = v * scale;
+    if (!(fabs(s) < kFixLimit)) {
+        *ovf = 1;
+        return 0;
+    }
+    return __double2ll_rn(s);
+}
+
+__device__ __forceinline__ void fx_add(unsigned long long* p, long long v)
+{
+    atomicAdd(p, (unsigned long long)v);
+}
+
+template <typename T>
+__device__ __forceinline__ void lds_add(T* p, T v)
+{
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// ------------------------------------------------------------ HCT integral
+// H(r; rt, S): the (1/4 pi) integral of |x|^-4 over the part of the ball of
+// radius S at distance r outside radius rt.  General closed form (all cases).
+template <typename T>
+__device__ __forceinline__ T hct_general(T r, T invr, T rt, T S)
+{
+    T U = r + S;
+    T L = fmax(rt, fabs(r - S));
+    T a = rcp(L), b = rcp(U);
+    T a2 = a * a, b2 = b * b;
+    T h = (a - b) + T(0.25) * r * (b2 - a2) + T(0.5) * invr * ln(L * b)
+        + T(0.25) * S * S * invr * (a2 - b2);
+    T H = T(0.5) * h;
+    if (rt < S - r) H += rcp(rt) - a;
+    return rt >= U ? T(0) : H;
+}
+
+// Partials of H at fixed (L, U): dH/dr, dH/drt, dH/dS (all cases).
+template <typename T>
+__device__ __forceinline__ void hct_general_grad(T r, T invr, T rt, T S, T& dr, T& drt, T& dS)
+{
+    T U = r + S;
+    T ad = fabs(r - S);
+    bool l_rt = rt > ad;
+    T L = l_rt ? rt : ad;
+    T a = rcp(L), b = rcp(U);
+    T a2 = a * a, b2 = b * b;
+    T invr2 = invr * invr;
+    dr = T(0.5) * (T(0.25) * (b2 - a2) * (T(1) + S * S * invr2) - T(0.5) * ln(L * b) * invr2);
+    dS = T(0.25) * S * invr * (a2 - b2);
+    T ri = rcp(rt);
+    T e = l_rt ? T(0.25) * ((L - r) * (L - r) - S * S) * invr * a2 * a
+               : (rt < S - r ? -ri * ri : T(0));
+    drt = e;
+    if (rt >= U) { dr = T(0); drt = T(0); dS = T(0); }
+}
+
+// Pass-1 pair: both directions H(r; rt_i, S_j) and H(r; rt_j, S_i).
+__device__ __forceinline__ void radii_pair(float dx, float dy, float dz, float rti, float Si,
+                                           float rtj, float Sj, float& hij, float& hji)
+{
+    float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    float invr = rsq(r2);
+    float r = r2 * invr;
+    // non-overlapping pairs: H = x^3 P(x^2) / r, x = S / r
+    float xij = Sj * invr, yij = xij * xij;
+    float xji = Si * invr, yji = xji * xji;
+    hij = xij * yij * invr * hct_poly(yij);
+    hji = xji * yji * invr * hct_poly(yji);
+    bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX);
+    bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX);
+    if (!(f_ij & f_ji)) {
+        if (!f_ij) hij = hct_general(r, invr, rti, Sj);
+        if (!f_ji) hji = hct_general(r, invr, rtj, Si);
+    }
+}
+
+__device__ __forceinline__ void radii_pair(double dx, double dy, double dz, double rti, double Si,
+                                           double rtj, double Sj, double& hij, double& hji)
+{
+    double r2 = dx * dx + dy * dy + dz * dz;
+    double invr = rsq(r2);
+    double r = r2 * invr;
+    hij = hct_general(r, invr, rti, Sj);
+    hji = hct_general(r, invr, rtj, Si);
+}
+
+// Pass-3 pair: dH/dr, dH/drt, dH/dS in both directions.
+__device__ __forceinline__ void chain_pair_grads(float r, float invr, float rti, float Si,
+                                                 float rtj, float Sj, float* gij, float* gji)
+{
+    float invr2 = invr * invr;
+    float xij = Sj * invr, yij = xij * xij;
+    float xji = Si * invr, yji = xji * xji;
+    // non-overlapping: dH/dr = -x^3 (P + 1/(1-y)^2) / r^2,  dH/dS = y/((1-y)^2 r^2)
+    float wij = rcp(1.0f - yij), wji = rcp(1.0f - yji);
+    wij *= wij;
+    wji *= wji;
+    gij[0] = -xij * yij * invr2 * (hct_poly(yij) + wij);
+    gij[1] = 0.0f;
+    gij[2] = yij * wij * invr2;
+    gji[0] = -xji * yji * invr2 * (hct_poly(yji) + wji);
+    gji[1] = 0.0f;
+    gji[2] = yji * wji * invr2;
+    bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX);
+    bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX);
+    if (!(f_ij & f_ji)) {
+        if (!f_ij) hct_general_grad(r, invr, rti, Sj, gij[0], gij[1], gij[2]);
+        if (!f_ji) hct_general_grad(r, invr, rtj, Si, gji[0], gji[1], gji[2]);
+    }
+}
+
+__device__ __forceinline__ void chain_pair_grads(double r, double invr, double rti, double Si,
+                                                 double rtj, double Sj, double* gij, double* gji)
+{
+    hct_general_grad(r, invr, rti, Sj, gij[0], gij[1], gij[2]);
+    hct_general_grad(r, invr, rtj, Si, gji[0], gji[1], gji[2]);
+}
+
+// ---------------------------------------------------------------- helpers
+
+template <typename T>
+__device__ __forceinline__ void dummy_pos(int local, T& x, T& y, T& z)
+{
+    x = T(1.0e6) + T(4096) * T(local);
+    y = T(1.0e6);
+    z = T(1.0e6);
+}
+
+__device__ __forceinline__ void wave_sync() { __syncthreads(); }   // workgroup == one wavefront
+
+// ================================================================ pass 1
+// I_i = sum_{j != i} H(r_ij; rt_i, S_j) over every unordered pair once.
+
+template <typename T>
+__global__ __launch_bounds__(kTile) void k_radii_pairs(
+    const WorkItem* __restrict__ items, const T* __restrict__ X, const T* __restrict__ Y,
+    const T* __restrict__ Z, const T* __restrict__ RHO, const T* __restrict__ SCR, T offset,
+    unsigned long long* __restrict__ I_fx, int* __restrict__ ovf)
+{
+    __shared__ Q4<T> sj[2 * kTile];
+    __shared__ T sS[2 * kTile];
+    __shared__ T acc[2 * kTile];
+    const int lane = threadIdx.x;
+    const WorkItem w = items[blockIdx.x];
+    const int i = w.I * kTile + lane;
+    const bool vi = i < w.n;
+    T xi, yi, zi, rti, Si;
+    if (vi) {
+        int g = w.base + i;
+        xi = X[g]; yi = Y[g]; zi = Z[g];
+        rti = RHO[g] - offset;
+        Si = SCR[g] * rti;
+    } else {
+        dummy_pos(i, xi, yi, zi);
+        rti = T(1);
+        Si = T(0);
+    }
+    long long ifix = 0;
+    for (int J = w.J0; J < w.J1; ++J) {
+        const int j = J * kTile + lane;
+        const bool vj = j < w.n;
+        Q4<T> pj;
+        T Sj;
+        if (vj) {
+            int g = w.base + j;
+            pj.x = X[g]; pj.y = Y[g]; pj.z = Z[g];
+            pj.w = RHO[g] - offset;
+            Sj = SCR[g] * pj.w;
+        } else {
+            dummy_pos(j, pj.x, pj.y, pj.z);
+            pj.w = T(1);
+            Sj = T(0);
+        }
+        wave_sync();
+        sj[lane] = pj;
+        sj[lane + kTile] = pj;
+        sS[lane] = Sj;
+        sS[lane + kTile] = Sj;
+        acc[lane] = T(0);
+        acc[lane + kTile] = T(0);
+        wave_sync();
+        T ai = T(0);
+        if (J != w.I) {
+#pragma unroll 4
+            for (int k = 0; k < kTile; ++k) {
+                const int s = lane + k;
+                const Q4<T> p = sj[s];
+                T hij, hji;
+                radii_pair(xi - p.x, yi - p.y, zi - p.z, rti, Si, p.w, sS[s], hij, hji);
+                ai += hij;
+                lds_add(&acc[s], hji);
+            }
+        } else {
+#pragma unroll 4
+            for (int k = 1; k < kTile / 2; ++k) {
+                const int s = lane + k;
+                const Q4<T> p = sj[s];
+                T hij, hji;
+                radii_pair(xi - p.x, yi - p.y, zi - p.z, rti, Si, p.w, sS[s], hij, hji);
+                ai += hij;
+                lds_add(&acc[s], hji);
+            }
+            if (lane < kTile / 2) {   // step 32 pairs lane l with l + 32 once
+                const int s = lane + kTile / 2;
+                const Q4<T> p = sj[s];
+                T hij, hji;
+                radii_pair(xi - p.x, yi - p.y, zi - p.z, rti, Si, p.w, sS[s], hij, hji);
+                ai += hij;
+                lds_add(&acc[s], hji);
+            }
+        }
+        wave_sync();
+        if (vj) fx_add(&I_fx[w.base + j], to_fixed((double)(acc[lane] + acc[lane + kTile]), kScaleI, ovf));
+        ifix += to_fixed((double)ai, kScaleI, ovf);
+    }
+    if (vi) fx_add(&I_fx[w.base + i], ifix);
+}
+
+// Per atom: OBC radius from the descreening sum (FP64), and the per-atom state
+// of the later passes.  Also clears the pass-2/3 accumulators.
+template <typename T>
+__global__ void k_radii_finalize(int n_atoms, const T* __restrict__ RHO, GBConst c, Work<T> w,
+                                 T* __restrict__ born_R)
+{
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_atoms) return;
+    double rho = (double)RHO[g];
+    double rt = rho - c.offset;
+    double I = (double)(long long)w.I_fx[g] * (1.0 / kScaleI);
+    double psi = rt * I;
+    double th = c.alpha * psi - c.beta * psi * psi + c.gamma * psi * psi * psi;
+    double t = tanh(th);
+    double R = 1.0 / (1.0 / rt - t / rho);
+    w.I64[g] = I;
+    w.R64[g] = R;
+    w.T64[g] = t;
+    w.dRdPsi64[g] = R * R * (1.0 - t * t) * (c.alpha - 2.0 * c.beta * psi + 3.0 * c.gamma * psi * psi) / rho;
+    w.R_t[g] = (T)R;
+    w.a_t[g] = (T)(kAScale / R);
+    if (born_R) born_R[g] = (T)R;
+}
+
+// ================================================================ pass 2
+// Coulomb + GB energy, explicit pair forces, G = dE/dR, phi = dE/dq.
+
+template <typename T, bool GRAD>
+__global__ __launch_bounds__(kTile) void k_energy_pairs(
+    const WorkItem* __restrict__ items, const T* __restrict__ X, const T* __restrict__ Y,
+    const T* __restrict__ Z, const T* __restrict__ Q, const T* __restrict__ Rt,
+    const T* __restrict__ At, T kC, T kT, Work<T> wk)
+{
+    __shared__ Q4<T> sj[2 * kTile];     // x, y, z, q
+    __shared__ Q4<T> sr[2 * kTile];     // R, a, -, -
+    __shared__ T acc[5][2 * kTile];     // fx, fy, fz, G, phi
+    const int lane = threadIdx.x;
+    const WorkItem w = items[blockIdx.x];
+    const int i = w.I * kTile + lane;
+    const bool vi = i < w.n;
+    T xi, yi, zi, qi, Ri, ai;
+    if (vi) {
+        int g = w.base + i;
+        xi = X[g]; yi = Y[g]; zi = Z[g]; qi = Q[g];
+        Ri = Rt[g]; ai = At[g];
+    } else {
+        dummy_pos(i, xi, yi, zi);
+        qi = T(0); Ri = T(1); ai = T(kAScale);
+    }
+    long long fix[5] = {0, 0, 0, 0, 0};
+    long long efix[2] = {0, 0};
+    for (int J = w.J0; J < w.J1; ++J) {
+        const int j = J * kTile + lane;
+        const bool vj = j < w.n;
+        Q4<T> pj, rj;
+        if (vj) {
+            int g = w.base + j;
+            pj.x = X[g]; pj.y = Y[g]; pj.z = Z[g]; pj.w = Q[g];
+            rj.x = Rt[g]; rj.y = At[g];
+        } else {
+            dummy_pos(j, pj.x, pj.y, pj.z);
+            pj.w = T(0);
+            rj.x = T(1); rj.y = T(kAScale);
+        }
+        rj.z = rj.w = T(0);
+        wave_sync();
+        sj[lane] = pj; sj[lane + kTile] = pj;
+        sr[lane] = rj; sr[lane + kTile] = rj;
+        if (GRAD) {
+#pragma unroll
+            for (int a = 0; a < 5; ++a) { acc[a][lane] = T(0); acc[a][lane + kTile] = T(0); }
+        }
+        wave_sync();
+        T fxi = 0, fyi = 0, fzi = 0, Gi = 0, phii = 0, eC = 0, eG = 0;
+        auto pair = [&](int s) {
+            const Q4<T> p = sj[s];
+            const Q4<T> rr = sr[s];
+            T dx = xi - p.x, dy = yi - p.y, dz = zi - p.z;
+            T r2 = dx * dx + dy * dy + dz * dz;
+            T invr = rsq(r2);
+            T t = r2 * (ai * rr.y);              // r^2 log2(e) / (4 R_i R_j)
+            T ex = exp2neg(t);                   // exp(-D)
+            T f2 = Ri * rr.x * ex + r2;
+            T invf = rsq(f2);
+            T qq = qi * p.w;
+            eC += qq * invr;
+            eG += qq * invf;
+            if (GRAD) {
+                T wgt = kC * invr - kT * invf;
+                phii += wgt * p.w;
+                T invf3 = invf * invf * invf;
+                T invr3 = invr * invr * invr;
+                T fr = qq * (kT * invf3 * (T(1) - T(0.25) * ex) - kC * invr3);   // (dE/dr)/r
+                T fx = fr * dx, fy = fr * dy, fz = fr * dz;
+                fxi -= fx; fyi -= fy; fzi -= fz;
+                T cg = T(0.5) * kT * qq * invf3 * ex * (T(1) + t * T(kLn2));
+                Gi += cg * rr.x;
+                lds_add(&acc[0][s], fx);
+                lds_add(&acc[1][s], fy);
+                lds_add(&acc[2][s], fz);
+                lds_add(&acc[3][s], cg * Ri);
+                lds_add(&acc[4][s], wgt * qi);
+            }
+        };
+        if (J != w.I) {
+#pragma unroll 2
+            for (int k = 0; k < kTile; ++k) pair(lane + k);
+        } else {
+#pragma unroll 2
+            for (int k = 1; k < kTile / 2; ++k) pair(lane + k);
+            if (lane < kTile / 2) pair(lane + kTile / 2);
+            // self terms: -(kT/2) q_i^2 / R_i in E_GB, -kT q_i / R_i in phi,
+            // (kT/2) q_i^2 / R_i^2 in G
+            T invR = rcp(Ri);
+            eG += T(0.5) * qi * qi * invR;
+            if (GRAD) {
+                phii -= kT * qi * invR;
+                Gi += T(0.5) * kT * qi * qi * invR * invR;
+            }
+        }
+        wave_sync();
+        if (GRAD) {
+            if (vj) {
+                int g = w.base + j;
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+                    fx_add(&wk.F_fx[3 * (size_t)g + a],
+                           to_fixed((double)(acc[a][lane] + acc[a][lane + kTile]), kScaleF, wk.ovf));
+                fx_add(&wk.G_fx[g], to_fixed((double)(acc[3][lane] + acc[3][lane + kTile]), kScaleF, wk.ovf));
+                fx_add(&wk.phi_fx[g], to_fixed((double)(acc[4][lane] + acc[4][lane + kTile]), kScaleF, wk.ovf));
+            }
+            fix[0] += to_fixed((double)fxi, kScaleF, wk.ovf);
+            fix[1] += to_fixed((double)fyi, kScaleF, wk.ovf);
+            fix[2] += to_fixed((double)fzi, kScaleF, wk.ovf);
+            fix[3] += to_fixed((double)Gi, kScaleF, wk.ovf);
+            fix[4] += to_fixed((double)phii, kScaleF, wk.ovf);
+        }
+        efix[0] += to_fixed((double)(kC * eC), kScaleE, wk.ovf);
+        efix[1] += to_fixed((double)(-kT * eG), kScaleE, wk.ovf);
+    }
+    if (GRAD && vi) {
+        int g = w.base + i;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) fx_add(&wk.F_fx[3 * (size_t)g + a], fix[a]);
+        fx_add(&wk.G_fx[g], fix[3]);
+        fx_add(&wk.phi_fx[g], fix[4]);
+    }
+    // energies: exact integer wavefront sum, one atomic per item
+    long long e0 = vi ? efix[0] : 0, e1 = vi ? efix[1] : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        e0 += __shfl_xor(e0, off);
+        e1 += __shfl_xor(e1, off);
+    }
+    if (lane == 0) {
+        fx_add(&wk.E_fx[2 * w.sys + 0], e0);
+        fx_add(&wk.E_fx[2 * w.sys + 1], e1);
+    }
+}
+
+// Per atom after pass 2: B = G dR/dPsi for the chain pass; dE/dq output;
+// energies per system.
+template <typename T>
+__global__ void k_energy_finalize(int n_atoms, int n_sys, const T* __restrict__ RHO, double offset,
+                                  Work<T> w, double* __restrict__ e_coul, double* __restrict__ e_gb,
+                                  T* __restrict__ dEdq, bool grad)
+{
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n_sys) {
+        if (e_coul) e_coul[g] = (double)(long long)w.E_fx[2 * g] * (1.0 / kScaleE);
+        if (e_gb) e_gb[g] = (double)(long long)w.E_fx[2 * g + 1] * (1.0 / kScaleE);
+    }
+    if (!grad || g >= n_atoms) return;
+    double G = (double)(long long)w.G_fx[g] * (1.0 / kScaleF);
+    double B = G * w.dRdPsi64[g];
+    w.G64[g] = G;
+    w.B64[g] = B;
+    w.Brt_t[g] = (T)(B * ((double)RHO[g] - offset));
+    if (dEdq) dEdq[g] = (T)((double)(long long)w.phi_fx[g] * (1.0 / kScaleF));
+}
+
+// ================================================================ pass 3
+// Born-radius chain: force through Psi and the pair part of dE/drho.
+
+template <typename T>
+__global__ __launch_bounds__(kTile) void k_chain_pairs(
+    const WorkItem* __restrict__ items, const T* __restrict__ X, const T* __restrict__ Y,
+    const T* __restrict__ Z, const T* __restrict__ RHO, const T* __restrict__ SCR, T offset,
+    const T* __restrict__ Brt, Work<T> wk)
+{
+    __shared__ Q4<T> sj[2 * kTile];     // x, y, z, rt
+    __shared__ Q4<T> sb[2 * kTile];     // S, B rt, screen, -
+    __shared__ T acc[4][2 * kTile];     // fx, fy, fz, drho
+    const int lane = threadIdx.x;
+    const WorkItem w = items[blockIdx.x];
+    const int i = w.I * kTile + lane;
+    const bool vi = i < w.n;
+    T xi, yi, zi, rti, Si, Bi, si;
+    if (vi) {
+        int g = w.base + i;
+        xi = X[g]; yi = Y[g]; zi = Z[g];
+        rti = RHO[g] - offset;
+        si = SCR[g];
+        Si = si * rti;
+        Bi = Brt[g];
+    } else {
+        dummy_pos(i, xi, yi, zi);
+        rti = T(1); si = T(0); Si = T(0); Bi = T(0);
+    }
+    long long fix[4] = {0, 0, 0, 0};
+    for (int J = w.J0; J < w.J1; ++J) {
+        const int j = J * kTile + lane;
+        const bool vj = j < w.n;
+        Q4<T> pj, bj;
+        if (vj) {
+            int g = w.base + j;
+            pj.x = X[g]; pj.y = Y[g]; pj.z = Z[g];
+            pj.w = RHO[g] - offset;
+            bj.z = SCR[g];
+            bj.x = bj.z * pj.w;
+            bj.y = Brt[g];
+        } else {
+            dummy_pos(j, pj.x, pj.y, pj.z);
+            pj.w = T(1);
+            bj.x = bj.y = bj.z = T(0);
+        }
+        bj.w = T(0);
+        wave_sync();
+        sj[lane] = pj; sj[lane + kTile] = pj;
+        sb[lane] = bj; sb[lane + kTile] = bj;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) { acc[a][lane] = T(0); acc[a][lane + kTile] = T(0); }
+        wave_sync();
+        T fxi = 0, fyi = 0, fzi = 0, dri = 0;
+        auto pair = [&](int s) {
+            const Q4<T> p = sj[s];
+            const Q4<T> b = sb[s];
+            T dx = xi - p.x, dy = yi - p.y, dz = zi - p.z;
+            T r2 = dx * dx + dy * dy + dz * dz;
+            T invr = rsq(r2);
+            T r = r2 * invr;
+            T gij[3], gji[3];
+            chain_pair_grads(r, invr, rti, Si, p.w, b.x, gij, gji);
+            T dEdr = Bi * gij[0] + b.y * gji[0];
+            T fr = dEdr * invr;
+            T fx = fr * dx, fy = fr * dy, fz = fr * dz;
+            fxi -= fx; fyi -= fy; fzi -= fz;
+            dri += Bi * gij[1] + si * b.y * gji[2];
+            lds_add(&acc[0][s], fx);
+            lds_add(&acc[1][s], fy);
+            lds_add(&acc[2][s], fz);
+            lds_add(&acc[3][s], b.y * gji[1] + b.z * Bi * gij[2]);
+        };
+        if (J != w.I) {
+#pragma unroll 2
+            for (int k = 0; k < kTile; ++k) pair(lane + k);
+        } else {
+#pragma unroll 2
+            for (int k = 1; k < kTile / 2; ++k) pair(lane + k);
+            if (lane < kTile / 2) pair(lane + kTile / 2);
+        }
+        wave_sync();
+        if (vj) {
+            int g = w.base + j;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                fx_add(&wk.F_fx[3 * (size_t)g + a],
+                       to_fixed((double)(acc[a][lane] + acc[a][lane + kTile]), kScaleF, wk.ovf));
+            fx_add(&wk.drho_fx[g], to_fixed((double)(acc[3][lane] + acc[3][lane + kTile]), kScaleF, wk.ovf));
+        }
+        fix[0] += to_fixed((double)fxi, kScaleF, wk.ovf);
+        fix[1] += to_fixed((double)fyi, kScaleF, wk.ovf);
+        fix[2] += to_fixed((double)fzi, kScaleF, wk.ovf);
+        fix[3] += to_fixed((double)dri, kScaleF, wk.ovf);
+    }
+    if (vi) {
+        int g = w.base + i;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) fx_add(&wk.F_fx[3 * (size_t)g + a], fix[a]);
+        fx_add(&wk.drho_fx[g], fix[3]);
+    }
+}
+
+// Per atom after pass 3 (or pass 2 when only dE/dq is asked): forces and dE/drho.
+//   dE/drho_k = G_k R_k^2 (1/rt_k^2 - T_k/rho_k^2) + B_k I_k + (pair part)
+template <typename T>
+__global__ void k_grad_finalize(int n_atoms, const T* __restrict__ RHO, double offset, Work<T> w,
+                                T* __restrict__ force, T* __restrict__ dEdrho)
+{
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_atoms) return;
+    if (force) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            force[3 * (size_t)g + a] = (T)((double)(long long)w.F_fx[3 * (size_t)g + a] * (1.0 / kScaleF));
+    }
+    if (dEdrho) {
+        double rho = (double)RHO[g];
+        double rt = rho - offset;
+        double R = w.R64[g];
+        double v = w.G64[g] * R * R * (1.0 / (rt * rt) - w.T64[g] / (rho * rho))
+                 + w.B64[g] * w.I64[g]
+                 + (double)(long long)w.drho_fx[g] * (1.0 / kScaleF);
+        dEdrho[g] = (T)v;
+    }
+}
+
+__global__ void k_zero64(unsigned long long* __restrict__ p, size_t n)
+{
+    size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; g < n; g += stride) p[g] = 0ull;
+}
+
+// ============================================================ Monte Carlo
+// Delta E_elec needs the potential phi_i on every site atom in FP64: a row pass
+// over all atoms of the system, split in chunks written to phi_part and summed
+// in chunk order by k_site_dE (no atomics, deterministic).
+
+template <typename T>
+__global__ __launch_bounds__(kTile) void k_site_phi_rows(
+    const RowItem* __restrict__ items, const int32_t* __restrict__ site_atoms,
+    const T* __restrict__ X, const T* __restrict__ Y, const T* __restrict__ Z,
+    const T* __restrict__ Q, const double* __restrict__ R64, double kC, double kT,
+    double* __restrict__ phi_part)
+{
+    const RowItem w = items[blockIdx.x];
+    const int lane = threadIdx.x;
+    const int sa = w.sa0 + lane;
+    const bool v = sa < w.sa1;
+    int gi = v ? site_atoms[sa] : w.base;
+    double xi = X[gi], yi = Y[gi], zi = Z[gi], Ri = R64[gi];
+    double acc = 0.0;
+    for (int j = w.j0; j < w.j1; ++j) {
+        const int gj = w.base + j;
+        double dx = xi - (double)X[gj], dy = yi - (double)Y[gj], dz = zi - (double)Z[gj];
+        double r2 = dx * dx + dy * dy + dz * dz;
+        double Rj = R64[gj];
+        double qj = (double)Q[gj];
+        double RR = Ri * Rj;
+        double f = sqrt(r2 + RR * exp(-r2 / (4.0 * RR)));
+        double term = qj * (kC / sqrt(r2) - kT / f);
+        acc += (gj == gi) ? 0.0 : term;
+    }
+    if (v) phi_part[w.out + lane] = acc;
+}
+
+__device__ __forceinline__ double pairK(double xa, double ya, double za, double Ra, double xb,
+                                        double yb, double zb, double Rb, double kC, double kT)
+{
+    double dx = xa - xb, dy = ya - yb, dz = za - zb;
+    double r2 = dx * dx + dy * dy + dz * dz;
+    double RR = Ra * Rb;
+    double f = sqrt(r2 + RR * exp(-r2 / (4.0 * RR)));
+    return kC / sqrt(r2) - kT / f;
+}
+
+// deterministic block reduction of NV doubles per thread (blockDim = 256)
+template <int NV>
+__device__ void block_sum(double (*buf)[256], double* v)
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int a = 0; a < NV; ++a) buf[a][t] = v[a];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (t < off) {
+#pragma unroll
+            for (int a = 0; a < NV; ++a) buf[a][t] += buf[a][t + off];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int a = 0; a < NV; ++a) v[a] = buf[a][0];
+    __syncthreads();
+}
+
+constexpr int kMC = 256;   // threads of the per-site / per-system Monte Carlo kernels
+
+template <typename T>
+__global__ __launch_bounds__(kMC) void k_site_dE(
+    SiteDev sd, const T* __restrict__ X, const T* __restrict__ Y, const T* __restrict__ Z,
+    const T* __restrict__ Q, const double* __restrict__ R64, double kC, double kT,
+    const double* __restrict__ phi_part, const int32_t* __restrict__ current_state,
+    const double* __restrict__ pH, const double* __restrict__ E_volt, double T_kelvin,
+    double* __restrict__ dE, double* __restrict__ dG)
+{
+    __shared__ double sx[kMaxSiteAtoms], sy[kMaxSiteAtoms], sz[kMaxSiteAtoms], sR[kMaxSiteAtoms];
+    __shared__ double sphi[kMaxSiteAtoms];
+    __shared__ double sdq[kMaxStates - 1][kMaxSiteAtoms];
+    __shared__ double red[2 * (kMaxStates - 1)][256];
+    const int m = blockIdx.x;
+    const int t = threadIdx.x;
+    const int a0 = sd.site_atom_offset[m];
+    const int na = sd.site_atom_offset[m + 1] - a0;
+    const int g0 = sd.site_state_offset[m];
+    const int ns = sd.site_state_offset[m + 1] - g0;
+    const int cur = current_state[m];
+    const int nc = ns - 1;
+    const int chunks = sd.site_chunks[m];
+    const int sa_sys0 = sd.sys_sa_offset[sd.site_system[m]];
+    const int sa_site0 = sd.site_sa_offset[m];
+    const int n_sa_sys = sd.sys_sa_offset[sd.site_system[m] + 1] - sa_sys0;
+    const double* qcur = sd.state_charges + sd.state_charge_offset[g0 + cur];
+    for (int a = t; a < na; a += kMC) {
+        int g = sd.site_atoms[a0 + a];
+        double R = R64[g];
+        sx[a] = X[g]; sy[a] = Y[g]; sz[a] = Z[g]; sR[a] = R;
+        double phi = -kT * (double)Q[g] / R;           // self term
+        const int slot = sa_site0 - sa_sys0 + a;
+        for (int c = 0; c < chunks; ++c) phi += phi_part[sd.site_phi_offset[m] + c * n_sa_sys + slot];
+        sphi[a] = phi;
+        for (int c = 0; c < nc; ++c) {
+            int s_new = c < cur ? c : c + 1;
+            sdq[c][a] = sd.state_charges[sd.state_charge_offset[g0 + s_new] + a] - qcur[a];
+        }
+    }
+    __syncthreads();
+    double part[2 * (kMaxStates - 1)];
+#pragma unroll
+    for (int c = 0; c < 2 * (kMaxStates - 1); ++c) part[c] = 0.0;
+    // linear term
+    for (int a = t; a < na; a += kMC) {
+#pragma unroll
+        for (int c = 0; c < kMaxStates - 1; ++c)
+            if (c < nc) part[c] += sdq[c][a] * sphi[a];
+    }
+    // quadratic term: diagonal once, off-diagonal pairs twice
+    for (int p = t; p < na * na; p += kMC) {
+        int a = p / na, b = p - a * na;
+        if (b < a) continue;
+        double K = (a == b) ? -kT / sR[a]
+                            : 2.0 * pairK(sx[a], sy[a], sz[a], sR[a], sx[b], sy[b], sz[b], sR[b], kC, kT);
+#pragma unroll
+        for (int c = 0; c < kMaxStates - 1; ++c)
+            if (c < nc) part[kMaxStates - 1 + c] += sdq[c][a] * sdq[c][b] * K;
+    }
+    block_sum<2 * (kMaxStates - 1)>(red, part);
+    double lin = 0.0, quad = 0.0;
+#pragma unroll
+    for (int c = 0; c < kMaxStates - 1; ++c)
+        if (c == t) { lin = part[c]; quad = part[kMaxStates - 1 + c]; }
+    if (t < nc) {
+        int c = t;
+        int s_new = c < cur ? c : c + 1;
+        double de = lin + 0.5 * quad;
+        int cand = sd.cand_offset[m] + c;
+        dE[cand] = de;
+        if (dG) {
+            int b = sd.site_system[m];
+            double drive = sd.site_kind[m] == 0 ? kKB * T_kelvin * kLn10 * pH[b] : kFaraday * E_volt[b];
+            dG[cand] = de + drive * (double)(sd.state_count[g0 + s_new] - sd.state_count[g0 + cur])
+                     - (sd.state_gref[g0 + s_new] - sd.state_gref[g0 + cur]);
+        }
+    }
+}
+
+__device__ __forceinline__ int pick_index(double u, int n)
+{
+    int k = (int)floor(u * (double)n);
+    return k < n - 1 ? (k < 0 ? 0 : k) : n - 1;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kMC) void k_mc_step(
+    SiteDev sd, const T* __restrict__ X, const T* __restrict__ Y, const T* __restrict__ Z,
+    T* __restrict__ Q, const double* __restrict__ R64, double kC, double kT,
+    int32_t* __restrict__ current_state, const double* __restrict__ pH,
+    const double* __restrict__ E_volt, double T_kelvin, const double* __restrict__ dEin,
+    const double* __restrict__ dGin, const double* __restrict__ u,
+    int32_t* __restrict__ n_electrons, int64_t* __restrict__ counters,
+    int32_t* __restrict__ accepted)
+{
+    __shared__ double red[1][256];
+    const int b = blockIdx.x;
+    const int t = threadIdx.x;
+    const double* ub = u + 6 * (size_t)b;
+    const double kTB = kKB * T_kelvin;
+    int acc_p = 0, m_p = -1, s_p = 0, snew_p = 0;
+    // ---- protonation attempt
+    {
+        const int p0 = sd.sys_prot_offset[b], np = sd.sys_prot_offset[b + 1] - p0;
+        if (np > 0) {
+            m_p = sd.sys_prot_sites[p0 + pick_index(ub[0], np)];
+            const int g0 = sd.site_state_offset[m_p];
+            const int ns = sd.site_state_offset[m_p + 1] - g0;
+            s_p = current_state[m_p];
+            const int tp = pick_index(ub[1], ns - 1);
+            snew_p = tp < s_p ? tp : tp + 1;
+            const double dg = dGin[sd.cand_offset[m_p] + tp];
+            acc_p = ub[2] < exp(-dg / kTB) ? 1 : 0;
+        }
+    }
+    // ---- redox attempt, on the charges left by the protonation attempt
+    int acc_r = 0, m_r = -1, s_r = 0, snew_r = 0;
+    {
+        const int r0 = sd.sys_redox_offset[b], nr = sd.sys_redox_offset[b + 1] - r0;
+        if (nr > 0) {
+            m_r = sd.sys_redox_sites[r0 + pick_index(ub[3], nr)];
+            const int g0 = sd.site_state_offset[m_r];
+            const int ns = sd.site_state_offset[m_r + 1] - g0;
+            s_r = current_state[m_r];
+            const int tp = pick_index(ub[4], ns - 1);
+            snew_r = tp < s_r ? tp : tp + 1;
+            double dg = dGin[sd.cand_offset[m_r] + tp];
+            if (acc_p) {
+                // cross term dq_redox . K . dq_prot (sites are disjoint)
+                const int ar0 = sd.site_atom_offset[m_r], nar = sd.site_atom_offset[m_r + 1] - ar0;
+                const int ap0 = sd.site_atom_offset[m_p], nap = sd.site_atom_offset[m_p + 1] - ap0;
+                const int gp0 = sd.site_state_offset[m_p];
+                const double* qr1 = sd.state_charges + sd.state_charge_offset[g0 + snew_r];
+                const double* qr0 = sd.state_charges + sd.state_charge_offset[g0 + s_r];
+                const double* qp1 = sd.state_charges + sd.state_charge_offset[gp0 + snew_p];
+                const double* qp0 = sd.state_charges + sd.state_charge_offset[gp0 + s_p];
+                double part[1] = {0.0};
+                for (int p = t; p < nar * nap; p += kMC) {
+                    int a = p / nap, c = p - a * nap;
+                    int ga = sd.site_atoms[ar0 + a], gc = sd.site_atoms[ap0 + c];
+                    double K = pairK(X[ga], Y[ga], Z[ga], R64[ga], X[gc], Y[gc], Z[gc], R64[gc], kC, kT);
+                    part[0] += (qr1[a] - qr0[a]) * (qp1[c] - qp0[c]) * K;
+                }
+                block_sum<1>(red, part);
+                dg += part[0];
+            }
+            acc_r = ub[5] < exp(-dg / kTB) ? 1 : 0;
+        }
+    }
+    // ---- apply
+    __syncthreads();
+    for (int pass = 0; pass < 2; ++pass) {
+        const int m = pass == 0 ? m_p : m_r;
+        const int acc = pass == 0 ? acc_p : acc_r;
+        const int snew = pass == 0 ? snew_p : snew_r;
+        if (m < 0) continue;
+        if (acc) {
+            const int a0 = sd.site_atom_offset[m], na = sd.site_atom_offset[m + 1] - a0;
+            const double* qn = sd.state_charges + sd.state_charge_offset[sd.site_state_offset[m] + snew];
+            for (int a = t; a < na; a += kMC) Q[sd.site_atoms[a0 + a]] = (T)qn[a];
+        }
+        if (t == 0) {
+            if (acc) current_state[m] = snew;
+            if (counters) {
+                counters[2 * (size_t)m] += 1;
+                counters[2 * (size_t)m + 1] += acc;
+            }
+        }
+    }
+    if (t == 0) {
+        if (accepted) { accepted[2 * b] = acc_p; accepted[2 * b + 1] = acc_r; }
+        if (n_electrons) {
+            const int r0 = sd.sys_redox_offset[b], nr = sd.sys_redox_offset[b + 1] - r0;
+            int ne = 0;
+            for (int k = 0; k < nr; ++k) {
+                int m = sd.sys_redox_sites[r0 + k];
+                int st = (m == m_r && acc_r) ? snew_r : current_state[m];
+                ne += sd.state_count[sd.site_state_offset[m] + st];
+            }
+            n_electrons[b] = ne;
+        }
+    }
+}
+
+// E-REMD exchange: one workgroup; pairs are disjoint so they update in parallel.
+__global__ __launch_bounds__(256) void k_remd_exchange(int M, const double* __restrict__ E_rung,
+                                                       const int32_t* __restrict__ Ne,
+                                                       int32_t* __restrict__ rep, double T_kelvin,
+                                                       int parity, int wrap,
+                                                       const double* __restrict__ u,
+                                                       int32_t* __restrict__ accepted,
+                                                       double* __restrict__ E_of_rep)
+{
+    const int n_inner = (M - parity) / 2;
+    const int n_pairs = n_inner + ((parity == 1 && wrap && (M % 2 == 0) && M > 2) ? 1 : 0);
+    const double beta = kFaraday / (kKB * T_kelvin);
+    for (int p = threadIdx.x; p < n_pairs; p += blockDim.x) {
+        int l, n2;
+        if (p < n_inner) { l = parity + 2 * p; n2 = l + 1; }
+        else { l = M - 1; n2 = 0; }
+        int i = rep[l], j = rep[n2];
+        // a malformed permutation never reads out of bounds: such a pair is not exchanged
+        bool ok = (unsigned)i < (unsigned)M && (unsigned)j < (unsigned)M;
+        double delta = ok ? beta * (E_rung[n2] - E_rung[l]) * (double)(Ne[i] - Ne[j]) : 0.0;
+        int acc = (ok && (delta < 0.0 || u[p] < exp(-delta))) ? 1 : 0;
+        if (acc) { rep[l] = j; rep[n2] = i; }
+        if (accepted) accepted[p] = acc;
+    }
+    __syncthreads();
+    if (E_of_rep)
+        for (int l = threadIdx.x; l < M; l += blockDim.x)
+            if ((unsigned)rep[l] < (unsigned)M) E_of_rep[rep[l]] = E_rung[l];
+}
+
+// ============================================================ launchers
+
+static inline int blocks_for(size_t n, int bs) { return (int)((n + bs - 1) / bs); }
+
+static inline void mark(hipEvent_t* ev, int id, int end, hipStream_t s)
+{
+    if (ev) (void)hipEventRecord(ev[2 * id + end], s);
+}
+
+template <typename T>
+hipError_t launch_radii(const WorkItem* items, int n_items, int n_atoms, const int32_t*,
+                        const T* x, const T* y, const T* z, const T* rho, const T* screen,
+                        const GBConst& c, const Work<T>& w, T* born_R, hipStream_t s,
+                        hipEvent_t* ev)
+{
+    if (n_atoms == 0) return hipSuccess;
+    // I_fx and the overflow word right after it start every evaluation at zero
+    hipLaunchKernelGGL(k_zero64, dim3(blocks_for(n_atoms + 1, 256)), dim3(256), 0, s, w.I_fx,
+                       (size_t)n_atoms + 1);
+    if (n_items > 0) {
+        mark(ev, kKRadii, 0, s);
+        hipLaunchKernelGGL(k_radii_pairs<T>, dim3(n_items), dim3(kTile), 0, s, items, x, y, z, rho,
+                           screen, (T)c.offset, w.I_fx, w.ovf);
+        mark(ev, kKRadii, 1, s);
+    }
+    hipLaunchKernelGGL(k_radii_finalize<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
+                       rho, c, w, born_R);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_energy_forces(const WorkItem* items, int n_items, int n_atoms, int n_sys,
+                                const T* x, const T* y, const T* z, const T* q, const T* rho,
+                                const T* screen, const GBConst& c, const Work<T>& w,
+                                double* e_coul, double* e_gb, T* force, T* dEdq, T* dEdrho,
+                                hipStream_t s, hipEvent_t* ev)
+{
+    const bool grad = force || dEdq || dEdrho;
+    const bool chain = force || dEdrho;
+    // F, G, phi, drho are contiguous after I_fx in the workspace; E_fx follows
+    size_t nz = grad ? (size_t)6 * n_atoms : 0;
+    if (nz) hipLaunchKernelGGL(k_zero64, dim3(blocks_for(nz, 256)), dim3(256), 0, s, w.F_fx, nz);
+    hipLaunchKernelGGL(k_zero64, dim3(1), dim3(256), 0, s, w.E_fx, (size_t)2 * n_sys);
+    if (n_items > 0) {
+        mark(ev, kKEnergy, 0, s);
+        if (grad)
+            hipLaunchKernelGGL((k_energy_pairs<T, true>), dim3(n_items), dim3(kTile), 0, s, items, x,
+                               y, z, q, w.R_t, w.a_t, (T)c.kC, (T)c.kT, w);
+        else
+            hipLaunchKernelGGL((k_energy_pairs<T, false>), dim3(n_items), dim3(kTile), 0, s, items,
+                               x, y, z, q, w.R_t, w.a_t, (T)c.kC, (T)c.kT, w);
+        mark(ev, kKEnergy, 1, s);
+    }
+    int nb = blocks_for(n_atoms > n_sys ? n_atoms : n_sys, 256);
+    if (nb > 0)
+        hipLaunchKernelGGL(k_energy_finalize<T>, dim3(nb), dim3(256), 0, s, n_atoms, n_sys, rho,
+                           c.offset, w, e_coul, e_gb, dEdq, grad);
+    if (chain && n_items > 0) {
+        mark(ev, kKChain, 0, s);
+        hipLaunchKernelGGL(k_chain_pairs<T>, dim3(n_items), dim3(kTile), 0, s, items, x, y, z, rho,
+                           screen, (T)c.offset, w.Brt_t, w);
+        mark(ev, kKChain, 1, s);
+    }
+    if (chain && n_atoms > 0)
+        hipLaunchKernelGGL(k_grad_finalize<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s,
+                           n_atoms, rho, c.offset, w, force, dEdrho);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_state_dE(const SiteDev& sd, const T* x, const T* y, const T* z, const T* q,
+                           const GBConst& c, const Work<T>& w, double* phi_part,
+                           const int32_t* current_state, const double* pH, const double* E_volt,
+                           double T_kelvin, double* dE, double* dG, hipStream_t s, hipEvent_t* ev)
+{
+    if (sd.n_sites == 0) return hipSuccess;
+    if (sd.n_rowitems > 0) {
+        mark(ev, kKSiteRows, 0, s);
+        hipLaunchKernelGGL(k_site_phi_rows<T>, dim3(sd.n_rowitems), dim3(kTile), 0, s, sd.rowitems,
+                           sd.site_atoms, x, y, z, q, w.R64, c.kC, c.kT, phi_part);
+        mark(ev, kKSiteRows, 1, s);
+    }
+    mark(ev, kKSiteDE, 0, s);
+    hipLaunchKernelGGL(k_site_dE<T>, dim3(sd.n_sites), dim3(kMC), 0, s, sd, x, y, z, q, w.R64, c.kC,
+                       c.kT, phi_part, current_state, pH, E_volt, T_kelvin, dE, dG);
+    mark(ev, kKSiteDE, 1, s);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_mc_step(const SiteDev& sd, int n_sys, const T* x, const T* y, const T* z,
+                          T* q, const GBConst& c, const Work<T>& w, int32_t* current_state,
+                          const double* pH, const double* E_volt, double T_kelvin,
+                          const double* dE, const double* dG, const double* u,
+                          int32_t* n_electrons, int64_t* counters, int32_t* accepted,
+                          hipStream_t s, hipEvent_t* ev)
+{
+    if (n_sys == 0) return hipSuccess;
+    mark(ev, kKMCStep, 0, s);
+    hipLaunchKernelGGL(k_mc_step<T>, dim3(n_sys), dim3(kMC), 0, s, sd, x, y, z, q, w.R64, c.kC,
+                       c.kT, current_state, pH, E_volt, T_kelvin, dE, dG, u, n_electrons, counters,
+                       accepted);
+    mark(ev, kKMCStep, 1, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_remd_exchange(int M, const double* E_rung, const int32_t* Ne, int32_t* rep,
+                                double T_kelvin, int parity, int wrap, const double* u,
+                                int32_t* accepted, double* E_of_rep, hipStream_t s)
+{
+    if (M < 2) return hipSuccess;
+    hipLaunchKernelGGL(k_remd_exchange, dim3(1), dim3(256), 0, s, M, E_rung, Ne, rep, T_kelvin,
+                       parity, wrap, u, accepted, E_of_rep);
+    return hipGetLastError();
+}
+
+#define GBMC_INSTANTIATE(T)                                                                      \
+    template hipError_t launch_radii<T>(const WorkItem*, int, int, const int32_t*, const T*,     \
+                                        const T*, const T*, const T*, const T*, const GBConst&,  \
+                                        const Work<T>&, T*, hipStream_t, hipEvent_t*);           \
+    template hipError_t launch_energy_forces<T>(const WorkItem*, int, int, int, const T*,        \
+                                                const T*, const T*, const T*, const T*,          \
+                                                const T*, const GBConst&, const Work<T>&,        \
+                                                double*, double*, T*, T*, T*, hipStream_t,       \
+                                                hipEvent_t*);                                    \
+    template hipError_t launch_state_dE<T>(const SiteDev&, const T*, const T*, const T*,         \
+                                           const T*, const GBConst&, const Work<T>&, double*,    \
+                                           const int32_t*, const double*, const double*, double, \
+                                           double*, double*, hipStream_t, hipEvent_t*);          \
+    template hipError_t launch_mc_step<T>(const SiteDev&, int, const T*, const T*, const T*, T*, \
+                                          const GBConst&, const Work<T>&, int32_t*,              \
+                                          const double*, const double*, double, const double*,   \
+                                          const double*, const double*, int32_t*, int64_t*,      \
+                                          int32_t*, hipStream_t, hipEvent_t*);
+
+GBMC_INSTANTIATE(float)
+GBMC_INSTANTIATE(double)
+
+}  // namespace gbmc

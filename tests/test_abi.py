@@ -1,0 +1,170 @@
+"""CPU-only checks of the C ABI: the library loads, exports every function
+include/gbmc.h declares, and its host-side validation and scheduling behave.
+No compute call is made (there is no GPU here)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gbmc.h")
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_1803_09652_amd import _lib
+    _lib.load()
+    return _lib
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:gbmc_status|void|size_t|int32_t|const char\*)\s+(\w+)\s*\(",
+                       text, flags=re.M)
+    return names
+
+
+def test_every_declared_symbol_is_exported_and_bound(L):
+    names = header_functions()
+    assert len(names) >= 18
+    lib = C.CDLL(L.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(names) == sorted(L.SIGNATURES), "binding and header disagree"
+
+
+def test_missing_library_fails_loudly(monkeypatch, L):
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", "/nonexistent/libgbmc.so")
+    with pytest.raises(RuntimeError, match="not built"):
+        L.load()
+
+
+def _i32p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def test_params_validation(L):
+    lib = L.load()
+    ok = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, 0.0)
+    assert lib.gbmc_params_validate(C.byref(ok)) == L.GBMC_OK
+    salt = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, 0.1)
+    assert lib.gbmc_params_validate(C.byref(salt)) == L.GBMC_ERR_UNSUPPORTED
+    assert b"kappa" in lib.gbmc_last_error()
+    bad = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 0.0, 78.5, 332.0522, 0.0)
+    assert lib.gbmc_params_validate(C.byref(bad)) == L.GBMC_ERR_INVALID
+    nan = L.gbmc_gb_params(float("nan"), 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, 0.0)
+    assert lib.gbmc_params_validate(C.byref(nan)) == L.GBMC_ERR_INVALID
+
+
+def schedule(L, off, jb=None):
+    lib = L.load()
+    off = np.ascontiguousarray(off, dtype=np.int32)
+    n = C.c_int32()
+    tun = C.byref(L.gbmc_tuning(jb)) if jb else None
+    st = lib.gbmc_schedule_build(off.size - 1, _i32p(off), tun, C.byref(n), None)
+    if st != 0:
+        return st, None
+    items = np.zeros(4 * n.value, dtype=np.int32)
+    assert lib.gbmc_schedule_build(off.size - 1, _i32p(off), tun, C.byref(n), _i32p(items)) == 0
+    return st, items.reshape(-1, 4)
+
+
+@pytest.mark.parametrize("jb", [None, 1, 3, 8, 1000])
+def test_schedule_covers_every_tile_once(L, jb):
+    sizes = [1, 64, 65, 0, 200, 2500, 130]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    st, items = schedule(L, off, jb)
+    assert st == 0
+    seen = {}
+    for sys_, I, J0, J1 in items:
+        assert 0 <= I <= J0 < J1
+        for J in range(J0, J1):
+            key = (sys_, I, J)
+            assert key not in seen
+            seen[key] = 1
+    for b, n in enumerate(sizes):
+        nb = (n + 63) // 64
+        for I in range(nb):
+            for J in range(I, nb):
+                assert (b, I, J) in seen
+    assert len(seen) == sum(((n + 63) // 64) * ((n + 63) // 64 + 1) // 2 for n in sizes)
+    # longest first
+    cost = 2 * (items[:, 3] - items[:, 2]) - (items[:, 2] == items[:, 1])
+    assert np.all(np.diff(cost) <= 0)
+
+
+def test_schedule_rejects_bad_offsets(L):
+    assert schedule(L, [1, 5])[0] == L.GBMC_ERR_INVALID
+    assert schedule(L, [0, 5, 3])[0] == L.GBMC_ERR_INVALID
+    st, items = schedule(L, [0])
+    assert st == 0 and items.size == 0
+
+
+def test_plan_create_rejects_bad_layout_before_touching_the_gpu(L):
+    lib = L.load()
+    h = C.c_void_p()
+    off = np.array([0, 10, 5], dtype=np.int32)
+    assert lib.gbmc_plan_create(C.byref(h), 2, _i32p(off), 0, None) == L.GBMC_ERR_INVALID
+    off = np.array([0, 10], dtype=np.int32)
+    assert lib.gbmc_plan_create(C.byref(h), 1, _i32p(off), 7, None) == L.GBMC_ERR_INVALID
+    bad = C.byref(L.gbmc_tuning(0))
+    assert lib.gbmc_plan_create(C.byref(h), 1, _i32p(off), 0, bad) == L.GBMC_ERR_INVALID
+
+
+def _sites_args(batch):
+    return (batch.n_systems, _i32p(batch.atom_offset), batch.n_sites, _i32p(batch.site_system),
+            _i32p(batch.site_kind), _i32p(batch.site_atom_offset), _i32p(batch.site_atoms),
+            _i32p(batch.site_state_offset), _i32p(batch.state_charge_offset),
+            _i32p(batch.state_count))
+
+
+def test_sites_validation(L):
+    lib = L.load()
+    batch = synth.make_batch(synth.config2(n_rep=3))
+    assert lib.gbmc_sites_validate(*_sites_args(batch)) == L.GBMC_OK
+    # overlapping sites
+    b2 = synth.make_batch(synth.config2(n_rep=3))
+    b2.site_atoms[b2.site_atom_offset[1]] = b2.site_atoms[0]
+    assert lib.gbmc_sites_validate(*_sites_args(b2)) == L.GBMC_ERR_INVALID
+    assert b"overlap" in lib.gbmc_last_error()
+    # atom outside its system
+    b3 = synth.make_batch(synth.config2(n_rep=3))
+    b3.site_atoms[0] = b3.atom_offset[2] + 1
+    assert lib.gbmc_sites_validate(*_sites_args(b3)) == L.GBMC_ERR_INVALID
+    # a one-state site
+    s = synth.make_system(1, 100, 8.0, n_redox=1, redox_atoms=5)
+    s.sites[0].charges = s.sites[0].charges[:1]
+    s.sites[0].counts = s.sites[0].counts[:1]
+    b4 = synth.make_batch([s])
+    assert lib.gbmc_sites_validate(*_sites_args(b4)) == L.GBMC_ERR_UNSUPPORTED
+    # more than 256 atoms in a site
+    big = synth.make_system(2, 400, 12.0, n_redox=1, redox_atoms=300)
+    assert lib.gbmc_sites_validate(*_sites_args(synth.make_batch([big]))) == L.GBMC_ERR_UNSUPPORTED
+    # systems out of order
+    b5 = synth.make_batch(synth.config2(n_rep=3))
+    b5.site_system[0] = 2
+    assert lib.gbmc_sites_validate(*_sites_args(b5)) == L.GBMC_ERR_INVALID
+
+
+def test_exchange_rejects_bad_arguments_on_host(L):
+    lib = L.load()
+    assert lib.remd_exchange(4, None, None, None, 300.0, 2, 1, None, None, None, None) == L.GBMC_ERR_INVALID
+    assert lib.remd_exchange(4, None, None, None, -1.0, 0, 1, None, None, None, None) == L.GBMC_ERR_INVALID
+    assert lib.remd_exchange(4, None, None, None, 300.0, 0, 1, None, None, None, None) == L.GBMC_ERR_INVALID
+    # one replica: nothing to do, no device access
+    assert lib.remd_exchange(1, None, None, None, 300.0, 0, 1, None, None, None, None) == L.GBMC_OK
+
+
+def test_entry_points_reject_null_plan(L):
+    lib = L.load()
+    p = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, 0.0)
+    a = L.gbmc_atoms()
+    assert lib.gb_radii(None, C.byref(a), C.byref(p), None, None, None) == L.GBMC_ERR_INVALID
+    assert lib.gb_energy_forces(None, C.byref(a), C.byref(p), None, None, None, None, None, None,
+                                None) == L.GBMC_ERR_INVALID

@@ -1,0 +1,180 @@
+"""GPU parity of gb_radii / gb_energy_forces (C ABI) against the FP64 oracle.
+
+Sizes span several 64-atom tiles and ragged tails; batches mix uneven and
+empty systems; the full-size workloads run in the launch configuration of the
+benchmark and are compared on every atom of selected systems.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_common import TOL, build, compare_system, gpu_eval, oracle_eval, params_pair, rel_inf
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp32", "fp64"]
+
+
+def _sys(seed, n, r=None, **kw):
+    r = r if r is not None else max(4.0, 18.0 * (n / 2500.0) ** (1 / 3))
+    return synth.make_system(seed, n, r, **kw)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("pname", ["IGB5", "IGB2"])
+def test_config0_parity(prec, pname):
+    p_gpu, p_or = params_pair(pname)
+    systems = synth.config0()
+    g, batch, plan, atoms = build(systems, prec)
+    res = gpu_eval(plan, atoms, p_gpu)
+    ref = oracle_eval(systems[0], p_or, ("c0", pname))
+    errs = compare_system(res, 0, batch.atom_offset, ref, prec)
+    print(prec, pname, errs)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_config1_parity(prec):
+    p_gpu, p_or = params_pair()
+    systems = synth.config1()
+    g, batch, plan, atoms = build(systems, prec)
+    res = gpu_eval(plan, atoms, p_gpu)
+    ref = oracle_eval(systems[0], p_or, ("c1", "IGB5"))
+    print(prec, compare_system(res, 0, batch.atom_offset, ref, prec))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_ragged_and_degenerate_sizes(prec):
+    # 1 atom (Born ion), 2 atoms, one tile minus/plus one, several tiles with a
+    # ragged tail, and an empty system in the middle of the batch
+    p_gpu, p_or = params_pair()
+    sizes = [1, 2, 63, 64, 65, 0, 130, 200]
+    systems = [_sys(100 + k, n) if n > 0 else synth.System(*(np.zeros(0),) * 6)
+               for k, n in enumerate(sizes)]
+    g, batch, plan, atoms = build(systems, prec)
+    res = gpu_eval(plan, atoms, p_gpu)
+    for b, s in enumerate(systems):
+        ref = oracle_eval(s, p_or) if s.n > 0 else None
+        compare_system(res, b, batch.atom_offset, ref, prec)
+
+
+def test_engulfed_and_overlapping_pairs():
+    # close contacts (0.3-0.6 A) with large screened radii exercise every branch
+    # of the HCT integral and its derivatives in both precisions
+    p_gpu, p_or = params_pair()
+    s = synth.make_system(7, 150, 6.0, min_dist=0.3)
+    s.rho = synth.f32(np.random.default_rng(1).uniform(0.8, 2.6, s.n))
+    s.screen = synth.f32(np.random.default_rng(2).uniform(0.6, 0.99, s.n))
+    ref = oracle_eval(s, p_or)
+    for prec in PRECS:
+        g, batch, plan, atoms = build([s], prec)
+        res = gpu_eval(plan, atoms, p_gpu)
+        print(prec, compare_system(res, 0, batch.atom_offset, ref, prec))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_config2_batch_all_replicas(prec):
+    # the E-REMD batch (16 x 2500) in the benchmark's launch configuration
+    p_gpu, p_or = params_pair()
+    systems = synth.config2()
+    g, batch, plan, atoms = build(systems, prec)
+    res = gpu_eval(plan, atoms, p_gpu)
+    worst = {}
+    for b, s in enumerate(systems):
+        e = compare_system(res, b, batch.atom_offset, oracle_eval(s, p_or, ("c2", b)), prec)
+        for k, v in e.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+    print(prec, worst)
+
+
+def test_config4_uneven_batch_sampled_systems():
+    # the uneven 64-system batch runs in one launch; the smallest, the largest
+    # and one middle system are compared on every atom
+    p_gpu, p_or = params_pair()
+    systems = synth.config4()
+    sizes = np.array([s.n for s in systems])
+    pick = [int(np.argmin(sizes)), int(np.argmax(sizes)), int(np.argsort(sizes)[len(sizes) // 2])]
+    g, batch, plan, atoms = build(systems, "fp32")
+    res = gpu_eval(plan, atoms, p_gpu)
+    for b in pick:
+        e = compare_system(res, b, batch.atom_offset, oracle_eval(systems[b], p_or, ("c4", b)), "fp32")
+        print(b, sizes[b], e)
+
+
+def test_fp32_bitwise_deterministic_and_shape_independent():
+    p_gpu, _ = params_pair()
+    systems = [_sys(11, 700), _sys(12, 333)]
+    outs = []
+    for jb in (8, 8, 1, 3, 64):
+        g, batch, plan, atoms = build(systems, "fp32", j_blocks=jb)
+        outs.append(gpu_eval(plan, atoms, p_gpu))
+    for o in outs[1:]:
+        for k in ("R", "Ec", "Egb", "force", "dEdq", "dEdrho"):
+            assert np.array_equal(o[k], outs[0][k]), k
+
+
+def test_batch_equals_single_systems_bitwise():
+    p_gpu, _ = params_pair()
+    systems = [_sys(21, 90), _sys(22, 640), _sys(23, 129), _sys(24, 1)]
+    g, batch, plan, atoms = build(systems, "fp32")
+    whole = gpu_eval(plan, atoms, p_gpu)
+    off = batch.atom_offset
+    for b, s in enumerate(systems):
+        g, bb, pl, at = build([s], "fp32")
+        one = gpu_eval(pl, at, p_gpu)
+        assert np.array_equal(one["R"], whole["R"][off[b]:off[b + 1]])
+        assert np.array_equal(one["force"], whole["force"][off[b]:off[b + 1]])
+        assert np.array_equal(one["dEdrho"], whole["dEdrho"][off[b]:off[b + 1]])
+        assert one["Ec"][0] == whole["Ec"][b] and one["Egb"][0] == whole["Egb"][b]
+
+
+def test_energy_only_mode_matches_full():
+    p_gpu, _ = params_pair()
+    g, batch, plan, atoms = build([_sys(31, 300)], "fp32")
+    full = gpu_eval(plan, atoms, p_gpu)
+    eo = gpu_eval(plan, atoms, p_gpu, force=False, dEdq=False, dEdrho=False)
+    assert eo["Ec"][0] == full["Ec"][0] and eo["Egb"][0] == full["Egb"][0]
+    only_q = gpu_eval(plan, atoms, p_gpu, force=False, dEdq=True, dEdrho=False)
+    assert np.array_equal(only_q["dEdq"], full["dEdq"])
+
+
+def test_overflow_flag_is_raised_and_cleared():
+    # charges far outside any physical range overflow the 2^32 energy scale;
+    # the flag is reported, not a fault
+    g, batch, plan, atoms = build([_sys(41, 100)], "fp32")
+    atoms.q.mul_(1.0e6)
+    p_gpu, _ = params_pair()
+    g.radii(plan, atoms, p_gpu)
+    g.energy_forces(plan, atoms, p_gpu)
+    assert g.check_overflow(plan) is True
+    assert g.check_overflow(plan) is False
+    atoms.q.div_(1.0e6)
+    g.radii(plan, atoms, p_gpu)
+    g.energy_forces(plan, atoms, p_gpu)
+    assert g.check_overflow(plan) is False
+
+
+def test_graph_replay_matches_eager():
+    p_gpu, _ = params_pair()
+    g, batch, plan, atoms = build([_sys(51, 500), _sys(52, 260)], "fp32")
+    eager = gpu_eval(plan, atoms, p_gpu)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        # warm-up on the capture stream, then capture
+        g.radii(plan, atoms, p_gpu)
+        g.energy_forces(plan, atoms, p_gpu)
+    torch.cuda.current_stream().wait_stream(s)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        R = g.radii(plan, atoms, p_gpu)
+        out = g.energy_forces(plan, atoms, p_gpu)
+    for rep in range(4):
+        graph.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(R.double().cpu().numpy(), eager["R"])
+        assert np.array_equal(out["force"].double().cpu().numpy(), eager["force"])
+        assert np.array_equal(out["e_gb"].cpu().numpy(), eager["Egb"])
+        # eager work between replays
+        gpu_eval(plan, atoms, p_gpu)
