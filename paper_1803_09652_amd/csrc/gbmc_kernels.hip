@@ -3,19 +3,25 @@
 // the E-REMD exchange.
 //
 // Pair work is split into 64 x 64 tiles of one system (i block I, j block J,
-// J >= I); one wavefront owns a tile.  Lane l holds atom i = 64 I + l in
-// registers.  The j block is staged twice into the wavefront's LDS slice, so
-// that at step k lane l reads j = (l + k) mod 64 at slot l + k with no wrap:
-// the 64 lanes touch 64 distinct j every step, which makes the j-side
-// accumulation a conflict-free, order-fixed LDS float atomic add (ds_add) and
-// lets every unordered pair be evaluated once.  At the end of a tile both the
-// i-side (registers) and the j-side (LDS) partial sums are rounded once into
-// 64-bit fixed point; tiles combine with integer atomics, so sums are exact
-// and the result does not depend on the order in which tiles run.
+// J >= I); one wavefront owns a tile and evaluates every unordered pair of it
+// once.  Lane l keeps atom i = 64 I + l and its i-side sums in registers.  The
+// j block is staged twice into the wavefront's LDS slice, so that at step k
+// lane l reads j = (l + k) mod 64 from slot l + k without a wrap.  The j-side
+// sums live in registers too: lane l holds the sums of the j it visits, and
+// after every step they move one lane down with a DPP full-wavefront rotation
+// (wave_rol:1, lane l <- lane l + 1), so at step k + 1 each lane again holds
+// the sums of the j it is about to visit.  After the 64 steps of a tile every
+// lane holds the sums of j = 64 J + l.  (LDS float atomics for the j side were
+// measured ~40x slower than this rotation on gfx950.)
 //
-// Atoms past the end of a system (ragged last block) are replaced by dummies
-// with q = 0, screen = 0, B = 0 placed far away: every pair term involving a
-// dummy vanishes on the real atom's side, and dummies are never flushed.
+// At the end of a tile both partial sums are rounded once into 64-bit fixed
+// point; tiles combine with integer atomics, so sums are exact, the result does
+// not depend on the order in which tiles run, and it does not depend on how
+// many j blocks one work item walks.
+//
+// Atoms past the end of a system (ragged last block) are dummies with q = 0,
+// screen = 0, B = 0 placed far away: every pair term involving a dummy vanishes
+// on the real atom's side, and dummies are never flushed.
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -26,7 +32,6 @@ namespace gbmc {
 
 #include "hct_poly.inc"
 
-constexpr float kLn2f = 0.693147180559945309f;
 constexpr double kLn2 = 0.693147180559945309;
 constexpr double kKB = 1.98720426e-3;      // kcal/(mol K)
 constexpr double kFaraday = 23.0605478;    // kcal/(mol V)
@@ -43,11 +48,9 @@ struct alignas(4 * sizeof(T)) Q4 {
 
 __device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
 __device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
-__device__ __forceinline__ float ln(float v) { return __builtin_amdgcn_logf(v) * kLn2f; }
 __device__ __forceinline__ float exp2neg(float t) { return __builtin_amdgcn_exp2f(-t); }
 __device__ __forceinline__ double rsq(double v) { return 1.0 / sqrt(v); }
 __device__ __forceinline__ double rcp(double v) { return 1.0 / v; }
-__device__ __forceinline__ double ln(double v) { return log(v); }
 __device__ __forceinline__ double exp2neg(double t) { return exp2(-t); }
 
 __device__ __forceinline__ long long to_fixed(double v, double scale, int* ovf)
@@ -65,57 +68,94 @@ __device__ __forceinline__ void fx_add(unsigned long long* p, long long v)
     atomicAdd(p, (unsigned long long)v);
 }
 
-template <typename T>
-__device__ __forceinline__ void lds_add(T* p, T v)
+// --------------------------------------------------- cross-lane movement
+// rot1: lane l receives lane (l + 1) mod 64 (DPP wave_rol:1, all lanes active).
+__device__ __forceinline__ int rot1i(int v)
 {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return __builtin_amdgcn_update_dpp(0, v, 0x134, 0xF, 0xF, false);
+}
+__device__ __forceinline__ float rot1(float v)
+{
+    return __builtin_bit_cast(float, rot1i(__builtin_bit_cast(int, v)));
+}
+__device__ __forceinline__ double rot1(double v)
+{
+    long long b = __builtin_bit_cast(long long, v);
+    int lo = rot1i((int)b), hi = rot1i((int)(b >> 32));
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// lane l receives the value of lane src (ds_bpermute; LDS crossbar, no LDS memory)
+__device__ __forceinline__ int from_lane_i(int v, int src)
+{
+    return __builtin_amdgcn_ds_bpermute(src << 2, v);
+}
+__device__ __forceinline__ float from_lane(float v, int src)
+{
+    return __builtin_bit_cast(float, from_lane_i(__builtin_bit_cast(int, v), src));
+}
+__device__ __forceinline__ double from_lane(double v, int src)
+{
+    long long b = __builtin_bit_cast(long long, v);
+    int lo = from_lane_i((int)b, src), hi = from_lane_i((int)(b >> 32), src);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
 }
 
 // ------------------------------------------------------------ HCT integral
 // H(r; rt, S): the (1/4 pi) integral of |x|^-4 over the part of the ball of
-// radius S at distance r outside radius rt.  General closed form (all cases).
-template <typename T>
-__device__ __forceinline__ T hct_general(T r, T invr, T rt, T S)
+// radius S at distance r outside radius rt.  General closed form (all cases),
+// in FP64: when the two spheres overlap the bracket cancels by up to ~10^2.
+__device__ __forceinline__ double hct_general(double r, double invr, double rt, double S)
 {
-    T U = r + S;
-    T L = fmax(rt, fabs(r - S));
-    T a = rcp(L), b = rcp(U);
-    T a2 = a * a, b2 = b * b;
-    T h = (a - b) + T(0.25) * r * (b2 - a2) + T(0.5) * invr * ln(L * b)
-        + T(0.25) * S * S * invr * (a2 - b2);
-    T H = T(0.5) * h;
-    if (rt < S - r) H += rcp(rt) - a;
-    return rt >= U ? T(0) : H;
+    double U = r + S;
+    double L = fmax(rt, fabs(r - S));
+    double a = 1.0 / L, b = 1.0 / U;
+    double a2 = a * a, b2 = b * b;
+    double h = (a - b) + 0.25 * r * (b2 - a2) + 0.5 * invr * log(L * b) + 0.25 * S * S * invr * (a2 - b2);
+    double H = 0.5 * h;
+    if (rt < S - r) H += 1.0 / rt - a;
+    return rt >= U ? 0.0 : H;
 }
 
-// Partials of H at fixed (L, U): dH/dr, dH/drt, dH/dS (all cases).
-template <typename T>
-__device__ __forceinline__ void hct_general_grad(T r, T invr, T rt, T S, T& dr, T& drt, T& dS)
+// Partials of H: dH/dr, dH/drt, dH/dS (all cases; FP64).  dh/dL vanishes at
+// L = r - S, dh/dU at U = r + S, and in the engulfed case the L-dependence
+// cancels against the full-shell term, so dr and dS are partials at fixed L, U.
+__device__ __forceinline__ void hct_general_grad(double r, double invr, double rt, double S,
+                                                 double& dr, double& drt, double& dS)
 {
-    T U = r + S;
-    T ad = fabs(r - S);
+    double U = r + S;
+    double ad = fabs(r - S);
     bool l_rt = rt > ad;
-    T L = l_rt ? rt : ad;
-    T a = rcp(L), b = rcp(U);
-    T a2 = a * a, b2 = b * b;
-    T invr2 = invr * invr;
-    dr = T(0.5) * (T(0.25) * (b2 - a2) * (T(1) + S * S * invr2) - T(0.5) * ln(L * b) * invr2);
-    dS = T(0.25) * S * invr * (a2 - b2);
-    T ri = rcp(rt);
-    T e = l_rt ? T(0.25) * ((L - r) * (L - r) - S * S) * invr * a2 * a
-               : (rt < S - r ? -ri * ri : T(0));
-    drt = e;
-    if (rt >= U) { dr = T(0); drt = T(0); dS = T(0); }
+    double L = l_rt ? rt : ad;
+    double a = 1.0 / L, b = 1.0 / U;
+    double a2 = a * a, b2 = b * b;
+    double invr2 = invr * invr;
+    dr = 0.5 * (0.25 * (b2 - a2) * (1.0 + S * S * invr2) - 0.5 * log(L * b) * invr2);
+    dS = 0.25 * S * invr * (a2 - b2);
+    drt = l_rt ? 0.25 * ((L - r) * (L - r) - S * S) * invr * a2 * a
+               : (rt < S - r ? -1.0 / (rt * rt) : 0.0);
+    if (rt >= U) { dr = 0.0; drt = 0.0; dS = 0.0; }
 }
 
-// Pass-1 pair: both directions H(r; rt_i, S_j) and H(r; rt_j, S_i).
-__device__ __forceinline__ void radii_pair(float dx, float dy, float dz, float rti, float Si,
-                                           float rtj, float Sj, float& hij, float& hji)
+__device__ __forceinline__ void dist64(double xi, double yi, double zi, double xj, double yj,
+                                       double zj, double& r, double& invr)
 {
+    double dx = xi - xj, dy = yi - yj, dz = zi - zj;
+    double r2 = dx * dx + dy * dy + dz * dz;
+    r = sqrt(r2);
+    invr = 1.0 / r;
+}
+
+// Pass-1 pair: H(r; rt_i, S_j) and H(r; rt_j, S_i).
+// FP32: non-overlapping pairs (r - S >= rt, x = S/r with x^2 <= YMAX) use
+// H = x^3 P(x^2) / r; every other pair takes the FP64 closed form.
+__device__ __forceinline__ void radii_pair(float xi, float yi, float zi, float xj, float yj, float zj,
+                                           float rti, float Si, float rtj, float Sj, float& hij,
+                                           float& hji)
+{
+    float dx = xi - xj, dy = yi - yj, dz = zi - zj;
     float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     float invr = rsq(r2);
     float r = r2 * invr;
-    // non-overlapping pairs: H = x^3 P(x^2) / r, x = S / r
     float xij = Sj * invr, yij = xij * xij;
     float xji = Si * invr, yji = xji * xji;
     hij = xij * yij * invr * hct_poly(yij);
@@ -123,23 +163,26 @@ __device__ __forceinline__ void radii_pair(float dx, float dy, float dz, float r
     bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX);
     bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX);
     if (!(f_ij & f_ji)) {
-        if (!f_ij) hij = hct_general(r, invr, rti, Sj);
-        if (!f_ji) hji = hct_general(r, invr, rtj, Si);
+        double rd, invrd;
+        dist64(xi, yi, zi, xj, yj, zj, rd, invrd);
+        if (!f_ij) hij = (float)hct_general(rd, invrd, rti, Sj);
+        if (!f_ji) hji = (float)hct_general(rd, invrd, rtj, Si);
     }
 }
 
-__device__ __forceinline__ void radii_pair(double dx, double dy, double dz, double rti, double Si,
-                                           double rtj, double Sj, double& hij, double& hji)
+__device__ __forceinline__ void radii_pair(double xi, double yi, double zi, double xj, double yj,
+                                           double zj, double rti, double Si, double rtj, double Sj,
+                                           double& hij, double& hji)
 {
-    double r2 = dx * dx + dy * dy + dz * dz;
-    double invr = rsq(r2);
-    double r = r2 * invr;
+    double r, invr;
+    dist64(xi, yi, zi, xj, yj, zj, r, invr);
     hij = hct_general(r, invr, rti, Sj);
     hji = hct_general(r, invr, rtj, Si);
 }
 
-// Pass-3 pair: dH/dr, dH/drt, dH/dS in both directions.
-__device__ __forceinline__ void chain_pair_grads(float r, float invr, float rti, float Si,
+// Pass-3 pair: dH/dr, dH/drt, dH/dS in both directions (same split).
+__device__ __forceinline__ void chain_pair_grads(float xi, float yi, float zi, float xj, float yj,
+                                                 float zj, float r, float invr, float rti, float Si,
                                                  float rtj, float Sj, float* gij, float* gji)
 {
     float invr2 = invr * invr;
@@ -158,13 +201,23 @@ __device__ __forceinline__ void chain_pair_grads(float r, float invr, float rti,
     bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX);
     bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX);
     if (!(f_ij & f_ji)) {
-        if (!f_ij) hct_general_grad(r, invr, rti, Sj, gij[0], gij[1], gij[2]);
-        if (!f_ji) hct_general_grad(r, invr, rtj, Si, gji[0], gji[1], gji[2]);
+        double rd, invrd, a, b, c;
+        dist64(xi, yi, zi, xj, yj, zj, rd, invrd);
+        if (!f_ij) {
+            hct_general_grad(rd, invrd, rti, Sj, a, b, c);
+            gij[0] = (float)a; gij[1] = (float)b; gij[2] = (float)c;
+        }
+        if (!f_ji) {
+            hct_general_grad(rd, invrd, rtj, Si, a, b, c);
+            gji[0] = (float)a; gji[1] = (float)b; gji[2] = (float)c;
+        }
     }
 }
 
-__device__ __forceinline__ void chain_pair_grads(double r, double invr, double rti, double Si,
-                                                 double rtj, double Sj, double* gij, double* gji)
+__device__ __forceinline__ void chain_pair_grads(double xi, double yi, double zi, double xj,
+                                                 double yj, double zj, double r, double invr,
+                                                 double rti, double Si, double rtj, double Sj,
+                                                 double* gij, double* gji)
 {
     hct_general_grad(r, invr, rti, Sj, gij[0], gij[1], gij[2]);
     hct_general_grad(r, invr, rtj, Si, gji[0], gji[1], gji[2]);
@@ -182,6 +235,39 @@ __device__ __forceinline__ void dummy_pos(int local, T& x, T& y, T& z)
 
 __device__ __forceinline__ void wave_sync() { __syncthreads(); }   // workgroup == one wavefront
 
+// Walks the steps of one tile.  pair(s, act, acc_j) evaluates the pair of this
+// lane with the j at LDS slot s and adds the j-side terms to acc_j (an array of
+// NJ sums); act is false only for the lanes that must skip a duplicated pair.
+// On return acc_j of lane l holds the sums of j = 64 J + l.
+template <typename T, int NJ, class Pair>
+__device__ __forceinline__ void walk_tile(bool diagonal, T (&acc_j)[NJ], Pair&& pair)
+{
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int a = 0; a < NJ; ++a) acc_j[a] = T(0);
+    if (!diagonal) {
+#pragma unroll 1
+        for (int k = 0; k < kTile; ++k) {
+            pair(lane + k, true, acc_j);
+#pragma unroll
+            for (int a = 0; a < NJ; ++a) acc_j[a] = rot1(acc_j[a]);
+        }
+    } else {
+        // pairs (l, l + k) for k = 1..31, and k = 32 for lanes 0..31 only
+#pragma unroll 1
+        for (int k = 1; k < kTile / 2; ++k) {
+            pair(lane + k, true, acc_j);
+#pragma unroll
+            for (int a = 0; a < NJ; ++a) acc_j[a] = rot1(acc_j[a]);
+        }
+        pair(lane + kTile / 2, lane < kTile / 2, acc_j);
+        // lane l now holds j = l + 32; one more rotation would give l + 33.
+        // Bring j = l home: it sits in lane (l - 32) mod 64.
+#pragma unroll
+        for (int a = 0; a < NJ; ++a) acc_j[a] = from_lane(acc_j[a], (lane + kTile / 2) & (kTile - 1));
+    }
+}
+
 // ================================================================ pass 1
 // I_i = sum_{j != i} H(r_ij; rt_i, S_j) over every unordered pair once.
 
@@ -193,7 +279,6 @@ __global__ __launch_bounds__(kTile) void k_radii_pairs(
 {
     __shared__ Q4<T> sj[2 * kTile];
     __shared__ T sS[2 * kTile];
-    __shared__ T acc[2 * kTile];
     const int lane = threadIdx.x;
     const WorkItem w = items[blockIdx.x];
     const int i = w.I * kTile + lane;
@@ -230,48 +315,24 @@ __global__ __launch_bounds__(kTile) void k_radii_pairs(
         sj[lane + kTile] = pj;
         sS[lane] = Sj;
         sS[lane + kTile] = Sj;
-        acc[lane] = T(0);
-        acc[lane + kTile] = T(0);
         wave_sync();
         T ai = T(0);
-        if (J != w.I) {
-#pragma unroll 4
-            for (int k = 0; k < kTile; ++k) {
-                const int s = lane + k;
-                const Q4<T> p = sj[s];
-                T hij, hji;
-                radii_pair(xi - p.x, yi - p.y, zi - p.z, rti, Si, p.w, sS[s], hij, hji);
-                ai += hij;
-                lds_add(&acc[s], hji);
-            }
-        } else {
-#pragma unroll 4
-            for (int k = 1; k < kTile / 2; ++k) {
-                const int s = lane + k;
-                const Q4<T> p = sj[s];
-                T hij, hji;
-                radii_pair(xi - p.x, yi - p.y, zi - p.z, rti, Si, p.w, sS[s], hij, hji);
-                ai += hij;
-                lds_add(&acc[s], hji);
-            }
-            if (lane < kTile / 2) {   // step 32 pairs lane l with l + 32 once
-                const int s = lane + kTile / 2;
-                const Q4<T> p = sj[s];
-                T hij, hji;
-                radii_pair(xi - p.x, yi - p.y, zi - p.z, rti, Si, p.w, sS[s], hij, hji);
-                ai += hij;
-                lds_add(&acc[s], hji);
-            }
-        }
-        wave_sync();
-        if (vj) fx_add(&I_fx[w.base + j], to_fixed((double)(acc[lane] + acc[lane + kTile]), kScaleI, ovf));
+        T aj[1];
+        walk_tile<T, 1>(J == w.I, aj, [&](int s, bool act, T (&acc)[1]) {
+            const Q4<T> p = sj[s];
+            T hij, hji;
+            radii_pair(xi, yi, zi, p.x, p.y, p.z, rti, Si, p.w, sS[s], hij, hji);
+            ai += act ? hij : T(0);
+            acc[0] += act ? hji : T(0);
+        });
+        if (vj) fx_add(&I_fx[w.base + j], to_fixed((double)aj[0], kScaleI, ovf));
         ifix += to_fixed((double)ai, kScaleI, ovf);
     }
     if (vi) fx_add(&I_fx[w.base + i], ifix);
 }
 
 // Per atom: OBC radius from the descreening sum (FP64), and the per-atom state
-// of the later passes.  Also clears the pass-2/3 accumulators.
+// of the later passes.
 template <typename T>
 __global__ void k_radii_finalize(int n_atoms, const T* __restrict__ RHO, GBConst c, Work<T> w,
                                  T* __restrict__ born_R)
@@ -304,8 +365,9 @@ __global__ __launch_bounds__(kTile) void k_energy_pairs(
     const T* __restrict__ At, T kC, T kT, Work<T> wk)
 {
     __shared__ Q4<T> sj[2 * kTile];     // x, y, z, q
-    __shared__ Q4<T> sr[2 * kTile];     // R, a, -, -
-    __shared__ T acc[5][2 * kTile];     // fx, fy, fz, G, phi
+    __shared__ T sR[2 * kTile];
+    __shared__ T sA[2 * kTile];
+    constexpr int NJ = GRAD ? 5 : 1;
     const int lane = threadIdx.x;
     const WorkItem w = items[blockIdx.x];
     const int i = w.I * kTile + lane;
@@ -324,63 +386,57 @@ __global__ __launch_bounds__(kTile) void k_energy_pairs(
     for (int J = w.J0; J < w.J1; ++J) {
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
-        Q4<T> pj, rj;
+        Q4<T> pj;
+        T Rj, Aj;
         if (vj) {
             int g = w.base + j;
             pj.x = X[g]; pj.y = Y[g]; pj.z = Z[g]; pj.w = Q[g];
-            rj.x = Rt[g]; rj.y = At[g];
+            Rj = Rt[g]; Aj = At[g];
         } else {
             dummy_pos(j, pj.x, pj.y, pj.z);
             pj.w = T(0);
-            rj.x = T(1); rj.y = T(kAScale);
+            Rj = T(1); Aj = T(kAScale);
         }
-        rj.z = rj.w = T(0);
         wave_sync();
         sj[lane] = pj; sj[lane + kTile] = pj;
-        sr[lane] = rj; sr[lane + kTile] = rj;
-        if (GRAD) {
-#pragma unroll
-            for (int a = 0; a < 5; ++a) { acc[a][lane] = T(0); acc[a][lane + kTile] = T(0); }
-        }
+        sR[lane] = Rj; sR[lane + kTile] = Rj;
+        sA[lane] = Aj; sA[lane + kTile] = Aj;
         wave_sync();
         T fxi = 0, fyi = 0, fzi = 0, Gi = 0, phii = 0, eC = 0, eG = 0;
-        auto pair = [&](int s) {
+        T aj[NJ];
+        walk_tile<T, NJ>(J == w.I, aj, [&](int s, bool act, T (&acc)[NJ]) {
             const Q4<T> p = sj[s];
-            const Q4<T> rr = sr[s];
+            const T rj = sR[s];
             T dx = xi - p.x, dy = yi - p.y, dz = zi - p.z;
             T r2 = dx * dx + dy * dy + dz * dz;
             T invr = rsq(r2);
-            T t = r2 * (ai * rr.y);              // r^2 log2(e) / (4 R_i R_j)
+            T t = r2 * (ai * sA[s]);             // r^2 log2(e) / (4 R_i R_j)
             T ex = exp2neg(t);                   // exp(-D)
-            T f2 = Ri * rr.x * ex + r2;
+            T f2 = Ri * rj * ex + r2;
             T invf = rsq(f2);
-            T qq = qi * p.w;
+            T qq = act ? qi * p.w : T(0);
             eC += qq * invr;
             eG += qq * invf;
             if (GRAD) {
+                T qj = act ? p.w : T(0);
+                T qi_ = act ? qi : T(0);
                 T wgt = kC * invr - kT * invf;
-                phii += wgt * p.w;
+                phii += wgt * qj;
                 T invf3 = invf * invf * invf;
                 T invr3 = invr * invr * invr;
                 T fr = qq * (kT * invf3 * (T(1) - T(0.25) * ex) - kC * invr3);   // (dE/dr)/r
                 T fx = fr * dx, fy = fr * dy, fz = fr * dz;
                 fxi -= fx; fyi -= fy; fzi -= fz;
                 T cg = T(0.5) * kT * qq * invf3 * ex * (T(1) + t * T(kLn2));
-                Gi += cg * rr.x;
-                lds_add(&acc[0][s], fx);
-                lds_add(&acc[1][s], fy);
-                lds_add(&acc[2][s], fz);
-                lds_add(&acc[3][s], cg * Ri);
-                lds_add(&acc[4][s], wgt * qi);
+                Gi += cg * rj;
+                acc[0] += fx;
+                acc[1] += fy;
+                acc[2] += fz;
+                acc[3] += cg * Ri;
+                acc[4] += wgt * qi_;
             }
-        };
-        if (J != w.I) {
-#pragma unroll 2
-            for (int k = 0; k < kTile; ++k) pair(lane + k);
-        } else {
-#pragma unroll 2
-            for (int k = 1; k < kTile / 2; ++k) pair(lane + k);
-            if (lane < kTile / 2) pair(lane + kTile / 2);
+        });
+        if (J == w.I) {
             // self terms: -(kT/2) q_i^2 / R_i in E_GB, -kT q_i / R_i in phi,
             // (kT/2) q_i^2 / R_i^2 in G
             T invR = rcp(Ri);
@@ -390,16 +446,14 @@ __global__ __launch_bounds__(kTile) void k_energy_pairs(
                 Gi += T(0.5) * kT * qi * qi * invR * invR;
             }
         }
-        wave_sync();
         if (GRAD) {
             if (vj) {
                 int g = w.base + j;
 #pragma unroll
                 for (int a = 0; a < 3; ++a)
-                    fx_add(&wk.F_fx[3 * (size_t)g + a],
-                           to_fixed((double)(acc[a][lane] + acc[a][lane + kTile]), kScaleF, wk.ovf));
-                fx_add(&wk.G_fx[g], to_fixed((double)(acc[3][lane] + acc[3][lane + kTile]), kScaleF, wk.ovf));
-                fx_add(&wk.phi_fx[g], to_fixed((double)(acc[4][lane] + acc[4][lane + kTile]), kScaleF, wk.ovf));
+                    fx_add(&wk.F_fx[3 * (size_t)g + a], to_fixed((double)aj[a], kScaleF, wk.ovf));
+                fx_add(&wk.G_fx[g], to_fixed((double)aj[3], kScaleF, wk.ovf));
+                fx_add(&wk.phi_fx[g], to_fixed((double)aj[4], kScaleF, wk.ovf));
             }
             fix[0] += to_fixed((double)fxi, kScaleF, wk.ovf);
             fix[1] += to_fixed((double)fyi, kScaleF, wk.ovf);
@@ -462,7 +516,6 @@ __global__ __launch_bounds__(kTile) void k_chain_pairs(
 {
     __shared__ Q4<T> sj[2 * kTile];     // x, y, z, rt
     __shared__ Q4<T> sb[2 * kTile];     // S, B rt, screen, -
-    __shared__ T acc[4][2 * kTile];     // fx, fy, fz, drho
     const int lane = threadIdx.x;
     const WorkItem w = items[blockIdx.x];
     const int i = w.I * kTile + lane;
@@ -500,11 +553,10 @@ __global__ __launch_bounds__(kTile) void k_chain_pairs(
         wave_sync();
         sj[lane] = pj; sj[lane + kTile] = pj;
         sb[lane] = bj; sb[lane + kTile] = bj;
-#pragma unroll
-        for (int a = 0; a < 4; ++a) { acc[a][lane] = T(0); acc[a][lane + kTile] = T(0); }
         wave_sync();
         T fxi = 0, fyi = 0, fzi = 0, dri = 0;
-        auto pair = [&](int s) {
+        T aj[4];
+        walk_tile<T, 4>(J == w.I, aj, [&](int s, bool act, T (&acc)[4]) {
             const Q4<T> p = sj[s];
             const Q4<T> b = sb[s];
             T dx = xi - p.x, dy = yi - p.y, dz = zi - p.z;
@@ -512,33 +564,25 @@ __global__ __launch_bounds__(kTile) void k_chain_pairs(
             T invr = rsq(r2);
             T r = r2 * invr;
             T gij[3], gji[3];
-            chain_pair_grads(r, invr, rti, Si, p.w, b.x, gij, gji);
-            T dEdr = Bi * gij[0] + b.y * gji[0];
+            chain_pair_grads(xi, yi, zi, p.x, p.y, p.z, r, invr, rti, Si, p.w, b.x, gij, gji);
+            T bj_ = act ? b.y : T(0);
+            T bi_ = act ? Bi : T(0);
+            T dEdr = bi_ * gij[0] + bj_ * gji[0];
             T fr = dEdr * invr;
             T fx = fr * dx, fy = fr * dy, fz = fr * dz;
             fxi -= fx; fyi -= fy; fzi -= fz;
-            dri += Bi * gij[1] + si * b.y * gji[2];
-            lds_add(&acc[0][s], fx);
-            lds_add(&acc[1][s], fy);
-            lds_add(&acc[2][s], fz);
-            lds_add(&acc[3][s], b.y * gji[1] + b.z * Bi * gij[2]);
-        };
-        if (J != w.I) {
-#pragma unroll 2
-            for (int k = 0; k < kTile; ++k) pair(lane + k);
-        } else {
-#pragma unroll 2
-            for (int k = 1; k < kTile / 2; ++k) pair(lane + k);
-            if (lane < kTile / 2) pair(lane + kTile / 2);
-        }
-        wave_sync();
+            dri += bi_ * gij[1] + si * bj_ * gji[2];
+            acc[0] += fx;
+            acc[1] += fy;
+            acc[2] += fz;
+            acc[3] += bj_ * gji[1] + b.z * bi_ * gij[2];
+        });
         if (vj) {
             int g = w.base + j;
 #pragma unroll
             for (int a = 0; a < 3; ++a)
-                fx_add(&wk.F_fx[3 * (size_t)g + a],
-                       to_fixed((double)(acc[a][lane] + acc[a][lane + kTile]), kScaleF, wk.ovf));
-            fx_add(&wk.drho_fx[g], to_fixed((double)(acc[3][lane] + acc[3][lane + kTile]), kScaleF, wk.ovf));
+                fx_add(&wk.F_fx[3 * (size_t)g + a], to_fixed((double)aj[a], kScaleF, wk.ovf));
+            fx_add(&wk.drho_fx[g], to_fixed((double)aj[3], kScaleF, wk.ovf));
         }
         fix[0] += to_fixed((double)fxi, kScaleF, wk.ovf);
         fix[1] += to_fixed((double)fyi, kScaleF, wk.ovf);
@@ -553,7 +597,7 @@ __global__ __launch_bounds__(kTile) void k_chain_pairs(
     }
 }
 
-// Per atom after pass 3 (or pass 2 when only dE/dq is asked): forces and dE/drho.
+// Per atom after pass 3: forces and dE/drho.
 //   dE/drho_k = G_k R_k^2 (1/rt_k^2 - T_k/rho_k^2) + B_k I_k + (pair part)
 template <typename T>
 __global__ void k_grad_finalize(int n_atoms, const T* __restrict__ RHO, double offset, Work<T> w,
