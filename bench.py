@@ -46,13 +46,15 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--order", choices=["spatial", "identity"], default="spatial",
+                    help="processing order of the pair passes (results are order independent)")
     return ap.parse_args()
 
 
 class Workload:
     """Config-2 E-REMD batch resident on the GPU, with static step buffers."""
 
-    def __init__(self, precision, n_steps):
+    def __init__(self, precision, n_steps, order="spatial"):
         import numpy as np
         import torch
         import paper_1803_09652_amd as g
@@ -62,6 +64,8 @@ class Workload:
         self.batch = b = synth.make_batch(self.systems)
         self.B = b.n_systems
         self.plan = g.Plan(b.atom_offset, precision)
+        if order == "spatial":
+            self.plan.set_order(g.spatial_order(b.atom_offset, b.x, b.y, b.z))
         self.atoms = g.Atoms.from_batch(self.plan, b)
         dev = self.plan.device
         self.params = g.IGB5
@@ -120,10 +124,10 @@ class Workload:
         self.ux.copy_(self.ux_all[k])
 
 
-def run_gpu(precision, steps, warmup, use_graph, kernel_steps):
+def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial"):
     import torch
     n_total = steps + warmup + kernel_steps + 2
-    w = Workload(precision, n_total)
+    w = Workload(precision, n_total, order)
     torch.cuda.synchronize()
     k = 0
     graphs = None
@@ -212,7 +216,8 @@ def main():
     import torch
     torch.cuda.set_device(0)
     use_graph = not args.no_graph
-    w, ms_step, wall_ms, kms = run_gpu("fp32", args.steps, args.warmup, use_graph, args.kernel_steps)
+    w, ms_step, wall_ms, kms = run_gpu("fp32", args.steps, args.warmup, use_graph, args.kernel_steps,
+                                       args.order)
     pairs, n_cand = w.pairs, w.n_cand
     value = pairs / (ms_step * 1e-3)
     out = {
@@ -233,7 +238,7 @@ def main():
                         "protonation sites each, E ladder -0.40..-0.10 V, pH 7, T 300 K, igb=5, "
                         "no cutoff",
             "systems": w.B, "atoms": w.batch.n_atoms, "pairs_per_step": pairs,
-            "candidates_per_step": n_cand, "hip_graph": use_graph,
+            "candidates_per_step": n_cand, "hip_graph": use_graph, "atom_order": args.order,
             "precision": "FP32 pair arithmetic, int64 fixed-point sums, FP64 MC",
         },
         "mc_dE_evals_per_s": n_cand / (ms_step * 1e-3),
@@ -258,7 +263,7 @@ def main():
                             "exchange_accepted_eager": w.exchanges_accepted}
     del w
     if not args.no_fp64:
-        w64, ms64, _, k64 = run_gpu("fp64", args.fp64_steps, 2, use_graph, 3)
+        w64, ms64, _, k64 = run_gpu("fp64", args.fp64_steps, 2, use_graph, 3, args.order)
         v64 = pairs / (ms64 * 1e-3)
         out["fp64"] = {"value": v64, "ms_per_step": ms64, "steps": args.fp64_steps,
                        "kernel_ms": k64}

@@ -115,6 +115,23 @@ gbmc_status gbmc_plan_create(gbmc_plan** plan, int32_t n_systems, const int32_t*
                              gbmc_precision precision, const gbmc_tuning* tuning);
 void gbmc_plan_destroy(gbmc_plan* plan);
 
+/* Processing order (staging).  Every pair pass first packs the atoms of each
+ * system into the workspace in the plan's processing order; an order that
+ * keeps nearby atoms together confines the overlapping pairs (which take the
+ * slow branch of the descreening integral) to few tiles.  host_order (host,
+ * N_tot entries, copied) lists for every internal position the caller atom
+ * index processed there and must be a permutation of each system's atom range.
+ * Outputs are always in caller order; results depend on the order only
+ * through FP32 rounding inside tiles (bitwise reproducible for a given order).
+ * The default is the identity.  Synchronous (not graph-capturable). */
+gbmc_status gbmc_plan_set_order(gbmc_plan* plan, const int32_t* host_order);
+
+/* Host-only helper: a spatial (Morton, 10 bits per axis) order of each
+ * system's atoms from host coordinates x, y, z [N_tot] (double), written to
+ * order[N_tot] for gbmc_plan_set_order. */
+gbmc_status gbmc_spatial_order(int32_t n_systems, const int32_t* host_atom_offset, const double* x,
+                               const double* y, const double* z, int32_t* order);
+
 /* Bytes of caller-owned device workspace a plan needs (256-byte aligned).
  * The workspace carries per-atom state from gb_radii to gb_energy_forces and
  * mc_state_dE; one workspace may serve one stream at a time. */

@@ -103,6 +103,15 @@ class Plan:
     def n_atoms(self) -> int:
         return int(self.offset[-1])
 
+    def set_order(self, order) -> None:
+        """Processing order of the pair passes (a permutation of each system's
+        atom range); see spatial_order()."""
+        o = np.ascontiguousarray(order, dtype=np.int32)
+        if o.shape != (self.n_atoms,):
+            raise ValueError("order must have one entry per atom")
+        with torch.cuda.device(self.device):
+            L.check(L.load().gbmc_plan_set_order(self._h, _i32p(o)))
+
     def set_timing(self, enable: bool = True) -> None:
         """Record HIP events around each hot-path kernel of later eager calls."""
         L.check(L.load().gbmc_plan_set_timing(self._h, int(bool(enable))))
@@ -144,6 +153,17 @@ class Atoms:
         return L.gbmc_atoms(self.x.data_ptr(), self.y.data_ptr(), self.z.data_ptr(),
                             (self.q if q is None else q).data_ptr(), self.rho.data_ptr(),
                             self.screen.data_ptr())
+
+
+def spatial_order(atom_offset, x, y, z) -> np.ndarray:
+    """Morton order of each system's atoms (host computation in libgbmc)."""
+    off = np.ascontiguousarray(atom_offset, dtype=np.int32)
+    f64 = lambda v: np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+    xs, ys, zs = f64(x), f64(y), f64(z)
+    out = np.zeros(int(off[-1]), dtype=np.int32)
+    L.check(L.load().gbmc_spatial_order(int(off.size - 1), _i32p(off), _f64p(xs), _f64p(ys),
+                                        _f64p(zs), _i32p(out)))
+    return out
 
 
 def radii(plan: Plan, atoms: Atoms, params: GBParams = IGB5) -> torch.Tensor:

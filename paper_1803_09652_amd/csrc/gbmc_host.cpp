@@ -9,6 +9,7 @@
 #include <exception>
 #include <initializer_list>
 #include <new>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -46,6 +47,7 @@ struct gbmc_plan {
     std::vector<int32_t> offset;     // [B+1]
     int32_t n_items = 0;
     WorkItem* d_items = nullptr;
+    int32_t* d_perm = nullptr;       // [N] internal -> caller atom index
     int device = 0;
     // timing hook: events bracketing each timed kernel, recorded while enabled
     bool timing = false;
@@ -53,7 +55,7 @@ struct gbmc_plan {
     bool recorded[kNumKernels] = {};
     // workspace layout (byte offsets)
     size_t off_I, off_F, off_G, off_phi, off_drho, off_E, off_I64, off_R64, off_T64, off_dR64,
-        off_G64, off_B64, off_Rt, off_at, off_Brt, off_ovf, ws_bytes;
+        off_G64, off_B64, off_Rt, off_at, off_Brt, off_ovf, off_P, off_Gx, off_A64, ws_bytes;
 };
 
 struct gbmc_sites {
@@ -123,6 +125,9 @@ static Work<T> carve(const gbmc_plan* p, void* ws)
 {
     char* b = static_cast<char*>(ws);
     Work<T> w;
+    w.perm = p->d_perm;
+    w.P = reinterpret_cast<Q4<T>*>(b + p->off_P);
+    w.Gx = reinterpret_cast<Q4<T>*>(b + p->off_Gx);
     w.I_fx = reinterpret_cast<unsigned long long*>(b + p->off_I);
     w.F_fx = reinterpret_cast<unsigned long long*>(b + p->off_F);
     w.G_fx = reinterpret_cast<unsigned long long*>(b + p->off_G);
@@ -131,6 +136,7 @@ static Work<T> carve(const gbmc_plan* p, void* ws)
     w.E_fx = reinterpret_cast<unsigned long long*>(b + p->off_E);
     w.I64 = reinterpret_cast<double*>(b + p->off_I64);
     w.R64 = reinterpret_cast<double*>(b + p->off_R64);
+    w.A64 = reinterpret_cast<double*>(b + p->off_A64);
     w.T64 = reinterpret_cast<double*>(b + p->off_T64);
     w.dRdPsi64 = reinterpret_cast<double*>(b + p->off_dR64);
     w.G64 = reinterpret_cast<double*>(b + p->off_G64);
@@ -158,6 +164,7 @@ static void layout(gbmc_plan* p)
     p->off_E = seg(8 * 2 * B);
     p->off_I64 = seg(8 * N);
     p->off_R64 = seg(8 * N);
+    p->off_A64 = seg(8 * N);
     p->off_T64 = seg(8 * N);
     p->off_dR64 = seg(8 * N);
     p->off_G64 = seg(8 * N);
@@ -165,6 +172,8 @@ static void layout(gbmc_plan* p)
     p->off_Rt = seg(ts * N);
     p->off_at = seg(ts * N);
     p->off_Brt = seg(ts * N);
+    p->off_P = seg(4 * ts * N);
+    p->off_Gx = seg(4 * ts * N);
     p->ws_bytes = o;
 }
 
@@ -270,11 +279,21 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
         layout(p);
         hipError_t e = hipGetDevice(&p->device);
         if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
-        if (!items.empty()) {
-            e = hipMalloc(&p->d_items, items.size() * sizeof(WorkItem));
-            if (e != hipSuccess) { delete p; return hip_fail(e, "hipMalloc(work list)"); }
-            e = hipMemcpy(p->d_items, items.data(), items.size() * sizeof(WorkItem), hipMemcpyHostToDevice);
-            if (e != hipSuccess) { (void)hipFree(p->d_items); delete p; return hip_fail(e, "hipMemcpy(work list)"); }
+        // one device allocation: work list, then the processing order (identity)
+        const size_t items_bytes = align256(items.size() * sizeof(WorkItem));
+        const size_t perm_bytes = 4 * (size_t)p->n_atoms;
+        if (items_bytes + perm_bytes > 0) {
+            char* d = nullptr;
+            e = hipMalloc(&d, items_bytes + perm_bytes);
+            if (e != hipSuccess) { delete p; return hip_fail(e, "hipMalloc(plan tables)"); }
+            p->d_items = reinterpret_cast<WorkItem*>(d);
+            p->d_perm = reinterpret_cast<int32_t*>(d + items_bytes);
+            std::vector<char> h(items_bytes + perm_bytes, 0);
+            if (!items.empty()) std::memcpy(h.data(), items.data(), items.size() * sizeof(WorkItem));
+            int32_t* id = reinterpret_cast<int32_t*>(h.data() + items_bytes);
+            for (int32_t k = 0; k < p->n_atoms; ++k) id[k] = k;
+            e = hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) { (void)hipFree(d); delete p; return hip_fail(e, "hipMemcpy(plan tables)"); }
         }
         *out = p;
         return GBMC_OK;
@@ -319,6 +338,83 @@ gbmc_status gbmc_plan_kernel_ms(gbmc_plan* p, float* ms)
 }
 
 size_t gbmc_plan_workspace_bytes(const gbmc_plan* p) { return p ? p->ws_bytes : 0; }
+
+static gbmc_status check_order(int32_t n_systems, const int32_t* off, const int32_t* order)
+{
+    const int32_t N = n_systems > 0 ? off[n_systems] : 0;
+    if (N > 0 && !order) return fail(GBMC_ERR_INVALID, "order is NULL");
+    std::vector<char> seen(N, 0);
+    for (int32_t b = 0; b < n_systems; ++b)
+        for (int32_t k = off[b]; k < off[b + 1]; ++k) {
+            const int32_t c = order[k];
+            if (c < off[b] || c >= off[b + 1])
+                return fail(GBMC_ERR_INVALID, "order maps an atom outside its system");
+            if (seen[c]) return fail(GBMC_ERR_INVALID, "order is not a permutation");
+            seen[c] = 1;
+        }
+    return GBMC_OK;
+}
+
+gbmc_status gbmc_plan_set_order(gbmc_plan* p, const int32_t* order)
+{
+    try {
+        if (!p) return fail(GBMC_ERR_INVALID, "plan is NULL");
+        gbmc_status st = check_order(p->n_sys, p->offset.data(), order);
+        if (st != GBMC_OK) return st;
+        if (p->n_atoms == 0) return GBMC_OK;
+        hipError_t e = hipMemcpy(p->d_perm, order, 4 * (size_t)p->n_atoms, hipMemcpyHostToDevice);
+        return e == hipSuccess ? GBMC_OK : hip_fail(e, "hipMemcpy(order)");
+    } catch (const std::bad_alloc&) {
+        return fail(GBMC_ERR_INVALID, "host allocation failed");
+    }
+}
+
+gbmc_status gbmc_spatial_order(int32_t n_systems, const int32_t* off, const double* x,
+                               const double* y, const double* z, int32_t* order)
+{
+    try {
+        gbmc_status st = check_offsets(n_systems, off);
+        if (st != GBMC_OK) return st;
+        const int32_t N = n_systems > 0 ? off[n_systems] : 0;
+        if (N > 0 && (!x || !y || !z || !order)) return fail(GBMC_ERR_INVALID, "NULL argument");
+        std::vector<std::pair<uint64_t, int32_t>> key;
+        for (int32_t b = 0; b < n_systems; ++b) {
+            const int32_t a0 = off[b], a1 = off[b + 1];
+            if (a1 == a0) continue;
+            double lo[3] = {x[a0], y[a0], z[a0]}, hi[3] = {x[a0], y[a0], z[a0]};
+            for (int32_t k = a0; k < a1; ++k) {
+                const double v[3] = {x[k], y[k], z[k]};
+                for (int d = 0; d < 3; ++d) {
+                    if (!std::isfinite(v[d])) return fail(GBMC_ERR_INVALID, "non-finite coordinate");
+                    lo[d] = std::min(lo[d], v[d]);
+                    hi[d] = std::max(hi[d], v[d]);
+                }
+            }
+            key.clear();
+            for (int32_t k = a0; k < a1; ++k) {
+                const double v[3] = {x[k], y[k], z[k]};
+                uint64_t code = 0;
+                uint32_t q[3];
+                for (int d = 0; d < 3; ++d) {
+                    const double span = hi[d] - lo[d];
+                    const double t = span > 0 ? (v[d] - lo[d]) / span : 0.0;
+                    q[d] = (uint32_t)std::min(1023.0, std::floor(t * 1024.0));
+                }
+                for (int bit = 9; bit >= 0; --bit)      // Morton (Z-order) interleave
+                    for (int d = 0; d < 3; ++d) code = (code << 1) | ((q[d] >> bit) & 1u);
+                key.emplace_back(code, k);
+            }
+            std::stable_sort(key.begin(), key.end(),
+                             [](const std::pair<uint64_t, int32_t>& a, const std::pair<uint64_t, int32_t>& c) {
+                                 return a.first < c.first;
+                             });
+            for (int32_t k = a0; k < a1; ++k) order[k] = key[k - a0].second;
+        }
+        return GBMC_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(GBMC_ERR_INVALID, "host allocation failed");
+    }
+}
 
 static hipEvent_t* events(gbmc_plan* p, std::initializer_list<int> ids)
 {

@@ -9,13 +9,18 @@ namespace gbmc {
 constexpr int kTile = 64;                 // atoms per block; one wavefront per tile
 constexpr int kMaxSiteAtoms = 256;
 constexpr int kMaxStates = 8;
-constexpr int kPhiChunk = 512;            // j atoms per FP64 potential-row work item
+constexpr int kPhiChunk = 128;            // j atoms per FP64 potential-row work item
 
 // Fixed-point scales (powers of two, so scaling is exact).
 constexpr double kScaleI = 4503599627370496.0;   // 2^52: descreening sums, 1/A
 constexpr double kScaleF = 1099511627776.0;      // 2^40: forces, dE/dR, dE/dq, dE/drho
 constexpr double kScaleE = 4294967296.0;         // 2^32: energies
 constexpr double kFixLimit = 4611686018427387904.0;  // 2^62
+
+template <typename T>
+struct alignas(4 * sizeof(T)) Q4 {
+    T x, y, z, w;
+};
 
 // One pair work item: system `sys` (atoms [base, base+n)), i block I, j blocks
 // [J0, J1) with J0 >= I.
@@ -29,24 +34,30 @@ struct RowItem {
     int32_t base, n, sa0, sa1, j0, j1, out, pad;
 };
 
-// Device pointers carved from the caller's workspace.
+// Device pointers carved from the caller's workspace.  Per-atom arrays marked
+// "internal" are in the plan's processing order (perm[k] is the caller index
+// of internal atom k); the FP64 per-atom state is in caller order.
 template <typename T>
 struct Work {
-    unsigned long long* I_fx;     // [N]
-    unsigned long long* F_fx;     // [3][N]
-    unsigned long long* G_fx;     // [N]
-    unsigned long long* phi_fx;   // [N]
-    unsigned long long* drho_fx;  // [N]
+    const int32_t* perm;          // [N] internal -> caller index (plan memory)
+    Q4<T>* P;                     // [N] internal: x, y, z, q
+    Q4<T>* Gx;                    // [N] internal: rho - offset, screen (rho - offset), screen, 0
+    unsigned long long* I_fx;     // [N] internal
+    unsigned long long* F_fx;     // [N][3] internal
+    unsigned long long* G_fx;     // [N] internal
+    unsigned long long* phi_fx;   // [N] internal
+    unsigned long long* drho_fx;  // [N] internal
     unsigned long long* E_fx;     // [B][2]
     double* I64;                  // [N] descreening sum
     double* R64;                  // [N] Born radius
+    double* A64;                  // [N] 1 / (2 R)
     double* T64;                  // [N] tanh(theta)
     double* dRdPsi64;             // [N]
     double* G64;                  // [N] dE/dR
     double* B64;                  // [N] dE/dR * dR/dPsi
-    T* R_t;                       // [N] Born radius in the pair precision
-    T* a_t;                       // [N] sqrt(log2(e)/4) / R
-    T* Brt_t;                     // [N] B * (rho - offset)
+    T* R_t;                       // [N] internal: Born radius in the pair precision
+    T* a_t;                       // [N] internal: sqrt(log2(e)/4) / R
+    T* Brt_t;                     // [N] internal: B * (rho - offset)
     int* ovf;                     // overflow flag
 };
 

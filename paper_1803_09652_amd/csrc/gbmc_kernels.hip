@@ -39,11 +39,6 @@ constexpr double kLn10 = 2.302585092994045684;
 // sqrt(log2(e) / 4): a_i a_j r^2 = r^2 log2(e) / (4 R_i R_j)
 constexpr double kAScale = 0.60056120439322491;
 
-template <typename T>
-struct alignas(4 * sizeof(T)) Q4 {
-    T x, y, z, w;
-};
-
 // ------------------------------------------------------------------ math
 
 __device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
@@ -103,7 +98,7 @@ __device__ __forceinline__ double from_lane(double v, int src)
 // ------------------------------------------------------------ HCT integral
 // H(r; rt, S): the (1/4 pi) integral of |x|^-4 over the part of the ball of
 // radius S at distance r outside radius rt.  General closed form (all cases),
-// in FP64: when the two spheres overlap the bracket cancels by up to ~10^2.
+// used by the FP64 plans.
 __device__ __forceinline__ double hct_general(double r, double invr, double rt, double S)
 {
     double U = r + S;
@@ -136,6 +131,60 @@ __device__ __forceinline__ void hct_general_grad(double r, double invr, double r
     if (rt >= U) { dr = 0.0; drt = 0.0; dS = 0.0; }
 }
 
+// FP32 form of H and its partials that does not cancel when the spheres
+// overlap.  With L = max(rt, |r - S|), U = r + S, e = (U - L)/L:
+//   (1/(4r)) * integral_L^U (S^2 - (t - r)^2) / t^3 dt = J / (4r),
+//   J = [e - log(1 + e)] + (S - r) e^2 / (2U),
+// and, at fixed L (the L-dependence vanishes or cancels, see hct_general_grad),
+//   dJ/dr = e/U - e^2/(2U) + (S - r)(e/(L U) - e^2/(2U^2)),
+//   dJ/dS = e/U + e^2/(2U) + (S - r)(e/(L U) - e^2/(2U^2)),
+//   dH/drt = -e (L + S - r) / (4 r L^2) when L = rt.
+// e - log(1 + e) = e z - 2 z^3 (1/3 + z^2/5 + ...), z = e / (2 + e), for e <= 1.
+__device__ __forceinline__ float e_minus_log1p(float e)
+{
+    if (e <= 1.0f) {
+        float z = e * rcp(2.0f + e), z2 = z * z;
+        float p = 1.0f / 17.0f;
+        p = fmaf(p, z2, 1.0f / 15.0f);
+        p = fmaf(p, z2, 1.0f / 13.0f);
+        p = fmaf(p, z2, 1.0f / 11.0f);
+        p = fmaf(p, z2, 1.0f / 9.0f);
+        p = fmaf(p, z2, 1.0f / 7.0f);
+        p = fmaf(p, z2, 1.0f / 5.0f);
+        p = fmaf(p, z2, 1.0f / 3.0f);
+        return fmaf(-2.0f * z * z2, p, e * z);
+    }
+    return e - __builtin_amdgcn_logf(1.0f + e) * 0.693147180559945309f;
+}
+
+template <bool GRAD>
+__device__ __forceinline__ float hct_slow32(float r, float invr, float rt, float S, float* g)
+{
+    float U = r + S;
+    float dRS = r - S, ad = fabsf(dRS);
+    bool l_rt = rt > ad;
+    float L = l_rt ? rt : ad;
+    float delta = l_rt ? ((S - rt) + r) : (dRS < 0.0f ? 2.0f * r : 2.0f * S);   // U - L
+    float invL = rcp(L), invU = rcp(U);
+    float e = delta * invL;
+    float J = fmaf((S - r) * 0.5f * invU, e * e, e_minus_log1p(e));
+    float H = 0.25f * invr * J;
+    bool eng = rt < S - r;
+    if (eng) H += ((S - rt) - r) * invL * rcp(rt);   // 1/rt - 1/L
+    bool zero = rt >= U;
+    if (GRAD) {
+        float eU = e * invU;
+        float cross = (S - r) * eU * (invL - 0.5f * e * invU);
+        float Jr = eU * (1.0f - 0.5f * e) + cross;
+        float JS = eU * (1.0f + 0.5f * e) + cross;
+        float irt = rcp(rt);
+        g[0] = zero ? 0.0f : 0.25f * invr * (Jr - J * invr);
+        g[1] = zero ? 0.0f : (l_rt ? -0.25f * invr * e * (L + S - r) * invL * invL : (eng ? -irt * irt : 0.0f));
+        g[2] = zero ? 0.0f : 0.25f * invr * JS;
+    }
+    return zero ? 0.0f : H;
+}
+
 __device__ __forceinline__ void dist64(double xi, double yi, double zi, double xj, double yj,
                                        double zj, double& r, double& invr)
 {
@@ -147,7 +196,7 @@ __device__ __forceinline__ void dist64(double xi, double yi, double zi, double x
 
 // Pass-1 pair: H(r; rt_i, S_j) and H(r; rt_j, S_i).
 // FP32: non-overlapping pairs (r - S >= rt, x = S/r with x^2 <= YMAX) use
-// H = x^3 P(x^2) / r; every other pair takes the FP64 closed form.
+// H = x^3 P(x^2) / r; every other pair takes hct_slow32.
 __device__ __forceinline__ void radii_pair(float xi, float yi, float zi, float xj, float yj, float zj,
                                            float rti, float Si, float rtj, float Sj, float& hij,
                                            float& hji)
@@ -163,10 +212,8 @@ __device__ __forceinline__ void radii_pair(float xi, float yi, float zi, float x
     bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX);
     bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX);
     if (!(f_ij & f_ji)) {
-        double rd, invrd;
-        dist64(xi, yi, zi, xj, yj, zj, rd, invrd);
-        if (!f_ij) hij = (float)hct_general(rd, invrd, rti, Sj);
-        if (!f_ji) hji = (float)hct_general(rd, invrd, rtj, Si);
+        if (!f_ij) hij = hct_slow32<false>(r, invr, rti, Sj, nullptr);
+        if (!f_ji) hji = hct_slow32<false>(r, invr, rtj, Si, nullptr);
     }
 }
 
@@ -201,16 +248,8 @@ __device__ __forceinline__ void chain_pair_grads(float xi, float yi, float zi, f
     bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX);
     bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX);
     if (!(f_ij & f_ji)) {
-        double rd, invrd, a, b, c;
-        dist64(xi, yi, zi, xj, yj, zj, rd, invrd);
-        if (!f_ij) {
-            hct_general_grad(rd, invrd, rti, Sj, a, b, c);
-            gij[0] = (float)a; gij[1] = (float)b; gij[2] = (float)c;
-        }
-        if (!f_ji) {
-            hct_general_grad(rd, invrd, rtj, Si, a, b, c);
-            gji[0] = (float)a; gji[1] = (float)b; gji[2] = (float)c;
-        }
+        if (!f_ij) hct_slow32<true>(r, invr, rti, Sj, gij);
+        if (!f_ji) hct_slow32<true>(r, invr, rtj, Si, gji);
     }
 }
 
@@ -268,16 +307,41 @@ __device__ __forceinline__ void walk_tile(bool diagonal, T (&acc_j)[NJ], Pair&& 
     }
 }
 
+// ============================================================ staging
+// Packs the caller's SoA inputs into the plan's processing order (a spatial
+// order keeps overlapping pairs inside few tiles): P = (x, y, z, q),
+// Gx = (rt, S, screen, 0) with rt = rho - offset and S = screen rt.
+
+template <typename T>
+__global__ void k_stage(int n_atoms, const int32_t* __restrict__ perm, const T* __restrict__ X,
+                        const T* __restrict__ Y, const T* __restrict__ Z, const T* __restrict__ Q,
+                        const T* __restrict__ RHO, const T* __restrict__ SCR, T offset,
+                        Q4<T>* __restrict__ P, Q4<T>* __restrict__ Gx)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_atoms) return;
+    int c = perm[k];
+    Q4<T> p;
+    p.x = X[c]; p.y = Y[c]; p.z = Z[c];
+    p.w = Q ? Q[c] : T(0);
+    P[k] = p;
+    Q4<T> g;
+    g.x = RHO[c] - offset;
+    g.z = SCR[c];
+    g.y = g.z * g.x;
+    g.w = T(0);
+    Gx[k] = g;
+}
+
 // ================================================================ pass 1
 // I_i = sum_{j != i} H(r_ij; rt_i, S_j) over every unordered pair once.
 
 template <typename T>
 __global__ __launch_bounds__(kTile) void k_radii_pairs(
-    const WorkItem* __restrict__ items, const T* __restrict__ X, const T* __restrict__ Y,
-    const T* __restrict__ Z, const T* __restrict__ RHO, const T* __restrict__ SCR, T offset,
+    const WorkItem* __restrict__ items, const Q4<T>* __restrict__ P, const Q4<T>* __restrict__ Gx,
     unsigned long long* __restrict__ I_fx, int* __restrict__ ovf)
 {
-    __shared__ Q4<T> sj[2 * kTile];
+    __shared__ Q4<T> sj[2 * kTile];     // x, y, z, rt
     __shared__ T sS[2 * kTile];
     const int lane = threadIdx.x;
     const WorkItem w = items[blockIdx.x];
@@ -285,10 +349,11 @@ __global__ __launch_bounds__(kTile) void k_radii_pairs(
     const bool vi = i < w.n;
     T xi, yi, zi, rti, Si;
     if (vi) {
-        int g = w.base + i;
-        xi = X[g]; yi = Y[g]; zi = Z[g];
-        rti = RHO[g] - offset;
-        Si = SCR[g] * rti;
+        const Q4<T> p = P[w.base + i];
+        const Q4<T> gx = Gx[w.base + i];
+        xi = p.x; yi = p.y; zi = p.z;
+        rti = gx.x;
+        Si = gx.y;
     } else {
         dummy_pos(i, xi, yi, zi);
         rti = T(1);
@@ -301,10 +366,11 @@ __global__ __launch_bounds__(kTile) void k_radii_pairs(
         Q4<T> pj;
         T Sj;
         if (vj) {
-            int g = w.base + j;
-            pj.x = X[g]; pj.y = Y[g]; pj.z = Z[g];
-            pj.w = RHO[g] - offset;
-            Sj = SCR[g] * pj.w;
+            const Q4<T> p = P[w.base + j];
+            const Q4<T> gx = Gx[w.base + j];
+            pj.x = p.x; pj.y = p.y; pj.z = p.z;
+            pj.w = gx.x;
+            Sj = gx.y;
         } else {
             dummy_pos(j, pj.x, pj.y, pj.z);
             pj.w = T(1);
@@ -332,26 +398,29 @@ __global__ __launch_bounds__(kTile) void k_radii_pairs(
 }
 
 // Per atom: OBC radius from the descreening sum (FP64), and the per-atom state
-// of the later passes.
+// of the later passes (FP64 state in caller order, pair-precision copies in
+// internal order).
 template <typename T>
 __global__ void k_radii_finalize(int n_atoms, const T* __restrict__ RHO, GBConst c, Work<T> w,
                                  T* __restrict__ born_R)
 {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n_atoms) return;
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_atoms) return;
+    const int g = w.perm[k];
     double rho = (double)RHO[g];
     double rt = rho - c.offset;
-    double I = (double)(long long)w.I_fx[g] * (1.0 / kScaleI);
+    double I = (double)(long long)w.I_fx[k] * (1.0 / kScaleI);
     double psi = rt * I;
     double th = c.alpha * psi - c.beta * psi * psi + c.gamma * psi * psi * psi;
     double t = tanh(th);
     double R = 1.0 / (1.0 / rt - t / rho);
     w.I64[g] = I;
     w.R64[g] = R;
+    w.A64[g] = 0.5 / R;
     w.T64[g] = t;
     w.dRdPsi64[g] = R * R * (1.0 - t * t) * (c.alpha - 2.0 * c.beta * psi + 3.0 * c.gamma * psi * psi) / rho;
-    w.R_t[g] = (T)R;
-    w.a_t[g] = (T)(kAScale / R);
+    w.R_t[k] = (T)R;
+    w.a_t[k] = (T)(kAScale / R);
     if (born_R) born_R[g] = (T)R;
 }
 
@@ -360,8 +429,7 @@ __global__ void k_radii_finalize(int n_atoms, const T* __restrict__ RHO, GBConst
 
 template <typename T, bool GRAD>
 __global__ __launch_bounds__(kTile) void k_energy_pairs(
-    const WorkItem* __restrict__ items, const T* __restrict__ X, const T* __restrict__ Y,
-    const T* __restrict__ Z, const T* __restrict__ Q, const T* __restrict__ Rt,
+    const WorkItem* __restrict__ items, const Q4<T>* __restrict__ P, const T* __restrict__ Rt,
     const T* __restrict__ At, T kC, T kT, Work<T> wk)
 {
     __shared__ Q4<T> sj[2 * kTile];     // x, y, z, q
@@ -375,7 +443,8 @@ __global__ __launch_bounds__(kTile) void k_energy_pairs(
     T xi, yi, zi, qi, Ri, ai;
     if (vi) {
         int g = w.base + i;
-        xi = X[g]; yi = Y[g]; zi = Z[g]; qi = Q[g];
+        const Q4<T> p = P[g];
+        xi = p.x; yi = p.y; zi = p.z; qi = p.w;
         Ri = Rt[g]; ai = At[g];
     } else {
         dummy_pos(i, xi, yi, zi);
@@ -390,7 +459,7 @@ __global__ __launch_bounds__(kTile) void k_energy_pairs(
         T Rj, Aj;
         if (vj) {
             int g = w.base + j;
-            pj.x = X[g]; pj.y = Y[g]; pj.z = Z[g]; pj.w = Q[g];
+            pj = P[g];
             Rj = Rt[g]; Aj = At[g];
         } else {
             dummy_pos(j, pj.x, pj.y, pj.z);
@@ -487,22 +556,22 @@ __global__ __launch_bounds__(kTile) void k_energy_pairs(
 // Per atom after pass 2: B = G dR/dPsi for the chain pass; dE/dq output;
 // energies per system.
 template <typename T>
-__global__ void k_energy_finalize(int n_atoms, int n_sys, const T* __restrict__ RHO, double offset,
-                                  Work<T> w, double* __restrict__ e_coul, double* __restrict__ e_gb,
-                                  T* __restrict__ dEdq, bool grad)
+__global__ void k_energy_finalize(int n_atoms, int n_sys, Work<T> w, double* __restrict__ e_coul,
+                                  double* __restrict__ e_gb, T* __restrict__ dEdq, bool grad)
 {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < n_sys) {
-        if (e_coul) e_coul[g] = (double)(long long)w.E_fx[2 * g] * (1.0 / kScaleE);
-        if (e_gb) e_gb[g] = (double)(long long)w.E_fx[2 * g + 1] * (1.0 / kScaleE);
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n_sys) {
+        if (e_coul) e_coul[k] = (double)(long long)w.E_fx[2 * k] * (1.0 / kScaleE);
+        if (e_gb) e_gb[k] = (double)(long long)w.E_fx[2 * k + 1] * (1.0 / kScaleE);
     }
-    if (!grad || g >= n_atoms) return;
-    double G = (double)(long long)w.G_fx[g] * (1.0 / kScaleF);
+    if (!grad || k >= n_atoms) return;
+    const int g = w.perm[k];
+    double G = (double)(long long)w.G_fx[k] * (1.0 / kScaleF);
     double B = G * w.dRdPsi64[g];
     w.G64[g] = G;
     w.B64[g] = B;
-    w.Brt_t[g] = (T)(B * ((double)RHO[g] - offset));
-    if (dEdq) dEdq[g] = (T)((double)(long long)w.phi_fx[g] * (1.0 / kScaleF));
+    w.Brt_t[k] = (T)(B * (double)w.Gx[k].x);
+    if (dEdq) dEdq[g] = (T)((double)(long long)w.phi_fx[k] * (1.0 / kScaleF));
 }
 
 // ================================================================ pass 3
@@ -510,8 +579,7 @@ __global__ void k_energy_finalize(int n_atoms, int n_sys, const T* __restrict__ 
 
 template <typename T>
 __global__ __launch_bounds__(kTile) void k_chain_pairs(
-    const WorkItem* __restrict__ items, const T* __restrict__ X, const T* __restrict__ Y,
-    const T* __restrict__ Z, const T* __restrict__ RHO, const T* __restrict__ SCR, T offset,
+    const WorkItem* __restrict__ items, const Q4<T>* __restrict__ P, const Q4<T>* __restrict__ Gx,
     const T* __restrict__ Brt, Work<T> wk)
 {
     __shared__ Q4<T> sj[2 * kTile];     // x, y, z, rt
@@ -523,10 +591,12 @@ __global__ __launch_bounds__(kTile) void k_chain_pairs(
     T xi, yi, zi, rti, Si, Bi, si;
     if (vi) {
         int g = w.base + i;
-        xi = X[g]; yi = Y[g]; zi = Z[g];
-        rti = RHO[g] - offset;
-        si = SCR[g];
-        Si = si * rti;
+        const Q4<T> p = P[g];
+        const Q4<T> gx = Gx[g];
+        xi = p.x; yi = p.y; zi = p.z;
+        rti = gx.x;
+        Si = gx.y;
+        si = gx.z;
         Bi = Brt[g];
     } else {
         dummy_pos(i, xi, yi, zi);
@@ -539,10 +609,12 @@ __global__ __launch_bounds__(kTile) void k_chain_pairs(
         Q4<T> pj, bj;
         if (vj) {
             int g = w.base + j;
-            pj.x = X[g]; pj.y = Y[g]; pj.z = Z[g];
-            pj.w = RHO[g] - offset;
-            bj.z = SCR[g];
-            bj.x = bj.z * pj.w;
+            const Q4<T> p = P[g];
+            const Q4<T> gx = Gx[g];
+            pj.x = p.x; pj.y = p.y; pj.z = p.z;
+            pj.w = gx.x;
+            bj.x = gx.y;
+            bj.z = gx.z;
             bj.y = Brt[g];
         } else {
             dummy_pos(j, pj.x, pj.y, pj.z);
@@ -603,12 +675,13 @@ template <typename T>
 __global__ void k_grad_finalize(int n_atoms, const T* __restrict__ RHO, double offset, Work<T> w,
                                 T* __restrict__ force, T* __restrict__ dEdrho)
 {
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n_atoms) return;
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_atoms) return;
+    const int g = w.perm[k];
     if (force) {
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-            force[3 * (size_t)g + a] = (T)((double)(long long)w.F_fx[3 * (size_t)g + a] * (1.0 / kScaleF));
+            force[3 * (size_t)g + a] = (T)((double)(long long)w.F_fx[3 * (size_t)k + a] * (1.0 / kScaleF));
     }
     if (dEdrho) {
         double rho = (double)RHO[g];
@@ -616,7 +689,7 @@ __global__ void k_grad_finalize(int n_atoms, const T* __restrict__ RHO, double o
         double R = w.R64[g];
         double v = w.G64[g] * R * R * (1.0 / (rt * rt) - w.T64[g] / (rho * rho))
                  + w.B64[g] * w.I64[g]
-                 + (double)(long long)w.drho_fx[g] * (1.0 / kScaleF);
+                 + (double)(long long)w.drho_fx[k] * (1.0 / kScaleF);
         dEdrho[g] = (T)v;
     }
 }
@@ -633,42 +706,49 @@ __global__ void k_zero64(unsigned long long* __restrict__ p, size_t n)
 // over all atoms of the system, split in chunks written to phi_part and summed
 // in chunk order by k_site_dE (no atomics, deterministic).
 
+// FP64 1/sqrt: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rsq64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
+// k/(eps_in r) - k tau / f_GB for one pair (FP64); a = 1/(2R).
+__device__ __forceinline__ double pairK(double dx, double dy, double dz, double Ra, double aa,
+                                        double Rb, double ab, double kC, double kT)
+{
+    double r2 = dx * dx + dy * dy + dz * dz;
+    double invr = rsq64(r2);
+    double ex = exp(-r2 * (aa * ab));
+    double invf = rsq64(fma(Ra * Rb, ex, r2));
+    return kC * invr - kT * invf;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kTile) void k_site_phi_rows(
     const RowItem* __restrict__ items, const int32_t* __restrict__ site_atoms,
     const T* __restrict__ X, const T* __restrict__ Y, const T* __restrict__ Z,
-    const T* __restrict__ Q, const double* __restrict__ R64, double kC, double kT,
-    double* __restrict__ phi_part)
+    const T* __restrict__ Q, const double* __restrict__ R64, const double* __restrict__ A64,
+    double kC, double kT, double* __restrict__ phi_part)
 {
     const RowItem w = items[blockIdx.x];
     const int lane = threadIdx.x;
     const int sa = w.sa0 + lane;
     const bool v = sa < w.sa1;
-    int gi = v ? site_atoms[sa] : w.base;
-    double xi = X[gi], yi = Y[gi], zi = Z[gi], Ri = R64[gi];
+    const int gi = v ? site_atoms[sa] : w.base;
+    const double xi = X[gi], yi = Y[gi], zi = Z[gi], Ri = R64[gi], Ai = A64[gi];
     double acc = 0.0;
+#pragma unroll 4
     for (int j = w.j0; j < w.j1; ++j) {
         const int gj = w.base + j;
-        double dx = xi - (double)X[gj], dy = yi - (double)Y[gj], dz = zi - (double)Z[gj];
-        double r2 = dx * dx + dy * dy + dz * dz;
-        double Rj = R64[gj];
-        double qj = (double)Q[gj];
-        double RR = Ri * Rj;
-        double f = sqrt(r2 + RR * exp(-r2 / (4.0 * RR)));
-        double term = qj * (kC / sqrt(r2) - kT / f);
-        acc += (gj == gi) ? 0.0 : term;
+        double K = pairK(xi - (double)X[gj], yi - (double)Y[gj], zi - (double)Z[gj], Ri, Ai,
+                         R64[gj], A64[gj], kC, kT);
+        acc += (gj == gi) ? 0.0 : (double)Q[gj] * K;
     }
     if (v) phi_part[w.out + lane] = acc;
-}
-
-__device__ __forceinline__ double pairK(double xa, double ya, double za, double Ra, double xb,
-                                        double yb, double zb, double Rb, double kC, double kT)
-{
-    double dx = xa - xb, dy = ya - yb, dz = za - zb;
-    double r2 = dx * dx + dy * dy + dz * dz;
-    double RR = Ra * Rb;
-    double f = sqrt(r2 + RR * exp(-r2 / (4.0 * RR)));
-    return kC / sqrt(r2) - kT / f;
 }
 
 // deterministic block reduction of NV doubles per thread (blockDim = 256)
@@ -696,12 +776,14 @@ constexpr int kMC = 256;   // threads of the per-site / per-system Monte Carlo k
 template <typename T>
 __global__ __launch_bounds__(kMC) void k_site_dE(
     SiteDev sd, const T* __restrict__ X, const T* __restrict__ Y, const T* __restrict__ Z,
-    const T* __restrict__ Q, const double* __restrict__ R64, double kC, double kT,
-    const double* __restrict__ phi_part, const int32_t* __restrict__ current_state,
+    const T* __restrict__ Q, const double* __restrict__ R64, const double* __restrict__ A64,
+    double kC, double kT, const double* __restrict__ phi_part,
+    const int32_t* __restrict__ current_state,
     const double* __restrict__ pH, const double* __restrict__ E_volt, double T_kelvin,
     double* __restrict__ dE, double* __restrict__ dG)
 {
     __shared__ double sx[kMaxSiteAtoms], sy[kMaxSiteAtoms], sz[kMaxSiteAtoms], sR[kMaxSiteAtoms];
+    __shared__ double sA[kMaxSiteAtoms];
     __shared__ double sphi[kMaxSiteAtoms];
     __shared__ double sdq[kMaxStates - 1][kMaxSiteAtoms];
     __shared__ double red[2 * (kMaxStates - 1)][256];
@@ -721,7 +803,7 @@ __global__ __launch_bounds__(kMC) void k_site_dE(
     for (int a = t; a < na; a += kMC) {
         int g = sd.site_atoms[a0 + a];
         double R = R64[g];
-        sx[a] = X[g]; sy[a] = Y[g]; sz[a] = Z[g]; sR[a] = R;
+        sx[a] = X[g]; sy[a] = Y[g]; sz[a] = Z[g]; sR[a] = R; sA[a] = A64[g];
         double phi = -kT * (double)Q[g] / R;           // self term
         const int slot = sa_site0 - sa_sys0 + a;
         for (int c = 0; c < chunks; ++c) phi += phi_part[sd.site_phi_offset[m] + c * n_sa_sys + slot];
@@ -746,7 +828,8 @@ __global__ __launch_bounds__(kMC) void k_site_dE(
         int a = p / na, b = p - a * na;
         if (b < a) continue;
         double K = (a == b) ? -kT / sR[a]
-                            : 2.0 * pairK(sx[a], sy[a], sz[a], sR[a], sx[b], sy[b], sz[b], sR[b], kC, kT);
+                            : 2.0 * pairK(sx[a] - sx[b], sy[a] - sy[b], sz[a] - sz[b], sR[a], sA[a],
+                                          sR[b], sA[b], kC, kT);
 #pragma unroll
         for (int c = 0; c < kMaxStates - 1; ++c)
             if (c < nc) part[kMaxStates - 1 + c] += sdq[c][a] * sdq[c][b] * K;
@@ -780,8 +863,8 @@ __device__ __forceinline__ int pick_index(double u, int n)
 template <typename T>
 __global__ __launch_bounds__(kMC) void k_mc_step(
     SiteDev sd, const T* __restrict__ X, const T* __restrict__ Y, const T* __restrict__ Z,
-    T* __restrict__ Q, const double* __restrict__ R64, double kC, double kT,
-    int32_t* __restrict__ current_state, const double* __restrict__ pH,
+    T* __restrict__ Q, const double* __restrict__ R64, const double* __restrict__ A64, double kC,
+    double kT, int32_t* __restrict__ current_state, const double* __restrict__ pH,
     const double* __restrict__ E_volt, double T_kelvin, const double* __restrict__ dEin,
     const double* __restrict__ dGin, const double* __restrict__ u,
     int32_t* __restrict__ n_electrons, int64_t* __restrict__ counters,
@@ -832,7 +915,9 @@ __global__ __launch_bounds__(kMC) void k_mc_step(
                 for (int p = t; p < nar * nap; p += kMC) {
                     int a = p / nap, c = p - a * nap;
                     int ga = sd.site_atoms[ar0 + a], gc = sd.site_atoms[ap0 + c];
-                    double K = pairK(X[ga], Y[ga], Z[ga], R64[ga], X[gc], Y[gc], Z[gc], R64[gc], kC, kT);
+                    double K = pairK((double)X[ga] - (double)X[gc], (double)Y[ga] - (double)Y[gc],
+                                     (double)Z[ga] - (double)Z[gc], R64[ga], A64[ga], R64[gc],
+                                     A64[gc], kC, kT);
                     part[0] += (qr1[a] - qr0[a]) * (qp1[c] - qp0[c]) * K;
                 }
                 block_sum<1>(red, part);
@@ -925,10 +1010,12 @@ hipError_t launch_radii(const WorkItem* items, int n_items, int n_atoms, const i
     // I_fx and the overflow word right after it start every evaluation at zero
     hipLaunchKernelGGL(k_zero64, dim3(blocks_for(n_atoms + 1, 256)), dim3(256), 0, s, w.I_fx,
                        (size_t)n_atoms + 1);
+    hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms, w.perm,
+                       x, y, z, (const T*)nullptr, rho, screen, (T)c.offset, w.P, w.Gx);
     if (n_items > 0) {
         mark(ev, kKRadii, 0, s);
-        hipLaunchKernelGGL(k_radii_pairs<T>, dim3(n_items), dim3(kTile), 0, s, items, x, y, z, rho,
-                           screen, (T)c.offset, w.I_fx, w.ovf);
+        hipLaunchKernelGGL(k_radii_pairs<T>, dim3(n_items), dim3(kTile), 0, s, items, w.P, w.Gx,
+                           w.I_fx, w.ovf);
         mark(ev, kKRadii, 1, s);
     }
     hipLaunchKernelGGL(k_radii_finalize<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
@@ -949,24 +1036,28 @@ hipError_t launch_energy_forces(const WorkItem* items, int n_items, int n_atoms,
     size_t nz = grad ? (size_t)6 * n_atoms : 0;
     if (nz) hipLaunchKernelGGL(k_zero64, dim3(blocks_for(nz, 256)), dim3(256), 0, s, w.F_fx, nz);
     hipLaunchKernelGGL(k_zero64, dim3(1), dim3(256), 0, s, w.E_fx, (size_t)2 * n_sys);
+    // positions and charges as given to this call, in processing order
+    if (n_atoms > 0)
+        hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
+                           w.perm, x, y, z, q, rho, screen, (T)c.offset, w.P, w.Gx);
     if (n_items > 0) {
         mark(ev, kKEnergy, 0, s);
         if (grad)
-            hipLaunchKernelGGL((k_energy_pairs<T, true>), dim3(n_items), dim3(kTile), 0, s, items, x,
-                               y, z, q, w.R_t, w.a_t, (T)c.kC, (T)c.kT, w);
+            hipLaunchKernelGGL((k_energy_pairs<T, true>), dim3(n_items), dim3(kTile), 0, s, items,
+                               w.P, w.R_t, w.a_t, (T)c.kC, (T)c.kT, w);
         else
             hipLaunchKernelGGL((k_energy_pairs<T, false>), dim3(n_items), dim3(kTile), 0, s, items,
-                               x, y, z, q, w.R_t, w.a_t, (T)c.kC, (T)c.kT, w);
+                               w.P, w.R_t, w.a_t, (T)c.kC, (T)c.kT, w);
         mark(ev, kKEnergy, 1, s);
     }
     int nb = blocks_for(n_atoms > n_sys ? n_atoms : n_sys, 256);
     if (nb > 0)
-        hipLaunchKernelGGL(k_energy_finalize<T>, dim3(nb), dim3(256), 0, s, n_atoms, n_sys, rho,
-                           c.offset, w, e_coul, e_gb, dEdq, grad);
+        hipLaunchKernelGGL(k_energy_finalize<T>, dim3(nb), dim3(256), 0, s, n_atoms, n_sys, w,
+                           e_coul, e_gb, dEdq, grad);
     if (chain && n_items > 0) {
         mark(ev, kKChain, 0, s);
-        hipLaunchKernelGGL(k_chain_pairs<T>, dim3(n_items), dim3(kTile), 0, s, items, x, y, z, rho,
-                           screen, (T)c.offset, w.Brt_t, w);
+        hipLaunchKernelGGL(k_chain_pairs<T>, dim3(n_items), dim3(kTile), 0, s, items, w.P, w.Gx,
+                           w.Brt_t, w);
         mark(ev, kKChain, 1, s);
     }
     if (chain && n_atoms > 0)
@@ -985,12 +1076,12 @@ hipError_t launch_state_dE(const SiteDev& sd, const T* x, const T* y, const T* z
     if (sd.n_rowitems > 0) {
         mark(ev, kKSiteRows, 0, s);
         hipLaunchKernelGGL(k_site_phi_rows<T>, dim3(sd.n_rowitems), dim3(kTile), 0, s, sd.rowitems,
-                           sd.site_atoms, x, y, z, q, w.R64, c.kC, c.kT, phi_part);
+                           sd.site_atoms, x, y, z, q, w.R64, w.A64, c.kC, c.kT, phi_part);
         mark(ev, kKSiteRows, 1, s);
     }
     mark(ev, kKSiteDE, 0, s);
-    hipLaunchKernelGGL(k_site_dE<T>, dim3(sd.n_sites), dim3(kMC), 0, s, sd, x, y, z, q, w.R64, c.kC,
-                       c.kT, phi_part, current_state, pH, E_volt, T_kelvin, dE, dG);
+    hipLaunchKernelGGL(k_site_dE<T>, dim3(sd.n_sites), dim3(kMC), 0, s, sd, x, y, z, q, w.R64, w.A64,
+                       c.kC, c.kT, phi_part, current_state, pH, E_volt, T_kelvin, dE, dG);
     mark(ev, kKSiteDE, 1, s);
     return hipGetLastError();
 }
@@ -1005,9 +1096,9 @@ hipError_t launch_mc_step(const SiteDev& sd, int n_sys, const T* x, const T* y, 
 {
     if (n_sys == 0) return hipSuccess;
     mark(ev, kKMCStep, 0, s);
-    hipLaunchKernelGGL(k_mc_step<T>, dim3(n_sys), dim3(kMC), 0, s, sd, x, y, z, q, w.R64, c.kC,
-                       c.kT, current_state, pH, E_volt, T_kelvin, dE, dG, u, n_electrons, counters,
-                       accepted);
+    hipLaunchKernelGGL(k_mc_step<T>, dim3(n_sys), dim3(kMC), 0, s, sd, x, y, z, q, w.R64, w.A64,
+                       c.kC, c.kT, current_state, pH, E_volt, T_kelvin, dE, dG, u, n_electrons,
+                       counters, accepted);
     mark(ev, kKMCStep, 1, s);
     return hipGetLastError();
 }

@@ -168,3 +168,22 @@ def test_entry_points_reject_null_plan(L):
     assert lib.gb_radii(None, C.byref(a), C.byref(p), None, None, None) == L.GBMC_ERR_INVALID
     assert lib.gb_energy_forces(None, C.byref(a), C.byref(p), None, None, None, None, None, None,
                                 None) == L.GBMC_ERR_INVALID
+
+
+def test_spatial_order_is_a_local_permutation(L):
+    lib = L.load()
+    systems = synth.config2(n_rep=3)
+    batch = synth.make_batch(systems)
+    off = batch.atom_offset
+    out = np.zeros(batch.n_atoms, dtype=np.int32)
+    d = lambda a: np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(C.POINTER(C.c_double))
+    assert lib.gbmc_spatial_order(batch.n_systems, _i32p(off), d(batch.x), d(batch.y), d(batch.z),
+                                  _i32p(out)) == 0
+    xyz = np.stack([batch.x, batch.y, batch.z], 1)
+    for b in range(batch.n_systems):
+        seg = out[off[b]:off[b + 1]]
+        assert sorted(seg.tolist()) == list(range(off[b], off[b + 1]))
+        # consecutive atoms in the order are much closer than in the input order
+        step = np.linalg.norm(np.diff(xyz[seg], axis=0), axis=1).mean()
+        step0 = np.linalg.norm(np.diff(xyz[off[b]:off[b + 1]], axis=0), axis=1).mean()
+        assert step < 0.4 * step0
