@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 64 MiB device copy (reference for HBM counters)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip the work-shape sweep and use the library defaults")
     ap.add_argument("--order", choices=["spatial", "identity"], default="spatial",
                     help="processing order of the pair passes (results are order independent)")
     return ap.parse_args()
@@ -54,7 +58,7 @@ def parse():
 class Workload:
     """Config-2 E-REMD batch resident on the GPU, with static step buffers."""
 
-    def __init__(self, precision, n_steps, order="spatial"):
+    def __init__(self, precision, n_steps, order="spatial", tuning=None):
         import numpy as np
         import torch
         import paper_1803_09652_amd as g
@@ -63,7 +67,8 @@ class Workload:
         self.systems = synth.config2()
         self.batch = b = synth.make_batch(self.systems)
         self.B = b.n_systems
-        self.plan = g.Plan(b.atom_offset, precision)
+        jb, wv = tuning if tuning else (None, None)
+        self.plan = g.Plan(b.atom_offset, precision, j_blocks_per_item=jb, waves_per_group=wv)
         if order == "spatial":
             self.plan.set_order(g.spatial_order(b.atom_offset, b.x, b.y, b.z))
         self.atoms = g.Atoms.from_batch(self.plan, b)
@@ -124,10 +129,20 @@ class Workload:
         self.ux.copy_(self.ux_all[k])
 
 
-def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial"):
+def autotune(precision, order):
+    """Work-shape sweep on the benchmark batch (untimed setup)."""
+    import paper_1803_09652_amd as g
+    from paper_1803_09652_amd import autotune as at
+    import synth
+    b = synth.make_batch(synth.config2())
+    o = g.spatial_order(b.atom_offset, b.x, b.y, b.z) if order == "spatial" else None
+    return at.tune(b, precision, order=o, use_cache=False)
+
+
+def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial", tuning=None):
     import torch
     n_total = steps + warmup + kernel_steps + 2
-    w = Workload(precision, n_total, order)
+    w = Workload(precision, n_total, order, tuning)
     torch.cuda.synchronize()
     k = 0
     graphs = None
@@ -216,8 +231,21 @@ def main():
     import torch
     torch.cuda.set_device(0)
     use_graph = not args.no_graph
+    copy_ref = None
+    if args.copy_calibration:
+        # a plain device copy of known size: FETCH_SIZE / WRITE_SIZE of this
+        # dispatch calibrate the HBM byte counters of the pair kernels
+        n = 16 * 1024 * 1024
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        copy_ref = {"bytes_read": 4 * n, "bytes_written": 4 * n, "dispatches": 3}
+        del a, b
+    tune32 = None if args.no_autotune else autotune("fp32", args.order)
     w, ms_step, wall_ms, kms = run_gpu("fp32", args.steps, args.warmup, use_graph, args.kernel_steps,
-                                       args.order)
+                                       args.order, tune32["best"] if tune32 else None)
     pairs, n_cand = w.pairs, w.n_cand
     value = pairs / (ms_step * 1e-3)
     out = {
@@ -239,6 +267,8 @@ def main():
                         "no cutoff",
             "systems": w.B, "atoms": w.batch.n_atoms, "pairs_per_step": pairs,
             "candidates_per_step": n_cand, "hip_graph": use_graph, "atom_order": args.order,
+            "tuning": ({"j_blocks_per_item": tune32["best"][0], "waves_per_group": tune32["best"][1],
+                        "sweep_pair_ms": tune32["ms"]} if tune32 else "library default"),
             "precision": "FP32 pair arithmetic, int64 fixed-point sums, FP64 MC",
         },
         "mc_dE_evals_per_s": n_cand / (ms_step * 1e-3),
@@ -263,12 +293,16 @@ def main():
                             "exchange_accepted_eager": w.exchanges_accepted}
     del w
     if not args.no_fp64:
-        w64, ms64, _, k64 = run_gpu("fp64", args.fp64_steps, 2, use_graph, 3, args.order)
+        tune64 = None if args.no_autotune else autotune("fp64", args.order)
+        w64, ms64, _, k64 = run_gpu("fp64", args.fp64_steps, 2, use_graph, 3, args.order,
+                                    tune64["best"] if tune64 else None)
         v64 = pairs / (ms64 * 1e-3)
         out["fp64"] = {"value": v64, "ms_per_step": ms64, "steps": args.fp64_steps,
-                       "kernel_ms": k64}
+                       "kernel_ms": k64, "tuning": tune64["best"] if tune64 else None}
         out["fp32_over_fp64"] = value / v64
         del w64
+    if copy_ref is not None:
+        out["copy_calibration"] = copy_ref
     if not args.no_cpu_baseline:
         import synth
         out["cpu_baseline"] = cpu_baseline(synth.config2())

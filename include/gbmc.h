@@ -72,12 +72,14 @@ typedef struct {
     const void* screen;
 } gbmc_atoms;
 
-/* Work-shape knob of the pair kernels: how many 64-atom j blocks one
- * wavefront walks for its i block (>= 1; default 8).  Every 64 x 64 tile is
- * rounded into fixed point on its own, so results are bitwise independent of
- * this knob. */
+/* Work-shape knobs of the pair kernels: how many 64-atom j blocks one
+ * wavefront walks for its i block (>= 1; default 8), and how many such
+ * independent wavefronts share a workgroup (1, 2, 4 or 8; default 4).  Every
+ * 64 x 64 tile is rounded into fixed point on its own, so results are bitwise
+ * independent of both knobs. */
 typedef struct {
     int32_t j_blocks_per_item;
+    int32_t waves_per_group;
 } gbmc_tuning;
 
 typedef struct gbmc_plan gbmc_plan;

@@ -39,7 +39,7 @@ class gbmc_atoms(C.Structure):
 
 
 class gbmc_tuning(C.Structure):
-    _fields_ = [("j_blocks_per_item", C.c_int32)]
+    _fields_ = [("j_blocks_per_item", C.c_int32), ("waves_per_group", C.c_int32)]
 
 
 _I32P = C.POINTER(C.c_int32)

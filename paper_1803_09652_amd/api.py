@@ -63,7 +63,8 @@ class Plan:
     "fp64".  Owns the plan's device workspace."""
 
     def __init__(self, atom_offset: Sequence[int], precision: str = "fp32",
-                 j_blocks_per_item: Optional[int] = None, device=None):
+                 j_blocks_per_item: Optional[int] = None, waves_per_group: Optional[int] = None,
+                 device=None):
         lib = L.load()
         self.offset = np.ascontiguousarray(atom_offset, dtype=np.int32)
         if self.offset.ndim != 1 or self.offset.size < 1:
@@ -75,8 +76,8 @@ class Plan:
         self.device = torch.device("cuda", torch.cuda.current_device()) if device is None \
             else torch.device(device)
         tun = None
-        if j_blocks_per_item is not None:
-            tun = C.byref(L.gbmc_tuning(int(j_blocks_per_item)))
+        if j_blocks_per_item is not None or waves_per_group is not None:
+            tun = C.byref(L.gbmc_tuning(int(j_blocks_per_item or 8), int(waves_per_group or 4)))
         h = C.c_void_p()
         with torch.cuda.device(self.device):
             L.check(lib.gbmc_plan_create(C.byref(h), int(self.offset.size - 1), _i32p(self.offset),

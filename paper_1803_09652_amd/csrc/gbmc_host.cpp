@@ -36,6 +36,7 @@ gbmc_status hip_fail(hipError_t e, const char* where)
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 constexpr int32_t kDefaultJBlocks = 8;
+constexpr int32_t kDefaultWaves = 4;
 
 }  // namespace
 
@@ -43,7 +44,7 @@ struct gbmc_plan {
     int32_t n_sys = 0;
     int32_t n_atoms = 0;
     gbmc_precision prec = GBMC_FP32_FIXED;
-    gbmc_tuning tuning{kDefaultJBlocks};
+    gbmc_tuning tuning{kDefaultJBlocks, kDefaultWaves};
     std::vector<int32_t> offset;     // [B+1]
     int32_t n_items = 0;
     WorkItem* d_items = nullptr;
@@ -112,10 +113,13 @@ static gbmc_status build_items(int32_t n_systems, const int32_t* off, const gbmc
 
 static gbmc_status check_tuning(const gbmc_tuning* in, gbmc_tuning& out)
 {
-    out = gbmc_tuning{kDefaultJBlocks};
+    out = gbmc_tuning{kDefaultJBlocks, kDefaultWaves};
     if (!in) return GBMC_OK;
     if (in->j_blocks_per_item < 1 || in->j_blocks_per_item > 65535)
         return fail(GBMC_ERR_INVALID, "tuning.j_blocks_per_item must be in [1, 65535]");
+    const int32_t wv = in->waves_per_group;
+    if (wv != 1 && wv != 2 && wv != 4 && wv != 8)
+        return fail(GBMC_ERR_INVALID, "tuning.waves_per_group must be 1, 2, 4 or 8");
     out = *in;
     return GBMC_OK;
 }
@@ -431,12 +435,14 @@ gbmc_status gb_radii(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp
     GBConst c = make_const(gp);
     hipError_t e;
     if (p->prec == GBMC_FP32_FIXED)
-        e = launch_radii<float>(p->d_items, p->n_items, p->n_atoms, nullptr, (const float*)a->x,
+        e = launch_radii<float>(p->d_items, p->n_items, p->tuning.waves_per_group, p->n_atoms, nullptr,
+                                (const float*)a->x,
                                 (const float*)a->y, (const float*)a->z, (const float*)a->rho,
                                 (const float*)a->screen, c, carve<float>(p, ws), (float*)born_R, s,
                                 p->n_items > 0 ? events(p, {kKRadii}) : nullptr);
     else
-        e = launch_radii<double>(p->d_items, p->n_items, p->n_atoms, nullptr, (const double*)a->x,
+        e = launch_radii<double>(p->d_items, p->n_items, p->tuning.waves_per_group, p->n_atoms,
+                                 nullptr, (const double*)a->x,
                                  (const double*)a->y, (const double*)a->z, (const double*)a->rho,
                                  (const double*)a->screen, c, carve<double>(p, ws), (double*)born_R, s,
                                  p->n_items > 0 ? events(p, {kKRadii}) : nullptr);
@@ -455,13 +461,15 @@ gbmc_status gb_energy_forces(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_pa
         ev = (force || dEdrho) ? events(p, {kKEnergy, kKChain}) : events(p, {kKEnergy});
     hipError_t e;
     if (p->prec == GBMC_FP32_FIXED)
-        e = launch_energy_forces<float>(p->d_items, p->n_items, p->n_atoms, p->n_sys,
+        e = launch_energy_forces<float>(p->d_items, p->n_items, p->tuning.waves_per_group,
+                                        p->n_atoms, p->n_sys,
                                         (const float*)a->x, (const float*)a->y, (const float*)a->z,
                                         (const float*)a->q, (const float*)a->rho,
                                         (const float*)a->screen, c, carve<float>(p, ws), e_coul,
                                         e_gb, (float*)force, (float*)dEdq, (float*)dEdrho, s, ev);
     else
-        e = launch_energy_forces<double>(p->d_items, p->n_items, p->n_atoms, p->n_sys,
+        e = launch_energy_forces<double>(p->d_items, p->n_items, p->tuning.waves_per_group,
+                                         p->n_atoms, p->n_sys,
                                          (const double*)a->x, (const double*)a->y,
                                          (const double*)a->z, (const double*)a->q,
                                          (const double*)a->rho, (const double*)a->screen, c,

@@ -97,12 +97,14 @@ enum KernelId { kKRadii = 0, kKEnergy = 1, kKChain = 2, kKSiteRows = 3, kKSiteDE
 // Launchers (gbmc_kernels.hip).  All return hipSuccess or the launch error.
 // ev (nullable) holds 2 * kNumKernels events recorded around the timed kernels.
 template <typename T>
-hipError_t launch_radii(const WorkItem* items, int n_items, int n_atoms, const int32_t* atom_sys,
+hipError_t launch_radii(const WorkItem* items, int n_items, int waves_per_group, int n_atoms,
+                        const int32_t* atom_sys,
                         const T* x, const T* y, const T* z, const T* rho, const T* screen,
                         const GBConst& c, const Work<T>& w, T* born_R, hipStream_t s,
                         hipEvent_t* ev);
 template <typename T>
-hipError_t launch_energy_forces(const WorkItem* items, int n_items, int n_atoms, int n_sys,
+hipError_t launch_energy_forces(const WorkItem* items, int n_items, int waves_per_group, int n_atoms,
+                                int n_sys,
                                 const T* x, const T* y, const T* z, const T* q, const T* rho,
                                 const T* screen, const GBConst& c, const Work<T>& w,
                                 double* e_coul, double* e_gb, T* force, T* dEdq, T* dEdrho,

@@ -67,7 +67,8 @@ __device__ __forceinline__ void fx_add(unsigned long long* p, long long v)
 // rot1: lane l receives lane (l + 1) mod 64 (DPP wave_rol:1, all lanes active).
 __device__ __forceinline__ int rot1i(int v)
 {
-    return __builtin_amdgcn_update_dpp(0, v, 0x134, 0xF, 0xF, false);
+    // old == src: the move happens in place, with no extra register copies
+    return __builtin_amdgcn_update_dpp(v, v, 0x134, 0xF, 0xF, false);
 }
 __device__ __forceinline__ float rot1(float v)
 {
@@ -272,36 +273,50 @@ __device__ __forceinline__ void dummy_pos(int local, T& x, T& y, T& z)
     z = T(1.0e6);
 }
 
-__device__ __forceinline__ void wave_sync() { __syncthreads(); }   // workgroup == one wavefront
-
-// Walks the steps of one tile.  pair(s, act, acc_j) evaluates the pair of this
-// lane with the j at LDS slot s and adds the j-side terms to acc_j (an array of
-// NJ sums); act is false only for the lanes that must skip a duplicated pair.
-// On return acc_j of lane l holds the sums of j = 64 J + l.
-template <typename T, int NJ, class Pair>
-__device__ __forceinline__ void walk_tile(bool diagonal, T (&acc_j)[NJ], Pair&& pair)
+// The waves of a workgroup work on independent items and never wait for each
+// other.  Inside one wave, LDS instructions execute in program order, so a
+// compiler fence is all that orders a lane's reads after other lanes' writes.
+__device__ __forceinline__ void wave_sync()
 {
-    const int lane = threadIdx.x;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Walks the steps of one tile.  load(s) fetches the j data at LDS slot s;
+// pair(d, act, acc_j) evaluates the pair of this lane with that j and adds the
+// j-side terms to acc_j (NJ sums); act is false only for the lanes that must
+// skip a duplicated pair.  The j data of step k + 1 is fetched before step k
+// is evaluated.  On return acc_j of lane l holds the sums of j = 64 J + l.
+template <typename T, int NJ, class Load, class Pair>
+__device__ __forceinline__ void walk_tile(int lane, bool diagonal, T (&acc_j)[NJ], Load&& load,
+                                          Pair&& pair)
+{
 #pragma unroll
     for (int a = 0; a < NJ; ++a) acc_j[a] = T(0);
     if (!diagonal) {
+        auto d = load(lane);
 #pragma unroll 1
         for (int k = 0; k < kTile; ++k) {
-            pair(lane + k, true, acc_j);
+            auto next = load(lane + k + 1);     // slot <= 127: inside the doubled block
+            pair(d, true, acc_j);
 #pragma unroll
             for (int a = 0; a < NJ; ++a) acc_j[a] = rot1(acc_j[a]);
+            d = next;
         }
     } else {
         // pairs (l, l + k) for k = 1..31, and k = 32 for lanes 0..31 only
+        auto d = load(lane + 1);
 #pragma unroll 1
         for (int k = 1; k < kTile / 2; ++k) {
-            pair(lane + k, true, acc_j);
+            auto next = load(lane + k + 1);
+            pair(d, true, acc_j);
 #pragma unroll
             for (int a = 0; a < NJ; ++a) acc_j[a] = rot1(acc_j[a]);
+            d = next;
         }
-        pair(lane + kTile / 2, lane < kTile / 2, acc_j);
-        // lane l now holds j = l + 32; one more rotation would give l + 33.
-        // Bring j = l home: it sits in lane (l - 32) mod 64.
+        pair(d, lane < kTile / 2, acc_j);
+        // lane l now holds j = l + 32; j = l sits in lane (l - 32) mod 64
 #pragma unroll
         for (int a = 0; a < NJ; ++a) acc_j[a] = from_lane(acc_j[a], (lane + kTile / 2) & (kTile - 1));
     }
@@ -336,15 +351,19 @@ __global__ void k_stage(int n_atoms, const int32_t* __restrict__ perm, const T* 
 // ================================================================ pass 1
 // I_i = sum_{j != i} H(r_ij; rt_i, S_j) over every unordered pair once.
 
-template <typename T>
-__global__ __launch_bounds__(kTile) void k_radii_pairs(
-    const WorkItem* __restrict__ items, const Q4<T>* __restrict__ P, const Q4<T>* __restrict__ Gx,
-    unsigned long long* __restrict__ I_fx, int* __restrict__ ovf)
+template <typename T, int W>
+__global__ __launch_bounds__(kTile * W) void k_radii_pairs(
+    const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
+    const Q4<T>* __restrict__ Gx, unsigned long long* __restrict__ I_fx, int* __restrict__ ovf)
 {
-    __shared__ Q4<T> sj[2 * kTile];     // x, y, z, rt
-    __shared__ T sS[2 * kTile];
-    const int lane = threadIdx.x;
-    const WorkItem w = items[blockIdx.x];
+    __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, rt
+    __shared__ T sS_w[W][2 * kTile];
+    const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
+    const int item = blockIdx.x * W + wave;
+    if (item >= n_items) return;
+    Q4<T>* sj = sj_w[wave];
+    T* sS = sS_w[wave];
+    const WorkItem w = items[item];
     const int i = w.I * kTile + lane;
     const bool vi = i < w.n;
     T xi, yi, zi, rti, Si;
@@ -359,13 +378,10 @@ __global__ __launch_bounds__(kTile) void k_radii_pairs(
         rti = T(1);
         Si = T(0);
     }
-    long long ifix = 0;
-    for (int J = w.J0; J < w.J1; ++J) {
+    // j block data, fetched one block ahead
+    auto fetch = [&](int J, Q4<T>& pj, T& Sj) {
         const int j = J * kTile + lane;
-        const bool vj = j < w.n;
-        Q4<T> pj;
-        T Sj;
-        if (vj) {
+        if (j < w.n) {
             const Q4<T> p = P[w.base + j];
             const Q4<T> gx = Gx[w.base + j];
             pj.x = p.x; pj.y = p.y; pj.z = p.z;
@@ -376,21 +392,32 @@ __global__ __launch_bounds__(kTile) void k_radii_pairs(
             pj.w = T(1);
             Sj = T(0);
         }
+    };
+    long long ifix = 0;
+    Q4<T> pj;
+    T Sj;
+    fetch(w.J0, pj, Sj);
+    for (int J = w.J0; J < w.J1; ++J) {
+        const int j = J * kTile + lane;
+        const bool vj = j < w.n;
         wave_sync();
         sj[lane] = pj;
         sj[lane + kTile] = pj;
         sS[lane] = Sj;
         sS[lane + kTile] = Sj;
         wave_sync();
+        if (J + 1 < w.J1) fetch(J + 1, pj, Sj);
         T ai = T(0);
         T aj[1];
-        walk_tile<T, 1>(J == w.I, aj, [&](int s, bool act, T (&acc)[1]) {
-            const Q4<T> p = sj[s];
-            T hij, hji;
-            radii_pair(xi, yi, zi, p.x, p.y, p.z, rti, Si, p.w, sS[s], hij, hji);
-            ai += act ? hij : T(0);
-            acc[0] += act ? hji : T(0);
-        });
+        struct JD { Q4<T> p; T S; };
+        walk_tile<T, 1>(
+            lane, J == w.I, aj, [&](int s) { return JD{sj[s], sS[s]}; },
+            [&](const JD& d, bool act, T (&acc)[1]) {
+                T hij, hji;
+                radii_pair(xi, yi, zi, d.p.x, d.p.y, d.p.z, rti, Si, d.p.w, d.S, hij, hji);
+                ai += act ? hij : T(0);
+                acc[0] += act ? hji : T(0);
+            });
         if (vj) fx_add(&I_fx[w.base + j], to_fixed((double)aj[0], kScaleI, ovf));
         ifix += to_fixed((double)ai, kScaleI, ovf);
     }
@@ -427,17 +454,22 @@ __global__ void k_radii_finalize(int n_atoms, const T* __restrict__ RHO, GBConst
 // ================================================================ pass 2
 // Coulomb + GB energy, explicit pair forces, G = dE/dR, phi = dE/dq.
 
-template <typename T, bool GRAD>
-__global__ __launch_bounds__(kTile) void k_energy_pairs(
-    const WorkItem* __restrict__ items, const Q4<T>* __restrict__ P, const T* __restrict__ Rt,
-    const T* __restrict__ At, T kC, T kT, Work<T> wk)
+template <typename T, bool GRAD, int W>
+__global__ __launch_bounds__(kTile * W) void k_energy_pairs(
+    const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
+    const T* __restrict__ Rt, const T* __restrict__ At, T kC, T kT, Work<T> wk)
 {
-    __shared__ Q4<T> sj[2 * kTile];     // x, y, z, q
-    __shared__ T sR[2 * kTile];
-    __shared__ T sA[2 * kTile];
+    __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, q
+    __shared__ T sR_w[W][2 * kTile];
+    __shared__ T sA_w[W][2 * kTile];
     constexpr int NJ = GRAD ? 5 : 1;
-    const int lane = threadIdx.x;
-    const WorkItem w = items[blockIdx.x];
+    const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
+    const int item = blockIdx.x * W + wave;
+    if (item >= n_items) return;
+    Q4<T>* sj = sj_w[wave];
+    T* sR = sR_w[wave];
+    T* sA = sA_w[wave];
+    const WorkItem w = items[item];
     const int i = w.I * kTile + lane;
     const bool vi = i < w.n;
     T xi, yi, zi, qi, Ri, ai;
@@ -450,14 +482,9 @@ __global__ __launch_bounds__(kTile) void k_energy_pairs(
         dummy_pos(i, xi, yi, zi);
         qi = T(0); Ri = T(1); ai = T(kAScale);
     }
-    long long fix[5] = {0, 0, 0, 0, 0};
-    long long efix[2] = {0, 0};
-    for (int J = w.J0; J < w.J1; ++J) {
+    auto fetch = [&](int J, Q4<T>& pj, T& Rj, T& Aj) {
         const int j = J * kTile + lane;
-        const bool vj = j < w.n;
-        Q4<T> pj;
-        T Rj, Aj;
-        if (vj) {
+        if (j < w.n) {
             int g = w.base + j;
             pj = P[g];
             Rj = Rt[g]; Aj = At[g];
@@ -466,20 +493,32 @@ __global__ __launch_bounds__(kTile) void k_energy_pairs(
             pj.w = T(0);
             Rj = T(1); Aj = T(kAScale);
         }
+    };
+    long long fix[5] = {0, 0, 0, 0, 0};
+    long long efix[2] = {0, 0};
+    Q4<T> pj;
+    T Rj, Aj;
+    fetch(w.J0, pj, Rj, Aj);
+    for (int J = w.J0; J < w.J1; ++J) {
+        const int j = J * kTile + lane;
+        const bool vj = j < w.n;
         wave_sync();
         sj[lane] = pj; sj[lane + kTile] = pj;
         sR[lane] = Rj; sR[lane + kTile] = Rj;
         sA[lane] = Aj; sA[lane + kTile] = Aj;
         wave_sync();
+        if (J + 1 < w.J1) fetch(J + 1, pj, Rj, Aj);
         T fxi = 0, fyi = 0, fzi = 0, Gi = 0, phii = 0, eC = 0, eG = 0;
         T aj[NJ];
-        walk_tile<T, NJ>(J == w.I, aj, [&](int s, bool act, T (&acc)[NJ]) {
-            const Q4<T> p = sj[s];
-            const T rj = sR[s];
+        struct JD { Q4<T> p; T R, A; };
+        walk_tile<T, NJ>(lane, J == w.I, aj, [&](int s) { return JD{sj[s], sR[s], sA[s]}; },
+                         [&](const JD& d, bool act, T (&acc)[NJ]) {
+            const Q4<T>& p = d.p;
+            const T rj = d.R;
             T dx = xi - p.x, dy = yi - p.y, dz = zi - p.z;
             T r2 = dx * dx + dy * dy + dz * dz;
             T invr = rsq(r2);
-            T t = r2 * (ai * sA[s]);             // r^2 log2(e) / (4 R_i R_j)
+            T t = r2 * (ai * d.A);               // r^2 log2(e) / (4 R_i R_j)
             T ex = exp2neg(t);                   // exp(-D)
             T f2 = Ri * rj * ex + r2;
             T invf = rsq(f2);
@@ -577,15 +616,19 @@ __global__ void k_energy_finalize(int n_atoms, int n_sys, Work<T> w, double* __r
 // ================================================================ pass 3
 // Born-radius chain: force through Psi and the pair part of dE/drho.
 
-template <typename T>
-__global__ __launch_bounds__(kTile) void k_chain_pairs(
-    const WorkItem* __restrict__ items, const Q4<T>* __restrict__ P, const Q4<T>* __restrict__ Gx,
-    const T* __restrict__ Brt, Work<T> wk)
+template <typename T, int W>
+__global__ __launch_bounds__(kTile * W) void k_chain_pairs(
+    const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
+    const Q4<T>* __restrict__ Gx, const T* __restrict__ Brt, Work<T> wk)
 {
-    __shared__ Q4<T> sj[2 * kTile];     // x, y, z, rt
-    __shared__ Q4<T> sb[2 * kTile];     // S, B rt, screen, -
-    const int lane = threadIdx.x;
-    const WorkItem w = items[blockIdx.x];
+    __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, rt
+    __shared__ Q4<T> sb_w[W][2 * kTile];     // S, B rt, screen, -
+    const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
+    const int item = blockIdx.x * W + wave;
+    if (item >= n_items) return;
+    Q4<T>* sj = sj_w[wave];
+    Q4<T>* sb = sb_w[wave];
+    const WorkItem w = items[item];
     const int i = w.I * kTile + lane;
     const bool vi = i < w.n;
     T xi, yi, zi, rti, Si, Bi, si;
@@ -602,12 +645,9 @@ __global__ __launch_bounds__(kTile) void k_chain_pairs(
         dummy_pos(i, xi, yi, zi);
         rti = T(1); si = T(0); Si = T(0); Bi = T(0);
     }
-    long long fix[4] = {0, 0, 0, 0};
-    for (int J = w.J0; J < w.J1; ++J) {
+    auto fetch = [&](int J, Q4<T>& pj, Q4<T>& bj) {
         const int j = J * kTile + lane;
-        const bool vj = j < w.n;
-        Q4<T> pj, bj;
-        if (vj) {
+        if (j < w.n) {
             int g = w.base + j;
             const Q4<T> p = P[g];
             const Q4<T> gx = Gx[g];
@@ -622,15 +662,25 @@ __global__ __launch_bounds__(kTile) void k_chain_pairs(
             bj.x = bj.y = bj.z = T(0);
         }
         bj.w = T(0);
+    };
+    long long fix[4] = {0, 0, 0, 0};
+    Q4<T> pj, bj;
+    fetch(w.J0, pj, bj);
+    for (int J = w.J0; J < w.J1; ++J) {
+        const int j = J * kTile + lane;
+        const bool vj = j < w.n;
         wave_sync();
         sj[lane] = pj; sj[lane + kTile] = pj;
         sb[lane] = bj; sb[lane + kTile] = bj;
         wave_sync();
+        if (J + 1 < w.J1) fetch(J + 1, pj, bj);
         T fxi = 0, fyi = 0, fzi = 0, dri = 0;
         T aj[4];
-        walk_tile<T, 4>(J == w.I, aj, [&](int s, bool act, T (&acc)[4]) {
-            const Q4<T> p = sj[s];
-            const Q4<T> b = sb[s];
+        struct JD { Q4<T> p, b; };
+        walk_tile<T, 4>(lane, J == w.I, aj, [&](int s) { return JD{sj[s], sb[s]}; },
+                        [&](const JD& d, bool act, T (&acc)[4]) {
+            const Q4<T>& p = d.p;
+            const Q4<T>& b = d.b;
             T dx = xi - p.x, dy = yi - p.y, dz = zi - p.z;
             T r2 = dx * dx + dy * dy + dz * dz;
             T invr = rsq(r2);
@@ -1000,8 +1050,17 @@ static inline void mark(hipEvent_t* ev, int id, int end, hipStream_t s)
     if (ev) (void)hipEventRecord(ev[2 * id + end], s);
 }
 
+// Pair-kernel launch with W independent wavefronts per workgroup.
+#define GBMC_DISPATCH_W(W_, CALL)             \
+    switch (W_) {                             \
+    case 1: { constexpr int W = 1; CALL; } break; \
+    case 2: { constexpr int W = 2; CALL; } break; \
+    case 4: { constexpr int W = 4; CALL; } break; \
+    default: { constexpr int W = 8; CALL; } break; \
+    }
+
 template <typename T>
-hipError_t launch_radii(const WorkItem* items, int n_items, int n_atoms, const int32_t*,
+hipError_t launch_radii(const WorkItem* items, int n_items, int wpg, int n_atoms, const int32_t*,
                         const T* x, const T* y, const T* z, const T* rho, const T* screen,
                         const GBConst& c, const Work<T>& w, T* born_R, hipStream_t s,
                         hipEvent_t* ev)
@@ -1014,8 +1073,9 @@ hipError_t launch_radii(const WorkItem* items, int n_items, int n_atoms, const i
                        x, y, z, (const T*)nullptr, rho, screen, (T)c.offset, w.P, w.Gx);
     if (n_items > 0) {
         mark(ev, kKRadii, 0, s);
-        hipLaunchKernelGGL(k_radii_pairs<T>, dim3(n_items), dim3(kTile), 0, s, items, w.P, w.Gx,
-                           w.I_fx, w.ovf);
+        GBMC_DISPATCH_W(wpg, hipLaunchKernelGGL((k_radii_pairs<T, W>), dim3(blocks_for(n_items, W)),
+                                                dim3(kTile * W), 0, s, items, n_items, w.P, w.Gx,
+                                                w.I_fx, w.ovf));
         mark(ev, kKRadii, 1, s);
     }
     hipLaunchKernelGGL(k_radii_finalize<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
@@ -1024,7 +1084,7 @@ hipError_t launch_radii(const WorkItem* items, int n_items, int n_atoms, const i
 }
 
 template <typename T>
-hipError_t launch_energy_forces(const WorkItem* items, int n_items, int n_atoms, int n_sys,
+hipError_t launch_energy_forces(const WorkItem* items, int n_items, int wpg, int n_atoms, int n_sys,
                                 const T* x, const T* y, const T* z, const T* q, const T* rho,
                                 const T* screen, const GBConst& c, const Work<T>& w,
                                 double* e_coul, double* e_gb, T* force, T* dEdq, T* dEdrho,
@@ -1043,11 +1103,15 @@ hipError_t launch_energy_forces(const WorkItem* items, int n_items, int n_atoms,
     if (n_items > 0) {
         mark(ev, kKEnergy, 0, s);
         if (grad)
-            hipLaunchKernelGGL((k_energy_pairs<T, true>), dim3(n_items), dim3(kTile), 0, s, items,
-                               w.P, w.R_t, w.a_t, (T)c.kC, (T)c.kT, w);
+            GBMC_DISPATCH_W(wpg, hipLaunchKernelGGL((k_energy_pairs<T, true, W>),
+                                                    dim3(blocks_for(n_items, W)), dim3(kTile * W), 0,
+                                                    s, items, n_items, w.P, w.R_t, w.a_t, (T)c.kC,
+                                                    (T)c.kT, w))
         else
-            hipLaunchKernelGGL((k_energy_pairs<T, false>), dim3(n_items), dim3(kTile), 0, s, items,
-                               w.P, w.R_t, w.a_t, (T)c.kC, (T)c.kT, w);
+            GBMC_DISPATCH_W(wpg, hipLaunchKernelGGL((k_energy_pairs<T, false, W>),
+                                                    dim3(blocks_for(n_items, W)), dim3(kTile * W), 0,
+                                                    s, items, n_items, w.P, w.R_t, w.a_t, (T)c.kC,
+                                                    (T)c.kT, w))
         mark(ev, kKEnergy, 1, s);
     }
     int nb = blocks_for(n_atoms > n_sys ? n_atoms : n_sys, 256);
@@ -1056,8 +1120,9 @@ hipError_t launch_energy_forces(const WorkItem* items, int n_items, int n_atoms,
                            e_coul, e_gb, dEdq, grad);
     if (chain && n_items > 0) {
         mark(ev, kKChain, 0, s);
-        hipLaunchKernelGGL(k_chain_pairs<T>, dim3(n_items), dim3(kTile), 0, s, items, w.P, w.Gx,
-                           w.Brt_t, w);
+        GBMC_DISPATCH_W(wpg, hipLaunchKernelGGL((k_chain_pairs<T, W>), dim3(blocks_for(n_items, W)),
+                                                dim3(kTile * W), 0, s, items, n_items, w.P, w.Gx,
+                                                w.Brt_t, w));
         mark(ev, kKChain, 1, s);
     }
     if (chain && n_atoms > 0)
@@ -1114,10 +1179,10 @@ hipError_t launch_remd_exchange(int M, const double* E_rung, const int32_t* Ne, 
 }
 
 #define GBMC_INSTANTIATE(T)                                                                      \
-    template hipError_t launch_radii<T>(const WorkItem*, int, int, const int32_t*, const T*,     \
+    template hipError_t launch_radii<T>(const WorkItem*, int, int, int, const int32_t*, const T*,\
                                         const T*, const T*, const T*, const T*, const GBConst&,  \
                                         const Work<T>&, T*, hipStream_t, hipEvent_t*);           \
-    template hipError_t launch_energy_forces<T>(const WorkItem*, int, int, int, const T*,        \
+    template hipError_t launch_energy_forces<T>(const WorkItem*, int, int, int, int, const T*,   \
                                                 const T*, const T*, const T*, const T*,          \
                                                 const T*, const GBConst&, const Work<T>&,        \
                                                 double*, double*, T*, T*, T*, hipStream_t,       \

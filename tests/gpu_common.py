@@ -34,10 +34,10 @@ def params_pair(name="IGB5"):
     return getattr(g, name), getattr(oracle, name)
 
 
-def build(systems, precision="fp32", j_blocks=None):
+def build(systems, precision="fp32", j_blocks=None, waves=None):
     g = gb()
     batch = synth.make_batch(systems)
-    plan = g.Plan(batch.atom_offset, precision, j_blocks_per_item=j_blocks)
+    plan = g.Plan(batch.atom_offset, precision, j_blocks_per_item=j_blocks, waves_per_group=waves)
     atoms = g.Atoms.from_batch(plan, batch)
     return g, batch, plan, atoms
 

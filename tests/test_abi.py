@@ -66,7 +66,7 @@ def schedule(L, off, jb=None):
     lib = L.load()
     off = np.ascontiguousarray(off, dtype=np.int32)
     n = C.c_int32()
-    tun = C.byref(L.gbmc_tuning(jb)) if jb else None
+    tun = C.byref(L.gbmc_tuning(jb, 4)) if jb else None
     st = lib.gbmc_schedule_build(off.size - 1, _i32p(off), tun, C.byref(n), None)
     if st != 0:
         return st, None
@@ -113,7 +113,9 @@ def test_plan_create_rejects_bad_layout_before_touching_the_gpu(L):
     assert lib.gbmc_plan_create(C.byref(h), 2, _i32p(off), 0, None) == L.GBMC_ERR_INVALID
     off = np.array([0, 10], dtype=np.int32)
     assert lib.gbmc_plan_create(C.byref(h), 1, _i32p(off), 7, None) == L.GBMC_ERR_INVALID
-    bad = C.byref(L.gbmc_tuning(0))
+    bad = C.byref(L.gbmc_tuning(0, 4))
+    assert lib.gbmc_plan_create(C.byref(h), 1, _i32p(off), 0, bad) == L.GBMC_ERR_INVALID
+    bad = C.byref(L.gbmc_tuning(8, 3))
     assert lib.gbmc_plan_create(C.byref(h), 1, _i32p(off), 0, bad) == L.GBMC_ERR_INVALID
 
 

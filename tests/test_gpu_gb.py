@@ -106,8 +106,8 @@ def test_fp32_bitwise_deterministic_and_shape_independent():
     p_gpu, _ = params_pair()
     systems = [_sys(11, 700), _sys(12, 333)]
     outs = []
-    for jb in (8, 8, 1, 3, 64):
-        g, batch, plan, atoms = build(systems, "fp32", j_blocks=jb)
+    for jb, wv in ((8, 4), (8, 4), (1, 1), (3, 2), (64, 8), (2, 8)):
+        g, batch, plan, atoms = build(systems, "fp32", j_blocks=jb, waves=wv)
         outs.append(gpu_eval(plan, atoms, p_gpu))
     for o in outs[1:]:
         for k in ("R", "Ec", "Egb", "force", "dEdq", "dEdrho"):
