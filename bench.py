@@ -268,7 +268,8 @@ def main():
             "systems": w.B, "atoms": w.batch.n_atoms, "pairs_per_step": pairs,
             "candidates_per_step": n_cand, "hip_graph": use_graph, "atom_order": args.order,
             "tuning": ({"j_blocks_per_item": tune32["best"][0], "waves_per_group": tune32["best"][1],
-                        "sweep_pair_ms": tune32["ms"]} if tune32 else "library default"),
+                        "passes": "radii, energy, chain", "tuned_pair_ms": tune32["pair_ms"]}
+                       if tune32 else "library default"),
             "precision": "FP32 pair arithmetic, int64 fixed-point sums, FP64 MC",
         },
         "mc_dE_evals_per_s": n_cand / (ms_step * 1e-3),

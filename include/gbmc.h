@@ -72,14 +72,16 @@ typedef struct {
     const void* screen;
 } gbmc_atoms;
 
-/* Work-shape knobs of the pair kernels: how many 64-atom j blocks one
- * wavefront walks for its i block (>= 1; default 8), and how many such
- * independent wavefronts share a workgroup (1, 2, 4 or 8; default 4).  Every
- * 64 x 64 tile is rounded into fixed point on its own, so results are bitwise
- * independent of both knobs. */
+/* Work-shape knobs of the three pair passes (index GBMC_PASS_*): how many
+ * 64-atom j blocks one wavefront walks for its i block (>= 1), and how many
+ * such independent wavefronts share a workgroup (1, 2, 4 or 8).  Every 64 x 64
+ * tile is rounded into fixed point on its own, so results are bitwise
+ * independent of the knobs.  Defaults: descreening 1 / 1, energy 8 / 8,
+ * chain 1 / 1. */
+enum { GBMC_PASS_RADII = 0, GBMC_PASS_ENERGY = 1, GBMC_PASS_CHAIN = 2, GBMC_N_PASSES = 3 };
 typedef struct {
-    int32_t j_blocks_per_item;
-    int32_t waves_per_group;
+    int32_t j_blocks_per_item[GBMC_N_PASSES];
+    int32_t waves_per_group[GBMC_N_PASSES];
 } gbmc_tuning;
 
 typedef struct gbmc_plan gbmc_plan;
@@ -96,7 +98,8 @@ const char* gbmc_last_error(void);
  * values. */
 gbmc_status gbmc_params_validate(const gbmc_gb_params* params);
 
-/* Host-only: the pair-tile work list a plan with this layout would use.
+/* Host-only: the pair-tile work list a plan with this layout would use for a
+ * pass walking j_blocks_per_item j blocks per item (>= 1).
  * host_atom_offset[n_systems+1] (host) must start at 0 and be non-decreasing.
  * Each item covers, for one system, the 64-atom i block I against the j
  * blocks [J0, J1) with J0 >= I (every unordered pair of atoms lies in exactly
@@ -105,7 +108,7 @@ gbmc_status gbmc_params_validate(const gbmc_gb_params* params);
  * (host) is not NULL it receives 4 int32 per item: system, I, J0, J1 (the
  * caller sizes it from a first call with items == NULL). */
 gbmc_status gbmc_schedule_build(int32_t n_systems, const int32_t* host_atom_offset,
-                                const gbmc_tuning* tuning, int32_t* n_items, int32_t* items);
+                                int32_t j_blocks_per_item, int32_t* n_items, int32_t* items);
 
 /* Create a plan for a batch of n_systems systems laid out back to back:
  * system b owns atoms [host_atom_offset[b], host_atom_offset[b+1]) (host array,

@@ -38,8 +38,12 @@ class gbmc_atoms(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in ("x", "y", "z", "q", "rho", "screen")]
 
 
+N_PASSES = 3          # descreening, energy/forces, Born chain
+PASS_NAMES = ("radii", "energy", "chain")
+
+
 class gbmc_tuning(C.Structure):
-    _fields_ = [("j_blocks_per_item", C.c_int32), ("waves_per_group", C.c_int32)]
+    _fields_ = [("j_blocks_per_item", C.c_int32 * N_PASSES), ("waves_per_group", C.c_int32 * N_PASSES)]
 
 
 _I32P = C.POINTER(C.c_int32)
@@ -52,7 +56,7 @@ SIGNATURES = {
     "gbmc_version": (_I32, []),
     "gbmc_last_error": (C.c_char_p, []),
     "gbmc_params_validate": (_I32, [C.POINTER(gbmc_gb_params)]),
-    "gbmc_schedule_build": (_I32, [_I32, _I32P, C.POINTER(gbmc_tuning), _I32P, _I32P]),
+    "gbmc_schedule_build": (_I32, [_I32, _I32P, _I32, _I32P, _I32P]),
     "gbmc_plan_create": (_I32, [C.POINTER(_VP), _I32, _I32P, _I32, C.POINTER(gbmc_tuning)]),
     "gbmc_plan_destroy": (None, [_VP]),
     "gbmc_plan_set_order": (_I32, [_VP, _I32P]),

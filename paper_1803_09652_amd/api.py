@@ -56,6 +56,32 @@ def _f64p(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
+DEFAULT_SHAPE = {"j_blocks_per_item": (1, 8, 1), "waves_per_group": (1, 8, 1)}
+
+
+def _per_pass(v, default):
+    if v is None:
+        return tuple(default)
+    if isinstance(v, (int, np.integer)):
+        return (int(v),) * L.N_PASSES
+    v = tuple(int(x) for x in v)
+    if len(v) != L.N_PASSES:
+        raise ValueError("give one value, or one per pass (radii, energy, chain)")
+    return v
+
+
+def tuning_struct(j_blocks_per_item=None, waves_per_group=None) -> L.gbmc_tuning:
+    """Work shape per pair pass; each argument is an int (all passes) or a
+    (radii, energy, chain) triple; None keeps the library default."""
+    jb = _per_pass(j_blocks_per_item, DEFAULT_SHAPE["j_blocks_per_item"])
+    wv = _per_pass(waves_per_group, DEFAULT_SHAPE["waves_per_group"])
+    t = L.gbmc_tuning()
+    for k in range(L.N_PASSES):
+        t.j_blocks_per_item[k] = jb[k]
+        t.waves_per_group[k] = wv[k]
+    return t
+
+
 class Plan:
     """A batch layout (systems back to back) and a precision.
 
@@ -63,8 +89,7 @@ class Plan:
     "fp64".  Owns the plan's device workspace."""
 
     def __init__(self, atom_offset: Sequence[int], precision: str = "fp32",
-                 j_blocks_per_item: Optional[int] = None, waves_per_group: Optional[int] = None,
-                 device=None):
+                 j_blocks_per_item=None, waves_per_group=None, device=None):
         lib = L.load()
         self.offset = np.ascontiguousarray(atom_offset, dtype=np.int32)
         if self.offset.ndim != 1 or self.offset.size < 1:
@@ -77,7 +102,7 @@ class Plan:
             else torch.device(device)
         tun = None
         if j_blocks_per_item is not None or waves_per_group is not None:
-            tun = C.byref(L.gbmc_tuning(int(j_blocks_per_item or 8), int(waves_per_group or 4)))
+            tun = C.byref(tuning_struct(j_blocks_per_item, waves_per_group))
         h = C.c_void_p()
         with torch.cuda.device(self.device):
             L.check(lib.gbmc_plan_create(C.byref(h), int(self.offset.size - 1), _i32p(self.offset),

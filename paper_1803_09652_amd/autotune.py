@@ -62,20 +62,22 @@ def _save_cache(cache: dict) -> None:
         pass
 
 
-def lookup(atom_offset: Sequence[int], precision: str = "fp32") -> Optional[Tuple[int, int]]:
+def lookup(atom_offset: Sequence[int], precision: str = "fp32"):
+    """Cached (j_blocks_per_item, waves_per_group) triples for this size bucket, or None."""
     hit = _load_cache().get(bucket_key(atom_offset, precision))
-    return (int(hit["j_blocks_per_item"]), int(hit["waves_per_group"])) if hit else None
+    return (tuple(hit["j_blocks_per_item"]), tuple(hit["waves_per_group"])) if hit else None
 
 
 def tune(batch, precision: str = "fp32", order: Optional[np.ndarray] = None,
          params: api.GBParams = api.IGB5, reps: int = 3,
          candidates: Optional[Iterable[Tuple[int, int]]] = None, use_cache: bool = True) -> dict:
     """Time every (j_blocks_per_item, waves_per_group) candidate on ``batch``
-    (any object with atom_offset, x, y, z, q, rho, screen) and return
-    {"best": (jb, wv), "ms": {shape: pair-kernel ms}}."""
+    (any object with atom_offset, x, y, z, q, rho, screen), applied to all three
+    pair passes, and pick the fastest shape of each pass.  Returns
+    {"best": ((jb radii, energy, chain), (wv radii, energy, chain)), ...}."""
     key = bucket_key(batch.atom_offset, precision)
     cands = list(candidates) if candidates is not None else [(j, w) for j in J_BLOCKS for w in WAVES]
-    table = {}
+    table, per_kernel = {}, {}
     for jb, wv in cands:
         plan = api.Plan(batch.atom_offset, precision, j_blocks_per_item=jb, waves_per_group=wv)
         if order is not None:
@@ -84,20 +86,30 @@ def tune(batch, precision: str = "fp32", order: Optional[np.ndarray] = None,
         api.radii(plan, atoms, params)                  # warm-up (code objects, caches)
         api.energy_forces(plan, atoms, params)
         plan.set_timing(True)
-        runs = []
+        runs, per = [], {k: [] for k in PAIR_KERNELS}
         for _ in range(reps):
             api.radii(plan, atoms, params)
             api.energy_forces(plan, atoms, params)
             ms = plan.kernel_ms()
             runs.append(sum(ms.get(k, 0.0) for k in PAIR_KERNELS))
+            for k in PAIR_KERNELS:
+                per[k].append(ms.get(k, 0.0))
         plan.set_timing(False)
         table[f"{jb}x{wv}"] = statistics.median(runs)
+        per_kernel[f"{jb}x{wv}"] = {k: statistics.median(v) for k, v in per.items()}
         del plan, atoms
     torch.cuda.synchronize()
-    best = min(table, key=table.get)
-    jb, wv = (int(v) for v in best.split("x"))
+    # the passes are separate launches: each takes its own fastest shape
+    jbs, wvs, total = [], [], 0.0
+    for k in PAIR_KERNELS:
+        shape = min(per_kernel, key=lambda c: per_kernel[c][k])
+        jb, wv = (int(v) for v in shape.split("x"))
+        jbs.append(jb)
+        wvs.append(wv)
+        total += per_kernel[shape][k]
+    best = (tuple(jbs), tuple(wvs))
     if use_cache:
         cache = _load_cache()
-        cache[key] = {"j_blocks_per_item": jb, "waves_per_group": wv, "pair_ms": table[best]}
+        cache[key] = {"j_blocks_per_item": list(jbs), "waves_per_group": list(wvs), "pair_ms": total}
         _save_cache(cache)
-    return {"key": key, "best": (jb, wv), "ms": table}
+    return {"key": key, "best": best, "pair_ms": total, "ms": table, "per_kernel_ms": per_kernel}

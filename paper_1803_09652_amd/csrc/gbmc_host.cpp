@@ -35,8 +35,7 @@ gbmc_status hip_fail(hipError_t e, const char* where)
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
-constexpr int32_t kDefaultJBlocks = 8;
-constexpr int32_t kDefaultWaves = 4;
+const gbmc_tuning kDefaultTuning = {{1, 8, 1}, {1, 8, 1}};
 
 }  // namespace
 
@@ -44,10 +43,11 @@ struct gbmc_plan {
     int32_t n_sys = 0;
     int32_t n_atoms = 0;
     gbmc_precision prec = GBMC_FP32_FIXED;
-    gbmc_tuning tuning{kDefaultJBlocks, kDefaultWaves};
+    gbmc_tuning tuning = kDefaultTuning;
     std::vector<int32_t> offset;     // [B+1]
-    int32_t n_items = 0;
-    WorkItem* d_items = nullptr;
+    int32_t n_items[GBMC_N_PASSES] = {0, 0, 0};
+    WorkItem* d_items[GBMC_N_PASSES] = {nullptr, nullptr, nullptr};
+    void* d_mem = nullptr;           // one allocation: the work lists and the order
     int32_t* d_perm = nullptr;       // [N] internal -> caller atom index
     int device = 0;
     // timing hook: events bracketing each timed kernel, recorded while enabled
@@ -56,7 +56,7 @@ struct gbmc_plan {
     bool recorded[kNumKernels] = {};
     // workspace layout (byte offsets)
     size_t off_I, off_F, off_G, off_phi, off_drho, off_E, off_I64, off_R64, off_T64, off_dR64,
-        off_G64, off_B64, off_Rt, off_at, off_Brt, off_ovf, off_P, off_Gx, off_A64, ws_bytes;
+        off_G64, off_B64, off_Rt, off_at, off_Brt, off_ovf, off_P, off_Gx, off_A64, off_rows, ws_bytes;
 };
 
 struct gbmc_sites {
@@ -83,11 +83,10 @@ static gbmc_status check_offsets(int32_t n_systems, const int32_t* off)
     return GBMC_OK;
 }
 
-static gbmc_status build_items(int32_t n_systems, const int32_t* off, const gbmc_tuning& t,
+static gbmc_status build_items(int32_t n_systems, const int32_t* off, int32_t jb,
                                std::vector<WorkItem>& items)
 {
     items.clear();
-    const int32_t jb = t.j_blocks_per_item;
     for (int32_t b = 0; b < n_systems; ++b) {
         const int32_t n = off[b + 1] - off[b];
         const int32_t nb = (n + kTile - 1) / kTile;
@@ -113,13 +112,15 @@ static gbmc_status build_items(int32_t n_systems, const int32_t* off, const gbmc
 
 static gbmc_status check_tuning(const gbmc_tuning* in, gbmc_tuning& out)
 {
-    out = gbmc_tuning{kDefaultJBlocks, kDefaultWaves};
+    out = kDefaultTuning;
     if (!in) return GBMC_OK;
-    if (in->j_blocks_per_item < 1 || in->j_blocks_per_item > 65535)
-        return fail(GBMC_ERR_INVALID, "tuning.j_blocks_per_item must be in [1, 65535]");
-    const int32_t wv = in->waves_per_group;
-    if (wv != 1 && wv != 2 && wv != 4 && wv != 8)
-        return fail(GBMC_ERR_INVALID, "tuning.waves_per_group must be 1, 2, 4 or 8");
+    for (int k = 0; k < GBMC_N_PASSES; ++k) {
+        if (in->j_blocks_per_item[k] < 1 || in->j_blocks_per_item[k] > 65535)
+            return fail(GBMC_ERR_INVALID, "tuning.j_blocks_per_item must be in [1, 65535]");
+        const int32_t wv = in->waves_per_group[k];
+        if (wv != 1 && wv != 2 && wv != 4 && wv != 8)
+            return fail(GBMC_ERR_INVALID, "tuning.waves_per_group must be 1, 2, 4 or 8");
+    }
     out = *in;
     return GBMC_OK;
 }
@@ -141,6 +142,7 @@ static Work<T> carve(const gbmc_plan* p, void* ws)
     w.I64 = reinterpret_cast<double*>(b + p->off_I64);
     w.R64 = reinterpret_cast<double*>(b + p->off_R64);
     w.A64 = reinterpret_cast<double*>(b + p->off_A64);
+    w.rows = reinterpret_cast<Row64*>(b + p->off_rows);
     w.T64 = reinterpret_cast<double*>(b + p->off_T64);
     w.dRdPsi64 = reinterpret_cast<double*>(b + p->off_dR64);
     w.G64 = reinterpret_cast<double*>(b + p->off_G64);
@@ -178,6 +180,7 @@ static void layout(gbmc_plan* p)
     p->off_Brt = seg(ts * N);
     p->off_P = seg(4 * ts * N);
     p->off_Gx = seg(4 * ts * N);
+    p->off_rows = seg(sizeof(Row64) * N);
     p->ws_bytes = o;
 }
 
@@ -231,17 +234,16 @@ gbmc_status gbmc_params_validate(const gbmc_gb_params* p)
 }
 
 gbmc_status gbmc_schedule_build(int32_t n_systems, const int32_t* host_atom_offset,
-                                const gbmc_tuning* tuning, int32_t* n_items, int32_t* items)
+                                int32_t j_blocks_per_item, int32_t* n_items, int32_t* items)
 {
     try {
         if (!n_items) return fail(GBMC_ERR_INVALID, "n_items is NULL");
         gbmc_status st = check_offsets(n_systems, host_atom_offset);
         if (st != GBMC_OK) return st;
-        gbmc_tuning t;
-        st = check_tuning(tuning, t);
-        if (st != GBMC_OK) return st;
+        if (j_blocks_per_item < 1 || j_blocks_per_item > 65535)
+            return fail(GBMC_ERR_INVALID, "j_blocks_per_item must be in [1, 65535]");
         std::vector<WorkItem> v;
-        build_items(n_systems, host_atom_offset, t, v);
+        build_items(n_systems, host_atom_offset, j_blocks_per_item, v);
         if (v.size() > 0x7fffffff) return fail(GBMC_ERR_UNSUPPORTED, "too many work items");
         *n_items = (int32_t)v.size();
         if (items)
@@ -270,8 +272,9 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
         gbmc_tuning t;
         st = check_tuning(tuning, t);
         if (st != GBMC_OK) return st;
-        std::vector<WorkItem> items;
-        build_items(n_systems, host_atom_offset, t, items);
+        std::vector<WorkItem> items[GBMC_N_PASSES];
+        for (int k = 0; k < GBMC_N_PASSES; ++k)
+            build_items(n_systems, host_atom_offset, t.j_blocks_per_item[k], items[k]);
         auto* p = new gbmc_plan();
         p->n_sys = n_systems;
         p->n_atoms = n_systems > 0 ? host_atom_offset[n_systems] : 0;
@@ -279,22 +282,33 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
         p->tuning = t;
         p->offset.assign(host_atom_offset, host_atom_offset + n_systems + 1);
         if (n_systems == 0) p->offset.assign(1, 0);
-        p->n_items = (int32_t)items.size();
         layout(p);
         hipError_t e = hipGetDevice(&p->device);
         if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
-        // one device allocation: work list, then the processing order (identity)
-        const size_t items_bytes = align256(items.size() * sizeof(WorkItem));
-        const size_t perm_bytes = 4 * (size_t)p->n_atoms;
-        if (items_bytes + perm_bytes > 0) {
+        // one device allocation: the three work lists, then the processing order (identity)
+        size_t at[GBMC_N_PASSES + 1];
+        size_t o = 0;
+        for (int k = 0; k < GBMC_N_PASSES; ++k) {
+            if (items[k].size() > 0x7fffffff) { delete p; return fail(GBMC_ERR_UNSUPPORTED, "too many work items"); }
+            p->n_items[k] = (int32_t)items[k].size();
+            at[k] = o;
+            o = align256(o + items[k].size() * sizeof(WorkItem));
+        }
+        at[GBMC_N_PASSES] = o;
+        const size_t total = o + 4 * (size_t)p->n_atoms;
+        if (total > 0) {
             char* d = nullptr;
-            e = hipMalloc(&d, items_bytes + perm_bytes);
+            e = hipMalloc(&d, total);
             if (e != hipSuccess) { delete p; return hip_fail(e, "hipMalloc(plan tables)"); }
-            p->d_items = reinterpret_cast<WorkItem*>(d);
-            p->d_perm = reinterpret_cast<int32_t*>(d + items_bytes);
-            std::vector<char> h(items_bytes + perm_bytes, 0);
-            if (!items.empty()) std::memcpy(h.data(), items.data(), items.size() * sizeof(WorkItem));
-            int32_t* id = reinterpret_cast<int32_t*>(h.data() + items_bytes);
+            p->d_mem = d;
+            std::vector<char> h(total, 0);
+            for (int k = 0; k < GBMC_N_PASSES; ++k) {
+                p->d_items[k] = reinterpret_cast<WorkItem*>(d + at[k]);
+                if (!items[k].empty())
+                    std::memcpy(h.data() + at[k], items[k].data(), items[k].size() * sizeof(WorkItem));
+            }
+            p->d_perm = reinterpret_cast<int32_t*>(d + at[GBMC_N_PASSES]);
+            int32_t* id = reinterpret_cast<int32_t*>(h.data() + at[GBMC_N_PASSES]);
             for (int32_t k = 0; k < p->n_atoms; ++k) id[k] = k;
             e = hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice);
             if (e != hipSuccess) { (void)hipFree(d); delete p; return hip_fail(e, "hipMemcpy(plan tables)"); }
@@ -309,7 +323,7 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
 void gbmc_plan_destroy(gbmc_plan* p)
 {
     if (!p) return;
-    if (p->d_items) (void)hipFree(p->d_items);
+    if (p->d_mem) (void)hipFree(p->d_mem);
     for (hipEvent_t e : p->ev)
         if (e) (void)hipEventDestroy(e);
     delete p;
@@ -435,17 +449,19 @@ gbmc_status gb_radii(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp
     GBConst c = make_const(gp);
     hipError_t e;
     if (p->prec == GBMC_FP32_FIXED)
-        e = launch_radii<float>(p->d_items, p->n_items, p->tuning.waves_per_group, p->n_atoms, nullptr,
+        e = launch_radii<float>(p->d_items[GBMC_PASS_RADII], p->n_items[GBMC_PASS_RADII],
+                                p->tuning.waves_per_group[GBMC_PASS_RADII], p->n_atoms, nullptr,
                                 (const float*)a->x,
                                 (const float*)a->y, (const float*)a->z, (const float*)a->rho,
                                 (const float*)a->screen, c, carve<float>(p, ws), (float*)born_R, s,
-                                p->n_items > 0 ? events(p, {kKRadii}) : nullptr);
+                                p->n_items[GBMC_PASS_RADII] > 0 ? events(p, {kKRadii}) : nullptr);
     else
-        e = launch_radii<double>(p->d_items, p->n_items, p->tuning.waves_per_group, p->n_atoms,
+        e = launch_radii<double>(p->d_items[GBMC_PASS_RADII], p->n_items[GBMC_PASS_RADII],
+                                 p->tuning.waves_per_group[GBMC_PASS_RADII], p->n_atoms,
                                  nullptr, (const double*)a->x,
                                  (const double*)a->y, (const double*)a->z, (const double*)a->rho,
                                  (const double*)a->screen, c, carve<double>(p, ws), (double*)born_R, s,
-                                 p->n_items > 0 ? events(p, {kKRadii}) : nullptr);
+                                 p->n_items[GBMC_PASS_RADII] > 0 ? events(p, {kKRadii}) : nullptr);
     return e == hipSuccess ? GBMC_OK : hip_fail(e, "gb_radii launch");
 }
 
@@ -457,19 +473,21 @@ gbmc_status gb_energy_forces(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_pa
     if (st != GBMC_OK) return st;
     GBConst c = make_const(gp);
     hipEvent_t* ev = nullptr;
-    if (p->n_items > 0)
+    if (p->n_items[GBMC_PASS_ENERGY] > 0)
         ev = (force || dEdrho) ? events(p, {kKEnergy, kKChain}) : events(p, {kKEnergy});
+    const PassShape pe{p->d_items[GBMC_PASS_ENERGY], p->n_items[GBMC_PASS_ENERGY],
+                       p->tuning.waves_per_group[GBMC_PASS_ENERGY]};
+    const PassShape pc{p->d_items[GBMC_PASS_CHAIN], p->n_items[GBMC_PASS_CHAIN],
+                       p->tuning.waves_per_group[GBMC_PASS_CHAIN]};
     hipError_t e;
     if (p->prec == GBMC_FP32_FIXED)
-        e = launch_energy_forces<float>(p->d_items, p->n_items, p->tuning.waves_per_group,
-                                        p->n_atoms, p->n_sys,
+        e = launch_energy_forces<float>(pe, pc, p->n_atoms, p->n_sys,
                                         (const float*)a->x, (const float*)a->y, (const float*)a->z,
                                         (const float*)a->q, (const float*)a->rho,
                                         (const float*)a->screen, c, carve<float>(p, ws), e_coul,
                                         e_gb, (float*)force, (float*)dEdq, (float*)dEdrho, s, ev);
     else
-        e = launch_energy_forces<double>(p->d_items, p->n_items, p->tuning.waves_per_group,
-                                         p->n_atoms, p->n_sys,
+        e = launch_energy_forces<double>(pe, pc, p->n_atoms, p->n_sys,
                                          (const double*)a->x, (const double*)a->y,
                                          (const double*)a->z, (const double*)a->q,
                                          (const double*)a->rho, (const double*)a->screen, c,
@@ -706,11 +724,11 @@ gbmc_status mc_state_dE(gbmc_plan* p, const gbmc_sites* s, const gbmc_atoms* a,
     hipEvent_t* ev = s->dev.n_rowitems > 0 ? events(p, {kKSiteRows, kKSiteDE}) : events(p, {kKSiteDE});
     hipError_t e;
     if (p->prec == GBMC_FP32_FIXED)
-        e = launch_state_dE<float>(s->dev, (const float*)a->x, (const float*)a->y, (const float*)a->z,
+        e = launch_state_dE<float>(s->dev, p->n_atoms, (const float*)a->x, (const float*)a->y, (const float*)a->z,
                                    (const float*)a->q, c, carve<float>(p, ws), (double*)sws,
                                    current_state, pH, E_volt, T, dE, dG, stream, ev);
     else
-        e = launch_state_dE<double>(s->dev, (const double*)a->x, (const double*)a->y,
+        e = launch_state_dE<double>(s->dev, p->n_atoms, (const double*)a->x, (const double*)a->y,
                                     (const double*)a->z, (const double*)a->q, c, carve<double>(p, ws),
                                     (double*)sws, current_state, pH, E_volt, T, dE, dG, stream, ev);
     return e == hipSuccess ? GBMC_OK : hip_fail(e, "mc_state_dE launch");

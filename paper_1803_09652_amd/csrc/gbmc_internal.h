@@ -9,7 +9,7 @@ namespace gbmc {
 constexpr int kTile = 64;                 // atoms per block; one wavefront per tile
 constexpr int kMaxSiteAtoms = 256;
 constexpr int kMaxStates = 8;
-constexpr int kPhiChunk = 128;            // j atoms per FP64 potential-row work item
+constexpr int kPhiChunk = 64;             // j atoms per FP64 potential-row work item
 
 // Fixed-point scales (powers of two, so scaling is exact).
 constexpr double kScaleI = 4503599627370496.0;   // 2^52: descreening sums, 1/A
@@ -34,6 +34,12 @@ struct RowItem {
     int32_t base, n, sa0, sa1, j0, j1, out, pad;
 };
 
+// One atom as the FP64 Monte Carlo kernels read it (caller order): a 64-byte
+// record, so a wave-uniform read is one scalar 64-byte load.
+struct alignas(64) Row64 {
+    double x, y, z, q, R, A, pad0, pad1;   // A = 1 / (2 R)
+};
+
 // Device pointers carved from the caller's workspace.  Per-atom arrays marked
 // "internal" are in the plan's processing order (perm[k] is the caller index
 // of internal atom k); the FP64 per-atom state is in caller order.
@@ -51,6 +57,7 @@ struct Work {
     double* I64;                  // [N] descreening sum
     double* R64;                  // [N] Born radius
     double* A64;                  // [N] 1 / (2 R)
+    Row64* rows;                  // [N] FP64 records for the Monte Carlo kernels
     double* T64;                  // [N] tanh(theta)
     double* dRdPsi64;             // [N]
     double* G64;                  // [N] dE/dR
@@ -102,16 +109,22 @@ hipError_t launch_radii(const WorkItem* items, int n_items, int waves_per_group,
                         const T* x, const T* y, const T* z, const T* rho, const T* screen,
                         const GBConst& c, const Work<T>& w, T* born_R, hipStream_t s,
                         hipEvent_t* ev);
+struct PassShape {
+    const WorkItem* items;
+    int n_items;
+    int waves_per_group;
+};
+
 template <typename T>
-hipError_t launch_energy_forces(const WorkItem* items, int n_items, int waves_per_group, int n_atoms,
+hipError_t launch_energy_forces(const PassShape& energy, const PassShape& chain, int n_atoms,
                                 int n_sys,
                                 const T* x, const T* y, const T* z, const T* q, const T* rho,
                                 const T* screen, const GBConst& c, const Work<T>& w,
                                 double* e_coul, double* e_gb, T* force, T* dEdq, T* dEdrho,
                                 hipStream_t s, hipEvent_t* ev);
 template <typename T>
-hipError_t launch_state_dE(const SiteDev& sd, const T* x, const T* y, const T* z, const T* q,
-                           const GBConst& c, const Work<T>& w, double* phi_part,
+hipError_t launch_state_dE(const SiteDev& sd, int n_atoms, const T* x, const T* y, const T* z,
+                           const T* q, const GBConst& c, const Work<T>& w, double* phi_part,
                            const int32_t* current_state, const double* pH, const double* E_volt,
                            double T_kelvin, double* dE, double* dG, hipStream_t s,
                            hipEvent_t* ev);

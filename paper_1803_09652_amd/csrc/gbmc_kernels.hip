@@ -777,47 +777,65 @@ __device__ __forceinline__ double pairK(double dx, double dy, double dz, double 
     return kC * invr - kT * invf;
 }
 
+// FP64 records (x, y, z, q, R, 1/(2R)) of every atom, for the Monte Carlo kernels.
 template <typename T>
+__global__ void k_stage_rows(int n_atoms, const T* __restrict__ X, const T* __restrict__ Y,
+                             const T* __restrict__ Z, const T* __restrict__ Q,
+                             const double* __restrict__ R64, const double* __restrict__ A64,
+                             Row64* __restrict__ rows)
+{
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_atoms) return;
+    Row64 r;
+    r.x = X[g]; r.y = Y[g]; r.z = Z[g]; r.q = Q[g];
+    r.R = R64[g]; r.A = A64[g];
+    r.pad0 = r.pad1 = 0.0;
+    rows[g] = r;
+}
+
+// One lane per site atom; the j atoms of the chunk are wave-uniform records.
 __global__ __launch_bounds__(kTile) void k_site_phi_rows(
     const RowItem* __restrict__ items, const int32_t* __restrict__ site_atoms,
-    const T* __restrict__ X, const T* __restrict__ Y, const T* __restrict__ Z,
-    const T* __restrict__ Q, const double* __restrict__ R64, const double* __restrict__ A64,
-    double kC, double kT, double* __restrict__ phi_part)
+    const Row64* __restrict__ rows, double kC, double kT, double* __restrict__ phi_part)
 {
     const RowItem w = items[blockIdx.x];
     const int lane = threadIdx.x;
     const int sa = w.sa0 + lane;
     const bool v = sa < w.sa1;
     const int gi = v ? site_atoms[sa] : w.base;
-    const double xi = X[gi], yi = Y[gi], zi = Z[gi], Ri = R64[gi], Ai = A64[gi];
+    const Row64 ri = rows[gi];
     double acc = 0.0;
 #pragma unroll 4
     for (int j = w.j0; j < w.j1; ++j) {
         const int gj = w.base + j;
-        double K = pairK(xi - (double)X[gj], yi - (double)Y[gj], zi - (double)Z[gj], Ri, Ai,
-                         R64[gj], A64[gj], kC, kT);
-        acc += (gj == gi) ? 0.0 : (double)Q[gj] * K;
+        const Row64 rj = rows[gj];
+        double K = pairK(ri.x - rj.x, ri.y - rj.y, ri.z - rj.z, ri.R, ri.A, rj.R, rj.A, kC, kT);
+        acc += (gj == gi) ? 0.0 : rj.q * K;
     }
     if (v) phi_part[w.out + lane] = acc;
 }
 
-// deterministic block reduction of NV doubles per thread (blockDim = 256)
+// Deterministic sum of NV doubles over a 256-thread block: a fixed butterfly
+// inside each wavefront, then the four wave sums in wave order.  Every thread
+// receives the totals.
 template <int NV>
-__device__ void block_sum(double (*buf)[256], double* v)
+__device__ void block_sum(double (*buf)[4], double* v)
 {
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = t % kTile, wave = t / kTile;
 #pragma unroll
-    for (int a = 0; a < NV; ++a) buf[a][t] = v[a];
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (t < off) {
+    for (int a = 0; a < NV; ++a) {
+        double x = v[a];
 #pragma unroll
-            for (int a = 0; a < NV; ++a) buf[a][t] += buf[a][t + off];
-        }
-        __syncthreads();
+        for (int off = kTile / 2; off > 0; off >>= 1) x += __shfl_xor(x, off);
+        v[a] = x;
     }
+    if (lane == 0) {
 #pragma unroll
-    for (int a = 0; a < NV; ++a) v[a] = buf[a][0];
+        for (int a = 0; a < NV; ++a) buf[a][wave] = v[a];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < NV; ++a) v[a] = ((buf[a][0] + buf[a][1]) + buf[a][2]) + buf[a][3];
     __syncthreads();
 }
 
@@ -836,7 +854,7 @@ __global__ __launch_bounds__(kMC) void k_site_dE(
     __shared__ double sA[kMaxSiteAtoms];
     __shared__ double sphi[kMaxSiteAtoms];
     __shared__ double sdq[kMaxStates - 1][kMaxSiteAtoms];
-    __shared__ double red[2 * (kMaxStates - 1)][256];
+    __shared__ double red[2 * (kMaxStates - 1)][4];
     const int m = blockIdx.x;
     const int t = threadIdx.x;
     const int a0 = sd.site_atom_offset[m];
@@ -920,7 +938,7 @@ __global__ __launch_bounds__(kMC) void k_mc_step(
     int32_t* __restrict__ n_electrons, int64_t* __restrict__ counters,
     int32_t* __restrict__ accepted)
 {
-    __shared__ double red[1][256];
+    __shared__ double red[1][4];
     const int b = blockIdx.x;
     const int t = threadIdx.x;
     const double* ub = u + 6 * (size_t)b;
@@ -1084,7 +1102,7 @@ hipError_t launch_radii(const WorkItem* items, int n_items, int wpg, int n_atoms
 }
 
 template <typename T>
-hipError_t launch_energy_forces(const WorkItem* items, int n_items, int wpg, int n_atoms, int n_sys,
+hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_atoms, int n_sys,
                                 const T* x, const T* y, const T* z, const T* q, const T* rho,
                                 const T* screen, const GBConst& c, const Work<T>& w,
                                 double* e_coul, double* e_gb, T* force, T* dEdq, T* dEdrho,
@@ -1100,29 +1118,32 @@ hipError_t launch_energy_forces(const WorkItem* items, int n_items, int wpg, int
     if (n_atoms > 0)
         hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
                            w.perm, x, y, z, q, rho, screen, (T)c.offset, w.P, w.Gx);
-    if (n_items > 0) {
+    if (pe.n_items > 0) {
         mark(ev, kKEnergy, 0, s);
         if (grad)
-            GBMC_DISPATCH_W(wpg, hipLaunchKernelGGL((k_energy_pairs<T, true, W>),
-                                                    dim3(blocks_for(n_items, W)), dim3(kTile * W), 0,
-                                                    s, items, n_items, w.P, w.R_t, w.a_t, (T)c.kC,
-                                                    (T)c.kT, w))
+            GBMC_DISPATCH_W(pe.waves_per_group,
+                            hipLaunchKernelGGL((k_energy_pairs<T, true, W>),
+                                               dim3(blocks_for(pe.n_items, W)), dim3(kTile * W), 0, s,
+                                               pe.items, pe.n_items, w.P, w.R_t, w.a_t, (T)c.kC,
+                                               (T)c.kT, w))
         else
-            GBMC_DISPATCH_W(wpg, hipLaunchKernelGGL((k_energy_pairs<T, false, W>),
-                                                    dim3(blocks_for(n_items, W)), dim3(kTile * W), 0,
-                                                    s, items, n_items, w.P, w.R_t, w.a_t, (T)c.kC,
-                                                    (T)c.kT, w))
+            GBMC_DISPATCH_W(pe.waves_per_group,
+                            hipLaunchKernelGGL((k_energy_pairs<T, false, W>),
+                                               dim3(blocks_for(pe.n_items, W)), dim3(kTile * W), 0, s,
+                                               pe.items, pe.n_items, w.P, w.R_t, w.a_t, (T)c.kC,
+                                               (T)c.kT, w))
         mark(ev, kKEnergy, 1, s);
     }
     int nb = blocks_for(n_atoms > n_sys ? n_atoms : n_sys, 256);
     if (nb > 0)
         hipLaunchKernelGGL(k_energy_finalize<T>, dim3(nb), dim3(256), 0, s, n_atoms, n_sys, w,
                            e_coul, e_gb, dEdq, grad);
-    if (chain && n_items > 0) {
+    if (chain && pc.n_items > 0) {
         mark(ev, kKChain, 0, s);
-        GBMC_DISPATCH_W(wpg, hipLaunchKernelGGL((k_chain_pairs<T, W>), dim3(blocks_for(n_items, W)),
-                                                dim3(kTile * W), 0, s, items, n_items, w.P, w.Gx,
-                                                w.Brt_t, w));
+        GBMC_DISPATCH_W(pc.waves_per_group,
+                        hipLaunchKernelGGL((k_chain_pairs<T, W>), dim3(blocks_for(pc.n_items, W)),
+                                           dim3(kTile * W), 0, s, pc.items, pc.n_items, w.P, w.Gx,
+                                           w.Brt_t, w));
         mark(ev, kKChain, 1, s);
     }
     if (chain && n_atoms > 0)
@@ -1132,16 +1153,18 @@ hipError_t launch_energy_forces(const WorkItem* items, int n_items, int wpg, int
 }
 
 template <typename T>
-hipError_t launch_state_dE(const SiteDev& sd, const T* x, const T* y, const T* z, const T* q,
-                           const GBConst& c, const Work<T>& w, double* phi_part,
+hipError_t launch_state_dE(const SiteDev& sd, int n_atoms, const T* x, const T* y, const T* z,
+                           const T* q, const GBConst& c, const Work<T>& w, double* phi_part,
                            const int32_t* current_state, const double* pH, const double* E_volt,
                            double T_kelvin, double* dE, double* dG, hipStream_t s, hipEvent_t* ev)
 {
     if (sd.n_sites == 0) return hipSuccess;
     if (sd.n_rowitems > 0) {
+        hipLaunchKernelGGL(k_stage_rows<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
+                           x, y, z, q, w.R64, w.A64, w.rows);
         mark(ev, kKSiteRows, 0, s);
-        hipLaunchKernelGGL(k_site_phi_rows<T>, dim3(sd.n_rowitems), dim3(kTile), 0, s, sd.rowitems,
-                           sd.site_atoms, x, y, z, q, w.R64, w.A64, c.kC, c.kT, phi_part);
+        hipLaunchKernelGGL(k_site_phi_rows, dim3(sd.n_rowitems), dim3(kTile), 0, s, sd.rowitems,
+                           sd.site_atoms, w.rows, c.kC, c.kT, phi_part);
         mark(ev, kKSiteRows, 1, s);
     }
     mark(ev, kKSiteDE, 0, s);
@@ -1182,12 +1205,13 @@ hipError_t launch_remd_exchange(int M, const double* E_rung, const int32_t* Ne, 
     template hipError_t launch_radii<T>(const WorkItem*, int, int, int, const int32_t*, const T*,\
                                         const T*, const T*, const T*, const T*, const GBConst&,  \
                                         const Work<T>&, T*, hipStream_t, hipEvent_t*);           \
-    template hipError_t launch_energy_forces<T>(const WorkItem*, int, int, int, int, const T*,   \
+    template hipError_t launch_energy_forces<T>(const PassShape&, const PassShape&, int, int,      \
+                                                const T*,                                          \
                                                 const T*, const T*, const T*, const T*,          \
                                                 const T*, const GBConst&, const Work<T>&,        \
                                                 double*, double*, T*, T*, T*, hipStream_t,       \
                                                 hipEvent_t*);                                    \
-    template hipError_t launch_state_dE<T>(const SiteDev&, const T*, const T*, const T*,         \
+    template hipError_t launch_state_dE<T>(const SiteDev&, int, const T*, const T*, const T*,    \
                                            const T*, const GBConst&, const Work<T>&, double*,    \
                                            const int32_t*, const double*, const double*, double, \
                                            double*, double*, hipStream_t, hipEvent_t*);          \

@@ -66,12 +66,12 @@ def schedule(L, off, jb=None):
     lib = L.load()
     off = np.ascontiguousarray(off, dtype=np.int32)
     n = C.c_int32()
-    tun = C.byref(L.gbmc_tuning(jb, 4)) if jb else None
-    st = lib.gbmc_schedule_build(off.size - 1, _i32p(off), tun, C.byref(n), None)
+    jb = jb or 8
+    st = lib.gbmc_schedule_build(off.size - 1, _i32p(off), jb, C.byref(n), None)
     if st != 0:
         return st, None
     items = np.zeros(4 * n.value, dtype=np.int32)
-    assert lib.gbmc_schedule_build(off.size - 1, _i32p(off), tun, C.byref(n), _i32p(items)) == 0
+    assert lib.gbmc_schedule_build(off.size - 1, _i32p(off), jb, C.byref(n), _i32p(items)) == 0
     return st, items.reshape(-1, 4)
 
 
@@ -100,6 +100,10 @@ def test_schedule_covers_every_tile_once(L, jb):
 
 
 def test_schedule_rejects_bad_offsets(L):
+    lib = L.load()
+    n = C.c_int32()
+    off = np.array([0, 10], dtype=np.int32)
+    assert lib.gbmc_schedule_build(1, _i32p(off), 0, C.byref(n), None) == L.GBMC_ERR_INVALID
     assert schedule(L, [1, 5])[0] == L.GBMC_ERR_INVALID
     assert schedule(L, [0, 5, 3])[0] == L.GBMC_ERR_INVALID
     st, items = schedule(L, [0])
@@ -113,9 +117,10 @@ def test_plan_create_rejects_bad_layout_before_touching_the_gpu(L):
     assert lib.gbmc_plan_create(C.byref(h), 2, _i32p(off), 0, None) == L.GBMC_ERR_INVALID
     off = np.array([0, 10], dtype=np.int32)
     assert lib.gbmc_plan_create(C.byref(h), 1, _i32p(off), 7, None) == L.GBMC_ERR_INVALID
-    bad = C.byref(L.gbmc_tuning(0, 4))
+    from paper_1803_09652_amd.api import tuning_struct
+    bad = C.byref(tuning_struct((1, 0, 1), 4))
     assert lib.gbmc_plan_create(C.byref(h), 1, _i32p(off), 0, bad) == L.GBMC_ERR_INVALID
-    bad = C.byref(L.gbmc_tuning(8, 3))
+    bad = C.byref(tuning_struct(8, (1, 3, 1)))
     assert lib.gbmc_plan_create(C.byref(h), 1, _i32p(off), 0, bad) == L.GBMC_ERR_INVALID
 
 

@@ -106,7 +106,7 @@ def test_fp32_bitwise_deterministic_and_shape_independent():
     p_gpu, _ = params_pair()
     systems = [_sys(11, 700), _sys(12, 333)]
     outs = []
-    for jb, wv in ((8, 4), (8, 4), (1, 1), (3, 2), (64, 8), (2, 8)):
+    for jb, wv in ((8, 4), (8, 4), (1, 1), (3, 2), (64, 8), ((1, 8, 2), (2, 1, 4))):
         g, batch, plan, atoms = build(systems, "fp32", j_blocks=jb, waves=wv)
         outs.append(gpu_eval(plan, atoms, p_gpu))
     for o in outs[1:]:
