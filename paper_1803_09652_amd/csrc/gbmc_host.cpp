@@ -49,13 +49,14 @@ struct gbmc_plan {
     WorkItem* d_items[GBMC_N_PASSES] = {nullptr, nullptr, nullptr};
     void* d_mem = nullptr;           // one allocation: the work lists and the order
     int32_t* d_perm = nullptr;       // [N] internal -> caller atom index
+    int32_t* d_offset = nullptr;     // [B+1] device copy of the atom offsets
     int device = 0;
     // timing hook: events bracketing each timed kernel, recorded while enabled
     bool timing = false;
     hipEvent_t ev[2 * kNumKernels] = {};
     bool recorded[kNumKernels] = {};
     // workspace layout (byte offsets)
-    size_t off_I, off_F, off_G, off_phi, off_drho, off_E, off_I64, off_R64, off_T64, off_dR64,
+    size_t off_I, off_F, off_G, off_phi, off_drho, off_EA, off_I64, off_R64, off_T64, off_dR64,
         off_G64, off_B64, off_Rt, off_at, off_Brt, off_ovf, off_P, off_Gx, off_A64, off_rows, ws_bytes;
 };
 
@@ -131,6 +132,7 @@ static Work<T> carve(const gbmc_plan* p, void* ws)
     char* b = static_cast<char*>(ws);
     Work<T> w;
     w.perm = p->d_perm;
+    w.atom_offset = p->d_offset;
     w.P = reinterpret_cast<Q4<T>*>(b + p->off_P);
     w.Gx = reinterpret_cast<Q4<T>*>(b + p->off_Gx);
     w.I_fx = reinterpret_cast<unsigned long long*>(b + p->off_I);
@@ -138,7 +140,7 @@ static Work<T> carve(const gbmc_plan* p, void* ws)
     w.G_fx = reinterpret_cast<unsigned long long*>(b + p->off_G);
     w.phi_fx = reinterpret_cast<unsigned long long*>(b + p->off_phi);
     w.drho_fx = reinterpret_cast<unsigned long long*>(b + p->off_drho);
-    w.E_fx = reinterpret_cast<unsigned long long*>(b + p->off_E);
+    w.EA_fx = reinterpret_cast<unsigned long long*>(b + p->off_EA);
     w.I64 = reinterpret_cast<double*>(b + p->off_I64);
     w.R64 = reinterpret_cast<double*>(b + p->off_R64);
     w.A64 = reinterpret_cast<double*>(b + p->off_A64);
@@ -162,12 +164,14 @@ static void layout(gbmc_plan* p)
     auto seg = [&](size_t bytes) { size_t at = o; o = align256(o + bytes); return at; };
     p->off_I = seg(8 * (N + 1));           // the overflow word follows I_fx
     p->off_ovf = p->off_I + 8 * N;
-    // F (3N), G, phi, drho are one contiguous run of 6N int64: cleared by one kernel
-    p->off_F = seg(8 * 6 * N);
+    // F (3N), G, phi, drho and the energy shares (2N) are one contiguous run of
+    // 8N int64: cleared by one kernel
+    p->off_F = seg(8 * 8 * N);
     p->off_G = p->off_F + 8 * 3 * N;
     p->off_phi = p->off_G + 8 * N;
     p->off_drho = p->off_phi + 8 * N;
-    p->off_E = seg(8 * 2 * B);
+    p->off_EA = p->off_drho + 8 * N;
+    (void)B;
     p->off_I64 = seg(8 * N);
     p->off_R64 = seg(8 * N);
     p->off_A64 = seg(8 * N);
@@ -295,7 +299,9 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
             o = align256(o + items[k].size() * sizeof(WorkItem));
         }
         at[GBMC_N_PASSES] = o;
-        const size_t total = o + 4 * (size_t)p->n_atoms;
+        const size_t off_bytes = 4 * (size_t)(n_systems + 1);
+        const size_t at_off = align256(o + 4 * (size_t)p->n_atoms);
+        const size_t total = at_off + off_bytes;
         if (total > 0) {
             char* d = nullptr;
             e = hipMalloc(&d, total);
@@ -310,6 +316,8 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
             p->d_perm = reinterpret_cast<int32_t*>(d + at[GBMC_N_PASSES]);
             int32_t* id = reinterpret_cast<int32_t*>(h.data() + at[GBMC_N_PASSES]);
             for (int32_t k = 0; k < p->n_atoms; ++k) id[k] = k;
+            p->d_offset = reinterpret_cast<int32_t*>(d + at_off);
+            std::memcpy(h.data() + at_off, p->offset.data(), off_bytes);
             e = hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice);
             if (e != hipSuccess) { (void)hipFree(d); delete p; return hip_fail(e, "hipMemcpy(plan tables)"); }
         }

@@ -53,7 +53,8 @@ struct Work {
     unsigned long long* G_fx;     // [N] internal
     unsigned long long* phi_fx;   // [N] internal
     unsigned long long* drho_fx;  // [N] internal
-    unsigned long long* E_fx;     // [B][2]
+    unsigned long long* EA_fx;    // [N][2] internal: per-atom Coulomb and GB energy shares
+    const int32_t* atom_offset;   // [B+1] (plan memory)
     double* I64;                  // [N] descreening sum
     double* R64;                  // [N] Born radius
     double* A64;                  // [N] 1 / (2 R)

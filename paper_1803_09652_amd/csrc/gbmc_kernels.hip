@@ -294,28 +294,35 @@ __device__ __forceinline__ void walk_tile(int lane, bool diagonal, T (&acc_j)[NJ
 {
 #pragma unroll
     for (int a = 0; a < NJ; ++a) acc_j[a] = T(0);
-    if (!diagonal) {
-        auto d = load(lane);
-#pragma unroll 1
-        for (int k = 0; k < kTile; ++k) {
-            auto next = load(lane + k + 1);     // slot <= 127: inside the doubled block
-            pair(d, true, acc_j);
+    auto step = [&](const auto& d, bool valid) {
+        pair(d, valid, acc_j);
 #pragma unroll
-            for (int a = 0; a < NJ; ++a) acc_j[a] = rot1(acc_j[a]);
-            d = next;
+        for (int a = 0; a < NJ; ++a) acc_j[a] = rot1(acc_j[a]);
+    };
+    // Two steps per trip with two load buffers, so that the next j is read
+    // while the current one is used and no register copies are needed.
+    if (!diagonal) {
+        auto a = load(lane);
+#pragma unroll 1
+        for (int k = 0; k < kTile; k += 2) {
+            auto b = load(lane + k + 1);
+            step(a, true);
+            a = load(lane + k + 2);             // slot <= 127: inside the doubled block
+            step(b, true);
         }
     } else {
         // pairs (l, l + k) for k = 1..31, and k = 32 for lanes 0..31 only
-        auto d = load(lane + 1);
+        auto a = load(lane + 1);
 #pragma unroll 1
-        for (int k = 1; k < kTile / 2; ++k) {
-            auto next = load(lane + k + 1);
-            pair(d, true, acc_j);
-#pragma unroll
-            for (int a = 0; a < NJ; ++a) acc_j[a] = rot1(acc_j[a]);
-            d = next;
+        for (int k = 1; k < kTile / 2 - 1; k += 2) {
+            auto b = load(lane + k + 1);
+            step(a, true);
+            a = load(lane + k + 2);
+            step(b, true);
         }
-        pair(d, lane < kTile / 2, acc_j);
+        auto b = load(lane + kTile / 2);
+        step(a, true);
+        pair(b, lane < kTile / 2, acc_j);
         // lane l now holds j = l + 32; j = l sits in lane (l - 32) mod 64
 #pragma unroll
         for (int a = 0; a < NJ; ++a) acc_j[a] = from_lane(acc_j[a], (lane + kTile / 2) & (kTile - 1));
@@ -579,31 +586,49 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
         fx_add(&wk.G_fx[g], fix[3]);
         fx_add(&wk.phi_fx[g], fix[4]);
     }
-    // energies: exact integer wavefront sum, one atomic per item
-    long long e0 = vi ? efix[0] : 0, e1 = vi ? efix[1] : 0;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        e0 += __shfl_xor(e0, off);
-        e1 += __shfl_xor(e1, off);
-    }
-    if (lane == 0) {
-        fx_add(&wk.E_fx[2 * w.sys + 0], e0);
-        fx_add(&wk.E_fx[2 * w.sys + 1], e1);
+    // energies: each atom's share, summed per system by k_energy_sum (exact
+    // integers, so the split into atoms does not change the totals)
+    if (vi) {
+        fx_add(&wk.EA_fx[2 * (size_t)(w.base + i) + 0], efix[0]);
+        fx_add(&wk.EA_fx[2 * (size_t)(w.base + i) + 1], efix[1]);
     }
 }
 
-// Per atom after pass 2: B = G dR/dPsi for the chain pass; dE/dq output;
-// energies per system.
+// Per system: E_C and E_GB from the atoms' fixed-point shares (one block per
+// system; integer sums, so the result does not depend on the order).
+__global__ __launch_bounds__(256) void k_energy_sum(const int32_t* __restrict__ off,
+                                                    const unsigned long long* __restrict__ EA,
+                                                    double* __restrict__ e_coul,
+                                                    double* __restrict__ e_gb)
+{
+    __shared__ long long part[2][4];
+    const int b = blockIdx.x, t = threadIdx.x, lane = t % kTile, wave = t / kTile;
+    long long s0 = 0, s1 = 0;
+    for (int g = off[b] + t; g < off[b + 1]; g += 256) {
+        s0 += (long long)EA[2 * (size_t)g];
+        s1 += (long long)EA[2 * (size_t)g + 1];
+    }
+#pragma unroll
+    for (int o = kTile / 2; o > 0; o >>= 1) {
+        s0 += __shfl_xor(s0, o);
+        s1 += __shfl_xor(s1, o);
+    }
+    if (lane == 0) { part[0][wave] = s0; part[1][wave] = s1; }
+    __syncthreads();
+    if (t == 0) {
+        long long c = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+        long long gb = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+        if (e_coul) e_coul[b] = (double)c * (1.0 / kScaleE);
+        if (e_gb) e_gb[b] = (double)gb * (1.0 / kScaleE);
+    }
+}
+
+// Per atom after pass 2: B = G dR/dPsi for the chain pass; dE/dq output.
 template <typename T>
-__global__ void k_energy_finalize(int n_atoms, int n_sys, Work<T> w, double* __restrict__ e_coul,
-                                  double* __restrict__ e_gb, T* __restrict__ dEdq, bool grad)
+__global__ void k_energy_finalize(int n_atoms, Work<T> w, T* __restrict__ dEdq)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k < n_sys) {
-        if (e_coul) e_coul[k] = (double)(long long)w.E_fx[2 * k] * (1.0 / kScaleE);
-        if (e_gb) e_gb[k] = (double)(long long)w.E_fx[2 * k + 1] * (1.0 / kScaleE);
-    }
-    if (!grad || k >= n_atoms) return;
+    if (k >= n_atoms) return;
     const int g = w.perm[k];
     double G = (double)(long long)w.G_fx[k] * (1.0 / kScaleF);
     double B = G * w.dRdPsi64[g];
@@ -1110,10 +1135,9 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
 {
     const bool grad = force || dEdq || dEdrho;
     const bool chain = force || dEdrho;
-    // F, G, phi, drho are contiguous after I_fx in the workspace; E_fx follows
-    size_t nz = grad ? (size_t)6 * n_atoms : 0;
+    // F, G, phi, drho and the per-atom energy shares are one contiguous run of 8N
+    const size_t nz = (size_t)8 * n_atoms;
     if (nz) hipLaunchKernelGGL(k_zero64, dim3(blocks_for(nz, 256)), dim3(256), 0, s, w.F_fx, nz);
-    hipLaunchKernelGGL(k_zero64, dim3(1), dim3(256), 0, s, w.E_fx, (size_t)2 * n_sys);
     // positions and charges as given to this call, in processing order
     if (n_atoms > 0)
         hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
@@ -1134,10 +1158,12 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
                                                (T)c.kT, w))
         mark(ev, kKEnergy, 1, s);
     }
-    int nb = blocks_for(n_atoms > n_sys ? n_atoms : n_sys, 256);
-    if (nb > 0)
-        hipLaunchKernelGGL(k_energy_finalize<T>, dim3(nb), dim3(256), 0, s, n_atoms, n_sys, w,
-                           e_coul, e_gb, dEdq, grad);
+    if (n_sys > 0 && (e_coul || e_gb))
+        hipLaunchKernelGGL(k_energy_sum, dim3(n_sys), dim3(256), 0, s, w.atom_offset, w.EA_fx, e_coul,
+                           e_gb);
+    if (grad && n_atoms > 0)
+        hipLaunchKernelGGL(k_energy_finalize<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s,
+                           n_atoms, w, dEdq);
     if (chain && pc.n_items > 0) {
         mark(ev, kKChain, 0, s);
         GBMC_DISPATCH_W(pc.waves_per_group,
