@@ -56,7 +56,9 @@ def _f64p(a: np.ndarray):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
-DEFAULT_SHAPE = {"j_blocks_per_item": (1, 8, 1), "waves_per_group": (1, 8, 1)}
+# the library's default work shapes (radii, energy, chain) per precision
+DEFAULT_SHAPE = {"fp32": {"j_blocks_per_item": (1, 2, 1), "waves_per_group": (4, 4, 1)},
+                 "fp64": {"j_blocks_per_item": (2, 2, 2), "waves_per_group": (2, 4, 4)}}
 
 
 def _per_pass(v, default):
@@ -70,11 +72,12 @@ def _per_pass(v, default):
     return v
 
 
-def tuning_struct(j_blocks_per_item=None, waves_per_group=None) -> L.gbmc_tuning:
+def tuning_struct(j_blocks_per_item=None, waves_per_group=None,
+                  precision: str = "fp32") -> L.gbmc_tuning:
     """Work shape per pair pass; each argument is an int (all passes) or a
     (radii, energy, chain) triple; None keeps the library default."""
-    jb = _per_pass(j_blocks_per_item, DEFAULT_SHAPE["j_blocks_per_item"])
-    wv = _per_pass(waves_per_group, DEFAULT_SHAPE["waves_per_group"])
+    jb = _per_pass(j_blocks_per_item, DEFAULT_SHAPE[precision]["j_blocks_per_item"])
+    wv = _per_pass(waves_per_group, DEFAULT_SHAPE[precision]["waves_per_group"])
     t = L.gbmc_tuning()
     for k in range(L.N_PASSES):
         t.j_blocks_per_item[k] = jb[k]
@@ -102,7 +105,7 @@ class Plan:
             else torch.device(device)
         tun = None
         if j_blocks_per_item is not None or waves_per_group is not None:
-            tun = C.byref(tuning_struct(j_blocks_per_item, waves_per_group))
+            tun = C.byref(tuning_struct(j_blocks_per_item, waves_per_group, precision))
         h = C.c_void_p()
         with torch.cuda.device(self.device):
             L.check(lib.gbmc_plan_create(C.byref(h), int(self.offset.size - 1), _i32p(self.offset),

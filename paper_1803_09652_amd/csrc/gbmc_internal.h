@@ -49,11 +49,13 @@ struct Work {
     Q4<T>* P;                     // [N] internal: x, y, z, q
     Q4<T>* Gx;                    // [N] internal: rho - offset, screen (rho - offset), screen, 0
     unsigned long long* I_fx;     // [N] internal
-    unsigned long long* F_fx;     // [N][3] internal
+    unsigned long long* F_fx;     // [3][N] internal (component-major: one atomic
+                                  //  instruction of a wave covers 512 contiguous bytes)
+    size_t n_atoms;               // N, the stride of F_fx
     unsigned long long* G_fx;     // [N] internal
     unsigned long long* phi_fx;   // [N] internal
     unsigned long long* drho_fx;  // [N] internal
-    unsigned long long* EA_fx;    // [N][2] internal: per-atom Coulomb and GB energy shares
+    unsigned long long* EA_fx;    // [2][N] internal: per-atom Coulomb and GB energy shares
     const int32_t* atom_offset;   // [B+1] (plan memory)
     double* I64;                  // [N] descreening sum
     double* R64;                  // [N] Born radius

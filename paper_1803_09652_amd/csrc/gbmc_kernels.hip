@@ -48,15 +48,22 @@ __device__ __forceinline__ double rsq(double v) { return 1.0 / sqrt(v); }
 __device__ __forceinline__ double rcp(double v) { return 1.0 / v; }
 __device__ __forceinline__ double exp2neg(double t) { return exp2(-t); }
 
-__device__ __forceinline__ long long to_fixed(double v, double scale, int* ovf)
+// Fixed-point value of v; an out-of-range (or NaN) v gives 0 and sets bad.
+// The flag stays in a register until the work item ends, so that the pair
+// loops issue no conditional stores.
+__device__ __forceinline__ long long to_fixed(double v, double scale, bool& bad)
 {
     double s = v * scale;
-    if (!(fabs(s) < kFixLimit)) {
-        *ovf = 1;
-        return 0;
-    }
-    return __double2ll_rn(s);
+    const bool ok = fabs(s) < kFixLimit;
+    bad |= !ok;
+    return ok ? __double2ll_rn(s) : 0ll;
 }
+
+// Row of atom a in a system of n >= 1 atoms.  Lanes past the end read (and add
+// zero to) the atom a mod n, so every lane issues the same memory operations
+// (the wait for the next block's loads then does not depend on the lane mix)
+// and the zero additions of one block go to distinct addresses.
+__device__ __forceinline__ int clamp_atom(int a, int n) { return a < n ? a : a % n; }
 
 __device__ __forceinline__ void fx_add(unsigned long long* p, long long v)
 {
@@ -386,34 +393,41 @@ __global__ __launch_bounds__(kTile * W) void k_radii_pairs(
         Si = T(0);
     }
     // j block data, fetched one block ahead
-    auto fetch = [&](int J, Q4<T>& pj, T& Sj) {
+    // loads of a j block (raw), and the stand-in values of lanes past the end,
+    // applied only when the block is written to LDS so the loads stay in flight
+    auto fetch = [&](int J, Q4<T>& pj, Q4<T>& gj) {
+        const int g = w.base + clamp_atom(J * kTile + lane, w.n);
+        pj = P[g];
+        gj = Gx[g];
+    };
+    auto tail = [&](int J, Q4<T>& pj, T& Sj, const Q4<T>& gj) {
         const int j = J * kTile + lane;
-        if (j < w.n) {
-            const Q4<T> p = P[w.base + j];
-            const Q4<T> gx = Gx[w.base + j];
-            pj.x = p.x; pj.y = p.y; pj.z = p.z;
-            pj.w = gx.x;
-            Sj = gx.y;
-        } else {
+        pj.w = gj.x;
+        Sj = gj.y;
+        if (j >= w.n) {
             dummy_pos(j, pj.x, pj.y, pj.z);
             pj.w = T(1);
             Sj = T(0);
         }
     };
     long long ifix = 0;
-    Q4<T> pj;
-    T Sj;
-    fetch(w.J0, pj, Sj);
-    for (int J = w.J0; J < w.J1; ++J) {
+    bool bad = false;
+    Q4<T> pj, gj;
+    fetch(w.J0, pj, gj);
+    // one 64 x 64 tile; the first is peeled so that the loop is entered, as
+    // on every later trip, with the previous tile's sums still in flight
+    auto tile = [&](int J) {
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
+        T Sj;
+        tail(J, pj, Sj, gj);
         wave_sync();
         sj[lane] = pj;
         sj[lane + kTile] = pj;
         sS[lane] = Sj;
         sS[lane + kTile] = Sj;
         wave_sync();
-        if (J + 1 < w.J1) fetch(J + 1, pj, Sj);
+        fetch(J + 1 < w.J1 ? J + 1 : J, pj, gj);     // the last trip re-reads J
         T ai = T(0);
         T aj[1];
         struct JD { Q4<T> p; T S; };
@@ -425,10 +439,14 @@ __global__ __launch_bounds__(kTile * W) void k_radii_pairs(
                 ai += act ? hij : T(0);
                 acc[0] += act ? hji : T(0);
             });
-        if (vj) fx_add(&I_fx[w.base + j], to_fixed((double)aj[0], kScaleI, ovf));
-        ifix += to_fixed((double)ai, kScaleI, ovf);
-    }
+        const long long hj = to_fixed((double)aj[0], kScaleI, bad);
+        fx_add(&I_fx[w.base + clamp_atom(j, w.n)], vj ? hj : 0ll);
+        ifix += to_fixed((double)ai, kScaleI, bad);
+    };
+    tile(w.J0);
+    for (int J = w.J0 + 1; J < w.J1; ++J) tile(J);
     if (vi) fx_add(&I_fx[w.base + i], ifix);
+    if (bad) *ovf = 1;
 }
 
 // Per atom: OBC radius from the descreening sum (FP64), and the per-atom state
@@ -489,13 +507,16 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
         dummy_pos(i, xi, yi, zi);
         qi = T(0); Ri = T(1); ai = T(kAScale);
     }
+    // raw loads of a j block; stand-ins for lanes past the end are applied
+    // when the block is written to LDS
     auto fetch = [&](int J, Q4<T>& pj, T& Rj, T& Aj) {
+        const int g = w.base + clamp_atom(J * kTile + lane, w.n);
+        pj = P[g];
+        Rj = Rt[g]; Aj = At[g];
+    };
+    auto tail = [&](int J, Q4<T>& pj, T& Rj, T& Aj) {
         const int j = J * kTile + lane;
-        if (j < w.n) {
-            int g = w.base + j;
-            pj = P[g];
-            Rj = Rt[g]; Aj = At[g];
-        } else {
+        if (j >= w.n) {
             dummy_pos(j, pj.x, pj.y, pj.z);
             pj.w = T(0);
             Rj = T(1); Aj = T(kAScale);
@@ -503,18 +524,22 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
     };
     long long fix[5] = {0, 0, 0, 0, 0};
     long long efix[2] = {0, 0};
+    bool bad = false;
     Q4<T> pj;
     T Rj, Aj;
     fetch(w.J0, pj, Rj, Aj);
-    for (int J = w.J0; J < w.J1; ++J) {
+    // one 64 x 64 tile; the first is peeled so that the loop is entered, as
+    // on every later trip, with the previous tile's sums still in flight
+    auto tile = [&](int J) {
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
+        tail(J, pj, Rj, Aj);
         wave_sync();
         sj[lane] = pj; sj[lane + kTile] = pj;
         sR[lane] = Rj; sR[lane + kTile] = Rj;
         sA[lane] = Aj; sA[lane + kTile] = Aj;
         wave_sync();
-        if (J + 1 < w.J1) fetch(J + 1, pj, Rj, Aj);
+        fetch(J + 1 < w.J1 ? J + 1 : J, pj, Rj, Aj);
         T fxi = 0, fyi = 0, fzi = 0, Gi = 0, phii = 0, eC = 0, eG = 0;
         T aj[NJ];
         struct JD { Q4<T> p; T R, A; };
@@ -562,41 +587,47 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
             }
         }
         if (GRAD) {
-            if (vj) {
-                int g = w.base + j;
+            const int g = w.base + clamp_atom(j, w.n);
+            long long v[5];
 #pragma unroll
-                for (int a = 0; a < 3; ++a)
-                    fx_add(&wk.F_fx[3 * (size_t)g + a], to_fixed((double)aj[a], kScaleF, wk.ovf));
-                fx_add(&wk.G_fx[g], to_fixed((double)aj[3], kScaleF, wk.ovf));
-                fx_add(&wk.phi_fx[g], to_fixed((double)aj[4], kScaleF, wk.ovf));
+            for (int a = 0; a < 5; ++a) {
+                v[a] = to_fixed((double)aj[a], kScaleF, bad);
+                v[a] = vj ? v[a] : 0ll;
             }
-            fix[0] += to_fixed((double)fxi, kScaleF, wk.ovf);
-            fix[1] += to_fixed((double)fyi, kScaleF, wk.ovf);
-            fix[2] += to_fixed((double)fzi, kScaleF, wk.ovf);
-            fix[3] += to_fixed((double)Gi, kScaleF, wk.ovf);
-            fix[4] += to_fixed((double)phii, kScaleF, wk.ovf);
+#pragma unroll
+            for (int a = 0; a < 3; ++a) fx_add(&wk.F_fx[a * wk.n_atoms + g], v[a]);
+            fx_add(&wk.G_fx[g], v[3]);
+            fx_add(&wk.phi_fx[g], v[4]);
+            fix[0] += to_fixed((double)fxi, kScaleF, bad);
+            fix[1] += to_fixed((double)fyi, kScaleF, bad);
+            fix[2] += to_fixed((double)fzi, kScaleF, bad);
+            fix[3] += to_fixed((double)Gi, kScaleF, bad);
+            fix[4] += to_fixed((double)phii, kScaleF, bad);
         }
-        efix[0] += to_fixed((double)(kC * eC), kScaleE, wk.ovf);
-        efix[1] += to_fixed((double)(-kT * eG), kScaleE, wk.ovf);
-    }
+        efix[0] += to_fixed((double)(kC * eC), kScaleE, bad);
+        efix[1] += to_fixed((double)(-kT * eG), kScaleE, bad);
+    };
+    tile(w.J0);
+    for (int J = w.J0 + 1; J < w.J1; ++J) tile(J);
+    if (bad) *wk.ovf = 1;
     if (GRAD && vi) {
         int g = w.base + i;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) fx_add(&wk.F_fx[3 * (size_t)g + a], fix[a]);
+        for (int a = 0; a < 3; ++a) fx_add(&wk.F_fx[a * wk.n_atoms + g], fix[a]);
         fx_add(&wk.G_fx[g], fix[3]);
         fx_add(&wk.phi_fx[g], fix[4]);
     }
     // energies: each atom's share, summed per system by k_energy_sum (exact
     // integers, so the split into atoms does not change the totals)
     if (vi) {
-        fx_add(&wk.EA_fx[2 * (size_t)(w.base + i) + 0], efix[0]);
-        fx_add(&wk.EA_fx[2 * (size_t)(w.base + i) + 1], efix[1]);
+        fx_add(&wk.EA_fx[w.base + i], efix[0]);
+        fx_add(&wk.EA_fx[wk.n_atoms + w.base + i], efix[1]);
     }
 }
 
 // Per system: E_C and E_GB from the atoms' fixed-point shares (one block per
 // system; integer sums, so the result does not depend on the order).
-__global__ __launch_bounds__(256) void k_energy_sum(const int32_t* __restrict__ off,
+__global__ __launch_bounds__(256) void k_energy_sum(const int32_t* __restrict__ off, size_t n_atoms,
                                                     const unsigned long long* __restrict__ EA,
                                                     double* __restrict__ e_coul,
                                                     double* __restrict__ e_gb)
@@ -605,8 +636,8 @@ __global__ __launch_bounds__(256) void k_energy_sum(const int32_t* __restrict__ 
     const int b = blockIdx.x, t = threadIdx.x, lane = t % kTile, wave = t / kTile;
     long long s0 = 0, s1 = 0;
     for (int g = off[b] + t; g < off[b + 1]; g += 256) {
-        s0 += (long long)EA[2 * (size_t)g];
-        s1 += (long long)EA[2 * (size_t)g + 1];
+        s0 += (long long)EA[g];
+        s1 += (long long)EA[n_atoms + g];
     }
 #pragma unroll
     for (int o = kTile / 2; o > 0; o >>= 1) {
@@ -670,35 +701,43 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
         dummy_pos(i, xi, yi, zi);
         rti = T(1); si = T(0); Si = T(0); Bi = T(0);
     }
-    auto fetch = [&](int J, Q4<T>& pj, Q4<T>& bj) {
+    // raw loads of a j block; stand-ins for lanes past the end are applied
+    // when the block is written to LDS
+    auto fetch = [&](int J, Q4<T>& pj, Q4<T>& gj, T& brj) {
+        const int g = w.base + clamp_atom(J * kTile + lane, w.n);
+        pj = P[g];
+        gj = Gx[g];
+        brj = Brt[g];
+    };
+    auto tail = [&](int J, Q4<T>& pj, Q4<T>& bj, const Q4<T>& gj, T brj) {
         const int j = J * kTile + lane;
-        if (j < w.n) {
-            int g = w.base + j;
-            const Q4<T> p = P[g];
-            const Q4<T> gx = Gx[g];
-            pj.x = p.x; pj.y = p.y; pj.z = p.z;
-            pj.w = gx.x;
-            bj.x = gx.y;
-            bj.z = gx.z;
-            bj.y = Brt[g];
-        } else {
+        pj.w = gj.x;
+        bj.x = gj.y;
+        bj.y = brj;
+        bj.z = gj.z;
+        bj.w = T(0);
+        if (j >= w.n) {
             dummy_pos(j, pj.x, pj.y, pj.z);
             pj.w = T(1);
             bj.x = bj.y = bj.z = T(0);
         }
-        bj.w = T(0);
     };
     long long fix[4] = {0, 0, 0, 0};
-    Q4<T> pj, bj;
-    fetch(w.J0, pj, bj);
-    for (int J = w.J0; J < w.J1; ++J) {
+    bool bad = false;
+    Q4<T> pj, gj, bj;
+    T brj;
+    fetch(w.J0, pj, gj, brj);
+    // one 64 x 64 tile; the first is peeled so that the loop is entered, as
+    // on every later trip, with the previous tile's sums still in flight
+    auto tile = [&](int J) {
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
+        tail(J, pj, bj, gj, brj);
         wave_sync();
         sj[lane] = pj; sj[lane + kTile] = pj;
         sb[lane] = bj; sb[lane + kTile] = bj;
         wave_sync();
-        if (J + 1 < w.J1) fetch(J + 1, pj, bj);
+        fetch(J + 1 < w.J1 ? J + 1 : J, pj, gj, brj);
         T fxi = 0, fyi = 0, fzi = 0, dri = 0;
         T aj[4];
         struct JD { Q4<T> p, b; };
@@ -724,22 +763,30 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
             acc[2] += fz;
             acc[3] += bj_ * gji[1] + b.z * bi_ * gij[2];
         });
-        if (vj) {
-            int g = w.base + j;
+        {
+            const int g = w.base + clamp_atom(j, w.n);
+            long long v[4];
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
-                fx_add(&wk.F_fx[3 * (size_t)g + a], to_fixed((double)aj[a], kScaleF, wk.ovf));
-            fx_add(&wk.drho_fx[g], to_fixed((double)aj[3], kScaleF, wk.ovf));
+            for (int a = 0; a < 4; ++a) {
+                v[a] = to_fixed((double)aj[a], kScaleF, bad);
+                v[a] = vj ? v[a] : 0ll;
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) fx_add(&wk.F_fx[a * wk.n_atoms + g], v[a]);
+            fx_add(&wk.drho_fx[g], v[3]);
         }
-        fix[0] += to_fixed((double)fxi, kScaleF, wk.ovf);
-        fix[1] += to_fixed((double)fyi, kScaleF, wk.ovf);
-        fix[2] += to_fixed((double)fzi, kScaleF, wk.ovf);
-        fix[3] += to_fixed((double)dri, kScaleF, wk.ovf);
-    }
+        fix[0] += to_fixed((double)fxi, kScaleF, bad);
+        fix[1] += to_fixed((double)fyi, kScaleF, bad);
+        fix[2] += to_fixed((double)fzi, kScaleF, bad);
+        fix[3] += to_fixed((double)dri, kScaleF, bad);
+    };
+    tile(w.J0);
+    for (int J = w.J0 + 1; J < w.J1; ++J) tile(J);
+    if (bad) *wk.ovf = 1;
     if (vi) {
         int g = w.base + i;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) fx_add(&wk.F_fx[3 * (size_t)g + a], fix[a]);
+        for (int a = 0; a < 3; ++a) fx_add(&wk.F_fx[a * wk.n_atoms + g], fix[a]);
         fx_add(&wk.drho_fx[g], fix[3]);
     }
 }
@@ -756,7 +803,7 @@ __global__ void k_grad_finalize(int n_atoms, const T* __restrict__ RHO, double o
     if (force) {
 #pragma unroll
         for (int a = 0; a < 3; ++a)
-            force[3 * (size_t)g + a] = (T)((double)(long long)w.F_fx[3 * (size_t)k + a] * (1.0 / kScaleF));
+            force[3 * (size_t)g + a] = (T)((double)(long long)w.F_fx[a * w.n_atoms + k] * (1.0 / kScaleF));
     }
     if (dEdrho) {
         double rho = (double)RHO[g];
@@ -1159,8 +1206,8 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
         mark(ev, kKEnergy, 1, s);
     }
     if (n_sys > 0 && (e_coul || e_gb))
-        hipLaunchKernelGGL(k_energy_sum, dim3(n_sys), dim3(256), 0, s, w.atom_offset, w.EA_fx, e_coul,
-                           e_gb);
+        hipLaunchKernelGGL(k_energy_sum, dim3(n_sys), dim3(256), 0, s, w.atom_offset, w.n_atoms,
+                           w.EA_fx, e_coul, e_gb);
     if (grad && n_atoms > 0)
         hipLaunchKernelGGL(k_energy_finalize<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s,
                            n_atoms, w, dEdq);
