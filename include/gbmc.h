@@ -258,11 +258,14 @@ gbmc_status remd_exchange(int32_t n_rep, const double* E_rung, const int32_t* Ne
                           hipStream_t stream);
 
 /* Kernel timing hook (tracing).  While enabled, every compute call on this
- * plan records HIP events on its stream immediately before and after each
- * kernel of the hot path; gbmc_plan_kernel_ms waits for the last recorded
- * events and writes the duration (ms) of the most recent launch of each kernel
- * into ms[GBMC_N_KERNELS] (-1 for kernels not launched since enabling).
- * Intended for eager calls, not for calls captured into a graph. */
+ * plan launches each kernel of the hot path with a start and a stop HIP event
+ * bound to the dispatch itself (hipExtLaunchKernelGGL), so that their interval
+ * is the kernel's own execution, without host synchronisation between calls.
+ * gbmc_plan_kernel_ms waits for the last recorded events and writes, per
+ * kernel, the mean duration (ms) over its launches since the previous read or
+ * the enabling call (the most recent 256 when there were more) into
+ * ms[GBMC_N_KERNELS], -1 for kernels not launched; the read starts a new
+ * count.  For eager calls only: disable it before capturing a graph. */
 enum {
     GBMC_K_RADII_PAIRS = 0,    /* descreening pair pass of gb_radii */
     GBMC_K_ENERGY_PAIRS = 1,   /* energy / explicit force pair pass */

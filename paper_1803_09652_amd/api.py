@@ -142,7 +142,8 @@ class Plan:
             L.check(L.load().gbmc_plan_set_order(self._h, _i32p(o)))
 
     def set_timing(self, enable: bool = True) -> None:
-        """Record HIP events around each hot-path kernel of later eager calls."""
+        """Time each hot-path kernel of later eager calls (HIP events bound to
+        the dispatch).  Disable before capturing a graph."""
         L.check(L.load().gbmc_plan_set_timing(self._h, int(bool(enable))))
 
     def kernel_ms(self) -> dict:

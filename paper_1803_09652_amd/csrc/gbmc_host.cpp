@@ -35,6 +35,8 @@ gbmc_status hip_fail(hipError_t e, const char* where)
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+constexpr int64_t kTimedMax = 256;   // launches kept per timed kernel between reads
+
 // Default work shapes (radii, energy, chain), the fastest measured for batches
 // of tens of thousands of atoms: the energy pass keeps two-tile items, which
 // halve its seven i-side flushes per tile.
@@ -55,10 +57,13 @@ struct gbmc_plan {
     int32_t* d_perm = nullptr;       // [N] internal -> caller atom index
     int32_t* d_offset = nullptr;     // [B+1] device copy of the atom offsets
     int device = 0;
-    // timing hook: events bracketing each timed kernel, recorded while enabled
+    // timing hook: a ring of start/stop event pairs per timed kernel (bound to
+    // the dispatches while enabled), the launches recorded since the last
+    // read, and the pairs handed to the current call
     bool timing = false;
-    hipEvent_t ev[2 * kNumKernels] = {};
-    bool recorded[kNumKernels] = {};
+    std::vector<hipEvent_t> ev_pool;  // [kNumKernels][kTimedMax][2]
+    int64_t n_rec[kNumKernels] = {};
+    hipEvent_t cur[2 * kNumKernels] = {};
     // workspace layout (byte offsets)
     size_t off_I, off_F, off_G, off_phi, off_drho, off_EA, off_I64, off_R64, off_T64, off_dR64,
         off_G64, off_B64, off_Rt, off_at, off_Brt, off_ovf, off_P, off_Gx, off_A64, off_rows, ws_bytes;
@@ -337,7 +342,7 @@ void gbmc_plan_destroy(gbmc_plan* p)
 {
     if (!p) return;
     if (p->d_mem) (void)hipFree(p->d_mem);
-    for (hipEvent_t e : p->ev)
+    for (hipEvent_t e : p->ev_pool)
         if (e) (void)hipEventDestroy(e);
     delete p;
 }
@@ -345,14 +350,25 @@ void gbmc_plan_destroy(gbmc_plan* p)
 gbmc_status gbmc_plan_set_timing(gbmc_plan* p, int32_t enable)
 {
     if (!p) return fail(GBMC_ERR_INVALID, "plan is NULL");
-    if (enable && !p->ev[0])
-        for (hipEvent_t& e : p->ev) {
+    if (enable && p->ev_pool.empty()) {
+        try {
+            p->ev_pool.assign((size_t)2 * kNumKernels * kTimedMax, nullptr);
+        } catch (const std::bad_alloc&) {
+            return fail(GBMC_ERR_INVALID, "host allocation failed");
+        }
+        for (hipEvent_t& e : p->ev_pool) {
             hipError_t r = hipEventCreate(&e);
             if (r != hipSuccess) return hip_fail(r, "hipEventCreate");
         }
+    }
     p->timing = enable != 0;
-    for (bool& r : p->recorded) r = false;
+    for (int64_t& n : p->n_rec) n = 0;
     return GBMC_OK;
+}
+
+static hipEvent_t* pool_pair(gbmc_plan* p, int k, int64_t launch)
+{
+    return &p->ev_pool[2 * ((size_t)k * kTimedMax + (size_t)(launch % kTimedMax))];
 }
 
 gbmc_status gbmc_plan_kernel_ms(gbmc_plan* p, float* ms)
@@ -360,10 +376,21 @@ gbmc_status gbmc_plan_kernel_ms(gbmc_plan* p, float* ms)
     if (!p || !ms) return fail(GBMC_ERR_INVALID, "NULL argument");
     for (int k = 0; k < kNumKernels; ++k) {
         ms[k] = -1.0f;
-        if (!p->recorded[k]) continue;
-        hipError_t r = hipEventSynchronize(p->ev[2 * k + 1]);
-        if (r == hipSuccess) r = hipEventElapsedTime(&ms[k], p->ev[2 * k], p->ev[2 * k + 1]);
-        if (r != hipSuccess) return hip_fail(r, "hipEventElapsedTime");
+        const int64_t n = p->n_rec[k];
+        if (n == 0) continue;
+        hipError_t r = hipEventSynchronize(pool_pair(p, k, n - 1)[1]);
+        if (r != hipSuccess) return hip_fail(r, "hipEventSynchronize");
+        const int64_t m = n < kTimedMax ? n : kTimedMax;   // the most recent launches kept
+        double sum = 0.0;
+        for (int64_t l = n - m; l < n; ++l) {
+            hipEvent_t* e = pool_pair(p, k, l);
+            float t = 0.0f;
+            r = hipEventElapsedTime(&t, e[0], e[1]);
+            if (r != hipSuccess) return hip_fail(r, "hipEventElapsedTime");
+            sum += t;
+        }
+        ms[k] = (float)(sum / (double)m);
+        p->n_rec[k] = 0;
     }
     return GBMC_OK;
 }
@@ -447,11 +474,17 @@ gbmc_status gbmc_spatial_order(int32_t n_systems, const int32_t* off, const doub
     }
 }
 
+// The event pairs for the kernels a call launches (ids), or NULL when the
+// timing hook is off.
 static hipEvent_t* events(gbmc_plan* p, std::initializer_list<int> ids)
 {
     if (!p->timing) return nullptr;
-    for (int k : ids) p->recorded[k] = true;
-    return p->ev;
+    for (int k : ids) {
+        hipEvent_t* e = pool_pair(p, k, p->n_rec[k]++);
+        p->cur[2 * k] = e[0];
+        p->cur[2 * k + 1] = e[1];
+    }
+    return p->cur;
 }
 
 gbmc_status gb_radii(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp, void* ws,

@@ -105,7 +105,8 @@ enum KernelId { kKRadii = 0, kKEnergy = 1, kKChain = 2, kKSiteRows = 3, kKSiteDE
                 kNumKernels = 6 };
 
 // Launchers (gbmc_kernels.hip).  All return hipSuccess or the launch error.
-// ev (nullable) holds 2 * kNumKernels events recorded around the timed kernels.
+// ev (nullable) holds 2 * kNumKernels events: the start and stop events bound to
+// the dispatch of each timed kernel.
 template <typename T>
 hipError_t launch_radii(const WorkItem* items, int n_items, int waves_per_group, int n_atoms,
                         const int32_t* atom_sys,

@@ -24,6 +24,7 @@
 // on the real atom's side, and dummies are never flushed.
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include "gbmc_internal.h"
@@ -557,7 +558,7 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
             T qq = act ? qi * p.w : T(0);
             eC += qq * invr;
             eG += qq * invf;
-            if (GRAD) {
+            if constexpr (GRAD) {
                 T qj = act ? p.w : T(0);
                 T qi_ = act ? qi : T(0);
                 T wgt = kC * invr - kT * invf;
@@ -581,12 +582,12 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
             // (kT/2) q_i^2 / R_i^2 in G
             T invR = rcp(Ri);
             eG += T(0.5) * qi * qi * invR;
-            if (GRAD) {
+            if constexpr (GRAD) {
                 phii -= kT * qi * invR;
                 Gi += T(0.5) * kT * qi * qi * invR * invR;
             }
         }
-        if (GRAD) {
+        if constexpr (GRAD) {
             const int g = w.base + clamp_atom(j, w.n);
             long long v[5];
 #pragma unroll
@@ -1135,10 +1136,17 @@ __global__ __launch_bounds__(256) void k_remd_exchange(int M, const double* __re
 
 static inline int blocks_for(size_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
-static inline void mark(hipEvent_t* ev, int id, int end, hipStream_t s)
-{
-    if (ev) (void)hipEventRecord(ev[2 * id + end], s);
-}
+// Launch of a kernel that the timing hook measures.  With the hook on (ev not
+// NULL) the start and stop events are bound to the dispatch itself, so their
+// interval is the kernel's own execution, without queue gaps.
+#define GBMC_LAUNCH_TIMED(ev, id, K, grid, block, s, ...)                                      \
+    do {                                                                                       \
+        if (ev)                                                                                \
+            hipExtLaunchKernelGGL(K, grid, block, 0, s, (ev)[2 * (id)], (ev)[2 * (id) + 1], 0, \
+                                  __VA_ARGS__);                                                \
+        else                                                                                   \
+            hipLaunchKernelGGL(K, grid, block, 0, s, __VA_ARGS__);                             \
+    } while (0)
 
 // Pair-kernel launch with W independent wavefronts per workgroup.
 #define GBMC_DISPATCH_W(W_, CALL)             \
@@ -1162,11 +1170,9 @@ hipError_t launch_radii(const WorkItem* items, int n_items, int wpg, int n_atoms
     hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms, w.perm,
                        x, y, z, (const T*)nullptr, rho, screen, (T)c.offset, w.P, w.Gx);
     if (n_items > 0) {
-        mark(ev, kKRadii, 0, s);
-        GBMC_DISPATCH_W(wpg, hipLaunchKernelGGL((k_radii_pairs<T, W>), dim3(blocks_for(n_items, W)),
-                                                dim3(kTile * W), 0, s, items, n_items, w.P, w.Gx,
-                                                w.I_fx, w.ovf));
-        mark(ev, kKRadii, 1, s);
+        GBMC_DISPATCH_W(wpg, GBMC_LAUNCH_TIMED(ev, kKRadii, (k_radii_pairs<T, W>),
+                                               dim3(blocks_for(n_items, W)), dim3(kTile * W), s,
+                                               items, n_items, w.P, w.Gx, w.I_fx, w.ovf));
     }
     hipLaunchKernelGGL(k_radii_finalize<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
                        rho, c, w, born_R);
@@ -1190,20 +1196,18 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
         hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
                            w.perm, x, y, z, q, rho, screen, (T)c.offset, w.P, w.Gx);
     if (pe.n_items > 0) {
-        mark(ev, kKEnergy, 0, s);
         if (grad)
             GBMC_DISPATCH_W(pe.waves_per_group,
-                            hipLaunchKernelGGL((k_energy_pairs<T, true, W>),
-                                               dim3(blocks_for(pe.n_items, W)), dim3(kTile * W), 0, s,
-                                               pe.items, pe.n_items, w.P, w.R_t, w.a_t, (T)c.kC,
-                                               (T)c.kT, w))
+                            GBMC_LAUNCH_TIMED(ev, kKEnergy, (k_energy_pairs<T, true, W>),
+                                              dim3(blocks_for(pe.n_items, W)), dim3(kTile * W), s,
+                                              pe.items, pe.n_items, w.P, w.R_t, w.a_t, (T)c.kC,
+                                              (T)c.kT, w))
         else
             GBMC_DISPATCH_W(pe.waves_per_group,
-                            hipLaunchKernelGGL((k_energy_pairs<T, false, W>),
-                                               dim3(blocks_for(pe.n_items, W)), dim3(kTile * W), 0, s,
-                                               pe.items, pe.n_items, w.P, w.R_t, w.a_t, (T)c.kC,
-                                               (T)c.kT, w))
-        mark(ev, kKEnergy, 1, s);
+                            GBMC_LAUNCH_TIMED(ev, kKEnergy, (k_energy_pairs<T, false, W>),
+                                              dim3(blocks_for(pe.n_items, W)), dim3(kTile * W), s,
+                                              pe.items, pe.n_items, w.P, w.R_t, w.a_t, (T)c.kC,
+                                              (T)c.kT, w))
     }
     if (n_sys > 0 && (e_coul || e_gb))
         hipLaunchKernelGGL(k_energy_sum, dim3(n_sys), dim3(256), 0, s, w.atom_offset, w.n_atoms,
@@ -1212,12 +1216,10 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
         hipLaunchKernelGGL(k_energy_finalize<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s,
                            n_atoms, w, dEdq);
     if (chain && pc.n_items > 0) {
-        mark(ev, kKChain, 0, s);
         GBMC_DISPATCH_W(pc.waves_per_group,
-                        hipLaunchKernelGGL((k_chain_pairs<T, W>), dim3(blocks_for(pc.n_items, W)),
-                                           dim3(kTile * W), 0, s, pc.items, pc.n_items, w.P, w.Gx,
-                                           w.Brt_t, w));
-        mark(ev, kKChain, 1, s);
+                        GBMC_LAUNCH_TIMED(ev, kKChain, (k_chain_pairs<T, W>),
+                                          dim3(blocks_for(pc.n_items, W)), dim3(kTile * W), s,
+                                          pc.items, pc.n_items, w.P, w.Gx, w.Brt_t, w));
     }
     if (chain && n_atoms > 0)
         hipLaunchKernelGGL(k_grad_finalize<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s,
@@ -1235,15 +1237,12 @@ hipError_t launch_state_dE(const SiteDev& sd, int n_atoms, const T* x, const T* 
     if (sd.n_rowitems > 0) {
         hipLaunchKernelGGL(k_stage_rows<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
                            x, y, z, q, w.R64, w.A64, w.rows);
-        mark(ev, kKSiteRows, 0, s);
-        hipLaunchKernelGGL(k_site_phi_rows, dim3(sd.n_rowitems), dim3(kTile), 0, s, sd.rowitems,
-                           sd.site_atoms, w.rows, c.kC, c.kT, phi_part);
-        mark(ev, kKSiteRows, 1, s);
+        GBMC_LAUNCH_TIMED(ev, kKSiteRows, k_site_phi_rows, dim3(sd.n_rowitems), dim3(kTile), s,
+                          sd.rowitems, sd.site_atoms, w.rows, c.kC, c.kT, phi_part);
     }
-    mark(ev, kKSiteDE, 0, s);
-    hipLaunchKernelGGL(k_site_dE<T>, dim3(sd.n_sites), dim3(kMC), 0, s, sd, x, y, z, q, w.R64, w.A64,
-                       c.kC, c.kT, phi_part, current_state, pH, E_volt, T_kelvin, dE, dG);
-    mark(ev, kKSiteDE, 1, s);
+    GBMC_LAUNCH_TIMED(ev, kKSiteDE, k_site_dE<T>, dim3(sd.n_sites), dim3(kMC), s, sd, x, y, z, q,
+                      w.R64, w.A64, c.kC, c.kT, phi_part, current_state, pH, E_volt, T_kelvin, dE,
+                      dG);
     return hipGetLastError();
 }
 
@@ -1256,11 +1255,9 @@ hipError_t launch_mc_step(const SiteDev& sd, int n_sys, const T* x, const T* y, 
                           hipStream_t s, hipEvent_t* ev)
 {
     if (n_sys == 0) return hipSuccess;
-    mark(ev, kKMCStep, 0, s);
-    hipLaunchKernelGGL(k_mc_step<T>, dim3(n_sys), dim3(kMC), 0, s, sd, x, y, z, q, w.R64, w.A64,
-                       c.kC, c.kT, current_state, pH, E_volt, T_kelvin, dE, dG, u, n_electrons,
-                       counters, accepted);
-    mark(ev, kKMCStep, 1, s);
+    GBMC_LAUNCH_TIMED(ev, kKMCStep, k_mc_step<T>, dim3(n_sys), dim3(kMC), s, sd, x, y, z, q, w.R64,
+                      w.A64, c.kC, c.kT, current_state, pH, E_volt, T_kelvin, dE, dG, u, n_electrons,
+                      counters, accepted);
     return hipGetLastError();
 }
 
