@@ -201,7 +201,9 @@ gbmc_status gbmc_sites_create(gbmc_plan* plan, gbmc_sites** sites, int32_t n_sit
                               const double* state_gref, const int32_t* state_count);
 void gbmc_sites_destroy(gbmc_sites* sites);
 int32_t gbmc_sites_n_candidates(const gbmc_sites* sites);
-/* Bytes of caller-owned device workspace mc_state_dE and mc_step need. */
+/* Bytes of caller-owned device workspace mc_state_dE and mc_step need: the
+ * site atoms' FP64 potentials as int64 fixed point (2^-44 kcal/mol/e), which
+ * mc_state_dE clears and fills on every call. */
 size_t gbmc_sites_workspace_bytes(const gbmc_sites* sites);
 
 /* Delta E_elec and Delta G of every candidate state change (sections II.A-B):
@@ -213,8 +215,9 @@ size_t gbmc_sites_workspace_bytes(const gbmc_sites* sites);
  *   redox:       dG = dE + F E_volt[b] (n_e(s') - n_e(s)) - (Gref(s') - Gref(s)),
  * the multi-state form of Eqs. 9 and 8.  current_state[S] (int32), pH[B] and
  * E_volt[B] (double) are device arrays; dE_elec and dG receive n_candidates
- * doubles (dG may be NULL).  Uses the Born radii of the last gb_radii call on
- * workspace; atoms->q must be the charges of current_state. */
+ * doubles (dG may be NULL).  Uses the coordinates and Born radii of the last
+ * gb_radii call on workspace: atoms must hold those coordinates, and atoms->q
+ * the charges of current_state. */
 gbmc_status mc_state_dE(gbmc_plan* plan, const gbmc_sites* sites, const gbmc_atoms* atoms,
                         const gbmc_gb_params* params, void* workspace, void* site_workspace,
                         const int32_t* current_state, const double* pH, const double* E_volt,

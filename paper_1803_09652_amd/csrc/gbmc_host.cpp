@@ -72,7 +72,7 @@ struct gbmc_plan {
 struct gbmc_sites {
     const gbmc_plan* plan = nullptr;
     int32_t n_sites = 0, n_cand = 0, n_rowitems = 0;
-    size_t phi_part_len = 0;
+    size_t n_site_atoms = 0;         // fixed-point potential slots in the site workspace
     void* d_mem = nullptr;
     SiteDev dev{};
 };
@@ -613,7 +613,7 @@ gbmc_status gbmc_sites_create(gbmc_plan* p, gbmc_sites** out, int32_t n_sites,
         const int32_t n_st = S > 0 ? site_state_offset[S] : 0;
         const int32_t n_q = n_st > 0 ? state_charge_offset[n_st] : 0;
         std::vector<int32_t> cand(S + 1, 0), prot_off(B + 1, 0), redox_off(B + 1, 0), prot, redox;
-        std::vector<int32_t> sys_sa(B + 1, 0), site_chunks(S, 0), site_phi(S, 0);
+        std::vector<int32_t> sys_sa(B + 1, 0);
         for (int32_t m = 0; m < S; ++m)
             cand[m + 1] = cand[m] + (site_state_offset[m + 1] - site_state_offset[m] - 1);
         // per-system site lists and site-atom ranges
@@ -634,18 +634,14 @@ gbmc_status gbmc_sites_create(gbmc_plan* p, gbmc_sites** out, int32_t n_sites,
         for (int32_t b = 0; b < B; ++b) sys_sa[b + 1] = last[b] >= 0 ? site_atom_offset[last[b] + 1] : sys_sa[b];
         for (int32_t b = 0; b < B; ++b)
             if (first[b] < 0) sys_sa[b] = sys_sa[b + 1];
-        // FP64 potential-row items: (64 site atoms) x (kPhiChunk atoms) per system
+        // FP64 potential-row items: (64 site atoms) x (kPhiChunk atoms) per system;
+        // each adds into the flattened site-atom slots of its 64 site atoms
         std::vector<RowItem> rows;
-        size_t phi_len = 0;
         for (int32_t b = 0; b < B; ++b) {
             const int32_t na = sys_sa[b + 1] - sys_sa[b];
             if (na == 0) continue;
             const int32_t n = p->offset[b + 1] - p->offset[b];
             const int32_t chunks = (n + kPhiChunk - 1) / kPhiChunk;
-            for (int32_t m = first[b]; m <= last[b]; ++m) {
-                site_chunks[m] = chunks;
-                site_phi[m] = (int32_t)phi_len;
-            }
             for (int32_t c = 0; c < chunks; ++c)
                 for (int32_t s0 = 0; s0 < na; s0 += kTile) {
                     RowItem r{};
@@ -655,10 +651,9 @@ gbmc_status gbmc_sites_create(gbmc_plan* p, gbmc_sites** out, int32_t n_sites,
                     r.sa1 = sys_sa[b] + std::min(na, s0 + kTile);
                     r.j0 = c * kPhiChunk;
                     r.j1 = std::min(n, (c + 1) * kPhiChunk);
-                    r.out = (int32_t)phi_len + c * na + s0;
+                    r.out = sys_sa[b] + s0;
                     rows.push_back(r);
                 }
-            phi_len += (size_t)chunks * na;
         }
         // one device allocation for every table
         size_t o = 0;
@@ -667,8 +662,8 @@ gbmc_status gbmc_sites_create(gbmc_plan* p, gbmc_sites** out, int32_t n_sites,
                o_sso = seg(4 * (S + 1)), o_sco = seg(4 * (n_st + 1)), o_q = seg(8 * n_q),
                o_gref = seg(8 * n_st), o_cnt = seg(4 * n_st), o_cand = seg(4 * (S + 1)),
                o_po = seg(4 * (B + 1)), o_ps = seg(4 * prot.size()), o_ro = seg(4 * (B + 1)),
-               o_rs = seg(4 * redox.size()), o_chunks = seg(4 * S), o_phi = seg(4 * S),
-               o_syssa = seg(4 * (B + 1)), o_rows = seg(sizeof(RowItem) * rows.size());
+               o_rs = seg(4 * redox.size()), o_syssa = seg(4 * (B + 1)),
+               o_rows = seg(sizeof(RowItem) * rows.size());
         std::vector<char> h(o, 0);
         auto put = [&](size_t at, const void* src, size_t bytes) { if (bytes) std::memcpy(h.data() + at, src, bytes); };
         if (S > 0) {
@@ -687,8 +682,6 @@ gbmc_status gbmc_sites_create(gbmc_plan* p, gbmc_sites** out, int32_t n_sites,
         put(o_ps, prot.data(), 4 * prot.size());
         put(o_ro, redox_off.data(), 4 * (B + 1));
         put(o_rs, redox.data(), 4 * redox.size());
-        put(o_chunks, site_chunks.data(), 4 * S);
-        put(o_phi, site_phi.data(), 4 * S);
         put(o_syssa, sys_sa.data(), 4 * (B + 1));
         put(o_rows, rows.data(), sizeof(RowItem) * rows.size());
         auto* sp = new gbmc_sites();
@@ -696,7 +689,7 @@ gbmc_status gbmc_sites_create(gbmc_plan* p, gbmc_sites** out, int32_t n_sites,
         sp->n_sites = S;
         sp->n_cand = cand[S];
         sp->n_rowitems = (int32_t)rows.size();
-        sp->phi_part_len = phi_len;
+        sp->n_site_atoms = (size_t)n_sa;
         hipError_t e = hipMalloc(&sp->d_mem, std::max<size_t>(o, 256));
         if (e != hipSuccess) { delete sp; return hip_fail(e, "hipMalloc(site tables)"); }
         e = hipMemcpy(sp->d_mem, h.data(), o, hipMemcpyHostToDevice);
@@ -706,6 +699,7 @@ gbmc_status gbmc_sites_create(gbmc_plan* p, gbmc_sites** out, int32_t n_sites,
         sd.n_sites = S;
         sd.n_cand = cand[S];
         sd.n_rowitems = (int32_t)rows.size();
+        sd.n_site_atoms = (int32_t)n_sa;
         sd.site_system = (const int32_t*)(d + o_sys);
         sd.site_kind = (const int32_t*)(d + o_kind);
         sd.site_atom_offset = (const int32_t*)(d + o_sao);
@@ -721,8 +715,6 @@ gbmc_status gbmc_sites_create(gbmc_plan* p, gbmc_sites** out, int32_t n_sites,
         sd.sys_redox_offset = (const int32_t*)(d + o_ro);
         sd.sys_redox_sites = (const int32_t*)(d + o_rs);
         sd.site_sa_offset = sd.site_atom_offset;
-        sd.site_chunks = (const int32_t*)(d + o_chunks);
-        sd.site_phi_offset = (const int32_t*)(d + o_phi);
         sd.sys_sa_offset = (const int32_t*)(d + o_syssa);
         sd.rowitems = (const RowItem*)(d + o_rows);
         *out = sp;
@@ -743,14 +735,14 @@ int32_t gbmc_sites_n_candidates(const gbmc_sites* s) { return s ? s->n_cand : 0;
 
 size_t gbmc_sites_workspace_bytes(const gbmc_sites* s)
 {
-    return s ? align256(std::max<size_t>(8 * s->phi_part_len, 8)) : 0;
+    return s ? align256(std::max<size_t>(8 * s->n_site_atoms, 8)) : 0;
 }
 
 static gbmc_status check_sites(const gbmc_plan* p, const gbmc_sites* s, const void* sws)
 {
     if (!s) return fail(GBMC_ERR_INVALID, "sites is NULL");
     if (s->plan != p) return fail(GBMC_ERR_INVALID, "sites were created for another plan");
-    if (s->phi_part_len > 0 && !sws) return fail(GBMC_ERR_INVALID, "site workspace is NULL");
+    if (s->n_site_atoms > 0 && !sws) return fail(GBMC_ERR_INVALID, "site workspace is NULL");
     return GBMC_OK;
 }
 
@@ -771,12 +763,12 @@ gbmc_status mc_state_dE(gbmc_plan* p, const gbmc_sites* s, const gbmc_atoms* a,
     hipError_t e;
     if (p->prec == GBMC_FP32_FIXED)
         e = launch_state_dE<float>(s->dev, p->n_atoms, (const float*)a->x, (const float*)a->y, (const float*)a->z,
-                                   (const float*)a->q, c, carve<float>(p, ws), (double*)sws,
+                                   (const float*)a->q, c, carve<float>(p, ws), (unsigned long long*)sws,
                                    current_state, pH, E_volt, T, dE, dG, stream, ev);
     else
         e = launch_state_dE<double>(s->dev, p->n_atoms, (const double*)a->x, (const double*)a->y,
                                     (const double*)a->z, (const double*)a->q, c, carve<double>(p, ws),
-                                    (double*)sws, current_state, pH, E_volt, T, dE, dG, stream, ev);
+                                    (unsigned long long*)sws, current_state, pH, E_volt, T, dE, dG, stream, ev);
     return e == hipSuccess ? GBMC_OK : hip_fail(e, "mc_state_dE launch");
 }
 

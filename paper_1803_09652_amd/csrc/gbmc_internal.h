@@ -9,12 +9,16 @@ namespace gbmc {
 constexpr int kTile = 64;                 // atoms per block; one wavefront per tile
 constexpr int kMaxSiteAtoms = 256;
 constexpr int kMaxStates = 8;
-constexpr int kPhiChunk = 64;             // j atoms per FP64 potential-row work item
+#ifndef GBMC_PHI_CHUNK
+#define GBMC_PHI_CHUNK 32
+#endif
+constexpr int kPhiChunk = GBMC_PHI_CHUNK;            // j atoms per FP64 potential-row work item
 
 // Fixed-point scales (powers of two, so scaling is exact).
 constexpr double kScaleI = 4503599627370496.0;   // 2^52: descreening sums, 1/A
 constexpr double kScaleF = 1099511627776.0;      // 2^40: forces, dE/dR, dE/dq, dE/drho
 constexpr double kScaleE = 4294967296.0;         // 2^32: energies
+constexpr double kScaleP = 17592186044416.0;     // 2^44: FP64 site-atom potentials
 constexpr double kFixLimit = 4611686018427387904.0;  // 2^62
 
 template <typename T>
@@ -29,15 +33,17 @@ struct WorkItem {
 };
 
 // One FP64 potential-row work item: up to 64 site atoms [sa0, sa1) of one system
-// against the system's atoms [j0, j1); the partial sums go to phi_part[out + k].
+// against the system's atoms [j0, j1); each lane adds its partial sum in fixed
+// point to phi_fx[out + k] (the flattened site-atom slot).
 struct RowItem {
     int32_t base, n, sa0, sa1, j0, j1, out, pad;
 };
 
-// One atom as the FP64 Monte Carlo kernels read it (caller order): a 64-byte
-// record, so a wave-uniform read is one scalar 64-byte load.
+// One atom as the FP64 Monte Carlo kernels read it (caller order; written by
+// the radii pass): a 64-byte record, so a wave-uniform read is one scalar
+// 64-byte load.
 struct alignas(64) Row64 {
-    double x, y, z, q, R, A, pad0, pad1;   // A = 1 / (2 R)
+    double x, y, z, R, A, pad0, pad1, pad2;   // A = 1 / (2 R)
 };
 
 // Device pointers carved from the caller's workspace.  Per-atom arrays marked
@@ -73,6 +79,7 @@ struct Work {
 
 struct SiteDev {
     int32_t n_sites, n_cand, n_rowitems;
+    int32_t n_site_atoms;             // flattened site-atom slots (site_atom_offset[S])
     const int32_t* site_system;
     const int32_t* site_kind;
     const int32_t* site_atom_offset;
@@ -88,8 +95,6 @@ struct SiteDev {
     const int32_t* sys_redox_offset;  // [B+1]
     const int32_t* sys_redox_sites;
     const int32_t* site_sa_offset;    // [S+1]: first flattened site-atom slot of each site
-    const int32_t* site_chunks;       // [S]: potential-row chunks of the site's system
-    const int32_t* site_phi_offset;   // [S]: first phi_part slot of the site's system
     const int32_t* sys_sa_offset;     // [B+1]
     const RowItem* rowitems;
 };
@@ -128,7 +133,7 @@ hipError_t launch_energy_forces(const PassShape& energy, const PassShape& chain,
                                 hipStream_t s, hipEvent_t* ev);
 template <typename T>
 hipError_t launch_state_dE(const SiteDev& sd, int n_atoms, const T* x, const T* y, const T* z,
-                           const T* q, const GBConst& c, const Work<T>& w, double* phi_part,
+                           const T* q, const GBConst& c, const Work<T>& w, unsigned long long* phi_fx,
                            const int32_t* current_state, const double* pH, const double* E_volt,
                            double T_kelvin, double* dE, double* dG, hipStream_t s,
                            hipEvent_t* ev);

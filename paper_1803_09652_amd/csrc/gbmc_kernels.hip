@@ -236,39 +236,61 @@ __device__ __forceinline__ void radii_pair(double xi, double yi, double zi, doub
     hji = hct_general(r, invr, rtj, Si);
 }
 
-// Pass-3 pair: dH/dr, dH/drt, dH/dS in both directions (same split).
-__device__ __forceinline__ void chain_pair_grads(float xi, float yi, float zi, float xj, float yj,
-                                                 float zj, float r, float invr, float rti, float Si,
-                                                 float rtj, float Sj, float* gij, float* gji)
+// Pass-3 pair terms with the Born chain weights bi = B_i rt_i, bj = B_j rt_j
+// applied: dEdr = bi dH(r; rt_i, S_j)/dr + bj dH(r; rt_j, S_i)/dr, the S
+// derivatives gij2 = dH(r; rt_i, S_j)/dS and gji2 = dH(r; rt_j, S_i)/dS, and
+// the rt derivatives, nonzero only for overlapping pairs, added as
+// dri += bi dH(r; rt_i, S_j)/drt and drj += bj dH(r; rt_j, S_i)/drt.
+// FP32: non-overlapping directions use the polynomial form,
+//   dH/dr = -x^3 (P + (1 - y)^-2) / r^2,  dH/dS = y (1 - y)^-2 / r^2,
+// with the common 1/r^2 of the two dH/dr applied once.
+__device__ __forceinline__ void chain_pair(float r, float r2, float invr, float rti, float Si,
+                                           float rtj, float Sj, float bi, float bj, float& dEdr,
+                                           float& gij2, float& gji2, float& dri, float& drj)
 {
-    float invr2 = invr * invr;
-    float xij = Sj * invr, yij = xij * xij;
-    float xji = Si * invr, yji = xji * xji;
-    // non-overlapping: dH/dr = -x^3 (P + 1/(1-y)^2) / r^2,  dH/dS = y/((1-y)^2 r^2)
+    const float u = invr * invr;
+    const float xij = Sj * invr, yij = xij * xij;
+    const float xji = Si * invr, yji = xji * xji;
     float wij = rcp(1.0f - yij), wji = rcp(1.0f - yji);
     wij *= wij;
     wji *= wji;
-    gij[0] = -xij * yij * invr2 * (hct_poly(yij) + wij);
-    gij[1] = 0.0f;
-    gij[2] = yij * wij * invr2;
-    gji[0] = -xji * yji * invr2 * (hct_poly(yji) + wji);
-    gji[1] = 0.0f;
-    gji[2] = yji * wji * invr2;
-    bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX);
-    bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX);
+    float aij = xij * yij * (hct_poly(yij) + wij);     // -r^2 dH/dr
+    float aji = xji * yji * (hct_poly(yji) + wji);
+    gij2 = yij * wij * u;
+    gji2 = yji * wji * u;
+    const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX);
+    const bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX);
     if (!(f_ij & f_ji)) {
-        if (!f_ij) hct_slow32<true>(r, invr, rti, Sj, gij);
-        if (!f_ji) hct_slow32<true>(r, invr, rtj, Si, gji);
+        float g[3];
+        if (!f_ij) {
+            hct_slow32<true>(r, invr, rti, Sj, g);
+            aij = -g[0] * r2;
+            gij2 = g[2];
+            dri = fmaf(bi, g[1], dri);
+        }
+        if (!f_ji) {
+            hct_slow32<true>(r, invr, rtj, Si, g);
+            aji = -g[0] * r2;
+            gji2 = g[2];
+            drj = fmaf(bj, g[1], drj);
+        }
     }
+    dEdr = -u * fmaf(bi, aij, bj * aji);
 }
 
-__device__ __forceinline__ void chain_pair_grads(double xi, double yi, double zi, double xj,
-                                                 double yj, double zj, double r, double invr,
-                                                 double rti, double Si, double rtj, double Sj,
-                                                 double* gij, double* gji)
+__device__ __forceinline__ void chain_pair(double r, double r2, double invr, double rti, double Si,
+                                           double rtj, double Sj, double bi, double bj,
+                                           double& dEdr, double& gij2, double& gji2, double& dri,
+                                           double& drj)
 {
+    double gij[3], gji[3];
     hct_general_grad(r, invr, rti, Sj, gij[0], gij[1], gij[2]);
     hct_general_grad(r, invr, rtj, Si, gji[0], gji[1], gji[2]);
+    dEdr = bi * gij[0] + bj * gji[0];
+    gij2 = gij[2];
+    gji2 = gji[2];
+    dri += bi * gij[1];
+    drj += bj * gji[1];
 }
 
 // ---------------------------------------------------------------- helpers
@@ -346,10 +368,14 @@ template <typename T>
 __global__ void k_stage(int n_atoms, const int32_t* __restrict__ perm, const T* __restrict__ X,
                         const T* __restrict__ Y, const T* __restrict__ Z, const T* __restrict__ Q,
                         const T* __restrict__ RHO, const T* __restrict__ SCR, T offset,
-                        Q4<T>* __restrict__ P, Q4<T>* __restrict__ Gx)
+                        Q4<T>* __restrict__ P, Q4<T>* __restrict__ Gx,
+                        unsigned long long* __restrict__ acc, int n_acc, int* __restrict__ ovf)
 {
     int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0 && ovf) *ovf = 0;
     if (k >= n_atoms) return;
+    // the pass's n_acc fixed-point accumulators of atom k ([n_acc][N]) start at zero
+    for (int a = 0; a < n_acc; ++a) acc[(size_t)a * n_atoms + k] = 0ull;
     int c = perm[k];
     Q4<T> p;
     p.x = X[c]; p.y = Y[c]; p.z = Z[c];
@@ -474,6 +500,13 @@ __global__ void k_radii_finalize(int n_atoms, const T* __restrict__ RHO, GBConst
     w.dRdPsi64[g] = R * R * (1.0 - t * t) * (c.alpha - 2.0 * c.beta * psi + 3.0 * c.gamma * psi * psi) / rho;
     w.R_t[k] = (T)R;
     w.a_t[k] = (T)(kAScale / R);
+    // FP64 record of the atom for the Monte Carlo kernels (caller order)
+    const Q4<T> p = w.P[k];
+    Row64 row;
+    row.x = (double)p.x; row.y = (double)p.y; row.z = (double)p.z;
+    row.R = R; row.A = 0.5 / R;
+    row.pad0 = row.pad1 = row.pad2 = 0.0;
+    w.rows[g] = row;
     if (born_R) born_R[g] = (T)R;
 }
 
@@ -750,19 +783,18 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
             T r2 = dx * dx + dy * dy + dz * dz;
             T invr = rsq(r2);
             T r = r2 * invr;
-            T gij[3], gji[3];
-            chain_pair_grads(xi, yi, zi, p.x, p.y, p.z, r, invr, rti, Si, p.w, b.x, gij, gji);
-            T bj_ = act ? b.y : T(0);
-            T bi_ = act ? Bi : T(0);
-            T dEdr = bi_ * gij[0] + bj_ * gji[0];
+            const T bj_ = act ? b.y : T(0);
+            const T bi_ = act ? Bi : T(0);
+            T dEdr, gij2, gji2;
+            chain_pair(r, r2, invr, rti, Si, p.w, b.x, bi_, bj_, dEdr, gij2, gji2, dri, acc[3]);
             T fr = dEdr * invr;
             T fx = fr * dx, fy = fr * dy, fz = fr * dz;
             fxi -= fx; fyi -= fy; fzi -= fz;
-            dri += bi_ * gij[1] + si * bj_ * gji[2];
+            dri += si * bj_ * gji2;
             acc[0] += fx;
             acc[1] += fy;
             acc[2] += fz;
-            acc[3] += bj_ * gji[1] + b.z * bi_ * gij[2];
+            acc[3] += b.z * bi_ * gij2;
         });
         {
             const int g = w.base + clamp_atom(j, w.n);
@@ -817,17 +849,11 @@ __global__ void k_grad_finalize(int n_atoms, const T* __restrict__ RHO, double o
     }
 }
 
-__global__ void k_zero64(unsigned long long* __restrict__ p, size_t n)
-{
-    size_t g = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (; g < n; g += stride) p[g] = 0ull;
-}
-
 // ============================================================ Monte Carlo
 // Delta E_elec needs the potential phi_i on every site atom in FP64: a row pass
-// over all atoms of the system, split in chunks written to phi_part and summed
-// in chunk order by k_site_dE (no atomics, deterministic).
+// over all atoms of the system, split in short chunks (many waves in flight);
+// each chunk's FP64 partial is added in 2^-44 fixed point, so the sum does not
+// depend on the order (deterministic) and k_site_dE reads one value per atom.
 
 // FP64 1/sqrt: hardware estimate refined by two Newton steps.
 __device__ __forceinline__ double rsq64(double x)
@@ -850,26 +876,13 @@ __device__ __forceinline__ double pairK(double dx, double dy, double dz, double 
     return kC * invr - kT * invf;
 }
 
-// FP64 records (x, y, z, q, R, 1/(2R)) of every atom, for the Monte Carlo kernels.
+// One lane per site atom; the j atoms of the chunk are wave-uniform records
+// (positions and radii of the last gb_radii call) and wave-uniform charges.
 template <typename T>
-__global__ void k_stage_rows(int n_atoms, const T* __restrict__ X, const T* __restrict__ Y,
-                             const T* __restrict__ Z, const T* __restrict__ Q,
-                             const double* __restrict__ R64, const double* __restrict__ A64,
-                             Row64* __restrict__ rows)
-{
-    int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n_atoms) return;
-    Row64 r;
-    r.x = X[g]; r.y = Y[g]; r.z = Z[g]; r.q = Q[g];
-    r.R = R64[g]; r.A = A64[g];
-    r.pad0 = r.pad1 = 0.0;
-    rows[g] = r;
-}
-
-// One lane per site atom; the j atoms of the chunk are wave-uniform records.
 __global__ __launch_bounds__(kTile) void k_site_phi_rows(
     const RowItem* __restrict__ items, const int32_t* __restrict__ site_atoms,
-    const Row64* __restrict__ rows, double kC, double kT, double* __restrict__ phi_part)
+    const Row64* __restrict__ rows, const T* __restrict__ Q, double kC, double kT,
+    unsigned long long* __restrict__ phi_fx, int* __restrict__ ovf)
 {
     const RowItem w = items[blockIdx.x];
     const int lane = threadIdx.x;
@@ -882,10 +895,20 @@ __global__ __launch_bounds__(kTile) void k_site_phi_rows(
     for (int j = w.j0; j < w.j1; ++j) {
         const int gj = w.base + j;
         const Row64 rj = rows[gj];
+        const double qj = (double)Q[gj];
         double K = pairK(ri.x - rj.x, ri.y - rj.y, ri.z - rj.z, ri.R, ri.A, rj.R, rj.A, kC, kT);
-        acc += (gj == gi) ? 0.0 : rj.q * K;
+        acc += (gj == gi) ? 0.0 : qj * K;
     }
-    if (v) phi_part[w.out + lane] = acc;
+    bool bad = false;
+    const long long f = to_fixed(acc, kScaleP, bad);
+    if (v) fx_add(&phi_fx[w.out + lane], f);
+    if (bad) *ovf = 1;
+}
+
+__global__ void k_clear64(unsigned long long* __restrict__ p, int n)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = 0ull;
 }
 
 // Deterministic sum of NV doubles over a 256-thread block: a fixed butterfly
@@ -918,7 +941,7 @@ template <typename T>
 __global__ __launch_bounds__(kMC) void k_site_dE(
     SiteDev sd, const T* __restrict__ X, const T* __restrict__ Y, const T* __restrict__ Z,
     const T* __restrict__ Q, const double* __restrict__ R64, const double* __restrict__ A64,
-    double kC, double kT, const double* __restrict__ phi_part,
+    double kC, double kT, const unsigned long long* __restrict__ phi_fx,
     const int32_t* __restrict__ current_state,
     const double* __restrict__ pH, const double* __restrict__ E_volt, double T_kelvin,
     double* __restrict__ dE, double* __restrict__ dG)
@@ -936,18 +959,14 @@ __global__ __launch_bounds__(kMC) void k_site_dE(
     const int ns = sd.site_state_offset[m + 1] - g0;
     const int cur = current_state[m];
     const int nc = ns - 1;
-    const int chunks = sd.site_chunks[m];
-    const int sa_sys0 = sd.sys_sa_offset[sd.site_system[m]];
     const int sa_site0 = sd.site_sa_offset[m];
-    const int n_sa_sys = sd.sys_sa_offset[sd.site_system[m] + 1] - sa_sys0;
     const double* qcur = sd.state_charges + sd.state_charge_offset[g0 + cur];
     for (int a = t; a < na; a += kMC) {
         int g = sd.site_atoms[a0 + a];
         double R = R64[g];
         sx[a] = X[g]; sy[a] = Y[g]; sz[a] = Z[g]; sR[a] = R; sA[a] = A64[g];
         double phi = -kT * (double)Q[g] / R;           // self term
-        const int slot = sa_site0 - sa_sys0 + a;
-        for (int c = 0; c < chunks; ++c) phi += phi_part[sd.site_phi_offset[m] + c * n_sa_sys + slot];
+        phi += (double)(long long)phi_fx[sa_site0 + a] * (1.0 / kScaleP);
         sphi[a] = phi;
         for (int c = 0; c < nc; ++c) {
             int s_new = c < cur ? c : c + 1;
@@ -1164,11 +1183,10 @@ hipError_t launch_radii(const WorkItem* items, int n_items, int wpg, int n_atoms
                         hipEvent_t* ev)
 {
     if (n_atoms == 0) return hipSuccess;
-    // I_fx and the overflow word right after it start every evaluation at zero
-    hipLaunchKernelGGL(k_zero64, dim3(blocks_for(n_atoms + 1, 256)), dim3(256), 0, s, w.I_fx,
-                       (size_t)n_atoms + 1);
+    // staging also clears I_fx and the overflow flag: every evaluation starts at zero
     hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms, w.perm,
-                       x, y, z, (const T*)nullptr, rho, screen, (T)c.offset, w.P, w.Gx);
+                       x, y, z, (const T*)nullptr, rho, screen, (T)c.offset, w.P, w.Gx, w.I_fx, 1,
+                       w.ovf);
     if (n_items > 0) {
         GBMC_DISPATCH_W(wpg, GBMC_LAUNCH_TIMED(ev, kKRadii, (k_radii_pairs<T, W>),
                                                dim3(blocks_for(n_items, W)), dim3(kTile * W), s,
@@ -1188,13 +1206,12 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
 {
     const bool grad = force || dEdq || dEdrho;
     const bool chain = force || dEdrho;
-    // F, G, phi, drho and the per-atom energy shares are one contiguous run of 8N
-    const size_t nz = (size_t)8 * n_atoms;
-    if (nz) hipLaunchKernelGGL(k_zero64, dim3(blocks_for(nz, 256)), dim3(256), 0, s, w.F_fx, nz);
-    // positions and charges as given to this call, in processing order
+    // positions and charges as given to this call, in processing order; F, G,
+    // phi, drho and the two energy shares ([8][N] from F_fx on) cleared alongside
     if (n_atoms > 0)
         hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
-                           w.perm, x, y, z, q, rho, screen, (T)c.offset, w.P, w.Gx);
+                           w.perm, x, y, z, q, rho, screen, (T)c.offset, w.P, w.Gx, w.F_fx, 8,
+                           (int*)nullptr);
     if (pe.n_items > 0) {
         if (grad)
             GBMC_DISPATCH_W(pe.waves_per_group,
@@ -1229,19 +1246,19 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
 
 template <typename T>
 hipError_t launch_state_dE(const SiteDev& sd, int n_atoms, const T* x, const T* y, const T* z,
-                           const T* q, const GBConst& c, const Work<T>& w, double* phi_part,
+                           const T* q, const GBConst& c, const Work<T>& w, unsigned long long* phi_fx,
                            const int32_t* current_state, const double* pH, const double* E_volt,
                            double T_kelvin, double* dE, double* dG, hipStream_t s, hipEvent_t* ev)
 {
     if (sd.n_sites == 0) return hipSuccess;
     if (sd.n_rowitems > 0) {
-        hipLaunchKernelGGL(k_stage_rows<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
-                           x, y, z, q, w.R64, w.A64, w.rows);
-        GBMC_LAUNCH_TIMED(ev, kKSiteRows, k_site_phi_rows, dim3(sd.n_rowitems), dim3(kTile), s,
-                          sd.rowitems, sd.site_atoms, w.rows, c.kC, c.kT, phi_part);
+        hipLaunchKernelGGL(k_clear64, dim3(blocks_for(sd.n_site_atoms, 256)), dim3(256), 0, s, phi_fx,
+                           sd.n_site_atoms);
+        GBMC_LAUNCH_TIMED(ev, kKSiteRows, k_site_phi_rows<T>, dim3(sd.n_rowitems), dim3(kTile), s,
+                          sd.rowitems, sd.site_atoms, w.rows, q, c.kC, c.kT, phi_fx, w.ovf);
     }
     GBMC_LAUNCH_TIMED(ev, kKSiteDE, k_site_dE<T>, dim3(sd.n_sites), dim3(kMC), s, sd, x, y, z, q,
-                      w.R64, w.A64, c.kC, c.kT, phi_part, current_state, pH, E_volt, T_kelvin, dE,
+                      w.R64, w.A64, c.kC, c.kT, phi_fx, current_state, pH, E_volt, T_kelvin, dE,
                       dG);
     return hipGetLastError();
 }
@@ -1282,7 +1299,8 @@ hipError_t launch_remd_exchange(int M, const double* E_rung, const int32_t* Ne, 
                                                 double*, double*, T*, T*, T*, hipStream_t,       \
                                                 hipEvent_t*);                                    \
     template hipError_t launch_state_dE<T>(const SiteDev&, int, const T*, const T*, const T*,    \
-                                           const T*, const GBConst&, const Work<T>&, double*,    \
+                                           const T*, const GBConst&, const Work<T>&,             \
+                                           unsigned long long*,                                  \
                                            const int32_t*, const double*, const double*, double, \
                                            double*, double*, hipStream_t, hipEvent_t*);          \
     template hipError_t launch_mc_step<T>(const SiteDev&, int, const T*, const T*, const T*, T*, \
