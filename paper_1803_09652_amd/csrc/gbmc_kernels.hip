@@ -911,11 +911,11 @@ __global__ void k_clear64(unsigned long long* __restrict__ p, int n)
     if (k < n) p[k] = 0ull;
 }
 
-// Deterministic sum of NV doubles over a 256-thread block: a fixed butterfly
-// inside each wavefront, then the four wave sums in wave order.  Every thread
-// receives the totals.
-template <int NV>
-__device__ void block_sum(double (*buf)[4], double* v)
+// Deterministic sum of NV doubles over a block of NW wavefronts: a fixed
+// butterfly inside each wavefront, then the wave sums in wave order.  Every
+// thread receives the totals.
+template <int NV, int NW>
+__device__ void block_sum(double (*buf)[NW], double* v)
 {
     const int t = threadIdx.x, lane = t % kTile, wave = t / kTile;
 #pragma unroll
@@ -930,15 +930,24 @@ __device__ void block_sum(double (*buf)[4], double* v)
         for (int a = 0; a < NV; ++a) buf[a][wave] = v[a];
     }
     __syncthreads();
+    // thread a adds the wave sums of value a in wave order
+    if (t < NV) {
+        double x = buf[t][0];
+#pragma unroll 1
+        for (int k = 1; k < NW; ++k) x += buf[t][k];
+        buf[t][0] = x;
+    }
+    __syncthreads();
 #pragma unroll
-    for (int a = 0; a < NV; ++a) v[a] = ((buf[a][0] + buf[a][1]) + buf[a][2]) + buf[a][3];
+    for (int a = 0; a < NV; ++a) v[a] = buf[a][0];
     __syncthreads();
 }
 
-constexpr int kMC = 256;   // threads of the per-site / per-system Monte Carlo kernels
+constexpr int kMC = 256;    // threads of the per-system Monte Carlo step
+constexpr int kSDE = 1024;  // threads of the per-site Delta E kernel (16 waves on one CU)
 
 template <typename T>
-__global__ __launch_bounds__(kMC) void k_site_dE(
+__global__ __launch_bounds__(kSDE) void k_site_dE(
     SiteDev sd, const T* __restrict__ X, const T* __restrict__ Y, const T* __restrict__ Z,
     const T* __restrict__ Q, const double* __restrict__ R64, const double* __restrict__ A64,
     double kC, double kT, const unsigned long long* __restrict__ phi_fx,
@@ -950,7 +959,7 @@ __global__ __launch_bounds__(kMC) void k_site_dE(
     __shared__ double sA[kMaxSiteAtoms];
     __shared__ double sphi[kMaxSiteAtoms];
     __shared__ double sdq[kMaxStates - 1][kMaxSiteAtoms];
-    __shared__ double red[2 * (kMaxStates - 1)][4];
+    __shared__ double red[2 * (kMaxStates - 1)][kSDE / kTile];
     const int m = blockIdx.x;
     const int t = threadIdx.x;
     const int a0 = sd.site_atom_offset[m];
@@ -961,7 +970,7 @@ __global__ __launch_bounds__(kMC) void k_site_dE(
     const int nc = ns - 1;
     const int sa_site0 = sd.site_sa_offset[m];
     const double* qcur = sd.state_charges + sd.state_charge_offset[g0 + cur];
-    for (int a = t; a < na; a += kMC) {
+    for (int a = t; a < na; a += kSDE) {
         int g = sd.site_atoms[a0 + a];
         double R = R64[g];
         sx[a] = X[g]; sy[a] = Y[g]; sz[a] = Z[g]; sR[a] = R; sA[a] = A64[g];
@@ -978,15 +987,20 @@ __global__ __launch_bounds__(kMC) void k_site_dE(
 #pragma unroll
     for (int c = 0; c < 2 * (kMaxStates - 1); ++c) part[c] = 0.0;
     // linear term
-    for (int a = t; a < na; a += kMC) {
+    for (int a = t; a < na; a += kSDE) {
 #pragma unroll
         for (int c = 0; c < kMaxStates - 1; ++c)
             if (c < nc) part[c] += sdq[c][a] * sphi[a];
     }
-    // quadratic term: diagonal once, off-diagonal pairs twice
-    for (int p = t; p < na * na; p += kMC) {
-        int a = p / na, b = p - a * na;
-        if (b < a) continue;
+    // quadratic term over the triangle b >= a (diagonal once, off-diagonal
+    // pairs twice); triangle index p = b (b + 1) / 2 + a
+    const int n_tri = na * (na + 1) / 2;
+#pragma unroll 1
+    for (int p = t; p < n_tri; p += kSDE) {
+        int b = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+        b += (b + 1) * (b + 2) / 2 <= p;          // guard the rounding of the root
+        b -= b * (b + 1) / 2 > p;
+        const int a = p - b * (b + 1) / 2;
         double K = (a == b) ? -kT / sR[a]
                             : 2.0 * pairK(sx[a] - sx[b], sy[a] - sy[b], sz[a] - sz[b], sR[a], sA[a],
                                           sR[b], sA[b], kC, kT);
@@ -994,7 +1008,7 @@ __global__ __launch_bounds__(kMC) void k_site_dE(
         for (int c = 0; c < kMaxStates - 1; ++c)
             if (c < nc) part[kMaxStates - 1 + c] += sdq[c][a] * sdq[c][b] * K;
     }
-    block_sum<2 * (kMaxStates - 1)>(red, part);
+    block_sum<2 * (kMaxStates - 1), kSDE / kTile>(red, part);
     double lin = 0.0, quad = 0.0;
 #pragma unroll
     for (int c = 0; c < kMaxStates - 1; ++c)
@@ -1080,7 +1094,7 @@ __global__ __launch_bounds__(kMC) void k_mc_step(
                                      A64[gc], kC, kT);
                     part[0] += (qr1[a] - qr0[a]) * (qp1[c] - qp0[c]) * K;
                 }
-                block_sum<1>(red, part);
+                block_sum<1, kMC / kTile>(red, part);
                 dg += part[0];
             }
             acc_r = ub[5] < exp(-dg / kTB) ? 1 : 0;
@@ -1257,7 +1271,7 @@ hipError_t launch_state_dE(const SiteDev& sd, int n_atoms, const T* x, const T* 
         GBMC_LAUNCH_TIMED(ev, kKSiteRows, k_site_phi_rows<T>, dim3(sd.n_rowitems), dim3(kTile), s,
                           sd.rowitems, sd.site_atoms, w.rows, q, c.kC, c.kT, phi_fx, w.ovf);
     }
-    GBMC_LAUNCH_TIMED(ev, kKSiteDE, k_site_dE<T>, dim3(sd.n_sites), dim3(kMC), s, sd, x, y, z, q,
+    GBMC_LAUNCH_TIMED(ev, kKSiteDE, k_site_dE<T>, dim3(sd.n_sites), dim3(kSDE), s, sd, x, y, z, q,
                       w.R64, w.A64, c.kC, c.kT, phi_fx, current_state, pH, E_volt, T_kelvin, dE,
                       dG);
     return hipGetLastError();
