@@ -5,8 +5,11 @@ A step is one pass of the whole hot path over the E-REMD batch (16 replicas x
 2,500 atoms): Born radii, energy + forces + dE/dq + dE/drho (with the Born
 radius chain), Delta E / Delta G of every candidate state change, one
 protonation + redox Metropolis attempt per replica, and one replica-exchange
-attempt along the redox-potential ladder.  The step is captured in a HIP graph
-(two graphs: even and odd exchange parity) and replayed.
+attempt along the redox-potential ladder.  The Monte Carlo branch (it needs
+only the radii and the current charges) runs on a second stream beside the
+energy / force passes and writes its charge update into the other of two
+charge buffers.  The step is captured in a HIP graph (two graphs: even and odd
+exchange parity, which also alternate the charge buffers) and replayed.
 
 Prints ONE JSON line.  Pair interactions/s = sum_b N_b (N_b - 1)/2 per step
 divided by the step time.
@@ -46,6 +49,10 @@ def parse():
     ap.add_argument("--fp64-steps", type=int, default=20)
     ap.add_argument("--kernel-steps", type=int, default=50)
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-overlap", action="store_true",
+                    help="run the Monte Carlo branch on the main stream after the force passes "
+                         "(by default it runs on a second stream beside them, with "
+                         "double-buffered charges)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -61,7 +68,7 @@ def parse():
 class Workload:
     """Config-2 E-REMD batch resident on the GPU, with static step buffers."""
 
-    def __init__(self, precision, n_steps, order="spatial", tuning=None):
+    def __init__(self, precision, n_steps, order="spatial", tuning=None, overlap=True):
         import numpy as np
         import torch
         import paper_1803_09652_amd as g
@@ -76,6 +83,15 @@ class Workload:
             self.plan.set_order(g.spatial_order(b.atom_offset, b.x, b.y, b.z))
         self.atoms = g.Atoms.from_batch(self.plan, b)
         dev = self.plan.device
+        # with overlap, two charge buffers: a step reads one and writes the
+        # Monte Carlo update into the other (even steps A -> B, odd steps
+        # B -> A), so the Monte Carlo branch can run on a second stream beside
+        # the energy / force passes; without, one buffer updated in place
+        self.overlap = overlap
+        self.atoms_b = g.Atoms(self.plan, self.atoms.x, self.atoms.y, self.atoms.z,
+                               self.atoms.q.clone(), self.atoms.rho,
+                               self.atoms.screen) if overlap else self.atoms
+        self.side = torch.cuda.Stream(device=dev) if overlap else None
         self.params = g.IGB5
         self.T = 300.0
         self.E_rung = torch.as_tensor(synth.E_LADDER, dtype=torch.float64, device=dev)
@@ -114,13 +130,29 @@ class Workload:
         self.counters = torch.zeros((b.n_sites, 2), dtype=torch.int64, device=dev)
 
     def step(self, parity):
-        g, p = self.g, self.params
-        g.radii(self.plan, self.atoms, p)
-        ef = g.energy_forces(self.plan, self.atoms, p)
-        dE, dG = g.mc_state_dE(self.plan, self.sites, self.atoms, self.cur, self.pH, self.E_rep,
-                               self.T, p)
-        mc = g.mc_step(self.plan, self.sites, self.atoms, self.cur, self.pH, self.E_rep, dE, dG,
-                       self.u, self.T, p, counters=self.counters)
+        """One step; parity alternates from step to step (it selects the
+        exchange pairs and the charge buffer read)."""
+        g, p, torch = self.g, self.params, self.torch
+        cur, nxt = (self.atoms, self.atoms_b) if parity == 0 else (self.atoms_b, self.atoms)
+        main = torch.cuda.current_stream()
+        g.radii(self.plan, cur, p)
+        if not self.overlap:
+            ef = g.energy_forces(self.plan, cur, p)
+        mc_stream = self.side if self.overlap else main
+        if mc_stream is not main:
+            mc_stream.wait_stream(main)
+        with torch.cuda.stream(mc_stream):
+            # Monte Carlo branch: needs the radii and the current charges only
+            if nxt is not cur:
+                nxt.q.copy_(cur.q)
+            dE, dG = g.mc_state_dE(self.plan, self.sites, cur, self.cur, self.pH, self.E_rep,
+                                   self.T, p)
+            mc = g.mc_step(self.plan, self.sites, cur, self.cur, self.pH, self.E_rep, dE, dG,
+                           self.u, self.T, p, counters=self.counters, q_out=nxt.q)
+        if self.overlap:
+            ef = g.energy_forces(self.plan, cur, p)
+        if mc_stream is not main:
+            main.wait_stream(mc_stream)
         acc, E_new = g.remd_exchange(self.E_rung, mc["n_electrons"], self.rep_of_rung, parity,
                                      self.ux, self.T, True)
         self.E_rep.copy_(E_new)
@@ -142,12 +174,13 @@ def autotune(precision, order):
     return at.tune(b, precision, order=o, use_cache=False)
 
 
-def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial", tuning=None):
+def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial", tuning=None,
+            overlap=True):
     import torch
     n_total = steps + warmup + kernel_steps + 2
-    w = Workload(precision, n_total, order, tuning)
+    w = Workload(precision, n_total, order, tuning, overlap)
     torch.cuda.synchronize()
-    k = 0
+    k = 0       # steps done so far; step k has exchange parity k % 2
     graphs = None
     if use_graph:
         side = torch.cuda.Stream()
@@ -166,23 +199,23 @@ def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial", 
                 w.step(parity)
             graphs.append(gr)
 
-    def one(i):
+    def one():
         nonlocal k
         w.load_uniforms(k)
-        k += 1
         if graphs is not None:
-            graphs[i % 2].replay()
+            graphs[k % 2].replay()
         else:
-            w.step(i % 2)
+            w.step(k % 2)
+        k += 1
 
-    for i in range(warmup):
-        one(i)
+    for _ in range(warmup):
+        one()
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record()
-    for i in range(steps):
-        one(i)
+    for _ in range(steps):
+        one()
     ev1.record()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -193,10 +226,10 @@ def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial", 
     # region), read once as the mean per launch
     w.plan.set_timing(True)
     acc = torch.zeros((), dtype=torch.int64, device=w.plan.device)
-    for i in range(kernel_steps):
+    for _ in range(kernel_steps):
         w.load_uniforms(k)
+        w.step(k % 2)
         k += 1
-        w.step(i % 2)
         acc += w.last_exchange.sum()
     kernel_ms = w.plan.kernel_ms() if kernel_steps > 0 else {}
     w.plan.set_timing(False)
@@ -292,7 +325,8 @@ def main():
         del a, b
     tune32 = autotune("fp32", args.order) if args.autotune else None
     w, ms_step, wall_ms, kms = run_gpu("fp32", args.steps, args.warmup, use_graph, args.kernel_steps,
-                                       args.order, tune32["best"] if tune32 else None)
+                                       args.order, tune32["best"] if tune32 else None,
+                                       not args.no_overlap)
     pairs, n_cand = w.pairs, w.n_cand
     value = pairs / (ms_step * 1e-3)
     out = {
@@ -314,6 +348,8 @@ def main():
                         "no cutoff",
             "systems": w.B, "atoms": w.batch.n_atoms, "pairs_per_step": pairs,
             "candidates_per_step": n_cand, "hip_graph": use_graph, "atom_order": args.order,
+            "mc_branch": "second stream beside the force passes" if not args.no_overlap
+                         else "after the force passes",
             "tuning": ({"j_blocks_per_item": tune32["best"][0], "waves_per_group": tune32["best"][1],
                         "passes": "radii, energy, chain", "tuned_pair_ms": tune32["pair_ms"]}
                        if tune32 else "library default"),
@@ -346,7 +382,7 @@ def main():
     if not args.no_fp64:
         tune64 = autotune("fp64", args.order) if args.autotune else None
         w64, ms64, _, k64 = run_gpu("fp64", args.fp64_steps, 2, use_graph, 3, args.order,
-                                    tune64["best"] if tune64 else None)
+                                    tune64["best"] if tune64 else None, not args.no_overlap)
         v64 = pairs / (ms64 * 1e-3)
         out["fp64"] = {"value": v64, "ms_per_step": ms64, "steps": args.fp64_steps,
                        "kernel_ms": k64, "tuning": tune64["best"] if tune64 else None}

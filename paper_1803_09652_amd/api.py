@@ -311,10 +311,16 @@ def mc_state_dE(plan: Plan, sites: Sites, atoms: Atoms, current_state: torch.Ten
 
 def mc_step(plan: Plan, sites: Sites, atoms: Atoms, current_state: torch.Tensor, pH, E_volt,
             dE: torch.Tensor, dG: torch.Tensor, u: torch.Tensor, T: float = 300.0,
-            params: GBParams = IGB5, counters: Optional[torch.Tensor] = None) -> dict:
-    """One protonation + redox attempt pair per system; updates atoms.q and
-    current_state in place."""
+            params: GBParams = IGB5, counters: Optional[torch.Tensor] = None,
+            q_out: Optional[torch.Tensor] = None) -> dict:
+    """One protonation + redox attempt pair per system; updates current_state
+    in place and writes the accepted states' site charges into q_out (default
+    atoms.q).  Only those charges are written, so a separate q_out must already
+    hold the other charges (a copy of atoms.q)."""
     dev = plan.device
+    q_dst = atoms.q if q_out is None else q_out
+    if q_dst.dtype != plan.dtype or q_dst.shape != (plan.n_atoms,) or not q_dst.is_contiguous():
+        raise ValueError("q_out must be a contiguous [N] tensor of the plan dtype")
     if u.dtype != torch.float64 or u.shape != (plan.n_systems, 6):
         raise ValueError("u must be float64 [B, 6]")
     pH_t = _dev_f64(pH, plan.n_systems, dev)
@@ -322,7 +328,7 @@ def mc_step(plan: Plan, sites: Sites, atoms: Atoms, current_state: torch.Tensor,
     ne = torch.empty(plan.n_systems, dtype=torch.int32, device=dev)
     acc = torch.empty((plan.n_systems, 2), dtype=torch.int32, device=dev)
     a, p = atoms.c(), params.c()
-    L.check(L.load().mc_step(plan.handle, sites.handle, C.byref(a), _ptr(atoms.q), C.byref(p),
+    L.check(L.load().mc_step(plan.handle, sites.handle, C.byref(a), _ptr(q_dst), C.byref(p),
                              _ptr(plan.workspace), _ptr(sites.workspace), _ptr(current_state),
                              _ptr(pH_t), _ptr(E_t), float(T), _ptr(dE), _ptr(dG),
                              _ptr(u.contiguous()), _ptr(ne), _ptr(counters), _ptr(acc),

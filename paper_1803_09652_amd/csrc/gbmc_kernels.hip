@@ -876,28 +876,38 @@ __device__ __forceinline__ double pairK(double dx, double dy, double dz, double 
     return kC * invr - kT * invf;
 }
 
-// One lane per site atom; the j atoms of the chunk are wave-uniform records
-// (positions and radii of the last gb_radii call) and wave-uniform charges.
+// One lane per site atom.  The chunk's j atoms (positions and radii of the
+// last gb_radii call, current charges) are staged into LDS by the first
+// kPhiChunk lanes with one load each, then read as wave-uniform broadcasts.
 template <typename T>
 __global__ __launch_bounds__(kTile) void k_site_phi_rows(
     const RowItem* __restrict__ items, const int32_t* __restrict__ site_atoms,
     const Row64* __restrict__ rows, const T* __restrict__ Q, double kC, double kT,
     unsigned long long* __restrict__ phi_fx, int* __restrict__ ovf)
 {
+    __shared__ double2 s_xy[kPhiChunk], s_zR[kPhiChunk], s_Aq[kPhiChunk];
     const RowItem w = items[blockIdx.x];
     const int lane = threadIdx.x;
     const int sa = w.sa0 + lane;
     const bool v = sa < w.sa1;
     const int gi = v ? site_atoms[sa] : w.base;
+    const int nj = w.j1 - w.j0;                    // 1 .. kPhiChunk
+    if (lane < nj) {
+        const int gj = w.base + w.j0 + lane;
+        const Row64 r = rows[gj];
+        s_xy[lane] = make_double2(r.x, r.y);
+        s_zR[lane] = make_double2(r.z, r.R);
+        s_Aq[lane] = make_double2(r.A, (double)Q[gj]);
+    }
     const Row64 ri = rows[gi];
+    const int self = gi - (w.base + w.j0);         // this lane's own atom, if in the chunk
+    __syncthreads();
     double acc = 0.0;
 #pragma unroll 4
-    for (int j = w.j0; j < w.j1; ++j) {
-        const int gj = w.base + j;
-        const Row64 rj = rows[gj];
-        const double qj = (double)Q[gj];
-        double K = pairK(ri.x - rj.x, ri.y - rj.y, ri.z - rj.z, ri.R, ri.A, rj.R, rj.A, kC, kT);
-        acc += (gj == gi) ? 0.0 : qj * K;
+    for (int k = 0; k < nj; ++k) {
+        const double2 xy = s_xy[k], zR = s_zR[k], Aq = s_Aq[k];
+        double K = pairK(ri.x - xy.x, ri.y - xy.y, ri.z - zR.x, ri.R, ri.A, zR.y, Aq.x, kC, kT);
+        acc += (k == self) ? 0.0 : Aq.y * K;
     }
     bool bad = false;
     const long long f = to_fixed(acc, kScaleP, bad);
