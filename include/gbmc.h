@@ -100,16 +100,22 @@ const char* gbmc_last_error(void);
 gbmc_status gbmc_params_validate(const gbmc_gb_params* params);
 
 /* Host-only: the pair-tile work list a plan with this layout would use for a
- * pass walking j_blocks_per_item j blocks per item (>= 1).
+ * pass walking j_blocks_per_item j blocks per item (>= 1); row_pairs != 0
+ * gives the schedule of the FP32 plans' energy pass, 0 that of every other
+ * pass.
  * host_atom_offset[n_systems+1] (host) must start at 0 and be non-decreasing.
- * Each item covers, for one system, the 64-atom i block I against the j
- * blocks [J0, J1) with J0 >= I (every unordered pair of atoms lies in exactly
- * one tile, the diagonal tile I == J holding the pairs inside one block).
- * Items are ordered by decreasing cost.  *n_items receives the count; if items
- * (host) is not NULL it receives 4 int32 per item: system, I, J0, J1 (the
- * caller sizes it from a first call with items == NULL). */
+ * Each item covers, for one system, the 64-atom i blocks [I0, I1) (one or
+ * two) against the j blocks [J0, J1), J0 >= I0 (every unordered pair of atoms
+ * lies in exactly one tile, the diagonal tile I == J holding the pairs inside
+ * one block).  With row_pairs the i blocks are paired (2a, 2a + 1): two-row
+ * items cover the pair against J >= 2a + 2, one-row items the diagonal band
+ * and an unpaired last block; without, every item has one i block.  Items are
+ * ordered by decreasing cost.  *n_items receives the count; if items (host) is
+ * not NULL it receives 5 int32 per item: system, I0, I1, J0, J1 (the caller
+ * sizes it from a first call with items == NULL). */
 gbmc_status gbmc_schedule_build(int32_t n_systems, const int32_t* host_atom_offset,
-                                int32_t j_blocks_per_item, int32_t* n_items, int32_t* items);
+                                int32_t j_blocks_per_item, int32_t row_pairs, int32_t* n_items,
+                                int32_t* items);
 
 /* Create a plan for a batch of n_systems systems laid out back to back:
  * system b owns atoms [host_atom_offset[b], host_atom_offset[b+1]) (host array,

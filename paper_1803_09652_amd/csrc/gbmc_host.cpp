@@ -93,28 +93,49 @@ static gbmc_status check_offsets(int32_t n_systems, const int32_t* off)
     return GBMC_OK;
 }
 
-static gbmc_status build_items(int32_t n_systems, const int32_t* off, int32_t jb,
+// With row_pairs, the i blocks of a system are taken in pairs (2a, 2a + 1):
+// the tiles of the pair against j blocks J >= 2a + 2 form two-row items; the
+// diagonal band (2a, 2a), (2a, 2a + 1), (2a + 1, 2a + 1) and an unpaired last
+// block form one-row items.  Without, every i block has one-row items.  Each
+// run of j blocks is cut into items of at most jb blocks.
+static gbmc_status build_items(int32_t n_systems, const int32_t* off, int32_t jb, bool row_pairs,
                                std::vector<WorkItem>& items)
 {
     items.clear();
+    auto add = [&](int32_t b, int32_t rows, int32_t I, int32_t J0, int32_t J1) {
+        for (int32_t j = J0; j < J1; j += jb) {
+            WorkItem w{};
+            w.base = off[b];
+            w.n = off[b + 1] - off[b];
+            w.sys = b;
+            w.I = I;
+            w.J0 = j;
+            w.J1 = std::min(J1, j + jb);
+            w.rows = rows;
+            items.push_back(w);
+        }
+    };
     for (int32_t b = 0; b < n_systems; ++b) {
-        const int32_t n = off[b + 1] - off[b];
-        const int32_t nb = (n + kTile - 1) / kTile;
-        for (int32_t I = 0; I < nb; ++I)
-            for (int32_t J0 = I; J0 < nb; J0 += jb) {
-                WorkItem w{};
-                w.base = off[b];
-                w.n = n;
-                w.sys = b;
-                w.I = I;
-                w.J0 = J0;
-                w.J1 = std::min(nb, J0 + jb);
-                items.push_back(w);
+        const int32_t nb = (off[b + 1] - off[b] + kTile - 1) / kTile;
+        if (!row_pairs) {
+            for (int32_t I = 0; I < nb; ++I) add(b, 1, I, I, nb);
+            continue;
+        }
+        for (int32_t a = 0; a < nb; a += 2) {
+            if (a + 1 < nb) {
+                add(b, 1, a, a, a + 2);
+                add(b, 1, a + 1, a + 1, a + 2);
+                add(b, 2, a, a + 2, nb);
+            } else {
+                add(b, 1, a, a, a + 1);
             }
+        }
     }
-    // longest first (a diagonal tile costs half an off-diagonal one); ties keep
-    // the construction order so the schedule is deterministic
-    auto cost = [](const WorkItem& w) { return 2 * (w.J1 - w.J0) - (w.J0 == w.I ? 1 : 0); };
+    // longest first (in half tiles: a diagonal tile costs half an off-diagonal
+    // one); ties keep the construction order so the schedule is deterministic
+    auto cost = [](const WorkItem& w) {
+        return 2 * w.rows * (w.J1 - w.J0) - (w.J0 == w.I ? 1 : 0);
+    };
     std::stable_sort(items.begin(), items.end(),
                      [&](const WorkItem& a, const WorkItem& b) { return cost(a) > cost(b); });
     return GBMC_OK;
@@ -248,7 +269,8 @@ gbmc_status gbmc_params_validate(const gbmc_gb_params* p)
 }
 
 gbmc_status gbmc_schedule_build(int32_t n_systems, const int32_t* host_atom_offset,
-                                int32_t j_blocks_per_item, int32_t* n_items, int32_t* items)
+                                int32_t j_blocks_per_item, int32_t row_pairs, int32_t* n_items,
+                                int32_t* items)
 {
     try {
         if (!n_items) return fail(GBMC_ERR_INVALID, "n_items is NULL");
@@ -257,15 +279,16 @@ gbmc_status gbmc_schedule_build(int32_t n_systems, const int32_t* host_atom_offs
         if (j_blocks_per_item < 1 || j_blocks_per_item > 65535)
             return fail(GBMC_ERR_INVALID, "j_blocks_per_item must be in [1, 65535]");
         std::vector<WorkItem> v;
-        build_items(n_systems, host_atom_offset, j_blocks_per_item, v);
+        build_items(n_systems, host_atom_offset, j_blocks_per_item, row_pairs != 0, v);
         if (v.size() > 0x7fffffff) return fail(GBMC_ERR_UNSUPPORTED, "too many work items");
         *n_items = (int32_t)v.size();
         if (items)
             for (size_t k = 0; k < v.size(); ++k) {
-                items[4 * k + 0] = v[k].sys;
-                items[4 * k + 1] = v[k].I;
-                items[4 * k + 2] = v[k].J0;
-                items[4 * k + 3] = v[k].J1;
+                items[5 * k + 0] = v[k].sys;
+                items[5 * k + 1] = v[k].I;
+                items[5 * k + 2] = v[k].I + v[k].rows;
+                items[5 * k + 3] = v[k].J0;
+                items[5 * k + 4] = v[k].J1;
             }
         return GBMC_OK;
     } catch (const std::exception& e) {
@@ -288,7 +311,8 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
         if (st != GBMC_OK) return st;
         std::vector<WorkItem> items[GBMC_N_PASSES];
         for (int k = 0; k < GBMC_N_PASSES; ++k)
-            build_items(n_systems, host_atom_offset, t.j_blocks_per_item[k], items[k]);
+            build_items(n_systems, host_atom_offset, t.j_blocks_per_item[k],
+                        precision == GBMC_FP32_FIXED && k == GBMC_PASS_ENERGY, items[k]);
         auto* p = new gbmc_plan();
         p->n_sys = n_systems;
         p->n_atoms = n_systems > 0 ? host_atom_offset[n_systems] : 0;

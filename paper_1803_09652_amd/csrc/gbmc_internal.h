@@ -26,10 +26,11 @@ struct alignas(4 * sizeof(T)) Q4 {
     T x, y, z, w;
 };
 
-// One pair work item: system `sys` (atoms [base, base+n)), i block I, j blocks
-// [J0, J1) with J0 >= I.
+// One pair work item: system `sys` (atoms [base, base+n)), the `rows` (1 or 2)
+// i blocks [I, I + rows), j blocks [J0, J1) with J0 >= I (J0 >= I + 2 for two
+// rows).
 struct WorkItem {
-    int32_t base, n, sys, I, J0, J1, pad0, pad1;
+    int32_t base, n, sys, I, J0, J1, rows, pad;
 };
 
 // One FP64 potential-row work item: up to 64 site atoms [sa0, sa1) of one system

@@ -314,10 +314,10 @@ __device__ __forceinline__ void wave_sync()
 }
 
 // Walks the steps of one tile.  load(s) fetches the j data at LDS slot s;
-// pair(d, act, acc_j) evaluates the pair of this lane with that j and adds the
-// j-side terms to acc_j (NJ sums); act is false only for the lanes that must
-// skip a duplicated pair.  The j data of step k + 1 is fetched before step k
-// is evaluated.  On return acc_j of lane l holds the sums of j = 64 J + l.
+// pair(d, r, act, acc_j) evaluates the pair of this lane's i row r with that j
+// and adds the j-side terms to acc_j (NJ sums); act is false only for the
+// lanes that must skip a duplicated pair.  On return acc_j of lane l holds the
+// sums of j = 64 J + l.
 template <typename T, int NJ, class Load, class Pair>
 __device__ __forceinline__ void walk_tile(int lane, bool diagonal, T (&acc_j)[NJ], Load&& load,
                                           Pair&& pair)
@@ -325,7 +325,7 @@ __device__ __forceinline__ void walk_tile(int lane, bool diagonal, T (&acc_j)[NJ
 #pragma unroll
     for (int a = 0; a < NJ; ++a) acc_j[a] = T(0);
     auto step = [&](const auto& d, bool valid) {
-        pair(d, valid, acc_j);
+        pair(d, 0, valid, acc_j);
 #pragma unroll
         for (int a = 0; a < NJ; ++a) acc_j[a] = rot1(acc_j[a]);
     };
@@ -352,10 +352,33 @@ __device__ __forceinline__ void walk_tile(int lane, bool diagonal, T (&acc_j)[NJ
         }
         auto b = load(lane + kTile / 2);
         step(a, true);
-        pair(b, lane < kTile / 2, acc_j);
+        pair(b, 0, lane < kTile / 2, acc_j);
         // lane l now holds j = l + 32; j = l sits in lane (l - 32) mod 64
 #pragma unroll
         for (int a = 0; a < NJ; ++a) acc_j[a] = from_lane(acc_j[a], (lane + kTile / 2) & (kTile - 1));
+    }
+}
+
+// The same walk for a two-row item (no diagonal): every j serves the pairs of
+// both i rows of the lane before the j sums move on.
+template <typename T, int NJ, class Load, class Pair>
+__device__ __forceinline__ void walk_tile_rows2(int lane, T (&acc_j)[NJ], Load&& load, Pair&& pair)
+{
+#pragma unroll
+    for (int a = 0; a < NJ; ++a) acc_j[a] = T(0);
+    auto step = [&](const auto& d) {
+        pair(d, 0, true, acc_j);
+        pair(d, 1, true, acc_j);
+#pragma unroll
+        for (int a = 0; a < NJ; ++a) acc_j[a] = rot1(acc_j[a]);
+    };
+    auto a = load(lane);
+#pragma unroll 1
+    for (int k = 0; k < kTile; k += 2) {
+        auto b = load(lane + k + 1);
+        step(a);
+        a = load(lane + k + 2);                 // slot <= 127: inside the doubled block
+        step(b);
     }
 }
 
@@ -392,34 +415,37 @@ __global__ void k_stage(int n_atoms, const int32_t* __restrict__ perm, const T* 
 // ================================================================ pass 1
 // I_i = sum_{j != i} H(r_ij; rt_i, S_j) over every unordered pair once.
 
-template <typename T, int W>
-__global__ __launch_bounds__(kTile * W) void k_radii_pairs(
-    const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
-    const Q4<T>* __restrict__ Gx, unsigned long long* __restrict__ I_fx, int* __restrict__ ovf)
+// One work item: R (1 or 2) consecutive 64-atom i blocks [I, I + R) against
+// the j blocks [J0, J1) of one system.  Two-row items hold no diagonal tile
+// (J0 >= I + 2): every j read from LDS serves two pairs per lane and the j
+// sums move once per two pairs.  Every (i row, j block) tile is rounded into
+// fixed point on its own on the i side; the j side of a two-row item rounds
+// the sum of its two tiles, the same for every work shape.
+template <typename T, int R>
+__device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* sj, T* sS,
+                                           const Q4<T>* __restrict__ P,
+                                           const Q4<T>* __restrict__ Gx,
+                                           unsigned long long* __restrict__ I_fx,
+                                           int* __restrict__ ovf)
 {
-    __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, rt
-    __shared__ T sS_w[W][2 * kTile];
-    const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
-    const int item = blockIdx.x * W + wave;
-    if (item >= n_items) return;
-    Q4<T>* sj = sj_w[wave];
-    T* sS = sS_w[wave];
-    const WorkItem w = items[item];
-    const int i = w.I * kTile + lane;
-    const bool vi = i < w.n;
-    T xi, yi, zi, rti, Si;
-    if (vi) {
-        const Q4<T> p = P[w.base + i];
-        const Q4<T> gx = Gx[w.base + i];
-        xi = p.x; yi = p.y; zi = p.z;
-        rti = gx.x;
-        Si = gx.y;
-    } else {
-        dummy_pos(i, xi, yi, zi);
-        rti = T(1);
-        Si = T(0);
+    T xi[R], yi[R], zi[R], rti[R], Si[R];
+    bool vi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = (w.I + r) * kTile + lane;
+        vi[r] = i < w.n;
+        if (vi[r]) {
+            const Q4<T> p = P[w.base + i];
+            const Q4<T> gx = Gx[w.base + i];
+            xi[r] = p.x; yi[r] = p.y; zi[r] = p.z;
+            rti[r] = gx.x;
+            Si[r] = gx.y;
+        } else {
+            dummy_pos(i, xi[r], yi[r], zi[r]);
+            rti[r] = T(1);
+            Si[r] = T(0);
+        }
     }
-    // j block data, fetched one block ahead
     // loads of a j block (raw), and the stand-in values of lanes past the end,
     // applied only when the block is written to LDS so the loads stay in flight
     auto fetch = [&](int J, Q4<T>& pj, Q4<T>& gj) {
@@ -437,12 +463,14 @@ __global__ __launch_bounds__(kTile * W) void k_radii_pairs(
             Sj = T(0);
         }
     };
-    long long ifix = 0;
+    long long ifix[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) ifix[r] = 0;
     bool bad = false;
     Q4<T> pj, gj;
     fetch(w.J0, pj, gj);
-    // one 64 x 64 tile; the first is peeled so that the loop is entered, as
-    // on every later trip, with the previous tile's sums still in flight
+    // one tile; the first is peeled so that the loop is entered, as on every
+    // later trip, with the previous tile's sums still in flight
     auto tile = [&](int J) {
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
@@ -455,25 +483,50 @@ __global__ __launch_bounds__(kTile * W) void k_radii_pairs(
         sS[lane + kTile] = Sj;
         wave_sync();
         fetch(J + 1 < w.J1 ? J + 1 : J, pj, gj);     // the last trip re-reads J
-        T ai = T(0);
+        T ai[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) ai[r] = T(0);
         T aj[1];
         struct JD { Q4<T> p; T S; };
-        walk_tile<T, 1>(
-            lane, J == w.I, aj, [&](int s) { return JD{sj[s], sS[s]}; },
-            [&](const JD& d, bool act, T (&acc)[1]) {
-                T hij, hji;
-                radii_pair(xi, yi, zi, d.p.x, d.p.y, d.p.z, rti, Si, d.p.w, d.S, hij, hji);
-                ai += act ? hij : T(0);
-                acc[0] += act ? hji : T(0);
-            });
+        auto load = [&](int s) { return JD{sj[s], sS[s]}; };
+        auto pair = [&](const JD& d, int r, bool act, T (&acc)[1]) {
+            T hij, hji;
+            radii_pair(xi[r], yi[r], zi[r], d.p.x, d.p.y, d.p.z, rti[r], Si[r], d.p.w, d.S, hij,
+                       hji);
+            ai[r] += act ? hij : T(0);
+            acc[0] += act ? hji : T(0);
+        };
+        if constexpr (R == 1)
+            walk_tile<T, 1>(lane, J == w.I, aj, load, pair);
+        else
+            walk_tile_rows2<T, 1>(lane, aj, load, pair);
         const long long hj = to_fixed((double)aj[0], kScaleI, bad);
         fx_add(&I_fx[w.base + clamp_atom(j, w.n)], vj ? hj : 0ll);
-        ifix += to_fixed((double)ai, kScaleI, bad);
+#pragma unroll
+        for (int r = 0; r < R; ++r) ifix[r] += to_fixed((double)ai[r], kScaleI, bad);
     };
     tile(w.J0);
     for (int J = w.J0 + 1; J < w.J1; ++J) tile(J);
-    if (vi) fx_add(&I_fx[w.base + i], ifix);
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+        if (vi[r]) fx_add(&I_fx[w.base + (w.I + r) * kTile + lane], ifix[r]);
     if (bad) *ovf = 1;
+}
+
+template <typename T, int W>
+__global__ __launch_bounds__(kTile * W) void k_radii_pairs(
+    const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
+    const Q4<T>* __restrict__ Gx, unsigned long long* __restrict__ I_fx, int* __restrict__ ovf)
+{
+    __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, rt
+    __shared__ T sS_w[W][2 * kTile];
+    const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
+    const int item = blockIdx.x * W + wave;
+    if (item >= n_items) return;
+    const WorkItem w = items[item];
+    // the descreening pass runs one-row items only (its two-row form was
+    // slower: fewer waves in flight for less saved work)
+    radii_item<T, 1>(w, lane, sj_w[wave], sS_w[wave], P, Gx, I_fx, ovf);
 }
 
 // Per atom: OBC radius from the descreening sum (FP64), and the per-atom state
@@ -513,33 +566,29 @@ __global__ void k_radii_finalize(int n_atoms, const T* __restrict__ RHO, GBConst
 // ================================================================ pass 2
 // Coulomb + GB energy, explicit pair forces, G = dE/dR, phi = dE/dq.
 
-template <typename T, bool GRAD, int W>
-__global__ __launch_bounds__(kTile * W) void k_energy_pairs(
-    const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
-    const T* __restrict__ Rt, const T* __restrict__ At, T kC, T kT, Work<T> wk)
+// One work item of R (1 or 2) i blocks; see radii_item.
+template <typename T, bool GRAD, int R>
+__device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* sj, T* sR, T* sA,
+                                            const Q4<T>* __restrict__ P, const T* __restrict__ Rt,
+                                            const T* __restrict__ At, T kC, T kT,
+                                            const Work<T>& wk)
 {
-    __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, q
-    __shared__ T sR_w[W][2 * kTile];
-    __shared__ T sA_w[W][2 * kTile];
     constexpr int NJ = GRAD ? 5 : 1;
-    const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
-    const int item = blockIdx.x * W + wave;
-    if (item >= n_items) return;
-    Q4<T>* sj = sj_w[wave];
-    T* sR = sR_w[wave];
-    T* sA = sA_w[wave];
-    const WorkItem w = items[item];
-    const int i = w.I * kTile + lane;
-    const bool vi = i < w.n;
-    T xi, yi, zi, qi, Ri, ai;
-    if (vi) {
-        int g = w.base + i;
-        const Q4<T> p = P[g];
-        xi = p.x; yi = p.y; zi = p.z; qi = p.w;
-        Ri = Rt[g]; ai = At[g];
-    } else {
-        dummy_pos(i, xi, yi, zi);
-        qi = T(0); Ri = T(1); ai = T(kAScale);
+    T xi[R], yi[R], zi[R], qi[R], Ri[R], ai[R];
+    bool vi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = (w.I + r) * kTile + lane;
+        vi[r] = i < w.n;
+        if (vi[r]) {
+            const int g = w.base + i;
+            const Q4<T> p = P[g];
+            xi[r] = p.x; yi[r] = p.y; zi[r] = p.z; qi[r] = p.w;
+            Ri[r] = Rt[g]; ai[r] = At[g];
+        } else {
+            dummy_pos(i, xi[r], yi[r], zi[r]);
+            qi[r] = T(0); Ri[r] = T(1); ai[r] = T(kAScale);
+        }
     }
     // raw loads of a j block; stand-ins for lanes past the end are applied
     // when the block is written to LDS
@@ -556,14 +605,19 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
             Rj = T(1); Aj = T(kAScale);
         }
     };
-    long long fix[5] = {0, 0, 0, 0, 0};
-    long long efix[2] = {0, 0};
+    long long fix[R][5], efix[R][2];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int a = 0; a < 5; ++a) fix[r][a] = 0;
+        efix[r][0] = efix[r][1] = 0;
+    }
     bool bad = false;
     Q4<T> pj;
     T Rj, Aj;
     fetch(w.J0, pj, Rj, Aj);
-    // one 64 x 64 tile; the first is peeled so that the loop is entered, as
-    // on every later trip, with the previous tile's sums still in flight
+    // one tile; the first is peeled so that the loop is entered, as on every
+    // later trip, with the previous tile's sums still in flight
     auto tile = [&](int J) {
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
@@ -574,50 +628,57 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
         sA[lane] = Aj; sA[lane + kTile] = Aj;
         wave_sync();
         fetch(J + 1 < w.J1 ? J + 1 : J, pj, Rj, Aj);
-        T fxi = 0, fyi = 0, fzi = 0, Gi = 0, phii = 0, eC = 0, eG = 0;
+        T fxi[R], fyi[R], fzi[R], Gi[R], phii[R], eC[R], eG[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+            fxi[r] = fyi[r] = fzi[r] = Gi[r] = phii[r] = eC[r] = eG[r] = T(0);
         T aj[NJ];
-        struct JD { Q4<T> p; T R, A; };
-        walk_tile<T, NJ>(lane, J == w.I, aj, [&](int s) { return JD{sj[s], sR[s], sA[s]}; },
-                         [&](const JD& d, bool act, T (&acc)[NJ]) {
+        struct JD { Q4<T> p; T Rv, Av; };
+        auto load = [&](int s) { return JD{sj[s], sR[s], sA[s]}; };
+        auto pair = [&](const JD& d, int r, bool act, T (&acc)[NJ]) {
             const Q4<T>& p = d.p;
-            const T rj = d.R;
-            T dx = xi - p.x, dy = yi - p.y, dz = zi - p.z;
+            const T rj = d.Rv;
+            T dx = xi[r] - p.x, dy = yi[r] - p.y, dz = zi[r] - p.z;
             T r2 = dx * dx + dy * dy + dz * dz;
             T invr = rsq(r2);
-            T t = r2 * (ai * d.A);               // r^2 log2(e) / (4 R_i R_j)
+            T t = r2 * (ai[r] * d.Av);            // r^2 log2(e) / (4 R_i R_j)
             T ex = exp2neg(t);                   // exp(-D)
-            T f2 = Ri * rj * ex + r2;
+            T f2 = Ri[r] * rj * ex + r2;
             T invf = rsq(f2);
-            T qq = act ? qi * p.w : T(0);
-            eC += qq * invr;
-            eG += qq * invf;
+            T qq = act ? qi[r] * p.w : T(0);
+            eC[r] += qq * invr;
+            eG[r] += qq * invf;
             if constexpr (GRAD) {
                 T qj = act ? p.w : T(0);
-                T qi_ = act ? qi : T(0);
+                T qi_ = act ? qi[r] : T(0);
                 T wgt = kC * invr - kT * invf;
-                phii += wgt * qj;
+                phii[r] += wgt * qj;
                 T invf3 = invf * invf * invf;
                 T invr3 = invr * invr * invr;
                 T fr = qq * (kT * invf3 * (T(1) - T(0.25) * ex) - kC * invr3);   // (dE/dr)/r
                 T fx = fr * dx, fy = fr * dy, fz = fr * dz;
-                fxi -= fx; fyi -= fy; fzi -= fz;
+                fxi[r] -= fx; fyi[r] -= fy; fzi[r] -= fz;
                 T cg = T(0.5) * kT * qq * invf3 * ex * (T(1) + t * T(kLn2));
-                Gi += cg * rj;
+                Gi[r] += cg * rj;
                 acc[0] += fx;
                 acc[1] += fy;
                 acc[2] += fz;
-                acc[3] += cg * Ri;
+                acc[3] += cg * Ri[r];
                 acc[4] += wgt * qi_;
             }
-        });
-        if (J == w.I) {
+        };
+        if constexpr (R == 1)
+            walk_tile<T, NJ>(lane, J == w.I, aj, load, pair);
+        else
+            walk_tile_rows2<T, NJ>(lane, aj, load, pair);
+        if (R == 1 && J == w.I) {
             // self terms: -(kT/2) q_i^2 / R_i in E_GB, -kT q_i / R_i in phi,
             // (kT/2) q_i^2 / R_i^2 in G
-            T invR = rcp(Ri);
-            eG += T(0.5) * qi * qi * invR;
+            T invR = rcp(Ri[0]);
+            eG[0] += T(0.5) * qi[0] * qi[0] * invR;
             if constexpr (GRAD) {
-                phii -= kT * qi * invR;
-                Gi += T(0.5) * kT * qi * qi * invR * invR;
+                phii[0] -= kT * qi[0] * invR;
+                Gi[0] += T(0.5) * kT * qi[0] * qi[0] * invR * invR;
             }
         }
         if constexpr (GRAD) {
@@ -632,31 +693,59 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
             for (int a = 0; a < 3; ++a) fx_add(&wk.F_fx[a * wk.n_atoms + g], v[a]);
             fx_add(&wk.G_fx[g], v[3]);
             fx_add(&wk.phi_fx[g], v[4]);
-            fix[0] += to_fixed((double)fxi, kScaleF, bad);
-            fix[1] += to_fixed((double)fyi, kScaleF, bad);
-            fix[2] += to_fixed((double)fzi, kScaleF, bad);
-            fix[3] += to_fixed((double)Gi, kScaleF, bad);
-            fix[4] += to_fixed((double)phii, kScaleF, bad);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                fix[r][0] += to_fixed((double)fxi[r], kScaleF, bad);
+                fix[r][1] += to_fixed((double)fyi[r], kScaleF, bad);
+                fix[r][2] += to_fixed((double)fzi[r], kScaleF, bad);
+                fix[r][3] += to_fixed((double)Gi[r], kScaleF, bad);
+                fix[r][4] += to_fixed((double)phii[r], kScaleF, bad);
+            }
         }
-        efix[0] += to_fixed((double)(kC * eC), kScaleE, bad);
-        efix[1] += to_fixed((double)(-kT * eG), kScaleE, bad);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            efix[r][0] += to_fixed((double)(kC * eC[r]), kScaleE, bad);
+            efix[r][1] += to_fixed((double)(-kT * eG[r]), kScaleE, bad);
+        }
     };
     tile(w.J0);
     for (int J = w.J0 + 1; J < w.J1; ++J) tile(J);
     if (bad) *wk.ovf = 1;
-    if (GRAD && vi) {
-        int g = w.base + i;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) fx_add(&wk.F_fx[a * wk.n_atoms + g], fix[a]);
-        fx_add(&wk.G_fx[g], fix[3]);
-        fx_add(&wk.phi_fx[g], fix[4]);
+    for (int r = 0; r < R; ++r) {
+        if (!vi[r]) continue;
+        const int g = w.base + (w.I + r) * kTile + lane;
+        if constexpr (GRAD) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) fx_add(&wk.F_fx[a * wk.n_atoms + g], fix[r][a]);
+            fx_add(&wk.G_fx[g], fix[r][3]);
+            fx_add(&wk.phi_fx[g], fix[r][4]);
+        }
+        // energies: each atom's share, summed per system by k_energy_sum
+        // (exact integers, so the split into atoms does not change the totals)
+        fx_add(&wk.EA_fx[g], efix[r][0]);
+        fx_add(&wk.EA_fx[wk.n_atoms + g], efix[r][1]);
     }
-    // energies: each atom's share, summed per system by k_energy_sum (exact
-    // integers, so the split into atoms does not change the totals)
-    if (vi) {
-        fx_add(&wk.EA_fx[w.base + i], efix[0]);
-        fx_add(&wk.EA_fx[wk.n_atoms + w.base + i], efix[1]);
-    }
+}
+
+template <typename T, bool GRAD, int W>
+__global__ __launch_bounds__(kTile * W) void k_energy_pairs(
+    const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
+    const T* __restrict__ Rt, const T* __restrict__ At, T kC, T kT, Work<T> wk)
+{
+    __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, q
+    __shared__ T sR_w[W][2 * kTile];
+    __shared__ T sA_w[W][2 * kTile];
+    const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
+    const int item = blockIdx.x * W + wave;
+    if (item >= n_items) return;
+    const WorkItem w = items[item];
+    // two-row items exist in the energy pass of FP32 plans only
+    if (sizeof(T) == 4 && w.rows == 2)
+        energy_item<T, GRAD, sizeof(T) == 4 ? 2 : 1>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P,
+                                                     Rt, At, kC, kT, wk);
+    else
+        energy_item<T, GRAD, 1>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P, Rt, At, kC, kT, wk);
 }
 
 // Per system: E_C and E_GB from the atoms' fixed-point shares (one block per
@@ -706,34 +795,32 @@ __global__ void k_energy_finalize(int n_atoms, Work<T> w, T* __restrict__ dEdq)
 // ================================================================ pass 3
 // Born-radius chain: force through Psi and the pair part of dE/drho.
 
-template <typename T, int W>
-__global__ __launch_bounds__(kTile * W) void k_chain_pairs(
-    const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
-    const Q4<T>* __restrict__ Gx, const T* __restrict__ Brt, Work<T> wk)
+// One work item of R (1 or 2) i blocks; see radii_item.
+template <typename T, int R>
+__device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* sj, Q4<T>* sb,
+                                           const Q4<T>* __restrict__ P,
+                                           const Q4<T>* __restrict__ Gx,
+                                           const T* __restrict__ Brt, const Work<T>& wk)
 {
-    __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, rt
-    __shared__ Q4<T> sb_w[W][2 * kTile];     // S, B rt, screen, -
-    const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
-    const int item = blockIdx.x * W + wave;
-    if (item >= n_items) return;
-    Q4<T>* sj = sj_w[wave];
-    Q4<T>* sb = sb_w[wave];
-    const WorkItem w = items[item];
-    const int i = w.I * kTile + lane;
-    const bool vi = i < w.n;
-    T xi, yi, zi, rti, Si, Bi, si;
-    if (vi) {
-        int g = w.base + i;
-        const Q4<T> p = P[g];
-        const Q4<T> gx = Gx[g];
-        xi = p.x; yi = p.y; zi = p.z;
-        rti = gx.x;
-        Si = gx.y;
-        si = gx.z;
-        Bi = Brt[g];
-    } else {
-        dummy_pos(i, xi, yi, zi);
-        rti = T(1); si = T(0); Si = T(0); Bi = T(0);
+    T xi[R], yi[R], zi[R], rti[R], Si[R], Bi[R], si[R];
+    bool vi[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = (w.I + r) * kTile + lane;
+        vi[r] = i < w.n;
+        if (vi[r]) {
+            const int g = w.base + i;
+            const Q4<T> p = P[g];
+            const Q4<T> gx = Gx[g];
+            xi[r] = p.x; yi[r] = p.y; zi[r] = p.z;
+            rti[r] = gx.x;
+            Si[r] = gx.y;
+            si[r] = gx.z;
+            Bi[r] = Brt[g];
+        } else {
+            dummy_pos(i, xi[r], yi[r], zi[r]);
+            rti[r] = T(1); si[r] = T(0); Si[r] = T(0); Bi[r] = T(0);
+        }
     }
     // raw loads of a j block; stand-ins for lanes past the end are applied
     // when the block is written to LDS
@@ -756,13 +843,15 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
             bj.x = bj.y = bj.z = T(0);
         }
     };
-    long long fix[4] = {0, 0, 0, 0};
+    long long fix[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r) fix[r][0] = fix[r][1] = fix[r][2] = fix[r][3] = 0;
     bool bad = false;
     Q4<T> pj, gj, bj;
     T brj;
     fetch(w.J0, pj, gj, brj);
-    // one 64 x 64 tile; the first is peeled so that the loop is entered, as
-    // on every later trip, with the previous tile's sums still in flight
+    // one tile; the first is peeled so that the loop is entered, as on every
+    // later trip, with the previous tile's sums still in flight
     auto tile = [&](int J) {
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
@@ -772,30 +861,37 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
         sb[lane] = bj; sb[lane + kTile] = bj;
         wave_sync();
         fetch(J + 1 < w.J1 ? J + 1 : J, pj, gj, brj);
-        T fxi = 0, fyi = 0, fzi = 0, dri = 0;
+        T fxi[R], fyi[R], fzi[R], dri[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) fxi[r] = fyi[r] = fzi[r] = dri[r] = T(0);
         T aj[4];
         struct JD { Q4<T> p, b; };
-        walk_tile<T, 4>(lane, J == w.I, aj, [&](int s) { return JD{sj[s], sb[s]}; },
-                        [&](const JD& d, bool act, T (&acc)[4]) {
+        auto load = [&](int s) { return JD{sj[s], sb[s]}; };
+        auto pair = [&](const JD& d, int r, bool act, T (&acc)[4]) {
             const Q4<T>& p = d.p;
             const Q4<T>& b = d.b;
-            T dx = xi - p.x, dy = yi - p.y, dz = zi - p.z;
+            T dx = xi[r] - p.x, dy = yi[r] - p.y, dz = zi[r] - p.z;
             T r2 = dx * dx + dy * dy + dz * dz;
             T invr = rsq(r2);
-            T r = r2 * invr;
+            T rr = r2 * invr;
             const T bj_ = act ? b.y : T(0);
-            const T bi_ = act ? Bi : T(0);
+            const T bi_ = act ? Bi[r] : T(0);
             T dEdr, gij2, gji2;
-            chain_pair(r, r2, invr, rti, Si, p.w, b.x, bi_, bj_, dEdr, gij2, gji2, dri, acc[3]);
+            chain_pair(rr, r2, invr, rti[r], Si[r], p.w, b.x, bi_, bj_, dEdr, gij2, gji2, dri[r],
+                       acc[3]);
             T fr = dEdr * invr;
             T fx = fr * dx, fy = fr * dy, fz = fr * dz;
-            fxi -= fx; fyi -= fy; fzi -= fz;
-            dri += si * bj_ * gji2;
+            fxi[r] -= fx; fyi[r] -= fy; fzi[r] -= fz;
+            dri[r] += si[r] * bj_ * gji2;
             acc[0] += fx;
             acc[1] += fy;
             acc[2] += fz;
             acc[3] += b.z * bi_ * gij2;
-        });
+        };
+        if constexpr (R == 1)
+            walk_tile<T, 4>(lane, J == w.I, aj, load, pair);
+        else
+            walk_tile_rows2<T, 4>(lane, aj, load, pair);
         {
             const int g = w.base + clamp_atom(j, w.n);
             long long v[4];
@@ -808,20 +904,41 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
             for (int a = 0; a < 3; ++a) fx_add(&wk.F_fx[a * wk.n_atoms + g], v[a]);
             fx_add(&wk.drho_fx[g], v[3]);
         }
-        fix[0] += to_fixed((double)fxi, kScaleF, bad);
-        fix[1] += to_fixed((double)fyi, kScaleF, bad);
-        fix[2] += to_fixed((double)fzi, kScaleF, bad);
-        fix[3] += to_fixed((double)dri, kScaleF, bad);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            fix[r][0] += to_fixed((double)fxi[r], kScaleF, bad);
+            fix[r][1] += to_fixed((double)fyi[r], kScaleF, bad);
+            fix[r][2] += to_fixed((double)fzi[r], kScaleF, bad);
+            fix[r][3] += to_fixed((double)dri[r], kScaleF, bad);
+        }
     };
     tile(w.J0);
     for (int J = w.J0 + 1; J < w.J1; ++J) tile(J);
     if (bad) *wk.ovf = 1;
-    if (vi) {
-        int g = w.base + i;
 #pragma unroll
-        for (int a = 0; a < 3; ++a) fx_add(&wk.F_fx[a * wk.n_atoms + g], fix[a]);
-        fx_add(&wk.drho_fx[g], fix[3]);
+    for (int r = 0; r < R; ++r) {
+        if (!vi[r]) continue;
+        const int g = w.base + (w.I + r) * kTile + lane;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) fx_add(&wk.F_fx[a * wk.n_atoms + g], fix[r][a]);
+        fx_add(&wk.drho_fx[g], fix[r][3]);
     }
+}
+
+template <typename T, int W>
+__global__ __launch_bounds__(kTile * W) void k_chain_pairs(
+    const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
+    const Q4<T>* __restrict__ Gx, const T* __restrict__ Brt, Work<T> wk)
+{
+    __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, rt
+    __shared__ Q4<T> sb_w[W][2 * kTile];     // S, B rt, screen, -
+    const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
+    const int item = blockIdx.x * W + wave;
+    if (item >= n_items) return;
+    const WorkItem w = items[item];
+    // the chain pass runs one-row items only (its two-row form was slower:
+    // fewer waves in flight for less saved work)
+    chain_item<T, 1>(w, lane, sj_w[wave], sb_w[wave], P, Gx, Brt, wk);
 }
 
 // Per atom after pass 3: forces and dE/drho.

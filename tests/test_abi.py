@@ -62,40 +62,50 @@ def test_params_validation(L):
     assert lib.gbmc_params_validate(C.byref(nan)) == L.GBMC_ERR_INVALID
 
 
-def schedule(L, off, jb=None):
+def schedule(L, off, jb=None, row_pairs=1):
     lib = L.load()
     off = np.ascontiguousarray(off, dtype=np.int32)
     n = C.c_int32()
     jb = jb or 8
-    st = lib.gbmc_schedule_build(off.size - 1, _i32p(off), jb, C.byref(n), None)
+    st = lib.gbmc_schedule_build(off.size - 1, _i32p(off), jb, row_pairs, C.byref(n), None)
     if st != 0:
         return st, None
-    items = np.zeros(4 * n.value, dtype=np.int32)
-    assert lib.gbmc_schedule_build(off.size - 1, _i32p(off), jb, C.byref(n), _i32p(items)) == 0
-    return st, items.reshape(-1, 4)
+    items = np.zeros(5 * n.value, dtype=np.int32)
+    assert lib.gbmc_schedule_build(off.size - 1, _i32p(off), jb, row_pairs, C.byref(n),
+                                   _i32p(items)) == 0
+    return st, items.reshape(-1, 5)
 
 
+@pytest.mark.parametrize("row_pairs", [1, 0])
 @pytest.mark.parametrize("jb", [None, 1, 3, 8, 1000])
-def test_schedule_covers_every_tile_once(L, jb):
-    sizes = [1, 64, 65, 0, 200, 2500, 130]
+def test_schedule_covers_every_tile_once(L, jb, row_pairs):
+    sizes = [1, 64, 65, 0, 200, 2500, 130, 129]
     off = np.concatenate([[0], np.cumsum(sizes)])
-    st, items = schedule(L, off, jb)
+    st, items = schedule(L, off, jb, row_pairs)
     assert st == 0
     seen = {}
-    for sys_, I, J0, J1 in items:
-        assert 0 <= I <= J0 < J1
-        for J in range(J0, J1):
-            key = (sys_, I, J)
-            assert key not in seen
-            seen[key] = 1
+    for sys_, I0, I1, J0, J1 in items:
+        rows = I1 - I0
+        assert rows in ((1, 2) if row_pairs else (1,))
+        assert 0 <= I0 <= J0 < J1
+        if rows == 2:
+            assert I0 % 2 == 0 and J0 >= I0 + 2
+        if jb:
+            assert J1 - J0 <= jb
+        for I in range(I0, I1):
+            for J in range(J0, J1):
+                key = (sys_, I, J)
+                assert key not in seen
+                seen[key] = 1
     for b, n in enumerate(sizes):
         nb = (n + 63) // 64
         for I in range(nb):
             for J in range(I, nb):
                 assert (b, I, J) in seen
     assert len(seen) == sum(((n + 63) // 64) * ((n + 63) // 64 + 1) // 2 for n in sizes)
-    # longest first
-    cost = 2 * (items[:, 3] - items[:, 2]) - (items[:, 2] == items[:, 1])
+    # longest first, in half tiles
+    rows = items[:, 2] - items[:, 1]
+    cost = 2 * rows * (items[:, 4] - items[:, 3]) - (items[:, 3] == items[:, 1])
     assert np.all(np.diff(cost) <= 0)
 
 
@@ -103,7 +113,7 @@ def test_schedule_rejects_bad_offsets(L):
     lib = L.load()
     n = C.c_int32()
     off = np.array([0, 10], dtype=np.int32)
-    assert lib.gbmc_schedule_build(1, _i32p(off), 0, C.byref(n), None) == L.GBMC_ERR_INVALID
+    assert lib.gbmc_schedule_build(1, _i32p(off), 0, 1, C.byref(n), None) == L.GBMC_ERR_INVALID
     assert schedule(L, [1, 5])[0] == L.GBMC_ERR_INVALID
     assert schedule(L, [0, 5, 3])[0] == L.GBMC_ERR_INVALID
     st, items = schedule(L, [0])
