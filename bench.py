@@ -124,6 +124,11 @@ class Workload:
         self.ux_all = torch.rand((n_steps, self.B), dtype=torch.float64, device=dev, generator=rng)
         self.u = torch.zeros((self.B, 6), dtype=torch.float64, device=dev)
         self.ux = torch.zeros(self.B, dtype=torch.float64, device=dev)
+        # device-side step index: every step (eager or graph replay) gathers
+        # its uniforms from row k of the tables and advances k itself (modulo
+        # the table length, so an index never leaves the tables)
+        self.n_rows = n_steps
+        self.k_dev = torch.zeros(1, dtype=torch.int64, device=dev)
         self.pairs = int(sum(s.n * (s.n - 1) // 2 for s in self.systems))
         self.n_cand = self.sites.n_candidates
         # per-site attempt / acceptance counters, accumulated by the MC kernel
@@ -143,6 +148,9 @@ class Workload:
             mc_stream.wait_stream(main)
         with torch.cuda.stream(mc_stream):
             # Monte Carlo branch: needs the radii and the current charges only
+            torch.index_select(self.u_all, 0, self.k_dev, out=self.u.view(1, self.B, 6))
+            torch.index_select(self.ux_all, 0, self.k_dev, out=self.ux.view(1, self.B))
+            self.k_dev.add_(1).remainder_(self.n_rows)
             if nxt is not cur:
                 nxt.q.copy_(cur.q)
             dE, dG = g.mc_state_dE(self.plan, self.sites, cur, self.cur, self.pH, self.E_rep,
@@ -153,15 +161,11 @@ class Workload:
             ef = g.energy_forces(self.plan, cur, p)
         if mc_stream is not main:
             main.wait_stream(mc_stream)
-        acc, E_new = g.remd_exchange(self.E_rung, mc["n_electrons"], self.rep_of_rung, parity,
-                                     self.ux, self.T, True)
-        self.E_rep.copy_(E_new)
+        acc, _ = g.remd_exchange(self.E_rung, mc["n_electrons"], self.rep_of_rung, parity,
+                                 self.ux, self.T, True, E_out=self.E_rep)
         self.last_exchange = acc
         return ef
 
-    def load_uniforms(self, k):
-        self.u.copy_(self.u_all[k])
-        self.ux.copy_(self.ux_all[k])
 
 
 def autotune(precision, order):
@@ -187,7 +191,6 @@ def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial", 
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
             for parity in (0, 1):
-                w.load_uniforms(k)
                 w.step(parity)
                 k += 1
         torch.cuda.current_stream().wait_stream(side)
@@ -201,7 +204,6 @@ def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial", 
 
     def one():
         nonlocal k
-        w.load_uniforms(k)
         if graphs is not None:
             graphs[k % 2].replay()
         else:
@@ -227,7 +229,6 @@ def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial", 
     w.plan.set_timing(True)
     acc = torch.zeros((), dtype=torch.int64, device=w.plan.device)
     for _ in range(kernel_steps):
-        w.load_uniforms(k)
         w.step(k % 2)
         k += 1
         acc += w.last_exchange.sum()

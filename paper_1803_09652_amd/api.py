@@ -337,13 +337,18 @@ def mc_step(plan: Plan, sites: Sites, atoms: Atoms, current_state: torch.Tensor,
 
 
 def remd_exchange(E_rung: torch.Tensor, Ne_of_rep: torch.Tensor, rep_of_rung: torch.Tensor,
-                  parity: int, u: torch.Tensor, T: float = 300.0, wrap: bool = True):
+                  parity: int, u: torch.Tensor, T: float = 300.0, wrap: bool = True,
+                  E_out: Optional[torch.Tensor] = None):
     """E-REMD exchange attempt; rep_of_rung (int32) is updated in place.
-    Returns (accepted[n_pairs] int32, E_of_rep[M] float64)."""
+    Returns (accepted[n_pairs] int32, E_of_rep[M] float64); E_of_rep is
+    written into E_out when given (it may be the caller's per-replica E)."""
     M = int(E_rung.shape[0])
     dev = E_rung.device
     acc = torch.empty(max(M, 1), dtype=torch.int32, device=dev)
-    Eo = torch.empty(M, dtype=torch.float64, device=dev)
+    if E_out is not None and (E_out.dtype != torch.float64 or E_out.shape != (M,)
+                              or not E_out.is_contiguous()):
+        raise ValueError("E_out must be a contiguous float64 [M] tensor")
+    Eo = torch.empty(M, dtype=torch.float64, device=dev) if E_out is None else E_out
     L.check(L.load().remd_exchange(M, _ptr(E_rung), _ptr(Ne_of_rep), _ptr(rep_of_rung), float(T),
                                    int(parity), int(bool(wrap)), _ptr(u), _ptr(acc), _ptr(Eo),
                                    _stream(dev)))

@@ -721,7 +721,7 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
             fx_add(&wk.G_fx[g], fix[r][3]);
             fx_add(&wk.phi_fx[g], fix[r][4]);
         }
-        // energies: each atom's share, summed per system by k_energy_sum
+        // energies: each atom's share, summed per system by k_energy_finalize
         // (exact integers, so the split into atoms does not change the totals)
         fx_add(&wk.EA_fx[g], efix[r][0]);
         fx_add(&wk.EA_fx[wk.n_atoms + g], efix[r][1]);
@@ -748,41 +748,43 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
         energy_item<T, GRAD, 1>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P, Rt, At, kC, kT, wk);
 }
 
-// Per system: E_C and E_GB from the atoms' fixed-point shares (one block per
-// system; integer sums, so the result does not depend on the order).
-__global__ __launch_bounds__(256) void k_energy_sum(const int32_t* __restrict__ off, size_t n_atoms,
-                                                    const unsigned long long* __restrict__ EA,
-                                                    double* __restrict__ e_coul,
-                                                    double* __restrict__ e_gb)
-{
-    __shared__ long long part[2][4];
-    const int b = blockIdx.x, t = threadIdx.x, lane = t % kTile, wave = t / kTile;
-    long long s0 = 0, s1 = 0;
-    for (int g = off[b] + t; g < off[b + 1]; g += 256) {
-        s0 += (long long)EA[g];
-        s1 += (long long)EA[n_atoms + g];
-    }
-#pragma unroll
-    for (int o = kTile / 2; o > 0; o >>= 1) {
-        s0 += __shfl_xor(s0, o);
-        s1 += __shfl_xor(s1, o);
-    }
-    if (lane == 0) { part[0][wave] = s0; part[1][wave] = s1; }
-    __syncthreads();
-    if (t == 0) {
-        long long c = part[0][0] + part[0][1] + part[0][2] + part[0][3];
-        long long gb = part[1][0] + part[1][1] + part[1][2] + part[1][3];
-        if (e_coul) e_coul[b] = (double)c * (1.0 / kScaleE);
-        if (e_gb) e_gb[b] = (double)gb * (1.0 / kScaleE);
-    }
-}
-
-// Per atom after pass 2: B = G dR/dPsi for the chain pass; dE/dq output.
+// After pass 2, one launch: blocks [0, n_sum) sum the atoms' fixed-point
+// energy shares of one system each (E_C, E_GB; integer sums, so the result
+// does not depend on the order), the following blocks finalize one atom per
+// thread: B = G dR/dPsi for the chain pass and the dE/dq output.
 template <typename T>
-__global__ void k_energy_finalize(int n_atoms, Work<T> w, T* __restrict__ dEdq)
+__global__ __launch_bounds__(256) void k_energy_finalize(int n_atoms, int n_sum, Work<T> w,
+                                                         double* __restrict__ e_coul,
+                                                         double* __restrict__ e_gb,
+                                                         T* __restrict__ dEdq, bool grad)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_atoms) return;
+    const int t = threadIdx.x;
+    if ((int)blockIdx.x < n_sum) {
+        __shared__ long long part[2][4];
+        const int b = blockIdx.x, lane = t % kTile, wave = t / kTile;
+        const unsigned long long* EA = w.EA_fx;
+        long long s0 = 0, s1 = 0;
+        for (int g = w.atom_offset[b] + t; g < w.atom_offset[b + 1]; g += 256) {
+            s0 += (long long)EA[g];
+            s1 += (long long)EA[w.n_atoms + g];
+        }
+#pragma unroll
+        for (int o = kTile / 2; o > 0; o >>= 1) {
+            s0 += __shfl_xor(s0, o);
+            s1 += __shfl_xor(s1, o);
+        }
+        if (lane == 0) { part[0][wave] = s0; part[1][wave] = s1; }
+        __syncthreads();
+        if (t == 0) {
+            long long c = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+            long long gb = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+            if (e_coul) e_coul[b] = (double)c * (1.0 / kScaleE);
+            if (e_gb) e_gb[b] = (double)gb * (1.0 / kScaleE);
+        }
+        return;
+    }
+    const int k = ((int)blockIdx.x - n_sum) * 256 + t;
+    if (!grad || k >= n_atoms) return;
     const int g = w.perm[k];
     double G = (double)(long long)w.G_fx[k] * (1.0 / kScaleF);
     double B = G * w.dRdPsi64[g];
@@ -1367,12 +1369,11 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
                                               pe.items, pe.n_items, w.P, w.R_t, w.a_t, (T)c.kC,
                                               (T)c.kT, w))
     }
-    if (n_sys > 0 && (e_coul || e_gb))
-        hipLaunchKernelGGL(k_energy_sum, dim3(n_sys), dim3(256), 0, s, w.atom_offset, w.n_atoms,
-                           w.EA_fx, e_coul, e_gb);
-    if (grad && n_atoms > 0)
-        hipLaunchKernelGGL(k_energy_finalize<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s,
-                           n_atoms, w, dEdq);
+    const int n_sum = (e_coul || e_gb) ? n_sys : 0;
+    const int n_fin = grad ? blocks_for(n_atoms, 256) : 0;
+    if (n_sum + n_fin > 0)
+        hipLaunchKernelGGL(k_energy_finalize<T>, dim3(n_sum + n_fin), dim3(256), 0, s, n_atoms, n_sum,
+                           w, e_coul, e_gb, dEdq, grad);
     if (chain && pc.n_items > 0) {
         GBMC_DISPATCH_W(pc.waves_per_group,
                         GBMC_LAUNCH_TIMED(ev, kKChain, (k_chain_pairs<T, W>),

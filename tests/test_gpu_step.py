@@ -19,7 +19,6 @@ def _run(overlap, use_graph, n_steps):
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):
             for _ in range(2):
-                w.load_uniforms(k)
                 w.step(k % 2)
                 k += 1
         torch.cuda.current_stream().wait_stream(side)
@@ -32,7 +31,6 @@ def _run(overlap, use_graph, n_steps):
             graphs.append(gr)
     snaps = []
     while k < n_steps:
-        w.load_uniforms(k)
         if graphs is not None:
             graphs[k % 2].replay()
         else:
