@@ -141,11 +141,12 @@ class Workload:
         cur, nxt = (self.atoms, self.atoms_b) if parity == 0 else (self.atoms_b, self.atoms)
         main = torch.cuda.current_stream()
         g.radii(self.plan, cur, p)
-        if not self.overlap:
-            ef = g.energy_forces(self.plan, cur, p)
         mc_stream = self.side if self.overlap else main
         if mc_stream is not main:
             mc_stream.wait_stream(main)
+        # the force passes are issued first, so that they continue on the
+        # radii's queue and the Monte Carlo branch is the one that forks off
+        ef = g.energy_forces(self.plan, cur, p)
         with torch.cuda.stream(mc_stream):
             # Monte Carlo branch: needs the radii and the current charges only
             torch.index_select(self.u_all, 0, self.k_dev, out=self.u.view(1, self.B, 6))
@@ -157,8 +158,6 @@ class Workload:
                                    self.T, p)
             mc = g.mc_step(self.plan, self.sites, cur, self.cur, self.pH, self.E_rep, dE, dG,
                            self.u, self.T, p, counters=self.counters, q_out=nxt.q)
-        if self.overlap:
-            ef = g.energy_forces(self.plan, cur, p)
         if mc_stream is not main:
             main.wait_stream(mc_stream)
         acc, _ = g.remd_exchange(self.E_rung, mc["n_electrons"], self.rep_of_rung, parity,
