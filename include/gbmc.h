@@ -77,8 +77,8 @@ typedef struct {
  * such independent wavefronts share a workgroup (1, 2, 4 or 8).  Every 64 x 64
  * tile is rounded into fixed point on its own, so results are bitwise
  * independent of the knobs.  Defaults (j blocks / waves): FP32 descreening
- * 1 / 4, energy 2 / 4, chain 1 / 1; FP64 descreening 2 / 2, energy 2 / 4,
- * chain 2 / 4. */
+ * 1 / 4, energy 2 / 4, chain 1 / 1; FP64 descreening 1 / 2, energy 2 / 4,
+ * chain 1 / 2. */
 enum { GBMC_PASS_RADII = 0, GBMC_PASS_ENERGY = 1, GBMC_PASS_CHAIN = 2, GBMC_N_PASSES = 3 };
 typedef struct {
     int32_t j_blocks_per_item[GBMC_N_PASSES];

@@ -41,7 +41,7 @@ constexpr int64_t kTimedMax = 256;   // launches kept per timed kernel between r
 // of tens of thousands of atoms: the energy pass keeps two-tile items, which
 // halve its seven i-side flushes per tile.
 const gbmc_tuning kDefaultTuning32 = {{1, 2, 1}, {4, 4, 1}};
-const gbmc_tuning kDefaultTuning64 = {{2, 2, 2}, {2, 4, 4}};
+const gbmc_tuning kDefaultTuning64 = {{1, 2, 1}, {2, 4, 2}};
 
 }  // namespace
 

@@ -45,8 +45,26 @@ constexpr double kAScale = 0.60056120439322491;
 __device__ __forceinline__ float rsq(float v) { return __builtin_amdgcn_rsqf(v); }
 __device__ __forceinline__ float rcp(float v) { return __builtin_amdgcn_rcpf(v); }
 __device__ __forceinline__ float exp2neg(float t) { return __builtin_amdgcn_exp2f(-t); }
-__device__ __forceinline__ double rsq(double v) { return 1.0 / sqrt(v); }
-__device__ __forceinline__ double rcp(double v) { return 1.0 / v; }
+// FP64 1/sqrt and 1/x: hardware estimates refined by two Newton steps (within
+// an ulp or two of the rounded result, at a fraction of the cost of the
+// correctly rounded division and square root).
+__device__ __forceinline__ double rsq64(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+__device__ __forceinline__ double rcp64(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return y;
+}
+__device__ __forceinline__ double rsq(double v) { return rsq64(v); }
+__device__ __forceinline__ double rcp(double v) { return rcp64(v); }
 __device__ __forceinline__ double exp2neg(double t) { return exp2(-t); }
 
 // Fixed-point value of v; an out-of-range (or NaN) v gives 0 and sets bad.
@@ -199,8 +217,8 @@ __device__ __forceinline__ void dist64(double xi, double yi, double zi, double x
 {
     double dx = xi - xj, dy = yi - yj, dz = zi - zj;
     double r2 = dx * dx + dy * dy + dz * dz;
-    r = sqrt(r2);
-    invr = 1.0 / r;
+    invr = rsq64(r2);
+    r = r2 * invr;
 }
 
 // Pass-1 pair: H(r; rt_i, S_j) and H(r; rt_j, S_i).
@@ -226,14 +244,24 @@ __device__ __forceinline__ void radii_pair(float xi, float yi, float zi, float x
     }
 }
 
+// FP64: the same split, with a degree-14 polynomial on y <= 0.25 (one ulp);
+// every other pair takes the closed form.
 __device__ __forceinline__ void radii_pair(double xi, double yi, double zi, double xj, double yj,
                                            double zj, double rti, double Si, double rtj, double Sj,
                                            double& hij, double& hji)
 {
     double r, invr;
     dist64(xi, yi, zi, xj, yj, zj, r, invr);
-    hij = hct_general(r, invr, rti, Sj);
-    hji = hct_general(r, invr, rtj, Si);
+    const double xij = Sj * invr, yij = xij * xij;
+    const double xji = Si * invr, yji = xji * xji;
+    hij = xij * yij * invr * hct_poly64(yij);
+    hji = xji * yji * invr * hct_poly64(yji);
+    const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX64);
+    const bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX64);
+    if (!(f_ij & f_ji)) {
+        if (!f_ij) hij = hct_general(r, invr, rti, Sj);
+        if (!f_ji) hji = hct_general(r, invr, rtj, Si);
+    }
 }
 
 // Pass-3 pair terms with the Born chain weights bi = B_i rt_i, bj = B_j rt_j
@@ -278,19 +306,41 @@ __device__ __forceinline__ void chain_pair(float r, float r2, float invr, float 
     dEdr = -u * fmaf(bi, aij, bj * aji);
 }
 
+// FP64: the same split with the FP64 polynomial; overlapping pairs take the
+// closed-form partials.
 __device__ __forceinline__ void chain_pair(double r, double r2, double invr, double rti, double Si,
                                            double rtj, double Sj, double bi, double bj,
                                            double& dEdr, double& gij2, double& gji2, double& dri,
                                            double& drj)
 {
-    double gij[3], gji[3];
-    hct_general_grad(r, invr, rti, Sj, gij[0], gij[1], gij[2]);
-    hct_general_grad(r, invr, rtj, Si, gji[0], gji[1], gji[2]);
-    dEdr = bi * gij[0] + bj * gji[0];
-    gij2 = gij[2];
-    gji2 = gji[2];
-    dri += bi * gij[1];
-    drj += bj * gji[1];
+    const double u = invr * invr;
+    const double xij = Sj * invr, yij = xij * xij;
+    const double xji = Si * invr, yji = xji * xji;
+    double wij = rcp64(1.0 - yij), wji = rcp64(1.0 - yji);
+    wij *= wij;
+    wji *= wji;
+    double aij = xij * yij * (hct_poly64(yij) + wij);    // -r^2 dH/dr
+    double aji = xji * yji * (hct_poly64(yji) + wji);
+    gij2 = yij * wij * u;
+    gji2 = yji * wji * u;
+    const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX64);
+    const bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX64);
+    if (!(f_ij & f_ji)) {
+        double g0, g1, g2;
+        if (!f_ij) {
+            hct_general_grad(r, invr, rti, Sj, g0, g1, g2);
+            aij = -g0 * r2;
+            gij2 = g2;
+            dri = fma(bi, g1, dri);
+        }
+        if (!f_ji) {
+            hct_general_grad(r, invr, rtj, Si, g0, g1, g2);
+            aji = -g0 * r2;
+            gji2 = g2;
+            drj = fma(bj, g1, drj);
+        }
+    }
+    dEdr = -u * fma(bi, aij, bj * aji);
 }
 
 // ---------------------------------------------------------------- helpers
@@ -973,16 +1023,6 @@ __global__ void k_grad_finalize(int n_atoms, const T* __restrict__ RHO, double o
 // over all atoms of the system, split in short chunks (many waves in flight);
 // each chunk's FP64 partial is added in 2^-44 fixed point, so the sum does not
 // depend on the order (deterministic) and k_site_dE reads one value per atom.
-
-// FP64 1/sqrt: hardware estimate refined by two Newton steps.
-__device__ __forceinline__ double rsq64(double x)
-{
-    double y = __builtin_amdgcn_rsq(x);
-    double h = 0.5 * x;
-    y = y * fma(-h * y, y, 1.5);
-    y = y * fma(-h * y, y, 1.5);
-    return y;
-}
 
 // k/(eps_in r) - k tau / f_GB for one pair (FP64); a = 1/(2R).
 __device__ __forceinline__ double pairK(double dx, double dy, double dz, double Ra, double aa,
