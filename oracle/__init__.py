@@ -104,6 +104,7 @@ def _declare(L):
                             _I, _I, C.c_double, C.c_double, C.c_double, _D]
     L.or_mc_step.argtypes = mc + [_I, _D]
     L.or_mc_run.argtypes = [C.c_int] + mc + [_I64, _I64]
+    L.or_mc_sweep.argtypes = mc[:-1] + [C.c_int, _D, _I, _D]
     L.or_remd_exchange.restype = C.c_int
     L.or_remd_exchange.argtypes = [C.c_int, _D, _I, _I, C.c_double, C.c_int, C.c_int, _D, _I, _D]
 
@@ -304,6 +305,22 @@ def mc_run(s, R, tables: SiteTables, pH: float, E_volt: float, T: float, u,
     args = _mc_args(s, R, p, tables, q, pH, E_volt, T, u)
     lib().or_mc_run(n_steps, *args, occ.ctypes.data_as(_I64), acc.ctypes.data_as(_I64))
     return occ, acc
+
+
+def mc_sweep(s, R, tables: SiteTables, pH: float, E_volt: float, T: float, u, kinds: int = 3,
+             p: Params = IGB5, q: Optional[np.ndarray] = None):
+    """One sequential sweep (every site of the kinds once; protonation first;
+    random order by u[:, 0]); u[n_sites][3].  Updates ``tables.current_state``.
+    Returns (q, accepted[n_sites] (1/0, -1 not attempted), dG[n_sites])."""
+    q = _d(s.q if q is None else q).copy()
+    u = _d(u)
+    if u.shape != (tables.n_sites, 3):
+        raise ValueError("u must be [n_sites, 3]")
+    acc = np.zeros(tables.n_sites, dtype=np.int32)
+    dG = np.zeros(tables.n_sites)
+    args = _mc_args(s, R, p, tables, q, pH, E_volt, T, u)
+    lib().or_mc_sweep(*args[:-1], int(kinds), _pd(u), _pi(acc), _pd(dG))
+    return q, acc, dG
 
 
 def remd_exchange(E_rung, Ne_of_rep, rep_of_rung, T: float, parity: int, wrap: bool, u):

@@ -433,6 +433,68 @@ void or_mc_step(int n, const double* x, const double* y, const double* z, double
     free(phi);
 }
 
+/* One sequential sweep of the explicit-solvent attempt loop (section
+ * III.A.2), at fixed coordinates and Born radii: every site of the requested
+ * kinds (bit 0 protonation, bit 1 redox) is attempted once; protonation sites
+ * come first when both kinds are swept (section III.A), each kind's sites in
+ * the random order of ascending u[3m] (ties by index).  Site m proposes the
+ * floor(u[3m+1] (n_states - 1))-th of its other states in ascending order and
+ * accepts iff u[3m+2] < exp(-dG/(kB T)), with Delta E taken at the charges
+ * left by the earlier attempts of the sweep (potentials recomputed from all
+ * atoms at every visit).  accepted[m] is 1/0 for attempted sites and -1 for
+ * the others; out_dG[m] receives the attempt's Delta G. */
+void or_mc_sweep(int n, const double* x, const double* y, const double* z, double* q,
+                 const double* R, const or_params* p, int n_sites, const int* site_kind,
+                 const int* site_atom_offset, const int* site_atoms, const int* site_state_offset,
+                 const int* state_charge_offset, const double* state_charges,
+                 const double* state_gref, const int* state_count, int* current_state,
+                 double pH, double E_volt, double T, int kinds, const double* u, int* accepted,
+                 double* out_dG)
+{
+    double* phi = malloc(sizeof(double) * n);
+    int* order = malloc(sizeof(int) * (n_sites > 0 ? n_sites : 1));
+    for (int m = 0; m < n_sites; ++m) { accepted[m] = -1; out_dG[m] = 0.0; }
+    for (int kind = 0; kind < 2; ++kind) {
+        if (!(kinds & (1 << kind))) continue;
+        int cnt = 0;
+        for (int m = 0; m < n_sites; ++m)
+            if (site_kind[m] == kind) order[cnt++] = m;
+        /* insertion sort by (u[3m], m) */
+        for (int a = 1; a < cnt; ++a) {
+            int m = order[a], b = a - 1;
+            while (b >= 0 && (u[3 * order[b]] > u[3 * m] ||
+                              (u[3 * order[b]] == u[3 * m] && order[b] > m))) {
+                order[b + 1] = order[b];
+                --b;
+            }
+            order[b + 1] = m;
+        }
+        for (int v = 0; v < cnt; ++v) {
+            int m = order[v];
+            int g0 = site_state_offset[m], ns = site_state_offset[m + 1] - g0;
+            int s = current_state[m];
+            int tp = pick(u[3 * m + 1], ns - 1);
+            int s_new = tp < s ? tp : tp + 1;
+            or_phi_fixedR(n, x, y, z, q, R, p, phi);
+            const int* atoms = site_atoms + site_atom_offset[m];
+            int na = site_atom_offset[m + 1] - site_atom_offset[m];
+            const double* q_new = state_charges + state_charge_offset[g0 + s_new];
+            const double* q_old = state_charges + state_charge_offset[g0 + s];
+            double dE = cand_dE(x, y, z, R, phi, p, atoms, na, q_new, q_old);
+            double dG = or_delta_G(kind, dE, state_count[g0 + s_new], state_count[g0 + s],
+                                   state_gref[g0 + s_new], state_gref[g0 + s], pH, E_volt, T);
+            out_dG[m] = dG;
+            accepted[m] = or_metropolis(dG, T, u[3 * m + 2]);
+            if (accepted[m]) {
+                current_state[m] = s_new;
+                for (int a = 0; a < na; ++a) q[atoms[a]] = q_new[a];
+            }
+        }
+    }
+    free(order);
+    free(phi);
+}
+
 /* n_steps attempt pairs at fixed coordinates and Born radii; u[n_steps][6].
  * occupancy[n_states_total] accumulates, after every step, one count for the
  * state each site is in. */

@@ -7,6 +7,9 @@
   and an uncoupled protonation site follows Henderson-Hasselbalch; a five-state
   site follows its Boltzmann distribution; the redox attempt sees the charges
   left by an accepted protonation attempt (section II.B and Fig. 1).
+* Sweep (section III.A.2): every visit's Delta G is the brute-force energy
+  difference at the charges left by the earlier visits, in the visit order;
+  a one-site sweep is the single attempt.
 * Exchange: the paper's worked numbers (31 % at 30 mV, 59.5 mV per pH unit),
   the pairing pattern of section III.B, and the Eq. 15 rate.
 """
@@ -221,6 +224,76 @@ def test_redox_attempt_sees_accepted_protonation(orc):
     # and differs from the value on the old charges when the sites interact
     dE_old = orc.site_dE(s, R)
     assert abs(dE_old[c_red] - dE[c_red]) > 1e-6
+
+
+# ------------------------------------------------------------------ sweep
+
+def _replay_sweep(orc, s, R, u, kinds, acc, pH, E, T):
+    """Replays a sweep from its reported decisions with brute-force energies:
+    the visit order (protonation first, each kind by ascending u[:, 0]), the
+    proposed state of each visit, and dG = E(q') - E(q) + drive - dGref at the
+    charges left by the earlier visits."""
+    w = s.copy()
+    out = {}
+    for kind in (0, 1):
+        if not kinds & (1 << kind):
+            continue
+        ms = sorted((m for m, x in enumerate(w.sites) if x.kind == kind), key=lambda m: (u[m, 0], m))
+        for m in ms:
+            site = w.sites[m]
+            cur = site.state
+            tp = min(int(math.floor(u[m, 1] * (site.n_states - 1))), site.n_states - 2)
+            new = tp if tp < cur else tp + 1
+            e0 = orc.energy_fixedR(w, R).sum()
+            q_try = w.q.copy()
+            q_try[site.atoms] = site.charges[new]
+            e1 = orc.energy_fixedR(w, R, q=q_try).sum()
+            drive = (orc.KB * T * math.log(10) * pH) if kind == 0 else (orc.FARADAY * E)
+            out[m] = (e1 - e0) + drive * (int(site.counts[new]) - int(site.counts[cur]))
+            if acc[m] == 1:
+                _set_state(w, m, new)
+    return out, w
+
+
+@pytest.mark.parametrize("kinds", [1, 2, 3])
+def test_sweep_matches_brute_force_replay(orc, kinds):
+    # several interacting sites: every attempt's dG is the brute-force energy
+    # difference at the charges left by the earlier attempts of the sweep, in
+    # the order the paper's explicit-solvent loop visits them
+    s = synth.make_system(51, 80, 7.0, n_redox=2, n_prot=3, redox_atoms=8, prot_atoms=(4, 6),
+                          prot_states=3, random_states=True)
+    R = orc.radii(s)["R"]
+    rng = np.random.default_rng(7)
+    u = rng.uniform(size=(len(s.sites), 3))
+    u[:, 2] = rng.choice([0.0, 0.999999], size=len(s.sites))   # force a mix of decisions
+    tab = orc.SiteTables(s)
+    q, acc, dG = orc.mc_sweep(s, R, tab, 7.0, -0.2, 300.0, u, kinds)
+    ref, w = _replay_sweep(orc, s, R, u, kinds, acc, 7.0, -0.2, 300.0)
+    for m, x in enumerate(s.sites):
+        if kinds & (1 << x.kind):
+            assert acc[m] in (0, 1)
+            assert abs(dG[m] - ref[m]) <= 1e-9, (m, dG[m], ref[m])
+            assert acc[m] == int(u[m, 2] < math.exp(-dG[m] / (orc.KB * 300.0)))
+        else:
+            assert acc[m] == -1
+    assert np.array_equal(q, w.q)
+    assert [int(v) for v in tab.current_state] == [x.state for x in w.sites]
+    # the sites interact: some later attempt saw an accepted earlier one
+    assert (acc == 1).any()
+
+
+def test_sweep_one_redox_site_equals_single_attempt(orc):
+    # with one redox site and no protonation site, a redox sweep is the
+    # implicit-solvent attempt of that site (same state pick and acceptance)
+    s = synth.make_system(52, 50, 6.0, n_redox=1, n_prot=0, redox_atoms=6, random_states=True)
+    R = orc.radii(s)["R"]
+    for ua in (0.0, 0.3, 0.999999):
+        t1, t2 = orc.SiteTables(s), orc.SiteTables(s)
+        q1, acc, dG = orc.mc_sweep(s, R, t1, 7.0, -0.25, 300.0, np.array([[0.5, 0.7, ua]]), 2)
+        q2, out, dG2 = orc.mc_step(s, R, t2, 7.0, -0.25, 300.0, [0.0, 0.0, 0.0, 0.1, 0.7, ua])
+        assert acc[0] == out[1] and abs(dG[0] - dG2[1]) <= 1e-12
+        assert np.array_equal(q1, q2)
+        assert list(t1.current_state) == list(t2.current_state)
 
 
 # ------------------------------------------------------------------ exchange
