@@ -249,6 +249,30 @@ gbmc_status mc_step(gbmc_plan* plan, const gbmc_sites* sites, const gbmc_atoms* 
                     int32_t* n_electrons, int64_t* counters, int32_t* accepted,
                     hipStream_t stream);
 
+/* One sequential Monte Carlo sweep per system: the explicit-solvent attempt
+ * loop of section III.A.2 run on the implicit-solvent energies.  Every site
+ * of the requested kinds (bit 0 of kinds: protonation, bit 1: redox) is
+ * attempted once; protonation sites come first when both kinds are swept
+ * (section III.A), each kind's sites of a system in the random order of
+ * ascending u[3m] (ties by site index).  Site m proposes the
+ * floor(u[3m+1] (n_states - 1))-th of its other states (clamped) and accepts
+ * iff u[3m+2] < exp(-dG/(kB T)), with dG as in mc_state_dE taken at the
+ * charges left by the earlier attempts of the sweep (FP64).  u[S][3] (double,
+ * device).  Accepted site charges are written into q (float or double per
+ * plan, may alias atoms->q; the other charges must already be there) and
+ * current_state[S] is updated in place.  Optional outputs: n_electrons[B]
+ * (int32) after the sweep, counters[S][2] (int64) attempts and acceptances
+ * added per site, accepted[S] (int32) 1/0 for the sites attempted (others
+ * untouched), dG[S] (double) of each attempt.  Needs the coordinates and Born
+ * radii of the last gb_radii call on workspace (atoms must hold them, and
+ * atoms->q the charges of current_state).  GBMC_ERR_UNSUPPORTED if a system
+ * has more than 1024 site atoms or more than 1024 sites of one kind. */
+gbmc_status mc_sweep(gbmc_plan* plan, const gbmc_sites* sites, const gbmc_atoms* atoms, void* q,
+                     const gbmc_gb_params* params, void* workspace, void* site_workspace,
+                     int32_t* current_state, const double* pH, const double* E_volt, double T,
+                     int32_t kinds, const double* u, int32_t* n_electrons, int64_t* counters,
+                     int32_t* accepted, double* dG, hipStream_t stream);
+
 /* E-REMD exchange attempt (section II.C, Eqs. 14-15; pairing of section
  * III.B).  Rungs 0..M-1 are ordered by increasing redox potential E_rung[M]
  * (double, volt); rep_of_rung[M] (int32, in/out) holds the replica at each

@@ -336,6 +336,36 @@ def mc_step(plan: Plan, sites: Sites, atoms: Atoms, current_state: torch.Tensor,
     return {"n_electrons": ne, "accepted": acc}
 
 
+def mc_sweep(plan: Plan, sites: Sites, atoms: Atoms, current_state: torch.Tensor, pH, E_volt,
+             u: torch.Tensor, T: float = 300.0, params: GBParams = IGB5, kinds: int = 3,
+             counters: Optional[torch.Tensor] = None,
+             q_out: Optional[torch.Tensor] = None) -> dict:
+    """One sequential sweep per system: every site of the kinds (bit 0
+    protonation, bit 1 redox) attempted once, protonation first, each kind in
+    the random order of ascending u[:, 0]; u is float64 [n_sites, 3].
+    Updates current_state in place and writes accepted site charges into q_out
+    (default atoms.q).  Needs a preceding radii() on the same plan and atoms.
+    Returns n_electrons [B], accepted [n_sites] (1/0, -1 for sites of kinds not
+    swept) and dG [n_sites] of each attempt."""
+    dev = plan.device
+    if u.dtype != torch.float64 or u.shape != (sites.n_sites, 3):
+        raise ValueError("u must be float64 [n_sites, 3]")
+    q_dst = atoms.q if q_out is None else q_out
+    if q_dst.dtype != plan.dtype or q_dst.shape != (plan.n_atoms,) or not q_dst.is_contiguous():
+        raise ValueError("q_out must be a contiguous [N] tensor of the plan dtype")
+    pH_t = _dev_f64(pH, plan.n_systems, dev)
+    E_t = _dev_f64(E_volt, plan.n_systems, dev)
+    ne = torch.empty(plan.n_systems, dtype=torch.int32, device=dev)
+    acc = torch.full((max(sites.n_sites, 1),), -1, dtype=torch.int32, device=dev)
+    dG = torch.zeros(max(sites.n_sites, 1), dtype=torch.float64, device=dev)
+    a, p = atoms.c(), params.c()
+    L.check(L.load().mc_sweep(plan.handle, sites.handle, C.byref(a), _ptr(q_dst), C.byref(p),
+                              _ptr(plan.workspace), _ptr(sites.workspace), _ptr(current_state),
+                              _ptr(pH_t), _ptr(E_t), float(T), int(kinds), _ptr(u.contiguous()),
+                              _ptr(ne), _ptr(counters), _ptr(acc), _ptr(dG), _stream(dev)))
+    return {"n_electrons": ne, "accepted": acc[:sites.n_sites], "dG": dG[:sites.n_sites]}
+
+
 def remd_exchange(E_rung: torch.Tensor, Ne_of_rep: torch.Tensor, rep_of_rung: torch.Tensor,
                   parity: int, u: torch.Tensor, T: float = 300.0, wrap: bool = True,
                   E_out: Optional[torch.Tensor] = None):

@@ -73,6 +73,8 @@ struct gbmc_sites {
     const gbmc_plan* plan = nullptr;
     int32_t n_sites = 0, n_cand = 0, n_rowitems = 0;
     size_t n_site_atoms = 0;         // fixed-point potential slots in the site workspace
+    int32_t max_sys_site_atoms = 0;  // largest number of site atoms in one system
+    int32_t max_sys_sites = 0;       // largest number of sites of one kind in one system
     void* d_mem = nullptr;
     SiteDev dev{};
 };
@@ -714,6 +716,11 @@ gbmc_status gbmc_sites_create(gbmc_plan* p, gbmc_sites** out, int32_t n_sites,
         sp->n_cand = cand[S];
         sp->n_rowitems = (int32_t)rows.size();
         sp->n_site_atoms = (size_t)n_sa;
+        for (int32_t b = 0; b < B; ++b) {
+            sp->max_sys_site_atoms = std::max(sp->max_sys_site_atoms, sys_sa[b + 1] - sys_sa[b]);
+            sp->max_sys_sites = std::max({sp->max_sys_sites, prot_off[b + 1] - prot_off[b],
+                                          redox_off[b + 1] - redox_off[b]});
+        }
         hipError_t e = hipMalloc(&sp->d_mem, std::max<size_t>(o, 256));
         if (e != hipSuccess) { delete sp; return hip_fail(e, "hipMalloc(site tables)"); }
         e = hipMemcpy(sp->d_mem, h.data(), o, hipMemcpyHostToDevice);
@@ -824,6 +831,41 @@ gbmc_status mc_step(gbmc_plan* p, const gbmc_sites* s, const gbmc_atoms* a, void
                                    current_state, pH, E_volt, T, dE, dG, u, n_electrons, counters,
                                    accepted, stream, ev);
     return e == hipSuccess ? GBMC_OK : hip_fail(e, "mc_step launch");
+}
+
+gbmc_status mc_sweep(gbmc_plan* p, const gbmc_sites* s, const gbmc_atoms* a, void* q,
+                     const gbmc_gb_params* gp, void* ws, void* sws, int32_t* current_state,
+                     const double* pH, const double* E_volt, double T, int32_t kinds,
+                     const double* u, int32_t* n_electrons, int64_t* counters, int32_t* accepted,
+                     double* dG, hipStream_t stream)
+{
+    gbmc_status st = check_call(p, a, gp, ws, true);
+    if (st != GBMC_OK) return st;
+    st = check_sites(p, s, sws);
+    if (st != GBMC_OK) return st;
+    if (kinds < 0 || kinds > 3) return fail(GBMC_ERR_INVALID, "kinds must be 0..3 (bit 0 protonation, bit 1 redox)");
+    if (p->n_sys == 0 || s->n_sites == 0) return GBMC_OK;
+    if (!q || !current_state || !u || !pH || !E_volt)
+        return fail(GBMC_ERR_INVALID, "a Monte Carlo array is NULL");
+    if (!(T > 0.0) || !std::isfinite(T)) return fail(GBMC_ERR_INVALID, "temperature must be > 0");
+    if (s->max_sys_site_atoms > kMaxSweepSiteAtoms || s->max_sys_sites > kMaxSweepSites)
+        return fail(GBMC_ERR_UNSUPPORTED, "mc_sweep supports at most 1024 site atoms and 1024 "
+                                          "sites of one kind per system");
+    GBConst c = make_const(gp);
+    hipError_t e;
+    if (p->prec == GBMC_FP32_FIXED)
+        e = launch_mc_sweep<float>(s->dev, p->n_sys, s->max_sys_site_atoms, (const float*)a->x,
+                                   (const float*)a->y, (const float*)a->z, (const float*)a->q,
+                                   (float*)q, c, carve<float>(p, ws), (unsigned long long*)sws,
+                                   current_state, pH, E_volt, T, kinds, u, n_electrons, counters,
+                                   accepted, dG, stream);
+    else
+        e = launch_mc_sweep<double>(s->dev, p->n_sys, s->max_sys_site_atoms, (const double*)a->x,
+                                    (const double*)a->y, (const double*)a->z, (const double*)a->q,
+                                    (double*)q, c, carve<double>(p, ws), (unsigned long long*)sws,
+                                    current_state, pH, E_volt, T, kinds, u, n_electrons, counters,
+                                    accepted, dG, stream);
+    return e == hipSuccess ? GBMC_OK : hip_fail(e, "mc_sweep launch");
 }
 
 gbmc_status remd_exchange(int32_t M, const double* E_rung, const int32_t* Ne, int32_t* rep, double T,

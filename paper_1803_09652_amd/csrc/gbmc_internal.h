@@ -9,6 +9,8 @@ namespace gbmc {
 constexpr int kTile = 64;                 // atoms per block; one wavefront per tile
 constexpr int kMaxSiteAtoms = 256;
 constexpr int kMaxStates = 8;
+constexpr int kMaxSweepSites = 1024;      // sites of one kind per system in mc_sweep
+constexpr int kMaxSweepSiteAtoms = 1024;  // site atoms per system in mc_sweep (LDS)
 #ifndef GBMC_PHI_CHUNK
 #define GBMC_PHI_CHUNK 32
 #endif
@@ -145,6 +147,13 @@ hipError_t launch_mc_step(const SiteDev& sd, int n_sys, const T* x, const T* y, 
                           const double* dE, const double* dG, const double* u,
                           int32_t* n_electrons, int64_t* counters, int32_t* accepted,
                           hipStream_t s, hipEvent_t* ev);
+template <typename T>
+hipError_t launch_mc_sweep(const SiteDev& sd, int n_sys, int n_sa_max, const T* x, const T* y,
+                           const T* z, const T* q, T* q_out, const GBConst& c, const Work<T>& w,
+                           unsigned long long* phi_fx, int32_t* current_state, const double* pH,
+                           const double* E_volt, double T_kelvin, int kinds, const double* u,
+                           int32_t* n_electrons, int64_t* counters, int32_t* accepted, double* dG,
+                           hipStream_t s);
 hipError_t launch_remd_exchange(int M, const double* E_rung, const int32_t* Ne, int32_t* rep,
                                 double T_kelvin, int parity, int wrap, const double* u,
                                 int32_t* accepted, double* E_of_rep, hipStream_t s);

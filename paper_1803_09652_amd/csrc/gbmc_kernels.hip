@@ -1304,6 +1304,139 @@ __global__ __launch_bounds__(kMC) void k_mc_step(
     }
 }
 
+// Sequential sweep (section III.A.2): one workgroup per system visits every
+// site of the requested kinds once, protonation sites first, each kind in the
+// order of ascending u[3m] (ties by site index).  The FP64 potentials of all
+// the system's site atoms live in LDS (dynamic, [6][n_sa]: x, y, z, R, A,
+// phi); a visit computes Delta E = dq . phi + 1/2 dq . K_SS . dq from them,
+// and an accepted change adds K dq to every site atom's potential, so the
+// next visit sees the charges it left.  All threads evaluate the same
+// block-reduced Delta G and so take the same decision.
+template <typename T>
+__global__ __launch_bounds__(kSDE) void k_mc_sweep(
+    SiteDev sd, const T* __restrict__ X, const T* __restrict__ Y, const T* __restrict__ Z,
+    const T* __restrict__ Q, T* __restrict__ Qout, const double* __restrict__ R64,
+    const double* __restrict__ A64, double kC, double kT,
+    const unsigned long long* __restrict__ phi_fx, int32_t* __restrict__ current_state,
+    const double* __restrict__ pH, const double* __restrict__ E_volt, double T_kelvin, int kinds,
+    const double* __restrict__ u, int32_t* __restrict__ n_electrons,
+    int64_t* __restrict__ counters, int32_t* __restrict__ accepted, double* __restrict__ dG_out)
+{
+    extern __shared__ double s_sa[];
+    __shared__ double sdq[kMaxSiteAtoms];
+    __shared__ int order[kMaxSweepSites];
+    __shared__ double red[2][kSDE / kTile];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int sa0 = sd.sys_sa_offset[b], nsa = sd.sys_sa_offset[b + 1] - sa0;
+    double* sx = s_sa;
+    double* sy = sx + nsa;
+    double* sz = sy + nsa;
+    double* sR = sz + nsa;
+    double* sA = sR + nsa;
+    double* sphi = sA + nsa;
+    for (int a = t; a < nsa; a += kSDE) {
+        const int g = sd.site_atoms[sa0 + a];
+        const double R = R64[g];
+        sx[a] = X[g]; sy[a] = Y[g]; sz[a] = Z[g];
+        sR[a] = R; sA[a] = A64[g];
+        sphi[a] = (double)(long long)phi_fx[sa0 + a] * (1.0 / kScaleP) - kT * (double)Q[g] / R;
+    }
+    const double kTB = kKB * T_kelvin;
+    for (int kind = 0; kind < 2; ++kind) {
+        if (!(kinds & (1 << kind))) continue;
+        const int o0 = kind == 0 ? sd.sys_prot_offset[b] : sd.sys_redox_offset[b];
+        const int cnt = (kind == 0 ? sd.sys_prot_offset[b + 1] : sd.sys_redox_offset[b + 1]) - o0;
+        const int32_t* list = (kind == 0 ? sd.sys_prot_sites : sd.sys_redox_sites) + o0;
+        __syncthreads();
+        // rank of each site by (u[3m], m); a NaN key sorts last, so the ranks
+        // always form a permutation
+        auto order_key = [&](int m) {
+            const double k = u[3 * (size_t)m];
+            return k == k ? k : 2.0;
+        };
+        for (int k = t; k < cnt; k += kSDE) {
+            const int m = list[k];
+            const double key = order_key(m);
+            int rank = 0;
+            for (int j = 0; j < cnt; ++j) {
+                const int mj = list[j];
+                const double kj = order_key(mj);
+                rank += (kj < key) || (kj == key && mj < m);
+            }
+            order[rank] = m;
+        }
+        __syncthreads();
+        const double drive = kind == 0 ? kKB * T_kelvin * kLn10 * pH[b] : kFaraday * E_volt[b];
+        for (int v = 0; v < cnt; ++v) {
+            const int m = order[v];
+            const int a0 = sd.site_atom_offset[m] - sa0;
+            const int na = sd.site_atom_offset[m + 1] - sd.site_atom_offset[m];
+            const int g0 = sd.site_state_offset[m];
+            const int ns = sd.site_state_offset[m + 1] - g0;
+            const int s = current_state[m];
+            const int tp = pick_index(u[3 * (size_t)m + 1], ns - 1);
+            const int s_new = tp < s ? tp : tp + 1;
+            const double* qn = sd.state_charges + sd.state_charge_offset[g0 + s_new];
+            const double* qo = sd.state_charges + sd.state_charge_offset[g0 + s];
+            for (int a = t; a < na; a += kSDE) sdq[a] = qn[a] - qo[a];
+            __syncthreads();
+            double part[2] = {0.0, 0.0};
+            for (int a = t; a < na; a += kSDE) part[0] += sdq[a] * sphi[a0 + a];
+            const int n_tri = na * (na + 1) / 2;
+#pragma unroll 1
+            for (int p = t; p < n_tri; p += kSDE) {
+                int c = (int)((sqrt(8.0 * p + 1.0) - 1.0) * 0.5);
+                c += (c + 1) * (c + 2) / 2 <= p;
+                c -= c * (c + 1) / 2 > p;
+                const int a = p - c * (c + 1) / 2;
+                const int ia = a0 + a, ic = a0 + c;
+                const double K = (a == c) ? -kT / sR[ia]
+                                          : 2.0 * pairK(sx[ia] - sx[ic], sy[ia] - sy[ic], sz[ia] - sz[ic],
+                                                        sR[ia], sA[ia], sR[ic], sA[ic], kC, kT);
+                part[1] += sdq[a] * sdq[c] * K;
+            }
+            block_sum<2, kSDE / kTile>(red, part);
+            const double dE = part[0] + 0.5 * part[1];
+            const double dg = dE + drive * (double)(sd.state_count[g0 + s_new] - sd.state_count[g0 + s])
+                            - (sd.state_gref[g0 + s_new] - sd.state_gref[g0 + s]);
+            const bool acc = u[3 * (size_t)m + 2] < exp(-dg / kTB);
+            if (t == 0) {
+                if (accepted) accepted[m] = acc ? 1 : 0;
+                if (dG_out) dG_out[m] = dg;
+                if (counters) {
+                    counters[2 * (size_t)m] += 1;
+                    counters[2 * (size_t)m + 1] += acc ? 1 : 0;
+                }
+                if (acc) current_state[m] = s_new;
+            }
+            if (acc) {
+                // every site atom's potential gains K dq of this site
+                for (int i = t; i < nsa; i += kSDE) {
+                    double d = 0.0;
+                    for (int c = 0; c < na; ++c) {
+                        const int ic = a0 + c;
+                        d += sdq[c] * (i == ic ? -kT / sR[i]
+                                               : pairK(sx[i] - sx[ic], sy[i] - sy[ic], sz[i] - sz[ic],
+                                                       sR[i], sA[i], sR[ic], sA[ic], kC, kT));
+                    }
+                    sphi[i] += d;
+                }
+                for (int a = t; a < na; a += kSDE) Qout[sd.site_atoms[sa0 + a0 + a]] = (T)qn[a];
+            }
+            __syncthreads();
+        }
+    }
+    if (t == 0 && n_electrons) {
+        const int r0 = sd.sys_redox_offset[b], nr = sd.sys_redox_offset[b + 1] - r0;
+        int ne = 0;
+        for (int k = 0; k < nr; ++k) {
+            const int m = sd.sys_redox_sites[r0 + k];
+            ne += sd.state_count[sd.site_state_offset[m] + current_state[m]];
+        }
+        n_electrons[b] = ne;
+    }
+}
+
 // E-REMD exchange: one workgroup; pairs are disjoint so they update in parallel.
 __global__ __launch_bounds__(256) void k_remd_exchange(int M, const double* __restrict__ E_rung,
                                                        const int32_t* __restrict__ Ne,
@@ -1460,6 +1593,28 @@ hipError_t launch_mc_step(const SiteDev& sd, int n_sys, const T* x, const T* y, 
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_mc_sweep(const SiteDev& sd, int n_sys, int n_sa_max, const T* x, const T* y,
+                           const T* z, const T* q, T* q_out, const GBConst& c, const Work<T>& w,
+                           unsigned long long* phi_fx, int32_t* current_state, const double* pH,
+                           const double* E_volt, double T_kelvin, int kinds, const double* u,
+                           int32_t* n_electrons, int64_t* counters, int32_t* accepted, double* dG,
+                           hipStream_t s)
+{
+    if (n_sys == 0) return hipSuccess;
+    if (sd.n_rowitems > 0) {
+        hipLaunchKernelGGL(k_clear64, dim3(blocks_for(sd.n_site_atoms, 256)), dim3(256), 0, s, phi_fx,
+                           sd.n_site_atoms);
+        hipLaunchKernelGGL(k_site_phi_rows<T>, dim3(sd.n_rowitems), dim3(kTile), 0, s, sd.rowitems,
+                           sd.site_atoms, w.rows, q, c.kC, c.kT, phi_fx, w.ovf);
+    }
+    const size_t lds = (size_t)6 * sizeof(double) * (size_t)(n_sa_max > 0 ? n_sa_max : 1);
+    hipLaunchKernelGGL(k_mc_sweep<T>, dim3(n_sys), dim3(kSDE), lds, s, sd, x, y, z, q, q_out, w.R64,
+                       w.A64, c.kC, c.kT, phi_fx, current_state, pH, E_volt, T_kelvin, kinds, u,
+                       n_electrons, counters, accepted, dG);
+    return hipGetLastError();
+}
+
 hipError_t launch_remd_exchange(int M, const double* E_rung, const int32_t* Ne, int32_t* rep,
                                 double T_kelvin, int parity, int wrap, const double* u,
                                 int32_t* accepted, double* E_of_rep, hipStream_t s)
@@ -1489,7 +1644,13 @@ hipError_t launch_remd_exchange(int M, const double* E_rung, const int32_t* Ne, 
                                           const GBConst&, const Work<T>&, int32_t*,              \
                                           const double*, const double*, double, const double*,   \
                                           const double*, const double*, int32_t*, int64_t*,      \
-                                          int32_t*, hipStream_t, hipEvent_t*);
+                                          int32_t*, hipStream_t, hipEvent_t*);                   \
+    template hipError_t launch_mc_sweep<T>(const SiteDev&, int, int, const T*, const T*,          \
+                                           const T*, const T*, T*, const GBConst&,               \
+                                           const Work<T>&, unsigned long long*, int32_t*,        \
+                                           const double*, const double*, double, int,            \
+                                           const double*, int32_t*, int64_t*, int32_t*, double*, \
+                                           hipStream_t);
 
 GBMC_INSTANTIATE(float)
 GBMC_INSTANTIATE(double)

@@ -1,0 +1,143 @@
+"""GPU parity of mc_sweep (C ABI), the sequential all-site Monte Carlo sweep,
+against the oracle's sweep: per-site decisions and Delta G, final states and
+charges, electron counts, counters; one-kind sweeps; graph capture."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from gpu_common import build, params_pair
+
+pytestmark = pytest.mark.gpu
+
+KB, F = 1.98720426e-3, 23.0605478
+T, PH = 300.0, 7.0
+
+
+def _gref_near_balance(systems, p_or, seed):
+    """Reference free energies that put every proposed move near 50 %
+    acceptance at the starting state (Delta G ~ N(0, 0.5) kcal/mol)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for b, s in enumerate(systems):
+        R = oracle.radii(s, p_or)["R"]
+        dE0 = oracle.site_dE(s, R, p_or, tables=oracle.SiteTables(s))
+        E = synth.E_LADDER[b % len(synth.E_LADDER)]
+        c = 0
+        for site in s.sites:
+            g = np.zeros(site.n_states)
+            for t in range(site.n_states):
+                if t == site.state:
+                    continue
+                drive = (KB * T * math.log(10) * PH if site.kind == 0 else F * E) \
+                    * (site.counts[t] - site.counts[site.state])
+                g[t] = dE0[c] + drive + rng.normal(0.0, 0.5)
+                c += 1
+            out.append(g)
+    return np.concatenate(out) if out else np.zeros(0)
+
+
+def _run(prec, kinds, n_sys=6, seed=11):
+    p_gpu, p_or = params_pair()
+    systems = synth.config2(n_rep=n_sys)
+    g, batch, plan, atoms = build(systems, prec)
+    gref = _gref_near_balance(systems, p_or, seed)
+    sites = g.Sites.from_batch(plan, batch, gref)
+    E_sys = np.array([synth.E_LADDER[b % len(synth.E_LADDER)] for b in range(n_sys)])
+    cur = torch.as_tensor(batch.current_state, device=plan.device)
+    counters = torch.zeros((batch.n_sites, 2), dtype=torch.int64, device=plan.device)
+    u = synth.uniforms(seed + 1, (batch.n_sites, 3))
+    R = g.radii(plan, atoms, p_gpu)
+    out = g.mc_sweep(plan, sites, atoms, cur, PH, E_sys, torch.as_tensor(u, device=plan.device),
+                     T, p_gpu, kinds=kinds, counters=counters)
+    torch.cuda.synchronize()
+    return (systems, batch, gref, u, E_sys, R.double().cpu().numpy(), atoms.q.double().cpu().numpy(),
+            cur.cpu().numpy(), counters.cpu().numpy(), {k: v.cpu().numpy() for k, v in out.items()})
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("kinds", [3, 1, 2])
+def test_sweep_matches_oracle(prec, kinds):
+    _, p_or = params_pair()
+    systems, batch, gref, u, E_sys, R_gpu, q_gpu, cur, counters, out = _run(prec, kinds)
+    off, soff = batch.atom_offset, batch.site_state_offset
+    m0 = 0
+    n_acc = 0
+    tol = 1e-9 if prec == "fp64" else 2e-4
+    for b, s in enumerate(systems):
+        ns = len(s.sites)
+        g0, g1 = soff[m0], soff[m0 + ns]
+        tab = oracle.SiteTables(s, gref[g0:g1])
+        # the FP64 plan is compared with the oracle's radii, the FP32 plan with
+        # its own (the sweep itself is FP64 on both sides)
+        R = oracle.radii(s, p_or)["R"] if prec == "fp64" else R_gpu[off[b]:off[b + 1]]
+        q_or, acc_or, dG_or = oracle.mc_sweep(s, R, tab, PH, E_sys[b], T, u[m0:m0 + ns], kinds, p_or)
+        acc = out["accepted"][m0:m0 + ns]
+        dG = out["dG"][m0:m0 + ns]
+        for k in range(ns):
+            if acc_or[k] < 0:
+                assert acc[k] == -1
+                continue
+            assert abs(dG[k] - dG_or[k]) <= tol * max(1.0, abs(dG_or[k])), (b, k, dG[k], dG_or[k])
+            p = math.exp(min(700.0, -dG_or[k] / (KB * T)))
+            if abs(u[m0 + k, 2] - p) > 1e-6:            # skip coin flips at the margin
+                assert acc[k] == acc_or[k], (b, k)
+        if all(abs(u[m0 + k, 2] - math.exp(min(700.0, -dG_or[k] / (KB * T)))) > 1e-6
+               for k in range(ns) if acc_or[k] >= 0):
+            assert list(cur[m0:m0 + ns]) == list(tab.current_state), b
+            assert np.allclose(q_gpu[off[b]:off[b + 1]], q_or, rtol=0, atol=1e-6), b
+        n_acc += int((acc == 1).sum())
+        m0 += ns
+    att = out["accepted"] >= 0
+    assert np.array_equal(counters[:, 0], att.astype(np.int64))
+    assert np.array_equal(counters[:, 1], (out["accepted"] == 1).astype(np.int64))
+    assert n_acc > 0
+    # electron counts after the sweep
+    ne = np.zeros(batch.n_systems, dtype=np.int64)
+    for m in range(batch.n_sites):
+        if batch.site_kind[m] == 1:
+            ne[batch.site_system[m]] += batch.state_count[soff[m] + cur[m]]
+    assert np.array_equal(out["n_electrons"], ne)
+
+
+def test_sweep_graph_replay_matches_eager():
+    # a captured sweep (rows, potentials, sequential decisions) replayed from a
+    # reset state gives the eager result bitwise, replay after replay
+    p_gpu, _ = params_pair()
+    systems = synth.config2(n_rep=4)
+    g, batch, plan, atoms = build(systems, "fp32")
+    sites = g.Sites.from_batch(plan, batch, np.zeros(batch.state_count.size))
+    dev = plan.device
+    q0 = atoms.q.clone()
+    cur0 = torch.as_tensor(batch.current_state, device=dev)
+    cur = cur0.clone()
+    u = torch.as_tensor(synth.uniforms(5, (batch.n_sites, 3)), device=dev)
+    E_sys = torch.full((4,), -0.25, dtype=torch.float64, device=dev)
+    pH = torch.full((4,), PH, dtype=torch.float64, device=dev)
+    g.radii(plan, atoms, p_gpu)
+    ref = g.mc_sweep(plan, sites, atoms, cur, pH, E_sys, u, T, p_gpu)
+    torch.cuda.synchronize()
+    ref = {k: v.clone() for k, v in ref.items()}
+    ref_q, ref_cur = atoms.q.clone(), cur.clone()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        atoms.q.copy_(q0)
+        cur.copy_(cur0)
+        g.mc_sweep(plan, sites, atoms, cur, pH, E_sys, u, T, p_gpu)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        out = g.mc_sweep(plan, sites, atoms, cur, pH, E_sys, u, T, p_gpu)
+    for _ in range(3):
+        atoms.q.copy_(q0)
+        cur.copy_(cur0)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(atoms.q, ref_q) and torch.equal(cur, ref_cur)
+        for k in ref:
+            assert torch.equal(out[k], ref[k]), k
