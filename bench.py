@@ -234,6 +234,7 @@ def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial", 
     kernel_ms = w.plan.kernel_ms() if kernel_steps > 0 else {}
     # the Monte Carlo Delta E kernels on their own (no concurrent force passes)
     cur = w.atoms if k % 2 == 0 else w.atoms_b
+    w.latest = cur                     # the buffer holding the current charges
     for _ in range(max(1, kernel_steps // 2)):
         w.g.mc_state_dE(w.plan, w.sites, cur, w.cur, w.pH, w.E_rep, w.T, w.params)
     w.mc_alone_ms = w.plan.kernel_ms()
@@ -241,6 +242,41 @@ def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial", 
     w.exchanges_accepted = int(acc)
     w.exchanges_attempted = kernel_steps * int(w.last_exchange.numel()) if kernel_steps else 0
     return w, ms_step, wall / steps * 1e3, kernel_ms
+
+
+def time_sweep(w, reps=20):
+    """Sequential all-site sweeps (mc_sweep) on the batch: every site of every
+    replica attempted once per sweep (potential rows, then one workgroup per
+    replica), timed with HIP events over back-to-back calls.  Acceptances are
+    counted by the kernel itself (counters), so the timed loop holds nothing
+    but the sweeps."""
+    import torch
+    g, dev = w.g, w.plan.device
+    n_sites = w.sites.n_sites
+    cur = w.latest
+    g.radii(w.plan, cur, w.params)
+    state = w.cur.clone()
+    counters = torch.zeros((n_sites, 2), dtype=torch.int64, device=dev)
+    rng = torch.Generator(device=dev)
+    rng.manual_seed(99)
+    u = torch.rand((reps + 2, n_sites, 3), dtype=torch.float64, device=dev, generator=rng)
+    for k in range(2):
+        g.mc_sweep(w.plan, w.sites, cur, state, w.pH, w.E_rep, u[k], w.T, w.params,
+                   counters=counters)
+    counters.zero_()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for k in range(reps):
+        g.mc_sweep(w.plan, w.sites, cur, state, w.pH, w.E_rep, u[k + 2], w.T, w.params,
+                   counters=counters)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    tot = counters.sum(0).cpu().tolist()
+    return {"ms_per_sweep": ms, "site_attempts_per_s": n_sites / (ms * 1e-3),
+            "sites_per_sweep": n_sites, "sweeps": reps,
+            "acceptance": tot[1] / max(1, tot[0])}
 
 
 def cpu_baseline(systems, min_wall_s=1.5, max_passes=8):
@@ -381,6 +417,7 @@ def main():
                            "traffic_detail": detail,
                            "per_kernel_tflops": {n: FLOPS_PER_PAIR[n] * pairs / (v * 1e-3) / 1e12
                                                  for n, v in pair_k.items()}}
+    out["mc_sweep"] = time_sweep(w)
     cnt = w.counters.sum(0).cpu().tolist()
     out["mc_acceptance"] = {"state_attempts": cnt[0], "state_accepted": cnt[1],
                             "exchange_attempts_eager": w.exchanges_attempted,
