@@ -25,6 +25,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 KB = 1.98720426e-3        # kcal/(mol K)
 FARADAY = 23.0605478      # kcal/(mol V)
+ACC = 418.4               # kcal/mol/(amu A) in A/ps^2
 
 
 def build(force: bool = True) -> str:
@@ -105,6 +106,9 @@ def _declare(L):
     L.or_mc_step.argtypes = mc + [_I, _D]
     L.or_mc_run.argtypes = [C.c_int] + mc + [_I64, _I64]
     L.or_mc_sweep.argtypes = mc[:-1] + [C.c_int, _D, _I, _D]
+    L.or_langevin_step.restype = None
+    L.or_langevin_step.argtypes = [C.c_int] + xyz + [_D, _D, _D, C.POINTER(_Params), _D, C.c_double,
+                                                     _D, _D, _D, C.c_double, C.c_double, C.c_double]
     L.or_remd_exchange.restype = C.c_int
     L.or_remd_exchange.argtypes = [C.c_int, _D, _I, _I, C.c_double, C.c_int, C.c_int, _D, _I, _D]
 
@@ -345,3 +349,22 @@ def count_electrons(s, tables: SiteTables) -> int:
         if tables.site_kind[m] == 1:
             n += int(tables.state_count[int(tables.site_state_offset[m]) + int(tables.current_state[m])])
     return n
+
+
+def langevin_step(s, v, inv_mass, xi, dt: float, gamma: float, T: float, p: Params = IGB5,
+                  xref=None, k_restr: float = 0.0):
+    """One leapfrog Langevin step of system s (Loncharich, Brooks & Pastor
+    1992) on the Coulomb + GB forces plus an optional harmonic restraint to
+    xref [n, 3].  v and xi are [n, 3] (A/ps; standard normals), inv_mass [n]
+    in 1/amu, dt in ps, gamma in 1/ps.  Returns (x, y, z, v) after the step;
+    s is not modified."""
+    n = s.n
+    x, y, z = (a.copy() for a in _xyz(s))
+    vv = _d(np.asarray(v, dtype=np.float64).T).copy()          # [3, n] component-major
+    xr = None if xref is None else _d(np.asarray(xref, dtype=np.float64).T)
+    pc = p.c()
+    lib().or_langevin_step(n, _pd(x), _pd(y), _pd(z), _pd(_d(s.q)), _pd(_d(s.rho)),
+                           _pd(_d(s.screen)), C.byref(pc), _pd(xr), float(k_restr), _pd(vv),
+                           _pd(_d(inv_mass)), _pd(_d(np.asarray(xi, dtype=np.float64).T)),
+                           float(dt), float(gamma), float(T))
+    return x, y, z, vv.T.copy()

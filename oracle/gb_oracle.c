@@ -30,6 +30,11 @@
  * Monte Carlo (section II.A-B): Delta G of a proposed state is Eq. 8 (redox)
  * or Eq. 9 (protonation) in their multi-state form; Metropolis acceptance.
  * Replica exchange (section II.C): Eq. 14 and Eq. 15.
+ * Dynamics between attempts (section III.D: Langevin thermostat): the leapfrog
+ * Langevin scheme of Loncharich, Brooks and Pastor (Biopolymers 32, 523,
+ * 1992) on the electrostatic forces, plus an optional harmonic restraint of
+ * every atom to reference coordinates standing in for the bonded and van der
+ * Waals terms of a full force field.  Units: ps, amu, Angstrom/ps.
  */
 #include <math.h>
 #include <stdint.h>
@@ -39,6 +44,8 @@
 #define OR_KB 1.98720426e-3        /* kcal/(mol K): CODATA R / 4184 */
 #define OR_FARADAY 23.0605478      /* kcal/(mol V): CODATA F / 4184 */
 #define OR_LN10 2.302585092994045684
+/* 1 kcal/mol per (amu Angstrom) in Angstrom/ps^2: 4184 J / 1e-3 kg, in A^2/ps^2 */
+#define OR_ACC 418.4
 
 typedef struct {
     double alpha, beta, gamma, offset, eps_in, eps_out, coulomb_k;
@@ -552,4 +559,41 @@ int or_remd_exchange(int M, const double* E_rung, const int* Ne_of_rep, int* rep
     }
     for (int l = 0; l < M; ++l) E_of_rep[rep_of_rung[l]] = E_rung[l];
     return np;
+}
+
+/* One leapfrog Langevin step of one system (Loncharich, Brooks & Pastor 1992).
+ * With a = gamma dt / 2 and c = OR_ACC (kcal/mol/(amu A) -> A/ps^2), for every
+ * atom i and Cartesian component:
+ *   F    = -dE_elec/dx_i - k_restr (x_i - xref_i)       (E_elec: Coulomb + GB)
+ *   v_i <- [ (1 - a) v_i + dt c F / m_i + sqrt(2 gamma kB T dt c / m_i) xi ]
+ *          / (1 + a)
+ *   x_i <- x_i + dt v_i
+ * v is the half-step velocity v(t - dt/2) on entry and v(t + dt/2) on exit,
+ * [3n] component-major, A/ps;  inv_mass[n] in 1/amu (0 freezes an atom);
+ * xi[3n] standard normal deviates, component-major;  xref[3n] or NULL (no
+ * restraint);  dt in ps, gamma in 1/ps, T in K.  Forces are evaluated at the
+ * coordinates on entry with the full FP64 definition (or_energy_forces). */
+void or_langevin_step(int n, double* x, double* y, double* z, const double* q,
+                      const double* rho, const double* screen, const or_params* p,
+                      const double* xref, double k_restr, double* v, const double* inv_mass,
+                      const double* xi, double dt, double gamma, double T)
+{
+    double* F = malloc(sizeof(double) * 3 * (size_t)(n > 0 ? n : 1));
+    double E[2];
+    or_energy_forces(n, x, y, z, q, rho, screen, p, E, F, NULL, NULL, NULL, NULL);
+    double* pos[3] = {x, y, z};
+    double a = 0.5 * gamma * dt;
+    for (int c = 0; c < 3; ++c) {
+        for (int i = 0; i < n; ++i) {
+            double f = F[c * n + i];
+            if (xref) f -= k_restr * (pos[c][i] - xref[c * n + i]);
+            double im = inv_mass[i];
+            double sig = sqrt(2.0 * gamma * OR_KB * T * dt * OR_ACC * im);
+            double vi = ((1.0 - a) * v[c * n + i] + dt * OR_ACC * f * im + sig * xi[c * n + i])
+                      / (1.0 + a);
+            v[c * n + i] = vi;
+            pos[c][i] += dt * vi;
+        }
+    }
+    free(F);
 }
