@@ -273,6 +273,28 @@ gbmc_status mc_sweep(gbmc_plan* plan, const gbmc_sites* sites, const gbmc_atoms*
                      int32_t kinds, const double* u, int32_t* n_electrons, int64_t* counters,
                      int32_t* accepted, double* dG, hipStream_t stream);
 
+/* One leapfrog Langevin step of every atom of the plan (Loncharich, Brooks &
+ * Pastor, Biopolymers 32 (1992) 523): the constant-charge dynamics between
+ * Monte Carlo attempts, with the Langevin thermostat of section III.D.  With
+ * a = gamma dt / 2, for atom i and component c:
+ *   F  = force[i][c] - k_restr (x_c - xref[c][i])    (restraint if xref given)
+ *   v' = [(1 - a) v + dt 418.4 F / m + sqrt(2 gamma kB T dt 418.4 / m) xi[c][i]]
+ *        / (1 + a)
+ *   x' = x + dt v'
+ * Units: Angstrom, ps, amu, kcal/mol (418.4 converts kcal/mol/(amu A) into
+ * A/ps^2).  x, y, z[N_tot] (positions, updated in place), v[3][N_tot]
+ * (half-step velocities v(t - dt/2) in, v(t + dt/2) out, A/ps), force[N_tot][3]
+ * (the force output of gb_energy_forces at x, or any force), inv_mass[N_tot]
+ * (1/amu; 0 with zero velocity holds an atom still), xi[3][N_tot] (standard normal deviates,
+ * drawn by the caller), xref[3][N_tot] (restraint centres, NULL for none):
+ * device arrays of the plan's float type, caller order; arithmetic in FP64.
+ * dt > 0 (ps), gamma >= 0 (1/ps), T >= 0 (K), k_restr >= 0 (kcal/mol/A^2).
+ * force must not alias x, y, z or v. */
+gbmc_status md_langevin_step(gbmc_plan* plan, void* x, void* y, void* z, void* v,
+                             const void* force, const void* inv_mass, const void* xi,
+                             const void* xref, double k_restr, double dt, double gamma, double T,
+                             hipStream_t stream);
+
 /* E-REMD exchange attempt (section II.C, Eqs. 14-15; pairing of section
  * III.B).  Rungs 0..M-1 are ordered by increasing redox potential E_rung[M]
  * (double, volt); rep_of_rung[M] (int32, in/out) holds the replica at each

@@ -569,7 +569,8 @@ int or_remd_exchange(int M, const double* E_rung, const int* Ne_of_rep, int* rep
  *          / (1 + a)
  *   x_i <- x_i + dt v_i
  * v is the half-step velocity v(t - dt/2) on entry and v(t + dt/2) on exit,
- * [3n] component-major, A/ps;  inv_mass[n] in 1/amu (0 freezes an atom);
+ * [3n] component-major, A/ps;  inv_mass[n] in 1/amu (0 with zero velocity
+ * holds an atom still);
  * xi[3n] standard normal deviates, component-major;  xref[3n] or NULL (no
  * restraint);  dt in ps, gamma in 1/ps, T in K.  Forces are evaluated at the
  * coordinates on entry with the full FP64 definition (or_energy_forces). */

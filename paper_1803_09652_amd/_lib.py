@@ -79,6 +79,7 @@ SIGNATURES = {
                        _VP, _VP, _VP, _D, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "mc_sweep": (_I32, [_VP, _VP, C.POINTER(gbmc_atoms), _VP, C.POINTER(gbmc_gb_params), _VP, _VP,
                         _VP, _VP, _VP, _D, _I32, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "md_langevin_step": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _D, _D, _D, _D, _VP]),
     "remd_exchange": (_I32, [_I32, _VP, _VP, _VP, _D, _I32, _I32, _VP, _VP, _VP, _VP]),
     "gbmc_plan_set_timing": (_I32, [_VP, _I32]),
     "gbmc_plan_kernel_ms": (_I32, [_VP, C.POINTER(C.c_float)]),

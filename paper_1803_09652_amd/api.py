@@ -366,6 +366,31 @@ def mc_sweep(plan: Plan, sites: Sites, atoms: Atoms, current_state: torch.Tensor
     return {"n_electrons": ne, "accepted": acc[:sites.n_sites], "dG": dG[:sites.n_sites]}
 
 
+def md_step(plan: Plan, atoms: Atoms, v: torch.Tensor, force: torch.Tensor,
+            inv_mass: torch.Tensor, xi: torch.Tensor, dt: float, gamma: float, T: float = 300.0,
+            xref: Optional[torch.Tensor] = None, k_restr: float = 0.0) -> None:
+    """One leapfrog Langevin step (Loncharich, Brooks & Pastor 1992) of every
+    atom: atoms.x/y/z and v [3, N] (A/ps) are updated in place from force
+    [N, 3] (kcal/mol/A, e.g. energy_forces()["force"]), inv_mass [N] (1/amu),
+    standard normals xi [3, N] and an optional harmonic restraint to xref
+    [3, N] (k_restr kcal/mol/A^2); dt in ps, gamma in 1/ps."""
+    n, dt_ = plan.n_atoms, plan.dtype
+
+    def chk(t, shape, name):
+        if t.dtype != dt_ or tuple(t.shape) != shape or not t.is_contiguous() or t.device != plan.device:
+            raise ValueError(f"{name} must be a contiguous {dt_} tensor {shape} on the plan's device")
+    chk(v, (3, n), "v")
+    chk(force, (n, 3), "force")
+    chk(inv_mass, (n,), "inv_mass")
+    chk(xi, (3, n), "xi")
+    if xref is not None:
+        chk(xref, (3, n), "xref")
+    L.check(L.load().md_langevin_step(plan.handle, _ptr(atoms.x), _ptr(atoms.y), _ptr(atoms.z),
+                                      _ptr(v), _ptr(force), _ptr(inv_mass), _ptr(xi), _ptr(xref),
+                                      float(k_restr), float(dt), float(gamma), float(T),
+                                      _stream(plan.device)))
+
+
 def remd_exchange(E_rung: torch.Tensor, Ne_of_rep: torch.Tensor, rep_of_rung: torch.Tensor,
                   parity: int, u: torch.Tensor, T: float = 300.0, wrap: bool = True,
                   E_out: Optional[torch.Tensor] = None):

@@ -881,6 +881,32 @@ gbmc_status remd_exchange(int32_t M, const double* E_rung, const int32_t* Ne, in
     return e == hipSuccess ? GBMC_OK : hip_fail(e, "remd_exchange launch");
 }
 
+gbmc_status md_langevin_step(gbmc_plan* p, void* x, void* y, void* z, void* v, const void* force,
+                             const void* inv_mass, const void* xi, const void* xref, double k_restr,
+                             double dt, double gamma, double T, hipStream_t stream)
+{
+    if (!p) return fail(GBMC_ERR_INVALID, "plan is NULL");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(GBMC_ERR_INVALID, "dt must be > 0");
+    if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(GBMC_ERR_INVALID, "gamma must be >= 0");
+    if (!(T >= 0.0) || !std::isfinite(T)) return fail(GBMC_ERR_INVALID, "temperature must be >= 0");
+    if (!(k_restr >= 0.0) || !std::isfinite(k_restr))
+        return fail(GBMC_ERR_INVALID, "restraint constant must be >= 0");
+    if (p->n_atoms == 0) return GBMC_OK;
+    if (!x || !y || !z || !v || !force || !inv_mass || !xi)
+        return fail(GBMC_ERR_INVALID, "a dynamics array is NULL");
+    hipError_t e;
+    if (p->prec == GBMC_FP32_FIXED)
+        e = launch_md_langevin<float>(p->n_atoms, (float*)x, (float*)y, (float*)z, (float*)v,
+                                      (const float*)force, (const float*)inv_mass, (const float*)xi,
+                                      (const float*)xref, k_restr, dt, gamma, T, stream);
+    else
+        e = launch_md_langevin<double>(p->n_atoms, (double*)x, (double*)y, (double*)z, (double*)v,
+                                       (const double*)force, (const double*)inv_mass,
+                                       (const double*)xi, (const double*)xref, k_restr, dt, gamma,
+                                       T, stream);
+    return e == hipSuccess ? GBMC_OK : hip_fail(e, "md_langevin_step launch");
+}
+
 gbmc_status gbmc_check_overflow(const gbmc_plan* p, void* ws, hipStream_t s, int32_t* flag)
 {
     if (!p || !ws || !flag) return fail(GBMC_ERR_INVALID, "NULL argument");

@@ -16,6 +16,9 @@ constexpr int kMaxSweepSiteAtoms = 1024;  // site atoms per system in mc_sweep (
 #endif
 constexpr int kPhiChunk = GBMC_PHI_CHUNK;            // j atoms per FP64 potential-row work item
 
+constexpr double kKB = 1.98720426e-3;      // kcal/(mol K)
+constexpr double kFaraday = 23.0605478;    // kcal/(mol V)
+
 // Fixed-point scales (powers of two, so scaling is exact).
 constexpr double kScaleI = 4503599627370496.0;   // 2^52: descreening sums, 1/A
 constexpr double kScaleF = 1099511627776.0;      // 2^40: forces, dE/dR, dE/dq, dE/drho
@@ -154,6 +157,10 @@ hipError_t launch_mc_sweep(const SiteDev& sd, int n_sys, int n_sa_max, const T* 
                            const double* E_volt, double T_kelvin, int kinds, const double* u,
                            int32_t* n_electrons, int64_t* counters, int32_t* accepted, double* dG,
                            hipStream_t s);
+template <typename T>
+hipError_t launch_md_langevin(int n, T* x, T* y, T* z, T* v, const T* force, const T* inv_mass,
+                              const T* xi, const T* xref, double k_restr, double dt, double gamma,
+                              double T_kelvin, hipStream_t s);
 hipError_t launch_remd_exchange(int M, const double* E_rung, const int32_t* Ne, int32_t* rep,
                                 double T_kelvin, int parity, int wrap, const double* u,
                                 int32_t* accepted, double* E_of_rep, hipStream_t s);

@@ -34,8 +34,6 @@ namespace gbmc {
 #include "hct_poly.inc"
 
 constexpr double kLn2 = 0.693147180559945309;
-constexpr double kKB = 1.98720426e-3;      // kcal/(mol K)
-constexpr double kFaraday = 23.0605478;    // kcal/(mol V)
 constexpr double kLn10 = 2.302585092994045684;
 // sqrt(log2(e) / 4): a_i a_j r^2 = r^2 log2(e) / (4 R_i R_j)
 constexpr double kAScale = 0.60056120439322491;

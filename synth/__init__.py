@@ -25,6 +25,8 @@ in FP64 and rounded to FP32, so that both sides see identical inputs):
   pattern summing to +1 e.  Five states is the discrete-state carboxylate model
   (one deprotonated and four protonated tautomers) of the glutamate and
   propionate sites titrated in section III.C.
+* dynamics: masses ~ U[12, 16] amu (heavy atoms, hydrogens folded in),
+  Maxwell-Boltzmann starting velocities, standard normal Langevin noise.
 
 Generators are ``numpy.random.Generator(PCG64(seed))``.
 """
@@ -258,6 +260,29 @@ def config2(n_rep: int = 16) -> List[System]:
     return [perturb(base, 2 + 1000 * r) for r in range(n_rep)]
 
 
+# Dynamics on the electrostatics alone: the globules carry no bonded or van der
+# Waals terms and no exclusions, so every atom is held near its start by a
+# harmonic restraint of this stiffness (kcal/mol/A^2), stiff enough that no
+# oppositely charged close pair of the config-1 globule can collapse.
+MD_RESTRAINT = 2000.0
+
+
+def config2_md(n_rep: int = 16) -> List[System]:
+    """E-REMD replicas for dynamics: the config-1 globule unperturbed (the
+    perturbed replicas hold pairs closer than any restraint can keep apart),
+    each replica with its own random site states."""
+    base = config1()[0]
+    out = []
+    for r in range(n_rep):
+        rng = rng_for(5 + 1000 * r)
+        rep = base.copy()
+        for s in rep.sites:
+            s.state = int(rng.integers(0, s.n_states))
+        _apply_states(rep)
+        out.append(rep)
+    return out
+
+
 def config3() -> List[System]:
     return [make_system(3, 10000, 26.0)]
 
@@ -364,3 +389,23 @@ def uniforms(seed: int, shape) -> np.ndarray:
     """FP64 uniforms in [0, 1) for the Monte Carlo decisions (passed as inputs
     to both sides)."""
     return rng_for(seed).random(size=shape)
+
+
+def normals(seed: int, shape) -> np.ndarray:
+    """FP64 standard normal deviates (the Langevin noise; passed as inputs to
+    both sides)."""
+    return rng_for(seed).standard_normal(size=shape)
+
+
+def masses(seed: int, n: int) -> np.ndarray:
+    """Atomic masses in amu for the dynamics: heavy atoms only, uniform in
+    [12, 16] (carbon to oxygen; hydrogens are folded into their heavy atoms, so
+    the 2 fs step needs no bond constraints), FP32-representable."""
+    return f32(rng_for(seed).uniform(12.0, 16.0, size=n))
+
+
+def thermal_velocities(seed: int, m: np.ndarray, T: float = 300.0) -> np.ndarray:
+    """Maxwell-Boltzmann velocities [n, 3] in A/ps (kB T / m per component,
+    with 1 kcal/mol/amu = 418.4 A^2/ps^2)."""
+    sd = np.sqrt(1.98720426e-3 * T * 418.4 / np.asarray(m, dtype=np.float64))
+    return rng_for(seed).standard_normal(size=(len(m), 3)) * sd[:, None]
