@@ -54,6 +54,8 @@ def parse():
                          "(by default it runs on a second stream beside them, with "
                          "double-buffered charges)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--md-steps", type=int, default=100,
+                    help="steps of the timed simulation loop (0: skip)")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 64 MiB device copy (reference for HBM counters)")
@@ -63,6 +65,28 @@ def parse():
     ap.add_argument("--order", choices=["spatial", "identity"], default="spatial",
                     help="processing order of the pair passes (results are order independent)")
     return ap.parse_args()
+
+
+def reference_gref(g, plan, b, atoms, cur, pH, E_rep, T, params):
+    """Reference free energies of every state (Eqs. 8 and 9): Delta G_elec,ref
+    is the Delta E of the starting geometry and states (radii() already run),
+    plus the reference compound's E0 / pKa term."""
+    import numpy as np
+    sites0 = g.Sites.from_batch(plan, b)
+    dE0, _ = g.mc_state_dE(plan, sites0, atoms, cur, pH, E_rep, T, params)
+    dE0 = dE0.cpu().numpy()
+    gref = np.zeros(b.state_count.size)
+    c = 0
+    for m in range(b.n_sites):
+        g0, g1 = int(b.site_state_offset[m]), int(b.site_state_offset[m + 1])
+        c0 = int(b.current_state[m])
+        ref = FARADAY * E0_REF if b.site_kind[m] == 1 else KB * T * math.log(10) * PKA_REF
+        for t in range(g1 - g0):
+            if t == c0:
+                continue
+            gref[g0 + t] = dE0[c] + ref * (b.state_count[g0 + t] - b.state_count[g0 + c0])
+            c += 1
+    return gref
 
 
 class Workload:
@@ -99,24 +123,9 @@ class Workload:
         self.E_rep = self.E_rung.clone()                   # replica r starts on rung r
         self.pH = torch.full((self.B,), synth.PH_DEFAULT, dtype=torch.float64, device=dev)
         self.cur = torch.as_tensor(b.current_state, device=dev)
-        # Gref: dG_elec,ref = Delta E of the starting geometry and states, plus
-        # the reference E0 / pKa terms (Eqs. 8 and 9)
-        sites0 = g.Sites.from_batch(self.plan, b)
         g.radii(self.plan, self.atoms, self.params)
-        dE0, _ = g.mc_state_dE(self.plan, sites0, self.atoms, self.cur, self.pH, self.E_rep,
-                               self.T, self.params)
-        dE0 = dE0.cpu().numpy()
-        gref = np.zeros(b.state_count.size)
-        c = 0
-        for m in range(b.n_sites):
-            g0, g1 = int(b.site_state_offset[m]), int(b.site_state_offset[m + 1])
-            cur = int(b.current_state[m])
-            ref = FARADAY * E0_REF if b.site_kind[m] == 1 else KB * self.T * math.log(10) * PKA_REF
-            for t in range(g1 - g0):
-                if t == cur:
-                    continue
-                gref[g0 + t] = dE0[c] + ref * (b.state_count[g0 + t] - b.state_count[g0 + cur])
-                c += 1
+        gref = reference_gref(g, self.plan, b, self.atoms, self.cur, self.pH, self.E_rep, self.T,
+                              self.params)
         self.sites = g.Sites.from_batch(self.plan, b, gref)
         rng = torch.Generator(device=dev)
         rng.manual_seed(2024)
@@ -279,6 +288,59 @@ def time_sweep(w, reps=20):
             "acceptance": tot[1] / max(1, tot[0])}
 
 
+def time_md_loop(steps, warmup, n_rep=16, attempt_every=5, exchange_every=10):
+    """The simulation loop (ReplicaMD) on the E-REMD batch for dynamics: 16
+    replicas x 2,500 atoms, 2 fs Langevin steps (gamma 5 / ps, every atom
+    restrained), a Monte Carlo attempt pair every 5 steps (10 fs, the
+    implicit-solvent attempt interval of section III.D) and an exchange
+    attempt every 10 steps (20 fs: EAF 50 / ps, the highest of section III.D).  Every
+    step is radii + energy / forces + Langevin update; timed with HIP events
+    over `steps` eager steps after `warmup`."""
+    import numpy as np
+    import torch
+    import paper_1803_09652_amd as g
+    import synth
+    from paper_1803_09652_amd.runtime import ReplicaMD
+    systems = synth.config2_md(n_rep)
+    b = synth.make_batch(systems)
+    plan = g.Plan(b.atom_offset, "fp32")
+    plan.set_order(g.spatial_order(b.atom_offset, b.x, b.y, b.z))
+    atoms = g.Atoms.from_batch(plan, b)
+    dev, T, params = plan.device, 300.0, g.IGB5
+    E_rung = np.array(synth.E_LADDER[:n_rep])
+    cur = torch.as_tensor(b.current_state, device=dev)
+    pH = torch.full((n_rep,), synth.PH_DEFAULT, dtype=torch.float64, device=dev)
+    g.radii(plan, atoms, params)
+    gref = reference_gref(g, plan, b, atoms, cur, pH, torch.as_tensor(E_rung, device=dev), T, params)
+    sites = g.Sites.from_batch(plan, b, gref)
+    m = synth.masses(3, b.n_atoms)
+    loop = ReplicaMD(plan, sites, atoms, b.current_state, 1.0 / m,
+                     synth.thermal_velocities(4, m, T).T, synth.PH_DEFAULT, E_rung, dt=0.002,
+                     gamma=5.0, T=T, attempt_every=attempt_every, exchange_every=exchange_every,
+                     params=params, xref=np.stack([b.x, b.y, b.z]), k_restr=synth.MD_RESTRAINT,
+                     seed=6)
+    loop.run(warmup, record=False)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    loop.run(steps, record=False)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / steps
+    cnt = loop.counters.sum(0).cpu().tolist()
+    ns_day = 0.002 * 86400.0 / (ms * 1e-3) / 1000.0     # ns of one replica per day
+    return {"workload": f"{n_rep} replicas x {b.n_atoms // n_rep} atoms, dt 2 fs, attempt every "
+                        f"{attempt_every} steps, exchange every {exchange_every} steps",
+            "ms_per_md_step": ms, "wall_ms_per_md_step": wall / steps * 1e3, "steps": steps,
+            "ns_per_day_per_replica": ns_day, "ns_per_day_all_replicas": ns_day * n_rep,
+            "pair_interactions_per_s": sum(s.n * (s.n - 1) // 2 for s in systems) / (ms * 1e-3),
+            "state_attempts": cnt[0], "state_accepted": cnt[1],
+            "exchange_pairs_accepted": loop.exchanges_accepted,
+            "overflow": bool(g.check_overflow(plan))}
+
+
 def cpu_baseline(systems, min_wall_s=1.5, max_passes=8):
     """The FP64 oracle as it stands, on the host cores: whole passes over every
     replica of the batch (full evaluation + every candidate Delta E), repeated
@@ -418,6 +480,8 @@ def main():
                            "per_kernel_tflops": {n: FLOPS_PER_PAIR[n] * pairs / (v * 1e-3) / 1e12
                                                  for n, v in pair_k.items()}}
     out["mc_sweep"] = time_sweep(w)
+    if args.md_steps > 0:
+        out["md_loop"] = time_md_loop(args.md_steps, 10)
     cnt = w.counters.sum(0).cpu().tolist()
     out["mc_acceptance"] = {"state_attempts": cnt[0], "state_accepted": cnt[1],
                             "exchange_attempts_eager": w.exchanges_attempted,
