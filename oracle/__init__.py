@@ -54,13 +54,14 @@ def lib():
 
 class _Params(C.Structure):
     _fields_ = [(n, C.c_double) for n in
-                ("alpha", "beta", "gamma", "offset", "eps_in", "eps_out", "coulomb_k")]
+                ("alpha", "beta", "gamma", "offset", "eps_in", "eps_out", "coulomb_k", "kappa")]
 
 
 @dataclass(frozen=True)
 class Params:
     """GB-OBC parameters.  Default: the OBC 'igb=5' set (alpha, beta, gamma =
-    1.0, 0.8, 4.85), offset 0.09 A, eps_in 1, eps_out 78.5, k = 332.0522."""
+    1.0, 0.8, 4.85), offset 0.09 A, eps_in 1, eps_out 78.5, k = 332.0522, no
+    salt (kappa, the inverse Debye length in 1/A, = 0)."""
     alpha: float = 1.0
     beta: float = 0.8
     gamma: float = 4.85
@@ -68,10 +69,11 @@ class Params:
     eps_in: float = 1.0
     eps_out: float = 78.5
     coulomb_k: float = 332.0522
+    kappa: float = 0.0
 
     def c(self) -> _Params:
         return _Params(self.alpha, self.beta, self.gamma, self.offset, self.eps_in,
-                       self.eps_out, self.coulomb_k)
+                       self.eps_out, self.coulomb_k, self.kappa)
 
 
 IGB5 = Params()

@@ -24,7 +24,10 @@
  *   R_i = 1 / (1/rt_i - tanh(theta_i)/rho_i)
  *   f_ij = sqrt(r^2 + R_i R_j exp(-r^2/(4 R_i R_j))),  f_ii = R_i
  *   E_C  = k sum_{i<j} q_i q_j / (eps_in r_ij)
- *   E_GB = -(k tau / 2) sum_i sum_j q_i q_j / f_ij,  tau = 1/eps_in - 1/eps_out
+ *   E_GB = -(k / 2) sum_i sum_j q_i q_j d(f_ij) / f_ij,
+ *   d(f) = 1/eps_in - exp(-kappa f)/eps_out   (salt: the Debye-Hueckel factor
+ *          of Srinivasan et al., Theor. Chem. Acc. 101 (1999) 426; with
+ *          kappa = 0, d = tau = 1/eps_in - 1/eps_out)
  * Units: Angstrom, elementary charge, kcal/mol, volt, kelvin.
  *
  * Monte Carlo (section II.A-B): Delta G of a proposed state is Eq. 8 (redox)
@@ -49,6 +52,7 @@
 
 typedef struct {
     double alpha, beta, gamma, offset, eps_in, eps_out, coulomb_k;
+    double kappa;   /* inverse Debye length (1/A); 0: no salt */
 } or_params;
 
 double or_kb(void) { return OR_KB; }
@@ -139,7 +143,19 @@ void or_radii(int n, const double* x, const double* y, const double* z,
     }
 }
 
-static inline double tau_of(const or_params* p) { return 1.0 / p->eps_in - 1.0 / p->eps_out; }
+/* Dielectric factor of one GB pair term (or self term, f = R_i):
+ * d(f) = 1/eps_in - exp(-kappa f)/eps_out. */
+static inline double gb_d(const or_params* p, double f)
+{
+    return 1.0 / p->eps_in - exp(-p->kappa * f) / p->eps_out;
+}
+
+/* Its slope factor: d/df [d(f)/f] = -gb_s(f) / f^2 with
+ * gb_s(f) = d(f) - kappa f exp(-kappa f) / eps_out (= tau when kappa = 0). */
+static inline double gb_s(const or_params* p, double f)
+{
+    return gb_d(p, f) - p->kappa * f * exp(-p->kappa * f) / p->eps_out;
+}
 
 /* Still's f_GB and its partials for i != j. */
 static inline void fgb(double r, double Ri, double Rj, double* f, double* ex, double* D)
@@ -154,38 +170,38 @@ static inline void fgb(double r, double Ri, double Rj, double* f, double* ex, do
 void or_energy_fixedR(int n, const double* x, const double* y, const double* z,
                       const double* q, const double* R, const or_params* p, double* out_E)
 {
-    double k = p->coulomb_k, tau = tau_of(p);
+    double k = p->coulomb_k;
     double ec = 0.0, eg = 0.0;
     #pragma omp parallel for schedule(dynamic, 16) reduction(+ : ec, eg)
     for (int i = 0; i < n; ++i) {
         double ci = 0.0, gi = 0.0;
         for (int j = 0; j < n; ++j) {
-            if (j == i) { gi += q[i] * q[i] / R[i]; continue; }
+            if (j == i) { gi += q[i] * q[i] * gb_d(p, R[i]) / R[i]; continue; }
             double r = dist(x, y, z, i, j), f, ex, D;
             fgb(r, R[i], R[j], &f, &ex, &D);
             if (j > i) ci += q[i] * q[j] / (p->eps_in * r);
-            gi += q[i] * q[j] / f;
+            gi += q[i] * q[j] * gb_d(p, f) / f;
         }
         ec += ci;
         eg += gi;
     }
     out_E[0] = k * ec;
-    out_E[1] = -0.5 * k * tau * eg;
+    out_E[1] = -0.5 * k * eg;
 }
 
 /* Charge gradient phi_i = dE/dq_i at given Born radii (self term included). */
 void or_phi_fixedR(int n, const double* x, const double* y, const double* z,
                    const double* q, const double* R, const or_params* p, double* phi)
 {
-    double k = p->coulomb_k, tau = tau_of(p);
+    double k = p->coulomb_k;
     #pragma omp parallel for schedule(dynamic, 16)
     for (int i = 0; i < n; ++i) {
-        double s = -k * tau * q[i] / R[i];
+        double s = -k * gb_d(p, R[i]) * q[i] / R[i];
         for (int j = 0; j < n; ++j) {
             if (j == i) continue;
             double r = dist(x, y, z, i, j), f, ex, D;
             fgb(r, R[i], R[j], &f, &ex, &D);
-            s += k * q[j] / (p->eps_in * r) - k * tau * q[j] / f;
+            s += k * q[j] / (p->eps_in * r) - k * gb_d(p, f) * q[j] / f;
         }
         phi[i] = s;
     }
@@ -200,7 +216,7 @@ void or_energy_forces(int n, const double* x, const double* y, const double* z,
                       const or_params* p, double* out_E, double* F, double* phi,
                       double* dEdrho, double* Gout, double* Rout)
 {
-    double k = p->coulomb_k, tau = tau_of(p);
+    double k = p->coulomb_k;
     double* I = malloc(sizeof(double) * n);
     double* R = malloc(sizeof(double) * n);
     double* T = malloc(sizeof(double) * n);
@@ -214,8 +230,8 @@ void or_energy_forces(int n, const double* x, const double* y, const double* z,
     #pragma omp parallel for schedule(dynamic, 16)
     for (int i = 0; i < n; ++i) {
         double fx = 0, fy = 0, fz = 0;
-        double g = 0.5 * k * tau * q[i] * q[i] / (R[i] * R[i]);
-        double ph = -k * tau * q[i] / R[i];
+        double g = 0.5 * k * gb_s(p, R[i]) * q[i] * q[i] / (R[i] * R[i]);
+        double ph = -k * gb_d(p, R[i]) * q[i] / R[i];
         for (int j = 0; j < n; ++j) {
             if (j == i) continue;
             double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
@@ -223,13 +239,14 @@ void or_energy_forces(int n, const double* x, const double* y, const double* z,
             fgb(r, R[i], R[j], &f, &ex, &D);
             double qq = q[i] * q[j];
             double dfdr = r / f * (1.0 - 0.25 * ex);
-            double dEdr = -k * qq / (p->eps_in * r * r) + k * tau * qq / (f * f) * dfdr;
+            double sf = gb_s(p, f);
+            double dEdr = -k * qq / (p->eps_in * r * r) + k * sf * qq / (f * f) * dfdr;
             fx -= dEdr * dx / r;
             fy -= dEdr * dy / r;
             fz -= dEdr * dz / r;
             double dfdRi = R[j] * ex * (1.0 + D) / (2.0 * f);
-            g += k * tau * qq / (f * f) * dfdRi;
-            ph += k * q[j] / (p->eps_in * r) - k * tau * q[j] / f;
+            g += k * sf * qq / (f * f) * dfdRi;
+            ph += k * q[j] / (p->eps_in * r) - k * gb_d(p, f) * q[j] / f;
         }
         if (F) { F[i] = fx; F[n + i] = fy; F[2 * n + i] = fz; }
         G[i] = g;
@@ -279,11 +296,11 @@ void or_energy_forces(int n, const double* x, const double* y, const double* z,
 static double pair_K(const double* x, const double* y, const double* z, const double* R,
                      const or_params* p, int i, int k)
 {
-    double kk = p->coulomb_k, tau = tau_of(p);
-    if (i == k) return -kk * tau / R[i];
+    double kk = p->coulomb_k;
+    if (i == k) return -kk * gb_d(p, R[i]) / R[i];
     double r = dist(x, y, z, i, k), f, ex, D;
     fgb(r, R[i], R[k], &f, &ex, &D);
-    return kk / (p->eps_in * r) - kk * tau / f;
+    return kk / (p->eps_in * r) - kk * gb_d(p, f) / f;
 }
 
 /* Delta E_elec of one candidate, bilinear form: dq.phi + 1/2 dq.K.dq
