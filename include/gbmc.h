@@ -49,8 +49,11 @@ typedef enum { GBMC_FP32_FIXED = 0, GBMC_FP64 = 1 } gbmc_precision;
  * AMBER's igb=2 set (section III.D/E: alpha 0.8, beta 0, gamma 2.909125); the
  * igb=5 set is alpha 1.0, beta 0.8, gamma 4.85.  offset is the dielectric
  * offset subtracted from every intrinsic radius (0.09 A); coulomb_k is the
- * Coulomb constant (332.0522 kcal A / (mol e^2)); kappa (inverse Debye length)
- * must be 0: salt screening is GBMC_ERR_UNSUPPORTED. */
+ * Coulomb constant (332.0522 kcal A / (mol e^2)); kappa >= 0 is the inverse
+ * Debye length (1/A) of added salt (the paper's runs have none: kappa = 0).
+ * With salt every GB pair and self term carries the Debye-Hueckel factor
+ * 1/eps_in - exp(-kappa f)/eps_out in place of 1/eps_in - 1/eps_out
+ * (Srinivasan et al., Theor. Chem. Acc. 101 (1999) 426). */
 typedef struct {
     double alpha, beta, gamma;
     double offset;
@@ -94,9 +97,8 @@ int32_t gbmc_version(void);
 /* Thread-local message describing the last failure of this thread. */
 const char* gbmc_last_error(void);
 
-/* Host-only check of GB parameters: GBMC_ERR_UNSUPPORTED for kappa != 0,
- * GBMC_ERR_INVALID for eps_in <= 0, eps_out <= 0, offset < 0 or non-finite
- * values. */
+/* Host-only check of GB parameters: GBMC_ERR_INVALID for kappa < 0,
+ * eps_in <= 0, eps_out <= 0, offset < 0 or non-finite values. */
 gbmc_status gbmc_params_validate(const gbmc_gb_params* params);
 
 /* Host-only: the pair-tile work list a plan with this layout would use for a
@@ -162,8 +164,9 @@ gbmc_status gb_radii(gbmc_plan* plan, const gbmc_atoms* atoms, const gbmc_gb_par
 /* Coulomb + GB energy and its derivatives, the electrostatics of the MD steps
  * between Monte Carlo attempts (section III.A, Fig. 1):
  *   E_C  = k sum_{i<j} q_i q_j / (eps_in r_ij)
- *   E_GB = -(k/2)(1/eps_in - 1/eps_out) sum_i sum_j q_i q_j / f_ij,
+ *   E_GB = -(k/2) sum_i sum_j q_i q_j d(f_ij) / f_ij,
  *   f_ij = sqrt(r^2 + R_i R_j exp(-r^2 / (4 R_i R_j))),  f_ii = R_i,
+ *   d(f) = 1/eps_in - exp(-kappa f)/eps_out  (1/eps_in - 1/eps_out without salt),
  * using the radii of the preceding gb_radii call on the same workspace and
  * atoms.  Outputs (each may be NULL):
  *   e_coul[B], e_gb[B]  double, per system;

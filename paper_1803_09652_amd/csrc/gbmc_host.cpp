@@ -230,6 +230,8 @@ static GBConst make_const(const gbmc_gb_params* gp)
     c.offset = gp->offset;
     c.kC = gp->coulomb_k / gp->eps_in;
     c.kT = gp->coulomb_k * (1.0 / gp->eps_in - 1.0 / gp->eps_out);
+    c.kO = gp->coulomb_k / gp->eps_out;
+    c.kappa = gp->kappa;
     return c;
 }
 
@@ -264,7 +266,7 @@ gbmc_status gbmc_params_validate(const gbmc_gb_params* p)
                         p->coulomb_k, p->kappa};
     for (double x : v)
         if (!std::isfinite(x)) return fail(GBMC_ERR_INVALID, "non-finite GB parameter");
-    if (p->kappa != 0.0) return fail(GBMC_ERR_UNSUPPORTED, "salt screening (kappa != 0) is not supported");
+    if (p->kappa < 0.0) return fail(GBMC_ERR_INVALID, "kappa must be >= 0");
     if (p->eps_in <= 0.0 || p->eps_out <= 0.0) return fail(GBMC_ERR_INVALID, "dielectric constants must be > 0");
     if (p->offset < 0.0) return fail(GBMC_ERR_INVALID, "offset must be >= 0");
     return GBMC_OK;

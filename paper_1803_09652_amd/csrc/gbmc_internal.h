@@ -109,6 +109,15 @@ struct GBConst {
     double alpha, beta, gamma, offset;
     double kC;      // k / eps_in
     double kT;      // k (1/eps_in - 1/eps_out)
+    double kO;      // k / eps_out
+    double kappa;   // inverse Debye length (1/A); 0: no salt
+};
+
+// Salt constants of the pair precision: kO = k/eps_out, kap = kappa,
+// kap2 = kappa log2(e) (exp(-kappa f) = exp2(-kap2 f)).
+template <typename T>
+struct SaltK {
+    T kO, kap, kap2;
 };
 
 // Kernel ids of the timing hook (events ev[2 id] / ev[2 id + 1] bracket a kernel).

@@ -34,6 +34,7 @@ namespace gbmc {
 #include "hct_poly.inc"
 
 constexpr double kLn2 = 0.693147180559945309;
+constexpr double kLog2e = 1.44269504088896340736;
 constexpr double kLn10 = 2.302585092994045684;
 // sqrt(log2(e) / 4): a_i a_j r^2 = r^2 log2(e) / (4 R_i R_j)
 constexpr double kAScale = 0.60056120439322491;
@@ -615,11 +616,11 @@ __global__ void k_radii_finalize(int n_atoms, const T* __restrict__ RHO, GBConst
 // Coulomb + GB energy, explicit pair forces, G = dE/dR, phi = dE/dq.
 
 // One work item of R (1 or 2) i blocks; see radii_item.
-template <typename T, bool GRAD, int R>
+template <typename T, bool GRAD, int R, bool SALT>
 __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* sj, T* sR, T* sA,
                                             const Q4<T>* __restrict__ P, const T* __restrict__ Rt,
                                             const T* __restrict__ At, T kC, T kT,
-                                            const Work<T>& wk)
+                                            const SaltK<T>& sk, const Work<T>& wk)
 {
     constexpr int NJ = GRAD ? 5 : 1;
     T xi[R], yi[R], zi[R], qi[R], Ri[R], ai[R];
@@ -695,18 +696,31 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
             T invf = rsq(f2);
             T qq = act ? qi[r] * p.w : T(0);
             eC[r] += qq * invr;
-            eG[r] += qq * invf;
+            // GB factor of the pair: k (1/eps_in - 1/eps_out) without salt;
+            // with salt kd = k (1/eps_in - exp(-kappa f)/eps_out) and the
+            // slope factor ks = kd - k kappa f exp(-kappa f)/eps_out
+            // (d/df (kd/f) = -ks/f^2)
+            T kd = kT, ks = kT;
+            if constexpr (SALT) {
+                const T f = f2 * invf;
+                const T es = sk.kO * exp2neg(sk.kap2 * f);
+                kd = kC - es;
+                ks = kd - es * sk.kap * f;
+                eG[r] += qq * kd * invf;
+            } else {
+                eG[r] += qq * invf;
+            }
             if constexpr (GRAD) {
                 T qj = act ? p.w : T(0);
                 T qi_ = act ? qi[r] : T(0);
-                T wgt = kC * invr - kT * invf;
+                T wgt = kC * invr - kd * invf;
                 phii[r] += wgt * qj;
                 T invf3 = invf * invf * invf;
                 T invr3 = invr * invr * invr;
-                T fr = qq * (kT * invf3 * (T(1) - T(0.25) * ex) - kC * invr3);   // (dE/dr)/r
+                T fr = qq * (ks * invf3 * (T(1) - T(0.25) * ex) - kC * invr3);   // (dE/dr)/r
                 T fx = fr * dx, fy = fr * dy, fz = fr * dz;
                 fxi[r] -= fx; fyi[r] -= fy; fzi[r] -= fz;
-                T cg = T(0.5) * kT * qq * invf3 * ex * (T(1) + t * T(kLn2));
+                T cg = T(0.5) * ks * qq * invf3 * ex * (T(1) + t * T(kLn2));
                 Gi[r] += cg * rj;
                 acc[0] += fx;
                 acc[1] += fy;
@@ -720,13 +734,21 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
         else
             walk_tile_rows2<T, NJ>(lane, aj, load, pair);
         if (R == 1 && J == w.I) {
-            // self terms: -(kT/2) q_i^2 / R_i in E_GB, -kT q_i / R_i in phi,
-            // (kT/2) q_i^2 / R_i^2 in G
+            // self terms (f_ii = R_i): -(kd/2) q_i^2 / R_i in E_GB, -kd q_i / R_i
+            // in phi, (ks/2) q_i^2 / R_i^2 in G
             T invR = rcp(Ri[0]);
-            eG[0] += T(0.5) * qi[0] * qi[0] * invR;
+            T kd = kT, ks = kT;
+            if constexpr (SALT) {
+                const T es = sk.kO * exp2neg(sk.kap2 * Ri[0]);
+                kd = kC - es;
+                ks = kd - es * sk.kap * Ri[0];
+                eG[0] += T(0.5) * qi[0] * qi[0] * kd * invR;
+            } else {
+                eG[0] += T(0.5) * qi[0] * qi[0] * invR;
+            }
             if constexpr (GRAD) {
-                phii[0] -= kT * qi[0] * invR;
-                Gi[0] += T(0.5) * kT * qi[0] * qi[0] * invR * invR;
+                phii[0] -= kd * qi[0] * invR;
+                Gi[0] += T(0.5) * ks * qi[0] * qi[0] * invR * invR;
             }
         }
         if constexpr (GRAD) {
@@ -753,7 +775,7 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             efix[r][0] += to_fixed((double)(kC * eC[r]), kScaleE, bad);
-            efix[r][1] += to_fixed((double)(-kT * eG[r]), kScaleE, bad);
+            efix[r][1] += to_fixed((double)(-(SALT ? T(1) : kT) * eG[r]), kScaleE, bad);
         }
     };
     tile(w.J0);
@@ -776,10 +798,10 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
     }
 }
 
-template <typename T, bool GRAD, int W>
+template <typename T, bool GRAD, int W, bool SALT>
 __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
     const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
-    const T* __restrict__ Rt, const T* __restrict__ At, T kC, T kT, Work<T> wk)
+    const T* __restrict__ Rt, const T* __restrict__ At, T kC, T kT, SaltK<T> sk, Work<T> wk)
 {
     __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, q
     __shared__ T sR_w[W][2 * kTile];
@@ -790,10 +812,11 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
     const WorkItem w = items[item];
     // two-row items exist in the energy pass of FP32 plans only
     if (sizeof(T) == 4 && w.rows == 2)
-        energy_item<T, GRAD, sizeof(T) == 4 ? 2 : 1>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P,
-                                                     Rt, At, kC, kT, wk);
+        energy_item<T, GRAD, sizeof(T) == 4 ? 2 : 1, SALT>(w, lane, sj_w[wave], sR_w[wave],
+                                                           sA_w[wave], P, Rt, At, kC, kT, sk, wk);
     else
-        energy_item<T, GRAD, 1>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P, Rt, At, kC, kT, wk);
+        energy_item<T, GRAD, 1, SALT>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P, Rt, At, kC,
+                                      kT, sk, wk);
 }
 
 // After pass 2, one launch: blocks [0, n_sum) sum the atoms' fixed-point
@@ -1022,15 +1045,25 @@ __global__ void k_grad_finalize(int n_atoms, const T* __restrict__ RHO, double o
 // each chunk's FP64 partial is added in 2^-44 fixed point, so the sum does not
 // depend on the order (deterministic) and k_site_dE reads one value per atom.
 
-// k/(eps_in r) - k tau / f_GB for one pair (FP64); a = 1/(2R).
+// k d(f), the GB factor of a pair term or a self term (f = R): kT = k (1/eps_in
+// - 1/eps_out) without salt, k (1/eps_in - exp(-kappa f)/eps_out) with
+// (kO = k/eps_out, kap = kappa).
+__device__ __forceinline__ double gb_kd(double f, double kC, double kT, double kO, double kap)
+{
+    return kap == 0.0 ? kT : kC - kO * exp(-kap * f);
+}
+
+// k/(eps_in r) - k d(f) / f_GB for one pair (FP64); a = 1/(2R).
 __device__ __forceinline__ double pairK(double dx, double dy, double dz, double Ra, double aa,
-                                        double Rb, double ab, double kC, double kT)
+                                        double Rb, double ab, double kC, double kT, double kO,
+                                        double kap)
 {
     double r2 = dx * dx + dy * dy + dz * dz;
     double invr = rsq64(r2);
     double ex = exp(-r2 * (aa * ab));
-    double invf = rsq64(fma(Ra * Rb, ex, r2));
-    return kC * invr - kT * invf;
+    double f2 = fma(Ra * Rb, ex, r2);
+    double invf = rsq64(f2);
+    return kC * invr - gb_kd(f2 * invf, kC, kT, kO, kap) * invf;
 }
 
 // One lane per site atom.  The chunk's j atoms (positions and radii of the
@@ -1039,7 +1072,8 @@ __device__ __forceinline__ double pairK(double dx, double dy, double dz, double 
 template <typename T>
 __global__ __launch_bounds__(kTile) void k_site_phi_rows(
     const RowItem* __restrict__ items, const int32_t* __restrict__ site_atoms,
-    const Row64* __restrict__ rows, const T* __restrict__ Q, double kC, double kT,
+    const Row64* __restrict__ rows, const T* __restrict__ Q, double kC, double kT, double kO,
+    double kap,
     unsigned long long* __restrict__ phi_fx, int* __restrict__ ovf)
 {
     __shared__ double2 s_xy[kPhiChunk], s_zR[kPhiChunk], s_Aq[kPhiChunk];
@@ -1063,7 +1097,7 @@ __global__ __launch_bounds__(kTile) void k_site_phi_rows(
 #pragma unroll 4
     for (int k = 0; k < nj; ++k) {
         const double2 xy = s_xy[k], zR = s_zR[k], Aq = s_Aq[k];
-        double K = pairK(ri.x - xy.x, ri.y - xy.y, ri.z - zR.x, ri.R, ri.A, zR.y, Aq.x, kC, kT);
+        double K = pairK(ri.x - xy.x, ri.y - xy.y, ri.z - zR.x, ri.R, ri.A, zR.y, Aq.x, kC, kT, kO, kap);
         acc += (k == self) ? 0.0 : Aq.y * K;
     }
     bool bad = false;
@@ -1117,7 +1151,7 @@ template <typename T>
 __global__ __launch_bounds__(kSDE) void k_site_dE(
     SiteDev sd, const T* __restrict__ X, const T* __restrict__ Y, const T* __restrict__ Z,
     const T* __restrict__ Q, const double* __restrict__ R64, const double* __restrict__ A64,
-    double kC, double kT, const unsigned long long* __restrict__ phi_fx,
+    double kC, double kT, double kO, double kap, const unsigned long long* __restrict__ phi_fx,
     const int32_t* __restrict__ current_state,
     const double* __restrict__ pH, const double* __restrict__ E_volt, double T_kelvin,
     double* __restrict__ dE, double* __restrict__ dG)
@@ -1141,7 +1175,7 @@ __global__ __launch_bounds__(kSDE) void k_site_dE(
         int g = sd.site_atoms[a0 + a];
         double R = R64[g];
         sx[a] = X[g]; sy[a] = Y[g]; sz[a] = Z[g]; sR[a] = R; sA[a] = A64[g];
-        double phi = -kT * (double)Q[g] / R;           // self term
+        double phi = -gb_kd(R, kC, kT, kO, kap) * (double)Q[g] / R;   // self term
         phi += (double)(long long)phi_fx[sa_site0 + a] * (1.0 / kScaleP);
         sphi[a] = phi;
         for (int c = 0; c < nc; ++c) {
@@ -1168,9 +1202,9 @@ __global__ __launch_bounds__(kSDE) void k_site_dE(
         b += (b + 1) * (b + 2) / 2 <= p;          // guard the rounding of the root
         b -= b * (b + 1) / 2 > p;
         const int a = p - b * (b + 1) / 2;
-        double K = (a == b) ? -kT / sR[a]
+        double K = (a == b) ? -gb_kd(sR[a], kC, kT, kO, kap) / sR[a]
                             : 2.0 * pairK(sx[a] - sx[b], sy[a] - sy[b], sz[a] - sz[b], sR[a], sA[a],
-                                          sR[b], sA[b], kC, kT);
+                                          sR[b], sA[b], kC, kT, kO, kap);
 #pragma unroll
         for (int c = 0; c < kMaxStates - 1; ++c)
             if (c < nc) part[kMaxStates - 1 + c] += sdq[c][a] * sdq[c][b] * K;
@@ -1205,7 +1239,8 @@ template <typename T>
 __global__ __launch_bounds__(kMC) void k_mc_step(
     SiteDev sd, const T* __restrict__ X, const T* __restrict__ Y, const T* __restrict__ Z,
     T* __restrict__ Q, const double* __restrict__ R64, const double* __restrict__ A64, double kC,
-    double kT, int32_t* __restrict__ current_state, const double* __restrict__ pH,
+    double kT, double kO, double kap, int32_t* __restrict__ current_state,
+    const double* __restrict__ pH,
     const double* __restrict__ E_volt, double T_kelvin, const double* __restrict__ dEin,
     const double* __restrict__ dGin, const double* __restrict__ u,
     int32_t* __restrict__ n_electrons, int64_t* __restrict__ counters,
@@ -1258,7 +1293,7 @@ __global__ __launch_bounds__(kMC) void k_mc_step(
                     int ga = sd.site_atoms[ar0 + a], gc = sd.site_atoms[ap0 + c];
                     double K = pairK((double)X[ga] - (double)X[gc], (double)Y[ga] - (double)Y[gc],
                                      (double)Z[ga] - (double)Z[gc], R64[ga], A64[ga], R64[gc],
-                                     A64[gc], kC, kT);
+                                     A64[gc], kC, kT, kO, kap);
                     part[0] += (qr1[a] - qr0[a]) * (qp1[c] - qp0[c]) * K;
                 }
                 block_sum<1, kMC / kTile>(red, part);
@@ -1314,7 +1349,7 @@ template <typename T>
 __global__ __launch_bounds__(kSDE) void k_mc_sweep(
     SiteDev sd, const T* __restrict__ X, const T* __restrict__ Y, const T* __restrict__ Z,
     const T* __restrict__ Q, T* __restrict__ Qout, const double* __restrict__ R64,
-    const double* __restrict__ A64, double kC, double kT,
+    const double* __restrict__ A64, double kC, double kT, double kO, double kap,
     const unsigned long long* __restrict__ phi_fx, int32_t* __restrict__ current_state,
     const double* __restrict__ pH, const double* __restrict__ E_volt, double T_kelvin, int kinds,
     const double* __restrict__ u, int32_t* __restrict__ n_electrons,
@@ -1337,7 +1372,8 @@ __global__ __launch_bounds__(kSDE) void k_mc_sweep(
         const double R = R64[g];
         sx[a] = X[g]; sy[a] = Y[g]; sz[a] = Z[g];
         sR[a] = R; sA[a] = A64[g];
-        sphi[a] = (double)(long long)phi_fx[sa0 + a] * (1.0 / kScaleP) - kT * (double)Q[g] / R;
+        sphi[a] = (double)(long long)phi_fx[sa0 + a] * (1.0 / kScaleP)
+                - gb_kd(R, kC, kT, kO, kap) * (double)Q[g] / R;
     }
     const double kTB = kKB * T_kelvin;
     for (int kind = 0; kind < 2; ++kind) {
@@ -1388,9 +1424,9 @@ __global__ __launch_bounds__(kSDE) void k_mc_sweep(
                 c -= c * (c + 1) / 2 > p;
                 const int a = p - c * (c + 1) / 2;
                 const int ia = a0 + a, ic = a0 + c;
-                const double K = (a == c) ? -kT / sR[ia]
+                const double K = (a == c) ? -gb_kd(sR[ia], kC, kT, kO, kap) / sR[ia]
                                           : 2.0 * pairK(sx[ia] - sx[ic], sy[ia] - sy[ic], sz[ia] - sz[ic],
-                                                        sR[ia], sA[ia], sR[ic], sA[ic], kC, kT);
+                                                        sR[ia], sA[ia], sR[ic], sA[ic], kC, kT, kO, kap);
                 part[1] += sdq[a] * sdq[c] * K;
             }
             block_sum<2, kSDE / kTile>(red, part);
@@ -1413,9 +1449,9 @@ __global__ __launch_bounds__(kSDE) void k_mc_sweep(
                     double d = 0.0;
                     for (int c = 0; c < na; ++c) {
                         const int ic = a0 + c;
-                        d += sdq[c] * (i == ic ? -kT / sR[i]
+                        d += sdq[c] * (i == ic ? -gb_kd(sR[i], kC, kT, kO, kap) / sR[i]
                                                : pairK(sx[i] - sx[ic], sy[i] - sy[ic], sz[i] - sz[ic],
-                                                       sR[i], sA[i], sR[ic], sA[ic], kC, kT));
+                                                       sR[i], sA[i], sR[ic], sA[ic], kC, kT, kO, kap));
                     }
                     sphi[i] += d;
                 }
@@ -1527,18 +1563,19 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
                            w.perm, x, y, z, q, rho, screen, (T)c.offset, w.P, w.Gx, w.F_fx, 8,
                            (int*)nullptr);
     if (pe.n_items > 0) {
-        if (grad)
-            GBMC_DISPATCH_W(pe.waves_per_group,
-                            GBMC_LAUNCH_TIMED(ev, kKEnergy, (k_energy_pairs<T, true, W>),
-                                              dim3(blocks_for(pe.n_items, W)), dim3(kTile * W), s,
-                                              pe.items, pe.n_items, w.P, w.R_t, w.a_t, (T)c.kC,
-                                              (T)c.kT, w))
-        else
-            GBMC_DISPATCH_W(pe.waves_per_group,
-                            GBMC_LAUNCH_TIMED(ev, kKEnergy, (k_energy_pairs<T, false, W>),
-                                              dim3(blocks_for(pe.n_items, W)), dim3(kTile * W), s,
-                                              pe.items, pe.n_items, w.P, w.R_t, w.a_t, (T)c.kC,
-                                              (T)c.kT, w))
+        const SaltK<T> sk{(T)c.kO, (T)c.kappa, (T)(c.kappa * kLog2e)};
+#define GBMC_ENERGY_LAUNCH(G_, S_)                                                                \
+    GBMC_DISPATCH_W(pe.waves_per_group,                                                          \
+                    GBMC_LAUNCH_TIMED(ev, kKEnergy, (k_energy_pairs<T, G_, W, S_>),              \
+                                      dim3(blocks_for(pe.n_items, W)), dim3(kTile * W), s,       \
+                                      pe.items, pe.n_items, w.P, w.R_t, w.a_t, (T)c.kC, (T)c.kT, \
+                                      sk, w))
+        if (c.kappa != 0.0) {
+            if (grad) GBMC_ENERGY_LAUNCH(true, true) else GBMC_ENERGY_LAUNCH(false, true)
+        } else {
+            if (grad) GBMC_ENERGY_LAUNCH(true, false) else GBMC_ENERGY_LAUNCH(false, false)
+        }
+#undef GBMC_ENERGY_LAUNCH
     }
     const int n_sum = (e_coul || e_gb) ? n_sys : 0;
     const int n_fin = grad ? blocks_for(n_atoms, 256) : 0;
@@ -1568,10 +1605,10 @@ hipError_t launch_state_dE(const SiteDev& sd, int n_atoms, const T* x, const T* 
         hipLaunchKernelGGL(k_clear64, dim3(blocks_for(sd.n_site_atoms, 256)), dim3(256), 0, s, phi_fx,
                            sd.n_site_atoms);
         GBMC_LAUNCH_TIMED(ev, kKSiteRows, k_site_phi_rows<T>, dim3(sd.n_rowitems), dim3(kTile), s,
-                          sd.rowitems, sd.site_atoms, w.rows, q, c.kC, c.kT, phi_fx, w.ovf);
+                          sd.rowitems, sd.site_atoms, w.rows, q, c.kC, c.kT, c.kO, c.kappa, phi_fx, w.ovf);
     }
     GBMC_LAUNCH_TIMED(ev, kKSiteDE, k_site_dE<T>, dim3(sd.n_sites), dim3(kSDE), s, sd, x, y, z, q,
-                      w.R64, w.A64, c.kC, c.kT, phi_fx, current_state, pH, E_volt, T_kelvin, dE,
+                      w.R64, w.A64, c.kC, c.kT, c.kO, c.kappa, phi_fx, current_state, pH, E_volt, T_kelvin, dE,
                       dG);
     return hipGetLastError();
 }
@@ -1586,7 +1623,7 @@ hipError_t launch_mc_step(const SiteDev& sd, int n_sys, const T* x, const T* y, 
 {
     if (n_sys == 0) return hipSuccess;
     GBMC_LAUNCH_TIMED(ev, kKMCStep, k_mc_step<T>, dim3(n_sys), dim3(kMC), s, sd, x, y, z, q, w.R64,
-                      w.A64, c.kC, c.kT, current_state, pH, E_volt, T_kelvin, dE, dG, u, n_electrons,
+                      w.A64, c.kC, c.kT, c.kO, c.kappa, current_state, pH, E_volt, T_kelvin, dE, dG, u, n_electrons,
                       counters, accepted);
     return hipGetLastError();
 }
@@ -1604,11 +1641,11 @@ hipError_t launch_mc_sweep(const SiteDev& sd, int n_sys, int n_sa_max, const T* 
         hipLaunchKernelGGL(k_clear64, dim3(blocks_for(sd.n_site_atoms, 256)), dim3(256), 0, s, phi_fx,
                            sd.n_site_atoms);
         hipLaunchKernelGGL(k_site_phi_rows<T>, dim3(sd.n_rowitems), dim3(kTile), 0, s, sd.rowitems,
-                           sd.site_atoms, w.rows, q, c.kC, c.kT, phi_fx, w.ovf);
+                           sd.site_atoms, w.rows, q, c.kC, c.kT, c.kO, c.kappa, phi_fx, w.ovf);
     }
     const size_t lds = (size_t)6 * sizeof(double) * (size_t)(n_sa_max > 0 ? n_sa_max : 1);
     hipLaunchKernelGGL(k_mc_sweep<T>, dim3(n_sys), dim3(kSDE), lds, s, sd, x, y, z, q, q_out, w.R64,
-                       w.A64, c.kC, c.kT, phi_fx, current_state, pH, E_volt, T_kelvin, kinds, u,
+                       w.A64, c.kC, c.kT, c.kO, c.kappa, phi_fx, current_state, pH, E_volt, T_kelvin, kinds, u,
                        n_electrons, counters, accepted, dG);
     return hipGetLastError();
 }

@@ -54,7 +54,9 @@ def test_params_validation(L):
     ok = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, 0.0)
     assert lib.gbmc_params_validate(C.byref(ok)) == L.GBMC_OK
     salt = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, 0.1)
-    assert lib.gbmc_params_validate(C.byref(salt)) == L.GBMC_ERR_UNSUPPORTED
+    assert lib.gbmc_params_validate(C.byref(salt)) == L.GBMC_OK
+    neg = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, -0.1)
+    assert lib.gbmc_params_validate(C.byref(neg)) == L.GBMC_ERR_INVALID
     assert b"kappa" in lib.gbmc_last_error()
     bad = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 0.0, 78.5, 332.0522, 0.0)
     assert lib.gbmc_params_validate(C.byref(bad)) == L.GBMC_ERR_INVALID
