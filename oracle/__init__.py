@@ -54,14 +54,17 @@ def lib():
 
 class _Params(C.Structure):
     _fields_ = [(n, C.c_double) for n in
-                ("alpha", "beta", "gamma", "offset", "eps_in", "eps_out", "coulomb_k", "kappa")]
+                ("alpha", "beta", "gamma", "offset", "eps_in", "eps_out", "coulomb_k", "kappa",
+                 "rgbmax", "cutoff")]
 
 
 @dataclass(frozen=True)
 class Params:
     """GB-OBC parameters.  Default: the OBC 'igb=5' set (alpha, beta, gamma =
     1.0, 0.8, 4.85), offset 0.09 A, eps_in 1, eps_out 78.5, k = 332.0522, no
-    salt (kappa, the inverse Debye length in 1/A, = 0)."""
+    salt (kappa, the inverse Debye length in 1/A, = 0), no cutoffs (rgbmax: the
+    descreening cutoff, cutoff: the pair cutoff of the energy terms, in A; 0 =
+    none)."""
     alpha: float = 1.0
     beta: float = 0.8
     gamma: float = 4.85
@@ -70,10 +73,12 @@ class Params:
     eps_out: float = 78.5
     coulomb_k: float = 332.0522
     kappa: float = 0.0
+    rgbmax: float = 0.0
+    cutoff: float = 0.0
 
     def c(self) -> _Params:
         return _Params(self.alpha, self.beta, self.gamma, self.offset, self.eps_in,
-                       self.eps_out, self.coulomb_k, self.kappa)
+                       self.eps_out, self.coulomb_k, self.kappa, self.rgbmax, self.cutoff)
 
 
 IGB5 = Params()
@@ -89,6 +94,10 @@ def _declare(L):
     L.or_hct.argtypes = [C.c_double] * 3
     L.or_hct_grad.restype = None
     L.or_hct_grad.argtypes = [C.c_double] * 3 + [_D]
+    L.or_hct_cut.restype = C.c_double
+    L.or_hct_cut.argtypes = [C.c_double] * 4
+    L.or_hct_cut_grad.restype = None
+    L.or_hct_cut_grad.argtypes = [C.c_double] * 4 + [_D]
     xyz = [_D, _D, _D]
     L.or_radii.argtypes = [C.c_int] + xyz + [_D, _D, C.POINTER(_Params), _D, _D, _D, _D]
     L.or_energy_fixedR.argtypes = [C.c_int] + xyz + [_D, _D, C.POINTER(_Params), _D]
@@ -135,6 +144,17 @@ def _pi(a):
 
 def hct(r: float, rt: float, S: float) -> float:
     return lib().or_hct(r, rt, S)
+
+
+def hct_cut(r: float, rt: float, S: float, c: float) -> float:
+    """H restricted to radius c around atom i (descreening cutoff)."""
+    return lib().or_hct_cut(r, rt, S, c)
+
+
+def hct_cut_grad(r: float, rt: float, S: float, c: float) -> np.ndarray:
+    out = np.zeros(3)
+    lib().or_hct_cut_grad(r, rt, S, c, _pd(out))
+    return out
 
 
 def hct_grad(r: float, rt: float, S: float) -> np.ndarray:

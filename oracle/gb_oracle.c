@@ -33,6 +33,10 @@
  * Monte Carlo (section II.A-B): Delta G of a proposed state is Eq. 8 (redox)
  * or Eq. 9 (protonation) in their multi-state form; Metropolis acceptance.
  * Replica exchange (section II.C): Eq. 14 and Eq. 15.
+ * Cutoffs (optional; the paper's runs have none): rgbmax restricts the
+ * descreening integral to the sphere of that radius around each atom
+ * (or_hct_cut); cutoff drops the Coulomb and GB pair terms of pairs at or
+ * beyond that distance (self terms stay).
  * Dynamics between attempts (section III.D: Langevin thermostat): the leapfrog
  * Langevin scheme of Loncharich, Brooks and Pastor (Biopolymers 32, 523,
  * 1992) on the electrostatic forces, plus an optional harmonic restraint of
@@ -53,6 +57,8 @@
 typedef struct {
     double alpha, beta, gamma, offset, eps_in, eps_out, coulomb_k;
     double kappa;   /* inverse Debye length (1/A); 0: no salt */
+    double rgbmax;  /* descreening cutoff (A); 0: none */
+    double cutoff;  /* pair cutoff of the energy terms (A); 0: none */
 } or_params;
 
 double or_kb(void) { return OR_KB; }
@@ -108,6 +114,36 @@ void or_hct_grad(double r, double rt, double S, double* out)
     }
 }
 
+/* H restricted to the sphere of radius c around atom i (the descreening
+ * cutoff): the part of ball j that lies inside radius c and outside rt,
+ *   H_c(r; rt, S) = H(r; rt, S) - H(r; c, S)   for c > rt,   0 for c <= rt,
+ * since H(r; c, S) is the part of ball j outside radius c.  c <= 0: no cutoff. */
+double or_hct_cut(double r, double rt, double S, double c)
+{
+    if (c <= 0.0) return or_hct(r, rt, S);
+    if (c <= rt) return 0.0;
+    return or_hct(r, rt, S) - or_hct(r, c, S);
+}
+
+/* Partials of or_hct_cut (dr, drt, dS); the c term does not depend on rt. */
+void or_hct_cut_grad(double r, double rt, double S, double c, double* out)
+{
+    or_hct_grad(r, rt, S, out);
+    if (c <= 0.0) return;
+    if (c <= rt) { out[0] = out[1] = out[2] = 0.0; return; }
+    double g[3];
+    or_hct_grad(r, c, S, g);
+    out[0] -= g[0];
+    out[2] -= g[2];
+}
+
+/* 1 if the pair at distance r lies beyond the energy cutoff (its Coulomb and
+ * GB pair terms are dropped; self terms never are). */
+static inline int beyond(const or_params* p, double r)
+{
+    return p->cutoff > 0.0 && r >= p->cutoff;
+}
+
 static inline double dist(const double* x, const double* y, const double* z, int i, int j)
 {
     double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
@@ -128,7 +164,7 @@ void or_radii(int n, const double* x, const double* y, const double* z,
         for (int j = 0; j < n; ++j) {
             if (j == i) continue;
             double Sj = screen[j] * (rho[j] - p->offset);
-            sum += or_hct(dist(x, y, z, i, j), rt, Sj);
+            sum += or_hct_cut(dist(x, y, z, i, j), rt, Sj, p->rgbmax);
         }
         double psi = rt * sum;
         double th = p->alpha * psi - p->beta * psi * psi + p->gamma * psi * psi * psi;
@@ -178,6 +214,7 @@ void or_energy_fixedR(int n, const double* x, const double* y, const double* z,
         for (int j = 0; j < n; ++j) {
             if (j == i) { gi += q[i] * q[i] * gb_d(p, R[i]) / R[i]; continue; }
             double r = dist(x, y, z, i, j), f, ex, D;
+            if (beyond(p, r)) continue;
             fgb(r, R[i], R[j], &f, &ex, &D);
             if (j > i) ci += q[i] * q[j] / (p->eps_in * r);
             gi += q[i] * q[j] * gb_d(p, f) / f;
@@ -200,6 +237,7 @@ void or_phi_fixedR(int n, const double* x, const double* y, const double* z,
         for (int j = 0; j < n; ++j) {
             if (j == i) continue;
             double r = dist(x, y, z, i, j), f, ex, D;
+            if (beyond(p, r)) continue;
             fgb(r, R[i], R[j], &f, &ex, &D);
             s += k * q[j] / (p->eps_in * r) - k * gb_d(p, f) * q[j] / f;
         }
@@ -236,6 +274,7 @@ void or_energy_forces(int n, const double* x, const double* y, const double* z,
             if (j == i) continue;
             double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
             double r = sqrt(dx * dx + dy * dy + dz * dz), f, ex, D;
+            if (beyond(p, r)) continue;
             fgb(r, R[i], R[j], &f, &ex, &D);
             double qq = q[i] * q[j];
             double dfdr = r / f * (1.0 - 0.25 * ex);
@@ -265,8 +304,8 @@ void or_energy_forces(int n, const double* x, const double* y, const double* z,
             double dx = x[a] - x[j], dy = y[a] - y[j], dz = z[a] - z[j];
             double r = sqrt(dx * dx + dy * dy + dz * dz);
             double gaj[3], gja[3];
-            or_hct_grad(r, rta, Sj, gaj);   /* H(r_aj; rt_a, S_j): in Psi_a */
-            or_hct_grad(r, rtj, Sa, gja);   /* H(r_ja; rt_j, S_a): in Psi_j */
+            or_hct_cut_grad(r, rta, Sj, p->rgbmax, gaj);   /* H(r_aj; rt_a, S_j): in Psi_a */
+            or_hct_cut_grad(r, rtj, Sa, p->rgbmax, gja);   /* H(r_ja; rt_j, S_a): in Psi_j */
             double dEdr = B[a] * rta * gaj[0] + B[j] * rtj * gja[0];
             fx -= dEdr * dx / r;
             fy -= dEdr * dy / r;
@@ -299,6 +338,7 @@ static double pair_K(const double* x, const double* y, const double* z, const do
     double kk = p->coulomb_k;
     if (i == k) return -kk * gb_d(p, R[i]) / R[i];
     double r = dist(x, y, z, i, k), f, ex, D;
+    if (beyond(p, r)) return 0.0;
     fgb(r, R[i], R[k], &f, &ex, &D);
     return kk / (p->eps_in * r) - kk * gb_d(p, f) / f;
 }
