@@ -53,13 +53,23 @@ typedef enum { GBMC_FP32_FIXED = 0, GBMC_FP64 = 1 } gbmc_precision;
  * Debye length (1/A) of added salt (the paper's runs have none: kappa = 0).
  * With salt every GB pair and self term carries the Debye-Hueckel factor
  * 1/eps_in - exp(-kappa f)/eps_out in place of 1/eps_in - 1/eps_out
- * (Srinivasan et al., Theor. Chem. Acc. 101 (1999) 426). */
+ * (Srinivasan et al., Theor. Chem. Acc. 101 (1999) 426).
+ * Optional cutoffs for large systems (0 = none, the paper's setting):
+ * rgbmax > 0 restricts each atom's descreening integral to the sphere of that
+ * radius around it (the part of ball j inside rgbmax and outside rt:
+ * H(r; rt, S) - H(r; rgbmax, S)); cutoff > 0 drops the Coulomb and GB pair
+ * terms of every pair at or beyond that distance (self terms stay), in the
+ * energies, forces, dE/dq, dE/drho and the Monte Carlo Delta E alike.  Tiles
+ * of 64 x 64 atoms whose bounding spheres are farther apart are skipped.
+ * gb_radii and gb_energy_forces must get the same parameters. */
 typedef struct {
     double alpha, beta, gamma;
     double offset;
     double eps_in, eps_out;
     double coulomb_k;
     double kappa;
+    double rgbmax;
+    double cutoff;
 } gbmc_gb_params;
 
 /* Per-atom SoA inputs over the whole batch (N_tot = atom_offset[B] atoms),
@@ -98,7 +108,8 @@ int32_t gbmc_version(void);
 const char* gbmc_last_error(void);
 
 /* Host-only check of GB parameters: GBMC_ERR_INVALID for kappa < 0,
- * eps_in <= 0, eps_out <= 0, offset < 0 or non-finite values. */
+ * rgbmax < 0, cutoff < 0, eps_in <= 0, eps_out <= 0, offset < 0 or non-finite
+ * values. */
 gbmc_status gbmc_params_validate(const gbmc_gb_params* params);
 
 /* Host-only: the pair-tile work list a plan with this layout would use for a

@@ -31,7 +31,8 @@ class GbmcError(RuntimeError):
 
 class gbmc_gb_params(C.Structure):
     _fields_ = [(n, C.c_double) for n in
-                ("alpha", "beta", "gamma", "offset", "eps_in", "eps_out", "coulomb_k", "kappa")]
+                ("alpha", "beta", "gamma", "offset", "eps_in", "eps_out", "coulomb_k", "kappa",
+                 "rgbmax", "cutoff")]
 
 
 class gbmc_atoms(C.Structure):

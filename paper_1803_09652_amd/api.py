@@ -21,7 +21,9 @@ KIND_REDOX = 1
 
 @dataclass(frozen=True)
 class GBParams:
-    """GB-OBC parameters (default: the igb=5 set; see IGB2 for the paper's)."""
+    """GB-OBC parameters (default: the igb=5 set; see IGB2 for the paper's).
+    kappa: inverse Debye length (1/A) of added salt; rgbmax: descreening
+    cutoff (A); cutoff: pair cutoff of the energy terms (A); 0 = none."""
     alpha: float = 1.0
     beta: float = 0.8
     gamma: float = 4.85
@@ -30,10 +32,13 @@ class GBParams:
     eps_out: float = 78.5
     coulomb_k: float = 332.0522
     kappa: float = 0.0
+    rgbmax: float = 0.0
+    cutoff: float = 0.0
 
     def c(self) -> L.gbmc_gb_params:
         return L.gbmc_gb_params(self.alpha, self.beta, self.gamma, self.offset, self.eps_in,
-                                self.eps_out, self.coulomb_k, self.kappa)
+                                self.eps_out, self.coulomb_k, self.kappa, self.rgbmax,
+                                self.cutoff)
 
 
 IGB5 = GBParams()

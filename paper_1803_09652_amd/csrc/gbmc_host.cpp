@@ -56,6 +56,8 @@ struct gbmc_plan {
     void* d_mem = nullptr;           // one allocation: the work lists and the order
     int32_t* d_perm = nullptr;       // [N] internal -> caller atom index
     int32_t* d_offset = nullptr;     // [B+1] device copy of the atom offsets
+    int32_t n_blocks = 0;            // 64-atom blocks of the batch
+    BlockSpan* d_blocks = nullptr;   // [n_blocks] atoms of each block (processing order)
     int device = 0;
     // timing hook: a ring of start/stop event pairs per timed kernel (bound to
     // the dispatches while enabled), the launches recorded since the last
@@ -66,7 +68,8 @@ struct gbmc_plan {
     hipEvent_t cur[2 * kNumKernels] = {};
     // workspace layout (byte offsets)
     size_t off_I, off_F, off_G, off_phi, off_drho, off_EA, off_I64, off_R64, off_T64, off_dR64,
-        off_G64, off_B64, off_Rt, off_at, off_Brt, off_ovf, off_P, off_Gx, off_A64, off_rows, ws_bytes;
+        off_G64, off_B64, off_Rt, off_at, off_Brt, off_ovf, off_P, off_Gx, off_A64, off_rows, off_bnd,
+        off_smax, ws_bytes;
 };
 
 struct gbmc_sites {
@@ -104,6 +107,7 @@ static gbmc_status build_items(int32_t n_systems, const int32_t* off, int32_t jb
                                std::vector<WorkItem>& items)
 {
     items.clear();
+    int32_t blk0 = 0;
     auto add = [&](int32_t b, int32_t rows, int32_t I, int32_t J0, int32_t J1) {
         for (int32_t j = J0; j < J1; j += jb) {
             WorkItem w{};
@@ -114,10 +118,11 @@ static gbmc_status build_items(int32_t n_systems, const int32_t* off, int32_t jb
             w.J0 = j;
             w.J1 = std::min(J1, j + jb);
             w.rows = rows;
+            w.blk0 = blk0;
             items.push_back(w);
         }
     };
-    for (int32_t b = 0; b < n_systems; ++b) {
+    for (int32_t b = 0; b < n_systems; ++b, blk0 += (off[b] - off[b - 1] + kTile - 1) / kTile) {
         const int32_t nb = (off[b + 1] - off[b] + kTile - 1) / kTile;
         if (!row_pairs) {
             for (int32_t I = 0; I < nb; ++I) add(b, 1, I, I, nb);
@@ -186,6 +191,8 @@ static Work<T> carve(const gbmc_plan* p, void* ws)
     w.a_t = reinterpret_cast<T*>(b + p->off_at);
     w.Brt_t = reinterpret_cast<T*>(b + p->off_Brt);
     w.ovf = reinterpret_cast<int*>(b + p->off_ovf);
+    w.bnd = reinterpret_cast<Q4<float>*>(b + p->off_bnd);
+    w.smax = reinterpret_cast<float*>(b + p->off_smax);
     return w;
 }
 
@@ -218,6 +225,8 @@ static void layout(gbmc_plan* p)
     p->off_P = seg(4 * ts * N);
     p->off_Gx = seg(4 * ts * N);
     p->off_rows = seg(sizeof(Row64) * N);
+    p->off_bnd = seg(sizeof(Q4<float>) * (size_t)p->n_blocks);
+    p->off_smax = seg(sizeof(float) * (size_t)p->n_blocks);
     p->ws_bytes = o;
 }
 
@@ -232,6 +241,8 @@ static GBConst make_const(const gbmc_gb_params* gp)
     c.kT = gp->coulomb_k * (1.0 / gp->eps_in - 1.0 / gp->eps_out);
     c.kO = gp->coulomb_k / gp->eps_out;
     c.kappa = gp->kappa;
+    c.rgbmax = gp->rgbmax;
+    c.cutoff = gp->cutoff;
     return c;
 }
 
@@ -263,10 +274,11 @@ gbmc_status gbmc_params_validate(const gbmc_gb_params* p)
 {
     if (!p) return fail(GBMC_ERR_INVALID, "params is NULL");
     const double v[] = {p->alpha, p->beta, p->gamma, p->offset, p->eps_in, p->eps_out,
-                        p->coulomb_k, p->kappa};
+                        p->coulomb_k, p->kappa, p->rgbmax, p->cutoff};
     for (double x : v)
         if (!std::isfinite(x)) return fail(GBMC_ERR_INVALID, "non-finite GB parameter");
     if (p->kappa < 0.0) return fail(GBMC_ERR_INVALID, "kappa must be >= 0");
+    if (p->rgbmax < 0.0 || p->cutoff < 0.0) return fail(GBMC_ERR_INVALID, "cutoffs must be >= 0 (0: none)");
     if (p->eps_in <= 0.0 || p->eps_out <= 0.0) return fail(GBMC_ERR_INVALID, "dielectric constants must be > 0");
     if (p->offset < 0.0) return fail(GBMC_ERR_INVALID, "offset must be >= 0");
     return GBMC_OK;
@@ -324,6 +336,11 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
         p->tuning = t;
         p->offset.assign(host_atom_offset, host_atom_offset + n_systems + 1);
         if (n_systems == 0) p->offset.assign(1, 0);
+        std::vector<BlockSpan> blocks;
+        for (int32_t b = 0; b < n_systems; ++b)
+            for (int32_t a = host_atom_offset[b]; a < host_atom_offset[b + 1]; a += kTile)
+                blocks.push_back(BlockSpan{a, std::min(kTile, host_atom_offset[b + 1] - a)});
+        p->n_blocks = (int32_t)blocks.size();
         layout(p);
         hipError_t e = hipGetDevice(&p->device);
         if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
@@ -339,7 +356,8 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
         at[GBMC_N_PASSES] = o;
         const size_t off_bytes = 4 * (size_t)(n_systems + 1);
         const size_t at_off = align256(o + 4 * (size_t)p->n_atoms);
-        const size_t total = at_off + off_bytes;
+        const size_t at_blk = align256(at_off + off_bytes);
+        const size_t total = at_blk + sizeof(BlockSpan) * blocks.size();
         if (total > 0) {
             char* d = nullptr;
             e = hipMalloc(&d, total);
@@ -356,6 +374,9 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
             for (int32_t k = 0; k < p->n_atoms; ++k) id[k] = k;
             p->d_offset = reinterpret_cast<int32_t*>(d + at_off);
             std::memcpy(h.data() + at_off, p->offset.data(), off_bytes);
+            p->d_blocks = reinterpret_cast<BlockSpan*>(d + at_blk);
+            if (!blocks.empty())
+                std::memcpy(h.data() + at_blk, blocks.data(), sizeof(BlockSpan) * blocks.size());
             e = hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice);
             if (e != hipSuccess) { (void)hipFree(d); delete p; return hip_fail(e, "hipMemcpy(plan tables)"); }
         }
@@ -524,15 +545,15 @@ gbmc_status gb_radii(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp
     hipError_t e;
     if (p->prec == GBMC_FP32_FIXED)
         e = launch_radii<float>(p->d_items[GBMC_PASS_RADII], p->n_items[GBMC_PASS_RADII],
-                                p->tuning.waves_per_group[GBMC_PASS_RADII], p->n_atoms, nullptr,
-                                (const float*)a->x,
+                                p->tuning.waves_per_group[GBMC_PASS_RADII], p->n_atoms,
+                                p->d_blocks, p->n_blocks, (const float*)a->x,
                                 (const float*)a->y, (const float*)a->z, (const float*)a->rho,
                                 (const float*)a->screen, c, carve<float>(p, ws), (float*)born_R, s,
                                 p->n_items[GBMC_PASS_RADII] > 0 ? events(p, {kKRadii}) : nullptr);
     else
         e = launch_radii<double>(p->d_items[GBMC_PASS_RADII], p->n_items[GBMC_PASS_RADII],
                                  p->tuning.waves_per_group[GBMC_PASS_RADII], p->n_atoms,
-                                 nullptr, (const double*)a->x,
+                                 p->d_blocks, p->n_blocks, (const double*)a->x,
                                  (const double*)a->y, (const double*)a->z, (const double*)a->rho,
                                  (const double*)a->screen, c, carve<double>(p, ws), (double*)born_R, s,
                                  p->n_items[GBMC_PASS_RADII] > 0 ? events(p, {kKRadii}) : nullptr);
@@ -555,13 +576,13 @@ gbmc_status gb_energy_forces(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_pa
                        p->tuning.waves_per_group[GBMC_PASS_CHAIN]};
     hipError_t e;
     if (p->prec == GBMC_FP32_FIXED)
-        e = launch_energy_forces<float>(pe, pc, p->n_atoms, p->n_sys,
+        e = launch_energy_forces<float>(pe, pc, p->n_atoms, p->n_sys, p->d_blocks, p->n_blocks,
                                         (const float*)a->x, (const float*)a->y, (const float*)a->z,
                                         (const float*)a->q, (const float*)a->rho,
                                         (const float*)a->screen, c, carve<float>(p, ws), e_coul,
                                         e_gb, (float*)force, (float*)dEdq, (float*)dEdrho, s, ev);
     else
-        e = launch_energy_forces<double>(pe, pc, p->n_atoms, p->n_sys,
+        e = launch_energy_forces<double>(pe, pc, p->n_atoms, p->n_sys, p->d_blocks, p->n_blocks,
                                          (const double*)a->x, (const double*)a->y,
                                          (const double*)a->z, (const double*)a->q,
                                          (const double*)a->rho, (const double*)a->screen, c,

@@ -33,9 +33,14 @@ struct alignas(4 * sizeof(T)) Q4 {
 
 // One pair work item: system `sys` (atoms [base, base+n)), the `rows` (1 or 2)
 // i blocks [I, I + rows), j blocks [J0, J1) with J0 >= I (J0 >= I + 2 for two
-// rows).
+// rows); blk0 is the batch-wide index of the system's first block.
 struct WorkItem {
-    int32_t base, n, sys, I, J0, J1, rows, pad;
+    int32_t base, n, sys, I, J0, J1, rows, blk0;
+};
+
+// One 64-atom block of the batch (processing order): atoms [start, start + count).
+struct BlockSpan {
+    int32_t start, count;
 };
 
 // One FP64 potential-row work item: up to 64 site atoms [sa0, sa1) of one system
@@ -81,6 +86,8 @@ struct Work {
     T* a_t;                       // [N] internal: sqrt(log2(e)/4) / R
     T* Brt_t;                     // [N] internal: B * (rho - offset)
     int* ovf;                     // overflow flag
+    Q4<float>* bnd;               // [n_blocks] bounding sphere of each block: centre, radius
+    float* smax;                  // [n_blocks] largest S = screen (rho - offset) of each block
 };
 
 struct SiteDev {
@@ -111,6 +118,14 @@ struct GBConst {
     double kT;      // k (1/eps_in - 1/eps_out)
     double kO;      // k / eps_out
     double kappa;   // inverse Debye length (1/A); 0: no salt
+    double rgbmax;  // descreening cutoff (A); 0: none
+    double cutoff;  // pair cutoff of the energy terms (A); 0: none
+};
+
+// Energy cutoff in the pair precision: cE = cutoff, cE2 = cutoff^2.
+template <typename T>
+struct CutK {
+    T cE, cE2;
 };
 
 // Salt constants of the pair precision: kO = k/eps_out, kap = kappa,
@@ -129,7 +144,7 @@ enum KernelId { kKRadii = 0, kKEnergy = 1, kKChain = 2, kKSiteRows = 3, kKSiteDE
 // the dispatch of each timed kernel.
 template <typename T>
 hipError_t launch_radii(const WorkItem* items, int n_items, int waves_per_group, int n_atoms,
-                        const int32_t* atom_sys,
+                        const BlockSpan* blocks, int n_blocks,
                         const T* x, const T* y, const T* z, const T* rho, const T* screen,
                         const GBConst& c, const Work<T>& w, T* born_R, hipStream_t s,
                         hipEvent_t* ev);
@@ -141,7 +156,7 @@ struct PassShape {
 
 template <typename T>
 hipError_t launch_energy_forces(const PassShape& energy, const PassShape& chain, int n_atoms,
-                                int n_sys,
+                                int n_sys, const BlockSpan* blocks, int n_blocks,
                                 const T* x, const T* y, const T* z, const T* q, const T* rho,
                                 const T* screen, const GBConst& c, const Work<T>& w,
                                 double* e_coul, double* e_gb, T* force, T* dEdq, T* dEdrho,

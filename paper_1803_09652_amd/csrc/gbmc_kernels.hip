@@ -342,6 +342,183 @@ __device__ __forceinline__ void chain_pair(double r, double r2, double invr, dou
     dEdr = -u * fma(bi, aij, bj * aji);
 }
 
+// ------------------------------------------------------- cutoff variants
+// With the descreening cutoff c the integral is restricted to the sphere of
+// radius c around atom i: H_c = H(r; rt, S) - H(r; c, S) for a ball j that
+// straddles that sphere (r - S < c < r + S), H for a ball inside it, 0 for
+// one beyond it (r - S >= c) or when c <= rt.  Straddling balls take the
+// closed form for both terms.
+__device__ __forceinline__ void radii_pair_cut(float xi, float yi, float zi, float xj, float yj,
+                                               float zj, float rti, float Si, float rtj, float Sj,
+                                               float c, float& hij, float& hji)
+{
+    float dx = xi - xj, dy = yi - yj, dz = zi - zj;
+    float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    float invr = rsq(r2);
+    float r = r2 * invr;
+    float xij = Sj * invr, yij = xij * xij;
+    float xji = Si * invr, yji = xji * xji;
+    hij = xij * yij * invr * hct_poly(yij);
+    hji = xji * yji * invr * hct_poly(yji);
+    const bool out_ij = (r - Sj >= c) | (c <= rti), out_ji = (r - Si >= c) | (c <= rtj);
+    const bool st_ij = !out_ij & (r + Sj > c), st_ji = !out_ji & (r + Si > c);
+    const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX) & !st_ij;
+    const bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX) & !st_ji;
+    if (!(f_ij & f_ji)) {
+        if (!f_ij) {
+            hij = hct_slow32<false>(r, invr, rti, Sj, nullptr);
+            if (st_ij) hij -= hct_slow32<false>(r, invr, c, Sj, nullptr);
+        }
+        if (!f_ji) {
+            hji = hct_slow32<false>(r, invr, rtj, Si, nullptr);
+            if (st_ji) hji -= hct_slow32<false>(r, invr, c, Si, nullptr);
+        }
+    }
+    hij = out_ij ? 0.0f : hij;
+    hji = out_ji ? 0.0f : hji;
+}
+
+__device__ __forceinline__ void radii_pair_cut(double xi, double yi, double zi, double xj,
+                                               double yj, double zj, double rti, double Si,
+                                               double rtj, double Sj, double c, double& hij,
+                                               double& hji)
+{
+    double r, invr;
+    dist64(xi, yi, zi, xj, yj, zj, r, invr);
+    const double xij = Sj * invr, yij = xij * xij;
+    const double xji = Si * invr, yji = xji * xji;
+    hij = xij * yij * invr * hct_poly64(yij);
+    hji = xji * yji * invr * hct_poly64(yji);
+    const bool out_ij = (r - Sj >= c) | (c <= rti), out_ji = (r - Si >= c) | (c <= rtj);
+    const bool st_ij = !out_ij & (r + Sj > c), st_ji = !out_ji & (r + Si > c);
+    const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX64) & !st_ij;
+    const bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX64) & !st_ji;
+    if (!(f_ij & f_ji)) {
+        if (!f_ij) {
+            hij = hct_general(r, invr, rti, Sj);
+            if (st_ij) hij -= hct_general(r, invr, c, Sj);
+        }
+        if (!f_ji) {
+            hji = hct_general(r, invr, rtj, Si);
+            if (st_ji) hji -= hct_general(r, invr, c, Si);
+        }
+    }
+    hij = out_ij ? 0.0 : hij;
+    hji = out_ji ? 0.0 : hji;
+}
+
+// Pass-3 pair terms of H_c (see chain_pair): the c term contributes to the r
+// and S partials, not to the rt partial.
+__device__ __forceinline__ void chain_pair_cut(float r, float r2, float invr, float rti, float Si,
+                                               float rtj, float Sj, float bi, float bj, float c,
+                                               float& dEdr, float& gij2, float& gji2, float& dri,
+                                               float& drj)
+{
+    const float u = invr * invr;
+    const float xij = Sj * invr, yij = xij * xij;
+    const float xji = Si * invr, yji = xji * xji;
+    float wij = rcp(1.0f - yij), wji = rcp(1.0f - yji);
+    wij *= wij;
+    wji *= wji;
+    float aij = xij * yij * (hct_poly(yij) + wij);     // -r^2 dH/dr
+    float aji = xji * yji * (hct_poly(yji) + wji);
+    gij2 = yij * wij * u;
+    gji2 = yji * wji * u;
+    const bool out_ij = (r - Sj >= c) | (c <= rti), out_ji = (r - Si >= c) | (c <= rtj);
+    const bool st_ij = !out_ij & (r + Sj > c), st_ji = !out_ji & (r + Si > c);
+    const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX) & !st_ij;
+    const bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX) & !st_ji;
+    if (!(f_ij & f_ji)) {
+        float g[3], gc[3];
+        if (!f_ij) {
+            hct_slow32<true>(r, invr, rti, Sj, g);
+            if (st_ij) {
+                hct_slow32<true>(r, invr, c, Sj, gc);
+                g[0] -= gc[0];
+                g[2] -= gc[2];
+            }
+            aij = -g[0] * r2;
+            gij2 = g[2];
+            dri = out_ij ? dri : fmaf(bi, g[1], dri);
+        }
+        if (!f_ji) {
+            hct_slow32<true>(r, invr, rtj, Si, g);
+            if (st_ji) {
+                hct_slow32<true>(r, invr, c, Si, gc);
+                g[0] -= gc[0];
+                g[2] -= gc[2];
+            }
+            aji = -g[0] * r2;
+            gji2 = g[2];
+            drj = out_ji ? drj : fmaf(bj, g[1], drj);
+        }
+    }
+    aij = out_ij ? 0.0f : aij;
+    aji = out_ji ? 0.0f : aji;
+    gij2 = out_ij ? 0.0f : gij2;
+    gji2 = out_ji ? 0.0f : gji2;
+    dEdr = -u * fmaf(bi, aij, bj * aji);
+}
+
+__device__ __forceinline__ void chain_pair_cut(double r, double r2, double invr, double rti,
+                                               double Si, double rtj, double Sj, double bi,
+                                               double bj, double c, double& dEdr, double& gij2,
+                                               double& gji2, double& dri, double& drj)
+{
+    const double u = invr * invr;
+    const double xij = Sj * invr, yij = xij * xij;
+    const double xji = Si * invr, yji = xji * xji;
+    double wij = rcp64(1.0 - yij), wji = rcp64(1.0 - yji);
+    wij *= wij;
+    wji *= wji;
+    double aij = xij * yij * (hct_poly64(yij) + wij);
+    double aji = xji * yji * (hct_poly64(yji) + wji);
+    gij2 = yij * wij * u;
+    gji2 = yji * wji * u;
+    const bool out_ij = (r - Sj >= c) | (c <= rti), out_ji = (r - Si >= c) | (c <= rtj);
+    const bool st_ij = !out_ij & (r + Sj > c), st_ji = !out_ji & (r + Si > c);
+    const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX64) & !st_ij;
+    const bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX64) & !st_ji;
+    if (!(f_ij & f_ji)) {
+        double g0, g1, g2, c0, c1, c2;
+        if (!f_ij) {
+            hct_general_grad(r, invr, rti, Sj, g0, g1, g2);
+            if (st_ij) {
+                hct_general_grad(r, invr, c, Sj, c0, c1, c2);
+                g0 -= c0;
+                g2 -= c2;
+            }
+            aij = -g0 * r2;
+            gij2 = g2;
+            dri = out_ij ? dri : fma(bi, g1, dri);
+        }
+        if (!f_ji) {
+            hct_general_grad(r, invr, rtj, Si, g0, g1, g2);
+            if (st_ji) {
+                hct_general_grad(r, invr, c, Si, c0, c1, c2);
+                g0 -= c0;
+                g2 -= c2;
+            }
+            aji = -g0 * r2;
+            gji2 = g2;
+            drj = out_ji ? drj : fma(bj, g1, drj);
+        }
+    }
+    aij = out_ij ? 0.0 : aij;
+    aji = out_ji ? 0.0 : aji;
+    gij2 = out_ij ? 0.0 : gij2;
+    gji2 = out_ji ? 0.0 : gji2;
+    dEdr = -u * fma(bi, aij, bj * aji);
+}
+
+// Lower bound of the distance between any atom of one block and any atom of
+// another, from their bounding spheres.
+__device__ __forceinline__ float block_gap(const Q4<float>& a, const Q4<float>& b)
+{
+    const float dx = a.x - b.x, dy = a.y - b.y, dz = a.z - b.z;
+    return sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))) - a.w - b.w;
+}
+
 // ---------------------------------------------------------------- helpers
 
 template <typename T>
@@ -461,6 +638,46 @@ __global__ void k_stage(int n_atoms, const int32_t* __restrict__ perm, const T* 
     Gx[k] = g;
 }
 
+// Bounding sphere of every 64-atom block (centre of the coordinate box,
+// radius to the farthest atom, widened by a margin that covers rounding) and
+// its largest S, for the cutoff passes: one wave per block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_block_bounds(const BlockSpan* __restrict__ blocks,
+                                                      int n_blocks, const Q4<T>* __restrict__ P,
+                                                      const Q4<T>* __restrict__ Gx,
+                                                      Q4<float>* __restrict__ bnd,
+                                                      float* __restrict__ smax)
+{
+    const int blk = blockIdx.x * 4 + threadIdx.x / kTile, lane = threadIdx.x % kTile;
+    if (blk >= n_blocks) return;
+    const BlockSpan b = blocks[blk];
+    const int k = b.start + (lane < b.count ? lane : b.count - 1);
+    const Q4<T> p = P[k];
+    const float x = (float)p.x, y = (float)p.y, z = (float)p.z;
+    float lo[3] = {x, y, z}, hi[3] = {x, y, z}, sm = (float)Gx[k].y;
+#pragma unroll
+    for (int o = kTile / 2; o > 0; o >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], o));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o));
+        }
+        sm = fmaxf(sm, __shfl_xor(sm, o));
+    }
+    const float cx = 0.5f * (lo[0] + hi[0]), cy = 0.5f * (lo[1] + hi[1]), cz = 0.5f * (lo[2] + hi[2]);
+    const float dx = x - cx, dy = y - cy, dz = z - cz;
+    float d = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+#pragma unroll
+    for (int o = kTile / 2; o > 0; o >>= 1) d = fmaxf(d, __shfl_xor(d, o));
+    if (lane == 0) {
+        Q4<float> q;
+        q.x = cx; q.y = cy; q.z = cz;
+        q.w = d * 1.000001f + 1e-3f;
+        bnd[blk] = q;
+        smax[blk] = sm;
+    }
+}
+
 // ================================================================ pass 1
 // I_i = sum_{j != i} H(r_ij; rt_i, S_j) over every unordered pair once.
 
@@ -470,12 +687,13 @@ __global__ void k_stage(int n_atoms, const int32_t* __restrict__ perm, const T* 
 // sums move once per two pairs.  Every (i row, j block) tile is rounded into
 // fixed point on its own on the i side; the j side of a two-row item rounds
 // the sum of its two tiles, the same for every work shape.
-template <typename T, int R>
+template <typename T, int R, bool CUT>
 __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* sj, T* sS,
                                            const Q4<T>* __restrict__ P,
                                            const Q4<T>* __restrict__ Gx,
                                            unsigned long long* __restrict__ I_fx,
-                                           int* __restrict__ ovf)
+                                           int* __restrict__ ovf, const Q4<float>* __restrict__ bnd,
+                                           const float* __restrict__ smax, T cR)
 {
     T xi[R], yi[R], zi[R], rti[R], Si[R];
     bool vi[R];
@@ -520,7 +738,21 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
     fetch(w.J0, pj, gj);
     // one tile; the first is peeled so that the loop is entered, as on every
     // later trip, with the previous tile's sums still in flight
+    Q4<float> bI;
+    float sI = 0.0f;
+    if constexpr (CUT) {
+        bI = bnd[w.blk0 + w.I];
+        sI = smax[w.blk0 + w.I];
+    }
     auto tile = [&](int J) {
+        if constexpr (CUT) {
+            // every ball of block J lies beyond the cutoff sphere of every atom
+            // of block I and the reverse: the tile adds nothing
+            if (block_gap(bI, bnd[w.blk0 + J]) - fmaxf(sI, smax[w.blk0 + J]) >= (float)cR) {
+                fetch(J + 1 < w.J1 ? J + 1 : J, pj, gj);
+                return;
+            }
+        }
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
         T Sj;
@@ -540,8 +772,12 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
         auto load = [&](int s) { return JD{sj[s], sS[s]}; };
         auto pair = [&](const JD& d, int r, bool act, T (&acc)[1]) {
             T hij, hji;
-            radii_pair(xi[r], yi[r], zi[r], d.p.x, d.p.y, d.p.z, rti[r], Si[r], d.p.w, d.S, hij,
-                       hji);
+            if constexpr (CUT)
+                radii_pair_cut(xi[r], yi[r], zi[r], d.p.x, d.p.y, d.p.z, rti[r], Si[r], d.p.w, d.S,
+                               cR, hij, hji);
+            else
+                radii_pair(xi[r], yi[r], zi[r], d.p.x, d.p.y, d.p.z, rti[r], Si[r], d.p.w, d.S, hij,
+                           hji);
             ai[r] += act ? hij : T(0);
             acc[0] += act ? hji : T(0);
         };
@@ -562,10 +798,11 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
     if (bad) *ovf = 1;
 }
 
-template <typename T, int W>
+template <typename T, int W, bool CUT>
 __global__ __launch_bounds__(kTile * W) void k_radii_pairs(
     const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
-    const Q4<T>* __restrict__ Gx, unsigned long long* __restrict__ I_fx, int* __restrict__ ovf)
+    const Q4<T>* __restrict__ Gx, unsigned long long* __restrict__ I_fx, int* __restrict__ ovf,
+    const Q4<float>* __restrict__ bnd, const float* __restrict__ smax, T cR)
 {
     __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, rt
     __shared__ T sS_w[W][2 * kTile];
@@ -575,7 +812,7 @@ __global__ __launch_bounds__(kTile * W) void k_radii_pairs(
     const WorkItem w = items[item];
     // the descreening pass runs one-row items only (its two-row form was
     // slower: fewer waves in flight for less saved work)
-    radii_item<T, 1>(w, lane, sj_w[wave], sS_w[wave], P, Gx, I_fx, ovf);
+    radii_item<T, 1, CUT>(w, lane, sj_w[wave], sS_w[wave], P, Gx, I_fx, ovf, bnd, smax, cR);
 }
 
 // Per atom: OBC radius from the descreening sum (FP64), and the per-atom state
@@ -616,11 +853,12 @@ __global__ void k_radii_finalize(int n_atoms, const T* __restrict__ RHO, GBConst
 // Coulomb + GB energy, explicit pair forces, G = dE/dR, phi = dE/dq.
 
 // One work item of R (1 or 2) i blocks; see radii_item.
-template <typename T, bool GRAD, int R, bool SALT>
+template <typename T, bool GRAD, int R, bool SALT, bool CUT>
 __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* sj, T* sR, T* sA,
                                             const Q4<T>* __restrict__ P, const T* __restrict__ Rt,
                                             const T* __restrict__ At, T kC, T kT,
-                                            const SaltK<T>& sk, const Work<T>& wk)
+                                            const SaltK<T>& sk, const CutK<T>& ck,
+                                            const Work<T>& wk)
 {
     constexpr int NJ = GRAD ? 5 : 1;
     T xi[R], yi[R], zi[R], qi[R], Ri[R], ai[R];
@@ -667,7 +905,23 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
     fetch(w.J0, pj, Rj, Aj);
     // one tile; the first is peeled so that the loop is entered, as on every
     // later trip, with the previous tile's sums still in flight
+    Q4<float> bI[R];
+    if constexpr (CUT) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) bI[r] = wk.bnd[w.blk0 + w.I + r];
+    }
     auto tile = [&](int J) {
+        if constexpr (CUT) {
+            // every pair of the tile (of both rows) lies beyond the cutoff
+            const Q4<float> bJ = wk.bnd[w.blk0 + J];
+            bool far = true;
+#pragma unroll
+            for (int r = 0; r < R; ++r) far = far && block_gap(bI[r], bJ) >= (float)ck.cE;
+            if (far) {
+                fetch(J + 1 < w.J1 ? J + 1 : J, pj, Rj, Aj);
+                return;
+            }
+        }
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
         tail(J, pj, Rj, Aj);
@@ -689,6 +943,7 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
             const T rj = d.Rv;
             T dx = xi[r] - p.x, dy = yi[r] - p.y, dz = zi[r] - p.z;
             T r2 = dx * dx + dy * dy + dz * dz;
+            if constexpr (CUT) act = act && r2 < ck.cE2;     // pairs beyond the cutoff drop out
             T invr = rsq(r2);
             T t = r2 * (ai[r] * d.Av);            // r^2 log2(e) / (4 R_i R_j)
             T ex = exp2neg(t);                   // exp(-D)
@@ -798,10 +1053,11 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
     }
 }
 
-template <typename T, bool GRAD, int W, bool SALT>
+template <typename T, bool GRAD, int W, bool SALT, bool CUT>
 __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
     const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
-    const T* __restrict__ Rt, const T* __restrict__ At, T kC, T kT, SaltK<T> sk, Work<T> wk)
+    const T* __restrict__ Rt, const T* __restrict__ At, T kC, T kT, SaltK<T> sk, CutK<T> ck,
+    Work<T> wk)
 {
     __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, q
     __shared__ T sR_w[W][2 * kTile];
@@ -812,11 +1068,12 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
     const WorkItem w = items[item];
     // two-row items exist in the energy pass of FP32 plans only
     if (sizeof(T) == 4 && w.rows == 2)
-        energy_item<T, GRAD, sizeof(T) == 4 ? 2 : 1, SALT>(w, lane, sj_w[wave], sR_w[wave],
-                                                           sA_w[wave], P, Rt, At, kC, kT, sk, wk);
+        energy_item<T, GRAD, sizeof(T) == 4 ? 2 : 1, SALT, CUT>(w, lane, sj_w[wave], sR_w[wave],
+                                                                sA_w[wave], P, Rt, At, kC, kT, sk,
+                                                                ck, wk);
     else
-        energy_item<T, GRAD, 1, SALT>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P, Rt, At, kC,
-                                      kT, sk, wk);
+        energy_item<T, GRAD, 1, SALT, CUT>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P, Rt, At,
+                                           kC, kT, sk, ck, wk);
 }
 
 // After pass 2, one launch: blocks [0, n_sum) sum the atoms' fixed-point
@@ -869,11 +1126,11 @@ __global__ __launch_bounds__(256) void k_energy_finalize(int n_atoms, int n_sum,
 // Born-radius chain: force through Psi and the pair part of dE/drho.
 
 // One work item of R (1 or 2) i blocks; see radii_item.
-template <typename T, int R>
+template <typename T, int R, bool CUT>
 __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* sj, Q4<T>* sb,
                                            const Q4<T>* __restrict__ P,
                                            const Q4<T>* __restrict__ Gx,
-                                           const T* __restrict__ Brt, const Work<T>& wk)
+                                           const T* __restrict__ Brt, const Work<T>& wk, T cR)
 {
     T xi[R], yi[R], zi[R], rti[R], Si[R], Bi[R], si[R];
     bool vi[R];
@@ -925,7 +1182,20 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
     fetch(w.J0, pj, gj, brj);
     // one tile; the first is peeled so that the loop is entered, as on every
     // later trip, with the previous tile's sums still in flight
+    Q4<float> bI;
+    float sI = 0.0f;
+    if constexpr (CUT) {
+        bI = wk.bnd[w.blk0 + w.I];
+        sI = wk.smax[w.blk0 + w.I];
+    }
     auto tile = [&](int J) {
+        if constexpr (CUT) {
+            // no ball of either block reaches into the other's cutoff spheres
+            if (block_gap(bI, wk.bnd[w.blk0 + J]) - fmaxf(sI, wk.smax[w.blk0 + J]) >= (float)cR) {
+                fetch(J + 1 < w.J1 ? J + 1 : J, pj, gj, brj);
+                return;
+            }
+        }
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
         tail(J, pj, bj, gj, brj);
@@ -950,8 +1220,12 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
             const T bj_ = act ? b.y : T(0);
             const T bi_ = act ? Bi[r] : T(0);
             T dEdr, gij2, gji2;
-            chain_pair(rr, r2, invr, rti[r], Si[r], p.w, b.x, bi_, bj_, dEdr, gij2, gji2, dri[r],
-                       acc[3]);
+            if constexpr (CUT)
+                chain_pair_cut(rr, r2, invr, rti[r], Si[r], p.w, b.x, bi_, bj_, cR, dEdr, gij2, gji2,
+                               dri[r], acc[3]);
+            else
+                chain_pair(rr, r2, invr, rti[r], Si[r], p.w, b.x, bi_, bj_, dEdr, gij2, gji2,
+                           dri[r], acc[3]);
             T fr = dEdr * invr;
             T fx = fr * dx, fy = fr * dy, fz = fr * dz;
             fxi[r] -= fx; fyi[r] -= fy; fzi[r] -= fz;
@@ -998,10 +1272,10 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
     }
 }
 
-template <typename T, int W>
+template <typename T, int W, bool CUT>
 __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
     const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
-    const Q4<T>* __restrict__ Gx, const T* __restrict__ Brt, Work<T> wk)
+    const Q4<T>* __restrict__ Gx, const T* __restrict__ Brt, Work<T> wk, T cR)
 {
     __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, rt
     __shared__ Q4<T> sb_w[W][2 * kTile];     // S, B rt, screen, -
@@ -1011,7 +1285,7 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
     const WorkItem w = items[item];
     // the chain pass runs one-row items only (its two-row form was slower:
     // fewer waves in flight for less saved work)
-    chain_item<T, 1>(w, lane, sj_w[wave], sb_w[wave], P, Gx, Brt, wk);
+    chain_item<T, 1, CUT>(w, lane, sj_w[wave], sb_w[wave], P, Gx, Brt, wk, cR);
 }
 
 // Per atom after pass 3: forces and dE/drho.
@@ -1053,12 +1327,14 @@ __device__ __forceinline__ double gb_kd(double f, double kC, double kT, double k
     return kap == 0.0 ? kT : kC - kO * exp(-kap * f);
 }
 
-// k/(eps_in r) - k d(f) / f_GB for one pair (FP64); a = 1/(2R).
+// k/(eps_in r) - k d(f) / f_GB for one pair (FP64); a = 1/(2R); 0 at or beyond
+// the pair cutoff (cut2 = cutoff^2, infinite for none).
 __device__ __forceinline__ double pairK(double dx, double dy, double dz, double Ra, double aa,
                                         double Rb, double ab, double kC, double kT, double kO,
-                                        double kap)
+                                        double kap, double cut2)
 {
     double r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 >= cut2) return 0.0;
     double invr = rsq64(r2);
     double ex = exp(-r2 * (aa * ab));
     double f2 = fma(Ra * Rb, ex, r2);
@@ -1073,7 +1349,7 @@ template <typename T>
 __global__ __launch_bounds__(kTile) void k_site_phi_rows(
     const RowItem* __restrict__ items, const int32_t* __restrict__ site_atoms,
     const Row64* __restrict__ rows, const T* __restrict__ Q, double kC, double kT, double kO,
-    double kap,
+    double kap, double cut2,
     unsigned long long* __restrict__ phi_fx, int* __restrict__ ovf)
 {
     __shared__ double2 s_xy[kPhiChunk], s_zR[kPhiChunk], s_Aq[kPhiChunk];
@@ -1097,7 +1373,7 @@ __global__ __launch_bounds__(kTile) void k_site_phi_rows(
 #pragma unroll 4
     for (int k = 0; k < nj; ++k) {
         const double2 xy = s_xy[k], zR = s_zR[k], Aq = s_Aq[k];
-        double K = pairK(ri.x - xy.x, ri.y - xy.y, ri.z - zR.x, ri.R, ri.A, zR.y, Aq.x, kC, kT, kO, kap);
+        double K = pairK(ri.x - xy.x, ri.y - xy.y, ri.z - zR.x, ri.R, ri.A, zR.y, Aq.x, kC, kT, kO, kap, cut2);
         acc += (k == self) ? 0.0 : Aq.y * K;
     }
     bool bad = false;
@@ -1151,7 +1427,8 @@ template <typename T>
 __global__ __launch_bounds__(kSDE) void k_site_dE(
     SiteDev sd, const T* __restrict__ X, const T* __restrict__ Y, const T* __restrict__ Z,
     const T* __restrict__ Q, const double* __restrict__ R64, const double* __restrict__ A64,
-    double kC, double kT, double kO, double kap, const unsigned long long* __restrict__ phi_fx,
+    double kC, double kT, double kO, double kap, double cut2,
+    const unsigned long long* __restrict__ phi_fx,
     const int32_t* __restrict__ current_state,
     const double* __restrict__ pH, const double* __restrict__ E_volt, double T_kelvin,
     double* __restrict__ dE, double* __restrict__ dG)
@@ -1204,7 +1481,7 @@ __global__ __launch_bounds__(kSDE) void k_site_dE(
         const int a = p - b * (b + 1) / 2;
         double K = (a == b) ? -gb_kd(sR[a], kC, kT, kO, kap) / sR[a]
                             : 2.0 * pairK(sx[a] - sx[b], sy[a] - sy[b], sz[a] - sz[b], sR[a], sA[a],
-                                          sR[b], sA[b], kC, kT, kO, kap);
+                                          sR[b], sA[b], kC, kT, kO, kap, cut2);
 #pragma unroll
         for (int c = 0; c < kMaxStates - 1; ++c)
             if (c < nc) part[kMaxStates - 1 + c] += sdq[c][a] * sdq[c][b] * K;
@@ -1239,7 +1516,7 @@ template <typename T>
 __global__ __launch_bounds__(kMC) void k_mc_step(
     SiteDev sd, const T* __restrict__ X, const T* __restrict__ Y, const T* __restrict__ Z,
     T* __restrict__ Q, const double* __restrict__ R64, const double* __restrict__ A64, double kC,
-    double kT, double kO, double kap, int32_t* __restrict__ current_state,
+    double kT, double kO, double kap, double cut2, int32_t* __restrict__ current_state,
     const double* __restrict__ pH,
     const double* __restrict__ E_volt, double T_kelvin, const double* __restrict__ dEin,
     const double* __restrict__ dGin, const double* __restrict__ u,
@@ -1293,7 +1570,7 @@ __global__ __launch_bounds__(kMC) void k_mc_step(
                     int ga = sd.site_atoms[ar0 + a], gc = sd.site_atoms[ap0 + c];
                     double K = pairK((double)X[ga] - (double)X[gc], (double)Y[ga] - (double)Y[gc],
                                      (double)Z[ga] - (double)Z[gc], R64[ga], A64[ga], R64[gc],
-                                     A64[gc], kC, kT, kO, kap);
+                                     A64[gc], kC, kT, kO, kap, cut2);
                     part[0] += (qr1[a] - qr0[a]) * (qp1[c] - qp0[c]) * K;
                 }
                 block_sum<1, kMC / kTile>(red, part);
@@ -1349,7 +1626,7 @@ template <typename T>
 __global__ __launch_bounds__(kSDE) void k_mc_sweep(
     SiteDev sd, const T* __restrict__ X, const T* __restrict__ Y, const T* __restrict__ Z,
     const T* __restrict__ Q, T* __restrict__ Qout, const double* __restrict__ R64,
-    const double* __restrict__ A64, double kC, double kT, double kO, double kap,
+    const double* __restrict__ A64, double kC, double kT, double kO, double kap, double cut2,
     const unsigned long long* __restrict__ phi_fx, int32_t* __restrict__ current_state,
     const double* __restrict__ pH, const double* __restrict__ E_volt, double T_kelvin, int kinds,
     const double* __restrict__ u, int32_t* __restrict__ n_electrons,
@@ -1426,7 +1703,7 @@ __global__ __launch_bounds__(kSDE) void k_mc_sweep(
                 const int ia = a0 + a, ic = a0 + c;
                 const double K = (a == c) ? -gb_kd(sR[ia], kC, kT, kO, kap) / sR[ia]
                                           : 2.0 * pairK(sx[ia] - sx[ic], sy[ia] - sy[ic], sz[ia] - sz[ic],
-                                                        sR[ia], sA[ia], sR[ic], sA[ic], kC, kT, kO, kap);
+                                                        sR[ia], sA[ia], sR[ic], sA[ic], kC, kT, kO, kap, cut2);
                 part[1] += sdq[a] * sdq[c] * K;
             }
             block_sum<2, kSDE / kTile>(red, part);
@@ -1451,7 +1728,7 @@ __global__ __launch_bounds__(kSDE) void k_mc_sweep(
                         const int ic = a0 + c;
                         d += sdq[c] * (i == ic ? -gb_kd(sR[i], kC, kT, kO, kap) / sR[i]
                                                : pairK(sx[i] - sx[ic], sy[i] - sy[ic], sz[i] - sz[ic],
-                                                       sR[i], sA[i], sR[ic], sA[ic], kC, kT, kO, kap));
+                                                       sR[i], sA[i], sR[ic], sA[ic], kC, kT, kO, kap, cut2));
                     }
                     sphi[i] += d;
                 }
@@ -1503,6 +1780,12 @@ __global__ __launch_bounds__(256) void k_remd_exchange(int M, const double* __re
 
 // ============================================================ launchers
 
+// Squared pair cutoff of the FP64 Monte Carlo kernels (infinite for none).
+static inline double cut2_of(const GBConst& c)
+{
+    return c.cutoff > 0.0 ? c.cutoff * c.cutoff : __builtin_huge_val();
+}
+
 static inline int blocks_for(size_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
 // Launch of a kernel that the timing hook measures.  With the hook on (ev not
@@ -1527,7 +1810,8 @@ static inline int blocks_for(size_t n, int bs) { return (int)((n + bs - 1) / bs)
     }
 
 template <typename T>
-hipError_t launch_radii(const WorkItem* items, int n_items, int wpg, int n_atoms, const int32_t*,
+hipError_t launch_radii(const WorkItem* items, int n_items, int wpg, int n_atoms,
+                        const BlockSpan* blocks, int n_blocks,
                         const T* x, const T* y, const T* z, const T* rho, const T* screen,
                         const GBConst& c, const Work<T>& w, T* born_R, hipStream_t s,
                         hipEvent_t* ev)
@@ -1537,10 +1821,21 @@ hipError_t launch_radii(const WorkItem* items, int n_items, int wpg, int n_atoms
     hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms, w.perm,
                        x, y, z, (const T*)nullptr, rho, screen, (T)c.offset, w.P, w.Gx, w.I_fx, 1,
                        w.ovf);
+    // block bounds for the cutoff passes (this call's and gb_energy_forces')
+    if ((c.rgbmax > 0.0 || c.cutoff > 0.0) && n_blocks > 0)
+        hipLaunchKernelGGL(k_block_bounds<T>, dim3(blocks_for(n_blocks, 4)), dim3(256), 0, s, blocks,
+                           n_blocks, w.P, w.Gx, w.bnd, w.smax);
     if (n_items > 0) {
-        GBMC_DISPATCH_W(wpg, GBMC_LAUNCH_TIMED(ev, kKRadii, (k_radii_pairs<T, W>),
-                                               dim3(blocks_for(n_items, W)), dim3(kTile * W), s,
-                                               items, n_items, w.P, w.Gx, w.I_fx, w.ovf));
+        if (c.rgbmax > 0.0)
+            GBMC_DISPATCH_W(wpg, GBMC_LAUNCH_TIMED(ev, kKRadii, (k_radii_pairs<T, W, true>),
+                                                   dim3(blocks_for(n_items, W)), dim3(kTile * W), s,
+                                                   items, n_items, w.P, w.Gx, w.I_fx, w.ovf, w.bnd,
+                                                   w.smax, (T)c.rgbmax))
+        else
+            GBMC_DISPATCH_W(wpg, GBMC_LAUNCH_TIMED(ev, kKRadii, (k_radii_pairs<T, W, false>),
+                                                   dim3(blocks_for(n_items, W)), dim3(kTile * W), s,
+                                                   items, n_items, w.P, w.Gx, w.I_fx, w.ovf, w.bnd,
+                                                   w.smax, (T)0))
     }
     hipLaunchKernelGGL(k_radii_finalize<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
                        rho, c, w, born_R);
@@ -1549,6 +1844,7 @@ hipError_t launch_radii(const WorkItem* items, int n_items, int wpg, int n_atoms
 
 template <typename T>
 hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_atoms, int n_sys,
+                                const BlockSpan* blocks, int n_blocks,
                                 const T* x, const T* y, const T* z, const T* q, const T* rho,
                                 const T* screen, const GBConst& c, const Work<T>& w,
                                 double* e_coul, double* e_gb, T* force, T* dEdq, T* dEdrho,
@@ -1562,18 +1858,33 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
         hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
                            w.perm, x, y, z, q, rho, screen, (T)c.offset, w.P, w.Gx, w.F_fx, 8,
                            (int*)nullptr);
+    // block bounds (positions as staged here, the same as the preceding
+    // gb_radii call's)
+    if ((c.rgbmax > 0.0 || c.cutoff > 0.0) && n_blocks > 0)
+        hipLaunchKernelGGL(k_block_bounds<T>, dim3(blocks_for(n_blocks, 4)), dim3(256), 0, s, blocks,
+                           n_blocks, w.P, w.Gx, w.bnd, w.smax);
     if (pe.n_items > 0) {
         const SaltK<T> sk{(T)c.kO, (T)c.kappa, (T)(c.kappa * kLog2e)};
-#define GBMC_ENERGY_LAUNCH(G_, S_)                                                                \
+        const CutK<T> ck{(T)c.cutoff, (T)(c.cutoff * c.cutoff)};
+#define GBMC_ENERGY_LAUNCH(G_, S_, C_)                                                            \
     GBMC_DISPATCH_W(pe.waves_per_group,                                                          \
-                    GBMC_LAUNCH_TIMED(ev, kKEnergy, (k_energy_pairs<T, G_, W, S_>),              \
+                    GBMC_LAUNCH_TIMED(ev, kKEnergy, (k_energy_pairs<T, G_, W, S_, C_>),          \
                                       dim3(blocks_for(pe.n_items, W)), dim3(kTile * W), s,       \
                                       pe.items, pe.n_items, w.P, w.R_t, w.a_t, (T)c.kC, (T)c.kT, \
-                                      sk, w))
-        if (c.kappa != 0.0) {
-            if (grad) GBMC_ENERGY_LAUNCH(true, true) else GBMC_ENERGY_LAUNCH(false, true)
+                                      sk, ck, w))
+        const bool salt = c.kappa != 0.0, cut = c.cutoff > 0.0;
+        if (grad) {
+            if (salt) {
+                if (cut) GBMC_ENERGY_LAUNCH(true, true, true) else GBMC_ENERGY_LAUNCH(true, true, false)
+            } else {
+                if (cut) GBMC_ENERGY_LAUNCH(true, false, true) else GBMC_ENERGY_LAUNCH(true, false, false)
+            }
         } else {
-            if (grad) GBMC_ENERGY_LAUNCH(true, false) else GBMC_ENERGY_LAUNCH(false, false)
+            if (salt) {
+                if (cut) GBMC_ENERGY_LAUNCH(false, true, true) else GBMC_ENERGY_LAUNCH(false, true, false)
+            } else {
+                if (cut) GBMC_ENERGY_LAUNCH(false, false, true) else GBMC_ENERGY_LAUNCH(false, false, false)
+            }
         }
 #undef GBMC_ENERGY_LAUNCH
     }
@@ -1583,10 +1894,17 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
         hipLaunchKernelGGL(k_energy_finalize<T>, dim3(n_sum + n_fin), dim3(256), 0, s, n_atoms, n_sum,
                            w, e_coul, e_gb, dEdq, grad);
     if (chain && pc.n_items > 0) {
-        GBMC_DISPATCH_W(pc.waves_per_group,
-                        GBMC_LAUNCH_TIMED(ev, kKChain, (k_chain_pairs<T, W>),
-                                          dim3(blocks_for(pc.n_items, W)), dim3(kTile * W), s,
-                                          pc.items, pc.n_items, w.P, w.Gx, w.Brt_t, w));
+        if (c.rgbmax > 0.0)
+            GBMC_DISPATCH_W(pc.waves_per_group,
+                            GBMC_LAUNCH_TIMED(ev, kKChain, (k_chain_pairs<T, W, true>),
+                                              dim3(blocks_for(pc.n_items, W)), dim3(kTile * W), s,
+                                              pc.items, pc.n_items, w.P, w.Gx, w.Brt_t, w,
+                                              (T)c.rgbmax))
+        else
+            GBMC_DISPATCH_W(pc.waves_per_group,
+                            GBMC_LAUNCH_TIMED(ev, kKChain, (k_chain_pairs<T, W, false>),
+                                              dim3(blocks_for(pc.n_items, W)), dim3(kTile * W), s,
+                                              pc.items, pc.n_items, w.P, w.Gx, w.Brt_t, w, (T)0))
     }
     if (chain && n_atoms > 0)
         hipLaunchKernelGGL(k_grad_finalize<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s,
@@ -1605,10 +1923,10 @@ hipError_t launch_state_dE(const SiteDev& sd, int n_atoms, const T* x, const T* 
         hipLaunchKernelGGL(k_clear64, dim3(blocks_for(sd.n_site_atoms, 256)), dim3(256), 0, s, phi_fx,
                            sd.n_site_atoms);
         GBMC_LAUNCH_TIMED(ev, kKSiteRows, k_site_phi_rows<T>, dim3(sd.n_rowitems), dim3(kTile), s,
-                          sd.rowitems, sd.site_atoms, w.rows, q, c.kC, c.kT, c.kO, c.kappa, phi_fx, w.ovf);
+                          sd.rowitems, sd.site_atoms, w.rows, q, c.kC, c.kT, c.kO, c.kappa, cut2_of(c), phi_fx, w.ovf);
     }
     GBMC_LAUNCH_TIMED(ev, kKSiteDE, k_site_dE<T>, dim3(sd.n_sites), dim3(kSDE), s, sd, x, y, z, q,
-                      w.R64, w.A64, c.kC, c.kT, c.kO, c.kappa, phi_fx, current_state, pH, E_volt, T_kelvin, dE,
+                      w.R64, w.A64, c.kC, c.kT, c.kO, c.kappa, cut2_of(c), phi_fx, current_state, pH, E_volt, T_kelvin, dE,
                       dG);
     return hipGetLastError();
 }
@@ -1623,7 +1941,7 @@ hipError_t launch_mc_step(const SiteDev& sd, int n_sys, const T* x, const T* y, 
 {
     if (n_sys == 0) return hipSuccess;
     GBMC_LAUNCH_TIMED(ev, kKMCStep, k_mc_step<T>, dim3(n_sys), dim3(kMC), s, sd, x, y, z, q, w.R64,
-                      w.A64, c.kC, c.kT, c.kO, c.kappa, current_state, pH, E_volt, T_kelvin, dE, dG, u, n_electrons,
+                      w.A64, c.kC, c.kT, c.kO, c.kappa, cut2_of(c), current_state, pH, E_volt, T_kelvin, dE, dG, u, n_electrons,
                       counters, accepted);
     return hipGetLastError();
 }
@@ -1641,11 +1959,11 @@ hipError_t launch_mc_sweep(const SiteDev& sd, int n_sys, int n_sa_max, const T* 
         hipLaunchKernelGGL(k_clear64, dim3(blocks_for(sd.n_site_atoms, 256)), dim3(256), 0, s, phi_fx,
                            sd.n_site_atoms);
         hipLaunchKernelGGL(k_site_phi_rows<T>, dim3(sd.n_rowitems), dim3(kTile), 0, s, sd.rowitems,
-                           sd.site_atoms, w.rows, q, c.kC, c.kT, c.kO, c.kappa, phi_fx, w.ovf);
+                           sd.site_atoms, w.rows, q, c.kC, c.kT, c.kO, c.kappa, cut2_of(c), phi_fx, w.ovf);
     }
     const size_t lds = (size_t)6 * sizeof(double) * (size_t)(n_sa_max > 0 ? n_sa_max : 1);
     hipLaunchKernelGGL(k_mc_sweep<T>, dim3(n_sys), dim3(kSDE), lds, s, sd, x, y, z, q, q_out, w.R64,
-                       w.A64, c.kC, c.kT, c.kO, c.kappa, phi_fx, current_state, pH, E_volt, T_kelvin, kinds, u,
+                       w.A64, c.kC, c.kT, c.kO, c.kappa, cut2_of(c), phi_fx, current_state, pH, E_volt, T_kelvin, kinds, u,
                        n_electrons, counters, accepted, dG);
     return hipGetLastError();
 }
@@ -1661,11 +1979,12 @@ hipError_t launch_remd_exchange(int M, const double* E_rung, const int32_t* Ne, 
 }
 
 #define GBMC_INSTANTIATE(T)                                                                      \
-    template hipError_t launch_radii<T>(const WorkItem*, int, int, int, const int32_t*, const T*,\
+    template hipError_t launch_radii<T>(const WorkItem*, int, int, int, const BlockSpan*, int,  \
+                                        const T*,                                                \
                                         const T*, const T*, const T*, const T*, const GBConst&,  \
                                         const Work<T>&, T*, hipStream_t, hipEvent_t*);           \
     template hipError_t launch_energy_forces<T>(const PassShape&, const PassShape&, int, int,      \
-                                                const T*,                                          \
+                                                const BlockSpan*, int, const T*,                   \
                                                 const T*, const T*, const T*, const T*,          \
                                                 const T*, const GBConst&, const Work<T>&,        \
                                                 double*, double*, T*, T*, T*, hipStream_t,       \

@@ -51,16 +51,18 @@ def _i32p(a):
 
 def test_params_validation(L):
     lib = L.load()
-    ok = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, 0.0)
+    ok = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, 0.0, 0.0, 0.0)
     assert lib.gbmc_params_validate(C.byref(ok)) == L.GBMC_OK
-    salt = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, 0.1)
+    salt = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, 0.1, 12.0, 15.0)
     assert lib.gbmc_params_validate(C.byref(salt)) == L.GBMC_OK
-    neg = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, -0.1)
+    neg = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, -0.1, 0.0, 0.0)
     assert lib.gbmc_params_validate(C.byref(neg)) == L.GBMC_ERR_INVALID
     assert b"kappa" in lib.gbmc_last_error()
-    bad = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 0.0, 78.5, 332.0522, 0.0)
+    negc = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, 0.0, -1.0, 0.0)
+    assert lib.gbmc_params_validate(C.byref(negc)) == L.GBMC_ERR_INVALID
+    bad = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 0.0, 78.5, 332.0522, 0.0, 0.0, 0.0)
     assert lib.gbmc_params_validate(C.byref(bad)) == L.GBMC_ERR_INVALID
-    nan = L.gbmc_gb_params(float("nan"), 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, 0.0)
+    nan = L.gbmc_gb_params(float("nan"), 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, 0.0, 0.0, 0.0)
     assert lib.gbmc_params_validate(C.byref(nan)) == L.GBMC_ERR_INVALID
 
 
@@ -182,7 +184,7 @@ def test_exchange_rejects_bad_arguments_on_host(L):
 
 def test_entry_points_reject_null_plan(L):
     lib = L.load()
-    p = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, 0.0)
+    p = L.gbmc_gb_params(1.0, 0.8, 4.85, 0.09, 1.0, 78.5, 332.0522, 0.0, 0.0, 0.0)
     a = L.gbmc_atoms()
     assert lib.gb_radii(None, C.byref(a), C.byref(p), None, None, None) == L.GBMC_ERR_INVALID
     assert lib.gb_energy_forces(None, C.byref(a), C.byref(p), None, None, None, None, None, None,
