@@ -54,6 +54,8 @@ def parse():
                          "(by default it runs on a second stream beside them, with "
                          "double-buffered charges)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cutoff-bench", action="store_true",
+                    help="skip the large-globule cutoff measurement")
     ap.add_argument("--md-steps", type=int, default=100,
                     help="steps of the timed simulation loop (0: skip)")
     ap.add_argument("--no-fp64", action="store_true")
@@ -288,6 +290,81 @@ def time_sweep(w, reps=20):
             "acceptance": tot[1] / max(1, tot[0])}
 
 
+def time_salt(w, kappa=0.1, steps=20):
+    """The force passes with salt (kappa = 0.1 / A, about 0.1 M) beside the
+    same passes without: radii and energy / forces of the batch, eager,
+    per-kernel means from the timing hook (no Monte Carlo branch sharing the
+    GPU, so the means are below those of the full step)."""
+    import dataclasses
+    g, plan = w.g, w.plan
+    atoms = w.latest
+    res = {}
+    for kap in (0.0, kappa):
+        p = dataclasses.replace(w.params, kappa=kap)
+        g.radii(plan, atoms, p)
+        g.energy_forces(plan, atoms, p)
+        w.torch.cuda.synchronize()
+        plan.set_timing(True)
+        plan.kernel_ms()
+        for _ in range(steps):
+            g.radii(plan, atoms, p)
+            g.energy_forces(plan, atoms, p)
+        w.torch.cuda.synchronize()
+        ms = plan.kernel_ms()
+        plan.set_timing(False)
+        res[kap] = {k: v for k, v in ms.items() if k in ("radii_pairs", "energy_pairs", "chain_pairs")}
+    salt, base = res[kappa], res[0.0]
+    return {"kappa_per_A": kappa, "kernel_ms": salt, "kernel_ms_no_salt": base,
+            "energy_pairs_salt_over_no_salt": salt["energy_pairs"] / base["energy_pairs"],
+            "pair_interactions_per_s_force_passes": w.pairs / (sum(salt.values()) * 1e-3)}
+
+
+def time_cutoff(n_atoms=100000, rgbmax=15.0, cutoff=16.0, steps=10, jb=4):
+    """Force evaluations (radii + energy / forces / dE/dq / dE/drho) of one
+    large globule with the descreening and pair cutoffs, against the same
+    evaluation over all pairs: per-kernel means from the timing hook and the
+    whole evaluation from HIP events, j ranges of 4 blocks per work item."""
+    import dataclasses
+    import torch
+    import paper_1803_09652_amd as g
+    import synth
+    from scipy.spatial import cKDTree
+    s = synth.make_system(140, n_atoms, 18.0 * (n_atoms / 2500.0) ** (1 / 3))
+    b = synth.make_batch([s])
+    plan = g.Plan(b.atom_offset, "fp32", j_blocks_per_item=jb)
+    plan.set_order(g.spatial_order(b.atom_offset, b.x, b.y, b.z))
+    atoms = g.Atoms.from_batch(plan, b)
+    out = {"workload": f"one {n_atoms}-atom globule, FP32 plan, rgbmax {rgbmax} A, pair cutoff "
+                       f"{cutoff} A", "j_blocks_per_item": jb}
+    for name, p, n in (("cutoff", dataclasses.replace(g.IGB5, rgbmax=rgbmax, cutoff=cutoff), steps),
+                       ("all_pairs", g.IGB5, 2)):
+        g.radii(plan, atoms, p)
+        g.energy_forces(plan, atoms, p)
+        torch.cuda.synchronize()
+        plan.set_timing(True)
+        plan.kernel_ms()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            g.radii(plan, atoms, p)
+            g.energy_forces(plan, atoms, p)
+        e1.record()
+        torch.cuda.synchronize()
+        kms = plan.kernel_ms()
+        plan.set_timing(False)
+        out[name] = {"ms_per_evaluation": e0.elapsed_time(e1) / n,
+                     "kernel_ms": {k: v for k, v in kms.items()
+                                   if k in ("radii_pairs", "energy_pairs", "chain_pairs")}}
+    out["overflow"] = bool(g.check_overflow(plan))
+    t = cKDTree(s.coords())
+    within = (t.count_neighbors(t, cutoff) - s.n) // 2
+    out["pairs_within_cutoff"] = int(within)
+    out["pairs_all"] = s.n * (s.n - 1) // 2
+    out["speedup"] = out["all_pairs"]["ms_per_evaluation"] / out["cutoff"]["ms_per_evaluation"]
+    out["pairs_within_cutoff_per_s"] = within / (out["cutoff"]["ms_per_evaluation"] * 1e-3)
+    return out
+
+
 def time_md_loop(steps, warmup, n_rep=16, attempt_every=5, exchange_every=10):
     """The simulation loop (ReplicaMD) on the E-REMD batch for dynamics: 16
     replicas x 2,500 atoms, 2 fs Langevin steps (gamma 5 / ps, every atom
@@ -480,8 +557,11 @@ def main():
                            "per_kernel_tflops": {n: FLOPS_PER_PAIR[n] * pairs / (v * 1e-3) / 1e12
                                                  for n, v in pair_k.items()}}
     out["mc_sweep"] = time_sweep(w)
+    out["salt"] = time_salt(w)
     if args.md_steps > 0:
         out["md_loop"] = time_md_loop(args.md_steps, 10)
+    if not args.no_cutoff_bench:
+        out["cutoff"] = time_cutoff()
     cnt = w.counters.sum(0).cpu().tolist()
     out["mc_acceptance"] = {"state_attempts": cnt[0], "state_accepted": cnt[1],
                             "exchange_attempts_eager": w.exchanges_attempted,

@@ -519,6 +519,29 @@ __device__ __forceinline__ float block_gap(const Q4<float>& a, const Q4<float>& 
     return sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))) - a.w - b.w;
 }
 
+// The j blocks of an item that a cutoff may leave non-empty, found 64 at a
+// time: lane k evaluates near(chunk + k) and the ballot marks the tiles to
+// visit.  next(J) is the first such block at or after J (J1 if none); every
+// value is wave-uniform.
+struct TileCursor {
+    int chunk, J1;
+    unsigned long long mask;
+    template <class Near>
+    __device__ __forceinline__ int next(int J, int lane, Near&& near)
+    {
+        while (J < J1) {
+            if (J >= chunk + kTile) {
+                chunk = J;
+                mask = __ballot(J + lane < J1 && near(J + lane));
+            }
+            const unsigned long long rest = mask >> (J - chunk);
+            if (rest) return J + __builtin_ctzll(rest);
+            J = chunk + kTile;
+        }
+        return J1;
+    }
+};
+
 // ---------------------------------------------------------------- helpers
 
 template <typename T>
@@ -735,24 +758,26 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
     for (int r = 0; r < R; ++r) ifix[r] = 0;
     bool bad = false;
     Q4<T> pj, gj;
-    fetch(w.J0, pj, gj);
-    // one tile; the first is peeled so that the loop is entered, as on every
-    // later trip, with the previous tile's sums still in flight
-    Q4<float> bI;
+    if constexpr (!CUT) fetch(w.J0, pj, gj);
+    // With a cutoff, tiles whose balls all lie beyond the cutoff spheres of
+    // the other block's atoms (both ways) add nothing and are not visited.
+    Q4<float> bI{};
     float sI = 0.0f;
     if constexpr (CUT) {
         bI = bnd[w.blk0 + w.I];
         sI = smax[w.blk0 + w.I];
     }
+    auto near = [&](int J) {
+        return block_gap(bI, bnd[w.blk0 + J]) - fmaxf(sI, smax[w.blk0 + J]) < (float)cR;
+    };
+    TileCursor tc{w.J0 - kTile, w.J1, 0ull};
+    int Jnext = w.J1;
+    // one tile, then the loads of the next tile; the first tile is peeled so
+    // that the loop is entered, as on every later trip, with the previous
+    // tile's sums still in flight
     auto tile = [&](int J) {
-        if constexpr (CUT) {
-            // every ball of block J lies beyond the cutoff sphere of every atom
-            // of block I and the reverse: the tile adds nothing
-            if (block_gap(bI, bnd[w.blk0 + J]) - fmaxf(sI, smax[w.blk0 + J]) >= (float)cR) {
-                fetch(J + 1 < w.J1 ? J + 1 : J, pj, gj);
-                return;
-            }
-        }
+        int Jn = J + 1;
+        if constexpr (CUT) Jnext = Jn = tc.next(J + 1, lane, near);
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
         T Sj;
@@ -763,7 +788,7 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
         sS[lane] = Sj;
         sS[lane + kTile] = Sj;
         wave_sync();
-        fetch(J + 1 < w.J1 ? J + 1 : J, pj, gj);     // the last trip re-reads J
+        fetch(Jn < w.J1 ? Jn : J, pj, gj);           // the last trip re-reads J
         T ai[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) ai[r] = T(0);
@@ -790,8 +815,15 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
 #pragma unroll
         for (int r = 0; r < R; ++r) ifix[r] += to_fixed((double)ai[r], kScaleI, bad);
     };
-    tile(w.J0);
-    for (int J = w.J0 + 1; J < w.J1; ++J) tile(J);
+    if constexpr (CUT) {
+        int J = tc.next(w.J0, lane, near);
+        if (J >= w.J1) return;                  // nothing within the cutoff: no sums to add
+        fetch(J, pj, gj);
+        for (; J < w.J1; J = Jnext) tile(J);
+    } else {
+        tile(w.J0);
+        for (int J = w.J0 + 1; J < w.J1; ++J) tile(J);
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r)
         if (vi[r]) fx_add(&I_fx[w.base + (w.I + r) * kTile + lane], ifix[r]);
@@ -902,26 +934,29 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
     bool bad = false;
     Q4<T> pj;
     T Rj, Aj;
-    fetch(w.J0, pj, Rj, Aj);
-    // one tile; the first is peeled so that the loop is entered, as on every
-    // later trip, with the previous tile's sums still in flight
+    if constexpr (!CUT) fetch(w.J0, pj, Rj, Aj);
+    // With a cutoff, tiles whose pairs (of every row) all lie beyond it are
+    // not visited.
     Q4<float> bI[R];
     if constexpr (CUT) {
 #pragma unroll
         for (int r = 0; r < R; ++r) bI[r] = wk.bnd[w.blk0 + w.I + r];
     }
-    auto tile = [&](int J) {
-        if constexpr (CUT) {
-            // every pair of the tile (of both rows) lies beyond the cutoff
-            const Q4<float> bJ = wk.bnd[w.blk0 + J];
-            bool far = true;
+    auto near = [&](int J) {
+        const Q4<float> bJ = wk.bnd[w.blk0 + J];
+        bool nr = false;
 #pragma unroll
-            for (int r = 0; r < R; ++r) far = far && block_gap(bI[r], bJ) >= (float)ck.cE;
-            if (far) {
-                fetch(J + 1 < w.J1 ? J + 1 : J, pj, Rj, Aj);
-                return;
-            }
-        }
+        for (int r = 0; r < R; ++r) nr = nr || block_gap(bI[r], bJ) < (float)ck.cE;
+        return nr;
+    };
+    TileCursor tc{w.J0 - kTile, w.J1, 0ull};
+    int Jnext = w.J1;
+    // one tile, then the loads of the next tile; the first tile is peeled so
+    // that the loop is entered, as on every later trip, with the previous
+    // tile's sums still in flight
+    auto tile = [&](int J) {
+        int Jn = J + 1;
+        if constexpr (CUT) Jnext = Jn = tc.next(J + 1, lane, near);
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
         tail(J, pj, Rj, Aj);
@@ -930,7 +965,7 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
         sR[lane] = Rj; sR[lane + kTile] = Rj;
         sA[lane] = Aj; sA[lane + kTile] = Aj;
         wave_sync();
-        fetch(J + 1 < w.J1 ? J + 1 : J, pj, Rj, Aj);
+        fetch(Jn < w.J1 ? Jn : J, pj, Rj, Aj);
         T fxi[R], fyi[R], fzi[R], Gi[R], phii[R], eC[R], eG[R];
 #pragma unroll
         for (int r = 0; r < R; ++r)
@@ -1033,8 +1068,15 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
             efix[r][1] += to_fixed((double)(-(SALT ? T(1) : kT) * eG[r]), kScaleE, bad);
         }
     };
-    tile(w.J0);
-    for (int J = w.J0 + 1; J < w.J1; ++J) tile(J);
+    if constexpr (CUT) {
+        int J = tc.next(w.J0, lane, near);
+        if (J >= w.J1) return;                  // nothing within the cutoff: no sums to add
+        fetch(J, pj, Rj, Aj);
+        for (; J < w.J1; J = Jnext) tile(J);
+    } else {
+        tile(w.J0);
+        for (int J = w.J0 + 1; J < w.J1; ++J) tile(J);
+    }
     if (bad) *wk.ovf = 1;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -1179,23 +1221,26 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
     bool bad = false;
     Q4<T> pj, gj, bj;
     T brj;
-    fetch(w.J0, pj, gj, brj);
-    // one tile; the first is peeled so that the loop is entered, as on every
-    // later trip, with the previous tile's sums still in flight
-    Q4<float> bI;
+    if constexpr (!CUT) fetch(w.J0, pj, gj, brj);
+    // With a cutoff, tiles where no ball of either block reaches into the
+    // other's cutoff spheres are not visited.
+    Q4<float> bI{};
     float sI = 0.0f;
     if constexpr (CUT) {
         bI = wk.bnd[w.blk0 + w.I];
         sI = wk.smax[w.blk0 + w.I];
     }
+    auto near = [&](int J) {
+        return block_gap(bI, wk.bnd[w.blk0 + J]) - fmaxf(sI, wk.smax[w.blk0 + J]) < (float)cR;
+    };
+    TileCursor tc{w.J0 - kTile, w.J1, 0ull};
+    int Jnext = w.J1;
+    // one tile, then the loads of the next tile; the first tile is peeled so
+    // that the loop is entered, as on every later trip, with the previous
+    // tile's sums still in flight
     auto tile = [&](int J) {
-        if constexpr (CUT) {
-            // no ball of either block reaches into the other's cutoff spheres
-            if (block_gap(bI, wk.bnd[w.blk0 + J]) - fmaxf(sI, wk.smax[w.blk0 + J]) >= (float)cR) {
-                fetch(J + 1 < w.J1 ? J + 1 : J, pj, gj, brj);
-                return;
-            }
-        }
+        int Jn = J + 1;
+        if constexpr (CUT) Jnext = Jn = tc.next(J + 1, lane, near);
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
         tail(J, pj, bj, gj, brj);
@@ -1203,7 +1248,7 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
         sj[lane] = pj; sj[lane + kTile] = pj;
         sb[lane] = bj; sb[lane + kTile] = bj;
         wave_sync();
-        fetch(J + 1 < w.J1 ? J + 1 : J, pj, gj, brj);
+        fetch(Jn < w.J1 ? Jn : J, pj, gj, brj);
         T fxi[R], fyi[R], fzi[R], dri[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) fxi[r] = fyi[r] = fzi[r] = dri[r] = T(0);
@@ -1259,8 +1304,15 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
             fix[r][3] += to_fixed((double)dri[r], kScaleF, bad);
         }
     };
-    tile(w.J0);
-    for (int J = w.J0 + 1; J < w.J1; ++J) tile(J);
+    if constexpr (CUT) {
+        int J = tc.next(w.J0, lane, near);
+        if (J >= w.J1) return;                  // nothing within the cutoff: no sums to add
+        fetch(J, pj, gj, brj);
+        for (; J < w.J1; J = Jnext) tile(J);
+    } else {
+        tile(w.J0);
+        for (int J = w.J0 + 1; J < w.J1; ++J) tile(J);
+    }
     if (bad) *wk.ovf = 1;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
