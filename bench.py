@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--autotune", action="store_true",
                     help="sweep the work shapes first instead of using the library defaults "
                          "(the committed HBM counters were taken with the defaults)")
-    ap.add_argument("--order", choices=["spatial", "identity"], default="spatial",
+    ap.add_argument("--order", choices=["spatial", "blocks", "identity"], default="spatial",
                     help="processing order of the pair passes (results are order independent)")
     return ap.parse_args()
 
@@ -107,6 +107,8 @@ class Workload:
         self.plan = g.Plan(b.atom_offset, precision, j_blocks_per_item=jb, waves_per_group=wv)
         if order == "spatial":
             self.plan.set_order(g.spatial_order(b.atom_offset, b.x, b.y, b.z))
+        elif order == "blocks":
+            self.plan.set_order(g.block_order(b.atom_offset, b.x, b.y, b.z))
         self.atoms = g.Atoms.from_batch(self.plan, b)
         dev = self.plan.device
         # with overlap, two charge buffers: a step reads one and writes the
@@ -319,11 +321,12 @@ def time_salt(w, kappa=0.1, steps=20):
             "pair_interactions_per_s_force_passes": w.pairs / (sum(salt.values()) * 1e-3)}
 
 
-def time_cutoff(n_atoms=100000, rgbmax=15.0, cutoff=16.0, steps=10, jb=4):
+def time_cutoff(n_atoms=100000, rgbmax=15.0, cutoff=16.0, steps=10):
     """Force evaluations (radii + energy / forces / dE/dq / dE/drho) of one
     large globule with the descreening and pair cutoffs, against the same
     evaluation over all pairs: per-kernel means from the timing hook and the
-    whole evaluation from HIP events, j ranges of 4 blocks per work item."""
+    whole evaluation from HIP events.  Atoms in compact 64-atom blocks
+    (block_order), library default work shapes."""
     import dataclasses
     import torch
     import paper_1803_09652_amd as g
@@ -331,11 +334,11 @@ def time_cutoff(n_atoms=100000, rgbmax=15.0, cutoff=16.0, steps=10, jb=4):
     from scipy.spatial import cKDTree
     s = synth.make_system(140, n_atoms, 18.0 * (n_atoms / 2500.0) ** (1 / 3))
     b = synth.make_batch([s])
-    plan = g.Plan(b.atom_offset, "fp32", j_blocks_per_item=jb)
-    plan.set_order(g.spatial_order(b.atom_offset, b.x, b.y, b.z))
+    plan = g.Plan(b.atom_offset, "fp32")
+    plan.set_order(g.block_order(b.atom_offset, b.x, b.y, b.z))
     atoms = g.Atoms.from_batch(plan, b)
     out = {"workload": f"one {n_atoms}-atom globule, FP32 plan, rgbmax {rgbmax} A, pair cutoff "
-                       f"{cutoff} A", "j_blocks_per_item": jb}
+                       f"{cutoff} A, compact-block order"}
     for name, p, n in (("cutoff", dataclasses.replace(g.IGB5, rgbmax=rgbmax, cutoff=cutoff), steps),
                        ("all_pairs", g.IGB5, 2)):
         g.radii(plan, atoms, p)

@@ -157,6 +157,14 @@ gbmc_status gbmc_plan_set_order(gbmc_plan* plan, const int32_t* host_order);
 gbmc_status gbmc_spatial_order(int32_t n_systems, const int32_t* host_atom_offset, const double* x,
                                const double* y, const double* z, int32_t* order);
 
+/* Host-only helper: an order of each system's atoms in which every 64-atom
+ * block is a compact cluster, by recursive bisection along the longest side
+ * of the bounding box with every cut after a multiple of 64 atoms (ties by
+ * index).  Compact blocks have small bounding spheres, so the cutoff passes
+ * visit fewer tiles.  Same arguments as gbmc_spatial_order. */
+gbmc_status gbmc_block_order(int32_t n_systems, const int32_t* host_atom_offset, const double* x,
+                             const double* y, const double* z, int32_t* order);
+
 /* Bytes of caller-owned device workspace a plan needs (256-byte aligned).
  * The workspace carries per-atom state from gb_radii to gb_energy_forces and
  * mc_state_dE; one workspace may serve one stream at a time. */

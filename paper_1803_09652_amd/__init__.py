@@ -6,10 +6,12 @@ include/gbmc.h); this package is its Python binding.
 """
 from ._lib import GbmcError, load  # noqa: F401
 from .api import (  # noqa: F401
-    IGB2, IGB5, KIND_PROT, KIND_REDOX, Atoms, GBEnergy, GBParams, Plan, Sites, check_overflow,
-    energy_forces, md_step, mc_state_dE, mc_step, mc_sweep, radii, remd_exchange, spatial_order,
+    IGB2, IGB5, KIND_PROT, KIND_REDOX, Atoms, GBEnergy, GBParams, Plan, Sites, block_order,
+    check_overflow, energy_forces, md_step, mc_state_dE, mc_step, mc_sweep, radii, remd_exchange,
+    spatial_order,
 )
 
 __all__ = ["GbmcError", "load", "IGB2", "IGB5", "KIND_PROT", "KIND_REDOX", "Atoms", "GBEnergy",
-           "GBParams", "Plan", "Sites", "check_overflow", "energy_forces", "mc_state_dE", "mc_step",
-           "mc_sweep", "md_step", "radii", "remd_exchange", "spatial_order"]
+           "GBParams", "Plan", "Sites", "block_order", "check_overflow", "energy_forces",
+           "mc_state_dE", "mc_step", "mc_sweep", "md_step", "radii", "remd_exchange",
+           "spatial_order"]

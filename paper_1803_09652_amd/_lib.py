@@ -63,6 +63,8 @@ SIGNATURES = {
     "gbmc_plan_set_order": (_I32, [_VP, _I32P]),
     "gbmc_spatial_order": (_I32, [_I32, _I32P, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                   C.POINTER(C.c_double), _I32P]),
+    "gbmc_block_order": (_I32, [_I32, _I32P, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                C.POINTER(C.c_double), _I32P]),
     "gbmc_plan_workspace_bytes": (C.c_size_t, [_VP]),
     "gb_radii": (_I32, [_VP, C.POINTER(gbmc_atoms), C.POINTER(gbmc_gb_params), _VP, _VP, _VP]),
     "gb_energy_forces": (_I32, [_VP, C.POINTER(gbmc_atoms), C.POINTER(gbmc_gb_params), _VP, _VP,

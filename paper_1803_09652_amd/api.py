@@ -201,6 +201,18 @@ def spatial_order(atom_offset, x, y, z) -> np.ndarray:
     return out
 
 
+def block_order(atom_offset, x, y, z) -> np.ndarray:
+    """Order of each system's atoms in compact 64-atom clusters (recursive
+    bisection; host computation in libgbmc), for Plan.set_order."""
+    off = np.ascontiguousarray(atom_offset, dtype=np.int32)
+    f64 = lambda v: np.ascontiguousarray(np.asarray(v, dtype=np.float64))
+    xs, ys, zs = f64(x), f64(y), f64(z)
+    out = np.zeros(int(off[-1]), dtype=np.int32)
+    L.check(L.load().gbmc_block_order(int(off.size - 1), _i32p(off), _f64p(xs), _f64p(ys),
+                                      _f64p(zs), _i32p(out)))
+    return out
+
+
 def radii(plan: Plan, atoms: Atoms, params: GBParams = IGB5) -> torch.Tensor:
     """Effective Born radii R[N] (plan dtype); leaves the per-atom state in the
     plan's workspace for energy_forces and mc_state_dE."""

@@ -58,6 +58,8 @@ struct gbmc_plan {
     int32_t* d_offset = nullptr;     // [B+1] device copy of the atom offsets
     int32_t n_blocks = 0;            // 64-atom blocks of the batch
     BlockSpan* d_blocks = nullptr;   // [n_blocks] atoms of each block (processing order)
+    int32_t n_chunks = 0;            // cutoff passes: block rows in chunks of 64 j blocks
+    WorkItem* d_chunks = nullptr;
     int device = 0;
     // timing hook: a ring of start/stop event pairs per timed kernel (bound to
     // the dispatches while enabled), the launches recorded since the last
@@ -69,7 +71,8 @@ struct gbmc_plan {
     // workspace layout (byte offsets)
     size_t off_I, off_F, off_G, off_phi, off_drho, off_EA, off_I64, off_R64, off_T64, off_dR64,
         off_G64, off_B64, off_Rt, off_at, off_Brt, off_ovf, off_P, off_Gx, off_A64, off_rows, off_bnd,
-        off_smax, ws_bytes;
+        off_smax, off_cit0, off_cit1, off_ccount, ws_bytes;
+    int32_t cut_cap = 0;             // capacity of each compacted cutoff work list
 };
 
 struct gbmc_sites {
@@ -193,6 +196,10 @@ static Work<T> carve(const gbmc_plan* p, void* ws)
     w.ovf = reinterpret_cast<int*>(b + p->off_ovf);
     w.bnd = reinterpret_cast<Q4<float>*>(b + p->off_bnd);
     w.smax = reinterpret_cast<float*>(b + p->off_smax);
+    w.citems[0] = reinterpret_cast<CutItem*>(b + p->off_cit0);
+    w.citems[1] = reinterpret_cast<CutItem*>(b + p->off_cit1);
+    w.ccount = reinterpret_cast<int*>(b + p->off_ccount);
+    w.cut_cap = p->cut_cap;
     return w;
 }
 
@@ -227,7 +234,15 @@ static void layout(gbmc_plan* p)
     p->off_rows = seg(sizeof(Row64) * N);
     p->off_bnd = seg(sizeof(Q4<float>) * (size_t)p->n_blocks);
     p->off_smax = seg(sizeof(float) * (size_t)p->n_blocks);
+    p->off_cit0 = seg(sizeof(CutItem) * (size_t)p->cut_cap);
+    p->off_cit1 = seg(sizeof(CutItem) * (size_t)p->cut_cap);
+    p->off_ccount = seg(2 * sizeof(int));
     p->ws_bytes = o;
+}
+
+static CutPlan cut_plan(const gbmc_plan* p)
+{
+    return CutPlan{p->d_blocks, p->n_blocks, p->d_chunks, p->n_chunks};
 }
 
 static GBConst make_const(const gbmc_gb_params* gp)
@@ -341,6 +356,16 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
             for (int32_t a = host_atom_offset[b]; a < host_atom_offset[b + 1]; a += kTile)
                 blocks.push_back(BlockSpan{a, std::min(kTile, host_atom_offset[b + 1] - a)});
         p->n_blocks = (int32_t)blocks.size();
+        // chunks of the cutoff passes: every block row against its j blocks,
+        // 64 at a time (the compaction kernel scans one chunk per wave)
+        std::vector<WorkItem> chunks;
+        build_items(n_systems, host_atom_offset, kCutChunk, false, chunks);
+        if ((uint64_t)chunks.size() * (kCutChunk / kCutTiles) > 0x7fffffffull) {
+            delete p;
+            return fail(GBMC_ERR_UNSUPPORTED, "too many blocks for the cutoff work lists");
+        }
+        p->n_chunks = (int32_t)chunks.size();
+        p->cut_cap = p->n_chunks * (kCutChunk / kCutTiles);
         layout(p);
         hipError_t e = hipGetDevice(&p->device);
         if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
@@ -357,7 +382,8 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
         const size_t off_bytes = 4 * (size_t)(n_systems + 1);
         const size_t at_off = align256(o + 4 * (size_t)p->n_atoms);
         const size_t at_blk = align256(at_off + off_bytes);
-        const size_t total = at_blk + sizeof(BlockSpan) * blocks.size();
+        const size_t at_chk = align256(at_blk + sizeof(BlockSpan) * blocks.size());
+        const size_t total = at_chk + sizeof(WorkItem) * chunks.size();
         if (total > 0) {
             char* d = nullptr;
             e = hipMalloc(&d, total);
@@ -377,6 +403,9 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
             p->d_blocks = reinterpret_cast<BlockSpan*>(d + at_blk);
             if (!blocks.empty())
                 std::memcpy(h.data() + at_blk, blocks.data(), sizeof(BlockSpan) * blocks.size());
+            p->d_chunks = reinterpret_cast<WorkItem*>(d + at_chk);
+            if (!chunks.empty())
+                std::memcpy(h.data() + at_chk, chunks.data(), sizeof(WorkItem) * chunks.size());
             e = hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice);
             if (e != hipSuccess) { (void)hipFree(d); delete p; return hip_fail(e, "hipMemcpy(plan tables)"); }
         }
@@ -523,6 +552,55 @@ gbmc_status gbmc_spatial_order(int32_t n_systems, const int32_t* off, const doub
     }
 }
 
+// Recursive bisection of one system's atoms (indices idx[lo, hi)) along the
+// longest side of their bounding box, each cut after a multiple of 64 atoms,
+// so that every 64-atom block of the result is one compact leaf.
+static void bisect_blocks(const double* x, const double* y, const double* z, int32_t* idx,
+                          int32_t lo, int32_t hi)
+{
+    const int32_t n = hi - lo;
+    if (n <= kTile) return;
+    double mn[3] = {x[idx[lo]], y[idx[lo]], z[idx[lo]]}, mx[3] = {mn[0], mn[1], mn[2]};
+    for (int32_t k = lo; k < hi; ++k) {
+        const double v[3] = {x[idx[k]], y[idx[k]], z[idx[k]]};
+        for (int d = 0; d < 3; ++d) {
+            mn[d] = std::min(mn[d], v[d]);
+            mx[d] = std::max(mx[d], v[d]);
+        }
+    }
+    int axis = 0;
+    for (int d = 1; d < 3; ++d)
+        if (mx[d] - mn[d] > mx[axis] - mn[axis]) axis = d;
+    const double* c = axis == 0 ? x : (axis == 1 ? y : z);
+    const int32_t nb = (n + kTile - 1) / kTile;
+    const int32_t mid = lo + kTile * (nb / 2);
+    // ties broken by index, so the order does not depend on the library's nth_element
+    std::nth_element(idx + lo, idx + mid, idx + hi, [c](int32_t a, int32_t b) {
+        return c[a] < c[b] || (c[a] == c[b] && a < b);
+    });
+    bisect_blocks(x, y, z, idx, lo, mid);
+    bisect_blocks(x, y, z, idx, mid, hi);
+}
+
+gbmc_status gbmc_block_order(int32_t n_systems, const int32_t* off, const double* x,
+                             const double* y, const double* z, int32_t* order)
+{
+    try {
+        gbmc_status st = check_offsets(n_systems, off);
+        if (st != GBMC_OK) return st;
+        const int32_t N = n_systems > 0 ? off[n_systems] : 0;
+        if (N > 0 && (!x || !y || !z || !order)) return fail(GBMC_ERR_INVALID, "NULL argument");
+        for (int32_t k = 0; k < N; ++k)
+            if (!std::isfinite(x[k]) || !std::isfinite(y[k]) || !std::isfinite(z[k]))
+                return fail(GBMC_ERR_INVALID, "non-finite coordinate");
+        for (int32_t k = 0; k < N; ++k) order[k] = k;
+        for (int32_t b = 0; b < n_systems; ++b) bisect_blocks(x, y, z, order, off[b], off[b + 1]);
+        return GBMC_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(GBMC_ERR_INVALID, "host allocation failed");
+    }
+}
+
 // The event pairs for the kernels a call launches (ids), or NULL when the
 // timing hook is off.
 static hipEvent_t* events(gbmc_plan* p, std::initializer_list<int> ids)
@@ -546,14 +624,14 @@ gbmc_status gb_radii(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp
     if (p->prec == GBMC_FP32_FIXED)
         e = launch_radii<float>(p->d_items[GBMC_PASS_RADII], p->n_items[GBMC_PASS_RADII],
                                 p->tuning.waves_per_group[GBMC_PASS_RADII], p->n_atoms,
-                                p->d_blocks, p->n_blocks, (const float*)a->x,
+                                cut_plan(p), (const float*)a->x,
                                 (const float*)a->y, (const float*)a->z, (const float*)a->rho,
                                 (const float*)a->screen, c, carve<float>(p, ws), (float*)born_R, s,
                                 p->n_items[GBMC_PASS_RADII] > 0 ? events(p, {kKRadii}) : nullptr);
     else
         e = launch_radii<double>(p->d_items[GBMC_PASS_RADII], p->n_items[GBMC_PASS_RADII],
                                  p->tuning.waves_per_group[GBMC_PASS_RADII], p->n_atoms,
-                                 p->d_blocks, p->n_blocks, (const double*)a->x,
+                                 cut_plan(p), (const double*)a->x,
                                  (const double*)a->y, (const double*)a->z, (const double*)a->rho,
                                  (const double*)a->screen, c, carve<double>(p, ws), (double*)born_R, s,
                                  p->n_items[GBMC_PASS_RADII] > 0 ? events(p, {kKRadii}) : nullptr);
@@ -576,13 +654,13 @@ gbmc_status gb_energy_forces(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_pa
                        p->tuning.waves_per_group[GBMC_PASS_CHAIN]};
     hipError_t e;
     if (p->prec == GBMC_FP32_FIXED)
-        e = launch_energy_forces<float>(pe, pc, p->n_atoms, p->n_sys, p->d_blocks, p->n_blocks,
+        e = launch_energy_forces<float>(pe, pc, p->n_atoms, p->n_sys, cut_plan(p),
                                         (const float*)a->x, (const float*)a->y, (const float*)a->z,
                                         (const float*)a->q, (const float*)a->rho,
                                         (const float*)a->screen, c, carve<float>(p, ws), e_coul,
                                         e_gb, (float*)force, (float*)dEdq, (float*)dEdrho, s, ev);
     else
-        e = launch_energy_forces<double>(pe, pc, p->n_atoms, p->n_sys, p->d_blocks, p->n_blocks,
+        e = launch_energy_forces<double>(pe, pc, p->n_atoms, p->n_sys, cut_plan(p),
                                          (const double*)a->x, (const double*)a->y,
                                          (const double*)a->z, (const double*)a->q,
                                          (const double*)a->rho, (const double*)a->screen, c,

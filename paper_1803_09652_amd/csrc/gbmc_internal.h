@@ -43,6 +43,25 @@ struct BlockSpan {
     int32_t start, count;
 };
 
+// One work item of a cutoff pass, written on the device: i block I of the
+// system at [base, base + n) against the j blocks J0 + k, k < J1 - J0 <= 64,
+// whose bit k is set in the mask (mask_hi:mask_lo); at most kCutTiles bits.
+struct CutItem {
+    int32_t base, n, I, J0, J1, blk0;
+    uint32_t mask_lo, mask_hi;
+};
+constexpr int kCutTiles = 4;
+constexpr int kCutChunk = 64;            // j blocks per chunk of a block row
+
+// Static tables of the cutoff passes: the 64-atom blocks of the batch and the
+// chunks of 64 j blocks of every block row that the compaction kernel scans.
+struct CutPlan {
+    const BlockSpan* blocks;
+    int n_blocks;
+    const WorkItem* chunks;
+    int n_chunks;
+};
+
 // One FP64 potential-row work item: up to 64 site atoms [sa0, sa1) of one system
 // against the system's atoms [j0, j1); each lane adds its partial sum in fixed
 // point to phi_fx[out + k] (the flattened site-atom slot).
@@ -88,6 +107,10 @@ struct Work {
     int* ovf;                     // overflow flag
     Q4<float>* bnd;               // [n_blocks] bounding sphere of each block: centre, radius
     float* smax;                  // [n_blocks] largest S = screen (rho - offset) of each block
+    CutItem* citems[2];           // [cut_cap] each: compacted items (0: descreening and
+                                  //  chain passes, 1: energy pass)
+    int* ccount;                  // [2] their counts
+    int cut_cap;                  // capacity of each list: n_chunks * (kCutChunk / kCutTiles)
 };
 
 struct SiteDev {
@@ -144,7 +167,7 @@ enum KernelId { kKRadii = 0, kKEnergy = 1, kKChain = 2, kKSiteRows = 3, kKSiteDE
 // the dispatch of each timed kernel.
 template <typename T>
 hipError_t launch_radii(const WorkItem* items, int n_items, int waves_per_group, int n_atoms,
-                        const BlockSpan* blocks, int n_blocks,
+                        const CutPlan& cp,
                         const T* x, const T* y, const T* z, const T* rho, const T* screen,
                         const GBConst& c, const Work<T>& w, T* born_R, hipStream_t s,
                         hipEvent_t* ev);
@@ -156,7 +179,7 @@ struct PassShape {
 
 template <typename T>
 hipError_t launch_energy_forces(const PassShape& energy, const PassShape& chain, int n_atoms,
-                                int n_sys, const BlockSpan* blocks, int n_blocks,
+                                int n_sys, const CutPlan& cp,
                                 const T* x, const T* y, const T* z, const T* q, const T* rho,
                                 const T* screen, const GBConst& c, const Work<T>& w,
                                 double* e_coul, double* e_gb, T* force, T* dEdq, T* dEdrho,

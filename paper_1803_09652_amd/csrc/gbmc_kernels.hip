@@ -27,6 +27,8 @@
 #include <hip/hip_ext.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "gbmc_internal.h"
 
 namespace gbmc {
@@ -362,17 +364,16 @@ __device__ __forceinline__ void radii_pair_cut(float xi, float yi, float zi, flo
     hji = xji * yji * invr * hct_poly(yji);
     const bool out_ij = (r - Sj >= c) | (c <= rti), out_ji = (r - Si >= c) | (c <= rtj);
     const bool st_ij = !out_ij & (r + Sj > c), st_ji = !out_ji & (r + Si > c);
-    const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX) & !st_ij;
-    const bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX) & !st_ji;
+    const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX);
+    const bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX);
     if (!(f_ij & f_ji)) {
-        if (!f_ij) {
-            hij = hct_slow32<false>(r, invr, rti, Sj, nullptr);
-            if (st_ij) hij -= hct_slow32<false>(r, invr, c, Sj, nullptr);
-        }
-        if (!f_ji) {
-            hji = hct_slow32<false>(r, invr, rtj, Si, nullptr);
-            if (st_ji) hji -= hct_slow32<false>(r, invr, c, Si, nullptr);
-        }
+        if (!f_ij) hij = hct_slow32<false>(r, invr, rti, Sj, nullptr);
+        if (!f_ji) hji = hct_slow32<false>(r, invr, rtj, Si, nullptr);
+    }
+    // the part of a straddling ball beyond c (the c term has L = c)
+    if (st_ij | st_ji) {
+        if (st_ij) hij -= hct_slow32<false>(r, invr, c, Sj, nullptr);
+        if (st_ji) hji -= hct_slow32<false>(r, invr, c, Si, nullptr);
     }
     hij = out_ij ? 0.0f : hij;
     hji = out_ji ? 0.0f : hji;
@@ -391,17 +392,15 @@ __device__ __forceinline__ void radii_pair_cut(double xi, double yi, double zi, 
     hji = xji * yji * invr * hct_poly64(yji);
     const bool out_ij = (r - Sj >= c) | (c <= rti), out_ji = (r - Si >= c) | (c <= rtj);
     const bool st_ij = !out_ij & (r + Sj > c), st_ji = !out_ji & (r + Si > c);
-    const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX64) & !st_ij;
-    const bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX64) & !st_ji;
+    const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX64);
+    const bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX64);
     if (!(f_ij & f_ji)) {
-        if (!f_ij) {
-            hij = hct_general(r, invr, rti, Sj);
-            if (st_ij) hij -= hct_general(r, invr, c, Sj);
-        }
-        if (!f_ji) {
-            hji = hct_general(r, invr, rtj, Si);
-            if (st_ji) hji -= hct_general(r, invr, c, Si);
-        }
+        if (!f_ij) hij = hct_general(r, invr, rti, Sj);
+        if (!f_ji) hji = hct_general(r, invr, rtj, Si);
+    }
+    if (st_ij | st_ji) {
+        if (st_ij) hij -= hct_general(r, invr, c, Sj);
+        if (st_ji) hji -= hct_general(r, invr, c, Si);
     }
     hij = out_ij ? 0.0 : hij;
     hji = out_ji ? 0.0 : hji;
@@ -426,31 +425,36 @@ __device__ __forceinline__ void chain_pair_cut(float r, float r2, float invr, fl
     gji2 = yji * wji * u;
     const bool out_ij = (r - Sj >= c) | (c <= rti), out_ji = (r - Si >= c) | (c <= rtj);
     const bool st_ij = !out_ij & (r + Sj > c), st_ji = !out_ji & (r + Si > c);
-    const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX) & !st_ij;
-    const bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX) & !st_ji;
+    const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX);
+    const bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX);
     if (!(f_ij & f_ji)) {
-        float g[3], gc[3];
+        float g[3];
         if (!f_ij) {
             hct_slow32<true>(r, invr, rti, Sj, g);
-            if (st_ij) {
-                hct_slow32<true>(r, invr, c, Sj, gc);
-                g[0] -= gc[0];
-                g[2] -= gc[2];
-            }
             aij = -g[0] * r2;
             gij2 = g[2];
             dri = out_ij ? dri : fmaf(bi, g[1], dri);
         }
         if (!f_ji) {
             hct_slow32<true>(r, invr, rtj, Si, g);
-            if (st_ji) {
-                hct_slow32<true>(r, invr, c, Si, gc);
-                g[0] -= gc[0];
-                g[2] -= gc[2];
-            }
             aji = -g[0] * r2;
             gji2 = g[2];
             drj = out_ji ? drj : fmaf(bj, g[1], drj);
+        }
+    }
+    // the part of a straddling ball beyond c: its r and S partials (its rt
+    // partial is zero)
+    if (st_ij | st_ji) {
+        float gc[3];
+        if (st_ij) {
+            hct_slow32<true>(r, invr, c, Sj, gc);
+            aij += gc[0] * r2;
+            gij2 -= gc[2];
+        }
+        if (st_ji) {
+            hct_slow32<true>(r, invr, c, Si, gc);
+            aji += gc[0] * r2;
+            gji2 -= gc[2];
         }
     }
     aij = out_ij ? 0.0f : aij;
@@ -477,31 +481,34 @@ __device__ __forceinline__ void chain_pair_cut(double r, double r2, double invr,
     gji2 = yji * wji * u;
     const bool out_ij = (r - Sj >= c) | (c <= rti), out_ji = (r - Si >= c) | (c <= rtj);
     const bool st_ij = !out_ij & (r + Sj > c), st_ji = !out_ji & (r + Si > c);
-    const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX64) & !st_ij;
-    const bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX64) & !st_ji;
+    const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX64);
+    const bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX64);
     if (!(f_ij & f_ji)) {
-        double g0, g1, g2, c0, c1, c2;
+        double g0, g1, g2;
         if (!f_ij) {
             hct_general_grad(r, invr, rti, Sj, g0, g1, g2);
-            if (st_ij) {
-                hct_general_grad(r, invr, c, Sj, c0, c1, c2);
-                g0 -= c0;
-                g2 -= c2;
-            }
             aij = -g0 * r2;
             gij2 = g2;
             dri = out_ij ? dri : fma(bi, g1, dri);
         }
         if (!f_ji) {
             hct_general_grad(r, invr, rtj, Si, g0, g1, g2);
-            if (st_ji) {
-                hct_general_grad(r, invr, c, Si, c0, c1, c2);
-                g0 -= c0;
-                g2 -= c2;
-            }
             aji = -g0 * r2;
             gji2 = g2;
             drj = out_ji ? drj : fma(bj, g1, drj);
+        }
+    }
+    if (st_ij | st_ji) {
+        double c0, c1, c2;
+        if (st_ij) {
+            hct_general_grad(r, invr, c, Sj, c0, c1, c2);
+            aij += c0 * r2;
+            gij2 -= c2;
+        }
+        if (st_ji) {
+            hct_general_grad(r, invr, c, Si, c0, c1, c2);
+            aji += c0 * r2;
+            gji2 -= c2;
         }
     }
     aij = out_ij ? 0.0 : aij;
@@ -519,28 +526,15 @@ __device__ __forceinline__ float block_gap(const Q4<float>& a, const Q4<float>& 
     return sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))) - a.w - b.w;
 }
 
-// The j blocks of an item that a cutoff may leave non-empty, found 64 at a
-// time: lane k evaluates near(chunk + k) and the ballot marks the tiles to
-// visit.  next(J) is the first such block at or after J (J1 if none); every
-// value is wave-uniform.
-struct TileCursor {
-    int chunk, J1;
-    unsigned long long mask;
-    template <class Near>
-    __device__ __forceinline__ int next(int J, int lane, Near&& near)
-    {
-        while (J < J1) {
-            if (J >= chunk + kTile) {
-                chunk = J;
-                mask = __ballot(J + lane < J1 && near(J + lane));
-            }
-            const unsigned long long rest = mask >> (J - chunk);
-            if (rest) return J + __builtin_ctzll(rest);
-            J = chunk + kTile;
-        }
-        return J1;
-    }
-};
+// Cutoff work items carry a tile mask: bit k set if j block J0 + k may hold a
+// pair within the cutoff (J1 <= J0 + 64).  The first such block at or after
+// J, or J1 if none.
+__device__ __forceinline__ int next_tile(unsigned long long mask, int J0, int J1, int J)
+{
+    const int k = J - J0;
+    const unsigned long long rest = k < 64 ? mask >> k : 0ull;
+    return rest ? J + __builtin_ctzll(rest) : J1;
+}
 
 // ---------------------------------------------------------------- helpers
 
@@ -669,9 +663,12 @@ __global__ __launch_bounds__(256) void k_block_bounds(const BlockSpan* __restric
                                                       int n_blocks, const Q4<T>* __restrict__ P,
                                                       const Q4<T>* __restrict__ Gx,
                                                       Q4<float>* __restrict__ bnd,
-                                                      float* __restrict__ smax)
+                                                      float* __restrict__ smax,
+                                                      int* __restrict__ ccount)
 {
     const int blk = blockIdx.x * 4 + threadIdx.x / kTile, lane = threadIdx.x % kTile;
+    // the compaction that follows starts its two lists empty
+    if (blockIdx.x == 0 && threadIdx.x < 2) ccount[threadIdx.x] = 0;
     if (blk >= n_blocks) return;
     const BlockSpan b = blocks[blk];
     const int k = b.start + (lane < b.count ? lane : b.count - 1);
@@ -701,6 +698,66 @@ __global__ __launch_bounds__(256) void k_block_bounds(const BlockSpan* __restric
     }
 }
 
+// Compaction of the cutoff passes' work: one wave per chunk (an i block
+// against up to 64 j blocks).  Lane k tests j block J0 + k against the
+// block bounds; the ballot of the tests is split into items of at most
+// kCutTiles tiles, appended to the list with one atomic per chunk.  List 0
+// (descreening and chain passes): some ball of one block may reach into the
+// rgbmax sphere of an atom of the other; list 1 (energy pass): some pair may
+// lie closer than the pair cutoff.  The order of the items varies with the
+// atomics, the results do not (integer sums, one rounding unit per tile and
+// per item's i sums, whatever the order).
+__device__ __forceinline__ void emit_cut_items(unsigned long long mask, const WorkItem& w, int lane,
+                                               CutItem* __restrict__ out, int* __restrict__ count,
+                                               int cap)
+{
+    const int p = __popcll(mask);
+    if (p == 0) return;
+    const int n_sub = (p + kCutTiles - 1) / kCutTiles;
+    int base = 0;
+    if (lane == 0) base = atomicAdd(count, n_sub);
+    base = __shfl(base, 0);
+    if (lane < n_sub && base + lane < cap) {
+        // the set bits of ranks [lane kCutTiles, (lane + 1) kCutTiles)
+        unsigned long long m = mask, sub = 0ull;
+        for (int rank = 0; m; ++rank) {
+            const unsigned long long low = m & (~m + 1ull);
+            m ^= low;
+            if (rank / kCutTiles == lane) sub |= low;
+        }
+        CutItem c;
+        c.base = w.base; c.n = w.n; c.I = w.I; c.J0 = w.J0; c.J1 = w.J1; c.blk0 = w.blk0;
+        c.mask_lo = (uint32_t)sub;
+        c.mask_hi = (uint32_t)(sub >> 32);
+        out[base + lane] = c;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cut_items(const WorkItem* __restrict__ chunks, int n_chunks,
+                                                   const Q4<float>* __restrict__ bnd,
+                                                   const float* __restrict__ smax, float cR,
+                                                   float cE, CutItem* __restrict__ out0,
+                                                   CutItem* __restrict__ out1,
+                                                   int* __restrict__ ccount, int cap)
+{
+    const int ci = blockIdx.x * 4 + threadIdx.x / kTile, lane = threadIdx.x % kTile;
+    if (ci >= n_chunks) return;
+    const WorkItem w = chunks[ci];
+    const Q4<float> bI = bnd[w.blk0 + w.I];
+    const float sI = smax[w.blk0 + w.I];
+    const int J = w.J0 + lane;
+    bool n0 = false, n1 = false;
+    if (J < w.J1) {
+        const Q4<float> bJ = bnd[w.blk0 + J];
+        const float gap = block_gap(bI, bJ);
+        n0 = cR > 0.0f && gap - fmaxf(sI, smax[w.blk0 + J]) < cR;
+        n1 = cE > 0.0f && gap < cE;
+    }
+    const unsigned long long m0 = __ballot(n0), m1 = __ballot(n1);
+    emit_cut_items(m0, w, lane, out0, &ccount[0], cap);
+    emit_cut_items(m1, w, lane, out1, &ccount[1], cap);
+}
+
 // ================================================================ pass 1
 // I_i = sum_{j != i} H(r_ij; rt_i, S_j) over every unordered pair once.
 
@@ -715,8 +772,7 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
                                            const Q4<T>* __restrict__ P,
                                            const Q4<T>* __restrict__ Gx,
                                            unsigned long long* __restrict__ I_fx,
-                                           int* __restrict__ ovf, const Q4<float>* __restrict__ bnd,
-                                           const float* __restrict__ smax, T cR)
+                                           int* __restrict__ ovf, unsigned long long tmask, T cR)
 {
     T xi[R], yi[R], zi[R], rti[R], Si[R];
     bool vi[R];
@@ -759,25 +815,14 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
     bool bad = false;
     Q4<T> pj, gj;
     if constexpr (!CUT) fetch(w.J0, pj, gj);
-    // With a cutoff, tiles whose balls all lie beyond the cutoff spheres of
-    // the other block's atoms (both ways) add nothing and are not visited.
-    Q4<float> bI{};
-    float sI = 0.0f;
-    if constexpr (CUT) {
-        bI = bnd[w.blk0 + w.I];
-        sI = smax[w.blk0 + w.I];
-    }
-    auto near = [&](int J) {
-        return block_gap(bI, bnd[w.blk0 + J]) - fmaxf(sI, smax[w.blk0 + J]) < (float)cR;
-    };
-    TileCursor tc{w.J0 - kTile, w.J1, 0ull};
+    // With a cutoff only the tiles of the item's mask are visited.
     int Jnext = w.J1;
     // one tile, then the loads of the next tile; the first tile is peeled so
     // that the loop is entered, as on every later trip, with the previous
     // tile's sums still in flight
     auto tile = [&](int J) {
         int Jn = J + 1;
-        if constexpr (CUT) Jnext = Jn = tc.next(J + 1, lane, near);
+        if constexpr (CUT) Jnext = Jn = next_tile(tmask, w.J0, w.J1, J + 1);
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
         T Sj;
@@ -816,7 +861,7 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
         for (int r = 0; r < R; ++r) ifix[r] += to_fixed((double)ai[r], kScaleI, bad);
     };
     if constexpr (CUT) {
-        int J = tc.next(w.J0, lane, near);
+        int J = next_tile(tmask, w.J0, w.J1, w.J0);
         if (J >= w.J1) return;                  // nothing within the cutoff: no sums to add
         fetch(J, pj, gj);
         for (; J < w.J1; J = Jnext) tile(J);
@@ -830,21 +875,41 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
     if (bad) *ovf = 1;
 }
 
+// The compacted items of a cutoff pass, taken in a grid-stride loop (the
+// count is known on the device only).
+__device__ __forceinline__ WorkItem cut_work_item(const CutItem& c, unsigned long long& mask)
+{
+    mask = ((unsigned long long)c.mask_hi << 32) | c.mask_lo;
+    WorkItem w;
+    w.base = c.base; w.n = c.n; w.sys = 0; w.I = c.I; w.J0 = c.J0; w.J1 = c.J1; w.rows = 1;
+    w.blk0 = c.blk0;
+    return w;
+}
+
 template <typename T, int W, bool CUT>
 __global__ __launch_bounds__(kTile * W) void k_radii_pairs(
-    const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
-    const Q4<T>* __restrict__ Gx, unsigned long long* __restrict__ I_fx, int* __restrict__ ovf,
-    const Q4<float>* __restrict__ bnd, const float* __restrict__ smax, T cR)
+    const WorkItem* __restrict__ items, int n_items, const CutItem* __restrict__ citems,
+    const int* __restrict__ n_citems, const Q4<T>* __restrict__ P, const Q4<T>* __restrict__ Gx,
+    unsigned long long* __restrict__ I_fx, int* __restrict__ ovf, T cR)
 {
     __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, rt
     __shared__ T sS_w[W][2 * kTile];
     const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
-    const int item = blockIdx.x * W + wave;
-    if (item >= n_items) return;
-    const WorkItem w = items[item];
     // the descreening pass runs one-row items only (its two-row form was
     // slower: fewer waves in flight for less saved work)
-    radii_item<T, 1, CUT>(w, lane, sj_w[wave], sS_w[wave], P, Gx, I_fx, ovf, bnd, smax, cR);
+    if constexpr (CUT) {
+        const int n = *n_citems;
+        for (int it = blockIdx.x * W + wave; it < n; it += gridDim.x * W) {
+            unsigned long long m;
+            const WorkItem w = cut_work_item(citems[it], m);
+            radii_item<T, 1, true>(w, lane, sj_w[wave], sS_w[wave], P, Gx, I_fx, ovf, m, cR);
+        }
+    } else {
+        const int item = blockIdx.x * W + wave;
+        if (item >= n_items) return;
+        const WorkItem w = items[item];
+        radii_item<T, 1, false>(w, lane, sj_w[wave], sS_w[wave], P, Gx, I_fx, ovf, 0ull, cR);
+    }
 }
 
 // Per atom: OBC radius from the descreening sum (FP64), and the per-atom state
@@ -890,7 +955,7 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
                                             const Q4<T>* __restrict__ P, const T* __restrict__ Rt,
                                             const T* __restrict__ At, T kC, T kT,
                                             const SaltK<T>& sk, const CutK<T>& ck,
-                                            const Work<T>& wk)
+                                            const Work<T>& wk, unsigned long long tmask)
 {
     constexpr int NJ = GRAD ? 5 : 1;
     T xi[R], yi[R], zi[R], qi[R], Ri[R], ai[R];
@@ -935,28 +1000,14 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
     Q4<T> pj;
     T Rj, Aj;
     if constexpr (!CUT) fetch(w.J0, pj, Rj, Aj);
-    // With a cutoff, tiles whose pairs (of every row) all lie beyond it are
-    // not visited.
-    Q4<float> bI[R];
-    if constexpr (CUT) {
-#pragma unroll
-        for (int r = 0; r < R; ++r) bI[r] = wk.bnd[w.blk0 + w.I + r];
-    }
-    auto near = [&](int J) {
-        const Q4<float> bJ = wk.bnd[w.blk0 + J];
-        bool nr = false;
-#pragma unroll
-        for (int r = 0; r < R; ++r) nr = nr || block_gap(bI[r], bJ) < (float)ck.cE;
-        return nr;
-    };
-    TileCursor tc{w.J0 - kTile, w.J1, 0ull};
+    // With a cutoff only the tiles of the item's mask are visited.
     int Jnext = w.J1;
     // one tile, then the loads of the next tile; the first tile is peeled so
     // that the loop is entered, as on every later trip, with the previous
     // tile's sums still in flight
     auto tile = [&](int J) {
         int Jn = J + 1;
-        if constexpr (CUT) Jnext = Jn = tc.next(J + 1, lane, near);
+        if constexpr (CUT) Jnext = Jn = next_tile(tmask, w.J0, w.J1, J + 1);
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
         tail(J, pj, Rj, Aj);
@@ -1069,7 +1120,7 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
         }
     };
     if constexpr (CUT) {
-        int J = tc.next(w.J0, lane, near);
+        int J = next_tile(tmask, w.J0, w.J1, w.J0);
         if (J >= w.J1) return;                  // nothing within the cutoff: no sums to add
         fetch(J, pj, Rj, Aj);
         for (; J < w.J1; J = Jnext) tile(J);
@@ -1105,17 +1156,29 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
     __shared__ T sR_w[W][2 * kTile];
     __shared__ T sA_w[W][2 * kTile];
     const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
-    const int item = blockIdx.x * W + wave;
-    if (item >= n_items) return;
-    const WorkItem w = items[item];
-    // two-row items exist in the energy pass of FP32 plans only
-    if (sizeof(T) == 4 && w.rows == 2)
-        energy_item<T, GRAD, sizeof(T) == 4 ? 2 : 1, SALT, CUT>(w, lane, sj_w[wave], sR_w[wave],
-                                                                sA_w[wave], P, Rt, At, kC, kT, sk,
-                                                                ck, wk);
-    else
-        energy_item<T, GRAD, 1, SALT, CUT>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P, Rt, At,
-                                           kC, kT, sk, ck, wk);
+    if constexpr (CUT) {
+        // compacted one-row items of the pair cutoff
+        const int n = wk.ccount[1];
+        for (int it = blockIdx.x * W + wave; it < n; it += gridDim.x * W) {
+            unsigned long long m;
+            const WorkItem w = cut_work_item(wk.citems[1][it], m);
+            energy_item<T, GRAD, 1, SALT, true>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P, Rt,
+                                                At, kC, kT, sk, ck, wk, m);
+        }
+    } else {
+        const int item = blockIdx.x * W + wave;
+        if (item >= n_items) return;
+        const WorkItem w = items[item];
+        // two-row items exist in the energy pass of FP32 plans only
+        if (sizeof(T) == 4 && w.rows == 2)
+            energy_item<T, GRAD, sizeof(T) == 4 ? 2 : 1, SALT, false>(w, lane, sj_w[wave],
+                                                                      sR_w[wave], sA_w[wave], P,
+                                                                      Rt, At, kC, kT, sk, ck, wk,
+                                                                      0ull);
+        else
+            energy_item<T, GRAD, 1, SALT, false>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P, Rt,
+                                                 At, kC, kT, sk, ck, wk, 0ull);
+    }
 }
 
 // After pass 2, one launch: blocks [0, n_sum) sum the atoms' fixed-point
@@ -1172,7 +1235,8 @@ template <typename T, int R, bool CUT>
 __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* sj, Q4<T>* sb,
                                            const Q4<T>* __restrict__ P,
                                            const Q4<T>* __restrict__ Gx,
-                                           const T* __restrict__ Brt, const Work<T>& wk, T cR)
+                                           const T* __restrict__ Brt, const Work<T>& wk, T cR,
+                                           unsigned long long tmask)
 {
     T xi[R], yi[R], zi[R], rti[R], Si[R], Bi[R], si[R];
     bool vi[R];
@@ -1222,25 +1286,14 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
     Q4<T> pj, gj, bj;
     T brj;
     if constexpr (!CUT) fetch(w.J0, pj, gj, brj);
-    // With a cutoff, tiles where no ball of either block reaches into the
-    // other's cutoff spheres are not visited.
-    Q4<float> bI{};
-    float sI = 0.0f;
-    if constexpr (CUT) {
-        bI = wk.bnd[w.blk0 + w.I];
-        sI = wk.smax[w.blk0 + w.I];
-    }
-    auto near = [&](int J) {
-        return block_gap(bI, wk.bnd[w.blk0 + J]) - fmaxf(sI, wk.smax[w.blk0 + J]) < (float)cR;
-    };
-    TileCursor tc{w.J0 - kTile, w.J1, 0ull};
+    // With a cutoff only the tiles of the item's mask are visited.
     int Jnext = w.J1;
     // one tile, then the loads of the next tile; the first tile is peeled so
     // that the loop is entered, as on every later trip, with the previous
     // tile's sums still in flight
     auto tile = [&](int J) {
         int Jn = J + 1;
-        if constexpr (CUT) Jnext = Jn = tc.next(J + 1, lane, near);
+        if constexpr (CUT) Jnext = Jn = next_tile(tmask, w.J0, w.J1, J + 1);
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
         tail(J, pj, bj, gj, brj);
@@ -1305,7 +1358,7 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
         }
     };
     if constexpr (CUT) {
-        int J = tc.next(w.J0, lane, near);
+        int J = next_tile(tmask, w.J0, w.J1, w.J0);
         if (J >= w.J1) return;                  // nothing within the cutoff: no sums to add
         fetch(J, pj, gj, brj);
         for (; J < w.J1; J = Jnext) tile(J);
@@ -1332,12 +1385,21 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
     __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, rt
     __shared__ Q4<T> sb_w[W][2 * kTile];     // S, B rt, screen, -
     const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
-    const int item = blockIdx.x * W + wave;
-    if (item >= n_items) return;
-    const WorkItem w = items[item];
     // the chain pass runs one-row items only (its two-row form was slower:
     // fewer waves in flight for less saved work)
-    chain_item<T, 1, CUT>(w, lane, sj_w[wave], sb_w[wave], P, Gx, Brt, wk, cR);
+    if constexpr (CUT) {
+        const int n = wk.ccount[0];
+        for (int it = blockIdx.x * W + wave; it < n; it += gridDim.x * W) {
+            unsigned long long m;
+            const WorkItem w = cut_work_item(wk.citems[0][it], m);
+            chain_item<T, 1, true>(w, lane, sj_w[wave], sb_w[wave], P, Gx, Brt, wk, cR, m);
+        }
+    } else {
+        const int item = blockIdx.x * W + wave;
+        if (item >= n_items) return;
+        const WorkItem w = items[item];
+        chain_item<T, 1, false>(w, lane, sj_w[wave], sb_w[wave], P, Gx, Brt, wk, cR, 0ull);
+    }
 }
 
 // Per atom after pass 3: forces and dE/drho.
@@ -1861,9 +1923,29 @@ static inline int blocks_for(size_t n, int bs) { return (int)((n + bs - 1) / bs)
     default: { constexpr int W = 8; CALL; } break; \
     }
 
+// Block bounds and the compacted work of the cutoff passes (positions as
+// staged by the caller of this function).
+template <typename T>
+static void launch_cut_lists(const CutPlan& cp, const GBConst& c, const Work<T>& w, hipStream_t s)
+{
+    if (cp.n_blocks == 0) return;
+    hipLaunchKernelGGL(k_block_bounds<T>, dim3(blocks_for(cp.n_blocks, 4)), dim3(256), 0, s,
+                       cp.blocks, cp.n_blocks, w.P, w.Gx, w.bnd, w.smax, w.ccount);
+    if (cp.n_chunks > 0)
+        hipLaunchKernelGGL(k_cut_items, dim3(blocks_for(cp.n_chunks, 4)), dim3(256), 0, s, cp.chunks,
+                           cp.n_chunks, w.bnd, w.smax, (float)c.rgbmax, (float)c.cutoff,
+                           w.citems[0], w.citems[1], w.ccount, w.cut_cap);
+}
+
+// Workgroups of a grid-stride cutoff pass: enough waves to fill the chip.
+static inline int cut_groups(int cap, int W)
+{
+    return std::max(1, std::min(blocks_for(cap, W), 16384 / W));
+}
+
 template <typename T>
 hipError_t launch_radii(const WorkItem* items, int n_items, int wpg, int n_atoms,
-                        const BlockSpan* blocks, int n_blocks,
+                        const CutPlan& cp,
                         const T* x, const T* y, const T* z, const T* rho, const T* screen,
                         const GBConst& c, const Work<T>& w, T* born_R, hipStream_t s,
                         hipEvent_t* ev)
@@ -1873,21 +1955,18 @@ hipError_t launch_radii(const WorkItem* items, int n_items, int wpg, int n_atoms
     hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms, w.perm,
                        x, y, z, (const T*)nullptr, rho, screen, (T)c.offset, w.P, w.Gx, w.I_fx, 1,
                        w.ovf);
-    // block bounds for the cutoff passes (this call's and gb_energy_forces')
-    if ((c.rgbmax > 0.0 || c.cutoff > 0.0) && n_blocks > 0)
-        hipLaunchKernelGGL(k_block_bounds<T>, dim3(blocks_for(n_blocks, 4)), dim3(256), 0, s, blocks,
-                           n_blocks, w.P, w.Gx, w.bnd, w.smax);
+    if (c.rgbmax > 0.0 || c.cutoff > 0.0) launch_cut_lists<T>(cp, c, w, s);
     if (n_items > 0) {
         if (c.rgbmax > 0.0)
             GBMC_DISPATCH_W(wpg, GBMC_LAUNCH_TIMED(ev, kKRadii, (k_radii_pairs<T, W, true>),
-                                                   dim3(blocks_for(n_items, W)), dim3(kTile * W), s,
-                                                   items, n_items, w.P, w.Gx, w.I_fx, w.ovf, w.bnd,
-                                                   w.smax, (T)c.rgbmax))
+                                                   dim3(cut_groups(w.cut_cap, W)), dim3(kTile * W),
+                                                   s, items, n_items, w.citems[0], w.ccount, w.P,
+                                                   w.Gx, w.I_fx, w.ovf, (T)c.rgbmax))
         else
             GBMC_DISPATCH_W(wpg, GBMC_LAUNCH_TIMED(ev, kKRadii, (k_radii_pairs<T, W, false>),
                                                    dim3(blocks_for(n_items, W)), dim3(kTile * W), s,
-                                                   items, n_items, w.P, w.Gx, w.I_fx, w.ovf, w.bnd,
-                                                   w.smax, (T)0))
+                                                   items, n_items, w.citems[0], w.ccount, w.P,
+                                                   w.Gx, w.I_fx, w.ovf, (T)0))
     }
     hipLaunchKernelGGL(k_radii_finalize<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
                        rho, c, w, born_R);
@@ -1896,7 +1975,7 @@ hipError_t launch_radii(const WorkItem* items, int n_items, int wpg, int n_atoms
 
 template <typename T>
 hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_atoms, int n_sys,
-                                const BlockSpan* blocks, int n_blocks,
+                                const CutPlan& cp,
                                 const T* x, const T* y, const T* z, const T* q, const T* rho,
                                 const T* screen, const GBConst& c, const Work<T>& w,
                                 double* e_coul, double* e_gb, T* force, T* dEdq, T* dEdrho,
@@ -1910,18 +1989,18 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
         hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
                            w.perm, x, y, z, q, rho, screen, (T)c.offset, w.P, w.Gx, w.F_fx, 8,
                            (int*)nullptr);
-    // block bounds (positions as staged here, the same as the preceding
-    // gb_radii call's)
-    if ((c.rgbmax > 0.0 || c.cutoff > 0.0) && n_blocks > 0)
-        hipLaunchKernelGGL(k_block_bounds<T>, dim3(blocks_for(n_blocks, 4)), dim3(256), 0, s, blocks,
-                           n_blocks, w.P, w.Gx, w.bnd, w.smax);
+    // block bounds and compacted work (positions as staged here, the same as
+    // the preceding gb_radii call's)
+    if (c.rgbmax > 0.0 || c.cutoff > 0.0) launch_cut_lists<T>(cp, c, w, s);
     if (pe.n_items > 0) {
         const SaltK<T> sk{(T)c.kO, (T)c.kappa, (T)(c.kappa * kLog2e)};
         const CutK<T> ck{(T)c.cutoff, (T)(c.cutoff * c.cutoff)};
 #define GBMC_ENERGY_LAUNCH(G_, S_, C_)                                                            \
     GBMC_DISPATCH_W(pe.waves_per_group,                                                          \
                     GBMC_LAUNCH_TIMED(ev, kKEnergy, (k_energy_pairs<T, G_, W, S_, C_>),          \
-                                      dim3(blocks_for(pe.n_items, W)), dim3(kTile * W), s,       \
+                                      dim3(C_ ? cut_groups(w.cut_cap, W)                         \
+                                              : blocks_for(pe.n_items, W)),                      \
+                                      dim3(kTile * W), s,                                        \
                                       pe.items, pe.n_items, w.P, w.R_t, w.a_t, (T)c.kC, (T)c.kT, \
                                       sk, ck, w))
         const bool salt = c.kappa != 0.0, cut = c.cutoff > 0.0;
@@ -1949,7 +2028,7 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
         if (c.rgbmax > 0.0)
             GBMC_DISPATCH_W(pc.waves_per_group,
                             GBMC_LAUNCH_TIMED(ev, kKChain, (k_chain_pairs<T, W, true>),
-                                              dim3(blocks_for(pc.n_items, W)), dim3(kTile * W), s,
+                                              dim3(cut_groups(w.cut_cap, W)), dim3(kTile * W), s,
                                               pc.items, pc.n_items, w.P, w.Gx, w.Brt_t, w,
                                               (T)c.rgbmax))
         else
@@ -2031,12 +2110,12 @@ hipError_t launch_remd_exchange(int M, const double* E_rung, const int32_t* Ne, 
 }
 
 #define GBMC_INSTANTIATE(T)                                                                      \
-    template hipError_t launch_radii<T>(const WorkItem*, int, int, int, const BlockSpan*, int,  \
+    template hipError_t launch_radii<T>(const WorkItem*, int, int, int, const CutPlan&,         \
                                         const T*,                                                \
                                         const T*, const T*, const T*, const T*, const GBConst&,  \
                                         const Work<T>&, T*, hipStream_t, hipEvent_t*);           \
     template hipError_t launch_energy_forces<T>(const PassShape&, const PassShape&, int, int,      \
-                                                const BlockSpan*, int, const T*,                   \
+                                                const CutPlan&, const T*,                          \
                                                 const T*, const T*, const T*, const T*,          \
                                                 const T*, const GBConst&, const Work<T>&,        \
                                                 double*, double*, T*, T*, T*, hipStream_t,       \

@@ -208,3 +208,42 @@ def test_spatial_order_is_a_local_permutation(L):
         step = np.linalg.norm(np.diff(xyz[seg], axis=0), axis=1).mean()
         step0 = np.linalg.norm(np.diff(xyz[off[b]:off[b + 1]], axis=0), axis=1).mean()
         assert step < 0.4 * step0
+
+
+def test_block_order_gives_compact_blocks(L):
+    lib = L.load()
+    systems = [synth.make_system(150, 3000, 20.0), synth.make_system(151, 130, 6.0),
+               synth.make_system(152, 1, 2.0), synth.make_system(153, 64, 5.0)]
+    batch = synth.make_batch(systems)
+    off = batch.atom_offset
+    out = np.zeros(batch.n_atoms, dtype=np.int32)
+    d = lambda a: np.ascontiguousarray(a, dtype=np.float64).ctypes.data_as(C.POINTER(C.c_double))
+    assert lib.gbmc_block_order(batch.n_systems, _i32p(off), d(batch.x), d(batch.y), d(batch.z),
+                                _i32p(out)) == 0
+    xyz = np.stack([batch.x, batch.y, batch.z], 1)
+
+    def radii_of(seg):
+        r = []
+        for k in range(0, seg.size, 64):
+            blk = xyz[seg[k:k + 64]]
+            c = 0.5 * (blk.min(0) + blk.max(0))
+            r.append(np.sqrt(((blk - c) ** 2).sum(1)).max())
+        return np.array(r)
+
+    for b in range(batch.n_systems):
+        seg = out[off[b]:off[b + 1]]
+        assert sorted(seg.tolist()) == list(range(off[b], off[b + 1]))
+    seg = out[off[0]:off[1]]
+    morton = np.zeros(batch.n_atoms, dtype=np.int32)
+    assert lib.gbmc_spatial_order(batch.n_systems, _i32p(off), d(batch.x), d(batch.y), d(batch.z),
+                                  _i32p(morton)) == 0
+    # every block is a compact cluster: at 0.09 atoms per A^3 a ball of 64
+    # atoms has radius ~5.5 A; the bisection keeps every block within ~2x that,
+    # and its largest block is smaller than the Morton order's
+    r = radii_of(seg)
+    assert r.max() < 12.0, r.max()
+    assert r.max() < radii_of(morton[off[0]:off[1]]).max()
+    # deterministic (ties by index)
+    out2 = np.zeros_like(out)
+    lib.gbmc_block_order(batch.n_systems, _i32p(off), d(batch.x), d(batch.y), d(batch.z), _i32p(out2))
+    assert np.array_equal(out, out2)

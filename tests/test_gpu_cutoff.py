@@ -2,7 +2,8 @@
 restricted to the sphere of that radius around each atom; energy cutoff: pair
 terms at or beyond it dropped), against the oracle's cutoff forms:
 
-* a ragged batch (1, 65, 300 and 2,500 atoms), both plans: radii, energies,
+* a ragged batch (1, 65, 300 and 2,500 atoms), both plans and the
+  compact-block order: radii, energies,
   forces, dE/dq, dE/drho (tiles skipped by their bounding spheres, balls
   straddling the descreening sphere, pairs beyond the energy cutoff);
 * Delta E / Delta G of every candidate with the pair cutoff (FP64 rows, K_SS);
@@ -50,13 +51,16 @@ def _pair(rgbmax, cutoff):
             dataclasses.replace(p_or, rgbmax=rgbmax, cutoff=cutoff))
 
 
-@pytest.mark.parametrize("prec", ["fp32", "fp64"])
-def test_cutoff_batch_parity(prec):
+@pytest.mark.parametrize("prec,order", [("fp32", "identity"), ("fp64", "identity"),
+                                        ("fp32", "blocks")])
+def test_cutoff_batch_parity(prec, order):
     systems = [synth.make_system(120, 1, 2.0), synth.make_system(121, 65, 5.0),
                synth.make_system(122, 300, 8.5)] + synth.config1()
     cut = _cutoff_in_gap(systems, 10.0, 10.5)
     p_gpu, p_or = _pair(12.0, cut)
     g, batch, plan, atoms = build(systems, prec)
+    if order == "blocks":
+        plan.set_order(g.block_order(batch.atom_offset, batch.x, batch.y, batch.z))
     res = gpu_eval(plan, atoms, p_gpu)
     off = batch.atom_offset
     for b, s in enumerate(systems):
