@@ -701,22 +701,20 @@ __global__ __launch_bounds__(256) void k_block_bounds(const BlockSpan* __restric
 // Compaction of the cutoff passes' work: one wave per chunk (an i block
 // against up to 64 j blocks).  Lane k tests j block J0 + k against the
 // block bounds; the ballot of the tests is split into items of at most
-// kCutTiles tiles, appended to the list with one atomic per chunk.  List 0
-// (descreening and chain passes): some ball of one block may reach into the
-// rgbmax sphere of an atom of the other; list 1 (energy pass): some pair may
-// lie closer than the pair cutoff.  The order of the items varies with the
-// atomics, the results do not (integer sums, one rounding unit per tile and
-// per item's i sums, whatever the order).
-__device__ __forceinline__ void emit_cut_items(unsigned long long mask, const WorkItem& w, int lane,
-                                               CutItem* __restrict__ out, int* __restrict__ count,
-                                               int cap)
+// kCutTiles tiles.  The 16 waves of a workgroup add their item counts in LDS
+// and reserve room in each list with one atomic per workgroup (same-address
+// device atomics are the expensive part).  List 0 (descreening and chain
+// passes): some ball of one block may reach into the rgbmax sphere of an atom
+// of the other; list 1 (energy pass): some pair may lie closer than the pair
+// cutoff.  The order of the items varies with the atomics, the results do
+// not (integer sums, one rounding unit per tile and per item's i sums).
+constexpr int kCutWaves = 16;
+
+__device__ __forceinline__ void write_cut_items(unsigned long long mask, const WorkItem& w,
+                                                int lane, int base, CutItem* __restrict__ out,
+                                                int cap)
 {
-    const int p = __popcll(mask);
-    if (p == 0) return;
-    const int n_sub = (p + kCutTiles - 1) / kCutTiles;
-    int base = 0;
-    if (lane == 0) base = atomicAdd(count, n_sub);
-    base = __shfl(base, 0);
+    const int n_sub = (__popcll(mask) + kCutTiles - 1) / kCutTiles;
     if (lane < n_sub && base + lane < cap) {
         // the set bits of ranks [lane kCutTiles, (lane + 1) kCutTiles)
         unsigned long long m = mask, sub = 0ull;
@@ -733,29 +731,50 @@ __device__ __forceinline__ void emit_cut_items(unsigned long long mask, const Wo
     }
 }
 
-__global__ __launch_bounds__(256) void k_cut_items(const WorkItem* __restrict__ chunks, int n_chunks,
-                                                   const Q4<float>* __restrict__ bnd,
-                                                   const float* __restrict__ smax, float cR,
-                                                   float cE, CutItem* __restrict__ out0,
-                                                   CutItem* __restrict__ out1,
-                                                   int* __restrict__ ccount, int cap)
+__global__ __launch_bounds__(kTile * kCutWaves) void k_cut_items(
+    const WorkItem* __restrict__ chunks, int n_chunks, const Q4<float>* __restrict__ bnd,
+    const float* __restrict__ smax, float cR, float cE, CutItem* __restrict__ out0,
+    CutItem* __restrict__ out1, int* __restrict__ ccount, int cap)
 {
-    const int ci = blockIdx.x * 4 + threadIdx.x / kTile, lane = threadIdx.x % kTile;
-    if (ci >= n_chunks) return;
-    const WorkItem w = chunks[ci];
-    const Q4<float> bI = bnd[w.blk0 + w.I];
-    const float sI = smax[w.blk0 + w.I];
-    const int J = w.J0 + lane;
-    bool n0 = false, n1 = false;
-    if (J < w.J1) {
-        const Q4<float> bJ = bnd[w.blk0 + J];
-        const float gap = block_gap(bI, bJ);
-        n0 = cR > 0.0f && gap - fmaxf(sI, smax[w.blk0 + J]) < cR;
-        n1 = cE > 0.0f && gap < cE;
+    __shared__ int cnt[2][kCutWaves];
+    __shared__ int base[2];
+    const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
+    const int ci = blockIdx.x * kCutWaves + wave;
+    unsigned long long m0 = 0ull, m1 = 0ull;
+    WorkItem w{};
+    if (ci < n_chunks) {                         // wave-uniform; every wave reaches the barriers
+        w = chunks[ci];
+        const Q4<float> bI = bnd[w.blk0 + w.I];
+        const float sI = smax[w.blk0 + w.I];
+        const int J = w.J0 + lane;
+        bool n0 = false, n1 = false;
+        if (J < w.J1) {
+            const Q4<float> bJ = bnd[w.blk0 + J];
+            const float gap = block_gap(bI, bJ);
+            n0 = cR > 0.0f && gap - fmaxf(sI, smax[w.blk0 + J]) < cR;
+            n1 = cE > 0.0f && gap < cE;
+        }
+        m0 = __ballot(n0);
+        m1 = __ballot(n1);
     }
-    const unsigned long long m0 = __ballot(n0), m1 = __ballot(n1);
-    emit_cut_items(m0, w, lane, out0, &ccount[0], cap);
-    emit_cut_items(m1, w, lane, out1, &ccount[1], cap);
+    if (lane == 0) {
+        cnt[0][wave] = (__popcll(m0) + kCutTiles - 1) / kCutTiles;
+        cnt[1][wave] = (__popcll(m1) + kCutTiles - 1) / kCutTiles;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2) {
+        int tot = 0;
+        for (int k = 0; k < kCutWaves; ++k) tot += cnt[threadIdx.x][k];
+        base[threadIdx.x] = tot > 0 ? atomicAdd(&ccount[threadIdx.x], tot) : 0;
+    }
+    __syncthreads();
+    int off0 = base[0], off1 = base[1];
+    for (int k = 0; k < wave; ++k) {
+        off0 += cnt[0][k];
+        off1 += cnt[1][k];
+    }
+    write_cut_items(m0, w, lane, off0, out0, cap);
+    write_cut_items(m1, w, lane, off1, out1, cap);
 }
 
 // ================================================================ pass 1
@@ -1932,9 +1951,10 @@ static void launch_cut_lists(const CutPlan& cp, const GBConst& c, const Work<T>&
     hipLaunchKernelGGL(k_block_bounds<T>, dim3(blocks_for(cp.n_blocks, 4)), dim3(256), 0, s,
                        cp.blocks, cp.n_blocks, w.P, w.Gx, w.bnd, w.smax, w.ccount);
     if (cp.n_chunks > 0)
-        hipLaunchKernelGGL(k_cut_items, dim3(blocks_for(cp.n_chunks, 4)), dim3(256), 0, s, cp.chunks,
-                           cp.n_chunks, w.bnd, w.smax, (float)c.rgbmax, (float)c.cutoff,
-                           w.citems[0], w.citems[1], w.ccount, w.cut_cap);
+        hipLaunchKernelGGL(k_cut_items, dim3(blocks_for(cp.n_chunks, kCutWaves)),
+                           dim3(kTile * kCutWaves), 0, s, cp.chunks, cp.n_chunks, w.bnd, w.smax,
+                           (float)c.rgbmax, (float)c.cutoff, w.citems[0], w.citems[1], w.ccount,
+                           w.cut_cap);
 }
 
 // Workgroups of a grid-stride cutoff pass: enough waves to fill the chip.
