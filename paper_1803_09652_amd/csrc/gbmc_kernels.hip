@@ -283,10 +283,12 @@ __device__ __forceinline__ void chain_pair(float r, float r2, float invr, float 
     float wij = rcp(1.0f - yij), wji = rcp(1.0f - yji);
     wij *= wij;
     wji *= wji;
-    float aij = xij * yij * (hct_poly(yij) + wij);     // -r^2 dH/dr
-    float aji = xji * yji * (hct_poly(yji) + wji);
-    gij2 = yij * wij * u;
-    gji2 = yji * wji * u;
+    // -r^2 dH/dr = x^3 (P + w) = x (y P + t), r^2 dH/dS = t = y w
+    const float tij = yij * wij, tji = yji * wji;
+    float aij = xij * fmaf(yij, hct_poly_d(yij), tij);
+    float aji = xji * fmaf(yji, hct_poly_d(yji), tji);
+    gij2 = tij * u;
+    gji2 = tji * u;
     const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX);
     const bool f_ji = (r - Si >= rtj) & (yji <= GBMC_HCT_YMAX);
     if (!(f_ij & f_ji)) {
@@ -419,10 +421,12 @@ __device__ __forceinline__ void chain_pair_cut(float r, float r2, float invr, fl
     float wij = rcp(1.0f - yij), wji = rcp(1.0f - yji);
     wij *= wij;
     wji *= wji;
-    float aij = xij * yij * (hct_poly(yij) + wij);     // -r^2 dH/dr
-    float aji = xji * yji * (hct_poly(yji) + wji);
-    gij2 = yij * wij * u;
-    gji2 = yji * wji * u;
+    // -r^2 dH/dr = x^3 (P + w) = x (y P + t), r^2 dH/dS = t = y w
+    const float tij = yij * wij, tji = yji * wji;
+    float aij = xij * fmaf(yij, hct_poly_d(yij), tij);
+    float aji = xji * fmaf(yji, hct_poly_d(yji), tji);
+    gij2 = tij * u;
+    gji2 = tji * u;
     const bool out_ij = (r - Sj >= c) | (c <= rti), out_ji = (r - Si >= c) | (c <= rtj);
     const bool st_ij = !out_ij & (r + Sj > c), st_ji = !out_ji & (r + Si > c);
     const bool f_ij = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX);

@@ -145,3 +145,28 @@ def test_fp64_gradcheck_tiny_system():
     g, batch, plan, pos, q, rho, scr = _inputs([s], "fp64")
     f = lambda p_, q_, r_: g.GBEnergy.apply(p_, q_, r_, scr, plan, p_gpu)
     assert torch.autograd.gradcheck(f, (pos, q, rho), eps=1e-3, atol=1e-3, rtol=1e-3)
+
+
+def test_fp64_gradients_with_salt_and_cutoffs():
+    # the autograd boundary with the GB variants: salt and both cutoffs, the
+    # gradients against the oracle's analytic ones (pinned on the CPU by
+    # central differences of the cut, salted energy)
+    import dataclasses
+    p_gpu, p_or = params_pair()
+    p_gpu = dataclasses.replace(p_gpu, kappa=0.12, rgbmax=9.0, cutoff=7.3)
+    p_or = dataclasses.replace(p_or, kappa=0.12, rgbmax=9.0, cutoff=7.3)
+    systems = [synth.make_system(84, 260, 9.0), synth.make_system(85, 90, 6.0)]
+    g, batch, plan, pos, q, rho, scr = _inputs(systems, "fp64")
+    E = g.GBEnergy.apply(pos, q, rho, scr, plan, p_gpu)
+    w = torch.tensor([1.25, -0.5], dtype=torch.float64, device=E.device)
+    (E * w).sum().backward()
+    off = batch.atom_offset
+    t = TOL["fp64"]
+    for b, s in enumerate(systems):
+        ref = oracle_eval(s, p_or)
+        s0, s1 = off[b], off[b + 1]
+        wb = float(w[b])
+        assert abs(float(E[b]) - ref["E"]) <= t["E"] * (abs(ref["Ec"]) + abs(ref["Egb"]))
+        assert rel_inf(pos.grad[s0:s1].cpu().numpy(), -wb * ref["F"]) <= t["grad"]
+        assert rel_inf(q.grad[s0:s1].cpu().numpy(), wb * ref["phi"]) <= t["grad"]
+        assert rel_inf(rho.grad[s0:s1].cpu().numpy(), wb * ref["dEdrho"]) <= t["grad"]

@@ -172,3 +172,35 @@ def test_fp32_eremd_batch_runs_in_range():
     rms = math.sqrt(((pos - xref.T) ** 2).sum(1).mean())
     assert rms < 0.3, rms
     assert loop.n_attempts == 8 and loop.n_exchanges == 4
+
+
+def test_pure_dynamics_loop_without_sites():
+    # CEMD's dynamics alone: no titratable sites, no attempts, no exchanges;
+    # a one-atom system beside a 30-atom one (FP64 against the oracle step)
+    from paper_1803_09652_amd.runtime import ReplicaMD
+    p_gpu, p_or = params_pair()
+    systems = [synth.make_system(701, 30, 4.5, min_dist=1.5), synth.make_system(702, 1, 2.0)]
+    g, batch, plan, atoms = build(systems, "fp64")
+    assert batch.n_sites == 0
+    sites = g.Sites.from_batch(plan, batch)
+    N = batch.x.shape[0]
+    m = synth.masses(12, N)
+    v0 = synth.thermal_velocities(13, m, T)
+    xref = np.stack([batch.x, batch.y, batch.z])
+    xi = synth.normals(14, (8, 3, N))
+    loop = ReplicaMD(plan, sites, atoms, np.zeros(0, np.int32), 1.0 / m, v0.T, PH, np.zeros(2),
+                     dt=DT, gamma=GAMMA, T=T, attempt_every=0, exchange_every=0, params=p_gpu,
+                     xref=xref, k_restr=KR)
+    rec = loop.run(8, torch.as_tensor(xi, device=plan.device))
+    torch.cuda.synchronize()
+    assert rec["state"].shape == (0, 0) and loop.n_attempts == 0 and loop.n_exchanges == 0
+    pos = torch.stack([atoms.x, atoms.y, atoms.z], 1).cpu().numpy()
+    off = batch.atom_offset
+    for b, s in enumerate(systems):
+        sl = slice(off[b], off[b + 1])
+        sys_, v = s.copy(), v0[sl].copy()
+        for k in range(8):
+            x, y, z, v = oracle.langevin_step(sys_, v, 1.0 / m[sl], xi[k][:, sl].T, DT, GAMMA, T, p_or,
+                                              xref=xref[:, sl].T, k_restr=KR)
+            sys_.x, sys_.y, sys_.z = x, y, z
+        assert np.abs(pos[sl] - sys_.coords()).max() <= 1e-9, b
