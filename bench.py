@@ -368,6 +368,29 @@ def time_cutoff(n_atoms=100000, rgbmax=15.0, cutoff=16.0, steps=10):
     return out
 
 
+def time_plain_fp64(w, reps=3):
+    """The plain FP64 GPU form (gb_plain_fp64: one thread per atom over its
+    whole row, closed forms, correctly rounded operations) of one full
+    evaluation of the E-REMD batch, timed with HIP events: the reference the
+    metric's FP32-fixed vs FP64 comparison names."""
+    import torch
+    g, b = w.g, w.batch
+    dev = w.plan.device
+    d = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev)
+    args = (b.atom_offset, d(b.x), d(b.y), d(b.z), d(b.q), d(b.rho), d(b.screen), w.params)
+    g.plain_fp64(*args)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        g.plain_fp64(*args)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"ms_per_evaluation": ms, "value": w.pairs / (ms * 1e-3), "reps": reps,
+            "form": "radii + energy + forces + dE/dq + dE/drho, every ordered pair, FP64"}
+
+
 def time_md_loop(steps, warmup, n_rep=16, attempt_every=5, exchange_every=10):
     """The simulation loop (ReplicaMD) on the E-REMD batch for dynamics: 16
     replicas x 2,500 atoms, 2 fs Langevin steps (gamma 5 / ps, every atom
@@ -559,6 +582,8 @@ def main():
                            "traffic_detail": detail,
                            "per_kernel_tflops": {n: FLOPS_PER_PAIR[n] * pairs / (v * 1e-3) / 1e12
                                                  for n, v in pair_k.items()}}
+    out["fp64_plain"] = time_plain_fp64(w)
+    out["fp32_over_fp64_plain"] = value / out["fp64_plain"]["value"]
     out["mc_sweep"] = time_sweep(w)
     out["salt"] = time_salt(w)
     if args.md_steps > 0:

@@ -198,6 +198,23 @@ gbmc_status gb_energy_forces(gbmc_plan* plan, const gbmc_atoms* atoms,
                              double* e_coul, double* e_gb, void* force, void* dEdq,
                              void* dEdrho, hipStream_t stream);
 
+/* The plain FP64 GPU form of one full evaluation: the same outputs as
+ * gb_radii + gb_energy_forces of an FP64 plan (radii born_R[N], e_coul[B],
+ * e_gb[B], force[N][3], dEdq[N], dEdrho[N]; each may be NULL) computed the
+ * direct way, one thread per atom over its whole row (every ordered pair),
+ * closed forms with correctly rounded division, square root, exp and log.  It
+ * is the reference the pair rate of the batched forms is compared with.
+ * Needs no plan: host_atom_offset (host) and atom_offset (device) [B+1]; all
+ * arrays double, caller order; workspace of gb_plain_workspace_bytes(N)
+ * bytes (caller-owned, device).  No salt and no cutoffs
+ * (GBMC_ERR_UNSUPPORTED). */
+size_t gb_plain_workspace_bytes(int32_t n_atoms);
+gbmc_status gb_plain_fp64(int32_t n_systems, const int32_t* host_atom_offset,
+                          const int32_t* atom_offset, const gbmc_atoms* atoms,
+                          const gbmc_gb_params* params, void* workspace, double* born_R,
+                          double* e_coul, double* e_gb, double* force, double* dEdq,
+                          double* dEdrho, hipStream_t stream);
+
 /* Titratable sites (host arrays, copied to the device; sites of one system
  * must be disjoint):
  *   site_system[S]          system of each site (non-decreasing)

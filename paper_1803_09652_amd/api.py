@@ -383,6 +383,38 @@ def mc_sweep(plan: Plan, sites: Sites, atoms: Atoms, current_state: torch.Tensor
     return {"n_electrons": ne, "accepted": acc[:sites.n_sites], "dG": dG[:sites.n_sites]}
 
 
+def plain_fp64(atom_offset, x, y, z, q, rho, screen, params: GBParams = IGB5,
+               device=None) -> dict:
+    """The plain FP64 GPU form of one full evaluation (one thread per atom
+    over its whole row, closed forms with correctly rounded operations): the
+    reference the batched forms' pair rate is compared with.  Inputs are 1-D
+    float64 device tensors (or arrays) in caller order; returns R, e_coul,
+    e_gb, force [N, 3], dEdq and dEdrho."""
+    off = np.ascontiguousarray(atom_offset, dtype=np.int32)
+    dev = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    d = lambda a: torch.as_tensor(a, dtype=torch.float64, device=dev).contiguous()
+    xs, ys, zs, qs, rs, ss = (d(a) for a in (x, y, z, q, rho, screen))
+    B, N = int(off.size - 1), int(off[-1])
+    lib = L.load()
+    ws = torch.empty(max(int(lib.gb_plain_workspace_bytes(N)), 256), dtype=torch.uint8, device=dev)
+    off_d = torch.as_tensor(off, device=dev)
+    out = {"R": torch.empty(N, dtype=torch.float64, device=dev),
+           "e_coul": torch.empty(B, dtype=torch.float64, device=dev),
+           "e_gb": torch.empty(B, dtype=torch.float64, device=dev),
+           "force": torch.empty((N, 3), dtype=torch.float64, device=dev),
+           "dEdq": torch.empty(N, dtype=torch.float64, device=dev),
+           "dEdrho": torch.empty(N, dtype=torch.float64, device=dev)}
+    a = L.gbmc_atoms(xs.data_ptr(), ys.data_ptr(), zs.data_ptr(), qs.data_ptr(), rs.data_ptr(),
+                     ss.data_ptr())
+    p = params.c()
+    L.check(lib.gb_plain_fp64(B, _i32p(off), _ptr(off_d), C.byref(a), C.byref(p), _ptr(ws),
+                              _ptr(out["R"]), _ptr(out["e_coul"]), _ptr(out["e_gb"]),
+                              _ptr(out["force"]), _ptr(out["dEdq"]), _ptr(out["dEdrho"]),
+                              _stream(dev)))
+    out["_keep"] = (xs, ys, zs, qs, rs, ss, ws, off_d)     # inputs live until the call finishes
+    return out
+
+
 def md_step(plan: Plan, atoms: Atoms, v: torch.Tensor, force: torch.Tensor,
             inv_mass: torch.Tensor, xi: torch.Tensor, dt: float, gamma: float, T: float = 300.0,
             xref: Optional[torch.Tensor] = None, k_restr: float = 0.0) -> None:

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgbmc.so")
-SOURCES = ["gbmc_kernels.hip", "gbmc_md.hip", "gbmc_host.cpp"]
+SOURCES = ["gbmc_kernels.hip", "gbmc_md.hip", "gbmc_plain.hip", "gbmc_host.cpp"]
 ARCH = os.environ.get("GBMC_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -1008,6 +1008,35 @@ gbmc_status md_langevin_step(gbmc_plan* p, void* x, void* y, void* z, void* v, c
     return e == hipSuccess ? GBMC_OK : hip_fail(e, "md_langevin_step launch");
 }
 
+size_t gb_plain_workspace_bytes(int32_t n_atoms)
+{
+    return n_atoms > 0 ? plain_workspace_bytes(n_atoms) : 0;
+}
+
+gbmc_status gb_plain_fp64(int32_t n_systems, const int32_t* host_atom_offset,
+                          const int32_t* atom_offset, const gbmc_atoms* a,
+                          const gbmc_gb_params* gp, void* workspace, double* born_R,
+                          double* e_coul, double* e_gb, double* force, double* dEdq,
+                          double* dEdrho, hipStream_t stream)
+{
+    gbmc_status st = check_offsets(n_systems, host_atom_offset);
+    if (st != GBMC_OK) return st;
+    if (!a || !gp) return fail(GBMC_ERR_INVALID, "NULL argument");
+    st = gbmc_params_validate(gp);
+    if (st != GBMC_OK) return st;
+    if (gp->kappa != 0.0 || gp->rgbmax != 0.0 || gp->cutoff != 0.0)
+        return fail(GBMC_ERR_UNSUPPORTED, "the plain FP64 form has no salt and no cutoffs");
+    const int32_t N = n_systems > 0 ? host_atom_offset[n_systems] : 0;
+    if (n_systems > 0 && !atom_offset) return fail(GBMC_ERR_INVALID, "atom_offset is NULL");
+    if (N > 0 && (!a->x || !a->y || !a->z || !a->q || !a->rho || !a->screen || !workspace))
+        return fail(GBMC_ERR_INVALID, "an input array or the workspace is NULL");
+    hipError_t e = launch_plain_fp64(n_systems, atom_offset, N, (const double*)a->x,
+                                     (const double*)a->y, (const double*)a->z, (const double*)a->q,
+                                     (const double*)a->rho, (const double*)a->screen, make_const(gp),
+                                     workspace, born_R, e_coul, e_gb, force, dEdq, dEdrho, stream);
+    return e == hipSuccess ? GBMC_OK : hip_fail(e, "gb_plain_fp64 launch");
+}
+
 gbmc_status gbmc_check_overflow(const gbmc_plan* p, void* ws, hipStream_t s, int32_t* flag)
 {
     if (!p || !ws || !flag) return fail(GBMC_ERR_INVALID, "NULL argument");

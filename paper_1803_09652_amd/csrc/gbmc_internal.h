@@ -208,6 +208,12 @@ template <typename T>
 hipError_t launch_md_langevin(int n, T* x, T* y, T* z, T* v, const T* force, const T* inv_mass,
                               const T* xi, const T* xref, double k_restr, double dt, double gamma,
                               double T_kelvin, hipStream_t s);
+size_t plain_workspace_bytes(int n_atoms);
+hipError_t launch_plain_fp64(int n_sys, const int32_t* atom_offset, int n_atoms, const double* x,
+                             const double* y, const double* z, const double* q, const double* rho,
+                             const double* screen, const GBConst& c, void* workspace,
+                             double* born_R, double* e_coul, double* e_gb, double* force,
+                             double* dEdq, double* dEdrho, hipStream_t s);
 hipError_t launch_remd_exchange(int M, const double* E_rung, const int32_t* Ne, int32_t* rep,
                                 double T_kelvin, int parity, int wrap, const double* u,
                                 int32_t* accepted, double* E_of_rep, hipStream_t s);
