@@ -51,13 +51,14 @@ def _pair(rgbmax, cutoff):
             dataclasses.replace(p_or, rgbmax=rgbmax, cutoff=cutoff))
 
 
-@pytest.mark.parametrize("prec,order", [("fp32", "identity"), ("fp64", "identity"),
-                                        ("fp32", "blocks")])
-def test_cutoff_batch_parity(prec, order):
+@pytest.mark.parametrize("prec,order,kappa", [("fp32", "identity", 0.0), ("fp64", "identity", 0.0),
+                                              ("fp32", "blocks", 0.0), ("fp32", "blocks", 0.1)])
+def test_cutoff_batch_parity(prec, order, kappa):
     systems = [synth.make_system(120, 1, 2.0), synth.make_system(121, 65, 5.0),
                synth.make_system(122, 300, 8.5)] + synth.config1()
     cut = _cutoff_in_gap(systems, 10.0, 10.5)
     p_gpu, p_or = _pair(12.0, cut)
+    p_gpu, p_or = dataclasses.replace(p_gpu, kappa=kappa), dataclasses.replace(p_or, kappa=kappa)
     g, batch, plan, atoms = build(systems, prec)
     if order == "blocks":
         plan.set_order(g.block_order(batch.atom_offset, batch.x, batch.y, batch.z))
@@ -109,3 +110,34 @@ def test_cutoff_large_globule_fp32():
     res = gpu_eval(plan, atoms, p_gpu)
     ref = oracle.energy_forces(s, p_or)
     compare_system(res, 0, batch.atom_offset, ref, "fp32")
+
+
+def test_cutoff_sweep_fp64():
+    # the sequential sweep with the pair cutoff (potential rows, K_SS and the
+    # K dq updates after each accepted visit) against the oracle's sweep
+    systems = synth.config2(n_rep=3)
+    cut = _cutoff_in_gap(systems, 9.0, 9.5)
+    p_gpu, p_or = _pair(11.0, cut)
+    g, batch, plan, atoms = build(systems, "fp64")
+    gref = np.random.default_rng(9).normal(0.0, 2.0, batch.state_count.size)
+    sites = g.Sites.from_batch(plan, batch, gref)
+    dev = plan.device
+    cur = torch.as_tensor(batch.current_state, device=dev)
+    u = synth.uniforms(31, (batch.n_sites, 3))
+    E = np.array([-0.3, -0.25, -0.2])
+    g.radii(plan, atoms, p_gpu)
+    out = g.mc_sweep(plan, sites, atoms, cur, 7.0, E, torch.as_tensor(u, device=dev), 300.0, p_gpu)
+    torch.cuda.synchronize()
+    dG = out["dG"].cpu().numpy()
+    st = cur.cpu().numpy()
+    m0, g0 = 0, 0
+    for b, s in enumerate(systems):
+        ns = len(s.sites)
+        n_st = sum(site.n_states for site in s.sites)
+        tab = oracle.SiteTables(s, gref[g0:g0 + n_st])
+        R = oracle.radii(s, p_or)["R"]
+        q_or, acc_or, dG_or = oracle.mc_sweep(s, R, tab, 7.0, E[b], 300.0, u[m0:m0 + ns], 3, p_or)
+        assert np.all(np.abs(dG[m0:m0 + ns] - dG_or) <= 1e-9 * np.maximum(1.0, np.abs(dG_or))), b
+        assert list(st[m0:m0 + ns]) == list(tab.current_state), b
+        m0 += ns
+        g0 += n_st
