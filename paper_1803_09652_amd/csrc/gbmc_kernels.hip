@@ -79,6 +79,23 @@ __device__ __forceinline__ long long to_fixed(double v, double scale, bool& bad)
     return ok ? __double2ll_rn(s) : 0ll;
 }
 
+// The same for an FP32 value in FP32 arithmetic, with the same result: with
+// m = |v| scale / 2^32 (exact, scale is a power of two), h = floor(m) and the
+// fraction m - h (exact for m >= 0), the nearest integer to |v| scale is
+// h 2^32 + rint((m - h) 2^32) (h 2^32 is even, so ties go the same way), and
+// rint(-x) = -rint(x).
+__device__ __forceinline__ long long to_fixed(float v, double scale, bool& bad)
+{
+    const float a = v * (float)(scale * (1.0 / 4294967296.0));
+    const float m = fabsf(a);
+    const bool ok = m < 1073741824.0f;                  // |v scale| < 2^62
+    bad |= !ok;
+    const float h = floorf(m);
+    const float lo = __builtin_rintf((m - h) * 4294967296.0f);
+    const long long r = (long long)(((unsigned long long)(unsigned)h << 32) | (unsigned)lo);
+    return ok ? (a < 0.0f ? -r : r) : 0ll;
+}
+
 // Row of atom a in a system of n >= 1 atoms.  Lanes past the end read (and add
 // zero to) the atom a mod n, so every lane issues the same memory operations
 // (the wait for the next block's loads then does not depend on the lane mix)
@@ -878,10 +895,10 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
             walk_tile<T, 1>(lane, J == w.I, aj, load, pair);
         else
             walk_tile_rows2<T, 1>(lane, aj, load, pair);
-        const long long hj = to_fixed((double)aj[0], kScaleI, bad);
+        const long long hj = to_fixed(aj[0], kScaleI, bad);
         fx_add(&I_fx[w.base + clamp_atom(j, w.n)], vj ? hj : 0ll);
 #pragma unroll
-        for (int r = 0; r < R; ++r) ifix[r] += to_fixed((double)ai[r], kScaleI, bad);
+        for (int r = 0; r < R; ++r) ifix[r] += to_fixed(ai[r], kScaleI, bad);
     };
     if constexpr (CUT) {
         int J = next_tile(tmask, w.J0, w.J1, w.J0);
@@ -1120,7 +1137,7 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
             long long v[5];
 #pragma unroll
             for (int a = 0; a < 5; ++a) {
-                v[a] = to_fixed((double)aj[a], kScaleF, bad);
+                v[a] = to_fixed(aj[a], kScaleF, bad);
                 v[a] = vj ? v[a] : 0ll;
             }
 #pragma unroll
@@ -1129,17 +1146,17 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
             fx_add(&wk.phi_fx[g], v[4]);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                fix[r][0] += to_fixed((double)fxi[r], kScaleF, bad);
-                fix[r][1] += to_fixed((double)fyi[r], kScaleF, bad);
-                fix[r][2] += to_fixed((double)fzi[r], kScaleF, bad);
-                fix[r][3] += to_fixed((double)Gi[r], kScaleF, bad);
-                fix[r][4] += to_fixed((double)phii[r], kScaleF, bad);
+                fix[r][0] += to_fixed(fxi[r], kScaleF, bad);
+                fix[r][1] += to_fixed(fyi[r], kScaleF, bad);
+                fix[r][2] += to_fixed(fzi[r], kScaleF, bad);
+                fix[r][3] += to_fixed(Gi[r], kScaleF, bad);
+                fix[r][4] += to_fixed(phii[r], kScaleF, bad);
             }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            efix[r][0] += to_fixed((double)(kC * eC[r]), kScaleE, bad);
-            efix[r][1] += to_fixed((double)(-(SALT ? T(1) : kT) * eG[r]), kScaleE, bad);
+            efix[r][0] += to_fixed(T(kC * eC[r]), kScaleE, bad);
+            efix[r][1] += to_fixed(T(-(SALT ? T(1) : kT) * eG[r]), kScaleE, bad);
         }
     };
     if constexpr (CUT) {
@@ -1365,7 +1382,7 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
             long long v[4];
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
-                v[a] = to_fixed((double)aj[a], kScaleF, bad);
+                v[a] = to_fixed(aj[a], kScaleF, bad);
                 v[a] = vj ? v[a] : 0ll;
             }
 #pragma unroll
@@ -1374,10 +1391,10 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            fix[r][0] += to_fixed((double)fxi[r], kScaleF, bad);
-            fix[r][1] += to_fixed((double)fyi[r], kScaleF, bad);
-            fix[r][2] += to_fixed((double)fzi[r], kScaleF, bad);
-            fix[r][3] += to_fixed((double)dri[r], kScaleF, bad);
+            fix[r][0] += to_fixed(fxi[r], kScaleF, bad);
+            fix[r][1] += to_fixed(fyi[r], kScaleF, bad);
+            fix[r][2] += to_fixed(fzi[r], kScaleF, bad);
+            fix[r][3] += to_fixed(dri[r], kScaleF, bad);
         }
     };
     if constexpr (CUT) {
