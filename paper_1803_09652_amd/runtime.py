@@ -19,7 +19,10 @@ the site states and the replica at each rung for the analysis.
 
 The systems of the plan are the replicas.  With exchange_every = 0 each
 system keeps its own redox potential (CEMD, C(pH,E)MD); otherwise the systems
-are replicas of one molecule on the ladder E_rung (E-REMD).
+are replicas of one molecule on the ladder E_rung (E-REMD).  Replicas at
+different pH form separate ladders (only replicas at the same pH exchange
+their redox potentials, section III.B): `ladders` lists the rung ranges
+[start, stop) of each, and each ladder's exchange attempt is its own call.
 """
 from __future__ import annotations
 
@@ -36,7 +39,7 @@ class ReplicaMD:
                  inv_mass, v, pH, E_rung, rep_of_rung=None, dt: float = 0.002, gamma: float = 5.0,
                  T: float = 300.0, attempt_every: int = 5, exchange_every: int = 0,
                  params: api.GBParams = api.IGB5, xref=None, k_restr: float = 0.0,
-                 wrap: bool = True, seed: int = 0):
+                 wrap: bool = True, seed: int = 0, ladders=None):
         if attempt_every < 0 or exchange_every < 0:
             raise ValueError("attempt_every and exchange_every must be >= 0")
         dev, dt_ = plan.device, plan.dtype
@@ -56,11 +59,31 @@ class ReplicaMD:
         if self.E_rung.shape != (B,):
             raise ValueError("E_rung must hold one redox potential per system")
         rep = np.arange(B) if rep_of_rung is None else np.asarray(rep_of_rung)
+        if sorted(rep.tolist()) != list(range(B)):
+            raise ValueError("rep_of_rung must be a permutation of the systems")
         self.rep_of_rung = torch.as_tensor(rep, dtype=torch.int32, device=dev).contiguous()
         # per-replica redox potential: replica rep_of_rung[l] sits at rung l
         E_rep = np.empty(B)
         E_rep[rep] = np.asarray(E_rung, dtype=np.float64)
         self.E_rep = torch.as_tensor(E_rep, device=dev)
+        # ladders: rung ranges; each ladder's replicas (fixed set, sorted) and
+        # their local indices on its rungs
+        lad = [(0, B)] if ladders is None else [(int(a), int(b)) for a, b in ladders]
+        if lad and (lad[0][0] != 0 or lad[-1][1] != B
+                    or any(l0[1] != l1[0] for l0, l1 in zip(lad, lad[1:]))
+                    or any(b <= a for a, b in lad)):
+            raise ValueError("ladders must partition the rungs 0..B in order")
+        self.ladders = []
+        for a, b in lad:
+            sys_k = np.sort(rep[a:b])
+            local = np.searchsorted(sys_k, rep[a:b]).astype(np.int32)
+            self.ladders.append({
+                "rungs": (a, b),
+                "sys": torch.as_tensor(sys_k, dtype=torch.int64, device=dev),
+                "rep": torch.as_tensor(local, device=dev).contiguous(),
+                "E_rung": self.E_rung[a:b].contiguous(),
+                "E_out": torch.empty(b - a, dtype=torch.float64, device=dev),
+            })
         st = np.asarray(current_state, dtype=np.int32)
         if st.shape != (sites.n_sites,):
             raise ValueError("current_state must hold one state per site")
@@ -127,10 +150,22 @@ class ReplicaMD:
             if self.exchange_every and (k + 1) % self.exchange_every == 0:
                 u = u_x[x_i] if u_x is not None else \
                     torch.rand(B, dtype=torch.float64, device=dev, generator=self.gen)
-                acc, _ = api.remd_exchange(self.E_rung, self.n_electrons, self.rep_of_rung,
-                                           self.n_exchanges % 2, u, self.T, self.wrap,
-                                           E_out=self.E_rep)
-                self._acc_x += acc.sum()
+                for lad in self.ladders:
+                    a, b = lad["rungs"]
+                    if len(self.ladders) == 1:
+                        # one ladder over every system: replica and local indices agree
+                        acc, _ = api.remd_exchange(self.E_rung, self.n_electrons, self.rep_of_rung,
+                                                   self.n_exchanges % 2, u, self.T, self.wrap,
+                                                   E_out=self.E_rep)
+                    else:
+                        ne = self.n_electrons.index_select(0, lad["sys"]).contiguous()
+                        acc, _ = api.remd_exchange(lad["E_rung"], ne, lad["rep"],
+                                                   self.n_exchanges % 2, u[a:b].contiguous(),
+                                                   self.T, self.wrap, E_out=lad["E_out"])
+                        self.E_rep.index_copy_(0, lad["sys"], lad["E_out"])
+                        self.rep_of_rung[a:b] = lad["sys"].index_select(
+                            0, lad["rep"].long()).to(torch.int32)
+                    self._acc_x += acc.sum()
                 x_i += 1
                 self.n_exchanges += 1
             f = api.energy_forces(plan, self.atoms, self.params, dEdq=False, dEdrho=False)["force"]

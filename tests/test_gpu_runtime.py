@@ -204,3 +204,63 @@ def test_pure_dynamics_loop_without_sites():
                                               xref=xref[:, sl].T, k_restr=KR)
             sys_.x, sys_.y, sys_.z = x, y, z
         assert np.abs(pos[sl] - sys_.coords()).max() <= 1e-9, b
+
+
+def test_two_ph_ladders_exchange_separately():
+    # replicas at pH 5 and pH 7 form two ladders; each ladder's exchange
+    # attempt sees only its own replicas (FP64, frozen geometry, against the
+    # oracle's attempt pair and exchange applied ladder by ladder)
+    from paper_1803_09652_amd.runtime import ReplicaMD
+    p_gpu, p_or = params_pair()
+    systems = _replicas(6)
+    g, batch, plan, atoms = build(systems, "fp64")
+    gref = synth.normals(17, batch.state_count.size) * 0.5
+    sites = g.Sites.from_batch(plan, batch, gref)
+    N, B = batch.x.shape[0], 6
+    pH = np.array([5.0, 5.0, 5.0, 7.0, 7.0, 7.0])
+    E_rung = np.array([-0.30, -0.27, -0.24, -0.30, -0.27, -0.24])
+    rep0 = np.array([1, 2, 0, 5, 3, 4])
+    ladders = [(0, 3), (3, 6)]
+    n_steps = 8
+    u_mc = synth.uniforms(18, (n_steps, B, 6))
+    u_x = synth.uniforms(19, (n_steps, B))
+    loop = ReplicaMD(plan, sites, atoms, batch.current_state, np.zeros(N), np.zeros((3, N)), pH,
+                     E_rung, rep0, dt=DT, gamma=GAMMA, T=T, attempt_every=1, exchange_every=1,
+                     params=p_gpu, ladders=ladders)
+    dev = plan.device
+    rec = loop.run(n_steps, u_mc=torch.as_tensor(u_mc, device=dev),
+                   u_x=torch.as_tensor(u_x, device=dev))
+    torch.cuda.synchronize()
+
+    soff = batch.site_state_offset
+    tabs, m0 = [], 0
+    for s in systems:
+        ns = len(s.sites)
+        tabs.append(oracle.SiteTables(s, gref[soff[m0]:soff[m0 + ns]]))
+        m0 += ns
+    sys_ = [s.copy() for s in systems]
+    rep = rep0.copy()
+    E_rep = np.empty(B)
+    E_rep[rep] = E_rung
+    ne = np.array([oracle.count_electrons(s, t) for s, t in zip(sys_, tabs)], np.int32)
+    for k in range(n_steps):
+        for b in range(B):
+            R = oracle.radii(sys_[b], p_or)["R"]
+            q, _, _ = oracle.mc_step(sys_[b], R, tabs[b], pH[b], E_rep[b], T, u_mc[k, b], p_or)
+            sys_[b].q = q
+            ne[b] = oracle.count_electrons(sys_[b], tabs[b])
+        assert np.array_equal(rec["state"][k].cpu().numpy(),
+                              np.concatenate([t.current_state for t in tabs])), k
+        assert np.array_equal(rec["rep_of_rung"][k].cpu().numpy(), rep), k
+        for a, e in ladders:
+            sys_k = np.sort(rep[a:e])
+            local = np.searchsorted(sys_k, rep[a:e])
+            loc, _, Eo = oracle.remd_exchange(E_rung[a:e], ne[sys_k], local, T, k % 2, True,
+                                              u_x[k, a:e])
+            rep[a:e] = sys_k[loc]
+            E_rep[sys_k] = Eo
+        # replicas never leave their ladder
+        assert set(rep[:3]) == {0, 1, 2} and set(rep[3:]) == {3, 4, 5}
+    assert np.array_equal(loop.rep_of_rung.cpu().numpy(), rep)
+    assert np.array_equal(loop.E_rep.cpu().numpy(), E_rep)
+    assert loop.exchanges_accepted > 0
