@@ -36,7 +36,8 @@ E0_REF, PKA_REF = -0.203, 4.4          # reference compound values of section II
 #   descreening pass 54 + 8, energy/force pass 53 + 4, chain pass 94 + 7.
 FLOPS_PER_PAIR = {"radii_pairs": 62, "energy_pairs": 57, "chain_pairs": 101}
 # Peak for FP32 vector arithmetic without packed-FP32 instructions (disabled in
-# this build): 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA) = 78.6 TFLOP/s;
+# every device build of the library): 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2
+# (FMA) = 78.6 TFLOP/s;
 # FP64 vector: 78.6 TFLOP/s.
 PEAK_TFLOPS = {"fp32": 78.6, "fp64": 78.6}
 
@@ -516,8 +517,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}): "
-              "the batch shards by replica across GPUs in principle, but this build measures "
-              "the single-GPU path", file=sys.stderr)
+              "the batch shards by replica across GPUs in principle, but the benchmark "
+              "measures the single-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)

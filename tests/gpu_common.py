@@ -1,7 +1,7 @@
 """Shared helpers of the GPU tests: build a plan from synthetic systems, run
 the GPU path through the C ABI, and fetch oracle references.
 
-Tolerances (the benchmark spec where it states one, otherwise derived here):
+Tolerances (the method's stated targets where there is one, otherwise derived here):
   FP32-fixed: forces, dE/dq, dE/drho  ||g - g_ref||_inf / ||g_ref||_inf <= 1e-5;
               Born radii   max |R - R_ref| / R_ref <= 2e-6 (pair terms carry
               ~1e-7 relative error; dR/dI amplifies it by at most ~10 here);
