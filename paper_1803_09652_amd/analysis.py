@@ -106,3 +106,45 @@ def fraction_by_rung(state, rep_of_rung, site_system, site_kind, site_state_offs
     # samples of rung l: the replica rep_of_rung[t, l] at time t
     by_rung = np.take_along_axis(ne, rep[:, :, None].astype(np.int64), axis=1)
     return by_rung.mean(axis=0) / n_e_max
+
+
+def fit_e0_of_ph(pH, E0, n_groups: int = 1, T: float = 300.0, v: int = 1, guess=None):
+    """Least-squares fit of Eq. 17 to standard potentials E0 measured at
+    several pH (the analysis of Fig. 4).  Returns (E0_prot, pka_red[n],
+    pka_oxi[n], residual rms).  guess: optional (E0_prot, pka_red, pka_oxi)."""
+    from scipy.optimize import least_squares
+
+    pH = np.asarray(pH, dtype=np.float64)
+    E0 = np.asarray(E0, dtype=np.float64)
+    n = int(n_groups)
+    if guess is None:
+        lo, hi = float(np.min(pH)), float(np.max(pH))
+        mid = np.linspace(lo, hi, n + 2)[1:-1]
+        guess = (float(E0[np.argmin(pH)]), mid + 0.5, mid - 0.5)
+    x0 = np.concatenate([[guess[0]], np.atleast_1d(guess[1]), np.atleast_1d(guess[2])])
+
+    def resid(x):
+        return e0_of_ph(pH, x[0], x[1:1 + n], x[1 + n:], T, v) - E0
+
+    r = least_squares(resid, x0, xtol=1e-14, ftol=1e-14, gtol=1e-14, max_nfev=20000)
+    x = r.x
+    return float(x[0]), x[1:1 + n].copy(), x[1 + n:].copy(), float(np.sqrt(np.mean(r.fun ** 2)))
+
+
+def fit_pka_of_e(E, sum_pka, T: float = 300.0, v: int = 1, guess=None):
+    """Least-squares fit of Eq. 18 to the summed pKa values measured at
+    several redox potentials.  Returns (sum_pka_red, E0_prot, E0_deprot,
+    residual rms)."""
+    from scipy.optimize import least_squares
+
+    E = np.asarray(E, dtype=np.float64)
+    y = np.asarray(sum_pka, dtype=np.float64)
+    if guess is None:
+        guess = (float(y[np.argmin(E)]), float(np.mean(E)) + 0.03, float(np.mean(E)) - 0.03)
+
+    def resid(x):
+        return sum_pka_of_e(E, x[0], x[1], x[2], T, v) - y
+
+    r = least_squares(resid, np.asarray(guess, dtype=np.float64), xtol=1e-14, ftol=1e-14,
+                      gtol=1e-14, max_nfev=20000)
+    return float(r.x[0]), float(r.x[1]), float(r.x[2]), float(np.sqrt(np.mean(r.fun ** 2)))

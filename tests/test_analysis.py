@@ -1,8 +1,9 @@
 """Pins of the analysis module (CPU): the Hill-form Nernst fit (Eq. 3) and the
 standard-potential / pKa relations of section II.D (Eqs. 16-18), checked
 against brute-force partition functions of one redox group coupled to
-independent pH-active groups, and the per-rung reduced fraction against a
-plain loop over the records."""
+independent pH-active groups, the fits of Eqs. 17 and 18 against exact
+curves, and the per-rung reduced fraction against a plain loop over the
+records."""
 import itertools
 import math
 
@@ -110,3 +111,33 @@ def test_fraction_by_rung_matches_plain_loop():
             for k, m in enumerate(redox):
                 ref[l, k] += cnt[sso[m] + state[t, m]]
     assert np.allclose(f, ref / a, rtol=0, atol=1e-15)
+
+
+def test_eq17_fit_recovers_one_group():
+    pH = np.linspace(2.0, 10.5, 18)                        # the pH grid of section IV.B
+    E0_prot, pr, po = -0.17, 6.1, 4.3
+    E0 = an.e0_of_ph(pH, E0_prot, [pr], [po], T)
+    e0p, fr, fo, rms = an.fit_e0_of_ph(pH, E0, 1, T)
+    assert rms < 1e-10
+    assert abs(e0p - E0_prot) < 1e-7 and abs(fr[0] - pr) < 1e-5 and abs(fo[0] - po) < 1e-5
+
+
+def test_eq17_fit_three_groups_reproduces_the_curve():
+    # three pH-active groups (two propionates and a glutamate in the paper's
+    # molecule): the parameters need not be unique, the fitted curve must be
+    pH = np.linspace(2.0, 10.5, 18)
+    E0 = an.e0_of_ph(pH, -0.15, [5.2, 6.0, 4.9], [4.1, 4.8, 4.6], T)
+    e0p, fr, fo, rms = an.fit_e0_of_ph(pH, E0, 3, T, guess=(-0.16, [5.0, 5.8, 5.0], [4.3, 4.5, 4.4]))
+    # nine parameters, weakly determined: the curve to 0.1 mV (the paper's fits
+    # carry errors of mV)
+    assert rms < 1e-4
+    # Eq. 16: the high-pH limit of the fitted curve is the fitted E0_deprot
+    assert abs(float(an.e0_of_ph(40.0, e0p, fr, fo, T)) - an.e0_deprot(e0p, fr, fo, T)) < 1e-9
+
+
+def test_eq18_fit_recovers_parameters():
+    E = np.linspace(-0.353, -0.023, 12)                    # the E grid of section IV.B
+    y = an.sum_pka_of_e(E, 13.5, -0.12, -0.21, T)
+    s, e0p, e0d, rms = an.fit_pka_of_e(E, y, T)
+    assert rms < 1e-10
+    assert abs(s - 13.5) < 1e-6 and abs(e0p + 0.12) < 1e-7 and abs(e0d + 0.21) < 1e-7
