@@ -29,17 +29,20 @@ sys.path.insert(0, ROOT)
 METRIC = "GB pair interactions/s (E+forces) & MC dE evals/s, FP32-fixed vs FP64, 1 GPU"
 KB, FARADAY = 1.98720426e-3, 23.0605478
 E0_REF, PKA_REF = -0.203, 4.4          # reference compound values of section III.C
+E_FIXED = E0_REF                        # redox potential of batches without an E ladder
 
 # Algorithmic work per unordered pair of one full evaluation, counted from the
 # closed-form expressions (FMA = 2; add, mul, min, max, abs, select = 1; each
 # reciprocal, sqrt, rsqrt, exp, log = 1 and counted as one operation):
 #   descreening pass 54 + 8, energy/force pass 53 + 4, chain pass 94 + 7.
 FLOPS_PER_PAIR = {"radii_pairs": 62, "energy_pairs": 57, "chain_pairs": 101}
-# Peak for FP32 vector arithmetic without packed-FP32 instructions (disabled in
-# every device build of the library): 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2
-# (FMA) = 78.6 TFLOP/s;
-# FP64 vector: 78.6 TFLOP/s.
-PEAK_TFLOPS = {"fp32": 78.6, "fp64": 78.6}
+# Peaks (MI355X, 256 CUs at 2.4 GHz): FP32 vector 157.3 TFLOP/s, FP64 vector
+# 78.6 TFLOP/s.  The library's device code has packed-FP32 instructions
+# disabled, yet the FP32 value is the attainable one: the FP32 pair kernels
+# issue up to 1.66 wave-instructions per SIMD per four cycles (SQ_INSTS_VALU
+# over GRBM_GUI_ACTIVE on the 64-system batch), more than a 16-lane issue
+# model (78.6 TFLOP/s) allows, so the wider published figure is the ceiling.
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 
 
 def parse():
@@ -57,6 +60,15 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cutoff-bench", action="store_true",
                     help="skip the large-globule cutoff measurement")
+    ap.add_argument("--no-uneven-bench", action="store_true",
+                    help="skip the uneven 64-system batch measurement")
+    ap.add_argument("--uneven-steps", type=int, default=20,
+                    help="timed steps of the uneven-batch measurement")
+    ap.add_argument("--no-uneven-tune", action="store_true",
+                    help="uneven batch: library default work shapes only (no autotuner run)")
+    ap.add_argument("--uneven-only", action="store_true",
+                    help="run only the uneven-batch measurement and print its JSON object "
+                         "(for profiling that batch on its own)")
     ap.add_argument("--md-steps", type=int, default=100,
                     help="steps of the timed simulation loop (0: skip)")
     ap.add_argument("--no-fp64", action="store_true")
@@ -93,15 +105,20 @@ def reference_gref(g, plan, b, atoms, cur, pH, E_rep, T, params):
 
 
 class Workload:
-    """Config-2 E-REMD batch resident on the GPU, with static step buffers."""
+    """A batch resident on the GPU, with static step buffers: by default the
+    E-REMD batch (16 replicas x 2,500 atoms on the E ladder, exchanges between
+    neighbouring rungs); with `systems` and exchange=False, any batch of
+    distinct systems (each at E_FIXED and pH 7, no exchange)."""
 
-    def __init__(self, precision, n_steps, order="spatial", tuning=None, overlap=True):
+    def __init__(self, precision, n_steps, order="spatial", tuning=None, overlap=True,
+                 systems=None, exchange=True):
         import numpy as np
         import torch
         import paper_1803_09652_amd as g
         import synth
         self.g, self.torch = g, torch
-        self.systems = synth.config2()
+        self.systems = systems if systems is not None else synth.config2()
+        self.exchange = exchange
         self.batch = b = synth.make_batch(self.systems)
         self.B = b.n_systems
         jb, wv = tuning if tuning else (None, None)
@@ -123,7 +140,8 @@ class Workload:
         self.side = torch.cuda.Stream(device=dev) if overlap else None
         self.params = g.IGB5
         self.T = 300.0
-        self.E_rung = torch.as_tensor(synth.E_LADDER, dtype=torch.float64, device=dev)
+        self.E_rung = (torch.as_tensor(synth.E_LADDER, dtype=torch.float64, device=dev) if exchange
+                       else torch.full((self.B,), E_FIXED, dtype=torch.float64, device=dev))
         self.rep_of_rung = torch.arange(self.B, dtype=torch.int32, device=dev)
         self.E_rep = self.E_rung.clone()                   # replica r starts on rung r
         self.pH = torch.full((self.B,), synth.PH_DEFAULT, dtype=torch.float64, device=dev)
@@ -174,9 +192,12 @@ class Workload:
                            self.u, self.T, p, counters=self.counters, q_out=nxt.q)
         if mc_stream is not main:
             main.wait_stream(mc_stream)
-        acc, _ = g.remd_exchange(self.E_rung, mc["n_electrons"], self.rep_of_rung, parity,
-                                 self.ux, self.T, True, E_out=self.E_rep)
-        self.last_exchange = acc
+        if self.exchange:
+            acc, _ = g.remd_exchange(self.E_rung, mc["n_electrons"], self.rep_of_rung, parity,
+                                     self.ux, self.T, True, E_out=self.E_rep)
+            self.last_exchange = acc
+        else:
+            self.last_exchange = None
         return ef
 
 
@@ -192,10 +213,10 @@ def autotune(precision, order):
 
 
 def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial", tuning=None,
-            overlap=True):
+            overlap=True, systems=None, exchange=True):
     import torch
     n_total = steps + warmup + kernel_steps + 2
-    w = Workload(precision, n_total, order, tuning, overlap)
+    w = Workload(precision, n_total, order, tuning, overlap, systems, exchange)
     torch.cuda.synchronize()
     k = 0       # steps done so far; step k has exchange parity k % 2
     graphs = None
@@ -244,7 +265,8 @@ def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial", 
     for _ in range(kernel_steps):
         w.step(k % 2)
         k += 1
-        acc += w.last_exchange.sum()
+        if w.last_exchange is not None:
+            acc += w.last_exchange.sum()
     kernel_ms = w.plan.kernel_ms() if kernel_steps > 0 else {}
     # the Monte Carlo Delta E kernels on their own (no concurrent force passes)
     cur = w.atoms if k % 2 == 0 else w.atoms_b
@@ -261,7 +283,8 @@ def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial", 
     w.force_alone_ms = w.plan.kernel_ms() if kernel_steps > 0 else {}
     w.plan.set_timing(False)
     w.exchanges_accepted = int(acc)
-    w.exchanges_attempted = kernel_steps * int(w.last_exchange.numel()) if kernel_steps else 0
+    w.exchanges_attempted = (kernel_steps * int(w.last_exchange.numel())
+                             if kernel_steps and w.last_exchange is not None else 0)
     return w, ms_step, wall / steps * 1e3, kernel_ms
 
 
@@ -379,8 +402,8 @@ def time_cutoff(n_atoms=100000, rgbmax=15.0, cutoff=16.0, steps=10):
 def time_plain_fp64(w, reps=3):
     """The plain FP64 GPU form (gb_plain_fp64: one thread per atom over its
     whole row, closed forms, correctly rounded operations) of one full
-    evaluation of the E-REMD batch, timed with HIP events: the reference the
-    metric's FP32-fixed vs FP64 comparison names."""
+    evaluation of the workload's batch, timed with HIP events: the reference
+    the metric's FP32-fixed vs FP64 comparison names."""
     import torch
     g, b = w.g, w.batch
     dev = w.plan.device
@@ -397,6 +420,58 @@ def time_plain_fp64(w, reps=3):
     ms = e0.elapsed_time(e1) / reps
     return {"ms_per_evaluation": ms, "value": w.pairs / (ms * 1e-3), "reps": reps,
             "form": "radii + energy + forces + dE/dq + dE/drho, every ordered pair, FP64"}
+
+
+def time_uneven_batch(steps=20, warmup=3, fp64_steps=5, tune=True):
+    """The uneven batch: 64 distinct systems of 500-20,000 atoms with 2-10
+    redox and 0-20 protonation sites each, one step = radii + energy / forces
+    (+ dE/dq, dE/drho) with the Monte Carlo branch (every candidate Delta E,
+    Metropolis attempt) beside it, captured in a HIP graph and replayed;
+    FP32-fixed with the library's default work shapes and with the shapes
+    the autotuner picks for this batch, the FP64 plan, and the plain FP64 form
+    of one evaluation."""
+    import numpy as np
+    import torch
+    import paper_1803_09652_amd as g
+    from paper_1803_09652_amd import autotune as at
+    import synth
+    systems = synth.config4()
+    n = np.array([s_.n for s_ in systems])
+    pairs = int((n * (n - 1) // 2).sum())
+    out = {"workload": f"{len(systems)} systems, {int(n.min())}-{int(n.max())} atoms "
+                       f"({int(n.sum())} in all), E = {E_FIXED} V, pH 7, no exchange",
+           "pairs_per_step": pairs}
+    runs = [("fp32", None, steps)]
+    if tune:
+        b = synth.make_batch(systems)
+        t = at.tune(b, "fp32", order=g.spatial_order(b.atom_offset, b.x, b.y, b.z),
+                    use_cache=False)
+        out["autotune"] = {"j_blocks_per_item": list(t["best"][0]),
+                           "waves_per_group": list(t["best"][1]),
+                           "tuned_pair_ms": t.get("pair_ms")}
+        runs.append(("fp32_autotuned", t["best"], steps))
+    runs.append(("fp64", None, fp64_steps))
+    for name, tuning, n_st in runs:
+        prec = "fp64" if name == "fp64" else "fp32"
+        w, ms, wall, kms = run_gpu(prec, n_st, warmup, True, 2, "spatial", tuning, True,
+                                   systems=systems, exchange=False)
+        out["candidates_per_step"] = w.n_cand
+        out[name] = {"ms_per_step": ms, "pair_interactions_per_s": pairs / (ms * 1e-3),
+                     "mc_dE_evals_per_s": w.n_cand / (ms * 1e-3), "steps": n_st,
+                     "kernel_ms": kms, "overflow": bool(g.check_overflow(w.plan)),
+                     # pair kernels inside the step (the Monte Carlo branch beside them)
+                     "pair_kernel_tflops": {k_: FLOPS_PER_PAIR[k_] * pairs / (kms[k_] * 1e-3) / 1e12
+                                            for k_ in FLOPS_PER_PAIR if k_ in kms},
+                     "peak_tflops": PEAK_TFLOPS[prec]}
+        if name == "fp32":
+            out["fp64_plain"] = time_plain_fp64(w, reps=1)
+        del w
+        torch.cuda.empty_cache()
+    best32 = max(v["pair_interactions_per_s"] for k_, v in out.items()
+                 if k_ in ("fp32", "fp32_autotuned"))
+    out["fp32_over_fp64"] = best32 / out["fp64"]["pair_interactions_per_s"]
+    out["fp32_over_fp64_plain"] = best32 / out["fp64_plain"]["value"]
+    return out
 
 
 def time_md_loop(steps, warmup, n_rep=16, attempt_every=5, exchange_every=10):
@@ -522,6 +597,10 @@ def main():
         sys.exit(2)
     import torch
     torch.cuda.set_device(0)
+    if args.uneven_only:
+        print(json.dumps(time_uneven_batch(args.uneven_steps, 2, max(1, args.uneven_steps // 4),
+                                           not args.no_uneven_tune)), flush=True)
+        return
     use_graph = not args.no_graph
     copy_ref = None
     if args.copy_calibration:
@@ -601,6 +680,9 @@ def main():
         out["md_loop"] = time_md_loop(args.md_steps, 10)
     if not args.no_cutoff_bench:
         out["cutoff"] = time_cutoff()
+    if not args.no_uneven_bench:
+        out["uneven_batch"] = time_uneven_batch(args.uneven_steps, 3, max(1, args.uneven_steps // 4),
+                                                not args.no_uneven_tune)
     cnt = w.counters.sum(0).cpu().tolist()
     out["mc_acceptance"] = {"state_attempts": cnt[0], "state_accepted": cnt[1],
                             "exchange_attempts_eager": w.exchanges_attempted,
