@@ -40,8 +40,8 @@ constexpr int64_t kTimedMax = 256;   // launches kept per timed kernel between r
 // Default work shapes (radii, energy, chain), the fastest measured for batches
 // of tens of thousands of atoms: the energy pass keeps two-tile items, which
 // halve its seven i-side flushes per tile.
-const gbmc_tuning kDefaultTuning32 = {{1, 2, 1}, {4, 4, 1}};
-const gbmc_tuning kDefaultTuning64 = {{1, 2, 1}, {2, 4, 2}};
+const gbmc_tuning kDefaultTuning32 = {{1, 1, 1}, {4, 8, 1}};
+const gbmc_tuning kDefaultTuning64 = {{1, 1, 1}, {2, 2, 2}};
 
 }  // namespace
 
@@ -649,9 +649,11 @@ gbmc_status gb_energy_forces(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_pa
     if (p->n_items[GBMC_PASS_ENERGY] > 0)
         ev = (force || dEdrho) ? events(p, {kKEnergy, kKChain}) : events(p, {kKEnergy});
     const PassShape pe{p->d_items[GBMC_PASS_ENERGY], p->n_items[GBMC_PASS_ENERGY],
-                       p->tuning.waves_per_group[GBMC_PASS_ENERGY]};
+                       p->tuning.waves_per_group[GBMC_PASS_ENERGY],
+                       p->tuning.j_blocks_per_item[GBMC_PASS_ENERGY] == 1};
     const PassShape pc{p->d_items[GBMC_PASS_CHAIN], p->n_items[GBMC_PASS_CHAIN],
-                       p->tuning.waves_per_group[GBMC_PASS_CHAIN]};
+                       p->tuning.waves_per_group[GBMC_PASS_CHAIN],
+                       p->tuning.j_blocks_per_item[GBMC_PASS_CHAIN] == 1};
     hipError_t e;
     if (p->prec == GBMC_FP32_FIXED)
         e = launch_energy_forces<float>(pe, pc, p->n_atoms, p->n_sys, cut_plan(p),

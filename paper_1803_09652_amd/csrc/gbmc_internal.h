@@ -175,6 +175,7 @@ struct PassShape {
     const WorkItem* items;
     int n_items;
     int waves_per_group;
+    bool one_tile;          // every item is a single tile (one j block per item)
 };
 
 template <typename T>

@@ -28,6 +28,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "gbmc_internal.h"
 
@@ -990,7 +991,7 @@ __global__ void k_radii_finalize(int n_atoms, const T* __restrict__ RHO, GBConst
 // Coulomb + GB energy, explicit pair forces, G = dE/dR, phi = dE/dq.
 
 // One work item of R (1 or 2) i blocks; see radii_item.
-template <typename T, bool GRAD, int R, bool SALT, bool CUT>
+template <typename T, bool GRAD, int R, bool SALT, bool CUT, bool ONE>
 __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* sj, T* sR, T* sA,
                                             const Q4<T>* __restrict__ P, const T* __restrict__ Rt,
                                             const T* __restrict__ At, T kC, T kT,
@@ -1045,7 +1046,10 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
     // one tile, then the loads of the next tile; the first tile is peeled so
     // that the loop is entered, as on every later trip, with the previous
     // tile's sums still in flight
-    auto tile = [&](int J) {
+    // FIRST (the peeled first tile of a full item): the i-side sums are set,
+    // not added to, so no zeroed accumulators stay live through the walk
+    auto tile = [&](int J, auto first_tag) {
+        constexpr bool FIRST = decltype(first_tag)::value;
         int Jn = J + 1;
         if constexpr (CUT) Jnext = Jn = next_tile(tmask, w.J0, w.J1, J + 1);
         const int j = J * kTile + lane;
@@ -1146,27 +1150,33 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
             fx_add(&wk.phi_fx[g], v[4]);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                fix[r][0] += to_fixed(fxi[r], kScaleF, bad);
-                fix[r][1] += to_fixed(fyi[r], kScaleF, bad);
-                fix[r][2] += to_fixed(fzi[r], kScaleF, bad);
-                fix[r][3] += to_fixed(Gi[r], kScaleF, bad);
-                fix[r][4] += to_fixed(phii[r], kScaleF, bad);
+                const long long f[5] = {to_fixed(fxi[r], kScaleF, bad), to_fixed(fyi[r], kScaleF, bad),
+                                        to_fixed(fzi[r], kScaleF, bad), to_fixed(Gi[r], kScaleF, bad),
+                                        to_fixed(phii[r], kScaleF, bad)};
+#pragma unroll
+                for (int a = 0; a < 5; ++a) fix[r][a] = FIRST ? f[a] : fix[r][a] + f[a];
             }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            efix[r][0] += to_fixed(T(kC * eC[r]), kScaleE, bad);
-            efix[r][1] += to_fixed(T(-(SALT ? T(1) : kT) * eG[r]), kScaleE, bad);
+            const long long e0 = to_fixed(T(kC * eC[r]), kScaleE, bad);
+            const long long e1 = to_fixed(T(-(SALT ? T(1) : kT) * eG[r]), kScaleE, bad);
+            efix[r][0] = FIRST ? e0 : efix[r][0] + e0;
+            efix[r][1] = FIRST ? e1 : efix[r][1] + e1;
         }
     };
     if constexpr (CUT) {
         int J = next_tile(tmask, w.J0, w.J1, w.J0);
         if (J >= w.J1) return;                  // nothing within the cutoff: no sums to add
         fetch(J, pj, Rj, Aj);
-        for (; J < w.J1; J = Jnext) tile(J);
+        for (; J < w.J1; J = Jnext) tile(J, std::false_type{});
     } else {
-        tile(w.J0);
-        for (int J = w.J0 + 1; J < w.J1; ++J) tile(J);
+        tile(w.J0, std::true_type{});
+        // ONE: every item of the launch is a single tile (one j block); the
+        // prefetch and the cross-tile sums then drop out, and the kernel
+        // needs fewer registers
+        if constexpr (!ONE)
+            for (int J = w.J0 + 1; J < w.J1; ++J) tile(J, std::false_type{});
     }
     if (bad) *wk.ovf = 1;
 #pragma unroll
@@ -1186,7 +1196,7 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
     }
 }
 
-template <typename T, bool GRAD, int W, bool SALT, bool CUT>
+template <typename T, bool GRAD, int W, bool SALT, bool CUT, bool ONE>
 __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
     const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
     const T* __restrict__ Rt, const T* __restrict__ At, T kC, T kT, SaltK<T> sk, CutK<T> ck,
@@ -1202,7 +1212,7 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
         for (int it = blockIdx.x * W + wave; it < n; it += gridDim.x * W) {
             unsigned long long m;
             const WorkItem w = cut_work_item(wk.citems[1][it], m);
-            energy_item<T, GRAD, 1, SALT, true>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P, Rt,
+            energy_item<T, GRAD, 1, SALT, true, false>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P, Rt,
                                                 At, kC, kT, sk, ck, wk, m);
         }
     } else {
@@ -1211,12 +1221,12 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
         const WorkItem w = items[item];
         // two-row items exist in the energy pass of FP32 plans only
         if (sizeof(T) == 4 && w.rows == 2)
-            energy_item<T, GRAD, sizeof(T) == 4 ? 2 : 1, SALT, false>(w, lane, sj_w[wave],
+            energy_item<T, GRAD, sizeof(T) == 4 ? 2 : 1, SALT, false, ONE>(w, lane, sj_w[wave],
                                                                       sR_w[wave], sA_w[wave], P,
                                                                       Rt, At, kC, kT, sk, ck, wk,
                                                                       0ull);
         else
-            energy_item<T, GRAD, 1, SALT, false>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P, Rt,
+            energy_item<T, GRAD, 1, SALT, false, ONE>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P, Rt,
                                                  At, kC, kT, sk, ck, wk, 0ull);
     }
 }
@@ -1271,7 +1281,7 @@ __global__ __launch_bounds__(256) void k_energy_finalize(int n_atoms, int n_sum,
 // Born-radius chain: force through Psi and the pair part of dE/drho.
 
 // One work item of R (1 or 2) i blocks; see radii_item.
-template <typename T, int R, bool CUT>
+template <typename T, int R, bool CUT, bool ONE>
 __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* sj, Q4<T>* sb,
                                            const Q4<T>* __restrict__ P,
                                            const Q4<T>* __restrict__ Gx,
@@ -1331,7 +1341,9 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
     // one tile, then the loads of the next tile; the first tile is peeled so
     // that the loop is entered, as on every later trip, with the previous
     // tile's sums still in flight
-    auto tile = [&](int J) {
+    // FIRST: as in the energy pass, the first tile sets the i-side sums
+    auto tile = [&](int J, auto first_tag) {
+        constexpr bool FIRST = decltype(first_tag)::value;
         int Jn = J + 1;
         if constexpr (CUT) Jnext = Jn = next_tile(tmask, w.J0, w.J1, J + 1);
         const int j = J * kTile + lane;
@@ -1391,20 +1403,21 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            fix[r][0] += to_fixed(fxi[r], kScaleF, bad);
-            fix[r][1] += to_fixed(fyi[r], kScaleF, bad);
-            fix[r][2] += to_fixed(fzi[r], kScaleF, bad);
-            fix[r][3] += to_fixed(dri[r], kScaleF, bad);
+            const long long f[4] = {to_fixed(fxi[r], kScaleF, bad), to_fixed(fyi[r], kScaleF, bad),
+                                    to_fixed(fzi[r], kScaleF, bad), to_fixed(dri[r], kScaleF, bad)};
+#pragma unroll
+            for (int a = 0; a < 4; ++a) fix[r][a] = FIRST ? f[a] : fix[r][a] + f[a];
         }
     };
     if constexpr (CUT) {
         int J = next_tile(tmask, w.J0, w.J1, w.J0);
         if (J >= w.J1) return;                  // nothing within the cutoff: no sums to add
         fetch(J, pj, gj, brj);
-        for (; J < w.J1; J = Jnext) tile(J);
+        for (; J < w.J1; J = Jnext) tile(J, std::false_type{});
     } else {
-        tile(w.J0);
-        for (int J = w.J0 + 1; J < w.J1; ++J) tile(J);
+        tile(w.J0, std::true_type{});
+        if constexpr (!ONE)                     // ONE: single-tile items, as in the energy pass
+            for (int J = w.J0 + 1; J < w.J1; ++J) tile(J, std::false_type{});
     }
     if (bad) *wk.ovf = 1;
 #pragma unroll
@@ -1417,7 +1430,7 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
     }
 }
 
-template <typename T, int W, bool CUT>
+template <typename T, int W, bool CUT, bool ONE>
 __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
     const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
     const Q4<T>* __restrict__ Gx, const T* __restrict__ Brt, Work<T> wk, T cR)
@@ -1432,13 +1445,13 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
         for (int it = blockIdx.x * W + wave; it < n; it += gridDim.x * W) {
             unsigned long long m;
             const WorkItem w = cut_work_item(wk.citems[0][it], m);
-            chain_item<T, 1, true>(w, lane, sj_w[wave], sb_w[wave], P, Gx, Brt, wk, cR, m);
+            chain_item<T, 1, true, false>(w, lane, sj_w[wave], sb_w[wave], P, Gx, Brt, wk, cR, m);
         }
     } else {
         const int item = blockIdx.x * W + wave;
         if (item >= n_items) return;
         const WorkItem w = items[item];
-        chain_item<T, 1, false>(w, lane, sj_w[wave], sb_w[wave], P, Gx, Brt, wk, cR, 0ull);
+        chain_item<T, 1, false, ONE>(w, lane, sj_w[wave], sb_w[wave], P, Gx, Brt, wk, cR, 0ull);
     }
 }
 
@@ -2036,26 +2049,34 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
     if (pe.n_items > 0) {
         const SaltK<T> sk{(T)c.kO, (T)c.kappa, (T)(c.kappa * kLog2e)};
         const CutK<T> ck{(T)c.cutoff, (T)(c.cutoff * c.cutoff)};
-#define GBMC_ENERGY_LAUNCH(G_, S_, C_)                                                            \
+#define GBMC_ENERGY_LAUNCH(G_, S_, C_, O_)                                                        \
     GBMC_DISPATCH_W(pe.waves_per_group,                                                          \
-                    GBMC_LAUNCH_TIMED(ev, kKEnergy, (k_energy_pairs<T, G_, W, S_, C_>),          \
+                    GBMC_LAUNCH_TIMED(ev, kKEnergy, (k_energy_pairs<T, G_, W, S_, C_, O_>),      \
                                       dim3(C_ ? cut_groups(w.cut_cap, W)                         \
                                               : blocks_for(pe.n_items, W)),                      \
                                       dim3(kTile * W), s,                                        \
                                       pe.items, pe.n_items, w.P, w.R_t, w.a_t, (T)c.kC, (T)c.kT, \
                                       sk, ck, w))
-        const bool salt = c.kappa != 0.0, cut = c.cutoff > 0.0;
+        const bool salt = c.kappa != 0.0, cut = c.cutoff > 0.0, one = pe.one_tile;
         if (grad) {
             if (salt) {
-                if (cut) GBMC_ENERGY_LAUNCH(true, true, true) else GBMC_ENERGY_LAUNCH(true, true, false)
+                if (cut) GBMC_ENERGY_LAUNCH(true, true, true, false)
+                else if (one) GBMC_ENERGY_LAUNCH(true, true, false, true)
+                else GBMC_ENERGY_LAUNCH(true, true, false, false)
             } else {
-                if (cut) GBMC_ENERGY_LAUNCH(true, false, true) else GBMC_ENERGY_LAUNCH(true, false, false)
+                if (cut) GBMC_ENERGY_LAUNCH(true, false, true, false)
+                else if (one) GBMC_ENERGY_LAUNCH(true, false, false, true)
+                else GBMC_ENERGY_LAUNCH(true, false, false, false)
             }
         } else {
             if (salt) {
-                if (cut) GBMC_ENERGY_LAUNCH(false, true, true) else GBMC_ENERGY_LAUNCH(false, true, false)
+                if (cut) GBMC_ENERGY_LAUNCH(false, true, true, false)
+                else if (one) GBMC_ENERGY_LAUNCH(false, true, false, true)
+                else GBMC_ENERGY_LAUNCH(false, true, false, false)
             } else {
-                if (cut) GBMC_ENERGY_LAUNCH(false, false, true) else GBMC_ENERGY_LAUNCH(false, false, false)
+                if (cut) GBMC_ENERGY_LAUNCH(false, false, true, false)
+                else if (one) GBMC_ENERGY_LAUNCH(false, false, false, true)
+                else GBMC_ENERGY_LAUNCH(false, false, false, false)
             }
         }
 #undef GBMC_ENERGY_LAUNCH
@@ -2068,13 +2089,18 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
     if (chain && pc.n_items > 0) {
         if (c.rgbmax > 0.0)
             GBMC_DISPATCH_W(pc.waves_per_group,
-                            GBMC_LAUNCH_TIMED(ev, kKChain, (k_chain_pairs<T, W, true>),
+                            GBMC_LAUNCH_TIMED(ev, kKChain, (k_chain_pairs<T, W, true, false>),
                                               dim3(cut_groups(w.cut_cap, W)), dim3(kTile * W), s,
                                               pc.items, pc.n_items, w.P, w.Gx, w.Brt_t, w,
                                               (T)c.rgbmax))
+        else if (pc.one_tile)
+            GBMC_DISPATCH_W(pc.waves_per_group,
+                            GBMC_LAUNCH_TIMED(ev, kKChain, (k_chain_pairs<T, W, false, true>),
+                                              dim3(blocks_for(pc.n_items, W)), dim3(kTile * W), s,
+                                              pc.items, pc.n_items, w.P, w.Gx, w.Brt_t, w, (T)0))
         else
             GBMC_DISPATCH_W(pc.waves_per_group,
-                            GBMC_LAUNCH_TIMED(ev, kKChain, (k_chain_pairs<T, W, false>),
+                            GBMC_LAUNCH_TIMED(ev, kKChain, (k_chain_pairs<T, W, false, false>),
                                               dim3(blocks_for(pc.n_items, W)), dim3(kTile * W), s,
                                               pc.items, pc.n_items, w.P, w.Gx, w.Brt_t, w, (T)0))
     }
