@@ -327,6 +327,41 @@ __device__ __forceinline__ void chain_pair(float r, float r2, float invr, float 
     dEdr = -u * fmaf(bi, aij, bj * aji);
 }
 
+// The polynomial form alone, for walks that defer the pairs it does not cover.
+// A pair that needs the closed form in either direction (act only) gets zero
+// terms and its bit in mask (one wave-uniform branch, taken only in the steps
+// that meet such a pair); the caller evaluates those pairs after the walk.
+__device__ __forceinline__ void chain_pair_fast(float r, float invr, float rti, float Si, float rtj,
+                                                float Sj, float bi, float bj, bool act,
+                                                unsigned long long bit, float& dEdr, float& gij2,
+                                                float& gji2, unsigned long long& mask)
+{
+    const float u = invr * invr;
+    const float xij = Sj * invr, yij = xij * xij;
+    const float xji = Si * invr, yji = xji * xji;
+    float wij = rcp(1.0f - yij), wji = rcp(1.0f - yji);
+    wij *= wij;
+    wji *= wji;
+    const float tij = yij * wij, tji = yji * wji;
+    float aij = xij * fmaf(yij, hct_poly_d(yij), tij);
+    float aji = xji * fmaf(yji, hct_poly_d(yji), tji);
+    gij2 = tij * u;
+    gji2 = tji * u;
+    const bool fast = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX) & (r - Si >= rtj) &
+                      (yji <= GBMC_HCT_YMAX);
+    if (__builtin_amdgcn_ballot_w64(!fast) != 0ull) {
+        // an empty volatile statement keeps this a branch (not selects on
+        // every step)
+        asm volatile("");
+        aij = fast ? aij : 0.0f;
+        aji = fast ? aji : 0.0f;
+        gij2 = fast ? gij2 : 0.0f;
+        gji2 = fast ? gji2 : 0.0f;
+        mask |= (!fast && act) ? bit : 0ull;
+    }
+    dEdr = -u * fmaf(bi, aij, bj * aji);
+}
+
 // FP64: the same split with the FP64 polynomial; overlapping pairs take the
 // closed-form partials.
 __device__ __forceinline__ void chain_pair(double r, double r2, double invr, double rti, double Si,
@@ -1283,11 +1318,20 @@ __global__ __launch_bounds__(256) void k_energy_finalize(int n_atoms, int n_sum,
 // One work item of R (1 or 2) i blocks; see radii_item.
 template <typename T, int R, bool CUT, bool ONE>
 __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* sj, Q4<T>* sb,
+                                           unsigned long long* sdef, int* slist,
                                            const Q4<T>* __restrict__ P,
                                            const Q4<T>* __restrict__ Gx,
                                            const T* __restrict__ Brt, const Work<T>& wk, T cR,
                                            unsigned long long tmask)
 {
+    // DEFER (FP32, one row, all pairs): the walk evaluates the polynomial form
+    // only and marks the pairs that need the closed form (overlapping spheres)
+    // in a per-lane mask of walk steps; after the walk the marked pairs are
+    // evaluated packed, one per lane per round, instead of with most of the
+    // wave masked off in the step that met them.  Their j-side terms go to the
+    // j atoms through LDS int64 fixed-point atomics (exact, so the result does
+    // not depend on the order of the rounds).
+    constexpr bool DEFER = sizeof(T) == 4 && R == 1 && !CUT;
     T xi[R], yi[R], zi[R], rti[R], Si[R], Bi[R], si[R];
     bool vi[R];
 #pragma unroll
@@ -1360,6 +1404,10 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
         T aj[4];
         struct JD { Q4<T> p, b; };
         auto load = [&](int s) { return JD{sj[s], sb[s]}; };
+        // DEFER: walk step of the next pair call (the walk visits slot lane + k
+        // at step k: k = 0..63 off the diagonal, 1..32 on it) and the marks
+        int kstep = J == w.I ? 1 : 0;
+        unsigned long long dmask = 0ull;
         auto pair = [&](const JD& d, int r, bool act, T (&acc)[4]) {
             const Q4<T>& p = d.p;
             const Q4<T>& b = d.b;
@@ -1370,12 +1418,20 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
             const T bj_ = act ? b.y : T(0);
             const T bi_ = act ? Bi[r] : T(0);
             T dEdr, gij2, gji2;
-            if constexpr (CUT)
+            if constexpr (CUT) {
                 chain_pair_cut(rr, r2, invr, rti[r], Si[r], p.w, b.x, bi_, bj_, cR, dEdr, gij2, gji2,
                                dri[r], acc[3]);
-            else
+            } else if constexpr (DEFER) {
+                // only pairs of a real i atom are marked (padding lanes sit far
+                // apart, so none of theirs needs the closed form anyway); the
+                // packed rounds read the i atom back from global memory
+                chain_pair_fast(rr, invr, rti[r], Si[r], p.w, b.x, bi_, bj_, act && vi[r],
+                                1ull << kstep, dEdr, gij2, gji2, dmask);
+                ++kstep;
+            } else {
                 chain_pair(rr, r2, invr, rti[r], Si[r], p.w, b.x, bi_, bj_, dEdr, gij2, gji2,
                            dri[r], acc[3]);
+            }
             T fr = dEdr * invr;
             T fx = fr * dx, fy = fr * dy, fz = fr * dz;
             fxi[r] -= fx; fyi[r] -= fy; fzi[r] -= fz;
@@ -1389,12 +1445,91 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
             walk_tile<T, 4>(lane, J == w.I, aj, load, pair);
         else
             walk_tile_rows2<T, 4>(lane, aj, load, pair);
+        // DEFER: the marked pairs, packed into rounds of up to 64 (the marks of
+        // all lanes listed in lane order, lane t of a round taking list entry
+        // t).  The j-side terms are rounded to fixed point per pair and added
+        // with LDS integer atomics (sdef[a * 64 + j lane]: exact, so the order
+        // of a round's lanes does not matter); the i-side terms go back to the
+        // i atom's lane, which owns a contiguous run of the round's entries,
+        // and join its FP32 sums in list order.
+        bool deferred = false;
+        if constexpr (DEFER) {
+            deferred = __builtin_amdgcn_ballot_w64(dmask != 0ull) != 0ull;
+            if (deferred) {
+#pragma unroll
+                for (int a = 0; a < 4; ++a) sdef[a * kTile + lane] = 0ull;
+                wave_sync();
+                for (;;) {
+                    const int cnt = __builtin_popcountll(dmask);
+                    int incl = cnt;                     // inclusive scan over the lanes
+#pragma unroll
+                    for (int d = 1; d < kTile; d <<= 1) {
+                        const int o = from_lane_i(incl, (lane - d) & (kTile - 1));
+                        incl += lane >= d ? o : 0;
+                    }
+                    const int total = __builtin_amdgcn_readlane(incl, kTile - 1);
+                    if (total == 0) break;
+                    // this lane's entries of the round: list slots [o0, o0 + n)
+                    const int o0 = incl - cnt;
+                    const int n = o0 < kTile ? min(cnt, kTile - o0) : 0;
+                    for (int t = o0; t < o0 + n; ++t) {
+                        const int k = __builtin_ctzll(dmask);
+                        dmask &= dmask - 1ull;
+                        slist[t] = (lane << 8) | k;
+                    }
+                    wave_sync();
+                    T iv[4] = {T(0), T(0), T(0), T(0)};
+                    if (lane < total) {
+                        const int e = slist[lane], il = e >> 8, k = e & 0xff;
+                        const int gi = w.base + w.I * kTile + il;
+                        const Q4<T> pi = P[gi];
+                        const Q4<T> gxi = Gx[gi];       // rt, S, screen
+                        const T bi_ = Brt[gi];
+                        const JD d = load(il + k);
+                        const Q4<T>& p = d.p;
+                        const Q4<T>& b = d.b;
+                        const T dx = pi.x - p.x, dy = pi.y - p.y, dz = pi.z - p.z;
+                        const T r2 = dx * dx + dy * dy + dz * dz;
+                        const T invr = rsq(r2);
+                        const T rr = r2 * invr;
+                        T ga[3], gb[3];
+                        hct_slow32<true>(rr, invr, gxi.x, b.x, ga);     // H(r; rt_i, S_j)
+                        hct_slow32<true>(rr, invr, p.w, gxi.y, gb);     // H(r; rt_j, S_i)
+                        const T bj_ = b.y;
+                        // dE/dr = bi dH_ij/dr + bj dH_ji/dr
+                        const T fr = fmaf(bi_, ga[0], bj_ * gb[0]) * invr;
+                        const T fx = fr * dx, fy = fr * dy, fz = fr * dz;
+                        iv[0] = -fx; iv[1] = -fy; iv[2] = -fz;
+                        iv[3] = fmaf(bi_, ga[1], gxi.z * bj_ * gb[2]);
+                        const T jv[4] = {fx, fy, fz, fmaf(b.z * bi_, ga[2], bj_ * gb[1])};
+                        const int jl = (il + k) & (kTile - 1);
+#pragma unroll
+                        for (int a = 0; a < 4; ++a)
+                            atomicAdd(&sdef[a * kTile + jl],
+                                      (unsigned long long)to_fixed(jv[a], kScaleF, bad));
+                    }
+                    // i side: every lane reads its run (all lanes take part in
+                    // each read, the sums only for u < n)
+                    for (int u = 0; __builtin_amdgcn_ballot_w64(u < n) != 0ull; ++u) {
+                        const int src = min(o0 + u, kTile - 1);
+                        const T v0 = from_lane(iv[0], src), v1 = from_lane(iv[1], src);
+                        const T v2 = from_lane(iv[2], src), v3 = from_lane(iv[3], src);
+                        if (u < n) {
+                            fxi[0] += v0; fyi[0] += v1; fzi[0] += v2; dri[0] += v3;
+                        }
+                    }
+                    wave_sync();
+                }
+            }
+        }
         {
             const int g = w.base + clamp_atom(j, w.n);
             long long v[4];
 #pragma unroll
             for (int a = 0; a < 4; ++a) {
                 v[a] = to_fixed(aj[a], kScaleF, bad);
+                if constexpr (DEFER)
+                    if (deferred) v[a] += (long long)sdef[a * kTile + lane];
                 v[a] = vj ? v[a] : 0ll;
             }
 #pragma unroll
@@ -1437,6 +1572,11 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
 {
     __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, rt
     __shared__ Q4<T> sb_w[W][2 * kTile];     // S, B rt, screen, -
+    // deferred pairs (FP32 all-pairs walk only): j-side sums, round list
+    constexpr int ND = (sizeof(T) == 4 && !CUT) ? 4 * kTile : 1;
+    constexpr int NL = (sizeof(T) == 4 && !CUT) ? kTile : 1;
+    __shared__ unsigned long long sd_w[W][ND];
+    __shared__ int sl_w[W][NL];
     const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
     // the chain pass runs one-row items only (its two-row form was slower:
     // fewer waves in flight for less saved work)
@@ -1445,13 +1585,15 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
         for (int it = blockIdx.x * W + wave; it < n; it += gridDim.x * W) {
             unsigned long long m;
             const WorkItem w = cut_work_item(wk.citems[0][it], m);
-            chain_item<T, 1, true, false>(w, lane, sj_w[wave], sb_w[wave], P, Gx, Brt, wk, cR, m);
+            chain_item<T, 1, true, false>(w, lane, sj_w[wave], sb_w[wave], sd_w[wave], sl_w[wave], P,
+                                          Gx, Brt, wk, cR, m);
         }
     } else {
         const int item = blockIdx.x * W + wave;
         if (item >= n_items) return;
         const WorkItem w = items[item];
-        chain_item<T, 1, false, ONE>(w, lane, sj_w[wave], sb_w[wave], P, Gx, Brt, wk, cR, 0ull);
+        chain_item<T, 1, false, ONE>(w, lane, sj_w[wave], sb_w[wave], sd_w[wave], sl_w[wave], P, Gx,
+                                     Brt, wk, cR, 0ull);
     }
 }
 
