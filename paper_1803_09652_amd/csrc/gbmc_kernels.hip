@@ -263,6 +263,32 @@ __device__ __forceinline__ void radii_pair(float xi, float yi, float zi, float x
     }
 }
 
+// The polynomial form alone, for walks that defer the pairs it does not cover
+// (as chain_pair_fast): a pair that needs the closed form in either direction
+// gets zero terms and, if act, its bit in mask.
+__device__ __forceinline__ void radii_pair_fast(float xi, float yi, float zi, float xj, float yj,
+                                                float zj, float rti, float Si, float rtj, float Sj,
+                                                bool act, unsigned long long bit, float& hij,
+                                                float& hji, unsigned long long& mask)
+{
+    float dx = xi - xj, dy = yi - yj, dz = zi - zj;
+    float r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    float invr = rsq(r2);
+    float r = r2 * invr;
+    float xij = Sj * invr, yij = xij * xij;
+    float xji = Si * invr, yji = xji * xji;
+    hij = xij * yij * invr * hct_poly(yij);
+    hji = xji * yji * invr * hct_poly(yji);
+    const bool fast = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX) & (r - Si >= rtj) &
+                      (yji <= GBMC_HCT_YMAX);
+    if (__builtin_amdgcn_ballot_w64(!fast) != 0ull) {
+        asm volatile("");                       // keeps this a branch
+        hij = fast ? hij : 0.0f;
+        hji = fast ? hji : 0.0f;
+        mask |= (!fast && act) ? bit : 0ull;
+    }
+}
+
 // FP64: the same split, with a degree-14 polynomial on y <= 0.25 (one ulp);
 // every other pair takes the closed form.
 __device__ __forceinline__ void radii_pair(double xi, double yi, double zi, double xj, double yj,
@@ -845,11 +871,15 @@ __global__ __launch_bounds__(kTile * kCutWaves) void k_cut_items(
 // the sum of its two tiles, the same for every work shape.
 template <typename T, int R, bool CUT>
 __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* sj, T* sS,
+                                           unsigned long long* sdef, int* slist,
                                            const Q4<T>* __restrict__ P,
                                            const Q4<T>* __restrict__ Gx,
                                            unsigned long long* __restrict__ I_fx,
                                            int* __restrict__ ovf, unsigned long long tmask, T cR)
 {
+    // DEFER (FP32, one row, all pairs): overlapping pairs are marked during
+    // the walk and evaluated afterwards in packed rounds, as in the chain pass
+    constexpr bool DEFER = sizeof(T) == 4 && R == 1 && !CUT;
     T xi[R], yi[R], zi[R], rti[R], Si[R];
     bool vi[R];
 #pragma unroll
@@ -916,14 +946,21 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
         T aj[1];
         struct JD { Q4<T> p; T S; };
         auto load = [&](int s) { return JD{sj[s], sS[s]}; };
+        int kstep = J == w.I ? 1 : 0;           // DEFER: walk step of the next pair
+        unsigned long long dmask = 0ull;
         auto pair = [&](const JD& d, int r, bool act, T (&acc)[1]) {
             T hij, hji;
-            if constexpr (CUT)
+            if constexpr (CUT) {
                 radii_pair_cut(xi[r], yi[r], zi[r], d.p.x, d.p.y, d.p.z, rti[r], Si[r], d.p.w, d.S,
                                cR, hij, hji);
-            else
+            } else if constexpr (DEFER) {
+                radii_pair_fast(xi[r], yi[r], zi[r], d.p.x, d.p.y, d.p.z, rti[r], Si[r], d.p.w, d.S,
+                                act && vi[r], 1ull << kstep, hij, hji, dmask);
+                ++kstep;
+            } else {
                 radii_pair(xi[r], yi[r], zi[r], d.p.x, d.p.y, d.p.z, rti[r], Si[r], d.p.w, d.S, hij,
                            hji);
+            }
             ai[r] += act ? hij : T(0);
             acc[0] += act ? hji : T(0);
         };
@@ -931,7 +968,59 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
             walk_tile<T, 1>(lane, J == w.I, aj, load, pair);
         else
             walk_tile_rows2<T, 1>(lane, aj, load, pair);
-        const long long hj = to_fixed(aj[0], kScaleI, bad);
+        // DEFER: packed rounds of the marked pairs (see chain_item): j-side
+        // terms through LDS integer atomics, i-side terms back to the i lane
+        bool deferred = false;
+        if constexpr (DEFER) {
+            deferred = __builtin_amdgcn_ballot_w64(dmask != 0ull) != 0ull;
+            if (deferred) {
+                sdef[lane] = 0ull;
+                wave_sync();
+                for (;;) {
+                    const int cnt = __builtin_popcountll(dmask);
+                    int incl = cnt;
+#pragma unroll
+                    for (int dd = 1; dd < kTile; dd <<= 1) {
+                        const int o = from_lane_i(incl, (lane - dd) & (kTile - 1));
+                        incl += lane >= dd ? o : 0;
+                    }
+                    const int total = __builtin_amdgcn_readlane(incl, kTile - 1);
+                    if (total == 0) break;
+                    const int o0 = incl - cnt;
+                    const int n = o0 < kTile ? min(cnt, kTile - o0) : 0;
+                    for (int t = o0; t < o0 + n; ++t) {
+                        const int k = __builtin_ctzll(dmask);
+                        dmask &= dmask - 1ull;
+                        slist[t] = (lane << 8) | k;
+                    }
+                    wave_sync();
+                    T iv = T(0);
+                    if (lane < total) {
+                        const int e = slist[lane], il = e >> 8, k = e & 0xff;
+                        const int gi = w.base + w.I * kTile + il;
+                        const Q4<T> pi = P[gi];
+                        const Q4<T> gxi = Gx[gi];       // rt, S
+                        const JD d = load(il + k);
+                        const T dx = pi.x - d.p.x, dy = pi.y - d.p.y, dz = pi.z - d.p.z;
+                        const T r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        const T invr = rsq(r2);
+                        const T rr = r2 * invr;
+                        iv = hct_slow32<false>(rr, invr, gxi.x, d.S, nullptr);           // H(r; rt_i, S_j)
+                        const T hv = hct_slow32<false>(rr, invr, d.p.w, gxi.y, nullptr); // H(r; rt_j, S_i)
+                        atomicAdd(&sdef[(il + k) & (kTile - 1)],
+                                  (unsigned long long)to_fixed(hv, kScaleI, bad));
+                    }
+                    for (int u = 0; __builtin_amdgcn_ballot_w64(u < n) != 0ull; ++u) {
+                        const T v = from_lane(iv, min(o0 + u, kTile - 1));
+                        if (u < n) ai[0] += v;
+                    }
+                    wave_sync();
+                }
+            }
+        }
+        long long hj = to_fixed(aj[0], kScaleI, bad);
+        if constexpr (DEFER)
+            if (deferred) hj += (long long)sdef[lane];
         fx_add(&I_fx[w.base + clamp_atom(j, w.n)], vj ? hj : 0ll);
 #pragma unroll
         for (int r = 0; r < R; ++r) ifix[r] += to_fixed(ai[r], kScaleI, bad);
@@ -970,6 +1059,10 @@ __global__ __launch_bounds__(kTile * W) void k_radii_pairs(
 {
     __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, rt
     __shared__ T sS_w[W][2 * kTile];
+    // deferred pairs (FP32 all-pairs walk only): j-side sums, round list
+    constexpr int NL = (sizeof(T) == 4 && !CUT) ? kTile : 1;
+    __shared__ unsigned long long sd_w[W][NL];
+    __shared__ int sl_w[W][NL];
     const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
     // the descreening pass runs one-row items only (its two-row form was
     // slower: fewer waves in flight for less saved work)
@@ -978,13 +1071,15 @@ __global__ __launch_bounds__(kTile * W) void k_radii_pairs(
         for (int it = blockIdx.x * W + wave; it < n; it += gridDim.x * W) {
             unsigned long long m;
             const WorkItem w = cut_work_item(citems[it], m);
-            radii_item<T, 1, true>(w, lane, sj_w[wave], sS_w[wave], P, Gx, I_fx, ovf, m, cR);
+            radii_item<T, 1, true>(w, lane, sj_w[wave], sS_w[wave], sd_w[wave], sl_w[wave], P, Gx,
+                                   I_fx, ovf, m, cR);
         }
     } else {
         const int item = blockIdx.x * W + wave;
         if (item >= n_items) return;
         const WorkItem w = items[item];
-        radii_item<T, 1, false>(w, lane, sj_w[wave], sS_w[wave], P, Gx, I_fx, ovf, 0ull, cR);
+        radii_item<T, 1, false>(w, lane, sj_w[wave], sS_w[wave], sd_w[wave], sl_w[wave], P, Gx,
+                                I_fx, ovf, 0ull, cR);
     }
 }
 
