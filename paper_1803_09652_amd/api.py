@@ -62,7 +62,7 @@ def _f64p(a: np.ndarray):
 
 
 # the library's default work shapes (radii, energy, chain) per precision
-DEFAULT_SHAPE = {"fp32": {"j_blocks_per_item": (1, 1, 1), "waves_per_group": (4, 8, 1)},
+DEFAULT_SHAPE = {"fp32": {"j_blocks_per_item": (1, 1, 1), "waves_per_group": (1, 8, 4)},
                  "fp64": {"j_blocks_per_item": (1, 1, 1), "waves_per_group": (2, 2, 2)}}
 
 

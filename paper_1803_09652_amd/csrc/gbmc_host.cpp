@@ -40,7 +40,7 @@ constexpr int64_t kTimedMax = 256;   // launches kept per timed kernel between r
 // Default work shapes (radii, energy, chain), the fastest measured for batches
 // of tens of thousands of atoms: the energy pass keeps two-tile items, which
 // halve its seven i-side flushes per tile.
-const gbmc_tuning kDefaultTuning32 = {{1, 1, 1}, {4, 8, 1}};
+const gbmc_tuning kDefaultTuning32 = {{1, 1, 1}, {1, 8, 4}};
 const gbmc_tuning kDefaultTuning64 = {{1, 1, 1}, {2, 2, 2}};
 
 }  // namespace
