@@ -256,6 +256,20 @@ def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial", 
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms_step = ev0.elapsed_time(ev1) / steps
+    # run-to-run spread: further steps, each bracketed by its own events
+    # (the rate above is the mean over the back-to-back timed region)
+    n_spread = min(50, steps)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(n_spread)]
+    for a, b in evs:
+        a.record()
+        one()
+        b.record()
+    torch.cuda.synchronize()
+    per = sorted(a.elapsed_time(b) for a, b in evs)
+    w.step_spread = ({"reps": n_spread, "median": per[n_spread // 2],
+                      "p10": per[n_spread // 10], "p90": per[(9 * n_spread) // 10],
+                      "min": per[0], "max": per[-1]} if n_spread else None)
     # per-kernel durations: eager steps on this stream, each hot-path kernel
     # launched with HIP start/stop events bound to its dispatch
     # (back to back, no host synchronisation until the read, like the timed
@@ -650,6 +664,7 @@ def main():
         },
         "mc_dE_evals_per_s": n_cand / (ms_step * 1e-3),
         "wall_ms_per_step": wall_ms,
+        "ms_per_step_spread": w.step_spread,
         "kernel_ms": kms,
     }
     alone = w.mc_alone_ms
