@@ -564,6 +564,49 @@ def cpu_baseline(systems, min_wall_s=1.5, max_passes=8):
                       f"(~{dt * cores:.0f} core-s)"}
 
 
+def cpu_oracle_detail(reps=3):
+    """The oracle on the host at the single-system sizes: one full evaluation
+    (radii, energy, forces, dE/dq, dE/drho; plus every candidate Delta E where
+    the system has sites) of the 256-, 2,500- and 10,000-atom systems, single
+    threaded and with OpenMP on every core, median of `reps` (one rep for the
+    10,000-atom system single threaded), with the host's core count and CPU
+    model."""
+    import ctypes
+    import statistics
+    import oracle
+    import synth
+    oracle.lib()
+    gomp = ctypes.CDLL("libgomp.so.1")
+    n_all = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
+    except OSError:
+        pass
+    out = {"kind": "oracle", "unit": "pair interactions/s", "nproc": os.cpu_count(),
+           "threads_all": n_all, "cpu_model": model, "systems": {}}
+    for name, sys_ in (("256 atoms", synth.config0()[0]), ("2500 atoms", synth.config1()[0]),
+                       ("10000 atoms", synth.config3()[0])):
+        pairs = sys_.n * (sys_.n - 1) // 2
+        res = {}
+        for label, nt in (("single_thread", 1), ("all_threads", n_all)):
+            gomp.omp_set_num_threads(nt)
+            k = 1 if (nt == 1 and sys_.n > 5000) else reps
+            ts = []
+            for _ in range(k):
+                t0 = time.perf_counter()
+                r = oracle.energy_forces(sys_)
+                if sys_.sites:
+                    oracle.site_dE(sys_, r["R"])
+                ts.append(time.perf_counter() - t0)
+            res[label] = {"value": pairs / statistics.median(ts), "reps": k,
+                          "median_s": statistics.median(ts)}
+        out["systems"][name] = res
+    gomp.omp_set_num_threads(n_all)
+    return out
+
+
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "hbm_counters_pair_kernels_ereMD_16x2500.md")
 
 
@@ -717,6 +760,7 @@ def main():
     if not args.no_cpu_baseline:
         import synth
         out["cpu_baseline"] = cpu_baseline(synth.config2())
+        out["cpu_oracle_detail"] = cpu_oracle_detail()
     print(json.dumps(out), flush=True)
 
 
