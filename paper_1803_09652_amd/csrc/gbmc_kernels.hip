@@ -425,6 +425,78 @@ __device__ __forceinline__ void chain_pair(double r, double r2, double invr, dou
     dEdr = -u * fma(bi, aij, bj * aji);
 }
 
+// FP64 forms of the two deferring pair functions (polynomial of degree 14 on
+// y <= 0.25; the pairs outside it are marked, as in FP32).
+__device__ __forceinline__ void radii_pair_fast(double xi, double yi, double zi, double xj,
+                                                double yj, double zj, double rti, double Si,
+                                                double rtj, double Sj, bool act,
+                                                unsigned long long bit, double& hij, double& hji,
+                                                unsigned long long& mask)
+{
+    double r, invr;
+    dist64(xi, yi, zi, xj, yj, zj, r, invr);
+    const double xij = Sj * invr, yij = xij * xij;
+    const double xji = Si * invr, yji = xji * xji;
+    hij = xij * yij * invr * hct_poly64(yij);
+    hji = xji * yji * invr * hct_poly64(yji);
+    const bool fast = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX64) & (r - Si >= rtj) &
+                      (yji <= GBMC_HCT_YMAX64);
+    if (__builtin_amdgcn_ballot_w64(!fast) != 0ull) {
+        asm volatile("");                       // keeps this a branch
+        hij = fast ? hij : 0.0;
+        hji = fast ? hji : 0.0;
+        mask |= (!fast && act) ? bit : 0ull;
+    }
+}
+
+__device__ __forceinline__ void chain_pair_fast(double r, double invr, double rti, double Si,
+                                                double rtj, double Sj, double bi, double bj,
+                                                bool act, unsigned long long bit, double& dEdr,
+                                                double& gij2, double& gji2,
+                                                unsigned long long& mask)
+{
+    const double u = invr * invr;
+    const double xij = Sj * invr, yij = xij * xij;
+    const double xji = Si * invr, yji = xji * xji;
+    double wij = rcp64(1.0 - yij), wji = rcp64(1.0 - yji);
+    wij *= wij;
+    wji *= wji;
+    double aij = xij * yij * (hct_poly64(yij) + wij);    // -r^2 dH/dr
+    double aji = xji * yji * (hct_poly64(yji) + wji);
+    gij2 = yij * wij * u;
+    gji2 = yji * wji * u;
+    const bool fast = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX64) & (r - Si >= rtj) &
+                      (yji <= GBMC_HCT_YMAX64);
+    if (__builtin_amdgcn_ballot_w64(!fast) != 0ull) {
+        asm volatile("");
+        aij = fast ? aij : 0.0;
+        aji = fast ? aji : 0.0;
+        gij2 = fast ? gij2 : 0.0;
+        gji2 = fast ? gji2 : 0.0;
+        mask |= (!fast && act) ? bit : 0ull;
+    }
+    dEdr = -u * fma(bi, aij, bj * aji);
+}
+
+// The closed form of H and of its partials (dH/dr, dH/drt, dH/dS) in either
+// precision, for the deferred pairs.
+__device__ __forceinline__ float slow_H(float r, float invr, float rt, float S)
+{
+    return hct_slow32<false>(r, invr, rt, S, nullptr);
+}
+__device__ __forceinline__ double slow_H(double r, double invr, double rt, double S)
+{
+    return hct_general(r, invr, rt, S);
+}
+__device__ __forceinline__ void slow_grad(float r, float invr, float rt, float S, float* g)
+{
+    hct_slow32<true>(r, invr, rt, S, g);
+}
+__device__ __forceinline__ void slow_grad(double r, double invr, double rt, double S, double* g)
+{
+    hct_general_grad(r, invr, rt, S, g[0], g[1], g[2]);
+}
+
 // ------------------------------------------------------- cutoff variants
 // With the descreening cutoff c the integral is restricted to the sphere of
 // radius c around atom i: H_c = H(r; rt, S) - H(r; c, S) for a ball j that
@@ -877,9 +949,9 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
                                            unsigned long long* __restrict__ I_fx,
                                            int* __restrict__ ovf, unsigned long long tmask, T cR)
 {
-    // DEFER (FP32, one row, all pairs): overlapping pairs are marked during
+    // DEFER (one row, all pairs): overlapping pairs are marked during
     // the walk and evaluated afterwards in packed rounds, as in the chain pass
-    constexpr bool DEFER = sizeof(T) == 4 && R == 1 && !CUT;
+    constexpr bool DEFER = R == 1 && !CUT;
     T xi[R], yi[R], zi[R], rti[R], Si[R];
     bool vi[R];
 #pragma unroll
@@ -1002,11 +1074,11 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
                         const Q4<T> gxi = Gx[gi];       // rt, S
                         const JD d = load(il + k);
                         const T dx = pi.x - d.p.x, dy = pi.y - d.p.y, dz = pi.z - d.p.z;
-                        const T r2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                        const T r2 = dx * dx + dy * dy + dz * dz;
                         const T invr = rsq(r2);
                         const T rr = r2 * invr;
-                        iv = hct_slow32<false>(rr, invr, gxi.x, d.S, nullptr);           // H(r; rt_i, S_j)
-                        const T hv = hct_slow32<false>(rr, invr, d.p.w, gxi.y, nullptr); // H(r; rt_j, S_i)
+                        iv = slow_H(rr, invr, gxi.x, d.S);              // H(r; rt_i, S_j)
+                        const T hv = slow_H(rr, invr, d.p.w, gxi.y);    // H(r; rt_j, S_i)
                         atomicAdd(&sdef[(il + k) & (kTile - 1)],
                                   (unsigned long long)to_fixed(hv, kScaleI, bad));
                     }
@@ -1059,8 +1131,8 @@ __global__ __launch_bounds__(kTile * W) void k_radii_pairs(
 {
     __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, rt
     __shared__ T sS_w[W][2 * kTile];
-    // deferred pairs (FP32 all-pairs walk only): j-side sums, round list
-    constexpr int NL = (sizeof(T) == 4 && !CUT) ? kTile : 1;
+    // deferred pairs (all-pairs walk only): j-side sums, round list
+    constexpr int NL = !CUT ? kTile : 1;
     __shared__ unsigned long long sd_w[W][NL];
     __shared__ int sl_w[W][NL];
     const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
@@ -1419,14 +1491,14 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
                                            const T* __restrict__ Brt, const Work<T>& wk, T cR,
                                            unsigned long long tmask)
 {
-    // DEFER (FP32, one row, all pairs): the walk evaluates the polynomial form
+    // DEFER (one row, all pairs): the walk evaluates the polynomial form
     // only and marks the pairs that need the closed form (overlapping spheres)
     // in a per-lane mask of walk steps; after the walk the marked pairs are
     // evaluated packed, one per lane per round, instead of with most of the
     // wave masked off in the step that met them.  Their j-side terms go to the
     // j atoms through LDS int64 fixed-point atomics (exact, so the result does
     // not depend on the order of the rounds).
-    constexpr bool DEFER = sizeof(T) == 4 && R == 1 && !CUT;
+    constexpr bool DEFER = R == 1 && !CUT;
     T xi[R], yi[R], zi[R], rti[R], Si[R], Bi[R], si[R];
     bool vi[R];
 #pragma unroll
@@ -1588,15 +1660,15 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
                         const T invr = rsq(r2);
                         const T rr = r2 * invr;
                         T ga[3], gb[3];
-                        hct_slow32<true>(rr, invr, gxi.x, b.x, ga);     // H(r; rt_i, S_j)
-                        hct_slow32<true>(rr, invr, p.w, gxi.y, gb);     // H(r; rt_j, S_i)
+                        slow_grad(rr, invr, gxi.x, b.x, ga);            // H(r; rt_i, S_j)
+                        slow_grad(rr, invr, p.w, gxi.y, gb);            // H(r; rt_j, S_i)
                         const T bj_ = b.y;
                         // dE/dr = bi dH_ij/dr + bj dH_ji/dr
-                        const T fr = fmaf(bi_, ga[0], bj_ * gb[0]) * invr;
+                        const T fr = T(fma(bi_, ga[0], bj_ * gb[0])) * invr;
                         const T fx = fr * dx, fy = fr * dy, fz = fr * dz;
                         iv[0] = -fx; iv[1] = -fy; iv[2] = -fz;
-                        iv[3] = fmaf(bi_, ga[1], gxi.z * bj_ * gb[2]);
-                        const T jv[4] = {fx, fy, fz, fmaf(b.z * bi_, ga[2], bj_ * gb[1])};
+                        iv[3] = T(fma(bi_, ga[1], gxi.z * bj_ * gb[2]));
+                        const T jv[4] = {fx, fy, fz, T(fma(b.z * bi_, ga[2], bj_ * gb[1]))};
                         const int jl = (il + k) & (kTile - 1);
 #pragma unroll
                         for (int a = 0; a < 4; ++a)
@@ -1667,9 +1739,9 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
 {
     __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, rt
     __shared__ Q4<T> sb_w[W][2 * kTile];     // S, B rt, screen, -
-    // deferred pairs (FP32 all-pairs walk only): j-side sums, round list
-    constexpr int ND = (sizeof(T) == 4 && !CUT) ? 4 * kTile : 1;
-    constexpr int NL = (sizeof(T) == 4 && !CUT) ? kTile : 1;
+    // deferred pairs (all-pairs walk only): j-side sums, round list
+    constexpr int ND = !CUT ? 4 * kTile : 1;
+    constexpr int NL = !CUT ? kTile : 1;
     __shared__ unsigned long long sd_w[W][ND];
     __shared__ int sl_w[W][NL];
     const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
