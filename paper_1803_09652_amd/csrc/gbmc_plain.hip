@@ -205,20 +205,36 @@ __global__ __launch_bounds__(256) void k_plain_chain(int N, int B, const int32_t
                   + Ba * (I[a] + rta * drt) + scr[a] * dS;
 }
 
-// Per-system energies: the atoms' shares summed in index order by one thread.
-__global__ void k_plain_energy_sum(int B, const int32_t* __restrict__ off, int N,
-                                   const double* __restrict__ e_share, double* __restrict__ e_coul,
-                                   double* __restrict__ e_gb)
+// Per-system energies: one workgroup per system; each thread sums the shares
+// of atoms tid, tid + 256, ... in index order, then a fixed tree over the 256
+// partial sums (the same order on every run).
+__global__ __launch_bounds__(256) void k_plain_energy_sum(int B, const int32_t* __restrict__ off,
+                                                          int N,
+                                                          const double* __restrict__ e_share,
+                                                          double* __restrict__ e_coul,
+                                                          double* __restrict__ e_gb)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= B) return;
+    __shared__ double sc[256], sg[256];
+    const int b = blockIdx.x, t = threadIdx.x;
     double ec = 0.0, eg = 0.0;
-    for (int i = off[b]; i < off[b + 1]; ++i) {
+    for (int i = off[b] + t; i < off[b + 1]; i += 256) {
         ec += e_share[i];
         eg += e_share[N + i];
     }
-    if (e_coul) e_coul[b] = ec;
-    if (e_gb) e_gb[b] = eg;
+    sc[t] = ec;
+    sg[t] = eg;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+            sc[t] += sc[t + h];
+            sg[t] += sg[t + h];
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        if (e_coul) e_coul[b] = sc[0];
+        if (e_gb) e_gb[b] = sg[0];
+    }
 }
 
 }  // namespace
@@ -249,8 +265,7 @@ hipError_t launch_plain_fp64(int B, const int32_t* off, int N, const double* x, 
         hipLaunchKernelGGL(k_plain_chain, dim3(nb), dim3(256), 0, s, N, B, off, x, y, z, rho, scr, I,
                            R, T, dR, G, pc, F, phi, force, dEdq, dEdrho);
     }
-    hipLaunchKernelGGL(k_plain_energy_sum, dim3((B + 255) / 256), dim3(256), 0, s, B, off, N, es,
-                       e_coul, e_gb);
+    hipLaunchKernelGGL(k_plain_energy_sum, dim3(B), dim3(256), 0, s, B, off, N, es, e_coul, e_gb);
     return hipGetLastError();
 }
 
