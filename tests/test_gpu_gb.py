@@ -114,6 +114,28 @@ def test_fp32_bitwise_deterministic_and_shape_independent():
             assert np.array_equal(o[k], outs[0][k]), k
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_overlap_heavy_tiles_shape_independent(prec):
+    # nearly every pair overlaps (150 atoms within 6 A, large screened radii):
+    # the deferred pairs fill several packed rounds per tile, and the result
+    # must not depend on the work shape (items of one or many tiles, waves per
+    # group) and must match the oracle
+    p_gpu, p_or = params_pair()
+    s = synth.make_system(7, 150, 6.0, min_dist=0.3)
+    s.rho = synth.f32(np.random.default_rng(1).uniform(0.8, 2.6, s.n))
+    s.screen = synth.f32(np.random.default_rng(2).uniform(0.6, 0.99, s.n))
+    dense = synth.make_system(8, 900, 9.0, min_dist=0.6)
+    outs = []
+    for jb, wv in ((1, 1), (8, 4), (2, 8)):
+        g, batch, plan, atoms = build([s, dense], prec, j_blocks=jb, waves=wv)
+        outs.append(gpu_eval(plan, atoms, p_gpu))
+    for o in outs[1:]:
+        for k in ("R", "Ec", "Egb", "force", "dEdq", "dEdrho"):
+            assert np.array_equal(o[k], outs[0][k]), k
+    ref = oracle_eval(s, p_or)
+    print(prec, compare_system(outs[0], 0, batch.atom_offset, ref, prec))
+
+
 def test_batch_equals_single_systems_bitwise():
     p_gpu, _ = params_pair()
     systems = [_sys(21, 90), _sys(22, 640), _sys(23, 129), _sys(24, 1)]
