@@ -117,7 +117,7 @@ class Workload:
         import paper_1803_09652_amd as g
         import synth
         self.g, self.torch = g, torch
-        self.systems = systems if systems is not None else synth.config2()
+        self.systems = systems if systems is not None else synth.eremd_batch()
         self.exchange = exchange
         self.batch = b = synth.make_batch(self.systems)
         self.B = b.n_systems
@@ -207,7 +207,7 @@ def autotune(precision, order):
     import paper_1803_09652_amd as g
     from paper_1803_09652_amd import autotune as at
     import synth
-    b = synth.make_batch(synth.config2())
+    b = synth.make_batch(synth.eremd_batch())
     o = g.spatial_order(b.atom_offset, b.x, b.y, b.z) if order == "spatial" else None
     return at.tune(b, precision, order=o, use_cache=False)
 
@@ -449,7 +449,7 @@ def time_uneven_batch(steps=20, warmup=3, fp64_steps=5, tune=True):
     import paper_1803_09652_amd as g
     from paper_1803_09652_amd import autotune as at
     import synth
-    systems = synth.config4()
+    systems = synth.uneven_batch_64()
     n = np.array([s_.n for s_ in systems])
     pairs = int((n * (n - 1) // 2).sum())
     out = {"workload": f"{len(systems)} systems, {int(n.min())}-{int(n.max())} atoms "
@@ -501,7 +501,7 @@ def time_md_loop(steps, warmup, n_rep=16, attempt_every=5, exchange_every=10):
     import paper_1803_09652_amd as g
     import synth
     from paper_1803_09652_amd.runtime import ReplicaMD
-    systems = synth.config2_md(n_rep)
+    systems = synth.eremd_batch_md(n_rep)
     b = synth.make_batch(systems)
     plan = g.Plan(b.atom_offset, "fp32")
     plan.set_order(g.spatial_order(b.atom_offset, b.x, b.y, b.z))
@@ -586,8 +586,8 @@ def cpu_oracle_detail(reps=3):
         pass
     out = {"kind": "oracle", "unit": "pair interactions/s", "nproc": os.cpu_count(),
            "threads_all": n_all, "cpu_model": model, "systems": {}}
-    for name, sys_ in (("256 atoms", synth.config0()[0]), ("2500 atoms", synth.config1()[0]),
-                       ("10000 atoms", synth.config3()[0])):
+    for name, sys_ in (("256 atoms", synth.globule_256()[0]), ("2500 atoms", synth.globule_2500()[0]),
+                       ("10000 atoms", synth.globule_10000()[0])):
         pairs = sys_.n * (sys_.n - 1) // 2
         res = {}
         for label, nt in (("single_thread", 1), ("all_threads", n_all)):
@@ -759,7 +759,7 @@ def main():
         out["copy_calibration"] = copy_ref
     if not args.no_cpu_baseline:
         import synth
-        out["cpu_baseline"] = cpu_baseline(synth.config2())
+        out["cpu_baseline"] = cpu_baseline(synth.eremd_batch())
         out["cpu_oracle_detail"] = cpu_oracle_detail()
     print(json.dumps(out), flush=True)
 

@@ -247,31 +247,31 @@ PH_DEFAULT = 7.0
 T_DEFAULT = 300.0
 
 
-def config0() -> List[System]:
+def globule_256() -> List[System]:
     return [make_system(0, 256, 12.0, n_redox=1, n_prot=0)]
 
 
-def config1() -> List[System]:
+def globule_2500() -> List[System]:
     return [make_system(1, 2500, 18.0, n_redox=4, n_prot=4)]
 
 
-def config2(n_rep: int = 16) -> List[System]:
-    base = config1()[0]
+def eremd_batch(n_rep: int = 16) -> List[System]:
+    base = globule_2500()[0]
     return [perturb(base, 2 + 1000 * r) for r in range(n_rep)]
 
 
 # Dynamics on the electrostatics alone: the globules carry no bonded or van der
 # Waals terms and no exclusions, so every atom is held near its start by a
 # harmonic restraint of this stiffness (kcal/mol/A^2), stiff enough that no
-# oppositely charged close pair of the config-1 globule can collapse.
+# oppositely charged close pair of the 2,500-atom globule can collapse.
 MD_RESTRAINT = 2000.0
 
 
-def config2_md(n_rep: int = 16) -> List[System]:
-    """E-REMD replicas for dynamics: the config-1 globule unperturbed (the
+def eremd_batch_md(n_rep: int = 16) -> List[System]:
+    """E-REMD replicas for dynamics: the 2,500-atom globule unperturbed (the
     perturbed replicas hold pairs closer than any restraint can keep apart),
     each replica with its own random site states."""
-    base = config1()[0]
+    base = globule_2500()[0]
     out = []
     for r in range(n_rep):
         rng = rng_for(5 + 1000 * r)
@@ -283,11 +283,11 @@ def config2_md(n_rep: int = 16) -> List[System]:
     return out
 
 
-def config3() -> List[System]:
+def globule_10000() -> List[System]:
     return [make_system(3, 10000, 26.0)]
 
 
-def config4_sizes(n_sys: int = 64):
+def uneven_batch_sizes(n_sys: int = 64):
     rng = rng_for(4)
     out = []
     for _ in range(n_sys):
@@ -304,20 +304,21 @@ def config4_sizes(n_sys: int = 64):
     return out
 
 
-def config4(n_sys: int = 64) -> List[System]:
+def uneven_batch_64(n_sys: int = 64) -> List[System]:
     systems = []
-    for b, (n, n_redox, n_prot) in enumerate(config4_sizes(n_sys)):
+    for b, (n, n_redox, n_prot) in enumerate(uneven_batch_sizes(n_sys)):
         r_glob = 18.0 * (n / 2500.0) ** (1.0 / 3.0)
         systems.append(make_system(4 + 1000 * b, n, r_glob, n_redox=n_redox, n_prot=n_prot,
                                    random_states=True))
     return systems
 
 
-CONFIGS = {0: config0, 1: config1, 2: config2, 3: config3, 4: config4}
+WORKLOADS = {"globule_256": globule_256, "globule_2500": globule_2500, "eremd_batch": eremd_batch,
+             "globule_10000": globule_10000, "uneven_batch_64": uneven_batch_64}
 
 
-def config(idx: int, **kw) -> List[System]:
-    return CONFIGS[idx](**kw)
+def workload(name: str, **kw) -> List[System]:
+    return WORKLOADS[name](**kw)
 
 
 # --------------------------------------------------------------------------

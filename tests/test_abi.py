@@ -147,15 +147,15 @@ def _sites_args(batch):
 
 def test_sites_validation(L):
     lib = L.load()
-    batch = synth.make_batch(synth.config2(n_rep=3))
+    batch = synth.make_batch(synth.eremd_batch(n_rep=3))
     assert lib.gbmc_sites_validate(*_sites_args(batch)) == L.GBMC_OK
     # overlapping sites
-    b2 = synth.make_batch(synth.config2(n_rep=3))
+    b2 = synth.make_batch(synth.eremd_batch(n_rep=3))
     b2.site_atoms[b2.site_atom_offset[1]] = b2.site_atoms[0]
     assert lib.gbmc_sites_validate(*_sites_args(b2)) == L.GBMC_ERR_INVALID
     assert b"overlap" in lib.gbmc_last_error()
     # atom outside its system
-    b3 = synth.make_batch(synth.config2(n_rep=3))
+    b3 = synth.make_batch(synth.eremd_batch(n_rep=3))
     b3.site_atoms[0] = b3.atom_offset[2] + 1
     assert lib.gbmc_sites_validate(*_sites_args(b3)) == L.GBMC_ERR_INVALID
     # a one-state site
@@ -168,7 +168,7 @@ def test_sites_validation(L):
     big = synth.make_system(2, 400, 12.0, n_redox=1, redox_atoms=300)
     assert lib.gbmc_sites_validate(*_sites_args(synth.make_batch([big]))) == L.GBMC_ERR_UNSUPPORTED
     # systems out of order
-    b5 = synth.make_batch(synth.config2(n_rep=3))
+    b5 = synth.make_batch(synth.eremd_batch(n_rep=3))
     b5.site_system[0] = 2
     assert lib.gbmc_sites_validate(*_sites_args(b5)) == L.GBMC_ERR_INVALID
 
@@ -193,7 +193,7 @@ def test_entry_points_reject_null_plan(L):
 
 def test_spatial_order_is_a_local_permutation(L):
     lib = L.load()
-    systems = synth.config2(n_rep=3)
+    systems = synth.eremd_batch(n_rep=3)
     batch = synth.make_batch(systems)
     off = batch.atom_offset
     out = np.zeros(batch.n_atoms, dtype=np.int32)

@@ -34,10 +34,10 @@ def _inputs(systems, precision, requires_grad=True):
     return g, batch, plan, pos, q, rho, scr
 
 
-def test_config3_forward_and_gradients_against_oracle():
+def test_globule_10000_forward_and_gradients_against_oracle():
     # one 10,000-atom globule, FP32-fixed forward and backward
     p_gpu, p_or = params_pair()
-    systems = synth.config3()
+    systems = synth.globule_10000()
     g, batch, plan, pos, q, rho, scr = _inputs(systems, "fp32")
     E = g.GBEnergy.apply(pos, q, rho, scr, plan, p_gpu)
     gE = 0.75

@@ -55,7 +55,7 @@ def _pair(rgbmax, cutoff):
                                               ("fp32", "blocks", 0.0), ("fp32", "blocks", 0.1)])
 def test_cutoff_batch_parity(prec, order, kappa):
     systems = [synth.make_system(120, 1, 2.0), synth.make_system(121, 65, 5.0),
-               synth.make_system(122, 300, 8.5)] + synth.config1()
+               synth.make_system(122, 300, 8.5)] + synth.globule_2500()
     cut = _cutoff_in_gap(systems, 10.0, 10.5)
     p_gpu, p_or = _pair(12.0, cut)
     p_gpu, p_or = dataclasses.replace(p_gpu, kappa=kappa), dataclasses.replace(p_or, kappa=kappa)
@@ -75,7 +75,7 @@ def test_cutoff_batch_parity(prec, order, kappa):
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_cutoff_state_dE_parity(prec):
-    systems = synth.config2(n_rep=3)
+    systems = synth.eremd_batch(n_rep=3)
     cut = _cutoff_in_gap(systems, 8.0, 8.5)
     p_gpu, p_or = _pair(10.0, cut)
     g, batch, plan, atoms = build(systems, prec)
@@ -115,7 +115,7 @@ def test_cutoff_large_globule_fp32():
 def test_cutoff_sweep_fp64():
     # the sequential sweep with the pair cutoff (potential rows, K_SS and the
     # K dq updates after each accepted visit) against the oracle's sweep
-    systems = synth.config2(n_rep=3)
+    systems = synth.eremd_batch(n_rep=3)
     cut = _cutoff_in_gap(systems, 9.0, 9.5)
     p_gpu, p_or = _pair(11.0, cut)
     g, batch, plan, atoms = build(systems, "fp64")

@@ -24,9 +24,9 @@ def _sys(seed, n, r=None, **kw):
 
 @pytest.mark.parametrize("prec", PRECS)
 @pytest.mark.parametrize("pname", ["IGB5", "IGB2"])
-def test_config0_parity(prec, pname):
+def test_globule_256_parity(prec, pname):
     p_gpu, p_or = params_pair(pname)
-    systems = synth.config0()
+    systems = synth.globule_256()
     g, batch, plan, atoms = build(systems, prec)
     res = gpu_eval(plan, atoms, p_gpu)
     ref = oracle_eval(systems[0], p_or, ("c0", pname))
@@ -35,9 +35,9 @@ def test_config0_parity(prec, pname):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_config1_parity(prec):
+def test_globule_2500_parity(prec):
     p_gpu, p_or = params_pair()
-    systems = synth.config1()
+    systems = synth.globule_2500()
     g, batch, plan, atoms = build(systems, prec)
     res = gpu_eval(plan, atoms, p_gpu)
     ref = oracle_eval(systems[0], p_or, ("c1", "IGB5"))
@@ -74,10 +74,10 @@ def test_engulfed_and_overlapping_pairs():
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_config2_batch_all_replicas(prec):
+def test_eremd_batch_all_replicas(prec):
     # the E-REMD batch (16 x 2500) in the benchmark's launch configuration
     p_gpu, p_or = params_pair()
-    systems = synth.config2()
+    systems = synth.eremd_batch()
     g, batch, plan, atoms = build(systems, prec)
     res = gpu_eval(plan, atoms, p_gpu)
     worst = {}
@@ -88,11 +88,11 @@ def test_config2_batch_all_replicas(prec):
     print(prec, worst)
 
 
-def test_config4_uneven_batch_sampled_systems():
+def test_uneven_batch_sampled_systems():
     # the uneven 64-system batch runs in one launch; the smallest, the largest
     # and one middle system are compared on every atom
     p_gpu, p_or = params_pair()
-    systems = synth.config4()
+    systems = synth.uneven_batch_64()
     sizes = np.array([s.n for s in systems])
     pick = [int(np.argmin(sizes)), int(np.argmax(sizes)), int(np.argsort(sizes)[len(sizes) // 2])]
     g, batch, plan, atoms = build(systems, "fp32")

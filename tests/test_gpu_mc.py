@@ -41,14 +41,15 @@ def _gpu_dE(g, plan, sites, atoms, batch, pH, E, T, params):
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-@pytest.mark.parametrize("cfg", [0, 1, 2])
+@pytest.mark.parametrize("cfg", ["globule_256", "globule_2500", "eremd_batch"])
 def test_state_dE_and_dG_parity(prec, cfg):
     p_gpu, p_or = params_pair()
-    systems = synth.config(cfg)
+    systems = synth.workload(cfg)
     g, batch, plan, atoms = build(systems, prec)
-    gref = _gref(batch, 5 + cfg)
+    seed = ["globule_256", "globule_2500", "eremd_batch"].index(cfg)
+    gref = _gref(batch, 5 + seed)
     sites = g.Sites.from_batch(plan, batch, gref)
-    rng = np.random.default_rng(cfg)
+    rng = np.random.default_rng(seed)
     pH = rng.uniform(3.0, 9.0, len(systems))
     E = rng.uniform(-0.4, -0.1, len(systems))
     T = 300.0
@@ -87,7 +88,7 @@ def _oracle_step(systems, slices, gref, pH, E, T, u, p_or, q_states):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_mc_step_parity(prec):
     p_gpu, p_or = params_pair()
-    systems = synth.config2()
+    systems = synth.eremd_batch()
     g, batch, plan, atoms = build(systems, prec)
     slices = _state_slices(systems)
     # Gref chosen so that the attempts are neither all accepted nor all rejected:
@@ -153,10 +154,10 @@ def _tables_with_state(s, sl, gref, states):
 
 
 def test_mc_trajectory_matches_oracle_fp64():
-    # 25 consecutive attempt pairs on config 1 (fixed coordinates): the state
+    # 25 consecutive attempt pairs on the 2,500-atom globule (fixed coordinates): the state
     # sequence, including protonation -> redox coupling, follows the oracle
     p_gpu, p_or = params_pair()
-    systems = synth.config1()
+    systems = synth.globule_2500()
     s = systems[0]
     g, batch, plan, atoms = build(systems, "fp64")
     rng = np.random.default_rng(3)
@@ -258,7 +259,7 @@ def test_full_step_graph_replay_follows_eager():
     # radii -> energy/forces -> all candidate dE -> MC step, captured once and
     # replayed; the state trajectory equals the eager one step by step
     p_gpu, _ = params_pair()
-    systems = synth.config2(n_rep=4)
+    systems = synth.eremd_batch(n_rep=4)
 
     def setup():
         g, batch, plan, atoms = build(systems, "fp32")

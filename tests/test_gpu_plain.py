@@ -43,7 +43,7 @@ def test_plain_fp64_ragged_batch(pname):
 
 def test_plain_fp64_ereMD_replicas():
     p_gpu, p_or = params_pair()
-    systems = synth.config2(n_rep=2)
+    systems = synth.eremd_batch(n_rep=2)
     b, res = _run(systems, p_gpu)
     for k, s in enumerate(systems):
         compare_system(res, k, b.atom_offset, oracle.energy_forces(s, p_or), "fp64")

@@ -153,7 +153,7 @@ def test_eremd_uncoupled_redox_site_follows_nernst():
 def test_fp32_eremd_batch_runs_in_range():
     from paper_1803_09652_amd.runtime import ReplicaMD
     p_gpu, _ = params_pair()
-    systems = synth.config2_md(n_rep=16)
+    systems = synth.eremd_batch_md(n_rep=16)
     g, batch, plan, atoms = build(systems, "fp32")
     sites = g.Sites.from_batch(plan, batch)
     N = batch.x.shape[0]

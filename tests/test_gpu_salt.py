@@ -32,7 +32,7 @@ def _salt_pair(kappa=KAPPA):
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_salt_energy_forces_parity(prec):
     p_gpu, p_or = _salt_pair()
-    systems = synth.config0() + [synth.make_system(80 + k, n, max(4.0, 18.0 * (n / 2500.0) ** (1 / 3)))
+    systems = synth.globule_256() + [synth.make_system(80 + k, n, max(4.0, 18.0 * (n / 2500.0) ** (1 / 3)))
                                  for k, n in enumerate((65, 1, 130, 300))]
     g, batch, plan, atoms = build(systems, prec)
     res = gpu_eval(plan, atoms, p_gpu)
@@ -48,7 +48,7 @@ def test_salt_energy_forces_parity(prec):
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_salt_state_dE_parity(prec):
     p_gpu, p_or = _salt_pair()
-    systems = synth.config2(n_rep=3)
+    systems = synth.eremd_batch(n_rep=3)
     g, batch, plan, atoms = build(systems, prec)
     gref = np.random.default_rng(5).normal(0.0, 20.0, batch.state_count.size)
     sites = g.Sites.from_batch(plan, batch, gref)
@@ -94,7 +94,7 @@ def _near_balance_gref(systems, p_or, T, pH, E, seed):
 
 def test_salt_step_and_sweep_fp64():
     p_gpu, p_or = _salt_pair()
-    systems = synth.config2(n_rep=4)
+    systems = synth.eremd_batch(n_rep=4)
     T, pH = 300.0, 7.0
     E = np.array(synth.E_LADDER[:4])
     gref = _near_balance_gref(systems, p_or, T, pH, E, 3)

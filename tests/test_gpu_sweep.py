@@ -42,7 +42,7 @@ def _gref_near_balance(systems, p_or, seed):
 
 def _run(prec, kinds, n_sys=6, seed=11):
     p_gpu, p_or = params_pair()
-    systems = synth.config2(n_rep=n_sys)
+    systems = synth.eremd_batch(n_rep=n_sys)
     g, batch, plan, atoms = build(systems, prec)
     gref = _gref_near_balance(systems, p_or, seed)
     sites = g.Sites.from_batch(plan, batch, gref)
@@ -107,7 +107,7 @@ def test_sweep_graph_replay_matches_eager():
     # a captured sweep (rows, potentials, sequential decisions) replayed from a
     # reset state gives the eager result bitwise, replay after replay
     p_gpu, _ = params_pair()
-    systems = synth.config2(n_rep=4)
+    systems = synth.eremd_batch(n_rep=4)
     g, batch, plan, atoms = build(systems, "fp32")
     sites = g.Sites.from_batch(plan, batch, np.zeros(batch.state_count.size))
     dev = plan.device

@@ -24,7 +24,7 @@ def one_system(xyz, q, rho, screen):
 
 @pytest.fixture(scope="module")
 def c0():
-    return synth.config0()[0]
+    return synth.globule_256()[0]
 
 
 @pytest.mark.parametrize("pname", ["IGB5", "IGB2"])

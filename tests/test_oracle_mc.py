@@ -33,7 +33,7 @@ def golden():
 
 @pytest.fixture(scope="module")
 def c1():
-    return synth.config1()[0]
+    return synth.globule_2500()[0]
 
 
 def small_system(n=60, seed=21, n_redox=1, n_prot=1, prot_states=5, redox_atoms=6,
@@ -43,8 +43,8 @@ def small_system(n=60, seed=21, n_redox=1, n_prot=1, prot_states=5, redox_atoms=
                              prot_states=prot_states, random_states=True)
 
 
-def test_bilinear_equals_brute_config0(orc):
-    s = synth.config0()[0]
+def test_bilinear_equals_brute_globule_256(orc):
+    s = synth.globule_256()[0]
     R = orc.radii(s)["R"]
     a = orc.site_dE(s, R)
     b = orc.site_dE(s, R, brute=True)
@@ -52,7 +52,7 @@ def test_bilinear_equals_brute_config0(orc):
     assert np.abs(a - b).max() <= 1e-9
 
 
-def test_bilinear_equals_brute_config1(orc, c1):
+def test_bilinear_equals_brute_globule_2500(orc, c1):
     R = orc.radii(c1)["R"]
     a = orc.site_dE(c1, R)
     b = orc.site_dE(c1, R, brute=True)
