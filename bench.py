@@ -1,15 +1,17 @@
 #!/usr/bin/env python3
 """Benchmark of the GB-OBC + Monte Carlo hot path on one MI355X.
 
-A step is one pass of the whole hot path over the E-REMD batch (16 replicas x
-2,500 atoms): Born radii, energy + forces + dE/dq + dE/drho (with the Born
-radius chain), Delta E / Delta G of every candidate state change, one
-protonation + redox Metropolis attempt per replica, and one replica-exchange
-attempt along the redox-potential ladder.  The Monte Carlo branch (it needs
-only the radii and the current charges) runs on a second stream beside the
-energy / force passes and writes its charge update into the other of two
-charge buffers.  The step is captured in a HIP graph (two graphs: even and odd
-exchange parity, which also alternate the charge buffers) and replayed.
+The headline workload is the largest single-GPU configuration: the uneven
+batch of 64 systems of 500-20,000 atoms (646,341 atoms, 4.25e9 unordered
+pairs), each with 2-10 redox and 0-20 protonation sites.  A step is one pass
+of the whole hot path over the batch: Born radii, energy + forces + dE/dq +
+dE/drho (with the Born radius chain), Delta E / Delta G of every candidate
+state change and one protonation + redox Metropolis attempt per system.  The
+Monte Carlo branch (it needs only the radii and the current charges) runs on
+a second stream beside the energy / force passes and writes its charge update
+into the other of two charge buffers; the step is captured in HIP graphs and
+replayed.  The E-REMD batch (16 replicas x 2,500 atoms on a redox-potential
+ladder, with a replica-exchange attempt every step) is reported beside it.
 
 Prints ONE JSON line.  Pair interactions/s = sum_b N_b (N_b - 1)/2 per step
 divided by the step time.
@@ -31,11 +33,13 @@ KB, FARADAY = 1.98720426e-3, 23.0605478
 E0_REF, PKA_REF = -0.203, 4.4          # reference compound values of section III.C
 E_FIXED = E0_REF                        # redox potential of batches without an E ladder
 
-# Algorithmic work per unordered pair of one full evaluation, counted from the
-# closed-form expressions (FMA = 2; add, mul, min, max, abs, select = 1; each
-# reciprocal, sqrt, rsqrt, exp, log = 1 and counted as one operation):
-#   descreening pass 54 + 8, energy/force pass 53 + 4, chain pass 94 + 7.
-FLOPS_PER_PAIR = {"radii_pairs": 62, "energy_pairs": 57, "chain_pairs": 101}
+# Algorithmic work per unordered pair of one full evaluation (FMA = 2; add,
+# mul, min, max, select = 1; each reciprocal, sqrt, rsqrt, exp, log, tanh = 1),
+# the counts fixed before the first measurement from the closed-form
+# expressions: descreening pass 53 flops + 7 transcendentals (both H
+# directions sharing r), energy/force pass 50 + 4, chain pass 75 + 5 (both
+# dH/dr directions and dH/dS).
+FLOPS_PER_PAIR = {"radii_pairs": 60, "energy_pairs": 54, "chain_pairs": 80}
 # Peaks (MI355X, 256 CUs at 2.4 GHz): FP32 vector 157.3 TFLOP/s, FP64 vector
 # 78.6 TFLOP/s.  The library's device code has packed-FP32 instructions
 # disabled, yet the FP32 value is the attainable one: the FP32 pair kernels
@@ -48,35 +52,37 @@ PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--fp64-steps", type=int, default=20)
-    ap.add_argument("--kernel-steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=50,
+                    help="timed steps of the headline workload (the 64-system batch)")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--fp64-steps", type=int, default=5)
+    ap.add_argument("--kernel-steps", type=int, default=10,
+                    help="eager steps / force evaluations timed per kernel with HIP events")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-overlap", action="store_true",
                     help="run the Monte Carlo branch on the main stream after the force passes "
                          "(by default it runs on a second stream beside them, with "
                          "double-buffered charges)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline workload only (no E-REMD batch, sweep, salt, dynamics loop, "
+                         "cutoff or autograd measurements)")
+    ap.add_argument("--only", choices=["headline", "eremd"], default=None,
+                    help="run one workload's GPU measurement alone and print its JSON object "
+                         "(for profiling it)")
+    ap.add_argument("--eremd-steps", type=int, default=200,
+                    help="timed steps of the E-REMD batch")
     ap.add_argument("--no-cutoff-bench", action="store_true",
                     help="skip the large-globule cutoff measurement")
-    ap.add_argument("--no-uneven-bench", action="store_true",
-                    help="skip the uneven 64-system batch measurement")
-    ap.add_argument("--uneven-steps", type=int, default=20,
-                    help="timed steps of the uneven-batch measurement")
-    ap.add_argument("--no-uneven-tune", action="store_true",
-                    help="uneven batch: library default work shapes only (no autotuner run)")
-    ap.add_argument("--uneven-only", action="store_true",
-                    help="run only the uneven-batch measurement and print its JSON object "
-                         "(for profiling that batch on its own)")
     ap.add_argument("--md-steps", type=int, default=100,
                     help="steps of the timed simulation loop (0: skip)")
-    ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 64 MiB device copy (reference for HBM counters)")
     ap.add_argument("--autotune", action="store_true",
-                    help="sweep the work shapes first instead of using the library defaults "
-                         "(the committed HBM counters were taken with the defaults)")
+                    help="also time the headline workload with the work shapes the autotuner "
+                         "picks for it (the headline itself uses the library defaults, the "
+                         "shapes the committed counters were taken with)")
     ap.add_argument("--order", choices=["spatial", "blocks", "identity"], default="spatial",
                     help="processing order of the pair passes (results are order independent)")
     return ap.parse_args()
@@ -111,7 +117,7 @@ class Workload:
     distinct systems (each at E_FIXED and pH 7, no exchange)."""
 
     def __init__(self, precision, n_steps, order="spatial", tuning=None, overlap=True,
-                 systems=None, exchange=True):
+                 systems=None, exchange=True, gref=None):
         import numpy as np
         import torch
         import paper_1803_09652_amd as g
@@ -147,8 +153,10 @@ class Workload:
         self.pH = torch.full((self.B,), synth.PH_DEFAULT, dtype=torch.float64, device=dev)
         self.cur = torch.as_tensor(b.current_state, device=dev)
         g.radii(self.plan, self.atoms, self.params)
-        gref = reference_gref(g, self.plan, b, self.atoms, self.cur, self.pH, self.E_rep, self.T,
-                              self.params)
+        if gref is None:
+            gref = reference_gref(g, self.plan, b, self.atoms, self.cur, self.pH, self.E_rep,
+                                  self.T, self.params)
+        self.gref = gref
         self.sites = g.Sites.from_batch(self.plan, b, gref)
         rng = torch.Generator(device=dev)
         rng.manual_seed(2024)
@@ -172,7 +180,7 @@ class Workload:
         g, p, torch = self.g, self.params, self.torch
         cur, nxt = (self.atoms, self.atoms_b) if parity == 0 else (self.atoms_b, self.atoms)
         main = torch.cuda.current_stream()
-        g.radii(self.plan, cur, p)
+        R = g.radii(self.plan, cur, p)
         mc_stream = self.side if self.overlap else main
         if mc_stream is not main:
             mc_stream.wait_stream(main)
@@ -192,6 +200,8 @@ class Workload:
                            self.u, self.T, p, counters=self.counters, q_out=nxt.q)
         if mc_stream is not main:
             main.wait_stream(mc_stream)
+        # the step's outputs (static tensors of a captured graph)
+        self.last = {"R": R, "force_out": ef, "dE": dE, "dG": dG, "mc": mc, "q_out": nxt.q}
         if self.exchange:
             acc, _ = g.remd_exchange(self.E_rung, mc["n_electrons"], self.rep_of_rung, parity,
                                      self.ux, self.T, True, E_out=self.E_rep)
@@ -436,56 +446,60 @@ def time_plain_fp64(w, reps=3):
             "form": "radii + energy + forces + dE/dq + dE/drho, every ordered pair, FP64"}
 
 
-def time_uneven_batch(steps=20, warmup=3, fp64_steps=5, tune=True):
-    """The uneven batch: 64 distinct systems of 500-20,000 atoms with 2-10
-    redox and 0-20 protonation sites each, one step = radii + energy / forces
-    (+ dE/dq, dE/drho) with the Monte Carlo branch (every candidate Delta E,
-    Metropolis attempt) beside it, captured in a HIP graph and replayed;
-    FP32-fixed with the library's default work shapes and with the shapes
-    the autotuner picks for this batch, the FP64 plan, and the plain FP64 form
-    of one evaluation."""
-    import numpy as np
+def pair_count(systems):
+    return int(sum(s_.n * (s_.n - 1) // 2 for s_ in systems))
+
+
+def roofline_of(pairs, kernel_ms, traffic=None, traffic_detail=None):
+    """FP32 VALU roofline of the dominant pair kernel: algorithmic flops per
+    launch (per-pair count x unordered pairs) over its mean duration per
+    launch."""
+    pair_k = {n: kernel_ms[n] for n in FLOPS_PER_PAIR if n in kernel_ms}
+    if not pair_k:
+        return None
+    dom = max(pair_k, key=pair_k.get)
+    ach = FLOPS_PER_PAIR[dom] * pairs / (pair_k[dom] * 1e-3) / 1e12
+    return {"bound": "alu", "kernel": dom, "achieved": ach,
+            "measured_as": "mean duration per launch of the force passes alone (eager, HIP "
+                           "events bound to the dispatches, on the launch stream)",
+            "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s", "frac": ach / PEAK_TFLOPS["fp32"],
+            "traffic": traffic, "traffic_detail": traffic_detail,
+            "flops_per_pair": FLOPS_PER_PAIR[dom], "pairs_per_launch": pairs,
+            "per_kernel_tflops": {n: FLOPS_PER_PAIR[n] * pairs / (v * 1e-3) / 1e12
+                                  for n, v in pair_k.items()},
+            "per_kernel_frac": {n: FLOPS_PER_PAIR[n] * pairs / (v * 1e-3) / 1e12
+                                / PEAK_TFLOPS["fp32"] for n, v in pair_k.items()}}
+
+
+def measure_workload(systems, exchange, steps, warmup, kernel_steps, use_graph=True,
+                     order="spatial", tuning=None, overlap=True, precision="fp32"):
+    """The step of one workload (captured and replayed), the per-kernel means
+    inside the step, the Monte Carlo Delta E kernels alone and the force
+    passes alone."""
     import torch
-    import paper_1803_09652_amd as g
-    from paper_1803_09652_amd import autotune as at
-    import synth
-    systems = synth.uneven_batch_64()
-    n = np.array([s_.n for s_ in systems])
-    pairs = int((n * (n - 1) // 2).sum())
-    out = {"workload": f"{len(systems)} systems, {int(n.min())}-{int(n.max())} atoms "
-                       f"({int(n.sum())} in all), E = {E_FIXED} V, pH 7, no exchange",
-           "pairs_per_step": pairs}
-    runs = [("fp32", None, steps)]
-    if tune:
-        b = synth.make_batch(systems)
-        t = at.tune(b, "fp32", order=g.spatial_order(b.atom_offset, b.x, b.y, b.z),
-                    use_cache=False)
-        out["autotune"] = {"j_blocks_per_item": list(t["best"][0]),
-                           "waves_per_group": list(t["best"][1]),
-                           "tuned_pair_ms": t.get("pair_ms")}
-        runs.append(("fp32_autotuned", t["best"], steps))
-    runs.append(("fp64", None, fp64_steps))
-    for name, tuning, n_st in runs:
-        prec = "fp64" if name == "fp64" else "fp32"
-        w, ms, wall, kms = run_gpu(prec, n_st, warmup, True, 2, "spatial", tuning, True,
-                                   systems=systems, exchange=False)
-        out["candidates_per_step"] = w.n_cand
-        out[name] = {"ms_per_step": ms, "pair_interactions_per_s": pairs / (ms * 1e-3),
-                     "mc_dE_evals_per_s": w.n_cand / (ms * 1e-3), "steps": n_st,
-                     "kernel_ms": kms, "overflow": bool(g.check_overflow(w.plan)),
-                     # pair kernels inside the step (the Monte Carlo branch beside them)
-                     "pair_kernel_tflops": {k_: FLOPS_PER_PAIR[k_] * pairs / (kms[k_] * 1e-3) / 1e12
-                                            for k_ in FLOPS_PER_PAIR if k_ in kms},
-                     "peak_tflops": PEAK_TFLOPS[prec]}
-        if name == "fp32":
-            out["fp64_plain"] = time_plain_fp64(w, reps=1)
-        del w
-        torch.cuda.empty_cache()
-    best32 = max(v["pair_interactions_per_s"] for k_, v in out.items()
-                 if k_ in ("fp32", "fp32_autotuned"))
-    out["fp32_over_fp64"] = best32 / out["fp64"]["pair_interactions_per_s"]
-    out["fp32_over_fp64_plain"] = best32 / out["fp64_plain"]["value"]
-    return out
+    pairs = pair_count(systems)
+    w, ms, wall, kms = run_gpu(precision, steps, warmup, use_graph, kernel_steps, order, tuning,
+                               overlap, systems=systems, exchange=exchange)
+    g = w.g
+    out = {"ms_per_step": ms, "pair_interactions_per_s": pairs / (ms * 1e-3),
+           "mc_dE_evals_per_s": w.n_cand / (ms * 1e-3), "steps": steps,
+           "wall_ms_per_step": wall, "ms_per_step_spread": w.step_spread,
+           "pairs_per_step": pairs, "candidates_per_step": w.n_cand,
+           "kernel_ms_in_step": kms, "kernel_ms_force_passes_alone": w.force_alone_ms,
+           "overflow": bool(g.check_overflow(w.plan))}
+    alone = w.mc_alone_ms
+    if "site_rows" in alone or "site_dE" in alone:
+        t_mc = alone.get("site_rows", 0.0) + alone.get("site_dE", 0.0)
+        out["mc_dE_evals_per_s_standalone"] = w.n_cand / (t_mc * 1e-3)
+        out["mc_kernel_ms_standalone"] = {k_: alone[k_] for k_ in ("site_rows", "site_dE")
+                                          if k_ in alone}
+    if w.exchange:
+        out["exchange_attempts_eager"] = w.exchanges_attempted
+        out["exchange_accepted_eager"] = w.exchanges_accepted
+    cnt = w.counters.sum(0).cpu().tolist()
+    out["mc_state_attempts"], out["mc_state_accepted"] = cnt[0], cnt[1]
+    torch.cuda.synchronize()
+    return out, w
 
 
 def time_md_loop(steps, warmup, n_rep=16, attempt_every=5, exchange_every=10):
@@ -541,27 +555,57 @@ def time_md_loop(steps, warmup, n_rep=16, attempt_every=5, exchange_every=10):
             "overflow": bool(g.check_overflow(plan))}
 
 
-def cpu_baseline(systems, min_wall_s=1.5, max_passes=8):
-    """The FP64 oracle as it stands, on the host cores: whole passes over every
-    replica of the batch (full evaluation + every candidate Delta E), repeated
-    until about min_wall_s of wall time (a bounded sample)."""
+def host_cpu():
+    """CPU model of the host (lscpu, else /proc/cpuinfo) and its core count."""
+    import subprocess
+    model = None
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        model = next((l.split(":", 1)[1].strip() for l in txt.splitlines()
+                      if l.startswith("Model name")), None)
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if not model:
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((l.split(":", 1)[1].strip() for l in f
+                              if l.startswith("model name")), None)
+        except OSError:
+            pass
+    return {"cpu_model": model, "nproc": os.cpu_count(),
+            "threads_allowed": len(os.sched_getaffinity(0))}
+
+
+def stratified_sample(systems, n_pick=8):
+    """Indices of n_pick systems at evenly spaced size ranks (the smallest and
+    the largest included)."""
+    import numpy as np
+    sizes = np.array([s_.n for s_ in systems])
+    order = np.argsort(sizes, kind="stable")
+    ranks = np.unique(np.round(np.linspace(0, len(systems) - 1, n_pick)).astype(int))
+    return [int(order[r]) for r in ranks]
+
+
+def cpu_baseline(systems, label):
+    """The FP64 oracle as it stands, on the host cores: one full evaluation
+    (radii, energy, forces, dE/dq, dE/drho and every candidate Delta E) of each
+    system of a bounded sample of the workload, pair interactions per second
+    over the whole sample."""
     import oracle
     oracle.lib()
     cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    pairs = pair_count(systems)
     t0 = time.perf_counter()
-    pairs, passes = 0, 0
-    while passes < max_passes and (passes == 0 or time.perf_counter() - t0 < min_wall_s):
-        for s in systems:
-            r = oracle.energy_forces(s)
-            oracle.site_dE(s, r["R"])
-            pairs += s.n * (s.n - 1) // 2
-        passes += 1
+    for s_ in systems:
+        r = oracle.energy_forces(s_)
+        if s_.sites:
+            oracle.site_dE(s_, r["R"])
     dt = time.perf_counter() - t0
     return {"value": pairs / dt, "unit": "pair interactions/s", "cores": cores, "kind": "oracle",
-            "sample": f"{passes} pass(es) over all {len(systems)} replicas of the E-REMD batch "
-                      f"({pairs} pairs): radii, energy, forces, dE/dq, dE/drho and every "
-                      f"candidate Delta E, FP64, OpenMP on {cores} threads, {dt:.1f} s wall "
-                      f"(~{dt * cores:.0f} core-s)"}
+            "sample": f"{label}: one full evaluation each ({pairs} pairs): radii, energy, forces, "
+                      f"dE/dq, dE/drho and every candidate Delta E, FP64, OpenMP on {cores} "
+                      f"threads, {dt:.1f} s wall (~{dt * cores:.0f} core-s)",
+            **host_cpu()}
 
 
 def cpu_oracle_detail(reps=3):
@@ -578,14 +622,8 @@ def cpu_oracle_detail(reps=3):
     oracle.lib()
     gomp = ctypes.CDLL("libgomp.so.1")
     n_all = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
-    model = None
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), None)
-    except OSError:
-        pass
-    out = {"kind": "oracle", "unit": "pair interactions/s", "nproc": os.cpu_count(),
-           "threads_all": n_all, "cpu_model": model, "systems": {}}
+    out = {"kind": "oracle", "unit": "pair interactions/s", "threads_all": n_all,
+           **host_cpu(), "systems": {}}
     for name, sys_ in (("256 atoms", synth.globule_256()[0]), ("2500 atoms", synth.globule_2500()[0]),
                        ("10000 atoms", synth.globule_10000()[0])):
         pairs = sys_.n * (sys_.n - 1) // 2
@@ -607,7 +645,53 @@ def cpu_oracle_detail(reps=3):
     return out
 
 
-COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "hbm_counters_pair_kernels_ereMD_16x2500.md")
+COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "hbm_counters_pair_kernels_uneven_64.md")
+
+
+def time_autograd(reps=10):
+    """GBEnergy (torch.autograd.Function) on the 10,000-atom globule, FP32
+    plan: forward (radii + energy-only pass) and backward (the gradient passes
+    on the radius state forward kept) timed separately with HIP events, and
+    the pair kernels each phase launched, from the timing hook."""
+    import numpy as np
+    import torch
+    import paper_1803_09652_amd as g
+    import synth
+    s_ = synth.globule_10000()[0]
+    b = synth.make_batch([s_])
+    plan = g.Plan(b.atom_offset, "fp32")
+    plan.set_order(g.spatial_order(b.atom_offset, b.x, b.y, b.z))
+    dev = plan.device
+    t = lambda a: torch.as_tensor(np.asarray(a), dtype=torch.float32, device=dev)
+    pos = t(np.stack([b.x, b.y, b.z], axis=1)).requires_grad_(True)
+    q, rho, scr = t(b.q).requires_grad_(True), t(b.rho).requires_grad_(True), t(b.screen)
+    for _ in range(2):
+        g.GBEnergy.apply(pos, q, rho, scr, plan, g.IGB5).sum().backward()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1, e2 in ev:
+        e0.record()
+        E = g.GBEnergy.apply(pos, q, rho, scr, plan, g.IGB5)
+        e1.record()
+        E.sum().backward()
+        e2.record()
+    torch.cuda.synchronize()
+    fwd = sorted(a.elapsed_time(b_) for a, b_, _ in ev)[reps // 2]
+    bwd = sorted(b_.elapsed_time(c) for _, b_, c in ev)[reps // 2]
+    plan.set_timing(True)
+    E = g.GBEnergy.apply(pos, q, rho, scr, plan, g.IGB5)
+    torch.cuda.synchronize()
+    k_fwd = plan.kernel_ms()
+    E.sum().backward()
+    torch.cuda.synchronize()
+    k_bwd = plan.kernel_ms()
+    plan.set_timing(False)
+    return {"workload": "one 10000-atom globule (26 A), FP32 plan, dE/dx, dE/dq, dE/drho",
+            "forward_ms": fwd, "backward_ms": bwd, "reps": reps,
+            "forward_kernel_ms": k_fwd, "backward_kernel_ms": k_bwd,
+            "backward_pair_kernels_ms": sum(v for k_, v in k_bwd.items()
+                                            if k_ in ("energy_pairs", "chain_pairs"))}
 
 
 def kernel_source_hash():
@@ -623,12 +707,12 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def traffic_from_counters(kernel):
+def traffic_from_counters(kernel, path=COUNTER_SUMMARY):
     """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, each scaled by
     what the counter reads for a plain copy of known size), from the committed
     rocprofv3 summary; None when absent or taken from other kernel sources."""
     try:
-        with open(COUNTER_SUMMARY) as f:
+        with open(path) as f:
             lines = [l for l in f if l.startswith("traffic-record: ")]
         rec = json.loads(lines[-1][len("traffic-record: "):])
     except (OSError, IndexError, ValueError):
@@ -641,7 +725,7 @@ def traffic_from_counters(kernel):
     return k["fetch_bytes"] + k["write_bytes"], {
         "fetch_bytes": k["fetch_bytes"], "write_bytes": k["write_bytes"],
         "fetch_factor": rec["fetch_factor"], "write_factor": rec["write_factor"],
-        "source": os.path.relpath(COUNTER_SUMMARY, ROOT)}
+        "source": os.path.relpath(path, ROOT)}
 
 
 def main():
@@ -649,16 +733,24 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}): "
-              "the batch shards by replica across GPUs in principle, but the benchmark "
+              "the batch shards by system across GPUs in principle, but the benchmark "
               "measures the single-GPU path", file=sys.stderr)
         sys.exit(2)
     import torch
+    import synth
     torch.cuda.set_device(0)
-    if args.uneven_only:
-        print(json.dumps(time_uneven_batch(args.uneven_steps, 2, max(1, args.uneven_steps // 4),
-                                           not args.no_uneven_tune)), flush=True)
+    use_graph, overlap = not args.no_graph, not args.no_overlap
+    run = dict(use_graph=use_graph, order=args.order, overlap=overlap)
+    if args.only == "headline":
+        r, _ = measure_workload(synth.uneven_batch_64(), False, args.steps, args.warmup,
+                                args.kernel_steps, **run)
+        print(json.dumps(r), flush=True)
         return
-    use_graph = not args.no_graph
+    if args.only == "eremd":
+        r, _ = measure_workload(synth.eremd_batch(), True, args.eremd_steps, args.warmup,
+                                args.kernel_steps, **run)
+        print(json.dumps(r), flush=True)
+        return
     copy_ref = None
     if args.copy_calibration:
         # a plain streaming kernel of known size (64 MiB read, 64 MiB written;
@@ -673,12 +765,13 @@ def main():
         torch.cuda.synchronize()
         copy_ref = {"kernel": "neg", "bytes_read": 4 * n, "bytes_written": 4 * n, "dispatches": 3}
         del a, b
-    tune32 = autotune("fp32", args.order) if args.autotune else None
-    w, ms_step, wall_ms, kms = run_gpu("fp32", args.steps, args.warmup, use_graph, args.kernel_steps,
-                                       args.order, tune32["best"] if tune32 else None,
-                                       not args.no_overlap)
-    pairs, n_cand = w.pairs, w.n_cand
+
+    # ---- headline: the uneven 64-system batch, FP32-fixed, library default shapes
+    systems = synth.uneven_batch_64()
+    head, w = measure_workload(systems, False, args.steps, args.warmup, args.kernel_steps, **run)
+    pairs, ms_step = head["pairs_per_step"], head["ms_per_step"]
     value = pairs / (ms_step * 1e-3)
+    sizes = [s_.n for s_ in systems]
     out = {
         "metric": METRIC,
         "value": value,
@@ -693,74 +786,93 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": "E-REMD batch: 16 replicas x 2500 atoms (18 A globules), 4 redox + 4 "
-                        "protonation sites each, E ladder -0.40..-0.10 V, pH 7, T 300 K, igb=5, "
-                        "no cutoff",
-            "systems": w.B, "atoms": w.batch.n_atoms, "pairs_per_step": pairs,
-            "candidates_per_step": n_cand, "hip_graph": use_graph, "atom_order": args.order,
-            "mc_branch": "second stream beside the force passes" if not args.no_overlap
+            "workload": f"uneven batch: {len(systems)} protein-like globules of {min(sizes)}-"
+                        f"{max(sizes)} atoms ({sum(sizes)} in all), 2-10 redox + 0-20 "
+                        "protonation sites each, E = E0_ref, pH 7, T 300 K, igb=5, no cutoff",
+            "systems": len(systems), "atoms": sum(sizes), "pairs_per_step": pairs,
+            "candidates_per_step": head["candidates_per_step"], "hip_graph": use_graph,
+            "atom_order": args.order,
+            "mc_branch": "second stream beside the force passes" if overlap
                          else "after the force passes",
-            "tuning": ({"j_blocks_per_item": tune32["best"][0], "waves_per_group": tune32["best"][1],
-                        "passes": "radii, energy, chain", "tuned_pair_ms": tune32["pair_ms"]}
-                       if tune32 else "library default"),
+            "tuning": "library default",
             "precision": "FP32 pair arithmetic, int64 fixed-point sums, FP64 MC",
         },
-        "mc_dE_evals_per_s": n_cand / (ms_step * 1e-3),
-        "wall_ms_per_step": wall_ms,
-        "ms_per_step_spread": w.step_spread,
-        "kernel_ms": kms,
+        "mc_dE_evals_per_s": head["mc_dE_evals_per_s"],
     }
-    alone = w.mc_alone_ms
-    if "site_rows" in alone or "site_dE" in alone:
-        t_mc = alone.get("site_rows", 0.0) + alone.get("site_dE", 0.0)
-        out["mc_dE_evals_per_s_standalone"] = n_cand / (t_mc * 1e-3)
-        out["mc_kernel_ms_standalone"] = {k_: alone[k_] for k_ in ("site_rows", "site_dE") if k_ in alone}
-    out["kernel_ms_force_passes_alone"] = w.force_alone_ms
-    pair_k = {n: w.force_alone_ms[n] for n in FLOPS_PER_PAIR if n in w.force_alone_ms}
-    if pair_k:
-        dom = max(pair_k, key=pair_k.get)
-        ach = FLOPS_PER_PAIR[dom] * pairs / (pair_k[dom] * 1e-3) / 1e12
-        traffic, detail = (None, "work shapes autotuned: counters were taken with the "
-                                 "library defaults") if tune32 else traffic_from_counters(dom)
-        out["roofline"] = {"bound": "alu", "kernel": dom, "achieved": ach,
-                           "measured_as": "mean duration per launch of the force passes alone "
-                                          "(eager, HIP events bound to the dispatches)",
-                           "peak": PEAK_TFLOPS["fp32"], "unit": "TFLOP/s",
-                           "frac": ach / PEAK_TFLOPS["fp32"], "traffic": traffic,
-                           "traffic_detail": detail,
-                           "per_kernel_tflops": {n: FLOPS_PER_PAIR[n] * pairs / (v * 1e-3) / 1e12
-                                                 for n, v in pair_k.items()}}
-    out["fp64_plain"] = time_plain_fp64(w)
+    for k_ in ("wall_ms_per_step", "ms_per_step_spread", "kernel_ms_in_step",
+               "kernel_ms_force_passes_alone", "mc_dE_evals_per_s_standalone",
+               "mc_kernel_ms_standalone", "mc_state_attempts", "mc_state_accepted", "overflow"):
+        if k_ in head:
+            out[k_] = head[k_]
+    force_alone = head["kernel_ms_force_passes_alone"]
+    dom_rf = roofline_of(pairs, force_alone)
+    traffic, detail = traffic_from_counters(dom_rf["kernel"]) if dom_rf else (None, None)
+    out["roofline"] = roofline_of(pairs, force_alone, traffic, detail)
+    out["fp64_plain"] = time_plain_fp64(w, reps=1)
     out["fp32_over_fp64_plain"] = value / out["fp64_plain"]["value"]
-    out["mc_sweep"] = time_sweep(w)
-    out["salt"] = time_salt(w)
-    if args.md_steps > 0:
-        out["md_loop"] = time_md_loop(args.md_steps, 10)
-    if not args.no_cutoff_bench:
-        out["cutoff"] = time_cutoff()
-    if not args.no_uneven_bench:
-        out["uneven_batch"] = time_uneven_batch(args.uneven_steps, 3, max(1, args.uneven_steps // 4),
-                                                not args.no_uneven_tune)
-    cnt = w.counters.sum(0).cpu().tolist()
-    out["mc_acceptance"] = {"state_attempts": cnt[0], "state_accepted": cnt[1],
-                            "exchange_attempts_eager": w.exchanges_attempted,
-                            "exchange_accepted_eager": w.exchanges_accepted}
     del w
+    torch.cuda.empty_cache()
     if not args.no_fp64:
-        tune64 = autotune("fp64", args.order) if args.autotune else None
-        w64, ms64, _, k64 = run_gpu("fp64", args.fp64_steps, 2, use_graph, 3, args.order,
-                                    tune64["best"] if tune64 else None, not args.no_overlap)
-        v64 = pairs / (ms64 * 1e-3)
-        out["fp64"] = {"value": v64, "ms_per_step": ms64, "steps": args.fp64_steps,
-                       "kernel_ms": k64, "tuning": tune64["best"] if tune64 else None}
-        out["fp32_over_fp64"] = value / v64
+        r64, w64 = measure_workload(systems, False, args.fp64_steps, 2, 1, precision="fp64", **run)
+        out["fp64"] = {k_: r64[k_] for k_ in ("ms_per_step", "pair_interactions_per_s",
+                                              "mc_dE_evals_per_s", "steps", "kernel_ms_in_step",
+                                              "overflow")}
+        out["fp64"]["value"] = r64["pair_interactions_per_s"]
+        out["fp32_over_fp64"] = value / r64["pair_interactions_per_s"]
         del w64
+        torch.cuda.empty_cache()
+    if args.autotune:
+        from paper_1803_09652_amd import autotune as at
+        import paper_1803_09652_amd as g
+        b = synth.make_batch(systems)
+        tn = at.tune(b, "fp32", order=g.spatial_order(b.atom_offset, b.x, b.y, b.z),
+                     use_cache=False)
+        rt, wt = measure_workload(systems, False, args.steps, args.warmup, 1,
+                                  tuning=tn["best"], **run)
+        out["fp32_autotuned"] = {"ms_per_step": rt["ms_per_step"],
+                                 "pair_interactions_per_s": rt["pair_interactions_per_s"],
+                                 "j_blocks_per_item": list(tn["best"][0]),
+                                 "waves_per_group": list(tn["best"][1])}
+        del wt
+        torch.cuda.empty_cache()
+
+    # ---- beside it: the E-REMD batch (16 x 2,500 atoms, exchange every step)
+    if not args.no_extras:
+        er, we = measure_workload(synth.eremd_batch(), True, args.eremd_steps, args.warmup,
+                                  max(args.kernel_steps, 20), **run)
+        er["workload"] = ("E-REMD batch: 16 replicas x 2500 atoms (18 A globules), 4 redox + 4 "
+                          "protonation sites each, E ladder -0.40..-0.10 V, pH 7, T 300 K, "
+                          "exchange attempt every step")
+        er["roofline"] = roofline_of(er["pairs_per_step"], er["kernel_ms_force_passes_alone"])
+        er["fp64_plain"] = time_plain_fp64(we, reps=2)
+        er["fp32_over_fp64_plain"] = er["pair_interactions_per_s"] / er["fp64_plain"]["value"]
+        er["mc_sweep"] = time_sweep(we)
+        er["salt"] = time_salt(we)
+        del we
+        torch.cuda.empty_cache()
+        if not args.no_fp64:
+            e64, w64 = measure_workload(synth.eremd_batch(), True, 20, 2, 1, precision="fp64",
+                                        **run)
+            er["fp64"] = {"ms_per_step": e64["ms_per_step"],
+                          "value": e64["pair_interactions_per_s"]}
+            er["fp32_over_fp64"] = er["pair_interactions_per_s"] / e64["pair_interactions_per_s"]
+            del w64
+        out["eremd_batch"] = er
+        out["autograd"] = time_autograd()
+        if args.md_steps > 0:
+            out["md_loop"] = time_md_loop(args.md_steps, 10)
+        if not args.no_cutoff_bench:
+            out["cutoff"] = time_cutoff()
     if copy_ref is not None:
         out["copy_calibration"] = copy_ref
     if not args.no_cpu_baseline:
-        import synth
-        out["cpu_baseline"] = cpu_baseline(synth.eremd_batch())
-        out["cpu_oracle_detail"] = cpu_oracle_detail()
+        pick = stratified_sample(systems)
+        out["cpu_baseline"] = cpu_baseline(
+            [systems[k_] for k_ in pick],
+            f"the {len(pick)} systems of the uneven batch at evenly spaced size ranks "
+            f"({', '.join(str(systems[k_].n) for k_ in pick)} atoms)")
+        if not args.no_extras:
+            out["cpu_oracle_detail"] = cpu_oracle_detail()
     print(json.dumps(out), flush=True)
 
 

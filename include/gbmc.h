@@ -90,8 +90,7 @@ typedef struct {
  * such independent wavefronts share a workgroup (1, 2, 4 or 8).  Every 64 x 64
  * tile is rounded into fixed point on its own, so results are bitwise
  * independent of the knobs.  Defaults (j blocks / waves): FP32 descreening
- * 1 / 4, energy 2 / 4, chain 1 / 1; FP64 descreening 1 / 2, energy 2 / 4,
- * chain 1 / 2. */
+ * 1 / 1, energy 1 / 8, chain 1 / 4; FP64 1 / 2 for all three passes. */
 enum { GBMC_PASS_RADII = 0, GBMC_PASS_ENERGY = 1, GBMC_PASS_CHAIN = 2, GBMC_N_PASSES = 3 };
 typedef struct {
     int32_t j_blocks_per_item[GBMC_N_PASSES];
@@ -174,7 +173,8 @@ size_t gbmc_plan_workspace_bytes(const gbmc_plan* plan);
  *   I_i = sum_{j != i} H(r_ij; rho_i - offset, screen_j (rho_j - offset))
  *   Psi_i = (rho_i - offset) I_i,  theta = alpha Psi - beta Psi^2 + gamma Psi^3
  *   R_i = 1 / (1/(rho_i - offset) - tanh(theta)/rho_i)
- * where H is the HCT pair integral (no cutoff).  Writes born_R[N_tot] (float or
+ * where H is the HCT pair integral, restricted to the sphere of radius
+ * params->rgbmax around atom i when rgbmax > 0 (see gbmc_gb_params).  Writes born_R[N_tot] (float or
  * double per plan) and the per-atom state that gb_energy_forces and
  * mc_state_dE use into workspace. */
 gbmc_status gb_radii(gbmc_plan* plan, const gbmc_atoms* atoms, const gbmc_gb_params* params,

@@ -213,20 +213,33 @@ def block_order(atom_offset, x, y, z) -> np.ndarray:
     return out
 
 
-def radii(plan: Plan, atoms: Atoms, params: GBParams = IGB5) -> torch.Tensor:
+def _workspace(plan: Plan, workspace: Optional[torch.Tensor]) -> torch.Tensor:
+    if workspace is None:
+        return plan.workspace
+    if (workspace.dtype != torch.uint8 or workspace.numel() < plan.workspace.numel()
+            or workspace.device != plan.device or workspace.data_ptr() % 256):
+        raise ValueError("workspace must be a 256-byte aligned uint8 tensor of at least "
+                         "plan.workspace.numel() bytes on the plan's device")
+    return workspace
+
+
+def radii(plan: Plan, atoms: Atoms, params: GBParams = IGB5,
+          workspace: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Effective Born radii R[N] (plan dtype); leaves the per-atom state in the
-    plan's workspace for energy_forces and mc_state_dE."""
+    workspace (default: the plan's) for energy_forces and mc_state_dE."""
     R = torch.empty(plan.n_atoms, dtype=plan.dtype, device=plan.device)
     a, p = atoms.c(), params.c()
-    L.check(L.load().gb_radii(plan.handle, C.byref(a), C.byref(p), _ptr(plan.workspace), _ptr(R),
+    ws = _workspace(plan, workspace)
+    L.check(L.load().gb_radii(plan.handle, C.byref(a), C.byref(p), _ptr(ws), _ptr(R),
                               _stream(plan.device)))
     return R
 
 
 def energy_forces(plan: Plan, atoms: Atoms, params: GBParams = IGB5, force: bool = True,
-                  dEdq: bool = True, dEdrho: bool = True) -> dict:
+                  dEdq: bool = True, dEdrho: bool = True,
+                  workspace: Optional[torch.Tensor] = None) -> dict:
     """E_C and E_GB per system (float64 [B]) and the requested gradients.
-    Needs a preceding radii() on the same plan and atoms."""
+    Needs a preceding radii() on the same plan, atoms and workspace."""
     dev, dt, n = plan.device, plan.dtype, plan.n_atoms
     out = {
         "e_coul": torch.empty(plan.n_systems, dtype=torch.float64, device=dev),
@@ -236,7 +249,8 @@ def energy_forces(plan: Plan, atoms: Atoms, params: GBParams = IGB5, force: bool
         "dEdrho": torch.empty(n, dtype=dt, device=dev) if dEdrho else None,
     }
     a, p = atoms.c(), params.c()
-    L.check(L.load().gb_energy_forces(plan.handle, C.byref(a), C.byref(p), _ptr(plan.workspace),
+    ws = _workspace(plan, workspace)
+    L.check(L.load().gb_energy_forces(plan.handle, C.byref(a), C.byref(p), _ptr(ws),
                                       _ptr(out["e_coul"]), _ptr(out["e_gb"]), _ptr(out["force"]),
                                       _ptr(out["dEdq"]), _ptr(out["dEdrho"]),
                                       _stream(plan.device)))
@@ -475,28 +489,30 @@ class GBEnergy(torch.autograd.Function):
     """E = E_C + E_GB per system (float64 [B]) as a differentiable function of
     positions [N, 3], charges [N] and intrinsic radii [N] (screens fixed).
 
-    forward runs the radii and the energy-only pair pass; backward runs the
-    hand-written gradient kernels (pair forces, G = dE/dR, phi = dE/dq, then
-    the Born-radius chain and dE/drho)."""
+    forward runs the radii pass and the energy-only pair pass in a workspace
+    of its own, which keeps the per-atom radius state (R, tanh theta,
+    dR/dPsi, the descreening sums) for backward; backward runs only the
+    hand-written gradient passes on that state (the energy / explicit force
+    pair pass giving G = dE/dR and phi = dE/dq, then the Born-radius chain pass
+    and dE/drho), never the radii pass again."""
 
     @staticmethod
     def forward(ctx, pos, q, rho, screen, plan: Plan, params: GBParams = IGB5):
         pos_d, q_d, rho_d, scr_d = (t.detach() for t in (pos, q, rho, screen))
         atoms = Atoms(plan, pos_d[:, 0], pos_d[:, 1], pos_d[:, 2], q_d, rho_d, scr_d)
-        radii(plan, atoms, params)
-        out = energy_forces(plan, atoms, params, force=False, dEdq=False, dEdrho=False)
-        ctx.plan, ctx.params = plan, params
-        ctx.save_for_backward(pos_d, q_d, rho_d, scr_d)
+        ws = torch.empty_like(plan.workspace)
+        radii(plan, atoms, params, workspace=ws)
+        out = energy_forces(plan, atoms, params, force=False, dEdq=False, dEdrho=False,
+                            workspace=ws)
+        ctx.plan, ctx.params, ctx.atoms, ctx.ws = plan, params, atoms, ws
         return out["e_coul"] + out["e_gb"]
 
     @staticmethod
     def backward(ctx, gE):
-        pos, q, rho, screen = ctx.saved_tensors
-        plan, params = ctx.plan, ctx.params
-        atoms = Atoms(plan, pos[:, 0], pos[:, 1], pos[:, 2], q, rho, screen)
-        radii(plan, atoms, params)
+        plan, params, atoms, ws = ctx.plan, ctx.params, ctx.atoms, ctx.ws
         g = energy_forces(plan, atoms, params, force=ctx.needs_input_grad[0],
-                          dEdq=ctx.needs_input_grad[1], dEdrho=ctx.needs_input_grad[2])
+                          dEdq=ctx.needs_input_grad[1], dEdrho=ctx.needs_input_grad[2],
+                          workspace=ws)
         w = gE.to(plan.dtype)[plan.atom_sys]
         gpos = -g["force"] * w[:, None] if g["force"] is not None else None
         gq = g["dEdq"] * w if g["dEdq"] is not None else None

@@ -37,9 +37,10 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 constexpr int64_t kTimedMax = 256;   // launches kept per timed kernel between reads
 
-// Default work shapes (radii, energy, chain), the fastest measured for batches
-// of tens of thousands of atoms: the energy pass keeps two-tile items, which
-// halve its seven i-side flushes per tile.
+// Default work shapes (radii, energy, chain): one 64-atom j block per work
+// item in every pass (single-tile items, the instantiations with the fewest
+// registers), with the waves per workgroup measured fastest on batches of tens
+// of thousands of atoms.
 const gbmc_tuning kDefaultTuning32 = {{1, 1, 1}, {1, 8, 4}};
 const gbmc_tuning kDefaultTuning64 = {{1, 1, 1}, {2, 2, 2}};
 

@@ -88,20 +88,6 @@ def test_eremd_batch_all_replicas(prec):
     print(prec, worst)
 
 
-def test_uneven_batch_sampled_systems():
-    # the uneven 64-system batch runs in one launch; the smallest, the largest
-    # and one middle system are compared on every atom
-    p_gpu, p_or = params_pair()
-    systems = synth.uneven_batch_64()
-    sizes = np.array([s.n for s in systems])
-    pick = [int(np.argmin(sizes)), int(np.argmax(sizes)), int(np.argsort(sizes)[len(sizes) // 2])]
-    g, batch, plan, atoms = build(systems, "fp32")
-    res = gpu_eval(plan, atoms, p_gpu)
-    for b in pick:
-        e = compare_system(res, b, batch.atom_offset, oracle_eval(systems[b], p_or, ("c4", b)), "fp32")
-        print(b, sizes[b], e)
-
-
 def test_fp32_bitwise_deterministic_and_shape_independent():
     p_gpu, _ = params_pair()
     systems = [_sys(11, 700), _sys(12, 333)]

@@ -58,6 +58,23 @@ def _run(prec, kinds, n_sys=6, seed=11):
             cur.cpu().numpy(), counters.cpu().numpy(), {k: v.cpu().numpy() for k, v in out.items()})
 
 
+# Delta G tolerance: FP64 plan 1e-9 relative (the sweep adds the potential
+# updates of accepted moves in FP64); FP32 plan the Delta E target, 1e-4
+# kcal/mol absolute, with the oracle's own radii on both sides (the FP32
+# radii carry <= 2e-6 relative error, which moves a site's Delta E by far less).
+# Acceptance decisions are compared bitwise away from the margin |u - p| below
+# MARGIN; after a decision at the margin the rest of that system's sweep may
+# legitimately differ (later visits see the charges it left), so the
+# comparison of that system stops there.
+MARGIN = {"fp64": 1e-9, "fp32": 1e-3}
+
+
+def _dG_ok(prec, got, ref):
+    if prec == "fp64":
+        return abs(got - ref) <= 1e-9 * max(1.0, abs(ref))
+    return abs(got - ref) <= 1e-4
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("kinds", [3, 1, 2])
 def test_sweep_matches_oracle(prec, kinds):
@@ -66,27 +83,34 @@ def test_sweep_matches_oracle(prec, kinds):
     off, soff = batch.atom_offset, batch.site_state_offset
     m0 = 0
     n_acc = 0
-    tol = 1e-9 if prec == "fp64" else 2e-4
+    n_cmp = 0
+    worst = 0.0
     for b, s in enumerate(systems):
         ns = len(s.sites)
         g0, g1 = soff[m0], soff[m0 + ns]
         tab = oracle.SiteTables(s, gref[g0:g1])
-        # the FP64 plan is compared with the oracle's radii, the FP32 plan with
-        # its own (the sweep itself is FP64 on both sides)
-        R = oracle.radii(s, p_or)["R"] if prec == "fp64" else R_gpu[off[b]:off[b + 1]]
+        # both plans against the oracle's own radii (no value from the GPU path)
+        R = oracle.radii(s, p_or)["R"]
         q_or, acc_or, dG_or = oracle.mc_sweep(s, R, tab, PH, E_sys[b], T, u[m0:m0 + ns], kinds, p_or)
         acc = out["accepted"][m0:m0 + ns]
         dG = out["dG"][m0:m0 + ns]
-        for k in range(ns):
+        # visit order of the sweep: protonation sites first, each kind by ascending u[:, 0]
+        kind = np.array([site.kind for site in s.sites])
+        order = sorted(range(ns), key=lambda k: (kind[k] != 0, u[m0 + k, 0], k))
+        at_margin = False
+        for k in order:
             if acc_or[k] < 0:
                 assert acc[k] == -1
                 continue
-            assert abs(dG[k] - dG_or[k]) <= tol * max(1.0, abs(dG_or[k])), (b, k, dG[k], dG_or[k])
+            assert _dG_ok(prec, dG[k], dG_or[k]), (b, k, dG[k], dG_or[k])
+            worst = max(worst, abs(dG[k] - dG_or[k]))
+            n_cmp += 1
             p = math.exp(min(700.0, -dG_or[k] / (KB * T)))
-            if abs(u[m0 + k, 2] - p) > 1e-6:            # skip coin flips at the margin
-                assert acc[k] == acc_or[k], (b, k)
-        if all(abs(u[m0 + k, 2] - math.exp(min(700.0, -dG_or[k] / (KB * T)))) > 1e-6
-               for k in range(ns) if acc_or[k] >= 0):
+            if abs(u[m0 + k, 2] - p) <= MARGIN[prec]:
+                at_margin = True
+                break
+            assert acc[k] == acc_or[k], (b, k)
+        if not at_margin:
             assert list(cur[m0:m0 + ns]) == list(tab.current_state), b
             assert np.allclose(q_gpu[off[b]:off[b + 1]], q_or, rtol=0, atol=1e-6), b
         n_acc += int((acc == 1).sum())
@@ -94,7 +118,8 @@ def test_sweep_matches_oracle(prec, kinds):
     att = out["accepted"] >= 0
     assert np.array_equal(counters[:, 0], att.astype(np.int64))
     assert np.array_equal(counters[:, 1], (out["accepted"] == 1).astype(np.int64))
-    assert n_acc > 0
+    assert n_acc > 0 and n_cmp > 0
+    print(prec, kinds, "visits compared", n_cmp, "max |dG - ref|", worst)
     # electron counts after the sweep
     ne = np.zeros(batch.n_systems, dtype=np.int64)
     for m in range(batch.n_sites):
