@@ -198,6 +198,16 @@ gbmc_status gb_energy_forces(gbmc_plan* plan, const gbmc_atoms* atoms,
                              double* e_coul, double* e_gb, void* force, void* dEdq,
                              void* dEdrho, hipStream_t stream);
 
+/* One full evaluation: gb_radii followed by gb_energy_forces on the same
+ * workspace (Born radii from the geometry, section III.D; the electrostatic
+ * energy and its derivatives of the MD steps, section III.A, Fig. 1).  Outputs
+ * and their layout as in those two calls (born_R may be NULL; the energies and
+ * gradients as in gb_energy_forces).  Leaves the per-atom state in workspace
+ * for mc_state_dE, mc_step and mc_sweep. */
+gbmc_status gb_evaluate(gbmc_plan* plan, const gbmc_atoms* atoms, const gbmc_gb_params* params,
+                        void* workspace, void* born_R, double* e_coul, double* e_gb, void* force,
+                        void* dEdq, void* dEdrho, hipStream_t stream);
+
 /* The plain FP64 GPU form of one full evaluation: the same outputs as
  * gb_radii + gb_energy_forces of an FP64 plan (radii born_R[N], e_coul[B],
  * e_gb[B], force[N][3], dEdq[N], dEdrho[N]; each may be NULL) computed the

@@ -257,6 +257,33 @@ def energy_forces(plan: Plan, atoms: Atoms, params: GBParams = IGB5, force: bool
     return out
 
 
+def _eval_outputs(plan: Plan, force: bool, dEdq: bool, dEdrho: bool) -> dict:
+    dev, dt, n = plan.device, plan.dtype, plan.n_atoms
+    return {
+        "R": torch.empty(n, dtype=dt, device=dev),
+        "e_coul": torch.empty(plan.n_systems, dtype=torch.float64, device=dev),
+        "e_gb": torch.empty(plan.n_systems, dtype=torch.float64, device=dev),
+        "force": torch.empty((n, 3), dtype=dt, device=dev) if force else None,
+        "dEdq": torch.empty(n, dtype=dt, device=dev) if dEdq else None,
+        "dEdrho": torch.empty(n, dtype=dt, device=dev) if dEdrho else None,
+    }
+
+
+def evaluate(plan: Plan, atoms: Atoms, params: GBParams = IGB5, force: bool = True,
+             dEdq: bool = True, dEdrho: bool = True,
+             workspace: Optional[torch.Tensor] = None) -> dict:
+    """One full evaluation (gb_evaluate): Born radii R, E_C and E_GB per
+    system and the requested gradients; leaves the per-atom state in the
+    workspace (default: the plan's) for the Monte Carlo calls."""
+    out = _eval_outputs(plan, force, dEdq, dEdrho)
+    a, p = atoms.c(), params.c()
+    ws = _workspace(plan, workspace)
+    L.check(L.load().gb_evaluate(plan.handle, C.byref(a), C.byref(p), _ptr(ws), _ptr(out["R"]),
+                                 _ptr(out["e_coul"]), _ptr(out["e_gb"]), _ptr(out["force"]),
+                                 _ptr(out["dEdq"]), _ptr(out["dEdrho"]), _stream(plan.device)))
+    return out
+
+
 class Sites:
     """Titratable-site tables of a plan (static), with the site workspace.
 
@@ -475,11 +502,12 @@ def remd_exchange(E_rung: torch.Tensor, Ne_of_rep: torch.Tensor, rep_of_rung: to
     return acc[:n_pairs], Eo
 
 
-def check_overflow(plan: Plan) -> bool:
-    """True if a fixed-point accumulator overflowed since the last radii()."""
+def check_overflow(plan: Plan, workspace: Optional[torch.Tensor] = None) -> bool:
+    """True if a fixed-point accumulator overflowed since the last radii() on
+    the workspace (default: the plan's)."""
     flag = C.c_int32(0)
-    st = L.load().gbmc_check_overflow(plan.handle, _ptr(plan.workspace), _stream(plan.device),
-                                      C.byref(flag))
+    ws = _ptr(_workspace(plan, workspace))
+    st = L.load().gbmc_check_overflow(plan.handle, ws, _stream(plan.device), C.byref(flag))
     if st not in (L.GBMC_OK, L.GBMC_ERR_OVERFLOW):
         L.check(st)
     return bool(flag.value)

@@ -672,6 +672,15 @@ gbmc_status gb_energy_forces(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_pa
     return e == hipSuccess ? GBMC_OK : hip_fail(e, "gb_energy_forces launch");
 }
 
+gbmc_status gb_evaluate(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp, void* ws,
+                        void* born_R, double* e_coul, double* e_gb, void* force, void* dEdq,
+                        void* dEdrho, hipStream_t s)
+{
+    gbmc_status st = gb_radii(p, a, gp, ws, born_R, s);
+    if (st != GBMC_OK) return st;
+    return gb_energy_forces(p, a, gp, ws, e_coul, e_gb, force, dEdq, dEdrho, s);
+}
+
 // ------------------------------------------------------------------ sites
 
 gbmc_status gbmc_sites_validate(int32_t n_systems, const int32_t* off, int32_t n_sites,

@@ -209,3 +209,19 @@ def test_spatial_order_parity_and_determinism():
     perm = gpu_eval(plan64, atoms64, p_gpu)
     assert rel_inf(perm["force"], ident["force"]) <= 1e-12
     assert np.max(np.abs(perm["R"] - ident["R"]) / ident["R"]) <= 1e-13
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_evaluate_equals_radii_then_energy_forces(prec):
+    # gb_evaluate (one call) gives the outputs of gb_radii + gb_energy_forces bitwise
+    p_gpu, p_or = params_pair()
+    systems = [_sys(71, 700), _sys(72, 65), _sys(73, 1)]
+    g, batch, plan, atoms = build(systems, prec)
+    two = gpu_eval(plan, atoms, p_gpu)
+    one = g.evaluate(plan, atoms, p_gpu)
+    torch.cuda.synchronize()
+    got = {"R": one["R"], "Ec": one["e_coul"], "Egb": one["e_gb"], "force": one["force"],
+           "dEdq": one["dEdq"], "dEdrho": one["dEdrho"]}
+    for k, v in got.items():
+        assert np.array_equal(v.double().cpu().numpy(), two[k]), k
+    compare_system(two, 0, batch.atom_offset, oracle_eval(systems[0], p_or), prec)
