@@ -208,6 +208,24 @@ gbmc_status gb_evaluate(gbmc_plan* plan, const gbmc_atoms* atoms, const gbmc_gb_
                         void* workspace, void* born_R, double* e_coul, double* e_gb, void* force,
                         void* dEdq, void* dEdrho, hipStream_t stream);
 
+/* gb_evaluate without a caller workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the workspace is a library-owned static array of
+ * 256 MiB per GPU (held until the process ends), so the call itself allocates
+ * nothing.  Inputs and outputs are the caller's, as in gb_evaluate.
+ * GBMC_ERR_UNSUPPORTED if the plan needs a larger workspace than that
+ * (gbmc_plan_workspace_bytes); GBMC_ERR_HIP if the array's device address
+ * could not be obtained when the plan was created.  Every call on one GPU
+ * shares that GPU's array and leaves its per-atom state there (each call
+ * clears what must start at zero): calls that may overlap on one GPU (other
+ * streams, other threads, other plans) race and must be serialised by the
+ * caller, and the state is not meant for mc_state_dE.  The overflow flag of
+ * these calls is read with gbmc_check_overflow(plan, NULL, ...). */
+gbmc_status gb_evaluate_static(gbmc_plan* plan, const gbmc_atoms* atoms,
+                               const gbmc_gb_params* params, void* born_R, double* e_coul,
+                               double* e_gb, void* force, void* dEdq, void* dEdrho,
+                               hipStream_t stream);
+
 /* The plain FP64 GPU form of one full evaluation: the same outputs as
  * gb_radii + gb_energy_forces of an FP64 plan (radii born_R[N], e_coul[B],
  * e_gb[B], force[N][3], dEdq[N], dEdrho[N]; each may be NULL) computed the
@@ -382,7 +400,8 @@ enum {
 gbmc_status gbmc_plan_set_timing(gbmc_plan* plan, int32_t enable);
 gbmc_status gbmc_plan_kernel_ms(gbmc_plan* plan, float* ms);
 
-/* Reads and clears the workspace's fixed-point overflow flag.  Synchronises
+/* Reads and clears the workspace's fixed-point overflow flag (workspace NULL:
+ * the static scratch of gb_evaluate_static on the plan's device).  Synchronises
  * stream.  Returns GBMC_ERR_OVERFLOW (and *flag = 1) if any accumulator since
  * the last gb_radii call (which clears the flag) or the last check would have
  * exceeded 2^62 in magnitude. */

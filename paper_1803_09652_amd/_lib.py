@@ -71,6 +71,8 @@ SIGNATURES = {
                                 _VP, _VP, _VP, _VP, _VP]),
     "gb_evaluate": (_I32, [_VP, C.POINTER(gbmc_atoms), C.POINTER(gbmc_gb_params), _VP, _VP, _VP,
                            _VP, _VP, _VP, _VP, _VP]),
+    "gb_evaluate_static": (_I32, [_VP, C.POINTER(gbmc_atoms), C.POINTER(gbmc_gb_params), _VP,
+                                  _VP, _VP, _VP, _VP, _VP, _VP]),
     "gb_plain_workspace_bytes": (C.c_size_t, [_I32]),
     "gb_plain_fp64": (_I32, [_I32, _I32P, _VP, C.POINTER(gbmc_atoms), C.POINTER(gbmc_gb_params), _VP,
                              _VP, _VP, _VP, _VP, _VP, _VP, _VP]),

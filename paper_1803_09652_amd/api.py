@@ -284,6 +284,21 @@ def evaluate(plan: Plan, atoms: Atoms, params: GBParams = IGB5, force: bool = Tr
     return out
 
 
+def evaluate_static(plan: Plan, atoms: Atoms, params: GBParams = IGB5, force: bool = True,
+                    dEdq: bool = True, dEdrho: bool = True, out: Optional[dict] = None) -> dict:
+    """gb_evaluate_static: the same evaluation in the library's static scratch
+    (the call allocates no device memory).  `out` may hold preallocated
+    output tensors (keys as returned) so that the call allocates nothing on
+    the torch side either."""
+    o = out if out is not None else _eval_outputs(plan, force, dEdq, dEdrho)
+    a, p = atoms.c(), params.c()
+    L.check(L.load().gb_evaluate_static(plan.handle, C.byref(a), C.byref(p), _ptr(o["R"]),
+                                        _ptr(o["e_coul"]), _ptr(o["e_gb"]), _ptr(o["force"]),
+                                        _ptr(o["dEdq"]), _ptr(o["dEdrho"]),
+                                        _stream(plan.device)))
+    return o
+
+
 class Sites:
     """Titratable-site tables of a plan (static), with the site workspace.
 
@@ -502,11 +517,13 @@ def remd_exchange(E_rung: torch.Tensor, Ne_of_rep: torch.Tensor, rep_of_rung: to
     return acc[:n_pairs], Eo
 
 
-def check_overflow(plan: Plan, workspace: Optional[torch.Tensor] = None) -> bool:
+def check_overflow(plan: Plan, workspace: Optional[torch.Tensor] = None,
+                   static: bool = False) -> bool:
     """True if a fixed-point accumulator overflowed since the last radii() on
-    the workspace (default: the plan's)."""
+    the workspace (default: the plan's; static=True: the static scratch of
+    evaluate_static)."""
     flag = C.c_int32(0)
-    ws = _ptr(_workspace(plan, workspace))
+    ws = None if static else _ptr(_workspace(plan, workspace))
     st = L.load().gbmc_check_overflow(plan.handle, ws, _stream(plan.device), C.byref(flag))
     if st not in (L.GBMC_OK, L.GBMC_ERR_OVERFLOW):
         L.check(st)

@@ -62,6 +62,8 @@ struct gbmc_plan {
     int32_t n_chunks = 0;            // cutoff passes: block rows in chunks of 64 j blocks
     WorkItem* d_chunks = nullptr;
     int device = 0;
+    void* scratch = nullptr;         // the library's static scratch on `device`
+    hipError_t scratch_err = hipSuccess;
     // timing hook: a ring of start/stop event pairs per timed kernel (bound to
     // the dispatches while enabled), the launches recorded since the last
     // read, and the pairs handed to the current call
@@ -370,6 +372,9 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
         layout(p);
         hipError_t e = hipGetDevice(&p->device);
         if (e != hipSuccess) { delete p; return hip_fail(e, "hipGetDevice"); }
+        // the device address of the static scratch of gb_evaluate_static on this
+        // device (resolved once per device; a failure only disables that call)
+        p->scratch_err = scratch_address(p->device, &p->scratch);
         // one device allocation: the three work lists, then the processing order (identity)
         size_t at[GBMC_N_PASSES + 1];
         size_t o = 0;
@@ -679,6 +684,20 @@ gbmc_status gb_evaluate(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params*
     gbmc_status st = gb_radii(p, a, gp, ws, born_R, s);
     if (st != GBMC_OK) return st;
     return gb_energy_forces(p, a, gp, ws, e_coul, e_gb, force, dEdq, dEdrho, s);
+}
+
+gbmc_status gb_evaluate_static(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp,
+                               void* born_R, double* e_coul, double* e_gb, void* force,
+                               void* dEdq, void* dEdrho, hipStream_t s)
+{
+    if (!p) return fail(GBMC_ERR_INVALID, "plan is NULL");
+    if (p->ws_bytes > kScratchBytes)
+        return fail(GBMC_ERR_UNSUPPORTED,
+                    "gb_evaluate_static: the plan needs " + std::to_string(p->ws_bytes) +
+                        " bytes of workspace, more than the library's static scratch of " +
+                        std::to_string(kScratchBytes) + " bytes; use gb_evaluate");
+    if (!p->scratch) return hip_fail(p->scratch_err, "gb_evaluate_static: static scratch");
+    return gb_evaluate(p, a, gp, p->scratch, born_R, e_coul, e_gb, force, dEdq, dEdrho, s);
 }
 
 // ------------------------------------------------------------------ sites
@@ -1051,7 +1070,9 @@ gbmc_status gb_plain_fp64(int32_t n_systems, const int32_t* host_atom_offset,
 
 gbmc_status gbmc_check_overflow(const gbmc_plan* p, void* ws, hipStream_t s, int32_t* flag)
 {
-    if (!p || !ws || !flag) return fail(GBMC_ERR_INVALID, "NULL argument");
+    if (!p || !flag) return fail(GBMC_ERR_INVALID, "NULL argument");
+    if (!ws) ws = p->scratch;     // the static scratch of gb_evaluate_static
+    if (!ws) return fail(GBMC_ERR_INVALID, "workspace is NULL");
     int* d = reinterpret_cast<int*>(static_cast<char*>(ws) + p->off_ovf);
     int h = 0;
     hipError_t e = hipMemcpyAsync(&h, d, sizeof(int), hipMemcpyDeviceToHost, s);

@@ -215,6 +215,12 @@ hipError_t launch_plain_fp64(int n_sys, const int32_t* atom_offset, int n_atoms,
                              const double* screen, const GBConst& c, void* workspace,
                              double* born_R, double* e_coul, double* e_gb, double* force,
                              double* dEdq, double* dEdrho, hipStream_t s);
+// Library-owned device scratch of gb_evaluate_static (one per GPU): its size
+// and its device address on `device`, which must be the current device
+// (resolved with hipGetSymbolAddress on the first request per device).
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+hipError_t scratch_address(int device, void** ptr);
+
 hipError_t launch_remd_exchange(int M, const double* E_rung, const int32_t* Ne, int32_t* rep,
                                 double T_kelvin, int parity, int wrap, const double* u,
                                 int32_t* accepted, double* E_of_rep, hipStream_t s);

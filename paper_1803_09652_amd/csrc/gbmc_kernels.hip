@@ -28,6 +28,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "gbmc_internal.h"
@@ -2515,5 +2516,39 @@ hipError_t launch_remd_exchange(int M, const double* E_rung, const int32_t* Ne, 
 
 GBMC_INSTANTIATE(float)
 GBMC_INSTANTIATE(double)
+
+// ====================================================== static scratch
+// The workspace of the no-allocation entry point (gb_evaluate_static): one
+// library-owned array per GPU, held until the process ends.  In host code the
+// name `scratch` is only a host-side stand-in for the symbol; the array's
+// device address (one per GPU) is obtained with hipGetSymbolAddress once per
+// device, with that device current, and only that address is ever handed to
+// kernels.
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+}  // namespace
+
+hipError_t scratch_address(int device, void** ptr)
+{
+    *ptr = nullptr;
+    if (device < 0 || device >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        int cur = 0;
+        hipError_t e = hipGetDevice(&cur);
+        if (e != hipSuccess) return e;
+        if (cur != device) return hipErrorInvalidDevice;   // the device must be current
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
 
 }  // namespace gbmc
