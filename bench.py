@@ -40,6 +40,9 @@ E_FIXED = E0_REF                        # redox potential of batches without an 
 # directions sharing r), energy/force pass 50 + 4, chain pass 75 + 5 (both
 # dH/dr directions and dH/dS).
 FLOPS_PER_PAIR = {"radii_pairs": 60, "energy_pairs": 54, "chain_pairs": 80}
+# the persistent launches: the energy and chain passes together, and all three
+FLOPS_PER_PAIR["force_pairs"] = FLOPS_PER_PAIR["energy_pairs"] + FLOPS_PER_PAIR["chain_pairs"]
+FLOPS_PER_PAIR["evaluate_pairs"] = FLOPS_PER_PAIR["radii_pairs"] + FLOPS_PER_PAIR["force_pairs"]
 # Peaks (MI355X, 256 CUs at 2.4 GHz): FP32 vector 157.3 TFLOP/s, FP64 vector
 # 78.6 TFLOP/s.  The library's device code has packed-FP32 instructions
 # disabled, yet the FP32 value is the attainable one: the FP32 pair kernels
@@ -68,7 +71,7 @@ def parse():
     ap.add_argument("--no-extras", action="store_true",
                     help="headline workload only (no E-REMD batch, sweep, salt, dynamics loop, "
                          "cutoff or autograd measurements)")
-    ap.add_argument("--only", choices=["headline", "eremd"], default=None,
+    ap.add_argument("--only", choices=["headline", "eremd", "single"], default=None,
                     help="run one workload's GPU measurement alone and print its JSON object "
                          "(for profiling it)")
     ap.add_argument("--eremd-steps", type=int, default=200,
@@ -446,6 +449,58 @@ def time_plain_fp64(w, reps=3):
             "form": "radii + energy + forces + dE/dq + dE/drho, every ordered pair, FP64"}
 
 
+def time_single_launch(systems, reps=5, precision="fp32"):
+    """One full evaluation (radii, energy, forces, dE/dq, dE/drho) of the
+    batch as gb_evaluate's single queued launch (all three pair passes, with
+    per-block dependency counters), beside gb_radii + gb_energy_forces (one
+    launch per pass), eager, on the same plan and inputs: HIP events around
+    each evaluation, and the timing hook's per-kernel means."""
+    import torch
+    import paper_1803_09652_amd as g
+    import synth
+    b = synth.make_batch(systems)
+    plan = g.Plan(b.atom_offset, precision)
+    plan.set_order(g.spatial_order(b.atom_offset, b.x, b.y, b.z))
+    atoms = g.Atoms.from_batch(plan, b)
+    pairs = pair_count(systems)
+
+    def single():
+        plan.set_single_launch(True)
+        g.evaluate(plan, atoms, g.IGB5)
+
+    def separate():
+        plan.set_single_launch(False)
+        g.radii(plan, atoms, g.IGB5)
+        g.energy_forces(plan, atoms, g.IGB5)
+
+    out = {"pairs": pairs}
+    for name, fn in (("single_launch", single), ("separate_launches", separate)):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        plan.set_timing(True)
+        plan.kernel_ms()
+        for _ in range(reps):
+            fn()
+        kms = plan.kernel_ms()
+        plan.set_timing(False)
+        out[name] = {"ms_per_evaluation": ms, "pair_interactions_per_s": pairs / (ms * 1e-3),
+                     "kernel_ms": kms, "overflow_or_wait_error": bool(g.check_overflow(plan))}
+    ev = out["single_launch"]["kernel_ms"].get("evaluate_pairs")
+    if ev:
+        ach = FLOPS_PER_PAIR["evaluate_pairs"] * pairs / (ev * 1e-3) / 1e12
+        out["single_launch"]["tflops"] = ach
+        out["single_launch"]["frac_of_fp32_peak"] = ach / PEAK_TFLOPS["fp32"]
+    return out
+
+
 def pair_count(systems):
     return int(sum(s_.n * (s_.n - 1) // 2 for s_ in systems))
 
@@ -746,6 +801,11 @@ def main():
                                 args.kernel_steps, **run)
         print(json.dumps(r), flush=True)
         return
+    if args.only == "single":
+        print(json.dumps({"uneven_batch": time_single_launch(synth.uneven_batch_64(), reps=3),
+                          "eremd_batch": time_single_launch(synth.eremd_batch(), reps=20)}),
+              flush=True)
+        return
     if args.only == "eremd":
         r, _ = measure_workload(synth.eremd_batch(), True, args.eremd_steps, args.warmup,
                                 args.kernel_steps, **run)
@@ -812,6 +872,7 @@ def main():
     out["fp32_over_fp64_plain"] = value / out["fp64_plain"]["value"]
     del w
     torch.cuda.empty_cache()
+    out["single_launch"] = time_single_launch(systems, reps=3)
     if not args.no_fp64:
         r64, w64 = measure_workload(systems, False, args.fp64_steps, 2, 1, precision="fp64", **run)
         out["fp64"] = {k_: r64[k_] for k_ in ("ms_per_step", "pair_interactions_per_s",
@@ -846,6 +907,7 @@ def main():
         er["roofline"] = roofline_of(er["pairs_per_step"], er["kernel_ms_force_passes_alone"])
         er["fp64_plain"] = time_plain_fp64(we, reps=2)
         er["fp32_over_fp64_plain"] = er["pair_interactions_per_s"] / er["fp64_plain"]["value"]
+        er["single_launch"] = time_single_launch(synth.eremd_batch(), reps=20)
         er["mc_sweep"] = time_sweep(we)
         er["salt"] = time_salt(we)
         del we

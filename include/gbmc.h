@@ -379,6 +379,27 @@ gbmc_status remd_exchange(int32_t n_rep, const double* E_rung, const int32_t* Ne
                           const double* u, int32_t* accepted, double* E_of_rep,
                           hipStream_t stream);
 
+/* Single-launch mode of gb_evaluate (off by default).  With enable != 0 a
+ * full evaluation without cutoffs (forces or dE/drho requested) runs its three
+ * pair passes as one kernel launch instead of one launch per pass.  Its work
+ * items form one sequence in pass order; each workgroup takes the next ticket
+ * from a device counter when it starts and runs the items of that ticket, so
+ * items start in sequence order.  An item of the energy or chain pass first
+ * waits until the 64-atom blocks it reads are final in the preceding pass
+ * (per-block completion counters; the wave that completes a block finalizes
+ * it).  Such a wait only ever waits for items that started earlier, so it
+ * ends; it is bounded all the same, by wait_polls polls (each about a
+ * microsecond; 0 with enable != 0: give up at once, which forces the failure
+ * path in tests; 0 with enable == 0 keeps the current bound; the default is
+ * 4194304, seconds, far beyond any wait the schedule produces).  A wave whose
+ * wait gives up sets the error flag that gbmc_check_overflow reports, and the
+ * launch drains without computing the remaining items.  Results are bitwise
+ * those of the separate launches.  On the MI355X the separate launches are
+ * faster (the same-address ticket counter and the wait for each item's
+ * fixed-point atomics before it counts itself done cost more than the
+ * overlap of the passes gains), hence the default. */
+gbmc_status gbmc_plan_set_single_launch(gbmc_plan* plan, int32_t enable, int32_t wait_polls);
+
 /* Kernel timing hook (tracing).  While enabled, every compute call on this
  * plan launches each kernel of the hot path with a start and a stop HIP event
  * bound to the dispatch itself (hipExtLaunchKernelGGL), so that their interval
@@ -395,16 +416,20 @@ enum {
     GBMC_K_SITE_ROWS = 3,      /* FP64 potential rows of mc_state_dE */
     GBMC_K_SITE_DE = 4,        /* per-site Delta E / Delta G of mc_state_dE */
     GBMC_K_MC_STEP = 5,        /* Metropolis step */
-    GBMC_N_KERNELS = 6
+    GBMC_K_FORCE_PAIRS = 6,    /* (reserved) */
+    GBMC_K_EVAL_PAIRS = 7,     /* single launch of all three passes (gb_evaluate) */
+    GBMC_N_KERNELS = 8
 };
 gbmc_status gbmc_plan_set_timing(gbmc_plan* plan, int32_t enable);
 gbmc_status gbmc_plan_kernel_ms(gbmc_plan* plan, float* ms);
 
-/* Reads and clears the workspace's fixed-point overflow flag (workspace NULL:
- * the static scratch of gb_evaluate_static on the plan's device).  Synchronises
- * stream.  Returns GBMC_ERR_OVERFLOW (and *flag = 1) if any accumulator since
- * the last gb_radii call (which clears the flag) or the last check would have
- * exceeded 2^62 in magnitude. */
+/* Reads and clears the workspace's error flags (workspace NULL: the static
+ * scratch of gb_evaluate_static on the plan's device).  Synchronises stream.
+ * *flag = 1 if, since the last gb_radii / gb_evaluate call (which clears the
+ * flags) or the last check, a fixed-point accumulator would have exceeded 2^62
+ * in magnitude (returns GBMC_ERR_OVERFLOW) or a dependency wait of a
+ * queued launch gave up (returns GBMC_ERR_HIP; the results of that call
+ * are not valid). */
 gbmc_status gbmc_check_overflow(const gbmc_plan* plan, void* workspace, hipStream_t stream,
                                 int32_t* flag);
 

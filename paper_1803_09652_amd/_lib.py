@@ -18,7 +18,8 @@ GBMC_ERR_OVERFLOW = -3
 GBMC_ERR_UNSUPPORTED = -4
 GBMC_FP32_FIXED = 0
 GBMC_FP64 = 1
-KERNEL_NAMES = ("radii_pairs", "energy_pairs", "chain_pairs", "site_rows", "site_dE", "mc_step")
+KERNEL_NAMES = ("radii_pairs", "energy_pairs", "chain_pairs", "site_rows", "site_dE", "mc_step",
+                "force_pairs", "evaluate_pairs")
 
 _STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "HIP", -3: "OVERFLOW", -4: "UNSUPPORTED"}
 
@@ -91,6 +92,7 @@ SIGNATURES = {
                         _VP, _VP, _VP, _D, _I32, _VP, _VP, _VP, _VP, _VP, _VP]),
     "md_langevin_step": (_I32, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _D, _D, _D, _D, _VP]),
     "remd_exchange": (_I32, [_I32, _VP, _VP, _VP, _D, _I32, _I32, _VP, _VP, _VP, _VP]),
+    "gbmc_plan_set_single_launch": (_I32, [_VP, _I32, _I32]),
     "gbmc_plan_set_timing": (_I32, [_VP, _I32]),
     "gbmc_plan_kernel_ms": (_I32, [_VP, C.POINTER(C.c_float)]),
     "gbmc_check_overflow": (_I32, [_VP, _VP, _VP, _I32P]),

@@ -146,6 +146,12 @@ class Plan:
         with torch.cuda.device(self.device):
             L.check(L.load().gbmc_plan_set_order(self._h, _i32p(o)))
 
+    def set_single_launch(self, enable: bool = True, wait_polls: int = 1 << 22) -> None:
+        """evaluate() as one kernel launch of the three pair passes (with
+        bounded dependency waits of wait_polls polls; 0 gives up at once, for
+        tests) instead of one launch per pass (the default, faster here)."""
+        L.check(L.load().gbmc_plan_set_single_launch(self._h, int(bool(enable)), int(wait_polls)))
+
     def set_timing(self, enable: bool = True) -> None:
         """Time each hot-path kernel of later eager calls (HIP events bound to
         the dispatch).  Disable before capturing a graph."""
@@ -519,13 +525,14 @@ def remd_exchange(E_rung: torch.Tensor, Ne_of_rep: torch.Tensor, rep_of_rung: to
 
 def check_overflow(plan: Plan, workspace: Optional[torch.Tensor] = None,
                    static: bool = False) -> bool:
-    """True if a fixed-point accumulator overflowed since the last radii() on
-    the workspace (default: the plan's; static=True: the static scratch of
-    evaluate_static)."""
+    """True if, since the last radii() on the workspace (default: the plan's;
+    static=True: the static scratch of evaluate_static), a fixed-point
+    accumulator overflowed or a dependency wait of a queued launch gave up
+    (the results are then not valid); reading clears the flags."""
     flag = C.c_int32(0)
     ws = None if static else _ptr(_workspace(plan, workspace))
     st = L.load().gbmc_check_overflow(plan.handle, ws, _stream(plan.device), C.byref(flag))
-    if st not in (L.GBMC_OK, L.GBMC_ERR_OVERFLOW):
+    if st != L.GBMC_OK and not flag.value:
         L.check(st)
     return bool(flag.value)
 

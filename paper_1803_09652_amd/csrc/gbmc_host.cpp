@@ -44,6 +44,11 @@ constexpr int64_t kTimedMax = 256;   // launches kept per timed kernel between r
 const gbmc_tuning kDefaultTuning32 = {{1, 1, 1}, {1, 8, 4}};
 const gbmc_tuning kDefaultTuning64 = {{1, 1, 1}, {2, 2, 2}};
 
+// Queued launch: the polls (each after a short sleep, about a microsecond
+// apiece) before a dependency wait gives up: seconds, far beyond any wait the
+// schedule produces.
+constexpr int kDefaultSpinLimit = 1 << 22;
+
 }  // namespace
 
 struct gbmc_plan {
@@ -59,6 +64,10 @@ struct gbmc_plan {
     int32_t* d_offset = nullptr;     // [B+1] device copy of the atom offsets
     int32_t n_blocks = 0;            // 64-atom blocks of the batch
     BlockSpan* d_blocks = nullptr;   // [n_blocks] atoms of each block (processing order)
+    int32_t* d_total = nullptr;      // [3][n_blocks] items of each pass touching each block
+    int n_cu = 0;                    // compute units of the device
+    bool single_launch = false;           // gb_evaluate as one queued launch
+    int spin_limit = kDefaultSpinLimit;   // polls before a wait of a queued launch gives up
     int32_t n_chunks = 0;            // cutoff passes: block rows in chunks of 64 j blocks
     WorkItem* d_chunks = nullptr;
     int device = 0;
@@ -73,7 +82,7 @@ struct gbmc_plan {
     hipEvent_t cur[2 * kNumKernels] = {};
     // workspace layout (byte offsets)
     size_t off_I, off_F, off_G, off_phi, off_drho, off_EA, off_I64, off_R64, off_T64, off_dR64,
-        off_G64, off_B64, off_Rt, off_at, off_Brt, off_ovf, off_P, off_Gx, off_A64, off_rows, off_bnd,
+        off_G64, off_B64, off_Rt, off_at, off_Brt, off_ovf, off_q, off_P, off_Gx, off_A64, off_rows, off_bnd,
         off_smax, off_cit0, off_cit1, off_ccount, ws_bytes;
     int32_t cut_cap = 0;             // capacity of each compacted cutoff work list
 };
@@ -154,6 +163,18 @@ static gbmc_status build_items(int32_t n_systems, const int32_t* off, int32_t jb
     return GBMC_OK;
 }
 
+// Distinct 64-atom blocks of a work item: its i blocks [I, I + rows), then
+// its j blocks [J0, J1) other than those (J0 >= I).  The queued launch
+// counts an item done on each of them.
+static int32_t item_blocks(const WorkItem& w)
+{
+    return w.rows + std::max(0, w.J1 - std::max(w.J0, w.I + w.rows));
+}
+static int32_t item_block(const WorkItem& w, int32_t k)
+{
+    return k < w.rows ? w.I + k : std::max(w.J0, w.I + w.rows) + (k - w.rows);
+}
+
 static gbmc_status check_tuning(const gbmc_tuning* in, gbmc_precision prec, gbmc_tuning& out)
 {
     out = prec == GBMC_FP64 ? kDefaultTuning64 : kDefaultTuning32;
@@ -197,6 +218,8 @@ static Work<T> carve(const gbmc_plan* p, void* ws)
     w.a_t = reinterpret_cast<T*>(b + p->off_at);
     w.Brt_t = reinterpret_cast<T*>(b + p->off_Brt);
     w.ovf = reinterpret_cast<int*>(b + p->off_ovf);
+    w.qhead = reinterpret_cast<int*>(b + p->off_q);
+    w.qcnt = reinterpret_cast<int*>(b + p->off_q + 4 * (size_t)kQueueWords);
     w.bnd = reinterpret_cast<Q4<float>*>(b + p->off_bnd);
     w.smax = reinterpret_cast<float*>(b + p->off_smax);
     w.citems[0] = reinterpret_cast<CutItem*>(b + p->off_cit0);
@@ -240,6 +263,8 @@ static void layout(gbmc_plan* p)
     p->off_cit0 = seg(sizeof(CutItem) * (size_t)p->cut_cap);
     p->off_cit1 = seg(sizeof(CutItem) * (size_t)p->cut_cap);
     p->off_ccount = seg(2 * sizeof(int));
+    // queue counters (one 128-byte line each), the error word, block counters
+    p->off_q = seg(4 * (size_t)kQueueWords + 4 * 3 * (size_t)p->n_blocks);
     p->ws_bytes = o;
 }
 
@@ -347,6 +372,28 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
         for (int k = 0; k < GBMC_N_PASSES; ++k)
             build_items(n_systems, host_atom_offset, t.j_blocks_per_item[k],
                         precision == GBMC_FP32_FIXED && k == GBMC_PASS_ENERGY, items[k]);
+        // The queued launch runs a pass's items before the next pass's; a
+        // block of the next pass can start once every item touching it is
+        // done.  The descreening and energy passes therefore take their items
+        // system by system (largest system first, each system's items by
+        // decreasing cost), so whole systems finish early and the next pass
+        // starts on them while the last systems finish; the chain pass, which
+        // ends the launch, keeps the global decreasing-cost order.
+        {
+            std::vector<int32_t> rank(n_systems);
+            for (int32_t b = 0; b < n_systems; ++b) rank[b] = b;
+            std::stable_sort(rank.begin(), rank.end(), [&](int32_t a, int32_t c) {
+                return host_atom_offset[a + 1] - host_atom_offset[a] >
+                       host_atom_offset[c + 1] - host_atom_offset[c];
+            });
+            std::vector<int32_t> pos(n_systems);
+            for (int32_t r = 0; r < n_systems; ++r) pos[rank[r]] = r;
+            for (int k : {GBMC_PASS_RADII, GBMC_PASS_ENERGY})
+                std::stable_sort(items[k].begin(), items[k].end(),
+                                 [&](const WorkItem& a, const WorkItem& c) {
+                                     return pos[a.sys] < pos[c.sys];
+                                 });
+        }
         auto* p = new gbmc_plan();
         p->n_sys = n_systems;
         p->n_atoms = n_systems > 0 ? host_atom_offset[n_systems] : 0;
@@ -375,6 +422,15 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
         // the device address of the static scratch of gb_evaluate_static on this
         // device (resolved once per device; a failure only disables that call)
         p->scratch_err = scratch_address(p->device, &p->scratch);
+        e = hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device);
+        if (e != hipSuccess) { delete p; return hip_fail(e, "hipDeviceGetAttribute"); }
+        // items of each pass touching each block (the counts the queued
+        // launch's per-block counters complete at)
+        std::vector<int32_t> totals((size_t)GBMC_N_PASSES * p->n_blocks, 0);
+        for (int k = 0; k < GBMC_N_PASSES; ++k)
+            for (const WorkItem& w : items[k])
+                for (int32_t d = 0; d < item_blocks(w); ++d)
+                    ++totals[(size_t)k * p->n_blocks + w.blk0 + item_block(w, d)];
         // one device allocation: the three work lists, then the processing order (identity)
         size_t at[GBMC_N_PASSES + 1];
         size_t o = 0;
@@ -389,7 +445,8 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
         const size_t at_off = align256(o + 4 * (size_t)p->n_atoms);
         const size_t at_blk = align256(at_off + off_bytes);
         const size_t at_chk = align256(at_blk + sizeof(BlockSpan) * blocks.size());
-        const size_t total = at_chk + sizeof(WorkItem) * chunks.size();
+        const size_t at_tot = align256(at_chk + sizeof(WorkItem) * chunks.size());
+        const size_t total = at_tot + sizeof(int32_t) * totals.size();
         if (total > 0) {
             char* d = nullptr;
             e = hipMalloc(&d, total);
@@ -412,6 +469,9 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
             p->d_chunks = reinterpret_cast<WorkItem*>(d + at_chk);
             if (!chunks.empty())
                 std::memcpy(h.data() + at_chk, chunks.data(), sizeof(WorkItem) * chunks.size());
+            p->d_total = reinterpret_cast<int32_t*>(d + at_tot);
+            if (!totals.empty())
+                std::memcpy(h.data() + at_tot, totals.data(), sizeof(int32_t) * totals.size());
             e = hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice);
             if (e != hipSuccess) { (void)hipFree(d); delete p; return hip_fail(e, "hipMemcpy(plan tables)"); }
         }
@@ -620,6 +680,45 @@ static hipEvent_t* events(gbmc_plan* p, std::initializer_list<int> ids)
     return p->cur;
 }
 
+}  // extern "C"
+
+static bool uses_cutoffs(const GBConst& c) { return c.rgbmax > 0.0 || c.cutoff > 0.0; }
+
+static QueueShape queue_shape(const gbmc_plan* p)
+{
+    QueueShape sh{};
+    for (int k = 0; k < GBMC_N_PASSES; ++k) {
+        sh.items[k] = p->d_items[k];
+        sh.n_items[k] = p->n_items[k];
+    }
+    sh.total = p->d_total;
+    sh.n_blocks = p->n_blocks;
+    sh.one_tile = p->tuning.j_blocks_per_item[GBMC_PASS_ENERGY] == 1 &&
+                  p->tuning.j_blocks_per_item[GBMC_PASS_CHAIN] == 1;
+    sh.spin_limit = p->spin_limit;
+    sh.n_cu = p->n_cu;
+    return sh;
+}
+
+// The three all-pairs passes of a full evaluation as one queued launch
+// (staging and output kernels around it); timed as kernel `id` by the timing
+// hook.
+template <typename T>
+static hipError_t run_queued(gbmc_plan* p, const gbmc_atoms* a, const GBConst& c, void* ws,
+                             void* born_R, double* e_coul, double* e_gb, void* force, void* dEdq,
+                             void* dEdrho, hipStream_t s, int id)
+{
+    int n = 0;
+    for (int k = 0; k < GBMC_N_PASSES; ++k) n += p->n_items[k];
+    hipEvent_t* ev = n > 0 ? events(p, {id}) : nullptr;
+    return launch_queued<T>(queue_shape(p), p->n_atoms, p->n_sys, (const T*)a->x, (const T*)a->y,
+                            (const T*)a->z, (const T*)a->q, (const T*)a->rho,
+                            (const T*)a->screen, c, carve<T>(p, ws), (T*)born_R, e_coul, e_gb,
+                            (T*)force, (T*)dEdq, (T*)dEdrho, s, ev, id);
+}
+
+extern "C" {
+
 gbmc_status gb_radii(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp, void* ws,
                      void* born_R, hipStream_t s)
 {
@@ -627,20 +726,21 @@ gbmc_status gb_radii(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp
     if (st != GBMC_OK || p->n_atoms == 0) return st;
     GBConst c = make_const(gp);
     hipError_t e;
-    if (p->prec == GBMC_FP32_FIXED)
+    if (p->prec == GBMC_FP32_FIXED) {
         e = launch_radii<float>(p->d_items[GBMC_PASS_RADII], p->n_items[GBMC_PASS_RADII],
                                 p->tuning.waves_per_group[GBMC_PASS_RADII], p->n_atoms,
                                 cut_plan(p), (const float*)a->x,
                                 (const float*)a->y, (const float*)a->z, (const float*)a->rho,
                                 (const float*)a->screen, c, carve<float>(p, ws), (float*)born_R, s,
                                 p->n_items[GBMC_PASS_RADII] > 0 ? events(p, {kKRadii}) : nullptr);
-    else
+    } else {
         e = launch_radii<double>(p->d_items[GBMC_PASS_RADII], p->n_items[GBMC_PASS_RADII],
                                  p->tuning.waves_per_group[GBMC_PASS_RADII], p->n_atoms,
                                  cut_plan(p), (const double*)a->x,
                                  (const double*)a->y, (const double*)a->z, (const double*)a->rho,
                                  (const double*)a->screen, c, carve<double>(p, ws), (double*)born_R, s,
                                  p->n_items[GBMC_PASS_RADII] > 0 ? events(p, {kKRadii}) : nullptr);
+    }
     return e == hipSuccess ? GBMC_OK : hip_fail(e, "gb_radii launch");
 }
 
@@ -651,16 +751,17 @@ gbmc_status gb_energy_forces(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_pa
     gbmc_status st = check_call(p, a, gp, ws, true);
     if (st != GBMC_OK) return st;
     GBConst c = make_const(gp);
+    const bool chain = force || dEdrho;
+    hipError_t e;
     hipEvent_t* ev = nullptr;
     if (p->n_items[GBMC_PASS_ENERGY] > 0)
-        ev = (force || dEdrho) ? events(p, {kKEnergy, kKChain}) : events(p, {kKEnergy});
+        ev = chain ? events(p, {kKEnergy, kKChain}) : events(p, {kKEnergy});
     const PassShape pe{p->d_items[GBMC_PASS_ENERGY], p->n_items[GBMC_PASS_ENERGY],
                        p->tuning.waves_per_group[GBMC_PASS_ENERGY],
                        p->tuning.j_blocks_per_item[GBMC_PASS_ENERGY] == 1};
     const PassShape pc{p->d_items[GBMC_PASS_CHAIN], p->n_items[GBMC_PASS_CHAIN],
                        p->tuning.waves_per_group[GBMC_PASS_CHAIN],
                        p->tuning.j_blocks_per_item[GBMC_PASS_CHAIN] == 1};
-    hipError_t e;
     if (p->prec == GBMC_FP32_FIXED)
         e = launch_energy_forces<float>(pe, pc, p->n_atoms, p->n_sys, cut_plan(p),
                                         (const float*)a->x, (const float*)a->y, (const float*)a->z,
@@ -681,9 +782,33 @@ gbmc_status gb_evaluate(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params*
                         void* born_R, double* e_coul, double* e_gb, void* force, void* dEdq,
                         void* dEdrho, hipStream_t s)
 {
-    gbmc_status st = gb_radii(p, a, gp, ws, born_R, s);
-    if (st != GBMC_OK) return st;
-    return gb_energy_forces(p, a, gp, ws, e_coul, e_gb, force, dEdq, dEdrho, s);
+    gbmc_status st = check_call(p, a, gp, ws, true);
+    if (st != GBMC_OK || p->n_atoms == 0) return st;
+    GBConst c = make_const(gp);
+    // in single-launch mode the three all-pairs passes of a full evaluation
+    // (forces or dE/drho requested) run as one queued launch; otherwise, and
+    // with cutoffs, as the separate launches of gb_radii and gb_energy_forces
+    const bool chain = force || dEdrho;
+    if (!p->single_launch || uses_cutoffs(c) || !chain) {
+        st = gb_radii(p, a, gp, ws, born_R, s);
+        if (st != GBMC_OK) return st;
+        return gb_energy_forces(p, a, gp, ws, e_coul, e_gb, force, dEdq, dEdrho, s);
+    }
+    hipError_t e = p->prec == GBMC_FP32_FIXED
+                       ? run_queued<float>(p, a, c, ws, born_R, e_coul, e_gb, force, dEdq, dEdrho,
+                                           s, kKEval)
+                       : run_queued<double>(p, a, c, ws, born_R, e_coul, e_gb, force, dEdq,
+                                            dEdrho, s, kKEval);
+    return e == hipSuccess ? GBMC_OK : hip_fail(e, "gb_evaluate launch");
+}
+
+gbmc_status gbmc_plan_set_single_launch(gbmc_plan* p, int32_t enable, int32_t wait_polls)
+{
+    if (!p) return fail(GBMC_ERR_INVALID, "plan is NULL");
+    if (wait_polls < 0) return fail(GBMC_ERR_INVALID, "wait_polls must be >= 0");
+    p->single_launch = enable != 0;
+    if (wait_polls > 0 || enable) p->spin_limit = wait_polls;
+    return GBMC_OK;
 }
 
 gbmc_status gb_evaluate_static(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp,
@@ -1073,17 +1198,22 @@ gbmc_status gbmc_check_overflow(const gbmc_plan* p, void* ws, hipStream_t s, int
     if (!p || !flag) return fail(GBMC_ERR_INVALID, "NULL argument");
     if (!ws) ws = p->scratch;     // the static scratch of gb_evaluate_static
     if (!ws) return fail(GBMC_ERR_INVALID, "workspace is NULL");
+    // two words: [0] a fixed-point accumulator overflowed, [1] a dependency
+    // wait of a queued launch gave up (its results are not valid)
     int* d = reinterpret_cast<int*>(static_cast<char*>(ws) + p->off_ovf);
-    int h = 0;
-    hipError_t e = hipMemcpyAsync(&h, d, sizeof(int), hipMemcpyDeviceToHost, s);
+    int h[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(h, d, sizeof(h), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "gbmc_check_overflow");
-    *flag = h ? 1 : 0;
-    if (h) {
-        const int zero = 0;
-        e = hipMemcpyAsync(d, &zero, sizeof(int), hipMemcpyHostToDevice, s);
+    *flag = (h[0] || h[1]) ? 1 : 0;
+    if (*flag) {
+        const int zero[2] = {0, 0};
+        e = hipMemcpyAsync(d, zero, sizeof(zero), hipMemcpyHostToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "gbmc_check_overflow");
+        if (h[1])
+            return fail(GBMC_ERR_HIP, "a dependency wait of a queued launch gave up "
+                                      "(see gbmc_plan_set_wait_limit); the results are not valid");
         return fail(GBMC_ERR_OVERFLOW, "a fixed-point accumulator overflowed");
     }
     return GBMC_OK;

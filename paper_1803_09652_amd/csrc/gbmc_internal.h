@@ -104,13 +104,33 @@ struct Work {
     T* R_t;                       // [N] internal: Born radius in the pair precision
     T* a_t;                       // [N] internal: sqrt(log2(e)/4) / R
     T* Brt_t;                     // [N] internal: B * (rho - offset)
-    int* ovf;                     // overflow flag
+    int* ovf;                     // [2]: fixed-point overflow; a wait of a queued
+                                  //  launch gave up (both since the last radii call)
+    int* qhead;                   // [kQueueWords]: ticket counter ([0]) and error word ([32])
+                                  //  of the queued launch
+    int* qcnt;                    // [3][n_blocks]: per-block item counters of the passes
     Q4<float>* bnd;               // [n_blocks] bounding sphere of each block: centre, radius
     float* smax;                  // [n_blocks] largest S = screen (rho - offset) of each block
     CutItem* citems[2];           // [cut_cap] each: compacted items (0: descreening and
                                   //  chain passes, 1: energy pass)
     int* ccount;                  // [2] their counts
     int cut_cap;                  // capacity of each list: n_chunks * (kCutChunk / kCutTiles)
+};
+
+// What a staging kernel clears besides packing the atoms: up to two runs of
+// fixed-point accumulators ([n_acc][N] int64 each), two small int flag arrays
+// and an int counter array.
+struct StageClear {
+    unsigned long long* acc0 = nullptr;
+    int n_acc0 = 0;
+    unsigned long long* acc1 = nullptr;
+    int n_acc1 = 0;
+    int* f0 = nullptr;
+    int n_f0 = 0;
+    int* f1 = nullptr;
+    int n_f1 = 0;
+    int* cnt = nullptr;
+    int n_cnt = 0;
 };
 
 struct SiteDev {
@@ -159,8 +179,12 @@ struct SaltK {
 };
 
 // Kernel ids of the timing hook (events ev[2 id] / ev[2 id + 1] bracket a kernel).
+// kKRadii, kKEnergy, kKChain: the passes as separate launches (with cutoffs);
+// kKRadii also the queued launch of the descreening pass alone, kKForce
+// the queued launch of the energy and chain passes, kKEval the queued
+// launch of all three.
 enum KernelId { kKRadii = 0, kKEnergy = 1, kKChain = 2, kKSiteRows = 3, kKSiteDE = 4, kKMCStep = 5,
-                kNumKernels = 6 };
+                kKForce = 6, kKEval = 7, kNumKernels = 8 };
 
 // Launchers (gbmc_kernels.hip).  All return hipSuccess or the launch error.
 // ev (nullable) holds 2 * kNumKernels events: the start and stop events bound to
@@ -185,6 +209,31 @@ hipError_t launch_energy_forces(const PassShape& energy, const PassShape& chain,
                                 const T* screen, const GBConst& c, const Work<T>& w,
                                 double* e_coul, double* e_gb, T* force, T* dEdq, T* dEdrho,
                                 hipStream_t s, hipEvent_t* ev);
+// Ints of the workspace taken by the queued launch's ticket counter and error
+// word (on separate 128-byte lines).
+constexpr int kQueueWords = 64;
+
+// The queued launch of the all-pairs passes: the plan's three work
+// lists, the number of items of each pass touching each 64-atom block
+// ([3][n_blocks], plan memory) and the launch parameters.
+struct QueueShape {
+    const WorkItem* items[3];
+    int n_items[3];
+    const int* total;
+    int n_blocks;
+    bool one_tile;          // energy and chain items are single tiles
+    int spin_limit;         // polls before a dependency wait gives up
+    int n_cu;               // compute units of the device
+};
+
+// Staging, the three all-pairs passes (descreening, energy / explicit
+// forces with gradients, Born chain) in one queued launch, and the outputs.
+template <typename T>
+hipError_t launch_queued(const QueueShape& sh, int n_atoms, int n_sys, const T* x, const T* y,
+                         const T* z, const T* q, const T* rho, const T* screen, const GBConst& c,
+                         const Work<T>& w, T* born_R, double* e_coul, double* e_gb, T* force,
+                         T* dEdq, T* dEdrho, hipStream_t s, hipEvent_t* ev, int timing_id);
+
 template <typename T>
 hipError_t launch_state_dE(const SiteDev& sd, int n_atoms, const T* x, const T* y, const T* z,
                            const T* q, const GBConst& c, const Work<T>& w, unsigned long long* phi_fx,

@@ -109,6 +109,21 @@ __device__ __forceinline__ void fx_add(unsigned long long* p, long long v)
     atomicAdd(p, (unsigned long long)v);
 }
 
+// Per-atom values that one wave of a queued launch writes and other waves
+// of the same launch read (Born radii and chain weights of finished blocks)
+// move through device-scope loads and stores (sc1: coherent across the L2
+// caches of the XCDs, which plain loads are not within one launch).
+template <typename T>
+__device__ __forceinline__ T ld_dev(const T* p)
+{
+    return __hip_atomic_load(const_cast<T*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void st_dev(T* p, T v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // --------------------------------------------------- cross-lane movement
 // rot1: lane l receives lane (l + 1) mod 64 (DPP wave_rol:1, all lanes active).
 __device__ __forceinline__ int rot1i(int v)
@@ -790,14 +805,17 @@ template <typename T>
 __global__ void k_stage(int n_atoms, const int32_t* __restrict__ perm, const T* __restrict__ X,
                         const T* __restrict__ Y, const T* __restrict__ Z, const T* __restrict__ Q,
                         const T* __restrict__ RHO, const T* __restrict__ SCR, T offset,
-                        Q4<T>* __restrict__ P, Q4<T>* __restrict__ Gx,
-                        unsigned long long* __restrict__ acc, int n_acc, int* __restrict__ ovf)
+                        Q4<T>* __restrict__ P, Q4<T>* __restrict__ Gx, StageClear z)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k == 0 && ovf) *ovf = 0;
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    // flags and counters of the call start at zero
+    if (k < z.n_f0) z.f0[k] = 0;
+    if (k < z.n_f1) z.f1[k] = 0;
+    for (int i = k; i < z.n_cnt; i += gridDim.x * blockDim.x) z.cnt[i] = 0;
     if (k >= n_atoms) return;
-    // the pass's n_acc fixed-point accumulators of atom k ([n_acc][N]) start at zero
-    for (int a = 0; a < n_acc; ++a) acc[(size_t)a * n_atoms + k] = 0ull;
+    // the call's fixed-point accumulators of atom k ([n_acc][N] each) start at zero
+    for (int a = 0; a < z.n_acc0; ++a) z.acc0[(size_t)a * n_atoms + k] = 0ull;
+    for (int a = 0; a < z.n_acc1; ++a) z.acc1[(size_t)a * n_atoms + k] = 0ull;
     int c = perm[k];
     Q4<T> p;
     p.x = X[c]; p.y = Y[c]; p.z = Z[c];
@@ -1141,14 +1159,16 @@ __global__ __launch_bounds__(kTile * W) void k_radii_pairs(
     // slower: fewer waves in flight for less saved work)
     if constexpr (CUT) {
         const int n = *n_citems;
-        for (int it = blockIdx.x * W + wave; it < n; it += gridDim.x * W) {
+        for (int it = __builtin_amdgcn_readfirstlane(blockIdx.x * W + wave); it < n;
+             it += gridDim.x * W) {
             unsigned long long m;
             const WorkItem w = cut_work_item(citems[it], m);
             radii_item<T, 1, true>(w, lane, sj_w[wave], sS_w[wave], sd_w[wave], sl_w[wave], P, Gx,
                                    I_fx, ovf, m, cR);
         }
     } else {
-        const int item = blockIdx.x * W + wave;
+        // wave-uniform (scalar registers), like everything derived from the item
+        const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * W + wave);
         if (item >= n_items) return;
         const WorkItem w = items[item];
         radii_item<T, 1, false>(w, lane, sj_w[wave], sS_w[wave], sd_w[wave], sl_w[wave], P, Gx,
@@ -1160,15 +1180,13 @@ __global__ __launch_bounds__(kTile * W) void k_radii_pairs(
 // of the later passes (FP64 state in caller order, pair-precision copies in
 // internal order).
 template <typename T>
-__global__ void k_radii_finalize(int n_atoms, const T* __restrict__ RHO, GBConst c, Work<T> w,
-                                 T* __restrict__ born_R)
+__device__ __forceinline__ void radii_final_atom(int k, const T* __restrict__ RHO, const GBConst& c,
+                                                 const Work<T>& w, T* __restrict__ born_R)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_atoms) return;
     const int g = w.perm[k];
     double rho = (double)RHO[g];
     double rt = rho - c.offset;
-    double I = (double)(long long)w.I_fx[k] * (1.0 / kScaleI);
+    double I = (double)(long long)ld_dev(w.I_fx + k) * (1.0 / kScaleI);
     double psi = rt * I;
     double th = c.alpha * psi - c.beta * psi * psi + c.gamma * psi * psi * psi;
     double t = tanh(th);
@@ -1177,9 +1195,10 @@ __global__ void k_radii_finalize(int n_atoms, const T* __restrict__ RHO, GBConst
     w.R64[g] = R;
     w.A64[g] = 0.5 / R;
     w.T64[g] = t;
-    w.dRdPsi64[g] = R * R * (1.0 - t * t) * (c.alpha - 2.0 * c.beta * psi + 3.0 * c.gamma * psi * psi) / rho;
-    w.R_t[k] = (T)R;
-    w.a_t[k] = (T)(kAScale / R);
+    st_dev(w.dRdPsi64 + g,
+           R * R * (1.0 - t * t) * (c.alpha - 2.0 * c.beta * psi + 3.0 * c.gamma * psi * psi) / rho);
+    st_dev(w.R_t + k, (T)R);
+    st_dev(w.a_t + k, (T)(kAScale / R));
     // FP64 record of the atom for the Monte Carlo kernels (caller order)
     const Q4<T> p = w.P[k];
     Row64 row;
@@ -1188,6 +1207,15 @@ __global__ void k_radii_finalize(int n_atoms, const T* __restrict__ RHO, GBConst
     row.pad0 = row.pad1 = row.pad2 = 0.0;
     w.rows[g] = row;
     if (born_R) born_R[g] = (T)R;
+}
+
+template <typename T>
+__global__ void k_radii_finalize(int n_atoms, const T* __restrict__ RHO, GBConst c, Work<T> w,
+                                 T* __restrict__ born_R)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_atoms) return;
+    radii_final_atom<T>(k, RHO, c, w, born_R);
 }
 
 // ================================================================ pass 2
@@ -1212,7 +1240,7 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
             const int g = w.base + i;
             const Q4<T> p = P[g];
             xi[r] = p.x; yi[r] = p.y; zi[r] = p.z; qi[r] = p.w;
-            Ri[r] = Rt[g]; ai[r] = At[g];
+            Ri[r] = ld_dev(Rt + g); ai[r] = ld_dev(At + g);
         } else {
             dummy_pos(i, xi[r], yi[r], zi[r]);
             qi[r] = T(0); Ri[r] = T(1); ai[r] = T(kAScale);
@@ -1223,7 +1251,7 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
     auto fetch = [&](int J, Q4<T>& pj, T& Rj, T& Aj) {
         const int g = w.base + clamp_atom(J * kTile + lane, w.n);
         pj = P[g];
-        Rj = Rt[g]; Aj = At[g];
+        Rj = ld_dev(Rt + g); Aj = ld_dev(At + g);
     };
     auto tail = [&](int J, Q4<T>& pj, T& Rj, T& Aj) {
         const int j = J * kTile + lane;
@@ -1412,14 +1440,16 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
     if constexpr (CUT) {
         // compacted one-row items of the pair cutoff
         const int n = wk.ccount[1];
-        for (int it = blockIdx.x * W + wave; it < n; it += gridDim.x * W) {
+        for (int it = __builtin_amdgcn_readfirstlane(blockIdx.x * W + wave); it < n;
+             it += gridDim.x * W) {
             unsigned long long m;
             const WorkItem w = cut_work_item(wk.citems[1][it], m);
             energy_item<T, GRAD, 1, SALT, true, false>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P, Rt,
                                                 At, kC, kT, sk, ck, wk, m);
         }
     } else {
-        const int item = blockIdx.x * W + wave;
+        // wave-uniform (scalar registers), like everything derived from the item
+        const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * W + wave);
         if (item >= n_items) return;
         const WorkItem w = items[item];
         // two-row items exist in the energy pass of FP32 plans only
@@ -1432,6 +1462,19 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
             energy_item<T, GRAD, 1, SALT, false, ONE>(w, lane, sj_w[wave], sR_w[wave], sA_w[wave], P, Rt,
                                                  At, kC, kT, sk, ck, wk, 0ull);
     }
+}
+
+// Per atom after pass 2: G = dE/dR and the chain weight B = G dR/dPsi (FP64,
+// caller order), and B (rho - offset) in the pair precision for the chain pass.
+template <typename T>
+__device__ __forceinline__ void energy_final_atom(int k, const Work<T>& w)
+{
+    const int g = w.perm[k];
+    double G = (double)(long long)ld_dev(w.G_fx + k) * (1.0 / kScaleF);
+    double B = G * ld_dev(w.dRdPsi64 + g);
+    w.G64[g] = G;
+    w.B64[g] = B;
+    st_dev(w.Brt_t + k, (T)(B * (double)w.Gx[k].x));
 }
 
 // After pass 2, one launch: blocks [0, n_sum) sum the atoms' fixed-point
@@ -1471,13 +1514,8 @@ __global__ __launch_bounds__(256) void k_energy_finalize(int n_atoms, int n_sum,
     }
     const int k = ((int)blockIdx.x - n_sum) * 256 + t;
     if (!grad || k >= n_atoms) return;
-    const int g = w.perm[k];
-    double G = (double)(long long)w.G_fx[k] * (1.0 / kScaleF);
-    double B = G * w.dRdPsi64[g];
-    w.G64[g] = G;
-    w.B64[g] = B;
-    w.Brt_t[k] = (T)(B * (double)w.Gx[k].x);
-    if (dEdq) dEdq[g] = (T)((double)(long long)w.phi_fx[k] * (1.0 / kScaleF));
+    energy_final_atom<T>(k, w);
+    if (dEdq) dEdq[w.perm[k]] = (T)((double)(long long)w.phi_fx[k] * (1.0 / kScaleF));
 }
 
 // ================================================================ pass 3
@@ -1514,7 +1552,7 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
             rti[r] = gx.x;
             Si[r] = gx.y;
             si[r] = gx.z;
-            Bi[r] = Brt[g];
+            Bi[r] = ld_dev(Brt + g);
         } else {
             dummy_pos(i, xi[r], yi[r], zi[r]);
             rti[r] = T(1); si[r] = T(0); Si[r] = T(0); Bi[r] = T(0);
@@ -1526,7 +1564,7 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
         const int g = w.base + clamp_atom(J * kTile + lane, w.n);
         pj = P[g];
         gj = Gx[g];
-        brj = Brt[g];
+        brj = ld_dev(Brt + g);
     };
     auto tail = [&](int J, Q4<T>& pj, Q4<T>& bj, const Q4<T>& gj, T brj) {
         const int j = J * kTile + lane;
@@ -1652,7 +1690,7 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
                         const int gi = w.base + w.I * kTile + il;
                         const Q4<T> pi = P[gi];
                         const Q4<T> gxi = Gx[gi];       // rt, S, screen
-                        const T bi_ = Brt[gi];
+                        const T bi_ = ld_dev(Brt + gi);
                         const JD d = load(il + k);
                         const Q4<T>& p = d.p;
                         const Q4<T>& b = d.b;
@@ -1750,14 +1788,16 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
     // fewer waves in flight for less saved work)
     if constexpr (CUT) {
         const int n = wk.ccount[0];
-        for (int it = blockIdx.x * W + wave; it < n; it += gridDim.x * W) {
+        for (int it = __builtin_amdgcn_readfirstlane(blockIdx.x * W + wave); it < n;
+             it += gridDim.x * W) {
             unsigned long long m;
             const WorkItem w = cut_work_item(wk.citems[0][it], m);
             chain_item<T, 1, true, false>(w, lane, sj_w[wave], sb_w[wave], sd_w[wave], sl_w[wave], P,
                                           Gx, Brt, wk, cR, m);
         }
     } else {
-        const int item = blockIdx.x * W + wave;
+        // wave-uniform (scalar registers), like everything derived from the item
+        const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * W + wave);
         if (item >= n_items) return;
         const WorkItem w = items[item];
         chain_item<T, 1, false, ONE>(w, lane, sj_w[wave], sb_w[wave], sd_w[wave], sl_w[wave], P, Gx,
@@ -1774,6 +1814,240 @@ __global__ void k_grad_finalize(int n_atoms, const T* __restrict__ RHO, double o
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_atoms) return;
     const int g = w.perm[k];
+    if (force) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+            force[3 * (size_t)g + a] = (T)((double)(long long)w.F_fx[a * w.n_atoms + k] * (1.0 / kScaleF));
+    }
+    if (dEdrho) {
+        double rho = (double)RHO[g];
+        double rt = rho - offset;
+        double R = w.R64[g];
+        double v = w.G64[g] * R * R * (1.0 / (rt * rt) - w.T64[g] / (rho * rho))
+                 + w.B64[g] * w.I64[g]
+                 + (double)(long long)w.drho_fx[k] * (1.0 / kScaleF);
+        dEdrho[g] = (T)v;
+    }
+}
+
+// ===================================================== one queued launch
+// The pair passes of one call (descreening, energy / explicit forces, Born
+// chain; all pairs) run as one launch.  Its work items form one sequence, in
+// pass order (within a pass as the plan lists them).  Every workgroup takes
+// the next ticket from a device counter when it starts and its W waves run the
+// W consecutive items of that ticket, so the items start in sequence order.
+// An item of a later pass first waits until every 64-atom block it touches is
+// final in the preceding pass: every item counts itself done on each of its
+// blocks (int counters), and the wave whose count completes a block finalizes
+// it (the OBC radius and its derivatives after the descreening pass, the
+// chain weight after the energy pass) and then marks it ready (count + 1).
+// Every wait ends: an item waits only for items earlier in the sequence, which
+// were taken by workgroups that started before it (or by its own workgroup)
+// and so are running or done.  Each wait is bounded all the same
+// (PQueue::spin_limit polls): a wave that gives up sets the launch's error
+// word and skips its item, every later wait then gives up at once, so the
+// launch drains, and the host reads the error (gbmc_check_overflow).
+// Counters, fixed-point sums and block finals move between the waves through
+// device-scope atomics, loads and stores (coherent across the XCDs' L2
+// caches).  (A grid of resident workgroups that loop over the sequence was
+// measured to need 30-50 % more registers per wave, hence fewer waves in
+// flight, than one item per wave.)
+struct PQueue {
+    const WorkItem* items[3];   // the work list of each pass
+    int n[3];                   // its item count
+    const int* total;           // [3][n_blocks] items of a pass touching a block
+    int* cnt;                   // [3][n_blocks] items done; total + 1 once finalized
+    int* head;                  // the ticket counter (cleared by the staging kernel)
+    int* err;                   // set when a wait gave up (this launch)
+    int* sticky;                // the same, kept until the next radii call
+    int n_blocks;
+    int spin_limit;             // polls before a wait gives up
+};
+
+// Distinct blocks of an item: its i blocks [I, I + rows), then its j blocks
+// [J0, J1) other than those (J0 >= I).
+__device__ __forceinline__ int pq_nd(const WorkItem& w)
+{
+    return w.rows + max(0, w.J1 - max(w.J0, w.I + w.rows));
+}
+__device__ __forceinline__ int pq_block(const WorkItem& w, int k)
+{
+    return k < w.rows ? w.I + k : max(w.J0, w.I + w.rows) + (k - w.rows);
+}
+
+// Waits until every block of item w is ready in pass `pass`; false if a wait
+// gave up (or another wave's did).
+__device__ bool pq_wait(const PQueue& q, int pass, const WorkItem& w, int lane)
+{
+    const int nd = pq_nd(w);
+    const int* cnt = q.cnt + (size_t)pass * q.n_blocks;
+    const int* tot = q.total + (size_t)pass * q.n_blocks;
+    for (int c = 0; c < nd; c += kTile) {
+        const int k = c + lane;
+        int X = 0, want = 0;
+        bool ok = k >= nd;
+        if (!ok) {
+            X = w.blk0 + pq_block(w, k);
+            want = tot[X] + 1;
+            ok = ld_dev(cnt + X) == want;
+        }
+        int spins = 0;
+        while (__builtin_amdgcn_ballot_w64(!ok) != 0ull) {
+            if (spins++ >= q.spin_limit || ld_dev(q.err) != 0) return false;
+            __builtin_amdgcn_s_sleep(1);
+            if (!ok) ok = ld_dev(cnt + X) == want;
+        }
+    }
+    return true;
+}
+
+// Counts item w done on its blocks in pass `pass`; for every block this
+// completes, fin(local block) finalizes it and the block is marked ready.
+template <class Fin>
+__device__ __forceinline__ void pq_complete(const PQueue& q, int pass, const WorkItem& w, int lane,
+                                            Fin&& fin)
+{
+    // every fixed-point atomic of the item is performed before its blocks are
+    // counted (vmcnt covers stores and atomics on gfx9)
+    __builtin_amdgcn_s_waitcnt(0x0f70);       // vmcnt(0)
+    const int nd = pq_nd(w);
+    int* cnt = q.cnt + (size_t)pass * q.n_blocks;
+    const int* tot = q.total + (size_t)pass * q.n_blocks;
+    for (int c = 0; c < nd; c += kTile) {
+        const int k = c + lane;
+        int Lb = 0;
+        bool last = false;
+        if (k < nd) {
+            Lb = pq_block(w, k);
+            const int X = w.blk0 + Lb;
+            last = atomicAdd(cnt + X, 1) == tot[X] - 1;
+        }
+        unsigned long long m = __builtin_amdgcn_ballot_w64(last);
+        while (m != 0ull) {
+            const int src = __builtin_ctzll(m);
+            m &= m - 1ull;
+            const int L = __builtin_amdgcn_readlane(Lb, src);
+            fin(L);
+            // the block's finals are visible device-wide before it is marked ready
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (lane == 0) atomicAdd(cnt + w.blk0 + L, 1);
+        }
+    }
+}
+
+// LDS bytes per wave: the largest of the three passes' slices.
+template <typename T>
+struct PLds {
+    static constexpr int radii = 2 * kTile * (int)sizeof(Q4<T>) + 2 * kTile * (int)sizeof(T) +
+                                 kTile * 8 + kTile * 4;
+    static constexpr int energy = 2 * kTile * (int)sizeof(Q4<T>) + 4 * kTile * (int)sizeof(T);
+    static constexpr int chain = 4 * kTile * (int)sizeof(Q4<T>) + 4 * kTile * 8 + kTile * 4;
+    static constexpr int bytes = radii > energy ? (radii > chain ? radii : chain)
+                                                : (energy > chain ? energy : chain);
+};
+
+template <typename T, int W, int P0, int P1, bool GRAD, bool SALT, bool ONE>
+__global__ __launch_bounds__(kTile * W) void k_pairs_queue(
+    PQueue q, const T* __restrict__ RHO, GBConst c, T kC, T kT, SaltK<T> sk, Work<T> wk,
+    T* __restrict__ born_R)
+{
+    __shared__ __align__(16) unsigned char lds_w[W][PLds<T>::bytes];
+    __shared__ int ticket;
+    const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
+    if (threadIdx.x == 0) ticket = atomicAdd(q.head, 1);
+    __syncthreads();
+    int ntot = 0;
+#pragma unroll
+    for (int p = P0; p <= P1; ++p) ntot += q.n[p];
+    // wave-uniform (scalar registers): the item and everything derived from it
+    const int idx = __builtin_amdgcn_readfirstlane(ticket * W + wave);
+    if (idx >= ntot) return;
+    int p = P0, loc = idx;
+    while (p < P1 && loc >= q.n[p]) { loc -= q.n[p]; ++p; }
+    const WorkItem w = q.items[p][loc];
+    if (p > P0 && !pq_wait(q, p - 1, w, lane)) {
+        if (lane == 0) {
+            atomicOr(q.err, 1);
+            atomicOr(q.sticky, 1);
+        }
+        return;
+    }
+    unsigned char* lds = lds_w[wave];
+    Q4<T>* sj = reinterpret_cast<Q4<T>*>(lds);
+    if (P0 == 0 && p == 0) {
+        T* sS = reinterpret_cast<T*>(sj + 2 * kTile);
+        unsigned long long* sdef = reinterpret_cast<unsigned long long*>(sS + 2 * kTile);
+        int* slist = reinterpret_cast<int*>(sdef + kTile);
+        radii_item<T, 1, false>(w, lane, sj, sS, sdef, slist, wk.P, wk.Gx, wk.I_fx, wk.ovf, 0ull,
+                                T(0));
+        pq_complete(q, 0, w, lane, [&](int L) {
+            const int i = L * kTile + lane;
+            if (i < w.n) radii_final_atom<T>(w.base + i, RHO, c, wk, born_R);
+        });
+    } else if (P0 <= 1 && P1 >= 1 && p == 1) {
+        const CutK<T> ck{T(0), T(0)};
+        T* sR = reinterpret_cast<T*>(sj + 2 * kTile);
+        T* sA = sR + 2 * kTile;
+        if (sizeof(T) == 4 && w.rows == 2)
+            energy_item<T, GRAD, sizeof(T) == 4 ? 2 : 1, SALT, false, ONE>(
+                w, lane, sj, sR, sA, wk.P, wk.R_t, wk.a_t, kC, kT, sk, ck, wk, 0ull);
+        else
+            energy_item<T, GRAD, 1, SALT, false, ONE>(w, lane, sj, sR, sA, wk.P, wk.R_t, wk.a_t,
+                                                      kC, kT, sk, ck, wk, 0ull);
+        // the energy pass finalizes its blocks when the chain pass follows
+        if (P1 == 2)
+            pq_complete(q, 1, w, lane, [&](int L) {
+                const int i = L * kTile + lane;
+                if (i < w.n) energy_final_atom<T>(w.base + i, wk);
+            });
+    } else if (P1 == 2 && p == 2) {
+        Q4<T>* sb = sj + 2 * kTile;
+        unsigned long long* sdef = reinterpret_cast<unsigned long long*>(sb + 2 * kTile);
+        int* slist = reinterpret_cast<int*>(sdef + 4 * kTile);
+        chain_item<T, 1, false, ONE>(w, lane, sj, sb, sdef, slist, wk.P, wk.Gx, wk.Brt_t, wk, T(0),
+                                     0ull);
+    }
+}
+
+// After a queued launch that ran the energy pass: blocks [0, n_sum) sum
+// the atoms' fixed-point energy shares of one system each (integer sums,
+// order independent); the following blocks write one atom's outputs per
+// thread: dE/dq, the forces and dE/drho (caller order).
+template <typename T>
+__global__ __launch_bounds__(256) void k_post(int n_atoms, int n_sum, Work<T> w,
+                                              double* __restrict__ e_coul,
+                                              double* __restrict__ e_gb, T* __restrict__ dEdq,
+                                              T* __restrict__ force, T* __restrict__ dEdrho,
+                                              const T* __restrict__ RHO, double offset)
+{
+    const int t = threadIdx.x;
+    if ((int)blockIdx.x < n_sum) {
+        __shared__ long long part[2][4];
+        const int b = blockIdx.x, lane = t % kTile, wave = t / kTile;
+        long long s0 = 0, s1 = 0;
+        for (int g = w.atom_offset[b] + t; g < w.atom_offset[b + 1]; g += 256) {
+            s0 += (long long)w.EA_fx[g];
+            s1 += (long long)w.EA_fx[w.n_atoms + g];
+        }
+#pragma unroll
+        for (int o = kTile / 2; o > 0; o >>= 1) {
+            s0 += __shfl_xor(s0, o);
+            s1 += __shfl_xor(s1, o);
+        }
+        if (lane == 0) { part[0][wave] = s0; part[1][wave] = s1; }
+        __syncthreads();
+        if (t == 0) {
+            long long ec = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+            long long eg = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+            if (e_coul) e_coul[b] = (double)ec * (1.0 / kScaleE);
+            if (e_gb) e_gb[b] = (double)eg * (1.0 / kScaleE);
+        }
+        return;
+    }
+    const int k = ((int)blockIdx.x - n_sum) * 256 + t;
+    if (k >= n_atoms) return;
+    const int g = w.perm[k];
+    if (dEdq) dEdq[g] = (T)((double)(long long)w.phi_fx[k] * (1.0 / kScaleF));
     if (force) {
 #pragma unroll
         for (int a = 0; a < 3; ++a)
@@ -2315,10 +2589,12 @@ hipError_t launch_radii(const WorkItem* items, int n_items, int wpg, int n_atoms
                         hipEvent_t* ev)
 {
     if (n_atoms == 0) return hipSuccess;
-    // staging also clears I_fx and the overflow flag: every evaluation starts at zero
+    // staging also clears I_fx and the overflow flags: every evaluation starts at zero
+    StageClear zc{};
+    zc.acc0 = w.I_fx; zc.n_acc0 = 1;
+    zc.f0 = w.ovf; zc.n_f0 = 2;
     hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms, w.perm,
-                       x, y, z, (const T*)nullptr, rho, screen, (T)c.offset, w.P, w.Gx, w.I_fx, 1,
-                       w.ovf);
+                       x, y, z, (const T*)nullptr, rho, screen, (T)c.offset, w.P, w.Gx, zc);
     if (c.rgbmax > 0.0 || c.cutoff > 0.0) launch_cut_lists<T>(cp, c, w, s);
     if (n_items > 0) {
         if (c.rgbmax > 0.0)
@@ -2349,10 +2625,12 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
     const bool chain = force || dEdrho;
     // positions and charges as given to this call, in processing order; F, G,
     // phi, drho and the two energy shares ([8][N] from F_fx on) cleared alongside
-    if (n_atoms > 0)
+    if (n_atoms > 0) {
+        StageClear zc{};
+        zc.acc0 = w.F_fx; zc.n_acc0 = 8;
         hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
-                           w.perm, x, y, z, q, rho, screen, (T)c.offset, w.P, w.Gx, w.F_fx, 8,
-                           (int*)nullptr);
+                           w.perm, x, y, z, q, rho, screen, (T)c.offset, w.P, w.Gx, zc);
+    }
     // block bounds and compacted work (positions as staged here, the same as
     // the preceding gb_radii call's)
     if (c.rgbmax > 0.0 || c.cutoff > 0.0) launch_cut_lists<T>(cp, c, w, s);
@@ -2417,6 +2695,76 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
     if (chain && n_atoms > 0)
         hipLaunchKernelGGL(k_grad_finalize<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s,
                            n_atoms, rho, c.offset, w, force, dEdrho);
+    return hipGetLastError();
+}
+
+constexpr int kPersistW = 8;     // waves per workgroup (items per ticket) of the queued launch
+
+template <typename T, int P0, int P1, bool G, bool S, bool O>
+static hipError_t queued_dispatch(const PQueue& pq, int ntot, const QueueShape& sh,
+                                      const T* rho, const GBConst& c, const Work<T>& w, T* born_R,
+                                      hipStream_t s, hipEvent_t* ev, int id)
+{
+    (void)sh;
+    auto kern = k_pairs_queue<T, kPersistW, P0, P1, G, S, O>;
+    const SaltK<T> sk{(T)c.kO, (T)c.kappa, (T)(c.kappa * kLog2e)};
+    GBMC_LAUNCH_TIMED(ev, id, kern, dim3(blocks_for(ntot, kPersistW)), dim3(kTile * kPersistW), s,
+                      pq, rho, c, (T)c.kC, (T)c.kT, sk, w, born_R);
+    return hipGetLastError();
+}
+
+template <typename T, int P0, int P1>
+static hipError_t queued_variant(bool salt, bool one, const PQueue& pq, int ntot,
+                                 const QueueShape& sh, const T* rho, const GBConst& c,
+                                 const Work<T>& w, T* born_R, hipStream_t s, hipEvent_t* ev, int id)
+{
+    if (salt)
+        return one ? queued_dispatch<T, P0, P1, true, true, true>(pq, ntot, sh, rho, c, w, born_R, s, ev, id)
+                   : queued_dispatch<T, P0, P1, true, true, false>(pq, ntot, sh, rho, c, w, born_R, s, ev, id);
+    return one ? queued_dispatch<T, P0, P1, true, false, true>(pq, ntot, sh, rho, c, w, born_R, s, ev, id)
+               : queued_dispatch<T, P0, P1, true, false, false>(pq, ntot, sh, rho, c, w, born_R, s, ev, id);
+}
+
+template <typename T>
+hipError_t launch_queued(const QueueShape& sh, int n_atoms, int n_sys, const T* x, const T* y,
+                         const T* z, const T* q, const T* rho, const T* screen, const GBConst& c,
+                         const Work<T>& w, T* born_R, double* e_coul, double* e_gb, T* force,
+                         T* dEdq, T* dEdrho, hipStream_t s, hipEvent_t* ev, int timing_id)
+{
+    if (n_atoms == 0) return hipSuccess;
+    // staging: atoms packed in processing order; the accumulators, the
+    // overflow flags, the ticket counter, the error word and the block
+    // counters start at zero
+    StageClear zc{};
+    zc.acc0 = w.I_fx; zc.n_acc0 = 1;
+    zc.acc1 = w.F_fx; zc.n_acc1 = 8;
+    zc.f0 = w.ovf; zc.n_f0 = 2;
+    zc.f1 = w.qhead; zc.n_f1 = kQueueWords;
+    zc.cnt = w.qcnt; zc.n_cnt = 3 * sh.n_blocks;
+    hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(std::max(n_atoms, kQueueWords), 256)),
+                       dim3(256), 0, s, n_atoms, w.perm, x, y, z, q, rho, screen, (T)c.offset, w.P,
+                       w.Gx, zc);
+    PQueue pq{};
+    int ntot = 0;
+    for (int k = 0; k < 3; ++k) {
+        pq.items[k] = sh.items[k];
+        pq.n[k] = sh.n_items[k];
+        ntot += pq.n[k];
+    }
+    pq.total = sh.total; pq.cnt = w.qcnt; pq.head = w.qhead; pq.err = w.qhead + 32;
+    pq.sticky = w.ovf + 1;
+    pq.n_blocks = sh.n_blocks;
+    pq.spin_limit = sh.spin_limit;
+    if (ntot > 0) {
+        hipError_t e = queued_variant<T, 0, 2>(c.kappa != 0.0, sh.one_tile, pq, ntot, sh, rho, c, w,
+                                               born_R, s, ev, timing_id);
+        if (e != hipSuccess) return e;
+    }
+    const int n_sum = (e_coul || e_gb) ? n_sys : 0;
+    const int n_fin = (force || dEdq || dEdrho) ? blocks_for(n_atoms, 256) : 0;
+    if (n_sum + n_fin > 0)
+        hipLaunchKernelGGL(k_post<T>, dim3(n_sum + n_fin), dim3(256), 0, s, n_atoms, n_sum, w,
+                           e_coul, e_gb, dEdq, force, dEdrho, rho, c.offset);
     return hipGetLastError();
 }
 
@@ -2497,6 +2845,10 @@ hipError_t launch_remd_exchange(int M, const double* E_rung, const int32_t* Ne, 
                                                 const T*, const GBConst&, const Work<T>&,        \
                                                 double*, double*, T*, T*, T*, hipStream_t,       \
                                                 hipEvent_t*);                                    \
+    template hipError_t launch_queued<T>(const QueueShape&, int, int, const T*, const T*,       \
+                                         const T*, const T*, const T*, const T*, const GBConst&, \
+                                         const Work<T>&, T*, double*, double*, T*, T*, T*,       \
+                                         hipStream_t, hipEvent_t*, int);                         \
     template hipError_t launch_state_dE<T>(const SiteDev&, int, const T*, const T*, const T*,    \
                                            const T*, const GBConst&, const Work<T>&,             \
                                            unsigned long long*,                                  \

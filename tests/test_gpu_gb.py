@@ -211,17 +211,54 @@ def test_spatial_order_parity_and_determinism():
     assert np.max(np.abs(perm["R"] - ident["R"]) / ident["R"]) <= 1e-13
 
 
+@pytest.mark.parametrize("single", [False, True])
 @pytest.mark.parametrize("prec", PRECS)
-def test_evaluate_equals_radii_then_energy_forces(prec):
-    # gb_evaluate (one call) gives the outputs of gb_radii + gb_energy_forces bitwise
+def test_evaluate_equals_radii_then_energy_forces(prec, single):
+    # gb_evaluate (one call; in single-launch mode one kernel launch of the
+    # three pair passes with per-block dependency counters) gives the outputs
+    # of gb_radii + gb_energy_forces bitwise
     p_gpu, p_or = params_pair()
-    systems = [_sys(71, 700), _sys(72, 65), _sys(73, 1)]
+    systems = [_sys(71, 700), _sys(72, 65), _sys(73, 1), _sys(74, 2500)]
     g, batch, plan, atoms = build(systems, prec)
     two = gpu_eval(plan, atoms, p_gpu)
-    one = g.evaluate(plan, atoms, p_gpu)
-    torch.cuda.synchronize()
-    got = {"R": one["R"], "Ec": one["e_coul"], "Egb": one["e_gb"], "force": one["force"],
-           "dEdq": one["dEdq"], "dEdrho": one["dEdrho"]}
-    for k, v in got.items():
-        assert np.array_equal(v.double().cpu().numpy(), two[k]), k
+    plan.set_single_launch(single)
+    for _ in range(3):
+        one = g.evaluate(plan, atoms, p_gpu)
+        torch.cuda.synchronize()
+        assert g.check_overflow(plan) is False
+        got = {"R": one["R"], "Ec": one["e_coul"], "Egb": one["e_gb"], "force": one["force"],
+               "dEdq": one["dEdq"], "dEdrho": one["dEdrho"]}
+        for k, v in got.items():
+            assert np.array_equal(v.double().cpu().numpy(), two[k]), k
     compare_system(two, 0, batch.atom_offset, oracle_eval(systems[0], p_or), prec)
+
+
+def test_single_launch_wait_failure_is_reported_never_silent():
+    # With a wait bound of 0 polls, an item that finds a block of the preceding
+    # pass not yet final gives up at once instead of waiting: the launch still
+    # ends normally, and the outcome is either the error flag or results equal
+    # to those of a normal run (when every block happened to be ready).  The
+    # next call with the default bound is correct again.
+    p_gpu, _ = params_pair()
+    systems = synth.eremd_batch(n_rep=8)
+    g, batch, plan, atoms = build(systems, "fp32")
+    ref = g.evaluate(plan, atoms, p_gpu)
+    torch.cuda.synchronize()
+    ref = {k: v.double().cpu().numpy() for k, v in ref.items() if v is not None}
+    assert g.check_overflow(plan) is False
+    plan.set_single_launch(True, 0)
+    out = g.evaluate(plan, atoms, p_gpu)
+    torch.cuda.synchronize()
+    flagged = g.check_overflow(plan)
+    if not flagged:
+        for k, v in out.items():
+            if v is not None:
+                assert np.array_equal(v.double().cpu().numpy(), ref[k]), k
+    print("wait bound 0: error reported" if flagged else "wait bound 0: every block was ready")
+    plan.set_single_launch(True, 1 << 22)
+    again = g.evaluate(plan, atoms, p_gpu)
+    torch.cuda.synchronize()
+    assert g.check_overflow(plan) is False
+    for k, v in again.items():
+        if v is not None:
+            assert np.array_equal(v.double().cpu().numpy(), ref[k]), k
