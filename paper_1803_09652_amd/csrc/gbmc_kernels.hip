@@ -70,6 +70,23 @@ __device__ __forceinline__ double rsq(double v) { return rsq64(v); }
 __device__ __forceinline__ double rcp(double v) { return rcp64(v); }
 __device__ __forceinline__ double exp2neg(double t) { return exp2(-t); }
 
+// 1/a and 1/b from one reciprocal: c = 1/(a b), 1/a = c b, 1/b = c a (a
+// transcendental costs several ordinary instructions).  For the polynomial
+// forms of the chain pass, where a, b = 1 - y >= 0.6 for every pair whose terms
+// are kept.
+__device__ __forceinline__ void rcp_pair(float a, float b, float& ia, float& ib)
+{
+    const float c = rcp(a * b);
+    ia = c * b;
+    ib = c * a;
+}
+__device__ __forceinline__ void rcp_pair(double a, double b, double& ia, double& ib)
+{
+    const double c = rcp64(a * b);
+    ia = c * b;
+    ib = c * a;
+}
+
 // Fixed-point value of v; an out-of-range (or NaN) v gives 0 and sets bad.
 // The flag stays in a register until the work item ends, so that the pair
 // loops issue no conditional stores.
@@ -381,7 +398,8 @@ __device__ __forceinline__ void chain_pair_fast(float r, float invr, float rti, 
     const float u = invr * invr;
     const float xij = Sj * invr, yij = xij * xij;
     const float xji = Si * invr, yji = xji * xji;
-    float wij = rcp(1.0f - yij), wji = rcp(1.0f - yji);
+    float wij, wji;
+    rcp_pair(1.0f - yij, 1.0f - yji, wij, wji);
     wij *= wij;
     wji *= wji;
     const float tij = yij * wij, tji = yji * wji;
@@ -474,7 +492,8 @@ __device__ __forceinline__ void chain_pair_fast(double r, double invr, double rt
     const double u = invr * invr;
     const double xij = Sj * invr, yij = xij * xij;
     const double xji = Si * invr, yji = xji * xji;
-    double wij = rcp64(1.0 - yij), wji = rcp64(1.0 - yji);
+    double wij, wji;
+    rcp_pair(1.0 - yij, 1.0 - yji, wij, wji);
     wij *= wij;
     wji *= wji;
     double aij = xij * yij * (hct_poly64(yij) + wij);    // -r^2 dH/dr
