@@ -501,6 +501,22 @@ def time_single_launch(systems, reps=5, precision="fp32"):
     return out
 
 
+def copy_calibration():
+    """A plain streaming kernel of known size (64 MiB read, 64 MiB written;
+    torch's elementwise negation, easy to find by name in the counter output):
+    FETCH_SIZE / WRITE_SIZE of these dispatches calibrate the HBM byte
+    counters of the pair kernels."""
+    import torch
+    n = 16 * 1024 * 1024
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        torch.neg(a, out=b)
+    torch.cuda.synchronize()
+    del a, b
+    return {"kernel": "neg", "bytes_read": 4 * n, "bytes_written": 4 * n, "dispatches": 3}
+
+
 def pair_count(systems):
     return int(sum(s_.n * (s_.n - 1) // 2 for s_ in systems))
 
@@ -701,6 +717,7 @@ def cpu_oracle_detail(reps=3):
 
 
 COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "hbm_counters_pair_kernels_uneven_64.md")
+EREMD_COUNTER_SUMMARY = os.path.join(ROOT, "profiles", "hbm_counters_pair_kernels_ereMD_16x2500.md")
 
 
 def time_autograd(reps=10):
@@ -796,9 +813,12 @@ def main():
     torch.cuda.set_device(0)
     use_graph, overlap = not args.no_graph, not args.no_overlap
     run = dict(use_graph=use_graph, order=args.order, overlap=overlap)
+    copy_ref = copy_calibration() if args.copy_calibration else None
     if args.only == "headline":
         r, _ = measure_workload(synth.uneven_batch_64(), False, args.steps, args.warmup,
                                 args.kernel_steps, **run)
+        if copy_ref is not None:
+            r["copy_calibration"] = copy_ref
         print(json.dumps(r), flush=True)
         return
     if args.only == "single":
@@ -809,23 +829,10 @@ def main():
     if args.only == "eremd":
         r, _ = measure_workload(synth.eremd_batch(), True, args.eremd_steps, args.warmup,
                                 args.kernel_steps, **run)
+        if copy_ref is not None:
+            r["copy_calibration"] = copy_ref
         print(json.dumps(r), flush=True)
         return
-    copy_ref = None
-    if args.copy_calibration:
-        # a plain streaming kernel of known size (64 MiB read, 64 MiB written;
-        # torch's elementwise negation, easy to find by name in the counter
-        # output): FETCH_SIZE / WRITE_SIZE of these dispatches calibrate the
-        # HBM byte counters of the pair kernels
-        n = 16 * 1024 * 1024
-        a = torch.ones(n, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        for _ in range(3):
-            torch.neg(a, out=b)
-        torch.cuda.synchronize()
-        copy_ref = {"kernel": "neg", "bytes_read": 4 * n, "bytes_written": 4 * n, "dispatches": 3}
-        del a, b
-
     # ---- headline: the uneven 64-system batch, FP32-fixed, library default shapes
     systems = synth.uneven_batch_64()
     head, w = measure_workload(systems, False, args.steps, args.warmup, args.kernel_steps, **run)
@@ -904,7 +911,11 @@ def main():
         er["workload"] = ("E-REMD batch: 16 replicas x 2500 atoms (18 A globules), 4 redox + 4 "
                           "protonation sites each, E ladder -0.40..-0.10 V, pH 7, T 300 K, "
                           "exchange attempt every step")
-        er["roofline"] = roofline_of(er["pairs_per_step"], er["kernel_ms_force_passes_alone"])
+        er_dom = roofline_of(er["pairs_per_step"], er["kernel_ms_force_passes_alone"])
+        er_t, er_d = (traffic_from_counters(er_dom["kernel"], EREMD_COUNTER_SUMMARY) if er_dom
+                      else (None, None))
+        er["roofline"] = roofline_of(er["pairs_per_step"], er["kernel_ms_force_passes_alone"],
+                                     er_t, er_d)
         er["fp64_plain"] = time_plain_fp64(we, reps=2)
         er["fp32_over_fp64_plain"] = er["pair_interactions_per_s"] / er["fp64_plain"]["value"]
         er["single_launch"] = time_single_launch(synth.eremd_batch(), reps=20)
