@@ -129,6 +129,25 @@ gbmc_status gbmc_schedule_build(int32_t n_systems, const int32_t* host_atom_offs
                                 int32_t j_blocks_per_item, int32_t row_pairs, int32_t* n_items,
                                 int32_t* items);
 
+/* Host-only: the work sequence of the queued single launch
+ * (gbmc_plan_set_single_launch) that a plan with this layout, precision and
+ * tuning (NULL: the defaults) runs, for checking its ordering off the GPU.
+ * n_items[3] (host) receives the item count of each pass; *n_blocks the number
+ * of 64-atom blocks of the batch (per system ceil(n / 64), systems in order).
+ * If items (host, 7 int32 per item, sized from a first call with items ==
+ * NULL) is not NULL it receives the items in sequence order (the descreening
+ * pass's, then the energy pass's, then the chain pass's): pass, system, index
+ * of the system's first block, I0, I1, J0, J1 (the tiles of i blocks [I0, I1)
+ * against j blocks [J0, J1), as in gbmc_schedule_build).  If totals (host,
+ * [3][n_blocks]) is not NULL it receives the number of items of each pass that
+ * touch each block: the counts at which the launch's per-block counters mark a
+ * block final for that pass.  GBMC_ERR_INVALID for bad offsets, precision or
+ * tuning, as gbmc_plan_create. */
+gbmc_status gbmc_queue_schedule(int32_t n_systems, const int32_t* host_atom_offset,
+                                gbmc_precision precision, const gbmc_tuning* tuning,
+                                int32_t* n_items, int32_t* items, int32_t* n_blocks,
+                                int32_t* totals);
+
 /* Create a plan for a batch of n_systems systems laid out back to back:
  * system b owns atoms [host_atom_offset[b], host_atom_offset[b+1]) (host array,
  * copied).  Empty systems are allowed.  tuning may be NULL (defaults).  The

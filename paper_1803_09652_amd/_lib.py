@@ -59,6 +59,8 @@ SIGNATURES = {
     "gbmc_last_error": (C.c_char_p, []),
     "gbmc_params_validate": (_I32, [C.POINTER(gbmc_gb_params)]),
     "gbmc_schedule_build": (_I32, [_I32, _I32P, _I32, _I32, _I32P, _I32P]),
+    "gbmc_queue_schedule": (_I32, [_I32, _I32P, _I32, C.POINTER(gbmc_tuning), _I32P, _I32P, _I32P,
+                                   _I32P]),
     "gbmc_plan_create": (_I32, [C.POINTER(_VP), _I32, _I32P, _I32, C.POINTER(gbmc_tuning)]),
     "gbmc_plan_destroy": (None, [_VP]),
     "gbmc_plan_set_order": (_I32, [_VP, _I32P]),

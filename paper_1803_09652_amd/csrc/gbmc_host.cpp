@@ -327,6 +327,42 @@ gbmc_status gbmc_params_validate(const gbmc_gb_params* p)
     return GBMC_OK;
 }
 
+// The work lists of a plan, one per pass (build_items with the pass's j
+// blocks per item; two-row items in the energy pass of FP32 plans), and the
+// number of items of each pass touching each 64-atom block (the counts the
+// queued launch's per-block counters complete at).  The queued launch runs a
+// pass's items before the next pass's, and a block of the next pass can start
+// once every item touching it is done, so the descreening and energy passes
+// take their items system by system (largest system first, each system's
+// items by decreasing cost): whole systems finish early and the next pass
+// starts on them while the last systems finish.  The chain pass, which ends
+// the launch, keeps the global decreasing-cost order.
+static void plan_schedule(int32_t n_systems, const int32_t* off, gbmc_precision prec,
+                          const gbmc_tuning& t, std::vector<WorkItem> (&items)[GBMC_N_PASSES],
+                          int32_t& n_blocks, std::vector<int32_t>& totals)
+{
+    for (int k = 0; k < GBMC_N_PASSES; ++k)
+        build_items(n_systems, off, t.j_blocks_per_item[k],
+                    prec == GBMC_FP32_FIXED && k == GBMC_PASS_ENERGY, items[k]);
+    std::vector<int32_t> rank(n_systems);
+    for (int32_t b = 0; b < n_systems; ++b) rank[b] = b;
+    std::stable_sort(rank.begin(), rank.end(), [&](int32_t a, int32_t c) {
+        return off[a + 1] - off[a] > off[c + 1] - off[c];
+    });
+    std::vector<int32_t> pos(n_systems);
+    for (int32_t r = 0; r < n_systems; ++r) pos[rank[r]] = r;
+    for (int k : {GBMC_PASS_RADII, GBMC_PASS_ENERGY})
+        std::stable_sort(items[k].begin(), items[k].end(),
+                         [&](const WorkItem& a, const WorkItem& c) { return pos[a.sys] < pos[c.sys]; });
+    n_blocks = 0;
+    for (int32_t b = 0; b < n_systems; ++b) n_blocks += (off[b + 1] - off[b] + kTile - 1) / kTile;
+    totals.assign((size_t)GBMC_N_PASSES * n_blocks, 0);
+    for (int k = 0; k < GBMC_N_PASSES; ++k)
+        for (const WorkItem& w : items[k])
+            for (int32_t d = 0; d < item_blocks(w); ++d)
+                ++totals[(size_t)k * n_blocks + w.blk0 + item_block(w, d)];
+}
+
 gbmc_status gbmc_schedule_build(int32_t n_systems, const int32_t* host_atom_offset,
                                 int32_t j_blocks_per_item, int32_t row_pairs, int32_t* n_items,
                                 int32_t* items)
@@ -355,6 +391,50 @@ gbmc_status gbmc_schedule_build(int32_t n_systems, const int32_t* host_atom_offs
     }
 }
 
+gbmc_status gbmc_queue_schedule(int32_t n_systems, const int32_t* host_atom_offset,
+                                gbmc_precision precision, const gbmc_tuning* tuning,
+                                int32_t* n_items, int32_t* items, int32_t* n_blocks,
+                                int32_t* totals)
+{
+    try {
+        if (!n_items || !n_blocks) return fail(GBMC_ERR_INVALID, "n_items or n_blocks is NULL");
+        gbmc_status st = check_offsets(n_systems, host_atom_offset);
+        if (st != GBMC_OK) return st;
+        if (precision != GBMC_FP32_FIXED && precision != GBMC_FP64)
+            return fail(GBMC_ERR_INVALID, "unknown precision");
+        gbmc_tuning t;
+        st = check_tuning(tuning, precision, t);
+        if (st != GBMC_OK) return st;
+        std::vector<WorkItem> v[GBMC_N_PASSES];
+        std::vector<int32_t> tot;
+        int32_t nb = 0;
+        plan_schedule(n_systems, host_atom_offset, precision, t, v, nb, tot);
+        size_t all = 0;
+        for (int k = 0; k < GBMC_N_PASSES; ++k) all += v[k].size();
+        if (all > 0x7fffffff / 7) return fail(GBMC_ERR_UNSUPPORTED, "too many work items");
+        for (int k = 0; k < GBMC_N_PASSES; ++k) n_items[k] = (int32_t)v[k].size();
+        *n_blocks = nb;
+        if (items) {
+            size_t r = 0;
+            for (int k = 0; k < GBMC_N_PASSES; ++k)
+                for (const WorkItem& w : v[k]) {
+                    int32_t* o = items + 7 * r++;
+                    o[0] = k;
+                    o[1] = w.sys;
+                    o[2] = w.blk0;
+                    o[3] = w.I;
+                    o[4] = w.I + w.rows;
+                    o[5] = w.J0;
+                    o[6] = w.J1;
+                }
+        }
+        if (totals && !tot.empty()) std::memcpy(totals, tot.data(), sizeof(int32_t) * tot.size());
+        return GBMC_OK;
+    } catch (const std::bad_alloc&) {
+        return fail(GBMC_ERR_INVALID, "host allocation failed");
+    }
+}
+
 gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* host_atom_offset,
                              gbmc_precision precision, const gbmc_tuning* tuning)
 {
@@ -369,31 +449,9 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
         st = check_tuning(tuning, precision, t);
         if (st != GBMC_OK) return st;
         std::vector<WorkItem> items[GBMC_N_PASSES];
-        for (int k = 0; k < GBMC_N_PASSES; ++k)
-            build_items(n_systems, host_atom_offset, t.j_blocks_per_item[k],
-                        precision == GBMC_FP32_FIXED && k == GBMC_PASS_ENERGY, items[k]);
-        // The queued launch runs a pass's items before the next pass's; a
-        // block of the next pass can start once every item touching it is
-        // done.  The descreening and energy passes therefore take their items
-        // system by system (largest system first, each system's items by
-        // decreasing cost), so whole systems finish early and the next pass
-        // starts on them while the last systems finish; the chain pass, which
-        // ends the launch, keeps the global decreasing-cost order.
-        {
-            std::vector<int32_t> rank(n_systems);
-            for (int32_t b = 0; b < n_systems; ++b) rank[b] = b;
-            std::stable_sort(rank.begin(), rank.end(), [&](int32_t a, int32_t c) {
-                return host_atom_offset[a + 1] - host_atom_offset[a] >
-                       host_atom_offset[c + 1] - host_atom_offset[c];
-            });
-            std::vector<int32_t> pos(n_systems);
-            for (int32_t r = 0; r < n_systems; ++r) pos[rank[r]] = r;
-            for (int k : {GBMC_PASS_RADII, GBMC_PASS_ENERGY})
-                std::stable_sort(items[k].begin(), items[k].end(),
-                                 [&](const WorkItem& a, const WorkItem& c) {
-                                     return pos[a.sys] < pos[c.sys];
-                                 });
-        }
+        std::vector<int32_t> totals;
+        int32_t n_blocks = 0;
+        plan_schedule(n_systems, host_atom_offset, precision, t, items, n_blocks, totals);
         auto* p = new gbmc_plan();
         p->n_sys = n_systems;
         p->n_atoms = n_systems > 0 ? host_atom_offset[n_systems] : 0;
@@ -406,6 +464,10 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
             for (int32_t a = host_atom_offset[b]; a < host_atom_offset[b + 1]; a += kTile)
                 blocks.push_back(BlockSpan{a, std::min(kTile, host_atom_offset[b + 1] - a)});
         p->n_blocks = (int32_t)blocks.size();
+        if (p->n_blocks != n_blocks) {
+            delete p;
+            return fail(GBMC_ERR_INVALID, "internal: block count mismatch");
+        }
         // chunks of the cutoff passes: every block row against its j blocks,
         // 64 at a time (the compaction kernel scans one chunk per wave)
         std::vector<WorkItem> chunks;
@@ -424,13 +486,6 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
         p->scratch_err = scratch_address(p->device, &p->scratch);
         e = hipDeviceGetAttribute(&p->n_cu, hipDeviceAttributeMultiprocessorCount, p->device);
         if (e != hipSuccess) { delete p; return hip_fail(e, "hipDeviceGetAttribute"); }
-        // items of each pass touching each block (the counts the queued
-        // launch's per-block counters complete at)
-        std::vector<int32_t> totals((size_t)GBMC_N_PASSES * p->n_blocks, 0);
-        for (int k = 0; k < GBMC_N_PASSES; ++k)
-            for (const WorkItem& w : items[k])
-                for (int32_t d = 0; d < item_blocks(w); ++d)
-                    ++totals[(size_t)k * p->n_blocks + w.blk0 + item_block(w, d)];
         // one device allocation: the three work lists, then the processing order (identity)
         size_t at[GBMC_N_PASSES + 1];
         size_t o = 0;
