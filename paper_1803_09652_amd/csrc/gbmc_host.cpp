@@ -83,7 +83,7 @@ struct gbmc_plan {
     // workspace layout (byte offsets)
     size_t off_I, off_F, off_G, off_phi, off_drho, off_EA, off_I64, off_R64, off_T64, off_dR64,
         off_G64, off_B64, off_Rt, off_at, off_Brt, off_ovf, off_q, off_P, off_Gx, off_A64, off_rows, off_bnd,
-        off_smax, off_cit0, off_cit1, off_ccount, ws_bytes;
+        off_smax, off_box, off_cit0, off_cit1, off_ccount, ws_bytes;
     int32_t cut_cap = 0;             // capacity of each compacted cutoff work list
 };
 
@@ -222,6 +222,7 @@ static Work<T> carve(const gbmc_plan* p, void* ws)
     w.qcnt = reinterpret_cast<int*>(b + p->off_q + 4 * (size_t)kQueueWords);
     w.bnd = reinterpret_cast<Q4<float>*>(b + p->off_bnd);
     w.smax = reinterpret_cast<float*>(b + p->off_smax);
+    w.box = reinterpret_cast<Q4<float>*>(b + p->off_box);
     w.citems[0] = reinterpret_cast<CutItem*>(b + p->off_cit0);
     w.citems[1] = reinterpret_cast<CutItem*>(b + p->off_cit1);
     w.ccount = reinterpret_cast<int*>(b + p->off_ccount);
@@ -260,6 +261,7 @@ static void layout(gbmc_plan* p)
     p->off_rows = seg(sizeof(Row64) * N);
     p->off_bnd = seg(sizeof(Q4<float>) * (size_t)p->n_blocks);
     p->off_smax = seg(sizeof(float) * (size_t)p->n_blocks);
+    p->off_box = seg(2 * sizeof(Q4<float>) * (size_t)p->n_blocks);
     p->off_cit0 = seg(sizeof(CutItem) * (size_t)p->cut_cap);
     p->off_cit1 = seg(sizeof(CutItem) * (size_t)p->cut_cap);
     p->off_ccount = seg(2 * sizeof(int));
@@ -747,6 +749,7 @@ static QueueShape queue_shape(const gbmc_plan* p)
         sh.n_items[k] = p->n_items[k];
     }
     sh.total = p->d_total;
+    sh.blocks = p->d_blocks;
     sh.n_blocks = p->n_blocks;
     sh.one_tile = p->tuning.j_blocks_per_item[GBMC_PASS_ENERGY] == 1 &&
                   p->tuning.j_blocks_per_item[GBMC_PASS_CHAIN] == 1;

@@ -111,6 +111,9 @@ struct Work {
     int* qcnt;                    // [3][n_blocks]: per-block item counters of the passes
     Q4<float>* bnd;               // [n_blocks] bounding sphere of each block: centre, radius
     float* smax;                  // [n_blocks] largest S = screen (rho - offset) of each block
+    Q4<float>* box;               // [2][n_blocks] coordinate box of each block (processing
+                                  //  order), written by staging: [2b] = lowest x, y, z and
+                                  //  largest S, [2b + 1] = highest x, y, z and largest rt
     CutItem* citems[2];           // [cut_cap] each: compacted items (0: descreening and
                                   //  chain passes, 1: energy pass)
     int* ccount;                  // [2] their counts
@@ -220,6 +223,7 @@ struct QueueShape {
     const WorkItem* items[3];
     int n_items[3];
     const int* total;
+    const BlockSpan* blocks;  // [n_blocks] atoms of each block (processing order)
     int n_blocks;
     bool one_tile;          // energy and chain items are single tiles
     int spin_limit;         // polls before a dependency wait gives up

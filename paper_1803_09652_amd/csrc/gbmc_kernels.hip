@@ -299,6 +299,7 @@ __device__ __forceinline__ void radii_pair(float xi, float yi, float zi, float x
 // The polynomial form alone, for walks that defer the pairs it does not cover
 // (as chain_pair_fast): a pair that needs the closed form in either direction
 // gets zero terms and, if act, its bit in mask.
+template <bool TEST = true>
 __device__ __forceinline__ void radii_pair_fast(float xi, float yi, float zi, float xj, float yj,
                                                 float zj, float rti, float Si, float rtj, float Sj,
                                                 bool act, unsigned long long bit, float& hij,
@@ -312,6 +313,7 @@ __device__ __forceinline__ void radii_pair_fast(float xi, float yi, float zi, fl
     float xji = Si * invr, yji = xji * xji;
     hij = xij * yij * invr * hct_poly(yij);
     hji = xji * yji * invr * hct_poly(yji);
+    if constexpr (!TEST) return;             // a separated tile: every pair is non-overlapping
     const bool fast = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX) & (r - Si >= rtj) &
                       (yji <= GBMC_HCT_YMAX);
     if (__builtin_amdgcn_ballot_w64(!fast) != 0ull) {
@@ -390,6 +392,7 @@ __device__ __forceinline__ void chain_pair(float r, float r2, float invr, float 
 // A pair that needs the closed form in either direction (act only) gets zero
 // terms and its bit in mask (one wave-uniform branch, taken only in the steps
 // that meet such a pair); the caller evaluates those pairs after the walk.
+template <bool TEST = true>
 __device__ __forceinline__ void chain_pair_fast(float r, float invr, float rti, float Si, float rtj,
                                                 float Sj, float bi, float bj, bool act,
                                                 unsigned long long bit, float& dEdr, float& gij2,
@@ -407,9 +410,9 @@ __device__ __forceinline__ void chain_pair_fast(float r, float invr, float rti, 
     float aji = xji * fmaf(yji, hct_poly_d(yji), tji);
     gij2 = tij * u;
     gji2 = tji * u;
-    const bool fast = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX) & (r - Si >= rtj) &
-                      (yji <= GBMC_HCT_YMAX);
-    if (__builtin_amdgcn_ballot_w64(!fast) != 0ull) {
+    const bool fast = !TEST || ((r - Sj >= rti) & (yij <= GBMC_HCT_YMAX) & (r - Si >= rtj) &
+                                (yji <= GBMC_HCT_YMAX));
+    if (TEST && __builtin_amdgcn_ballot_w64(!fast) != 0ull) {
         // an empty volatile statement keeps this a branch (not selects on
         // every step)
         asm volatile("");
@@ -461,6 +464,7 @@ __device__ __forceinline__ void chain_pair(double r, double r2, double invr, dou
 
 // FP64 forms of the two deferring pair functions (polynomial of degree 14 on
 // y <= 0.25; the pairs outside it are marked, as in FP32).
+template <bool TEST = true>
 __device__ __forceinline__ void radii_pair_fast(double xi, double yi, double zi, double xj,
                                                 double yj, double zj, double rti, double Si,
                                                 double rtj, double Sj, bool act,
@@ -473,6 +477,7 @@ __device__ __forceinline__ void radii_pair_fast(double xi, double yi, double zi,
     const double xji = Si * invr, yji = xji * xji;
     hij = xij * yij * invr * hct_poly64(yij);
     hji = xji * yji * invr * hct_poly64(yji);
+    if constexpr (!TEST) return;
     const bool fast = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX64) & (r - Si >= rtj) &
                       (yji <= GBMC_HCT_YMAX64);
     if (__builtin_amdgcn_ballot_w64(!fast) != 0ull) {
@@ -483,6 +488,7 @@ __device__ __forceinline__ void radii_pair_fast(double xi, double yi, double zi,
     }
 }
 
+template <bool TEST = true>
 __device__ __forceinline__ void chain_pair_fast(double r, double invr, double rti, double Si,
                                                 double rtj, double Sj, double bi, double bj,
                                                 bool act, unsigned long long bit, double& dEdr,
@@ -500,9 +506,9 @@ __device__ __forceinline__ void chain_pair_fast(double r, double invr, double rt
     double aji = xji * yji * (hct_poly64(yji) + wji);
     gij2 = yij * wij * u;
     gji2 = yji * wji * u;
-    const bool fast = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX64) & (r - Si >= rtj) &
-                      (yji <= GBMC_HCT_YMAX64);
-    if (__builtin_amdgcn_ballot_w64(!fast) != 0ull) {
+    const bool fast = !TEST || ((r - Sj >= rti) & (yij <= GBMC_HCT_YMAX64) & (r - Si >= rtj) &
+                                (yji <= GBMC_HCT_YMAX64));
+    if (TEST && __builtin_amdgcn_ballot_w64(!fast) != 0ull) {
         asm volatile("");
         aij = fast ? aij : 0.0;
         aji = fast ? aji : 0.0;
@@ -716,6 +722,30 @@ __device__ __forceinline__ float block_gap(const Q4<float>& a, const Q4<float>& 
     return sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))) - a.w - b.w;
 }
 
+// Whether every pair of an atom of block X with an atom of block Y (X != Y)
+// takes the polynomial form of H in both directions, from the staged boxes
+// (box[2b]: lowest x, y, z and largest S; box[2b + 1]: highest x, y, z and
+// largest rt): the gap g between the boxes bounds every pair distance from
+// below, so g >= S_j + rt_i and g >= S_i + rt_j for the blocks' largest S
+// and rt give r - S_j >= rt_i and r - S_i >= rt_j, and S^2 <= ymax g^2 gives
+// (S / r)^2 <= ymax, for every pair.  The margins (1e-3 A plus 1e-4 relative,
+// 0.1 % on ymax) lie far beyond the rounding of the per-pair test and of the
+// boxes, so on such a tile that test would pass for every pair: skipping it
+// changes no result.
+__device__ __forceinline__ bool blocks_separated(const Q4<float>* __restrict__ box, int X, int Y,
+                                                 float ymax)
+{
+    const Q4<float> lx = box[2 * X], hx = box[2 * X + 1];
+    const Q4<float> ly = box[2 * Y], hy = box[2 * Y + 1];
+    const float gx = fmaxf(0.0f, fmaxf(ly.x - hx.x, lx.x - hy.x));
+    const float gy = fmaxf(0.0f, fmaxf(ly.y - hx.y, lx.y - hy.y));
+    const float gz = fmaxf(0.0f, fmaxf(ly.z - hx.z, lx.z - hy.z));
+    const float g2 = fmaf(gx, gx, fmaf(gy, gy, gz * gz));
+    const float need = fmaf(fmaxf(ly.w + hx.w, lx.w + hy.w), 1.0001f, 1e-3f);
+    const float sm = fmaxf(lx.w, ly.w);
+    return g2 >= need * need && sm * sm <= 0.999f * ymax * g2;
+}
+
 // Cutoff work items carry a tile mask: bit k set if j block J0 + k may hold a
 // pair within the cutoff (J1 <= J0 + 64).  The first such block at or after
 // J, or J1 if none.
@@ -818,34 +848,65 @@ __device__ __forceinline__ void walk_tile_rows2(int lane, T (&acc_j)[NJ], Load&&
 // ============================================================ staging
 // Packs the caller's SoA inputs into the plan's processing order (a spatial
 // order keeps overlapping pairs inside few tiles): P = (x, y, z, q),
-// Gx = (rt, S, screen, 0) with rt = rho - offset and S = screen rt.
+// Gx = (rt, S, screen, 0) with rt = rho - offset and S = screen rt.  One wave
+// per 64-atom block: lane l stages atom l of the block, and the wave writes
+// the block's coordinate box with its largest S and rt (box[2b]: lowest x, y,
+// z and S; box[2b + 1]: highest x, y, z and rt), from which the pair passes
+// tell the tiles whose pairs all take the polynomial form (blocks_separated).
 
 template <typename T>
-__global__ void k_stage(int n_atoms, const int32_t* __restrict__ perm, const T* __restrict__ X,
-                        const T* __restrict__ Y, const T* __restrict__ Z, const T* __restrict__ Q,
-                        const T* __restrict__ RHO, const T* __restrict__ SCR, T offset,
-                        Q4<T>* __restrict__ P, Q4<T>* __restrict__ Gx, StageClear z)
+__global__ __launch_bounds__(256) void k_stage(const BlockSpan* __restrict__ blocks, int n_blocks,
+                                               int n_atoms, const int32_t* __restrict__ perm,
+                                               const T* __restrict__ X, const T* __restrict__ Y,
+                                               const T* __restrict__ Z, const T* __restrict__ Q,
+                                               const T* __restrict__ RHO,
+                                               const T* __restrict__ SCR, T offset,
+                                               Q4<T>* __restrict__ P, Q4<T>* __restrict__ Gx,
+                                               Q4<float>* __restrict__ box, StageClear z)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
     // flags and counters of the call start at zero
-    if (k < z.n_f0) z.f0[k] = 0;
-    if (k < z.n_f1) z.f1[k] = 0;
-    for (int i = k; i < z.n_cnt; i += gridDim.x * blockDim.x) z.cnt[i] = 0;
-    if (k >= n_atoms) return;
-    // the call's fixed-point accumulators of atom k ([n_acc][N] each) start at zero
-    for (int a = 0; a < z.n_acc0; ++a) z.acc0[(size_t)a * n_atoms + k] = 0ull;
-    for (int a = 0; a < z.n_acc1; ++a) z.acc1[(size_t)a * n_atoms + k] = 0ull;
-    int c = perm[k];
+    if (t < z.n_f0) z.f0[t] = 0;
+    if (t < z.n_f1) z.f1[t] = 0;
+    for (int i = t; i < z.n_cnt; i += gridDim.x * blockDim.x) z.cnt[i] = 0;
+    const int blk = blockIdx.x * 4 + threadIdx.x / kTile, lane = threadIdx.x % kTile;
+    if (blk >= n_blocks) return;
+    const BlockSpan b = blocks[blk];
+    const bool own = lane < b.count;
+    const int k = b.start + (own ? lane : b.count - 1);      // count >= 1
+    const int c = perm[k];
     Q4<T> p;
     p.x = X[c]; p.y = Y[c]; p.z = Z[c];
     p.w = Q ? Q[c] : T(0);
-    P[k] = p;
     Q4<T> g;
     g.x = RHO[c] - offset;
     g.z = SCR[c];
     g.y = g.z * g.x;
     g.w = T(0);
-    Gx[k] = g;
+    if (own) {
+        // the call's fixed-point accumulators of atom k ([n_acc][N] each) start at zero
+        for (int a = 0; a < z.n_acc0; ++a) z.acc0[(size_t)a * n_atoms + k] = 0ull;
+        for (int a = 0; a < z.n_acc1; ++a) z.acc1[(size_t)a * n_atoms + k] = 0ull;
+        P[k] = p;
+        Gx[k] = g;
+    }
+    // lanes past the end repeat the block's last atom (no effect on the box)
+    float lo[4] = {(float)p.x, (float)p.y, (float)p.z, (float)g.y};
+    float hi[4] = {lo[0], lo[1], lo[2], (float)g.x};
+#pragma unroll
+    for (int o = kTile / 2; o > 0; o >>= 1) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            lo[a] = fminf(lo[a], __shfl_xor(lo[a], o));
+            hi[a] = fmaxf(hi[a], __shfl_xor(hi[a], o));
+        }
+        lo[3] = fmaxf(lo[3], __shfl_xor(lo[3], o));
+        hi[3] = fmaxf(hi[3], __shfl_xor(hi[3], o));
+    }
+    if (lane == 0) {
+        box[2 * blk] = Q4<float>{lo[0], lo[1], lo[2], lo[3]};
+        box[2 * blk + 1] = Q4<float>{hi[0], hi[1], hi[2], hi[3]};
+    }
 }
 
 // Bounding sphere of every 64-atom block (centre of the coordinate box,
@@ -985,11 +1046,14 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
                                            const Q4<T>* __restrict__ P,
                                            const Q4<T>* __restrict__ Gx,
                                            unsigned long long* __restrict__ I_fx,
-                                           int* __restrict__ ovf, unsigned long long tmask, T cR)
+                                           int* __restrict__ ovf, unsigned long long tmask, T cR,
+                                           const Q4<float>* __restrict__ box)
 {
     // DEFER (one row, all pairs): overlapping pairs are marked during
-    // the walk and evaluated afterwards in packed rounds, as in the chain pass
+    // the walk and evaluated afterwards in packed rounds, as in the chain pass;
+    // tiles of separated blocks (blocks_separated) skip the per-pair test
     constexpr bool DEFER = R == 1 && !CUT;
+    constexpr float kYmax = sizeof(T) == 4 ? GBMC_HCT_YMAX : (float)GBMC_HCT_YMAX64;
     T xi[R], yi[R], zi[R], rti[R], Si[R];
     bool vi[R];
 #pragma unroll
@@ -1058,14 +1122,15 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
         auto load = [&](int s) { return JD{sj[s], sS[s]}; };
         int kstep = J == w.I ? 1 : 0;           // DEFER: walk step of the next pair
         unsigned long long dmask = 0ull;
-        auto pair = [&](const JD& d, int r, bool act, T (&acc)[1]) {
+        auto pair_any = [&](const JD& d, int r, bool act, T (&acc)[1], auto sep_tag) {
+            constexpr bool SEP = decltype(sep_tag)::value;
             T hij, hji;
             if constexpr (CUT) {
                 radii_pair_cut(xi[r], yi[r], zi[r], d.p.x, d.p.y, d.p.z, rti[r], Si[r], d.p.w, d.S,
                                cR, hij, hji);
             } else if constexpr (DEFER) {
-                radii_pair_fast(xi[r], yi[r], zi[r], d.p.x, d.p.y, d.p.z, rti[r], Si[r], d.p.w, d.S,
-                                act && vi[r], 1ull << kstep, hij, hji, dmask);
+                radii_pair_fast<!SEP>(xi[r], yi[r], zi[r], d.p.x, d.p.y, d.p.z, rti[r], Si[r],
+                                      d.p.w, d.S, act && vi[r], 1ull << kstep, hij, hji, dmask);
                 ++kstep;
             } else {
                 radii_pair(xi[r], yi[r], zi[r], d.p.x, d.p.y, d.p.z, rti[r], Si[r], d.p.w, d.S, hij,
@@ -1074,10 +1139,21 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
             ai[r] += act ? hij : T(0);
             acc[0] += act ? hji : T(0);
         };
-        if constexpr (R == 1)
-            walk_tile<T, 1>(lane, J == w.I, aj, load, pair);
-        else
+        auto pair = [&](const JD& d, int r, bool act, T (&acc)[1]) {
+            pair_any(d, r, act, acc, std::false_type{});
+        };
+        auto pair_sep = [&](const JD& d, int r, bool act, T (&acc)[1]) {
+            pair_any(d, r, act, acc, std::true_type{});
+        };
+        if constexpr (R == 1) {
+            // wave-uniform: the blocks of the tile come from the item
+            if (DEFER && J != w.I && blocks_separated(box, w.blk0 + w.I, w.blk0 + J, kYmax))
+                walk_tile<T, 1>(lane, false, aj, load, pair_sep);
+            else
+                walk_tile<T, 1>(lane, J == w.I, aj, load, pair);
+        } else {
             walk_tile_rows2<T, 1>(lane, aj, load, pair);
+        }
         // DEFER: packed rounds of the marked pairs (see chain_item): j-side
         // terms through LDS integer atomics, i-side terms back to the i lane
         bool deferred = false;
@@ -1165,7 +1241,8 @@ template <typename T, int W, bool CUT>
 __global__ __launch_bounds__(kTile * W) void k_radii_pairs(
     const WorkItem* __restrict__ items, int n_items, const CutItem* __restrict__ citems,
     const int* __restrict__ n_citems, const Q4<T>* __restrict__ P, const Q4<T>* __restrict__ Gx,
-    unsigned long long* __restrict__ I_fx, int* __restrict__ ovf, T cR)
+    unsigned long long* __restrict__ I_fx, int* __restrict__ ovf, T cR,
+    const Q4<float>* __restrict__ box)
 {
     __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, rt
     __shared__ T sS_w[W][2 * kTile];
@@ -1183,7 +1260,7 @@ __global__ __launch_bounds__(kTile * W) void k_radii_pairs(
             unsigned long long m;
             const WorkItem w = cut_work_item(citems[it], m);
             radii_item<T, 1, true>(w, lane, sj_w[wave], sS_w[wave], sd_w[wave], sl_w[wave], P, Gx,
-                                   I_fx, ovf, m, cR);
+                                   I_fx, ovf, m, cR, box);
         }
     } else {
         // wave-uniform (scalar registers), like everything derived from the item
@@ -1191,7 +1268,7 @@ __global__ __launch_bounds__(kTile * W) void k_radii_pairs(
         if (item >= n_items) return;
         const WorkItem w = items[item];
         radii_item<T, 1, false>(w, lane, sj_w[wave], sS_w[wave], sd_w[wave], sl_w[wave], P, Gx,
-                                I_fx, ovf, 0ull, cR);
+                                I_fx, ovf, 0ull, cR, box);
     }
 }
 
@@ -1249,6 +1326,15 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
                                             const Work<T>& wk, unsigned long long tmask)
 {
     constexpr int NJ = GRAD ? 5 : 1;
+    // Without salt the pair terms take the charges scaled by sqrt(kC), so that
+    // qq = kC q_i q_j carries the Coulomb constant and tau = kT / kC the GB
+    // factor; the phi and G sums are rescaled when they are rounded (sPhi,
+    // sG), which saves four multiplications per pair.  With salt the factors
+    // vary per pair and the charges stay as given.
+    const T sq = SALT ? T(1) : T(sqrt(kC));
+    const T tau = SALT || kC == T(0) ? T(0) : kT / kC;
+    const T qtau = T(-0.25) * tau;
+    const T sPhi = sq, sG = SALT ? T(1) : T(0.5) * tau;
     T xi[R], yi[R], zi[R], qi[R], Ri[R], ai[R];
     bool vi[R];
 #pragma unroll
@@ -1258,7 +1344,7 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
         if (vi[r]) {
             const int g = w.base + i;
             const Q4<T> p = P[g];
-            xi[r] = p.x; yi[r] = p.y; zi[r] = p.z; qi[r] = p.w;
+            xi[r] = p.x; yi[r] = p.y; zi[r] = p.z; qi[r] = p.w * sq;
             Ri[r] = ld_dev(Rt + g); ai[r] = ld_dev(At + g);
         } else {
             dummy_pos(i, xi[r], yi[r], zi[r]);
@@ -1305,8 +1391,10 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
         tail(J, pj, Rj, Aj);
+        Q4<T> ps = pj;
+        ps.w *= sq;
         wave_sync();
-        sj[lane] = pj; sj[lane + kTile] = pj;
+        sj[lane] = ps; sj[lane + kTile] = ps;
         sR[lane] = Rj; sR[lane + kTile] = Rj;
         sA[lane] = Aj; sA[lane + kTile] = Aj;
         wave_sync();
@@ -1331,11 +1419,12 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
             T invf = rsq(f2);
             T qq = act ? qi[r] * p.w : T(0);
             eC[r] += qq * invr;
-            // GB factor of the pair: k (1/eps_in - 1/eps_out) without salt;
-            // with salt kd = k (1/eps_in - exp(-kappa f)/eps_out) and the
-            // slope factor ks = kd - k kappa f exp(-kappa f)/eps_out
-            // (d/df (kd/f) = -ks/f^2)
-            T kd = kT, ks = kT;
+            // GB factor of the pair: with salt kd = k (1/eps_in -
+            // exp(-kappa f)/eps_out) and the slope factor ks = kd - k kappa f
+            // exp(-kappa f)/eps_out (d/df (kd/f) = -ks/f^2); without salt both
+            // are kT = k (1/eps_in - 1/eps_out) = tau kC, carried by the scaled
+            // charges and tau
+            [[maybe_unused]] T kd = kT, ks = kT;
             if constexpr (SALT) {
                 const T f = f2 * invf;
                 const T es = sk.kO * exp2neg(sk.kap2 * f);
@@ -1348,14 +1437,22 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
             if constexpr (GRAD) {
                 T qj = act ? p.w : T(0);
                 T qi_ = act ? qi[r] : T(0);
-                T wgt = kC * invr - kd * invf;
-                phii[r] += wgt * qj;
                 T invf3 = invf * invf * invf;
                 T invr3 = invr * invr * invr;
-                T fr = qq * (ks * invf3 * (T(1) - T(0.25) * ex) - kC * invr3);   // (dE/dr)/r
+                T wgt, fr, cg;
+                if constexpr (SALT) {
+                    wgt = kC * invr - kd * invf;
+                    fr = qq * (ks * invf3 * (T(1) - T(0.25) * ex) - kC * invr3);   // (dE/dr)/r
+                    cg = T(0.5) * ks * qq * invf3 * ex * (T(1) + t * T(kLn2));
+                } else {
+                    // scaled charges: phi weight over sqrt(kC), G term over tau / 2
+                    wgt = invr - tau * invf;
+                    fr = qq * ((ex * qtau + tau) * invf3 - invr3);
+                    cg = qq * invf3 * ex * (T(1) + t * T(kLn2));
+                }
+                phii[r] += wgt * qj;
                 T fx = fr * dx, fy = fr * dy, fz = fr * dz;
                 fxi[r] -= fx; fyi[r] -= fy; fzi[r] -= fz;
-                T cg = T(0.5) * ks * qq * invf3 * ex * (T(1) + t * T(kLn2));
                 Gi[r] += cg * rj;
                 acc[0] += fx;
                 acc[1] += fy;
@@ -1370,25 +1467,32 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
             walk_tile_rows2<T, NJ>(lane, aj, load, pair);
         if (R == 1 && J == w.I) {
             // self terms (f_ii = R_i): -(kd/2) q_i^2 / R_i in E_GB, -kd q_i / R_i
-            // in phi, (ks/2) q_i^2 / R_i^2 in G
+            // in phi, (ks/2) q_i^2 / R_i^2 in G (without salt in the scaled
+            // form of the walk's sums)
             T invR = rcp(Ri[0]);
-            T kd = kT, ks = kT;
+            [[maybe_unused]] T kd = kT, ks = kT;
             if constexpr (SALT) {
                 const T es = sk.kO * exp2neg(sk.kap2 * Ri[0]);
                 kd = kC - es;
                 ks = kd - es * sk.kap * Ri[0];
                 eG[0] += T(0.5) * qi[0] * qi[0] * kd * invR;
+                if constexpr (GRAD) {
+                    phii[0] -= kd * qi[0] * invR;
+                    Gi[0] += T(0.5) * ks * qi[0] * qi[0] * invR * invR;
+                }
             } else {
                 eG[0] += T(0.5) * qi[0] * qi[0] * invR;
-            }
-            if constexpr (GRAD) {
-                phii[0] -= kd * qi[0] * invR;
-                Gi[0] += T(0.5) * ks * qi[0] * qi[0] * invR * invR;
+                if constexpr (GRAD) {
+                    phii[0] -= tau * qi[0] * invR;
+                    Gi[0] += qi[0] * qi[0] * invR * invR;
+                }
             }
         }
         if constexpr (GRAD) {
             const int g = w.base + clamp_atom(j, w.n);
             long long v[5];
+            aj[3] *= sG;
+            aj[4] *= sPhi;
 #pragma unroll
             for (int a = 0; a < 5; ++a) {
                 v[a] = to_fixed(aj[a], kScaleF, bad);
@@ -1401,16 +1505,19 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const long long f[5] = {to_fixed(fxi[r], kScaleF, bad), to_fixed(fyi[r], kScaleF, bad),
-                                        to_fixed(fzi[r], kScaleF, bad), to_fixed(Gi[r], kScaleF, bad),
-                                        to_fixed(phii[r], kScaleF, bad)};
+                                        to_fixed(fzi[r], kScaleF, bad),
+                                        to_fixed(T(Gi[r] * sG), kScaleF, bad),
+                                        to_fixed(T(phii[r] * sPhi), kScaleF, bad)};
 #pragma unroll
                 for (int a = 0; a < 5; ++a) fix[r][a] = FIRST ? f[a] : fix[r][a] + f[a];
             }
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const long long e0 = to_fixed(T(kC * eC[r]), kScaleE, bad);
-            const long long e1 = to_fixed(T(-(SALT ? T(1) : kT) * eG[r]), kScaleE, bad);
+            // Coulomb: kC is in qq without salt; GB: -tau (scaled charges) or -1
+            // (salt: the factor is in every term)
+            const long long e0 = to_fixed(T((SALT ? kC : T(1)) * eC[r]), kScaleE, bad);
+            const long long e1 = to_fixed(T(-(SALT ? T(1) : tau) * eG[r]), kScaleE, bad);
             efix[r][0] = FIRST ? e0 : efix[r][0] + e0;
             efix[r][1] = FIRST ? e1 : efix[r][1] + e1;
         }
@@ -1557,6 +1664,7 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
     // j atoms through LDS int64 fixed-point atomics (exact, so the result does
     // not depend on the order of the rounds).
     constexpr bool DEFER = R == 1 && !CUT;
+    constexpr float kYmax = sizeof(T) == 4 ? GBMC_HCT_YMAX : (float)GBMC_HCT_YMAX64;
     T xi[R], yi[R], zi[R], rti[R], Si[R], Bi[R], si[R];
     bool vi[R];
 #pragma unroll
@@ -1633,7 +1741,8 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
         // at step k: k = 0..63 off the diagonal, 1..32 on it) and the marks
         int kstep = J == w.I ? 1 : 0;
         unsigned long long dmask = 0ull;
-        auto pair = [&](const JD& d, int r, bool act, T (&acc)[4]) {
+        auto pair_any = [&](const JD& d, int r, bool act, T (&acc)[4], auto sep_tag) {
+            constexpr bool SEP = decltype(sep_tag)::value;
             const Q4<T>& p = d.p;
             const Q4<T>& b = d.b;
             T dx = xi[r] - p.x, dy = yi[r] - p.y, dz = zi[r] - p.z;
@@ -1650,8 +1759,8 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
                 // only pairs of a real i atom are marked (padding lanes sit far
                 // apart, so none of theirs needs the closed form anyway); the
                 // packed rounds read the i atom back from global memory
-                chain_pair_fast(rr, invr, rti[r], Si[r], p.w, b.x, bi_, bj_, act && vi[r],
-                                1ull << kstep, dEdr, gij2, gji2, dmask);
+                chain_pair_fast<!SEP>(rr, invr, rti[r], Si[r], p.w, b.x, bi_, bj_, act && vi[r],
+                                      1ull << kstep, dEdr, gij2, gji2, dmask);
                 ++kstep;
             } else {
                 chain_pair(rr, r2, invr, rti[r], Si[r], p.w, b.x, bi_, bj_, dEdr, gij2, gji2,
@@ -1666,10 +1775,21 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
             acc[2] += fz;
             acc[3] += b.z * bi_ * gij2;
         };
-        if constexpr (R == 1)
-            walk_tile<T, 4>(lane, J == w.I, aj, load, pair);
-        else
+        auto pair = [&](const JD& d, int r, bool act, T (&acc)[4]) {
+            pair_any(d, r, act, acc, std::false_type{});
+        };
+        auto pair_sep = [&](const JD& d, int r, bool act, T (&acc)[4]) {
+            pair_any(d, r, act, acc, std::true_type{});
+        };
+        if constexpr (R == 1) {
+            // separated blocks (wave-uniform): no pair needs the closed form
+            if (DEFER && J != w.I && blocks_separated(wk.box, w.blk0 + w.I, w.blk0 + J, kYmax))
+                walk_tile<T, 4>(lane, false, aj, load, pair_sep);
+            else
+                walk_tile<T, 4>(lane, J == w.I, aj, load, pair);
+        } else {
             walk_tile_rows2<T, 4>(lane, aj, load, pair);
+        }
         // DEFER: the marked pairs, packed into rounds of up to 64 (the marks of
         // all lanes listed in lane order, lane t of a round taking list entry
         // t).  The j-side terms are rounded to fixed point per pair and added
@@ -1998,7 +2118,7 @@ __global__ __launch_bounds__(kTile * W) void k_pairs_queue(
         unsigned long long* sdef = reinterpret_cast<unsigned long long*>(sS + 2 * kTile);
         int* slist = reinterpret_cast<int*>(sdef + kTile);
         radii_item<T, 1, false>(w, lane, sj, sS, sdef, slist, wk.P, wk.Gx, wk.I_fx, wk.ovf, 0ull,
-                                T(0));
+                                T(0), wk.box);
         pq_complete(q, 0, w, lane, [&](int L) {
             const int i = L * kTile + lane;
             if (i < w.n) radii_final_atom<T>(w.base + i, RHO, c, wk, born_R);
@@ -2612,20 +2732,21 @@ hipError_t launch_radii(const WorkItem* items, int n_items, int wpg, int n_atoms
     StageClear zc{};
     zc.acc0 = w.I_fx; zc.n_acc0 = 1;
     zc.f0 = w.ovf; zc.n_f0 = 2;
-    hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms, w.perm,
-                       x, y, z, (const T*)nullptr, rho, screen, (T)c.offset, w.P, w.Gx, zc);
+    hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(cp.n_blocks, 4)), dim3(256), 0, s, cp.blocks,
+                       cp.n_blocks, n_atoms, w.perm, x, y, z, (const T*)nullptr, rho, screen,
+                       (T)c.offset, w.P, w.Gx, w.box, zc);
     if (c.rgbmax > 0.0 || c.cutoff > 0.0) launch_cut_lists<T>(cp, c, w, s);
     if (n_items > 0) {
         if (c.rgbmax > 0.0)
             GBMC_DISPATCH_W(wpg, GBMC_LAUNCH_TIMED(ev, kKRadii, (k_radii_pairs<T, W, true>),
                                                    dim3(cut_groups(w.cut_cap, W)), dim3(kTile * W),
                                                    s, items, n_items, w.citems[0], w.ccount, w.P,
-                                                   w.Gx, w.I_fx, w.ovf, (T)c.rgbmax))
+                                                   w.Gx, w.I_fx, w.ovf, (T)c.rgbmax, w.box))
         else
             GBMC_DISPATCH_W(wpg, GBMC_LAUNCH_TIMED(ev, kKRadii, (k_radii_pairs<T, W, false>),
                                                    dim3(blocks_for(n_items, W)), dim3(kTile * W), s,
                                                    items, n_items, w.citems[0], w.ccount, w.P,
-                                                   w.Gx, w.I_fx, w.ovf, (T)0))
+                                                   w.Gx, w.I_fx, w.ovf, (T)0, w.box))
     }
     hipLaunchKernelGGL(k_radii_finalize<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
                        rho, c, w, born_R);
@@ -2647,8 +2768,9 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
     if (n_atoms > 0) {
         StageClear zc{};
         zc.acc0 = w.F_fx; zc.n_acc0 = 8;
-        hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s, n_atoms,
-                           w.perm, x, y, z, q, rho, screen, (T)c.offset, w.P, w.Gx, zc);
+        hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(cp.n_blocks, 4)), dim3(256), 0, s,
+                           cp.blocks, cp.n_blocks, n_atoms, w.perm, x, y, z, q, rho, screen,
+                           (T)c.offset, w.P, w.Gx, w.box, zc);
     }
     // block bounds and compacted work (positions as staged here, the same as
     // the preceding gb_radii call's)
@@ -2760,9 +2882,10 @@ hipError_t launch_queued(const QueueShape& sh, int n_atoms, int n_sys, const T* 
     zc.f0 = w.ovf; zc.n_f0 = 2;
     zc.f1 = w.qhead; zc.n_f1 = kQueueWords;
     zc.cnt = w.qcnt; zc.n_cnt = 3 * sh.n_blocks;
-    hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(std::max(n_atoms, kQueueWords), 256)),
-                       dim3(256), 0, s, n_atoms, w.perm, x, y, z, q, rho, screen, (T)c.offset, w.P,
-                       w.Gx, zc);
+    // (one wave per block: at least 256 threads, beyond the kQueueWords flags)
+    hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(sh.n_blocks, 4)), dim3(256), 0, s, sh.blocks,
+                       sh.n_blocks, n_atoms, w.perm, x, y, z, q, rho, screen, (T)c.offset, w.P,
+                       w.Gx, w.box, zc);
     PQueue pq{};
     int ntot = 0;
     for (int k = 0; k < 3; ++k) {
