@@ -1394,9 +1394,9 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
         Q4<T> ps = pj;
         ps.w *= sq;
         wave_sync();
-        sj[lane] = ps; sj[lane + kTile] = ps;
-        sR[lane] = Rj; sR[lane + kTile] = Rj;
-        sA[lane] = Aj; sA[lane + kTile] = Aj;
+        sj[lane] = ps;
+        sR[lane] = Rj;
+        sA[lane] = Aj;
         wave_sync();
         fetch(Jn < w.J1 ? Jn : J, pj, Rj, Aj);
         T fxi[R], fyi[R], fzi[R], Gi[R], phii[R], eC[R], eG[R];
@@ -1405,7 +1405,12 @@ __device__ __forceinline__ void energy_item(const WorkItem& w, int lane, Q4<T>* 
             fxi[r] = fyi[r] = fzi[r] = Gi[r] = phii[r] = eC[r] = eG[r] = T(0);
         T aj[NJ];
         struct JD { Q4<T> p; T Rv, Av; };
-        auto load = [&](int s) { return JD{sj[s], sR[s], sA[s]}; };
+        // one copy of the block, read at slot (lane + step) mod 64 (measured
+        // faster here than the doubled copy the other passes read without a wrap)
+        auto load = [&](int s) {
+            const int m = s & (kTile - 1);
+            return JD{sj[m], sR[m], sA[m]};
+        };
         auto pair = [&](const JD& d, int r, bool act, T (&acc)[NJ]) {
             const Q4<T>& p = d.p;
             const T rj = d.Rv;
@@ -1559,9 +1564,9 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
     const T* __restrict__ Rt, const T* __restrict__ At, T kC, T kT, SaltK<T> sk, CutK<T> ck,
     Work<T> wk)
 {
-    __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, q
-    __shared__ T sR_w[W][2 * kTile];
-    __shared__ T sA_w[W][2 * kTile];
+    __shared__ Q4<T> sj_w[W][kTile];     // x, y, z, q
+    __shared__ T sR_w[W][kTile];
+    __shared__ T sA_w[W][kTile];
     const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
     if constexpr (CUT) {
         // compacted one-row items of the pair cutoff
