@@ -627,15 +627,20 @@ def time_md_loop(steps, warmup, n_rep=16, attempt_every=5, exchange_every=10):
 
 
 def host_cpu():
-    """CPU model of the host (lscpu, else /proc/cpuinfo) and its core count."""
+    """CPU model of the host (lscpu, else /proc/cpuinfo), the family / model /
+    stepping numbers and clock that identify it where the name is generic (a
+    virtual machine's), and its core count."""
     import subprocess
-    model = None
+    info = {}
     try:
         txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
-        model = next((l.split(":", 1)[1].strip() for l in txt.splitlines()
-                      if l.startswith("Model name")), None)
+        for l in txt.splitlines():
+            if ":" in l:
+                k, v = l.split(":", 1)
+                info[k.strip()] = v.strip()
     except (OSError, subprocess.SubprocessError):
         pass
+    model = info.get("Model name")
     if not model:
         try:
             with open("/proc/cpuinfo") as f:
@@ -643,8 +648,14 @@ def host_cpu():
                               if l.startswith("model name")), None)
         except OSError:
             pass
-    return {"cpu_model": model, "nproc": os.cpu_count(),
-            "threads_allowed": len(os.sched_getaffinity(0))}
+    out = {"cpu_model": model, "nproc": os.cpu_count(),
+           "threads_allowed": len(os.sched_getaffinity(0))}
+    for key, name in (("CPU family", "cpu_family"), ("Model", "cpu_model_number"),
+                      ("Stepping", "cpu_stepping"), ("CPU max MHz", "cpu_max_mhz"),
+                      ("BogoMIPS", "bogomips"), ("Hypervisor vendor", "hypervisor")):
+        if key in info:
+            out[name] = info[key]
+    return out
 
 
 def stratified_sample(systems, n_pick=8):

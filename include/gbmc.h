@@ -89,8 +89,10 @@ typedef struct {
  * 64-atom j blocks one wavefront walks for its i block (>= 1), and how many
  * such independent wavefronts share a workgroup (1, 2, 4 or 8).  Every 64 x 64
  * tile is rounded into fixed point on its own, so results are bitwise
- * independent of the knobs.  Defaults (j blocks / waves): FP32 descreening
- * 1 / 1, energy 1 / 8, chain 1 / 4; FP64 1 / 2 for all three passes. */
+ * independent of the knobs.  Defaults (tuning NULL; j blocks / waves): FP32
+ * descreening 1 / 2, energy 1 / 4, chain 1 / 4, and for FP32 batches of at
+ * least 2^19 tiles (sum over systems of nb (nb + 1) / 2, nb = ceil(n / 64))
+ * energy and chain 4 / 1; FP64 1 / 2 for all three passes. */
 enum { GBMC_PASS_RADII = 0, GBMC_PASS_ENERGY = 1, GBMC_PASS_CHAIN = 2, GBMC_N_PASSES = 3 };
 typedef struct {
     int32_t j_blocks_per_item[GBMC_N_PASSES];

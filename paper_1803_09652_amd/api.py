@@ -62,7 +62,12 @@ def _f64p(a: np.ndarray):
 
 
 # the library's default work shapes (radii, energy, chain) per precision
-DEFAULT_SHAPE = {"fp32": {"j_blocks_per_item": (1, 1, 1), "waves_per_group": (1, 8, 4)},
+# The library's default shapes for batches below its long-item size (a plan
+# created without either knob takes the library's own choice, which for FP32
+# batches of at least 2^19 tiles walks four j blocks per item with one wave per
+# workgroup in the energy and chain passes); a knob left None when the other
+# is given takes the value below.
+DEFAULT_SHAPE = {"fp32": {"j_blocks_per_item": (1, 1, 1), "waves_per_group": (2, 4, 4)},
                  "fp64": {"j_blocks_per_item": (1, 1, 1), "waves_per_group": (2, 2, 2)}}
 
 
