@@ -137,6 +137,30 @@ def test_batch_equals_single_systems_bitwise():
         assert one["Ec"][0] == whole["Ec"][b] and one["Egb"][0] == whole["Egb"][b]
 
 
+def test_uneven_batch_equals_its_systems_alone_bitwise():
+    # the 64-system batch (library default shapes for its size: items of four
+    # j blocks in the energy and chain passes) against 8 of its systems at
+    # evenly spaced size ranks, each run alone (single-tile items): every
+    # result bitwise equal, since every tile and item sum is rounded to fixed
+    # point on its own and the integer sums do not depend on the order
+    p_gpu, _ = params_pair()
+    systems = synth.uneven_batch_64()
+    g, batch, plan, atoms = build(systems, "fp32")
+    whole = gpu_eval(plan, atoms, p_gpu)
+    off = batch.atom_offset
+    del plan, atoms
+    sizes = np.array([s_.n for s_ in systems])
+    order = np.argsort(sizes, kind="stable")
+    pick = [int(order[r]) for r in np.unique(np.round(np.linspace(0, len(systems) - 1, 8)).astype(int))]
+    assert sizes[pick].min() == sizes.min() and sizes[pick].max() == sizes.max()
+    for b in pick:
+        g, bb, pl, at = build([systems[b]], "fp32")
+        one = gpu_eval(pl, at, p_gpu)
+        for k in ("R", "force", "dEdq", "dEdrho"):
+            assert np.array_equal(one[k], whole[k][off[b]:off[b + 1]]), (b, k)
+        assert one["Ec"][0] == whole["Ec"][b] and one["Egb"][0] == whole["Egb"][b], b
+
+
 def test_energy_only_mode_matches_full():
     p_gpu, _ = params_pair()
     g, batch, plan, atoms = build([_sys(31, 300)], "fp32")
