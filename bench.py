@@ -201,16 +201,19 @@ class Workload:
                                    self.T, p)
             mc = g.mc_step(self.plan, self.sites, cur, self.cur, self.pH, self.E_rep, dE, dG,
                            self.u, self.T, p, counters=self.counters, q_out=nxt.q)
+            # the exchange needs only the electron counts of the attempt
+            # (Eq. 14), so it ends the Monte Carlo branch instead of waiting
+            # on the main stream for the join
+            if self.exchange:
+                acc, _ = g.remd_exchange(self.E_rung, mc["n_electrons"], self.rep_of_rung, parity,
+                                         self.ux, self.T, True, E_out=self.E_rep)
+                self.last_exchange = acc
+            else:
+                self.last_exchange = None
         if mc_stream is not main:
             main.wait_stream(mc_stream)
         # the step's outputs (static tensors of a captured graph)
         self.last = {"R": R, "force_out": ef, "dE": dE, "dG": dG, "mc": mc, "q_out": nxt.q}
-        if self.exchange:
-            acc, _ = g.remd_exchange(self.E_rung, mc["n_electrons"], self.rep_of_rung, parity,
-                                     self.ux, self.T, True, E_out=self.E_rep)
-            self.last_exchange = acc
-        else:
-            self.last_exchange = None
         return ef
 
 

@@ -56,3 +56,34 @@ def test_overlapped_graph_step_equals_serial_eager_step():
             assert np.array_equal(a[key], b[key]), key
     # the Monte Carlo chain moved: some attempts were accepted
     assert ref[-1]["counters"][:, 1].sum() > 0
+
+
+def test_two_step_graph_equals_serial_eager_steps():
+    # the benchmark's replay loop: one graph holding an even and an odd step
+    # back to back; after every replay the state equals the eager sequence's
+    import bench
+    n = 12
+    ref = _run(overlap=False, use_graph=False, n_steps=n)
+    w = bench.Workload("fp32", n + 2, "spatial", None, True)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        w.step(0)
+        w.step(1)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    pair = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(pair):
+        w.step(0)
+        w.step(1)
+    k = 2
+    while k + 2 <= n:
+        pair.replay()
+        k += 2
+        torch.cuda.synchronize()
+        b = ref[k - 1]
+        assert np.array_equal(w.atoms.q.cpu().numpy(), b["q"])
+        assert np.array_equal(w.cur.cpu().numpy(), b["state"])
+        assert np.array_equal(w.E_rep.cpu().numpy(), b["E_rep"])
+        assert np.array_equal(w.rep_of_rung.cpu().numpy(), b["rep"])
+        assert np.array_equal(w.counters.cpu().numpy(), b["counters"])
