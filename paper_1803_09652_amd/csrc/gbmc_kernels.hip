@@ -311,9 +311,11 @@ __device__ __forceinline__ void radii_pair_fast(float xi, float yi, float zi, fl
     float r = r2 * invr;
     float xij = Sj * invr, yij = xij * xij;
     float xji = Si * invr, yji = xji * xji;
-    hij = xij * yij * invr * hct_poly(yij);
-    hji = xji * yji * invr * hct_poly(yji);
-    if constexpr (!TEST) return;             // a separated tile: every pair is non-overlapping
+    // a separated tile (!TEST): every pair is non-overlapping with y <= YFAR,
+    // where the short fit is as accurate as the wide one
+    hij = xij * yij * invr * (TEST ? hct_poly(yij) : hct_poly_far(yij));
+    hji = xji * yji * invr * (TEST ? hct_poly(yji) : hct_poly_far(yji));
+    if constexpr (!TEST) return;
     const bool fast = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX) & (r - Si >= rtj) &
                       (yji <= GBMC_HCT_YMAX);
     if (__builtin_amdgcn_ballot_w64(!fast) != 0ull) {
@@ -406,8 +408,8 @@ __device__ __forceinline__ void chain_pair_fast(float r, float invr, float rti, 
     wij *= wij;
     wji *= wji;
     const float tij = yij * wij, tji = yji * wji;
-    float aij = xij * fmaf(yij, hct_poly_d(yij), tij);
-    float aji = xji * fmaf(yji, hct_poly_d(yji), tji);
+    float aij = xij * fmaf(yij, TEST ? hct_poly_d(yij) : hct_poly_far(yij), tij);
+    float aji = xji * fmaf(yji, TEST ? hct_poly_d(yji) : hct_poly_far(yji), tji);
     gij2 = tij * u;
     gji2 = tji * u;
     const bool fast = !TEST || ((r - Sj >= rti) & (yij <= GBMC_HCT_YMAX) & (r - Si >= rtj) &
@@ -475,8 +477,8 @@ __device__ __forceinline__ void radii_pair_fast(double xi, double yi, double zi,
     dist64(xi, yi, zi, xj, yj, zj, r, invr);
     const double xij = Sj * invr, yij = xij * xij;
     const double xji = Si * invr, yji = xji * xji;
-    hij = xij * yij * invr * hct_poly64(yij);
-    hji = xji * yji * invr * hct_poly64(yji);
+    hij = xij * yij * invr * (TEST ? hct_poly64(yij) : hct_poly64_far(yij));
+    hji = xji * yji * invr * (TEST ? hct_poly64(yji) : hct_poly64_far(yji));
     if constexpr (!TEST) return;
     const bool fast = (r - Sj >= rti) & (yij <= GBMC_HCT_YMAX64) & (r - Si >= rtj) &
                       (yji <= GBMC_HCT_YMAX64);
@@ -502,8 +504,8 @@ __device__ __forceinline__ void chain_pair_fast(double r, double invr, double rt
     rcp_pair(1.0 - yij, 1.0 - yji, wij, wji);
     wij *= wij;
     wji *= wji;
-    double aij = xij * yij * (hct_poly64(yij) + wij);    // -r^2 dH/dr
-    double aji = xji * yji * (hct_poly64(yji) + wji);
+    double aij = xij * yij * ((TEST ? hct_poly64(yij) : hct_poly64_far(yij)) + wij);   // -r^2 dH/dr
+    double aji = xji * yji * ((TEST ? hct_poly64(yji) : hct_poly64_far(yji)) + wji);
     gij2 = yij * wij * u;
     gji2 = yji * wji * u;
     const bool fast = !TEST || ((r - Sj >= rti) & (yij <= GBMC_HCT_YMAX64) & (r - Si >= rtj) &
@@ -1051,9 +1053,10 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
 {
     // DEFER (one row, all pairs): overlapping pairs are marked during
     // the walk and evaluated afterwards in packed rounds, as in the chain pass;
-    // tiles of separated blocks (blocks_separated) skip the per-pair test
+    // tiles of separated blocks (blocks_separated) skip the per-pair test and
+    // take the short fit of H for y <= YFAR
     constexpr bool DEFER = R == 1 && !CUT;
-    constexpr float kYmax = sizeof(T) == 4 ? GBMC_HCT_YMAX : (float)GBMC_HCT_YMAX64;
+    constexpr float kYfar = GBMC_HCT_YFAR;    // separated tiles: every pair has y <= this
     T xi[R], yi[R], zi[R], rti[R], Si[R];
     bool vi[R];
 #pragma unroll
@@ -1147,7 +1150,7 @@ __device__ __forceinline__ void radii_item(const WorkItem& w, int lane, Q4<T>* s
         };
         if constexpr (R == 1) {
             // wave-uniform: the blocks of the tile come from the item
-            if (DEFER && J != w.I && blocks_separated(box, w.blk0 + w.I, w.blk0 + J, kYmax))
+            if (DEFER && J != w.I && blocks_separated(box, w.blk0 + w.I, w.blk0 + J, kYfar))
                 walk_tile<T, 1>(lane, false, aj, load, pair_sep);
             else
                 walk_tile<T, 1>(lane, J == w.I, aj, load, pair);
@@ -1669,7 +1672,7 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
     // j atoms through LDS int64 fixed-point atomics (exact, so the result does
     // not depend on the order of the rounds).
     constexpr bool DEFER = R == 1 && !CUT;
-    constexpr float kYmax = sizeof(T) == 4 ? GBMC_HCT_YMAX : (float)GBMC_HCT_YMAX64;
+    constexpr float kYfar = GBMC_HCT_YFAR;    // separated tiles: every pair has y <= this
     T xi[R], yi[R], zi[R], rti[R], Si[R], Bi[R], si[R];
     bool vi[R];
 #pragma unroll
@@ -1788,7 +1791,7 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
         };
         if constexpr (R == 1) {
             // separated blocks (wave-uniform): no pair needs the closed form
-            if (DEFER && J != w.I && blocks_separated(wk.box, w.blk0 + w.I, w.blk0 + J, kYmax))
+            if (DEFER && J != w.I && blocks_separated(wk.box, w.blk0 + w.I, w.blk0 + J, kYfar))
                 walk_tile<T, 4>(lane, false, aj, load, pair_sep);
             else
                 walk_tile<T, 4>(lane, J == w.I, aj, load, pair);
