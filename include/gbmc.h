@@ -115,8 +115,8 @@ gbmc_status gbmc_params_validate(const gbmc_gb_params* params);
 
 /* Host-only: the pair-tile work list a plan with this layout would use for a
  * pass walking j_blocks_per_item j blocks per item (>= 1); row_pairs != 0
- * gives the schedule of the FP32 plans' energy pass, 0 that of every other
- * pass.
+ * gives the schedule of the FP32 plans' energy and chain passes, 0 that of
+ * their descreening pass and of every pass of FP64 plans.
  * host_atom_offset[n_systems+1] (host) must start at 0 and be non-decreasing.
  * Each item covers, for one system, the 64-atom i blocks [I0, I1) (one or
  * two) against the j blocks [J0, J1), J0 >= I0 (every unordered pair of atoms

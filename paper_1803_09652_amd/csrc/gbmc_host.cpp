@@ -350,7 +350,8 @@ gbmc_status gbmc_params_validate(const gbmc_gb_params* p)
 }
 
 // The work lists of a plan, one per pass (build_items with the pass's j
-// blocks per item; two-row items in the energy pass of FP32 plans), and the
+// blocks per item; two-row items in the energy and chain passes of FP32
+// plans), and the
 // number of items of each pass touching each 64-atom block (the counts the
 // queued launch's per-block counters complete at).  The queued launch runs a
 // pass's items before the next pass's, and a block of the next pass can start
@@ -365,7 +366,7 @@ static void plan_schedule(int32_t n_systems, const int32_t* off, gbmc_precision 
 {
     for (int k = 0; k < GBMC_N_PASSES; ++k)
         build_items(n_systems, off, t.j_blocks_per_item[k],
-                    prec == GBMC_FP32_FIXED && k == GBMC_PASS_ENERGY, items[k]);
+                    prec == GBMC_FP32_FIXED && k != GBMC_PASS_RADII, items[k]);
     std::vector<int32_t> rank(n_systems);
     for (int32_t b = 0; b < n_systems; ++b) rank[b] = b;
     std::stable_sort(rank.begin(), rank.end(), [&](int32_t a, int32_t c) {

@@ -1664,14 +1664,14 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
                                            const T* __restrict__ Brt, const Work<T>& wk, T cR,
                                            unsigned long long tmask)
 {
-    // DEFER (one row, all pairs): the walk evaluates the polynomial form
-    // only and marks the pairs that need the closed form (overlapping spheres)
-    // in a per-lane mask of walk steps; after the walk the marked pairs are
-    // evaluated packed, one per lane per round, instead of with most of the
-    // wave masked off in the step that met them.  Their j-side terms go to the
-    // j atoms through LDS int64 fixed-point atomics (exact, so the result does
-    // not depend on the order of the rounds).
-    constexpr bool DEFER = R == 1 && !CUT;
+    // DEFER (all pairs): the walk evaluates the polynomial form only and
+    // marks the pairs that need the closed form (overlapping spheres) in a
+    // per-lane, per-row mask of walk steps; after the walk the marked pairs
+    // are evaluated packed, one per lane per round, instead of with most of
+    // the wave masked off in the step that met them.  Their j-side terms go to
+    // the j atoms through LDS int64 fixed-point atomics (exact, so the result
+    // does not depend on the order of the rounds).
+    constexpr bool DEFER = !CUT;
     constexpr float kYfar = GBMC_HCT_YFAR;    // separated tiles: every pair has y <= this
     T xi[R], yi[R], zi[R], rti[R], Si[R], Bi[R], si[R];
     bool vi[R];
@@ -1748,7 +1748,9 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
         // DEFER: walk step of the next pair call (the walk visits slot lane + k
         // at step k: k = 0..63 off the diagonal, 1..32 on it) and the marks
         int kstep = J == w.I ? 1 : 0;
-        unsigned long long dmask = 0ull;
+        unsigned long long dmask[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) dmask[r] = 0ull;
         auto pair_any = [&](const JD& d, int r, bool act, T (&acc)[4], auto sep_tag) {
             constexpr bool SEP = decltype(sep_tag)::value;
             const Q4<T>& p = d.p;
@@ -1768,8 +1770,8 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
                 // apart, so none of theirs needs the closed form anyway); the
                 // packed rounds read the i atom back from global memory
                 chain_pair_fast<!SEP>(rr, invr, rti[r], Si[r], p.w, b.x, bi_, bj_, act && vi[r],
-                                      1ull << kstep, dEdr, gij2, gji2, dmask);
-                ++kstep;
+                                      1ull << kstep, dEdr, gij2, gji2, dmask[r]);
+                if (r == R - 1) ++kstep;            // a step serves every row of the item
             } else {
                 chain_pair(rr, r2, invr, rti[r], Si[r], p.w, b.x, bi_, bj_, dEdr, gij2, gji2,
                            dri[r], acc[3]);
@@ -1796,24 +1798,34 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
             else
                 walk_tile<T, 4>(lane, J == w.I, aj, load, pair);
         } else {
-            walk_tile_rows2<T, 4>(lane, aj, load, pair);
+            // two rows (never a diagonal tile): separated if both rows' tiles are
+            if (DEFER && blocks_separated(wk.box, w.blk0 + w.I, w.blk0 + J, kYfar) &&
+                blocks_separated(wk.box, w.blk0 + w.I + 1, w.blk0 + J, kYfar))
+                walk_tile_rows2<T, 4>(lane, aj, load, pair_sep);
+            else
+                walk_tile_rows2<T, 4>(lane, aj, load, pair);
         }
         // DEFER: the marked pairs, packed into rounds of up to 64 (the marks of
         // all lanes listed in lane order, lane t of a round taking list entry
         // t).  The j-side terms are rounded to fixed point per pair and added
         // with LDS integer atomics (sdef[a * 64 + j lane]: exact, so the order
         // of a round's lanes does not matter); the i-side terms go back to the
-        // i atom's lane, which owns a contiguous run of the round's entries,
-        // and join its FP32 sums in list order.
+        // i atom's lane, which owns a contiguous run of the round's entries
+        // (its first row's marks, then its second row's), and join its FP32
+        // sums in list order.
         bool deferred = false;
         if constexpr (DEFER) {
-            deferred = __builtin_amdgcn_ballot_w64(dmask != 0ull) != 0ull;
+            unsigned long long any = 0ull;
+#pragma unroll
+            for (int r = 0; r < R; ++r) any |= dmask[r];
+            deferred = __builtin_amdgcn_ballot_w64(any != 0ull) != 0ull;
             if (deferred) {
 #pragma unroll
                 for (int a = 0; a < 4; ++a) sdef[a * kTile + lane] = 0ull;
                 wave_sync();
                 for (;;) {
-                    const int cnt = __builtin_popcountll(dmask);
+                    const int cnt0 = __builtin_popcountll(dmask[0]);
+                    const int cnt = R == 1 ? cnt0 : cnt0 + __builtin_popcountll(dmask[R - 1]);
                     int incl = cnt;                     // inclusive scan over the lanes
 #pragma unroll
                     for (int d = 1; d < kTile; d <<= 1) {
@@ -1825,16 +1837,25 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
                     // this lane's entries of the round: list slots [o0, o0 + n)
                     const int o0 = incl - cnt;
                     const int n = o0 < kTile ? min(cnt, kTile - o0) : 0;
+                    const int n0 = min(n, cnt0);        // entries [0, n0) of the run: first row
                     for (int t = o0; t < o0 + n; ++t) {
-                        const int k = __builtin_ctzll(dmask);
-                        dmask &= dmask - 1ull;
-                        slist[t] = (lane << 8) | k;
+                        int k, ir;
+                        if (R == 1 || dmask[0] != 0ull) {
+                            k = __builtin_ctzll(dmask[0]);
+                            dmask[0] &= dmask[0] - 1ull;
+                            ir = 0;
+                        } else {
+                            k = __builtin_ctzll(dmask[R - 1]);
+                            dmask[R - 1] &= dmask[R - 1] - 1ull;
+                            ir = 1;
+                        }
+                        slist[t] = (lane << 8) | (ir << 7) | k;
                     }
                     wave_sync();
                     T iv[4] = {T(0), T(0), T(0), T(0)};
                     if (lane < total) {
-                        const int e = slist[lane], il = e >> 8, k = e & 0xff;
-                        const int gi = w.base + w.I * kTile + il;
+                        const int e = slist[lane], il = e >> 8, k = e & 0x7f;
+                        const int gi = w.base + (w.I + ((e >> 7) & 1)) * kTile + il;
                         const Q4<T> pi = P[gi];
                         const Q4<T> gxi = Gx[gi];       // rt, S, screen
                         const T bi_ = ld_dev(Brt + gi);
@@ -1868,7 +1889,12 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
                         const T v0 = from_lane(iv[0], src), v1 = from_lane(iv[1], src);
                         const T v2 = from_lane(iv[2], src), v3 = from_lane(iv[3], src);
                         if (u < n) {
-                            fxi[0] += v0; fyi[0] += v1; fzi[0] += v2; dri[0] += v3;
+                            if (R == 1 || u < n0) {
+                                fxi[0] += v0; fyi[0] += v1; fzi[0] += v2; dri[0] += v3;
+                            } else {
+                                fxi[R - 1] += v0; fyi[R - 1] += v1; fzi[R - 1] += v2;
+                                dri[R - 1] += v3;
+                            }
                         }
                     }
                     wave_sync();
@@ -1931,8 +1957,6 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
     __shared__ unsigned long long sd_w[W][ND];
     __shared__ int sl_w[W][NL];
     const int wave = threadIdx.x / kTile, lane = threadIdx.x % kTile;
-    // the chain pass runs one-row items only (its two-row form was slower:
-    // fewer waves in flight for less saved work)
     if constexpr (CUT) {
         const int n = wk.ccount[0];
         for (int it = __builtin_amdgcn_readfirstlane(blockIdx.x * W + wave); it < n;
@@ -1947,8 +1971,14 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
         const int item = __builtin_amdgcn_readfirstlane(blockIdx.x * W + wave);
         if (item >= n_items) return;
         const WorkItem w = items[item];
-        chain_item<T, 1, false, ONE>(w, lane, sj_w[wave], sb_w[wave], sd_w[wave], sl_w[wave], P, Gx,
-                                     Brt, wk, cR, 0ull);
+        // two-row items exist in the chain and energy passes of FP32 plans only
+        if (sizeof(T) == 4 && w.rows == 2)
+            chain_item<T, sizeof(T) == 4 ? 2 : 1, false, ONE>(w, lane, sj_w[wave], sb_w[wave],
+                                                            sd_w[wave], sl_w[wave], P, Gx, Brt, wk,
+                                                            cR, 0ull);
+        else
+            chain_item<T, 1, false, ONE>(w, lane, sj_w[wave], sb_w[wave], sd_w[wave], sl_w[wave], P,
+                                         Gx, Brt, wk, cR, 0ull);
     }
 }
 
@@ -2151,8 +2181,12 @@ __global__ __launch_bounds__(kTile * W) void k_pairs_queue(
         Q4<T>* sb = sj + 2 * kTile;
         unsigned long long* sdef = reinterpret_cast<unsigned long long*>(sb + 2 * kTile);
         int* slist = reinterpret_cast<int*>(sdef + 4 * kTile);
-        chain_item<T, 1, false, ONE>(w, lane, sj, sb, sdef, slist, wk.P, wk.Gx, wk.Brt_t, wk, T(0),
-                                     0ull);
+        if (sizeof(T) == 4 && w.rows == 2)
+            chain_item<T, sizeof(T) == 4 ? 2 : 1, false, ONE>(w, lane, sj, sb, sdef, slist, wk.P,
+                                                            wk.Gx, wk.Brt_t, wk, T(0), 0ull);
+        else
+            chain_item<T, 1, false, ONE>(w, lane, sj, sb, sdef, slist, wk.P, wk.Gx, wk.Brt_t, wk,
+                                         T(0), 0ull);
     }
 }
 
