@@ -394,6 +394,8 @@ __device__ __forceinline__ void chain_pair(float r, float r2, float invr, float 
 // A pair that needs the closed form in either direction (act only) gets zero
 // terms and its bit in mask (one wave-uniform branch, taken only in the steps
 // that meet such a pair); the caller evaluates those pairs after the walk.
+// On separated tiles (TEST false, y <= YFAR) the factor (1 - y)^-2 comes from
+// its degree-5 fit, without a reciprocal.
 template <bool TEST = true>
 __device__ __forceinline__ void chain_pair_fast(float r, float invr, float rti, float Si, float rtj,
                                                 float Sj, float bi, float bj, bool act,
@@ -404,9 +406,14 @@ __device__ __forceinline__ void chain_pair_fast(float r, float invr, float rti, 
     const float xij = Sj * invr, yij = xij * xij;
     const float xji = Si * invr, yji = xji * xji;
     float wij, wji;
-    rcp_pair(1.0f - yij, 1.0f - yji, wij, wji);
-    wij *= wij;
-    wji *= wji;
+    if constexpr (TEST) {
+        rcp_pair(1.0f - yij, 1.0f - yji, wij, wji);
+        wij *= wij;
+        wji *= wji;
+    } else {
+        wij = hct_w_far(yij);
+        wji = hct_w_far(yji);
+    }
     const float tij = yij * wij, tji = yji * wji;
     float aij = xij * fmaf(yij, TEST ? hct_poly_d(yij) : hct_poly_far(yij), tij);
     float aji = xji * fmaf(yji, TEST ? hct_poly_d(yji) : hct_poly_far(yji), tji);
