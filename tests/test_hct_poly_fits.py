@@ -4,8 +4,8 @@ the fitting script.
 
 For a non-overlapping descreening sphere the HCT integral is H = g(x)/r with
 x = S/r and g(x) = (x/(1 - x^2) - atanh x)/2 (the published HCT pair integral
-of the GB-OBC model the paper names, Sec. III.D), whose Taylor series is g(x) = x^3 sum_{k>=1} k x^(2k-2)
-/ (2k + 1); the kernels evaluate P(y) = g(x)/x^3, y = x^2, and the factor
+of the GB-OBC model the paper names, Sec. III.D), whose Taylor series is
+g(x) = x^3 sum_{k>=1} k x^(2k-2) / (2k + 1); the kernels evaluate P(y) = g(x)/x^3, y = x^2, and the factor
 W(y) = (1 - y)^-2 of its derivatives.  Each fit is evaluated here by Horner's
 rule in its own precision (products and sums rounded separately, a bound on
 the fused form the kernels use) on a fine grid of its stated domain, and must
