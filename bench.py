@@ -52,6 +52,26 @@ FLOPS_PER_PAIR["evaluate_pairs"] = FLOPS_PER_PAIR["radii_pairs"] + FLOPS_PER_PAI
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 
 
+# Processing order of the pair passes: compact 64-atom blocks by recursive
+# bisection.  More tiles then have their two blocks far enough apart for the
+# walk without the per-pair overlap test than in a Morton order (90 % against
+# 76 % of the off-diagonal tiles of the 64-system batch), which measured
+# 1.5-3 % faster per step on both batches.
+DEFAULT_ORDER = "blocks"
+
+
+def set_atom_order(plan, b, order):
+    """Sets the plan's processing order: "blocks" (compact 64-atom blocks),
+    "spatial" (Morton) or "identity" (the caller's order)."""
+    import paper_1803_09652_amd as g
+    if order == "spatial":
+        plan.set_order(g.spatial_order(b.atom_offset, b.x, b.y, b.z))
+    elif order == "blocks":
+        plan.set_order(g.block_order(b.atom_offset, b.x, b.y, b.z))
+    elif order != "identity":
+        raise ValueError(f"unknown atom order {order!r}")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -86,8 +106,9 @@ def parse():
                     help="also time the headline workload with the work shapes the autotuner "
                          "picks for it (the headline itself uses the library defaults, the "
                          "shapes the committed counters were taken with)")
-    ap.add_argument("--order", choices=["spatial", "blocks", "identity"], default="spatial",
-                    help="processing order of the pair passes (results are order independent)")
+    ap.add_argument("--order", choices=["spatial", "blocks", "identity"], default=DEFAULT_ORDER,
+                    help="processing order of the pair passes (results depend on it only "
+                         "through FP32 rounding inside tiles)")
     return ap.parse_args()
 
 
@@ -119,7 +140,7 @@ class Workload:
     neighbouring rungs); with `systems` and exchange=False, any batch of
     distinct systems (each at E_FIXED and pH 7, no exchange)."""
 
-    def __init__(self, precision, n_steps, order="spatial", tuning=None, overlap=True,
+    def __init__(self, precision, n_steps, order=DEFAULT_ORDER, tuning=None, overlap=True,
                  systems=None, exchange=True, gref=None):
         import numpy as np
         import torch
@@ -132,10 +153,7 @@ class Workload:
         self.B = b.n_systems
         jb, wv = tuning if tuning else (None, None)
         self.plan = g.Plan(b.atom_offset, precision, j_blocks_per_item=jb, waves_per_group=wv)
-        if order == "spatial":
-            self.plan.set_order(g.spatial_order(b.atom_offset, b.x, b.y, b.z))
-        elif order == "blocks":
-            self.plan.set_order(g.block_order(b.atom_offset, b.x, b.y, b.z))
+        set_atom_order(self.plan, b, order)
         self.atoms = g.Atoms.from_batch(self.plan, b)
         dev = self.plan.device
         # with overlap, two charge buffers: a step reads one and writes the
@@ -218,17 +236,7 @@ class Workload:
 
 
 
-def autotune(precision, order):
-    """Work-shape sweep on the benchmark batch (untimed setup)."""
-    import paper_1803_09652_amd as g
-    from paper_1803_09652_amd import autotune as at
-    import synth
-    b = synth.make_batch(synth.eremd_batch())
-    o = g.spatial_order(b.atom_offset, b.x, b.y, b.z) if order == "spatial" else None
-    return at.tune(b, precision, order=o, use_cache=False)
-
-
-def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order="spatial", tuning=None,
+def run_gpu(precision, steps, warmup, use_graph, kernel_steps, order=DEFAULT_ORDER, tuning=None,
             overlap=True, systems=None, exchange=True):
     import torch
     n_total = steps + warmup + kernel_steps + 2
@@ -452,7 +460,7 @@ def time_plain_fp64(w, reps=3):
             "form": "radii + energy + forces + dE/dq + dE/drho, every ordered pair, FP64"}
 
 
-def time_single_launch(systems, reps=5, precision="fp32"):
+def time_single_launch(systems, reps=5, precision="fp32", order=DEFAULT_ORDER):
     """One full evaluation (radii, energy, forces, dE/dq, dE/drho) of the
     batch as gb_evaluate's single queued launch (all three pair passes, with
     per-block dependency counters), beside gb_radii + gb_energy_forces (one
@@ -463,7 +471,7 @@ def time_single_launch(systems, reps=5, precision="fp32"):
     import synth
     b = synth.make_batch(systems)
     plan = g.Plan(b.atom_offset, precision)
-    plan.set_order(g.spatial_order(b.atom_offset, b.x, b.y, b.z))
+    set_atom_order(plan, b, order)
     atoms = g.Atoms.from_batch(plan, b)
     pairs = pair_count(systems)
 
@@ -546,7 +554,7 @@ def roofline_of(pairs, kernel_ms, traffic=None, traffic_detail=None):
 
 
 def measure_workload(systems, exchange, steps, warmup, kernel_steps, use_graph=True,
-                     order="spatial", tuning=None, overlap=True, precision="fp32"):
+                     order=DEFAULT_ORDER, tuning=None, overlap=True, precision="fp32"):
     """The step of one workload (captured and replayed), the per-kernel means
     inside the step, the Monte Carlo Delta E kernels alone and the force
     passes alone."""
@@ -592,7 +600,7 @@ def time_md_loop(steps, warmup, n_rep=16, attempt_every=5, exchange_every=10):
     systems = synth.eremd_batch_md(n_rep)
     b = synth.make_batch(systems)
     plan = g.Plan(b.atom_offset, "fp32")
-    plan.set_order(g.spatial_order(b.atom_offset, b.x, b.y, b.z))
+    set_atom_order(plan, b, DEFAULT_ORDER)
     atoms = g.Atoms.from_batch(plan, b)
     dev, T, params = plan.device, 300.0, g.IGB5
     E_rung = np.array(synth.E_LADDER[:n_rep])
@@ -746,7 +754,7 @@ def time_autograd(reps=10):
     s_ = synth.globule_10000()[0]
     b = synth.make_batch([s_])
     plan = g.Plan(b.atom_offset, "fp32")
-    plan.set_order(g.spatial_order(b.atom_offset, b.x, b.y, b.z))
+    set_atom_order(plan, b, DEFAULT_ORDER)
     dev = plan.device
     t = lambda a: torch.as_tensor(np.asarray(a), dtype=torch.float32, device=dev)
     pos = t(np.stack([b.x, b.y, b.z], axis=1)).requires_grad_(True)
@@ -793,10 +801,11 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def traffic_from_counters(kernel, path=COUNTER_SUMMARY):
+def traffic_from_counters(kernel, path=COUNTER_SUMMARY, order=DEFAULT_ORDER):
     """HBM bytes per launch of `kernel` (FETCH_SIZE + WRITE_SIZE, each scaled by
     what the counter reads for a plain copy of known size), from the committed
-    rocprofv3 summary; None when absent or taken from other kernel sources."""
+    rocprofv3 summary; None when absent, taken from other kernel sources or
+    taken in another atom order than the one timed."""
     try:
         with open(path) as f:
             lines = [l for l in f if l.startswith("traffic-record: ")]
@@ -805,6 +814,8 @@ def traffic_from_counters(kernel, path=COUNTER_SUMMARY):
         return None, "no counter summary"
     if rec.get("source_sha256") != kernel_source_hash():
         return None, "kernel sources changed since the counters were taken"
+    if rec.get("atom_order") != order:
+        return None, f"counters taken in another atom order ({rec.get('atom_order')})"
     k = rec.get("kernels", {}).get(kernel)
     if not k:
         return None, f"no counters for {kernel}"
@@ -836,8 +847,10 @@ def main():
         print(json.dumps(r), flush=True)
         return
     if args.only == "single":
-        print(json.dumps({"uneven_batch": time_single_launch(synth.uneven_batch_64(), reps=3),
-                          "eremd_batch": time_single_launch(synth.eremd_batch(), reps=20)}),
+        print(json.dumps({"uneven_batch": time_single_launch(synth.uneven_batch_64(), reps=3,
+                                                            order=args.order),
+                          "eremd_batch": time_single_launch(synth.eremd_batch(), reps=20,
+                                                            order=args.order)}),
               flush=True)
         return
     if args.only == "eremd":
@@ -887,13 +900,14 @@ def main():
             out[k_] = head[k_]
     force_alone = head["kernel_ms_force_passes_alone"]
     dom_rf = roofline_of(pairs, force_alone)
-    traffic, detail = traffic_from_counters(dom_rf["kernel"]) if dom_rf else (None, None)
+    traffic, detail = (traffic_from_counters(dom_rf["kernel"], order=args.order) if dom_rf
+                       else (None, None))
     out["roofline"] = roofline_of(pairs, force_alone, traffic, detail)
     out["fp64_plain"] = time_plain_fp64(w, reps=1)
     out["fp32_over_fp64_plain"] = value / out["fp64_plain"]["value"]
     del w
     torch.cuda.empty_cache()
-    out["single_launch"] = time_single_launch(systems, reps=3)
+    out["single_launch"] = time_single_launch(systems, reps=3, order=args.order)
     if not args.no_fp64:
         r64, w64 = measure_workload(systems, False, args.fp64_steps, 2, 1, precision="fp64", **run)
         out["fp64"] = {k_: r64[k_] for k_ in ("ms_per_step", "pair_interactions_per_s",
@@ -907,7 +921,9 @@ def main():
         from paper_1803_09652_amd import autotune as at
         import paper_1803_09652_amd as g
         b = synth.make_batch(systems)
-        tn = at.tune(b, "fp32", order=g.spatial_order(b.atom_offset, b.x, b.y, b.z),
+        ords = {"spatial": g.spatial_order, "blocks": g.block_order}
+        tn = at.tune(b, "fp32", order=(ords[args.order](b.atom_offset, b.x, b.y, b.z)
+                                       if args.order in ords else None),
                      use_cache=False)
         rt, wt = measure_workload(systems, False, args.steps, args.warmup, 1,
                                   tuning=tn["best"], **run)
@@ -926,13 +942,14 @@ def main():
                           "protonation sites each, E ladder -0.40..-0.10 V, pH 7, T 300 K, "
                           "exchange attempt every step")
         er_dom = roofline_of(er["pairs_per_step"], er["kernel_ms_force_passes_alone"])
-        er_t, er_d = (traffic_from_counters(er_dom["kernel"], EREMD_COUNTER_SUMMARY) if er_dom
+        er_t, er_d = (traffic_from_counters(er_dom["kernel"], EREMD_COUNTER_SUMMARY, args.order)
+                      if er_dom
                       else (None, None))
         er["roofline"] = roofline_of(er["pairs_per_step"], er["kernel_ms_force_passes_alone"],
                                      er_t, er_d)
         er["fp64_plain"] = time_plain_fp64(we, reps=2)
         er["fp32_over_fp64_plain"] = er["pair_interactions_per_s"] / er["fp64_plain"]["value"]
-        er["single_launch"] = time_single_launch(synth.eremd_batch(), reps=20)
+        er["single_launch"] = time_single_launch(synth.eremd_batch(), reps=20, order=args.order)
         er["mc_sweep"] = time_sweep(we)
         er["salt"] = time_salt(we)
         del we

@@ -1,6 +1,6 @@
 """GPU parity at full size, in the launch configuration the benchmark times.
 
-The benchmark's step (``bench.Workload``: spatial (Morton) processing order,
+The benchmark's step (``bench.Workload``: its default processing order,
 the Monte Carlo branch on a second stream beside the force passes,
 double-buffered charges, two exchange-parity hipGraphs captured after two
 eager steps and then replayed) is run on
@@ -67,8 +67,8 @@ def _run_workload(prec, systems, exchange, n_steps, gref):
     warm-up), then the two parity graphs captured and replayed for steps
     2 .. n_steps - 1.  Returns the workload and one host snapshot per step."""
     import bench
-    w = bench.Workload(prec, n_steps, "spatial", None, True, systems=systems, exchange=exchange,
-                       gref=gref)
+    w = bench.Workload(prec, n_steps, bench.DEFAULT_ORDER, None, True, systems=systems,
+                       exchange=exchange, gref=gref)
 
     def snap(last):
         torch.cuda.synchronize()

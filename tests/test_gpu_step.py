@@ -11,7 +11,7 @@ pytestmark = pytest.mark.gpu
 
 def _run(overlap, use_graph, n_steps):
     import bench
-    w = bench.Workload("fp32", n_steps + 2, "spatial", None, overlap)
+    w = bench.Workload("fp32", n_steps + 2, bench.DEFAULT_ORDER, None, overlap)
     k = 0
     graphs = None
     if use_graph:
@@ -64,7 +64,7 @@ def test_two_step_graph_equals_serial_eager_steps():
     import bench
     n = 12
     ref = _run(overlap=False, use_graph=False, n_steps=n)
-    w = bench.Workload("fp32", n + 2, "spatial", None, True)
+    w = bench.Workload("fp32", n + 2, bench.DEFAULT_ORDER, None, True)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
