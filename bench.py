@@ -46,7 +46,7 @@ FLOPS_PER_PAIR["evaluate_pairs"] = FLOPS_PER_PAIR["radii_pairs"] + FLOPS_PER_PAI
 # Peaks (MI355X, 256 CUs at 2.4 GHz): FP32 vector 157.3 TFLOP/s, FP64 vector
 # 78.6 TFLOP/s.  The library's device code has packed-FP32 instructions
 # disabled, yet the FP32 value is the attainable one: the FP32 pair kernels
-# issue up to 1.68 wave-instructions per SIMD per four cycles (SQ_INSTS_VALU
+# issue up to 1.5 wave-instructions per SIMD per four cycles (SQ_INSTS_VALU
 # over GRBM_GUI_ACTIVE on the 64-system batch), more than a 16-lane issue
 # model (78.6 TFLOP/s) allows, so the wider published figure is the ceiling.
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
