@@ -201,13 +201,12 @@ class Workload:
         g, p, torch = self.g, self.params, self.torch
         cur, nxt = (self.atoms, self.atoms_b) if parity == 0 else (self.atoms_b, self.atoms)
         main = torch.cuda.current_stream()
-        R = g.radii(self.plan, cur, p)
         mc_stream = self.side if self.overlap else main
-        if mc_stream is not main:
-            mc_stream.wait_stream(main)
-        # the force passes are issued first, so that they continue on the
-        # radii's queue and the Monte Carlo branch is the one that forks off
-        ef = g.energy_forces(self.plan, cur, p)
+        # one full evaluation (inputs staged once); with overlap the Monte
+        # Carlo stream is released as soon as the radii are final, and the
+        # force passes continue on the radii's stream
+        ef = g.evaluate(self.plan, cur, p, fork=mc_stream if mc_stream is not main else None)
+        R = ef["R"]
         with torch.cuda.stream(mc_stream):
             # Monte Carlo branch: needs the radii and the current charges only
             torch.index_select(self.u_all, 0, self.k_dev, out=self.u.view(1, self.B, 6))

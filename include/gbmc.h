@@ -221,13 +221,32 @@ gbmc_status gb_energy_forces(gbmc_plan* plan, const gbmc_atoms* atoms,
 
 /* One full evaluation: gb_radii followed by gb_energy_forces on the same
  * workspace (Born radii from the geometry, section III.D; the electrostatic
- * energy and its derivatives of the MD steps, section III.A, Fig. 1).  Outputs
- * and their layout as in those two calls (born_R may be NULL; the energies and
- * gradients as in gb_energy_forces).  Leaves the per-atom state in workspace
- * for mc_state_dE, mc_step and mc_sweep. */
+ * energy and its derivatives of the MD steps, section III.A, Fig. 1), with the
+ * inputs staged once for all passes.  Outputs and their layout as in those
+ * two calls, bitwise the same (born_R may be NULL; the energies and gradients
+ * as in gb_energy_forces).  Leaves the per-atom state in workspace for
+ * mc_state_dE, mc_step and mc_sweep. */
 gbmc_status gb_evaluate(gbmc_plan* plan, const gbmc_atoms* atoms, const gbmc_gb_params* params,
                         void* workspace, void* born_R, double* e_coul, double* e_gb, void* force,
                         void* dEdq, void* dEdrho, hipStream_t stream);
+
+/* gb_evaluate that also hands the Born radii to a second stream as soon as
+ * they are final: the call records an event of the plan on `stream` after the
+ * radii pass and its finalize and makes `fork` wait on it (hipStreamWaitEvent),
+ * then issues the energy and force passes on `stream`.  Work the caller queues
+ * on `fork` after the call (mc_state_dE, mc_step: the Monte Carlo attempt of
+ * Fig. 1, which needs the radii and the charges only) then overlaps the energy
+ * and force passes; both streams may be under one hipGraph capture.  Outputs
+ * as in gb_evaluate, bitwise the same as gb_radii + gb_energy_forces.  Work on
+ * `fork` must not write the atoms' inputs or the workspace's pass
+ * accumulators before it rejoins `stream`.  GBMC_ERR_INVALID if fork equals
+ * stream; GBMC_ERR_HIP if the event record or wait fails.  Calls on one plan
+ * share its event: calls that may overlap (several streams, several threads)
+ * must be ordered by the caller. */
+gbmc_status gb_evaluate_fork(gbmc_plan* plan, const gbmc_atoms* atoms,
+                             const gbmc_gb_params* params, void* workspace, void* born_R,
+                             double* e_coul, double* e_gb, void* force, void* dEdq, void* dEdrho,
+                             hipStream_t stream, hipStream_t fork);
 
 /* gb_evaluate without a caller workspace, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses

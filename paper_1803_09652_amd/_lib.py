@@ -74,6 +74,8 @@ SIGNATURES = {
                                 _VP, _VP, _VP, _VP, _VP]),
     "gb_evaluate": (_I32, [_VP, C.POINTER(gbmc_atoms), C.POINTER(gbmc_gb_params), _VP, _VP, _VP,
                            _VP, _VP, _VP, _VP, _VP]),
+    "gb_evaluate_fork": (_I32, [_VP, C.POINTER(gbmc_atoms), C.POINTER(gbmc_gb_params), _VP, _VP,
+                                _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "gb_evaluate_static": (_I32, [_VP, C.POINTER(gbmc_atoms), C.POINTER(gbmc_gb_params), _VP,
                                   _VP, _VP, _VP, _VP, _VP, _VP]),
     "gb_plain_workspace_bytes": (C.c_size_t, [_I32]),

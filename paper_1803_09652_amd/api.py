@@ -282,16 +282,24 @@ def _eval_outputs(plan: Plan, force: bool, dEdq: bool, dEdrho: bool) -> dict:
 
 def evaluate(plan: Plan, atoms: Atoms, params: GBParams = IGB5, force: bool = True,
              dEdq: bool = True, dEdrho: bool = True,
-             workspace: Optional[torch.Tensor] = None) -> dict:
+             workspace: Optional[torch.Tensor] = None,
+             fork: Optional[torch.cuda.Stream] = None) -> dict:
     """One full evaluation (gb_evaluate): Born radii R, E_C and E_GB per
     system and the requested gradients; leaves the per-atom state in the
-    workspace (default: the plan's) for the Monte Carlo calls."""
+    workspace (default: the plan's) for the Monte Carlo calls.  With `fork`
+    (another stream; gb_evaluate_fork) that stream waits only until the radii
+    are final, so Monte Carlo work queued on it afterwards overlaps the energy
+    and force passes; rejoin it (wait_stream) before using the outputs there."""
     out = _eval_outputs(plan, force, dEdq, dEdrho)
     a, p = atoms.c(), params.c()
     ws = _workspace(plan, workspace)
-    L.check(L.load().gb_evaluate(plan.handle, C.byref(a), C.byref(p), _ptr(ws), _ptr(out["R"]),
-                                 _ptr(out["e_coul"]), _ptr(out["e_gb"]), _ptr(out["force"]),
-                                 _ptr(out["dEdq"]), _ptr(out["dEdrho"]), _stream(plan.device)))
+    args = (plan.handle, C.byref(a), C.byref(p), _ptr(ws), _ptr(out["R"]), _ptr(out["e_coul"]),
+            _ptr(out["e_gb"]), _ptr(out["force"]), _ptr(out["dEdq"]), _ptr(out["dEdrho"]),
+            _stream(plan.device))
+    if fork is None:
+        L.check(L.load().gb_evaluate(*args))
+    else:
+        L.check(L.load().gb_evaluate_fork(*args, C.c_void_p(fork.cuda_stream)))
     return out
 
 

@@ -78,6 +78,7 @@ struct gbmc_plan {
     int device = 0;
     void* scratch = nullptr;         // the library's static scratch on `device`
     hipError_t scratch_err = hipSuccess;
+    hipEvent_t fork_ev = nullptr;    // gb_evaluate_fork: recorded when the radii are final
     // timing hook: a ring of start/stop event pairs per timed kernel (bound to
     // the dispatches while enabled), the launches recorded since the last
     // read, and the pairs handed to the current call
@@ -553,6 +554,12 @@ gbmc_status gbmc_plan_create(gbmc_plan** out, int32_t n_systems, const int32_t* 
             e = hipMemcpy(d, h.data(), h.size(), hipMemcpyHostToDevice);
             if (e != hipSuccess) { (void)hipFree(d); delete p; return hip_fail(e, "hipMemcpy(plan tables)"); }
         }
+        e = hipEventCreateWithFlags(&p->fork_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (p->d_mem) (void)hipFree(p->d_mem);
+            delete p;
+            return hip_fail(e, "hipEventCreateWithFlags");
+        }
         *out = p;
         return GBMC_OK;
     } catch (const std::bad_alloc&) {
@@ -566,6 +573,7 @@ void gbmc_plan_destroy(gbmc_plan* p)
     if (p->d_mem) (void)hipFree(p->d_mem);
     for (hipEvent_t e : p->ev_pool)
         if (e) (void)hipEventDestroy(e);
+    if (p->fork_ev) (void)hipEventDestroy(p->fork_ev);
     delete p;
 }
 
@@ -798,40 +806,36 @@ static hipError_t run_queued(gbmc_plan* p, const gbmc_atoms* a, const GBConst& c
 
 extern "C" {
 
-gbmc_status gb_radii(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp, void* ws,
-                     void* born_R, hipStream_t s)
+// The descreening pass and OBC finalize; with q (the full evaluation) the
+// staging also packs the charges and clears the energy and chain passes'
+// accumulators, so that the energy call that follows stages nothing.
+static hipError_t radii_launch(gbmc_plan* p, const gbmc_atoms* a, const GBConst& c, void* ws,
+                               void* born_R, hipStream_t s, bool with_q)
 {
-    gbmc_status st = check_call(p, a, gp, ws, false);
-    if (st != GBMC_OK || p->n_atoms == 0) return st;
-    GBConst c = make_const(gp);
-    hipError_t e;
-    if (p->prec == GBMC_FP32_FIXED) {
-        e = launch_radii<float>(p->d_items[GBMC_PASS_RADII], p->n_items[GBMC_PASS_RADII],
+    hipEvent_t* ev = p->n_items[GBMC_PASS_RADII] > 0 ? events(p, {kKRadii}) : nullptr;
+    if (p->prec == GBMC_FP32_FIXED)
+        return launch_radii<float>(p->d_items[GBMC_PASS_RADII], p->n_items[GBMC_PASS_RADII],
+                                   p->tuning.waves_per_group[GBMC_PASS_RADII], p->n_atoms,
+                                   cut_plan(p), (const float*)a->x, (const float*)a->y,
+                                   (const float*)a->z, (const float*)a->rho,
+                                   (const float*)a->screen, c, carve<float>(p, ws),
+                                   (float*)born_R, s, ev,
+                                   with_q ? (const float*)a->q : nullptr);
+    return launch_radii<double>(p->d_items[GBMC_PASS_RADII], p->n_items[GBMC_PASS_RADII],
                                 p->tuning.waves_per_group[GBMC_PASS_RADII], p->n_atoms,
-                                cut_plan(p), (const float*)a->x,
-                                (const float*)a->y, (const float*)a->z, (const float*)a->rho,
-                                (const float*)a->screen, c, carve<float>(p, ws), (float*)born_R, s,
-                                p->n_items[GBMC_PASS_RADII] > 0 ? events(p, {kKRadii}) : nullptr);
-    } else {
-        e = launch_radii<double>(p->d_items[GBMC_PASS_RADII], p->n_items[GBMC_PASS_RADII],
-                                 p->tuning.waves_per_group[GBMC_PASS_RADII], p->n_atoms,
-                                 cut_plan(p), (const double*)a->x,
-                                 (const double*)a->y, (const double*)a->z, (const double*)a->rho,
-                                 (const double*)a->screen, c, carve<double>(p, ws), (double*)born_R, s,
-                                 p->n_items[GBMC_PASS_RADII] > 0 ? events(p, {kKRadii}) : nullptr);
-    }
-    return e == hipSuccess ? GBMC_OK : hip_fail(e, "gb_radii launch");
+                                cut_plan(p), (const double*)a->x, (const double*)a->y,
+                                (const double*)a->z, (const double*)a->rho,
+                                (const double*)a->screen, c, carve<double>(p, ws),
+                                (double*)born_R, s, ev, with_q ? (const double*)a->q : nullptr);
 }
 
-gbmc_status gb_energy_forces(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp, void* ws,
-                             double* e_coul, double* e_gb, void* force, void* dEdq, void* dEdrho,
-                             hipStream_t s)
+// The energy pass (and the chain pass when force or dEdrho is requested);
+// staged: the preceding radii launch of the same call staged the charges.
+static hipError_t energy_launch(gbmc_plan* p, const gbmc_atoms* a, const GBConst& c, void* ws,
+                                double* e_coul, double* e_gb, void* force, void* dEdq,
+                                void* dEdrho, hipStream_t s, bool staged)
 {
-    gbmc_status st = check_call(p, a, gp, ws, true);
-    if (st != GBMC_OK) return st;
-    GBConst c = make_const(gp);
     const bool chain = force || dEdrho;
-    hipError_t e;
     hipEvent_t* ev = nullptr;
     if (p->n_items[GBMC_PASS_ENERGY] > 0)
         ev = chain ? events(p, {kKEnergy, kKChain}) : events(p, {kKEnergy});
@@ -842,43 +846,93 @@ gbmc_status gb_energy_forces(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_pa
                        p->tuning.waves_per_group[GBMC_PASS_CHAIN],
                        p->tuning.j_blocks_per_item[GBMC_PASS_CHAIN] == 1};
     if (p->prec == GBMC_FP32_FIXED)
-        e = launch_energy_forces<float>(pe, pc, p->n_atoms, p->n_sys, cut_plan(p),
-                                        (const float*)a->x, (const float*)a->y, (const float*)a->z,
-                                        (const float*)a->q, (const float*)a->rho,
-                                        (const float*)a->screen, c, carve<float>(p, ws), e_coul,
-                                        e_gb, (float*)force, (float*)dEdq, (float*)dEdrho, s, ev);
-    else
-        e = launch_energy_forces<double>(pe, pc, p->n_atoms, p->n_sys, cut_plan(p),
-                                         (const double*)a->x, (const double*)a->y,
-                                         (const double*)a->z, (const double*)a->q,
-                                         (const double*)a->rho, (const double*)a->screen, c,
-                                         carve<double>(p, ws), e_coul, e_gb, (double*)force,
-                                         (double*)dEdq, (double*)dEdrho, s, ev);
+        return launch_energy_forces<float>(pe, pc, p->n_atoms, p->n_sys, cut_plan(p),
+                                           (const float*)a->x, (const float*)a->y,
+                                           (const float*)a->z, (const float*)a->q,
+                                           (const float*)a->rho, (const float*)a->screen, c,
+                                           carve<float>(p, ws), e_coul, e_gb, (float*)force,
+                                           (float*)dEdq, (float*)dEdrho, s, ev, staged);
+    return launch_energy_forces<double>(pe, pc, p->n_atoms, p->n_sys, cut_plan(p),
+                                        (const double*)a->x, (const double*)a->y,
+                                        (const double*)a->z, (const double*)a->q,
+                                        (const double*)a->rho, (const double*)a->screen, c,
+                                        carve<double>(p, ws), e_coul, e_gb, (double*)force,
+                                        (double*)dEdq, (double*)dEdrho, s, ev, staged);
+}
+
+gbmc_status gb_radii(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp, void* ws,
+                     void* born_R, hipStream_t s)
+{
+    gbmc_status st = check_call(p, a, gp, ws, false);
+    if (st != GBMC_OK || p->n_atoms == 0) return st;
+    hipError_t e = radii_launch(p, a, make_const(gp), ws, born_R, s, false);
+    return e == hipSuccess ? GBMC_OK : hip_fail(e, "gb_radii launch");
+}
+
+gbmc_status gb_energy_forces(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp, void* ws,
+                             double* e_coul, double* e_gb, void* force, void* dEdq, void* dEdrho,
+                             hipStream_t s)
+{
+    gbmc_status st = check_call(p, a, gp, ws, true);
+    if (st != GBMC_OK) return st;
+    hipError_t e = energy_launch(p, a, make_const(gp), ws, e_coul, e_gb, force, dEdq, dEdrho, s,
+                                 false);
     return e == hipSuccess ? GBMC_OK : hip_fail(e, "gb_energy_forces launch");
+}
+
+// A full evaluation: one staging of the inputs for all passes (radii, then
+// energies and gradients), or the queued launch in single-launch mode.  With
+// fork, that stream is made to wait on the plan's event, recorded on s once
+// the Born radii (and the per-atom state of the Monte Carlo calls) are final.
+static gbmc_status evaluate_impl(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp,
+                                 void* ws, void* born_R, double* e_coul, double* e_gb,
+                                 void* force, void* dEdq, void* dEdrho, hipStream_t s,
+                                 bool use_fork, hipStream_t fork)
+{
+    gbmc_status st = check_call(p, a, gp, ws, true);
+    if (st != GBMC_OK) return st;
+    auto mark = [&]() -> gbmc_status {
+        if (!use_fork) return GBMC_OK;
+        hipError_t e = hipEventRecord(p->fork_ev, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(fork, p->fork_ev, 0);
+        return e == hipSuccess ? GBMC_OK : hip_fail(e, "gb_evaluate_fork: fork event");
+    };
+    if (p->n_atoms == 0) return mark();
+    GBConst c = make_const(gp);
+    // in single-launch mode the three all-pairs passes of a full evaluation
+    // (forces or dE/drho requested, no cutoffs) run as one queued launch
+    const bool chain = force || dEdrho;
+    if (p->single_launch && !uses_cutoffs(c) && chain) {
+        hipError_t e = p->prec == GBMC_FP32_FIXED
+                           ? run_queued<float>(p, a, c, ws, born_R, e_coul, e_gb, force, dEdq,
+                                               dEdrho, s, kKEval)
+                           : run_queued<double>(p, a, c, ws, born_R, e_coul, e_gb, force, dEdq,
+                                                dEdrho, s, kKEval);
+        if (e != hipSuccess) return hip_fail(e, "gb_evaluate launch");
+        return mark();
+    }
+    hipError_t e = radii_launch(p, a, c, ws, born_R, s, true);
+    if (e != hipSuccess) return hip_fail(e, "gb_evaluate launch");
+    st = mark();
+    if (st != GBMC_OK) return st;
+    e = energy_launch(p, a, c, ws, e_coul, e_gb, force, dEdq, dEdrho, s, true);
+    return e == hipSuccess ? GBMC_OK : hip_fail(e, "gb_evaluate launch");
 }
 
 gbmc_status gb_evaluate(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp, void* ws,
                         void* born_R, double* e_coul, double* e_gb, void* force, void* dEdq,
                         void* dEdrho, hipStream_t s)
 {
-    gbmc_status st = check_call(p, a, gp, ws, true);
-    if (st != GBMC_OK || p->n_atoms == 0) return st;
-    GBConst c = make_const(gp);
-    // in single-launch mode the three all-pairs passes of a full evaluation
-    // (forces or dE/drho requested) run as one queued launch; otherwise, and
-    // with cutoffs, as the separate launches of gb_radii and gb_energy_forces
-    const bool chain = force || dEdrho;
-    if (!p->single_launch || uses_cutoffs(c) || !chain) {
-        st = gb_radii(p, a, gp, ws, born_R, s);
-        if (st != GBMC_OK) return st;
-        return gb_energy_forces(p, a, gp, ws, e_coul, e_gb, force, dEdq, dEdrho, s);
-    }
-    hipError_t e = p->prec == GBMC_FP32_FIXED
-                       ? run_queued<float>(p, a, c, ws, born_R, e_coul, e_gb, force, dEdq, dEdrho,
-                                           s, kKEval)
-                       : run_queued<double>(p, a, c, ws, born_R, e_coul, e_gb, force, dEdq,
-                                            dEdrho, s, kKEval);
-    return e == hipSuccess ? GBMC_OK : hip_fail(e, "gb_evaluate launch");
+    return evaluate_impl(p, a, gp, ws, born_R, e_coul, e_gb, force, dEdq, dEdrho, s, false,
+                         nullptr);
+}
+
+gbmc_status gb_evaluate_fork(gbmc_plan* p, const gbmc_atoms* a, const gbmc_gb_params* gp,
+                             void* ws, void* born_R, double* e_coul, double* e_gb, void* force,
+                             void* dEdq, void* dEdrho, hipStream_t s, hipStream_t fork)
+{
+    if (p && fork == s) return fail(GBMC_ERR_INVALID, "gb_evaluate_fork: fork is the call's stream");
+    return evaluate_impl(p, a, gp, ws, born_R, e_coul, e_gb, force, dEdq, dEdrho, s, true, fork);
 }
 
 gbmc_status gbmc_plan_set_single_launch(gbmc_plan* p, int32_t enable, int32_t wait_polls)

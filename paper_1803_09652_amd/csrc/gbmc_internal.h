@@ -197,7 +197,7 @@ hipError_t launch_radii(const WorkItem* items, int n_items, int waves_per_group,
                         const CutPlan& cp,
                         const T* x, const T* y, const T* z, const T* rho, const T* screen,
                         const GBConst& c, const Work<T>& w, T* born_R, hipStream_t s,
-                        hipEvent_t* ev);
+                        hipEvent_t* ev, const T* q = nullptr);
 struct PassShape {
     const WorkItem* items;
     int n_items;
@@ -211,7 +211,7 @@ hipError_t launch_energy_forces(const PassShape& energy, const PassShape& chain,
                                 const T* x, const T* y, const T* z, const T* q, const T* rho,
                                 const T* screen, const GBConst& c, const Work<T>& w,
                                 double* e_coul, double* e_gb, T* force, T* dEdq, T* dEdrho,
-                                hipStream_t s, hipEvent_t* ev);
+                                hipStream_t s, hipEvent_t* ev, bool staged = false);
 // Ints of the workspace taken by the queued launch's ticket counter and error
 // word (on separate 128-byte lines).
 constexpr int kQueueWords = 64;

@@ -2778,15 +2778,19 @@ hipError_t launch_radii(const WorkItem* items, int n_items, int wpg, int n_atoms
                         const CutPlan& cp,
                         const T* x, const T* y, const T* z, const T* rho, const T* screen,
                         const GBConst& c, const Work<T>& w, T* born_R, hipStream_t s,
-                        hipEvent_t* ev)
+                        hipEvent_t* ev, const T* q)
 {
     if (n_atoms == 0) return hipSuccess;
-    // staging also clears I_fx and the overflow flags: every evaluation starts at zero
+    // staging also clears I_fx and the overflow flags: every evaluation starts
+    // at zero.  With charges (q not NULL: the full evaluation, whose energy
+    // pass then stages nothing) it also packs them and clears the accumulators
+    // of the energy and chain passes ([8][N] from F_fx on).
     StageClear zc{};
     zc.acc0 = w.I_fx; zc.n_acc0 = 1;
     zc.f0 = w.ovf; zc.n_f0 = 2;
+    if (q) { zc.acc1 = w.F_fx; zc.n_acc1 = 8; }
     hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(cp.n_blocks, 4)), dim3(256), 0, s, cp.blocks,
-                       cp.n_blocks, n_atoms, w.perm, x, y, z, (const T*)nullptr, rho, screen,
+                       cp.n_blocks, n_atoms, w.perm, x, y, z, q, rho, screen,
                        (T)c.offset, w.P, w.Gx, w.box, zc);
     if (c.rgbmax > 0.0 || c.cutoff > 0.0) launch_cut_lists<T>(cp, c, w, s);
     if (n_items > 0) {
@@ -2812,13 +2816,14 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
                                 const T* x, const T* y, const T* z, const T* q, const T* rho,
                                 const T* screen, const GBConst& c, const Work<T>& w,
                                 double* e_coul, double* e_gb, T* force, T* dEdq, T* dEdrho,
-                                hipStream_t s, hipEvent_t* ev)
+                                hipStream_t s, hipEvent_t* ev, bool staged)
 {
     const bool grad = force || dEdq || dEdrho;
     const bool chain = force || dEdrho;
     // positions and charges as given to this call, in processing order; F, G,
-    // phi, drho and the two energy shares ([8][N] from F_fx on) cleared alongside
-    if (n_atoms > 0) {
+    // phi, drho and the two energy shares ([8][N] from F_fx on) cleared
+    // alongside (staged: the full evaluation's radii staging did both)
+    if (n_atoms > 0 && !staged) {
         StageClear zc{};
         zc.acc0 = w.F_fx; zc.n_acc0 = 8;
         hipLaunchKernelGGL(k_stage<T>, dim3(blocks_for(cp.n_blocks, 4)), dim3(256), 0, s,
@@ -3033,13 +3038,14 @@ hipError_t launch_remd_exchange(int M, const double* E_rung, const int32_t* Ne, 
     template hipError_t launch_radii<T>(const WorkItem*, int, int, int, const CutPlan&,         \
                                         const T*,                                                \
                                         const T*, const T*, const T*, const T*, const GBConst&,  \
-                                        const Work<T>&, T*, hipStream_t, hipEvent_t*);           \
+                                        const Work<T>&, T*, hipStream_t, hipEvent_t*,            \
+                                        const T*);                                               \
     template hipError_t launch_energy_forces<T>(const PassShape&, const PassShape&, int, int,      \
                                                 const CutPlan&, const T*,                          \
                                                 const T*, const T*, const T*, const T*,          \
                                                 const T*, const GBConst&, const Work<T>&,        \
                                                 double*, double*, T*, T*, T*, hipStream_t,       \
-                                                hipEvent_t*);                                    \
+                                                hipEvent_t*, bool);                              \
     template hipError_t launch_queued<T>(const QueueShape&, int, int, const T*, const T*,       \
                                          const T*, const T*, const T*, const T*, const GBConst&, \
                                          const Work<T>&, T*, double*, double*, T*, T*, T*,       \
