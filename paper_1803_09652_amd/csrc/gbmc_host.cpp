@@ -87,8 +87,8 @@ struct gbmc_plan {
     int64_t n_rec[kNumKernels] = {};
     hipEvent_t cur[2 * kNumKernels] = {};
     // workspace layout (byte offsets)
-    size_t off_I, off_F, off_G, off_phi, off_drho, off_EA, off_I64, off_R64, off_T64, off_dR64,
-        off_G64, off_B64, off_Rt, off_at, off_Brt, off_ovf, off_q, off_P, off_Gx, off_A64, off_rows, off_bnd,
+    size_t off_I, off_F, off_G, off_phi, off_drho, off_EA, off_I64, off_R64, off_T64, off_dR64, off_dRp,
+        off_Rt, off_at, off_ovf, off_q, off_P, off_Gx, off_A64, off_rows, off_bnd,
         off_smax, off_box, off_cit0, off_cit1, off_ccount, ws_bytes;
     int32_t cut_cap = 0;             // capacity of each compacted cutoff work list
 };
@@ -233,11 +233,9 @@ static Work<T> carve(const gbmc_plan* p, void* ws)
     w.rows = reinterpret_cast<Row64*>(b + p->off_rows);
     w.T64 = reinterpret_cast<double*>(b + p->off_T64);
     w.dRdPsi64 = reinterpret_cast<double*>(b + p->off_dR64);
-    w.G64 = reinterpret_cast<double*>(b + p->off_G64);
-    w.B64 = reinterpret_cast<double*>(b + p->off_B64);
+    w.dRdPsi_p = reinterpret_cast<double*>(b + p->off_dRp);
     w.R_t = reinterpret_cast<T*>(b + p->off_Rt);
     w.a_t = reinterpret_cast<T*>(b + p->off_at);
-    w.Brt_t = reinterpret_cast<T*>(b + p->off_Brt);
     w.ovf = reinterpret_cast<int*>(b + p->off_ovf);
     w.qhead = reinterpret_cast<int*>(b + p->off_q);
     w.qcnt = reinterpret_cast<int*>(b + p->off_q + 4 * (size_t)kQueueWords);
@@ -272,11 +270,9 @@ static void layout(gbmc_plan* p)
     p->off_A64 = seg(8 * N);
     p->off_T64 = seg(8 * N);
     p->off_dR64 = seg(8 * N);
-    p->off_G64 = seg(8 * N);
-    p->off_B64 = seg(8 * N);
+    p->off_dRp = seg(8 * N);
     p->off_Rt = seg(ts * N);
     p->off_at = seg(ts * N);
-    p->off_Brt = seg(ts * N);
     p->off_P = seg(4 * ts * N);
     p->off_Gx = seg(4 * ts * N);
     p->off_rows = seg(sizeof(Row64) * N);

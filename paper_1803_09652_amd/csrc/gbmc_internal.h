@@ -99,11 +99,10 @@ struct Work {
     Row64* rows;                  // [N] FP64 records for the Monte Carlo kernels
     double* T64;                  // [N] tanh(theta)
     double* dRdPsi64;             // [N]
-    double* G64;                  // [N] dE/dR
-    double* B64;                  // [N] dE/dR * dR/dPsi
+    double* dRdPsi_p;             // [N] internal: dR/dPsi in processing order (the chain
+                                  //  pass forms B rt from it and G_fx)
     T* R_t;                       // [N] internal: Born radius in the pair precision
     T* a_t;                       // [N] internal: sqrt(log2(e)/4) / R
-    T* Brt_t;                     // [N] internal: B * (rho - offset)
     int* ovf;                     // [2]: fixed-point overflow; a wait of a queued
                                   //  launch gave up (both since the last radii call)
     int* qhead;                   // [kQueueWords]: ticket counter ([0]) and error word ([32])

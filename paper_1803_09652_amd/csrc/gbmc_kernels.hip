@@ -1301,8 +1301,10 @@ __device__ __forceinline__ void radii_final_atom(int k, const T* __restrict__ RH
     w.R64[g] = R;
     w.A64[g] = 0.5 / R;
     w.T64[g] = t;
-    st_dev(w.dRdPsi64 + g,
-           R * R * (1.0 - t * t) * (c.alpha - 2.0 * c.beta * psi + 3.0 * c.gamma * psi * psi) / rho);
+    const double dRdPsi =
+        R * R * (1.0 - t * t) * (c.alpha - 2.0 * c.beta * psi + 3.0 * c.gamma * psi * psi) / rho;
+    st_dev(w.dRdPsi64 + g, dRdPsi);
+    st_dev(w.dRdPsi_p + k, dRdPsi);
     st_dev(w.R_t + k, (T)R);
     st_dev(w.a_t + k, (T)(kAScale / R));
     // FP64 record of the atom for the Monte Carlo kernels (caller order)
@@ -1605,19 +1607,6 @@ __global__ __launch_bounds__(kTile * W) void k_energy_pairs(
     }
 }
 
-// Per atom after pass 2: G = dE/dR and the chain weight B = G dR/dPsi (FP64,
-// caller order), and B (rho - offset) in the pair precision for the chain pass.
-template <typename T>
-__device__ __forceinline__ void energy_final_atom(int k, const Work<T>& w)
-{
-    const int g = w.perm[k];
-    double G = (double)(long long)ld_dev(w.G_fx + k) * (1.0 / kScaleF);
-    double B = G * ld_dev(w.dRdPsi64 + g);
-    w.G64[g] = G;
-    w.B64[g] = B;
-    st_dev(w.Brt_t + k, (T)(B * (double)w.Gx[k].x));
-}
-
 // After pass 2, one launch: blocks [0, n_sum) sum the atoms' fixed-point
 // energy shares of one system each (E_C, E_GB; integer sums, so the result
 // does not depend on the order), the following blocks finalize one atom per
@@ -1655,7 +1644,6 @@ __global__ __launch_bounds__(256) void k_energy_finalize(int n_atoms, int n_sum,
     }
     const int k = ((int)blockIdx.x - n_sum) * 256 + t;
     if (!grad || k >= n_atoms) return;
-    energy_final_atom<T>(k, w);
     if (dEdq) dEdq[w.perm[k]] = (T)((double)(long long)w.phi_fx[k] * (1.0 / kScaleF));
 }
 
@@ -1663,12 +1651,24 @@ __global__ __launch_bounds__(256) void k_energy_finalize(int n_atoms, int n_sum,
 // Born-radius chain: force through Psi and the pair part of dE/drho.
 
 // One work item of R (1 or 2) i blocks; see radii_item.
+// B (rho - offset) of one atom in the pair precision, formed from its G sum
+// (fixed point, final once the energy pass is) and dR/dPsi exactly as the
+// energy finalize forms it (B = G dR/dPsi in FP64), so no finalize launch is
+// needed between the energy and chain passes.
+template <typename T>
+__device__ __forceinline__ T brt_from(unsigned long long gfx, double dRdPsi, T rt)
+{
+    const double G = (double)(long long)gfx * (1.0 / kScaleF);
+    const double B = G * dRdPsi;
+    return (T)(B * (double)rt);
+}
+
 template <typename T, int R, bool CUT, bool ONE>
 __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* sj, Q4<T>* sb,
                                            unsigned long long* sdef, int* slist,
                                            const Q4<T>* __restrict__ P,
                                            const Q4<T>* __restrict__ Gx,
-                                           const T* __restrict__ Brt, const Work<T>& wk, T cR,
+                                           const Work<T>& wk, T cR,
                                            unsigned long long tmask)
 {
     // DEFER (all pairs): the walk evaluates the polynomial form only and
@@ -1694,7 +1694,7 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
             rti[r] = gx.x;
             Si[r] = gx.y;
             si[r] = gx.z;
-            Bi[r] = ld_dev(Brt + g);
+            Bi[r] = brt_from<T>(ld_dev(wk.G_fx + g), ld_dev(wk.dRdPsi_p + g), gx.x);
         } else {
             dummy_pos(i, xi[r], yi[r], zi[r]);
             rti[r] = T(1); si[r] = T(0); Si[r] = T(0); Bi[r] = T(0);
@@ -1702,17 +1702,21 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
     }
     // raw loads of a j block; stand-ins for lanes past the end are applied
     // when the block is written to LDS
-    auto fetch = [&](int J, Q4<T>& pj, Q4<T>& gj, T& brj) {
+    // raw loads of a j block (G sum and dR/dPsi for its B rt, formed when the
+    // block is written to LDS so that the loads stay in flight)
+    auto fetch = [&](int J, Q4<T>& pj, Q4<T>& gj, unsigned long long& gfj, double& drj) {
         const int g = w.base + clamp_atom(J * kTile + lane, w.n);
         pj = P[g];
         gj = Gx[g];
-        brj = ld_dev(Brt + g);
+        gfj = ld_dev(wk.G_fx + g);
+        drj = ld_dev(wk.dRdPsi_p + g);
     };
-    auto tail = [&](int J, Q4<T>& pj, Q4<T>& bj, const Q4<T>& gj, T brj) {
+    auto tail = [&](int J, Q4<T>& pj, Q4<T>& bj, const Q4<T>& gj, unsigned long long gfj,
+                    double drj) {
         const int j = J * kTile + lane;
         pj.w = gj.x;
         bj.x = gj.y;
-        bj.y = brj;
+        bj.y = brt_from<T>(gfj, drj, gj.x);
         bj.z = gj.z;
         bj.w = T(0);
         if (j >= w.n) {
@@ -1726,8 +1730,9 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
     for (int r = 0; r < R; ++r) fix[r][0] = fix[r][1] = fix[r][2] = fix[r][3] = 0;
     bool bad = false;
     Q4<T> pj, gj, bj;
-    T brj;
-    if constexpr (!CUT) fetch(w.J0, pj, gj, brj);
+    unsigned long long gfj;
+    double drj;
+    if constexpr (!CUT) fetch(w.J0, pj, gj, gfj, drj);
     // With a cutoff only the tiles of the item's mask are visited.
     int Jnext = w.J1;
     // one tile, then the loads of the next tile; the first tile is peeled so
@@ -1740,12 +1745,12 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
         if constexpr (CUT) Jnext = Jn = next_tile(tmask, w.J0, w.J1, J + 1);
         const int j = J * kTile + lane;
         const bool vj = j < w.n;
-        tail(J, pj, bj, gj, brj);
+        tail(J, pj, bj, gj, gfj, drj);
         wave_sync();
         sj[lane] = pj; sj[lane + kTile] = pj;
         sb[lane] = bj; sb[lane + kTile] = bj;
         wave_sync();
-        fetch(Jn < w.J1 ? Jn : J, pj, gj, brj);
+        fetch(Jn < w.J1 ? Jn : J, pj, gj, gfj, drj);
         T fxi[R], fyi[R], fzi[R], dri[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) fxi[r] = fyi[r] = fzi[r] = dri[r] = T(0);
@@ -1865,7 +1870,8 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
                         const int gi = w.base + (w.I + ((e >> 7) & 1)) * kTile + il;
                         const Q4<T> pi = P[gi];
                         const Q4<T> gxi = Gx[gi];       // rt, S, screen
-                        const T bi_ = ld_dev(Brt + gi);
+                        const T bi_ = brt_from<T>(ld_dev(wk.G_fx + gi),
+                                                  ld_dev(wk.dRdPsi_p + gi), gxi.x);
                         const JD d = load(il + k);
                         const Q4<T>& p = d.p;
                         const Q4<T>& b = d.b;
@@ -1933,7 +1939,7 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
     if constexpr (CUT) {
         int J = next_tile(tmask, w.J0, w.J1, w.J0);
         if (J >= w.J1) return;                  // nothing within the cutoff: no sums to add
-        fetch(J, pj, gj, brj);
+        fetch(J, pj, gj, gfj, drj);
         for (; J < w.J1; J = Jnext) tile(J, std::false_type{});
     } else {
         tile(w.J0, std::true_type{});
@@ -1954,7 +1960,7 @@ __device__ __forceinline__ void chain_item(const WorkItem& w, int lane, Q4<T>* s
 template <typename T, int W, bool CUT, bool ONE>
 __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
     const WorkItem* __restrict__ items, int n_items, const Q4<T>* __restrict__ P,
-    const Q4<T>* __restrict__ Gx, const T* __restrict__ Brt, Work<T> wk, T cR)
+    const Q4<T>* __restrict__ Gx, Work<T> wk, T cR)
 {
     __shared__ Q4<T> sj_w[W][2 * kTile];     // x, y, z, rt
     __shared__ Q4<T> sb_w[W][2 * kTile];     // S, B rt, screen, -
@@ -1971,7 +1977,7 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
             unsigned long long m;
             const WorkItem w = cut_work_item(wk.citems[0][it], m);
             chain_item<T, 1, true, false>(w, lane, sj_w[wave], sb_w[wave], sd_w[wave], sl_w[wave], P,
-                                          Gx, Brt, wk, cR, m);
+                                          Gx, wk, cR, m);
         }
     } else {
         // wave-uniform (scalar registers), like everything derived from the item
@@ -1981,38 +1987,14 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
         // two-row items exist in the chain and energy passes of FP32 plans only
         if (sizeof(T) == 4 && w.rows == 2)
             chain_item<T, sizeof(T) == 4 ? 2 : 1, false, ONE>(w, lane, sj_w[wave], sb_w[wave],
-                                                            sd_w[wave], sl_w[wave], P, Gx, Brt, wk,
+                                                            sd_w[wave], sl_w[wave], P, Gx, wk,
                                                             cR, 0ull);
         else
             chain_item<T, 1, false, ONE>(w, lane, sj_w[wave], sb_w[wave], sd_w[wave], sl_w[wave], P,
-                                         Gx, Brt, wk, cR, 0ull);
+                                         Gx, wk, cR, 0ull);
     }
 }
 
-// Per atom after pass 3: forces and dE/drho.
-//   dE/drho_k = G_k R_k^2 (1/rt_k^2 - T_k/rho_k^2) + B_k I_k + (pair part)
-template <typename T>
-__global__ void k_grad_finalize(int n_atoms, const T* __restrict__ RHO, double offset, Work<T> w,
-                                T* __restrict__ force, T* __restrict__ dEdrho)
-{
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_atoms) return;
-    const int g = w.perm[k];
-    if (force) {
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-            force[3 * (size_t)g + a] = (T)((double)(long long)w.F_fx[a * w.n_atoms + k] * (1.0 / kScaleF));
-    }
-    if (dEdrho) {
-        double rho = (double)RHO[g];
-        double rt = rho - offset;
-        double R = w.R64[g];
-        double v = w.G64[g] * R * R * (1.0 / (rt * rt) - w.T64[g] / (rho * rho))
-                 + w.B64[g] * w.I64[g]
-                 + (double)(long long)w.drho_fx[k] * (1.0 / kScaleF);
-        dEdrho[g] = (T)v;
-    }
-}
 
 // ===================================================== one queued launch
 // The pair passes of one call (descreening, energy / explicit forces, Born
@@ -2178,29 +2160,27 @@ __global__ __launch_bounds__(kTile * W) void k_pairs_queue(
         else
             energy_item<T, GRAD, 1, SALT, false, ONE>(w, lane, sj, sR, sA, wk.P, wk.R_t, wk.a_t,
                                                       kC, kT, sk, ck, wk, 0ull);
-        // the energy pass finalizes its blocks when the chain pass follows
-        if (P1 == 2)
-            pq_complete(q, 1, w, lane, [&](int L) {
-                const int i = L * kTile + lane;
-                if (i < w.n) energy_final_atom<T>(w.base + i, wk);
-            });
+        // when the chain pass follows, the energy pass marks its blocks ready
+        // (the chain pass forms B from their final G sums)
+        if (P1 == 2) pq_complete(q, 1, w, lane, [&](int) {});
     } else if (P1 == 2 && p == 2) {
         Q4<T>* sb = sj + 2 * kTile;
         unsigned long long* sdef = reinterpret_cast<unsigned long long*>(sb + 2 * kTile);
         int* slist = reinterpret_cast<int*>(sdef + 4 * kTile);
         if (sizeof(T) == 4 && w.rows == 2)
             chain_item<T, sizeof(T) == 4 ? 2 : 1, false, ONE>(w, lane, sj, sb, sdef, slist, wk.P,
-                                                            wk.Gx, wk.Brt_t, wk, T(0), 0ull);
+                                                            wk.Gx, wk, T(0), 0ull);
         else
-            chain_item<T, 1, false, ONE>(w, lane, sj, sb, sdef, slist, wk.P, wk.Gx, wk.Brt_t, wk,
+            chain_item<T, 1, false, ONE>(w, lane, sj, sb, sdef, slist, wk.P, wk.Gx, wk,
                                          T(0), 0ull);
     }
 }
 
-// After a queued launch that ran the energy pass: blocks [0, n_sum) sum
-// the atoms' fixed-point energy shares of one system each (integer sums,
-// order independent); the following blocks write one atom's outputs per
-// thread: dE/dq, the forces and dE/drho (caller order).
+// After the chain pass (three launches, or the queued launch): blocks
+// [0, n_sum) sum the atoms' fixed-point energy shares of one system each
+// (integer sums, order independent); the following blocks write one atom's
+// outputs per thread: dE/dq, the forces and dE/drho (caller order).
+//   dE/drho_k = G_k R_k^2 (1/rt_k^2 - T_k/rho_k^2) + B_k I_k + (pair part)
 template <typename T>
 __global__ __launch_bounds__(256) void k_post(int n_atoms, int n_sum, Work<T> w,
                                               double* __restrict__ e_coul,
@@ -2245,8 +2225,11 @@ __global__ __launch_bounds__(256) void k_post(int n_atoms, int n_sum, Work<T> w,
         double rho = (double)RHO[g];
         double rt = rho - offset;
         double R = w.R64[g];
-        double v = w.G64[g] * R * R * (1.0 / (rt * rt) - w.T64[g] / (rho * rho))
-                 + w.B64[g] * w.I64[g]
+        // G = dE/dR from its fixed-point sum and the chain weight B = G dR/dPsi
+        const double G = (double)(long long)w.G_fx[k] * (1.0 / kScaleF);
+        const double B = G * w.dRdPsi64[g];
+        double v = G * R * R * (1.0 / (rt * rt) - w.T64[g] / (rho * rho))
+                 + B * w.I64[g]
                  + (double)(long long)w.drho_fx[k] * (1.0 / kScaleF);
         dEdrho[g] = (T)v;
     }
@@ -2870,7 +2853,10 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
     }
     const int n_sum = (e_coul || e_gb) ? n_sys : 0;
     const int n_fin = grad ? blocks_for(n_atoms, 256) : 0;
-    if (n_sum + n_fin > 0)
+    // without the chain pass the energies and dE/dq are written here; with it
+    // the chain pass forms B from the G sums itself and k_post writes every
+    // output at the end (one launch fewer between the pair passes)
+    if (!chain && n_sum + n_fin > 0)
         hipLaunchKernelGGL(k_energy_finalize<T>, dim3(n_sum + n_fin), dim3(256), 0, s, n_atoms, n_sum,
                            w, e_coul, e_gb, dEdq, grad);
     if (chain && pc.n_items > 0) {
@@ -2878,22 +2864,22 @@ hipError_t launch_energy_forces(const PassShape& pe, const PassShape& pc, int n_
             GBMC_DISPATCH_W(pc.waves_per_group,
                             GBMC_LAUNCH_TIMED(ev, kKChain, (k_chain_pairs<T, W, true, false>),
                                               dim3(cut_groups(w.cut_cap, W)), dim3(kTile * W), s,
-                                              pc.items, pc.n_items, w.P, w.Gx, w.Brt_t, w,
+                                              pc.items, pc.n_items, w.P, w.Gx, w,
                                               (T)c.rgbmax))
         else if (pc.one_tile)
             GBMC_DISPATCH_W(pc.waves_per_group,
                             GBMC_LAUNCH_TIMED(ev, kKChain, (k_chain_pairs<T, W, false, true>),
                                               dim3(blocks_for(pc.n_items, W)), dim3(kTile * W), s,
-                                              pc.items, pc.n_items, w.P, w.Gx, w.Brt_t, w, (T)0))
+                                              pc.items, pc.n_items, w.P, w.Gx, w, (T)0))
         else
             GBMC_DISPATCH_W(pc.waves_per_group,
                             GBMC_LAUNCH_TIMED(ev, kKChain, (k_chain_pairs<T, W, false, false>),
                                               dim3(blocks_for(pc.n_items, W)), dim3(kTile * W), s,
-                                              pc.items, pc.n_items, w.P, w.Gx, w.Brt_t, w, (T)0))
+                                              pc.items, pc.n_items, w.P, w.Gx, w, (T)0))
     }
-    if (chain && n_atoms > 0)
-        hipLaunchKernelGGL(k_grad_finalize<T>, dim3(blocks_for(n_atoms, 256)), dim3(256), 0, s,
-                           n_atoms, rho, c.offset, w, force, dEdrho);
+    if (chain && n_sum + n_fin > 0)
+        hipLaunchKernelGGL(k_post<T>, dim3(n_sum + n_fin), dim3(256), 0, s, n_atoms, n_sum, w,
+                           e_coul, e_gb, dEdq, force, dEdrho, rho, c.offset);
     return hipGetLastError();
 }
 
