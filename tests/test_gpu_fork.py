@@ -41,6 +41,15 @@ def test_evaluate_and_fork_equal_separate_calls(prec):
     for k in KEYS:
         assert np.array_equal(one[k], ref[k]), k
         assert np.array_equal(fk[k], ref[k]), k
+    # in single-launch mode the fork follows the one queued launch
+    plan.set_single_launch(True)
+    sq = g.evaluate(plan, atoms, p_gpu, fork=side)
+    torch.cuda.current_stream().wait_stream(side)
+    assert not g.check_overflow(plan)
+    sq = _host(sq)
+    plan.set_single_launch(False)
+    for k in KEYS:
+        assert np.array_equal(sq[k], ref[k]), k
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
