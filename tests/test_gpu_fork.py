@@ -4,6 +4,8 @@ those of gb_radii + gb_energy_forces bitwise, and Monte Carlo work queued on
 the fork stream after the call (it needs only the radii) gives the same
 Delta E as the same work queued after the whole evaluation on one stream,
 eagerly and replayed from a captured hipGraph."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -101,6 +103,24 @@ def test_monte_carlo_on_the_fork_stream(prec):
                               out["force"].double().cpu().numpy())
         g.radii(plan, atoms, p_gpu)          # eager work between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_evaluate_with_cutoffs_and_salt_equals_separate_calls(prec):
+    # the cutoff lists are rebuilt by the energy call from the positions the
+    # single staging packed; salt takes the other energy kernels
+    p_gpu, _ = params_pair()
+    p_gpu = dataclasses.replace(p_gpu, rgbmax=10.0, cutoff=12.0, kappa=0.1)
+    g, batch, plan, atoms = build(_systems() + synth.globule_2500(), prec)
+    plan.set_order(g.block_order(batch.atom_offset, batch.x, batch.y, batch.z))
+    R = g.radii(plan, atoms, p_gpu)
+    ref = _host(dict(g.energy_forces(plan, atoms, p_gpu), R=R))
+    side = torch.cuda.Stream()
+    fk = g.evaluate(plan, atoms, p_gpu, fork=side)
+    torch.cuda.current_stream().wait_stream(side)
+    fk = _host(fk)
+    for k in KEYS:
+        assert np.array_equal(fk[k], ref[k]), k
 
 
 def test_fork_on_the_call_stream_is_rejected():
