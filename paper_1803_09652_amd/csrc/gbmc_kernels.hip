@@ -127,7 +127,7 @@ __device__ __forceinline__ void fx_add(unsigned long long* p, long long v)
 }
 
 // Per-atom values that one wave of a queued launch writes and other waves
-// of the same launch read (Born radii and chain weights of finished blocks)
+// of the same launch read (Born radii, dR/dPsi and G sums of finished blocks)
 // move through device-scope loads and stores (sc1: coherent across the L2
 // caches of the XCDs, which plain loads are not within one launch).
 template <typename T>
@@ -1652,9 +1652,10 @@ __global__ __launch_bounds__(256) void k_energy_finalize(int n_atoms, int n_sum,
 
 // One work item of R (1 or 2) i blocks; see radii_item.
 // B (rho - offset) of one atom in the pair precision, formed from its G sum
-// (fixed point, final once the energy pass is) and dR/dPsi exactly as the
-// energy finalize forms it (B = G dR/dPsi in FP64), so no finalize launch is
-// needed between the energy and chain passes.
+// (fixed point, final once the energy pass is) and dR/dPsi: B = G dR/dPsi in
+// FP64, then one rounding to the pair precision (the output kernel forms the
+// same FP64 B), so no finalize launch is needed between the energy and chain
+// passes.
 template <typename T>
 __device__ __forceinline__ T brt_from(unsigned long long gfx, double dRdPsi, T rt)
 {
@@ -2004,9 +2005,10 @@ __global__ __launch_bounds__(kTile * W) void k_chain_pairs(
 // W consecutive items of that ticket, so the items start in sequence order.
 // An item of a later pass first waits until every 64-atom block it touches is
 // final in the preceding pass: every item counts itself done on each of its
-// blocks (int counters), and the wave whose count completes a block finalizes
-// it (the OBC radius and its derivatives after the descreening pass, the
-// chain weight after the energy pass) and then marks it ready (count + 1).
+// blocks (int counters), and the wave whose count completes a block marks it
+// ready (count + 1), after the descreening pass once it has finalized the
+// block (the OBC radius and its derivatives; after the energy pass the block's
+// G sums are final, from which the chain items form the chain weights).
 // Every wait ends: an item waits only for items earlier in the sequence, which
 // were taken by workgroups that started before it (or by its own workgroup)
 // and so are running or done.  Each wait is bounded all the same
